@@ -1,0 +1,238 @@
+"""ctypes front end of the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the product path never does, and
+this module imports nothing from the product package.
+
+Every function follows a passage of the paper:
+  csr_build  -- Pauli sum (Eq. 3) compiled to CSR (Sec. III-E)
+  spmv       -- one sparse product (Eq. 7)
+  taylor5    -- fifth-order update, Eq. 6 via Eq. 7 and Eq. 8
+  normalize  -- unit-norm rescaling (the paper is silent; see the readings)
+  energy     -- Rayleigh quotient (Eq. 1)
+  gradients  -- pool gradients (Eq. 5) as 2 Re <H psi|A_j psi>
+  select     -- argmax |g_j| with a stated tie rule (Sec. III-D)
+  adapt_run  -- the adaptive loop of Sec. III-D with fixed step count
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.c")
+
+# Relative tolerance of the selection tie rule: candidates are all j with
+# |g_j| >= max|g| * (1 - REL_TIE); the lowest index among them is chosen.
+REL_TIE = 1e-6
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (no FMA contraction, OpenMP over rows)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                        "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC_PATH, "-lm"],
+                       check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_U64 = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_threads.restype = C.c_int
+        L.orc_csr_build.restype = C.c_int64
+        L.orc_csr_build.argtypes = [C.c_int, C.c_int64, _U64, _U64, _D, C.c_double, _I64,
+                                    C.c_void_p, C.c_void_p]
+        L.orc_spmv.restype = None
+        L.orc_spmv.argtypes = [C.c_int64, _I64, _I32, _D, _D, _D]
+        L.orc_taylor5.restype = None
+        L.orc_taylor5.argtypes = [C.c_int64, _I64, _I32, _D, C.c_double, _D, _D, _D]
+        L.orc_normalize.restype = C.c_double
+        L.orc_normalize.argtypes = [C.c_int64, _D]
+        L.orc_energy.restype = None
+        L.orc_energy.argtypes = [C.c_int64, _I64, _I32, _D, _D, _D, _D]
+        L.orc_gradients.restype = None
+        L.orc_gradients.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    _D, _D, _D, _D]
+        L.orc_select.restype = C.c_int32
+        L.orc_select.argtypes = [C.c_int32, _D, C.c_double, C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
+
+
+@dataclass
+class CSR:
+    n_qubits: int
+    rowptr: np.ndarray   # int64[dim+1]
+    col: np.ndarray      # int32[nnz]
+    val: np.ndarray      # complex128[nnz]
+
+    @property
+    def dim(self) -> int:
+        return self.rowptr.size - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def dense(self) -> np.ndarray:
+        m = np.zeros((self.dim, self.dim), dtype=np.complex128)
+        rows = np.repeat(np.arange(self.dim), np.diff(self.rowptr))
+        m[rows, self.col] = self.val
+        return m
+
+
+def default_tol(coeff) -> float:
+    """Drop threshold used by default: 1e-12 * max_t |c_t| (absolute)."""
+    coeff = np.asarray(coeff)
+    return 1e-12 * float(np.abs(coeff).max()) if coeff.size else 0.0
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def csr_build(n_qubits: int, xmask, zmask, coeff, tol: float | None = None) -> CSR:
+    """CSR of sum_t coeff[t] P(xmask[t], zmask[t]) (see oracle.c, orc_csr_build)."""
+    x = np.ascontiguousarray(xmask, dtype=np.uint64)
+    z = np.ascontiguousarray(zmask, dtype=np.uint64)
+    c = _c128(coeff)
+    if tol is None:
+        tol = default_tol(c)
+    dim = 1 << n_qubits
+    rowptr = np.zeros(dim + 1, dtype=np.int64)
+    cd = c.view(np.float64)
+    nnz = lib().orc_csr_build(n_qubits, x.size, x, z, cd, tol, rowptr, None, None)
+    if nnz < 0:
+        raise ValueError("oracle csr_build: bad arguments")
+    col = np.zeros(max(nnz, 1), dtype=np.int32)
+    val = np.zeros(max(nnz, 1), dtype=np.complex128)
+    lib().orc_csr_build(n_qubits, x.size, x, z, cd, tol, rowptr,
+                        col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p))
+    return CSR(n_qubits, rowptr, col[:nnz], val[:nnz])
+
+
+def csr_from_pack(pack, tol: float | None = None) -> CSR:
+    return csr_build(pack.n_qubits, pack.xmask, pack.zmask, pack.coeff, tol)
+
+
+def _colv(m: CSR):
+    col = m.col if m.col.size else np.zeros(1, dtype=np.int32)
+    val = m.val if m.val.size else np.zeros(1, dtype=np.complex128)
+    return np.ascontiguousarray(col), np.ascontiguousarray(val).view(np.float64)
+
+
+def spmv(m: CSR, x) -> np.ndarray:
+    x = _c128(x)
+    y = np.zeros(m.dim, dtype=np.complex128)
+    col, val = _colv(m)
+    lib().orc_spmv(m.dim, m.rowptr, col, val, x.view(np.float64), y.view(np.float64))
+    return y
+
+
+def taylor5(a: CSR, theta: float, psi) -> np.ndarray:
+    """Raw Eq. 8 result (not renormalised)."""
+    psi = _c128(psi)
+    out = np.zeros_like(psi)
+    work = np.zeros(4 * a.dim, dtype=np.float64)
+    col, val = _colv(a)
+    lib().orc_taylor5(a.dim, a.rowptr, col, val, float(theta), psi.view(np.float64),
+                      out.view(np.float64), work)
+    return out
+
+
+def normalize(psi) -> tuple[np.ndarray, float]:
+    out = _c128(psi).copy()
+    n2 = lib().orc_normalize(out.size, out.view(np.float64))
+    return out, float(n2)
+
+
+def energy(h: CSR, psi):
+    """Returns (E, <psi|psi>, Im<psi|H psi>, sigma = H psi)."""
+    psi = _c128(psi)
+    sigma = np.zeros_like(psi)
+    out = np.zeros(3, dtype=np.float64)
+    col, val = _colv(h)
+    lib().orc_energy(h.dim, h.rowptr, col, val, psi.view(np.float64), sigma.view(np.float64), out)
+    return float(out[0]), float(out[1]), float(out[2]), sigma
+
+
+def gradients(pool: list, psi, sigma) -> np.ndarray:
+    """g_j = 2 Re <sigma | A_j psi> for every operator of the pool (CSR list)."""
+    psi = _c128(psi)
+    sigma = _c128(sigma)
+    M = len(pool)
+    dim = psi.size
+    keep = [_colv(a) for a in pool]
+    rp = (C.c_void_p * M)(*[a.rowptr.ctypes.data for a in pool])
+    cp = (C.c_void_p * M)(*[k[0].ctypes.data for k in keep])
+    vp = (C.c_void_p * M)(*[k[1].ctypes.data for k in keep])
+    g = np.zeros(M, dtype=np.float64)
+    work = np.zeros(2 * dim, dtype=np.float64)
+    lib().orc_gradients(dim, M, rp, cp, vp, psi.view(np.float64), sigma.view(np.float64), g, work)
+    return g
+
+
+def select(g, rel_tie: float = REL_TIE) -> tuple[int, float]:
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    gm = C.c_double(0.0)
+    k = lib().orc_select(g.size, g, rel_tie, C.byref(gm))
+    return int(k), float(gm.value)
+
+
+@dataclass
+class AdaptTrace:
+    energies: list        # energy at psi_t before each update, then the final one
+    gradients: list       # g at psi_t
+    selected: list        # chosen index k_t
+    thetas: list
+    psi: np.ndarray       # final state
+
+
+def adapt_run(h: CSR, pool: list, psi0, thetas, steps: int, renormalize: bool = True,
+              forced=None, eps: float = 0.0) -> AdaptTrace:
+    """Adaptive loop (Sec. III-D): screen, select, check convergence, update.
+
+    ``forced`` (optional sequence of indices) replaces the selection, so that
+    another implementation can be compared along the same trajectory.
+    """
+    psi = _c128(psi0).copy()
+    tr = AdaptTrace([], [], [], [], psi)
+    for t in range(steps):
+        e, _, _, sigma = energy(h, psi)
+        g = gradients(pool, psi, sigma)
+        k, gmax = select(g)
+        tr.energies.append(e)
+        tr.gradients.append(g)
+        if gmax < eps:
+            break
+        if forced is not None:
+            k = int(forced[t])
+        tr.selected.append(k)
+        tr.thetas.append(float(thetas[t]))
+        psi = taylor5(pool[k], float(thetas[t]), psi)
+        if renormalize:
+            psi, _ = normalize(psi)
+    tr.energies.append(energy(h, psi)[0])
+    tr.psi = psi
+    return tr
