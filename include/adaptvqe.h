@@ -1,0 +1,259 @@
+/*
+ * adaptvqe.h -- C ABI of the MI355X (gfx950) adaptive-VQE hot path.
+ *
+ * The library evaluates, on one GPU, the classical core of an adaptive
+ * variational eigensolver step:
+ *   - compilation of a Pauli-sum operator (Sec. II-A, Eq. 3) into CSR
+ *     (the on-the-fly sparse compilation of Sec. III-E);
+ *   - the energy, a Rayleigh quotient <psi|H|psi>/<psi|psi> (Eq. 1), whose cost
+ *     is one sparse product with H;
+ *   - the pool-gradient screen g_j = <psi|[H, A_j]|psi> (Eq. 5), evaluated as
+ *     2 Re <H psi | A_j psi> for anti-Hermitian generators A_j;
+ *   - the selection of the largest |g_j| (Sec. III-D);
+ *   - the fifth-order Taylor state update of Eq. 6, i.e. the five chained
+ *     sparse products v_n = A v_{n-1} of Eq. 7 and the accumulation of Eq. 8.
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im) pairs: VQE_C128 uses two
+ *     doubles per element, VQE_C64 two floats.
+ *   - A state vector has dim = 2^n_qubits elements; basis index bit q is qubit q.
+ *   - All array pointers are DEVICE pointers owned by the caller unless an
+ *     argument says "host".  The library never frees caller memory; memory it
+ *     allocates for itself (workspace, plans) belongs to the context or plan.
+ *   - Work is enqueued on the context's HIP stream and is asynchronous; results
+ *     are valid after the stream is synchronised.  The sizing phase of
+ *     csr_build_from_pauli is the one exception: it synchronises the stream.
+ *   - Every call returns VQE_OK (0) or a negative status.  No C++ exception
+ *     crosses the ABI.  vqe_last_error() gives a message for the last failure.
+ *   - A context is not thread-safe: use one per host thread (or stream).
+ *   - Results do not depend on how many states share a launch: the order of
+ *     every floating-point sum is fixed by the operator's size alone.
+ */
+#ifndef ADAPTVQE_H
+#define ADAPTVQE_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define VQE_API __attribute__((visibility("default")))
+#else
+#define VQE_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum {
+    VQE_OK = 0,
+    VQE_EINVAL = -1,   /* bad argument: null pointer, n_qubits out of range,
+                          mask bit >= n_qubits, non-finite theta, dtype mismatch */
+    VQE_ESIZE = -2,    /* nnz > INT32_MAX, or a row longer than the builder supports */
+    VQE_ENOMEM = -3,   /* device workspace allocation failed */
+    VQE_EHIP = -4,     /* HIP runtime error (text in vqe_last_error) */
+    VQE_ENOTSUP = -5   /* operation not supported for this operator */
+};
+
+typedef enum { VQE_C128 = 0, VQE_C64 = 1 } vqe_dtype;
+
+/* vqe_csr.flags, set by csr_build_from_pauli */
+#define VQE_PAIRING 1u   /* every row holds at most one entry and col(col(r)) = r:
+                            true of every fermionic single or double excitation
+                            generator under JW or BK.  Enables the fused
+                            register-resident Taylor kernel. */
+
+/*
+ * A square CSR operator of dimension dim = 2^n_qubits.  Device arrays:
+ *   rowptr[dim+1] (int32, rowptr[0] = 0), col[nnz] (int32, strictly ascending
+ *   within a row), val[nnz] (complex of the given dtype).
+ * The stored matrix is S = M - diag_shift * I, where M is the operator itself.
+ * diag_shift is 0 for VQE_C128; for VQE_C64 it is the FP64 reference value
+ * subtracted before rounding to FP32 so that large diagonal entries lose no
+ * accuracy.  When diag_shift != 0 every row stores its diagonal entry.
+ */
+typedef struct vqe_csr {
+    int32_t n_qubits;
+    int32_t dtype;        /* vqe_dtype */
+    int64_t dim;
+    int64_t nnz;
+    int32_t *rowptr;
+    int32_t *col;
+    void *val;
+    double diag_shift;
+    uint32_t flags;
+    uint32_t reserved;
+} vqe_csr;
+
+/*
+ * An operator pool (Sec. III-A): M generators of one dimension and dtype.
+ * ops is a DEVICE array of M descriptors (each pointing to device CSR
+ * arrays); ops_host is the same array in host memory (read for sizes and
+ * flags, never dereferenced on the device).  Both are owned by the caller.
+ */
+typedef struct vqe_pool {
+    int32_t M;
+    int32_t n_qubits;
+    int32_t dtype;
+    int32_t all_pairing;  /* 1 if every generator has VQE_PAIRING */
+    const vqe_csr *ops;
+    const vqe_csr *ops_host;
+} vqe_pool;
+
+typedef struct vqe_ctx vqe_ctx;
+
+/* ------------------------------------------------------------------ context */
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t, or NULL for the null stream).  Returns VQE_EINVAL for a bad
+ * device, VQE_EHIP if the device cannot be used. */
+VQE_API int vqe_create(int device, void *hip_stream, vqe_ctx **out);
+VQE_API int vqe_destroy(vqe_ctx *ctx);
+/* Re-bind the context to another stream of the same device. */
+VQE_API int vqe_set_stream(vqe_ctx *ctx, void *hip_stream);
+VQE_API const char *vqe_strerror(int status);
+VQE_API const char *vqe_last_error(const vqe_ctx *ctx);
+/* Number of compute units and the device name (for reports). */
+VQE_API int vqe_device_info(const vqe_ctx *ctx, int32_t *n_cu, char *name, int32_t name_len);
+
+/* ------------------------------------------------------------------ build */
+/*
+ * Compile sum_t c_t P(x_t, z_t) into CSR (Eq. 3, Sec. III-E).
+ * xmask, zmask: HOST uint64[n_terms]; bit q of (x, z) selects the factor on
+ * qubit q: (0,0)=I, (1,0)=X, (0,1)=Z, (1,1)=Y.  coeff: HOST double[2*n_terms]
+ * (complex c_t, interleaved).  P(x,z)|c> = i^{|x&z|} (-1)^{|z&c|} |c^x>, so
+ * term t adds to entry (r, r^x_t) the value c_t i^{|x_t&z_t|} (-1)^{|z_t&(r^x_t)|}.
+ * Contributions to one entry are summed in ascending t from +0.0 in FP64
+ * with plain additions; an entry is dropped when |re| <= drop_tol and
+ * |im| <= drop_tol (it is kept regardless when it is a diagonal entry and
+ * diag_shift != 0).  Columns are ascending within each row.
+ *
+ * Two phases on the same `inout` descriptor:
+ *   1. inout->rowptr set (device int32[dim+1]), inout->col == inout->val ==
+ *      NULL: fills rowptr, sets nnz, flags, n_qubits, dim, dtype, diag_shift,
+ *      writes *nnz_out and synchronises the stream.
+ *   2. the caller allocates col[nnz] and val[nnz] (of `dtype`), stores them in
+ *      inout, and calls again with the same arguments: fills col and val.
+ * VQE_C64 values are fp32(value - diag_shift * [r == c]).
+ * Errors: VQE_EINVAL (n_qubits outside [1, 30], mask bit >= n_qubits, null
+ * pointers, n_terms < 0); VQE_ESIZE (nnz > INT32_MAX, or a row with more than
+ * 2048 entries); VQE_EHIP.
+ */
+VQE_API int csr_build_from_pauli(vqe_ctx *ctx, int32_t n_qubits, int64_t n_terms,
+                         const uint64_t *xmask, const uint64_t *zmask, const double *coeff,
+                         double drop_tol, int32_t dtype, double diag_shift,
+                         vqe_csr *inout, int64_t *nnz_out);
+
+/* ------------------------------------------------------------------ hot path */
+/*
+ * Fifth-order Taylor update (Eq. 6): psi <- sum_{n=0..5} (theta A)^n psi / n!,
+ * evaluated as v_n = A v_{n-1} (Eq. 7) and psi + sum_n theta^n/n! v_n (Eq. 8),
+ * in place on psi (device, dim elements of A->dtype).  Arithmetic is FP64 in
+ * registers for both dtypes.  For VQE_PAIRING operators one fused kernel runs
+ * all five products; other operators use a fused single-workgroup kernel
+ * when small and five chained launches otherwise.
+ * renormalize != 0 rescales psi to unit norm afterwards (FP64 norm).
+ * norm2_out (device double[1], nullable) receives the squared norm of the raw
+ * Eq. 8 result.  A must have diag_shift == 0.
+ * Errors: VQE_EINVAL (non-finite theta, null pointers, diag_shift != 0).
+ */
+VQE_API int taylor5_apply(vqe_ctx *ctx, const vqe_csr *A, double theta, void *psi,
+                  int32_t renormalize, double *norm2_out);
+
+/*
+ * Energy (Eq. 1).  sigma = S psi is written to sigma_out (device, dim elements
+ * of H->dtype; nullable -> workspace), where S = H - diag_shift I is the
+ * stored matrix.  out (device double[3]) receives
+ *   out[0] = diag_shift + Re<psi|S psi> / <psi|psi>   (the Rayleigh quotient),
+ *   out[1] = <psi|psi>,
+ *   out[2] = Im<psi|S psi>                             (zero for Hermitian H).
+ * Products are accumulated in FP64; the reductions are FP64 in a fixed order.
+ */
+VQE_API int energy(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma_out, double *out);
+
+/*
+ * Pool-gradient screen (Eq. 5): g_j = 2 Re sum_r conj(sigma_r) (A_j psi)_r for
+ * j = 0..M-1, with sigma = H psi.  `sigma` (device, nullable) is the stored
+ * product S psi returned by energy(); when NULL it is computed here.  The
+ * shift is added back, sigma = S psi + diag_shift psi, so g is exact for any
+ * pool.  g_out: device double[M].  FP64 accumulation, fixed order.
+ */
+VQE_API int pool_gradients(vqe_ctx *ctx, const vqe_csr *H, const vqe_pool *pool, const void *psi,
+                   const void *sigma, double *g_out);
+
+/*
+ * Selection (Sec. III-D): gmax = max_j |g_j|; the chosen index is the lowest
+ * j with |g_j| >= gmax * (1 - rel_tie).  g, k_out (int32[1]) and gmax_out
+ * (double[1]) are device pointers.  Convergence (gmax < eps) is the caller's
+ * test on gmax_out.
+ */
+VQE_API int vqe_select(vqe_ctx *ctx, int32_t M, const double *g, double rel_tie,
+               int32_t *k_out, double *gmax_out);
+
+/* ------------------------------------------------------------------ batching */
+/*
+ * A batch plan runs one adaptive step for B independent states in a fixed
+ * sequence of launches (replayable as one HIP graph):
+ *   sigma_s = S_s psi_s and E_s (Eq. 1); g_s over the state's pool (Eq. 5);
+ *   k_s = argmax |g_s| (or a caller-given index); psi_s <- T5(theta_s A_{k_s}) psi_s
+ *   (Eq. 6-8); optional renormalisation.
+ * States may differ in size and pool.  All buffers are the caller's device
+ * memory and must stay valid for the life of the plan:
+ *   psi, sigma        per state, dim_s elements of the plan dtype
+ *   theta             double[B]
+ *   energy_out        double[3*B] (as energy() out, per state)
+ *   g_out             double[sum_s M_s], state s at offset g_offset[s]
+ *   k_io              int32[B]  (output of the selection, or the input index
+ *                     when the step is run with VQE_STEP_FORCED)
+ *   gmax_out          double[B]
+ * Each state's pool must consist of VQE_PAIRING generators.
+ */
+typedef struct vqe_batch_item {
+    const vqe_csr *H;       /* host pointer to the state's Hamiltonian descriptor */
+    const vqe_pool *pool;   /* host pointer to the state's pool */
+    void *psi;
+    void *sigma;
+    int32_t spmv_lanes;     /* lanes per row for the H product: 0 = default, else 8/16/32/64 */
+    int32_t reserved;
+} vqe_batch_item;
+
+typedef struct vqe_batch_io {
+    double *theta;
+    double *energy_out;
+    double *g_out;
+    const int64_t *g_offset_host;   /* host int64[B]: offset of state s in g_out */
+    int32_t *k_io;
+    double *gmax_out;
+} vqe_batch_io;
+
+#define VQE_STEP_RENORM 1u      /* renormalise every state after its update */
+#define VQE_STEP_FORCED 2u      /* take k from k_io instead of selecting */
+#define VQE_STEP_NO_UPDATE 4u   /* screen only: energy, gradients, selection */
+#define VQE_STEP_GRAPH 8u       /* launch through a captured HIP graph (captured
+                                   once per flag set, then replayed) */
+
+typedef struct vqe_batch vqe_batch;
+
+VQE_API int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *items,
+                     const vqe_batch_io *io, double rel_tie, vqe_batch **out);
+VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
+VQE_API int vqe_batch_destroy(vqe_batch *plan);
+/* Bytes of device workspace the plan owns (for footprint accounting). */
+VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
+
+/* ------------------------------------------------------------------ tuning */
+/*
+ * Time the H product (sigma = S psi with the energy reduction) with the given
+ * lanes per row (8, 16, 32 or 64): `reps` back-to-back launches bracketed by
+ * HIP events on the context stream; *ms_out = average milliseconds per launch.
+ * Used by the schedule autotuner.
+ */
+VQE_API int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma,
+                  int32_t lanes, int32_t reps, float *ms_out);
+/* Default lanes per row chosen for an operator when no tuning is given. */
+VQE_API int32_t vqe_default_lanes(const vqe_csr *H);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADAPTVQE_H */

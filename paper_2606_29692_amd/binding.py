@@ -1,0 +1,383 @@
+"""Thin ctypes binding of libadaptvqe (include/adaptvqe.h).
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+provides device memory (tensors) and streams.  The functions keep the C names:
+``csr_build_from_pauli``, ``taylor5_apply``, ``energy``, ``pool_gradients``,
+``vqe_select`` and the batch plan.  If the library is missing or no GPU is
+visible, the calls raise; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libadaptvqe.so")
+
+VQE_OK, VQE_EINVAL, VQE_ESIZE, VQE_ENOMEM, VQE_EHIP, VQE_ENOTSUP = 0, -1, -2, -3, -4, -5
+VQE_C128, VQE_C64 = 0, 1
+VQE_PAIRING = 1
+VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_NO_UPDATE, VQE_STEP_GRAPH = 1, 2, 4, 8
+REL_TIE = 1e-6
+
+DTYPES = {"c128": VQE_C128, "c64": VQE_C64}
+
+
+class VqeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class vqe_csr(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("dtype", C.c_int32), ("dim", C.c_int64),
+                ("nnz", C.c_int64), ("rowptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p), ("diag_shift", C.c_double), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class vqe_pool(C.Structure):
+    _fields_ = [("M", C.c_int32), ("n_qubits", C.c_int32), ("dtype", C.c_int32),
+                ("all_pairing", C.c_int32), ("ops", C.c_void_p), ("ops_host", C.c_void_p)]
+
+
+class vqe_batch_item(C.Structure):
+    _fields_ = [("H", C.c_void_p), ("pool", C.c_void_p), ("psi", C.c_void_p),
+                ("sigma", C.c_void_p), ("spmv_lanes", C.c_int32), ("reserved", C.c_int32)]
+
+
+class vqe_batch_io(C.Structure):
+    _fields_ = [("theta", C.c_void_p), ("energy_out", C.c_void_p), ("g_out", C.c_void_p),
+                ("g_offset_host", C.c_void_p), ("k_io", C.c_void_p), ("gmax_out", C.c_void_p)]
+
+
+# name -> (restype, argtypes); the full exported surface of adaptvqe.h
+SIGNATURES = {
+    "vqe_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "vqe_destroy": (C.c_int, [C.c_void_p]),
+    "vqe_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "vqe_strerror": (C.c_char_p, [C.c_int]),
+    "vqe_last_error": (C.c_char_p, [C.c_void_p]),
+    "vqe_device_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_char_p, C.c_int32]),
+    "csr_build_from_pauli": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_double, C.c_int32, C.c_double,
+                                       C.POINTER(vqe_csr), C.POINTER(C.c_int64)]),
+    "taylor5_apply": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_double, C.c_void_p,
+                                C.c_int32, C.c_void_p]),
+    "energy": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pool_gradients": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.POINTER(vqe_pool),
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vqe_select": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p,
+                             C.c_void_p]),
+    "vqe_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_batch_item),
+                                   C.POINTER(vqe_batch_io), C.c_double, C.POINTER(C.c_void_p)]),
+    "vqe_batch_step": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "vqe_batch_destroy": (C.c_int, [C.c_void_p]),
+    "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
+    "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
+                                C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
+    "vqe_default_lanes": (C.c_int32, [C.POINTER(vqe_csr)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libadaptvqe.so (built in-tree by build.py); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2606_29692_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the adaptvqe HIP path needs an MI355X")
+    return torch
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+class Context:
+    """A vqe_ctx bound to one device and one stream (torch's current stream
+    unless given)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().vqe_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != VQE_OK:
+            raise VqeError(st, f"vqe_create: {lib().vqe_strerror(st).decode()}")
+        self.handle = h
+
+    def check(self, status: int, what: str):
+        if status != VQE_OK:
+            msg = lib().vqe_last_error(self.handle).decode()
+            raise VqeError(status, f"{what}: {lib().vqe_strerror(status).decode()}: {msg}")
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self.check(lib().vqe_set_stream(self.handle, C.c_void_p(stream.cuda_stream)), "vqe_set_stream")
+
+    def info(self):
+        n = C.c_int32()
+        buf = C.create_string_buffer(256)
+        self.check(lib().vqe_device_info(self.handle, C.byref(n), buf, 256), "vqe_device_info")
+        return int(n.value), buf.value.decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().vqe_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceCSR:
+    """A CSR operator in device memory (torch tensors) and its vqe_csr descriptor."""
+
+    def __init__(self, desc: vqe_csr, rowptr, col, val):
+        self.desc = desc
+        self.rowptr, self.col, self.val = rowptr, col, val
+
+    @property
+    def nnz(self) -> int:
+        return int(self.desc.nnz)
+
+    @property
+    def dim(self) -> int:
+        return int(self.desc.dim)
+
+    @property
+    def n_qubits(self) -> int:
+        return int(self.desc.n_qubits)
+
+    @property
+    def pairing(self) -> bool:
+        return bool(self.desc.flags & VQE_PAIRING)
+
+    @property
+    def diag_shift(self) -> float:
+        return float(self.desc.diag_shift)
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in (self.rowptr, self.col, self.val))
+
+
+def default_tol(coeff) -> float:
+    coeff = np.asarray(coeff)
+    return 1e-12 * float(np.abs(coeff).max()) if coeff.size else 0.0
+
+
+def csr_build_from_pauli(ctx: Context, n_qubits: int, xmask, zmask, coeff,
+                         drop_tol: float | None = None, dtype: str = "c128",
+                         diag_shift: float = 0.0) -> DeviceCSR:
+    """Compile sum_t coeff[t] P(xmask[t], zmask[t]) to a device CSR (two phases)."""
+    torch = _torch()
+    x = np.ascontiguousarray(xmask, dtype=np.uint64)
+    z = np.ascontiguousarray(zmask, dtype=np.uint64)
+    c = np.ascontiguousarray(np.asarray(coeff, dtype=np.complex128))
+    if drop_tol is None:
+        drop_tol = default_tol(c)
+    dt = DTYPES[dtype]
+    dim = 1 << n_qubits
+    rowptr = torch.empty(dim + 1, dtype=torch.int32, device=ctx.torch_device)
+    desc = vqe_csr()
+    desc.rowptr = rowptr.data_ptr()
+    nnz = C.c_int64()
+    args = (ctx.handle, n_qubits, x.size, x.ctypes.data, z.ctypes.data, c.ctypes.data,
+            float(drop_tol), dt, float(diag_shift))
+    ctx.check(lib().csr_build_from_pauli(*args, C.byref(desc), C.byref(nnz)),
+              "csr_build_from_pauli (sizing)")
+    n = max(int(nnz.value), 1)
+    col = torch.empty(n, dtype=torch.int32, device=ctx.torch_device)
+    val = torch.empty(n, dtype=torch.complex128 if dt == VQE_C128 else torch.complex64,
+                      device=ctx.torch_device)
+    desc.col = col.data_ptr()
+    desc.val = val.data_ptr()
+    ctx.check(lib().csr_build_from_pauli(*args, C.byref(desc), C.byref(nnz)),
+              "csr_build_from_pauli (fill)")
+    return DeviceCSR(desc, rowptr, col, val)
+
+
+def csr_from_pack(ctx: Context, pack, dtype: str = "c128", diag_shift: float = 0.0,
+                  drop_tol: float | None = None) -> DeviceCSR:
+    return csr_build_from_pauli(ctx, pack.n_qubits, pack.xmask, pack.zmask, pack.coeff,
+                                drop_tol, dtype, diag_shift)
+
+
+def taylor5_apply(ctx: Context, A: DeviceCSR, theta: float, psi, renormalize: bool = True,
+                  norm2_out=None):
+    """In-place fifth-order Taylor update of psi (Eq. 6-8)."""
+    ctx.check(lib().taylor5_apply(ctx.handle, C.byref(A.desc), float(theta), _ptr(psi),
+                                  1 if renormalize else 0, _ptr(norm2_out)), "taylor5_apply")
+    return psi
+
+
+def energy(ctx: Context, H: DeviceCSR, psi, sigma_out=None, out=None):
+    """out (device double[3]) = (E, <psi|psi>, Im<psi|S psi>); sigma_out = S psi."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=ctx.torch_device)
+    ctx.check(lib().energy(ctx.handle, C.byref(H.desc), _ptr(psi), _ptr(sigma_out), _ptr(out)),
+              "energy")
+    return out
+
+
+class DevicePool:
+    """M generators (DeviceCSR) and their device descriptor table."""
+
+    def __init__(self, ctx: Context, ops: list):
+        torch = _torch()
+        if not ops:
+            raise ValueError("empty pool")
+        self.ops = ops
+        M = len(ops)
+        self._host = (vqe_csr * M)(*[o.desc for o in ops])
+        raw = np.frombuffer(C.string_at(C.addressof(self._host), C.sizeof(self._host)), dtype=np.uint8)
+        self._dev = torch.from_numpy(raw.copy()).to(ctx.torch_device)
+        d0 = ops[0].desc
+        self.desc = vqe_pool()
+        self.desc.M = M
+        self.desc.n_qubits = d0.n_qubits
+        self.desc.dtype = d0.dtype
+        self.desc.all_pairing = int(all(o.pairing for o in ops))
+        self.desc.ops = self._dev.data_ptr()
+        self.desc.ops_host = C.addressof(self._host)
+
+    @property
+    def M(self) -> int:
+        return len(self.ops)
+
+    def nbytes(self) -> int:
+        return sum(o.nbytes() for o in self.ops) + self._dev.numel()
+
+
+def pool_from_packs(ctx: Context, packs, dtype: str = "c128") -> DevicePool:
+    return DevicePool(ctx, [csr_from_pack(ctx, p, dtype) for p in packs])
+
+
+def pool_gradients(ctx: Context, H: DeviceCSR, pool: DevicePool, psi, sigma=None, g_out=None):
+    """g_j = 2 Re <H psi | A_j psi> for every generator (Eq. 5); device double[M]."""
+    torch = _torch()
+    if g_out is None:
+        g_out = torch.empty(pool.M, dtype=torch.float64, device=ctx.torch_device)
+    ctx.check(lib().pool_gradients(ctx.handle, C.byref(H.desc), C.byref(pool.desc), _ptr(psi),
+                                   _ptr(sigma), _ptr(g_out)), "pool_gradients")
+    return g_out
+
+
+def vqe_select(ctx: Context, g, rel_tie: float = REL_TIE, k_out=None, gmax_out=None):
+    """Index of the largest |g_j| (lowest index within rel_tie); device tensors."""
+    torch = _torch()
+    if k_out is None:
+        k_out = torch.empty(1, dtype=torch.int32, device=ctx.torch_device)
+    if gmax_out is None:
+        gmax_out = torch.empty(1, dtype=torch.float64, device=ctx.torch_device)
+    ctx.check(lib().vqe_select(ctx.handle, int(g.numel()), _ptr(g), float(rel_tie), _ptr(k_out),
+                               _ptr(gmax_out)), "vqe_select")
+    return k_out, gmax_out
+
+
+def time_spmv(ctx: Context, H: DeviceCSR, psi, sigma, lanes: int, reps: int = 20) -> float:
+    ms = C.c_float()
+    ctx.check(lib().vqe_time_spmv(ctx.handle, C.byref(H.desc), _ptr(psi), _ptr(sigma), int(lanes),
+                                  int(reps), C.byref(ms)), "vqe_time_spmv")
+    return float(ms.value)
+
+
+def default_lanes(H: DeviceCSR) -> int:
+    return int(lib().vqe_default_lanes(C.byref(H.desc)))
+
+
+class BatchPlan:
+    """One adaptive step for B states per launch sequence (optionally a HIP graph).
+
+    ``states`` is a list of (H: DeviceCSR, pool: DevicePool, psi tensor) and the
+    plan allocates sigma, theta, energies, gradients, indices and gmax as torch
+    tensors that stay alive with it."""
+
+    def __init__(self, ctx: Context, states: list, lanes=None, rel_tie: float = REL_TIE):
+        torch = _torch()
+        self.ctx = ctx
+        B = len(states)
+        self.B = B
+        self.states = states
+        dev = ctx.torch_device
+        self.sigma = [torch.empty_like(psi) for (_, _, psi) in states]
+        self.g_offset = np.zeros(B, dtype=np.int64)
+        off = 0
+        for s, (_, pool, _) in enumerate(states):
+            self.g_offset[s] = off
+            off += pool.M
+        self.theta = torch.zeros(B, dtype=torch.float64, device=dev)
+        self.energies = torch.zeros(3 * B, dtype=torch.float64, device=dev)
+        self.g = torch.zeros(max(off, 1), dtype=torch.float64, device=dev)
+        self.k = torch.zeros(B, dtype=torch.int32, device=dev)
+        self.gmax = torch.zeros(B, dtype=torch.float64, device=dev)
+        items = (vqe_batch_item * B)()
+        for s, (H, pool, psi) in enumerate(states):
+            items[s].H = C.addressof(H.desc)
+            items[s].pool = C.addressof(pool.desc)
+            items[s].psi = psi.data_ptr()
+            items[s].sigma = self.sigma[s].data_ptr()
+            items[s].spmv_lanes = int(lanes[s]) if lanes is not None else 0
+        self._items = items
+        io = vqe_batch_io()
+        io.theta = self.theta.data_ptr()
+        io.energy_out = self.energies.data_ptr()
+        io.g_out = self.g.data_ptr()
+        io.g_offset_host = self.g_offset.ctypes.data
+        io.k_io = self.k.data_ptr()
+        io.gmax_out = self.gmax.data_ptr()
+        self._io = io
+        h = C.c_void_p()
+        ctx.check(lib().vqe_batch_create(ctx.handle, B, items, C.byref(io), float(rel_tie),
+                                         C.byref(h)), "vqe_batch_create")
+        self.handle = h
+
+    def step(self, renorm: bool = True, forced: bool = False, update: bool = True,
+             graph: bool = False):
+        flags = ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
+                 | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0))
+        self.ctx.check(lib().vqe_batch_step(self.handle, flags), "vqe_batch_step")
+
+    def gradients(self, s: int):
+        M = self.states[s][1].M
+        o = int(self.g_offset[s])
+        return self.g[o:o + M]
+
+    def workspace_bytes(self) -> int:
+        return int(lib().vqe_batch_workspace_bytes(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().vqe_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,487 @@
+// C ABI: contexts, workspace, status strings and the batch planner.
+//
+// The batch planner turns B independent adaptive steps into a fixed list of
+// launches over device task tables:
+//   H products with the energy reduction (one launch per lanes-per-row value),
+//   energy finalisation, pool gradients, gradient finalisation, selection,
+//   the fused pairing Taylor update and the renormalisation.
+// States are assigned to the 8 XCDs of the device (balanced by H bytes) and
+// every task table is interleaved so that workgroup i runs on XCD i % 8 and
+// only touches states of that XCD: each state's psi and sigma stay in one L2.
+// The launch list can be captured once into a HIP graph and replayed; theta,
+// the selected index and every result live in caller-owned device buffers, so
+// a replay needs no host round trip.
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+#include <vector>
+
+static const int kXcd = 8;
+
+extern "C" const char *vqe_strerror(int status)
+{
+    switch (status) {
+    case VQE_OK: return "success";
+    case VQE_EINVAL: return "invalid argument";
+    case VQE_ESIZE: return "size out of range";
+    case VQE_ENOMEM: return "out of device memory";
+    case VQE_EHIP: return "HIP runtime error";
+    case VQE_ENOTSUP: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *vqe_last_error(const vqe_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+extern "C" int vqe_create(int device, void *hip_stream, vqe_ctx **out)
+{
+    if (!out)
+        return VQE_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1)
+        return VQE_EHIP;
+    if (device < 0 || device >= n)
+        return VQE_EINVAL;
+    if (hipSetDevice(device) != hipSuccess)
+        return VQE_EHIP;
+    vqe_ctx *ctx = new (std::nothrow) vqe_ctx();
+    if (!ctx)
+        return VQE_ENOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete ctx;
+        return VQE_EHIP;
+    }
+    ctx->n_cu = prop.multiProcessorCount;
+    snprintf(ctx->name, sizeof(ctx->name), "%s (%s)", prop.name, prop.gcnArchName);
+    if (hipHostMalloc((void **)&ctx->host_scalars, 64, hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return VQE_ENOMEM;
+    }
+    *out = ctx;
+    return VQE_OK;
+}
+
+extern "C" int vqe_destroy(vqe_ctx *ctx)
+{
+    if (!ctx)
+        return VQE_EINVAL;
+    hipStreamSynchronize(ctx->stream);
+    if (ctx->ws)
+        hipFree(ctx->ws);
+    if (ctx->host_scalars)
+        hipHostFree(ctx->host_scalars);
+    delete ctx;
+    return VQE_OK;
+}
+
+extern "C" int vqe_set_stream(vqe_ctx *ctx, void *hip_stream)
+{
+    if (!ctx)
+        return VQE_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return VQE_OK;
+}
+
+extern "C" int vqe_device_info(const vqe_ctx *ctx, int32_t *n_cu, char *name, int32_t name_len)
+{
+    if (!ctx)
+        return VQE_EINVAL;
+    if (n_cu)
+        *n_cu = ctx->n_cu;
+    if (name && name_len > 0)
+        snprintf(name, (size_t)name_len, "%s", ctx->name);
+    return VQE_OK;
+}
+
+int vqe_ws_reserve(vqe_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->ws_bytes)
+        return VQE_OK;
+    // earlier work may still read the old scratch
+    VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->ws) {
+        hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    size_t sz = std::max<size_t>(bytes, (size_t)1 << 20);
+    if (hipMalloc(&ctx->ws, sz) != hipSuccess) {
+        ctx->ws = nullptr;
+        (void)hipGetLastError();
+        return vqe_fail(ctx, VQE_ENOMEM, "workspace allocation of %zu bytes failed", sz);
+    }
+    ctx->ws_bytes = sz;
+    return VQE_OK;
+}
+
+// ------------------------------------------------------------------ batch plan
+struct vqe_batch {
+    vqe_ctx *ctx = nullptr;
+    int32_t B = 0;
+    int32_t dtype = 0;
+    double rel_tie = 0.0;
+    char *dmem = nullptr;          // one allocation: tables + partials
+    size_t dmem_bytes = 0;
+    SpmvState *d_spmv = nullptr;
+    struct SpmvLaunch {
+        int lanes;
+        int2 *tasks;
+        unsigned grid;
+    };
+    std::vector<SpmvLaunch> spmv;
+    GradGroup *d_groups = nullptr;
+    int4 *d_grad_tasks = nullptr;
+    unsigned n_grad_tasks = 0;
+    int2 *d_grad_items = nullptr;
+    unsigned n_grad_items = 0;
+    SelectState *d_sel = nullptr;
+    TaylorState *d_tay = nullptr;
+    int2 *d_tay_tasks = nullptr;
+    unsigned n_tay_tasks = 0;
+    int2 *d_norm_tasks = nullptr;
+    unsigned n_norm_tasks = 0;
+    hipGraphExec_t exec[16] = {};
+    hipGraph_t graph[16] = {};
+};
+
+namespace {
+
+struct Arena {
+    std::vector<char> host;
+    size_t take(size_t bytes)
+    {
+        size_t o = host.size();
+        host.resize(o + vqe_align(bytes), 0);
+        return o;
+    }
+    template <class T> T *at(size_t off) { return reinterpret_cast<T *>(host.data() + off); }
+};
+
+// Interleave per-XCD task lists so that workgroup i belongs to XCD i % 8.
+template <class T>
+std::vector<T> interleave(const std::vector<std::vector<T>> &per, const T &pad)
+{
+    size_t longest = 0;
+    for (auto &v : per)
+        longest = std::max(longest, v.size());
+    std::vector<T> out;
+    out.reserve(longest * per.size());
+    for (size_t i = 0; i < longest; i++)
+        for (auto &v : per)
+            out.push_back(i < v.size() ? v[i] : pad);
+    return out;
+}
+
+int enqueue_step(vqe_batch *p, uint32_t flags)
+{
+    vqe_ctx *ctx = p->ctx;
+    hipStream_t s = ctx->stream;
+    SpmvState dummy{};
+    for (auto &l : p->spmv)
+        launch_spmv(p->dtype, l.lanes, dummy, p->d_spmv, l.tasks, l.grid, s);
+    k_energy_finalize<<<(unsigned)p->B, 64, 0, s>>>(dummy, p->d_spmv, p->B);
+    if (p->n_grad_tasks) {
+        launch_pool_grad(p->dtype, p->d_groups, p->d_grad_tasks, p->n_grad_tasks, s);
+        launch_grad_finalize(p->d_groups, p->d_grad_items, p->n_grad_items, s);
+    }
+    if (!(flags & VQE_STEP_FORCED))
+        launch_select(p->d_sel, (unsigned)p->B, p->rel_tie, s);
+    if (!(flags & VQE_STEP_NO_UPDATE)) {
+        launch_taylor_pair(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
+        if (flags & VQE_STEP_RENORM)
+            launch_norm(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, s);
+    }
+    VQE_LAUNCH_CHECK(ctx);
+    return VQE_OK;
+}
+
+}  // namespace
+
+extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *items,
+                                const vqe_batch_io *io, double rel_tie, vqe_batch **out)
+{
+    if (!ctx || !out)
+        return VQE_EINVAL;
+    *out = nullptr;
+    if (B < 1 || !items || !io || !io->theta || !io->energy_out || !io->g_out ||
+        !io->g_offset_host || !io->k_io || !io->gmax_out || !(rel_tie >= 0.0 && rel_tie < 1.0))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: bad arguments");
+    const int dtype = items[0].H ? items[0].H->dtype : -1;
+    for (int s = 0; s < B; s++) {
+        const vqe_batch_item &it = items[s];
+        int rc = check_csr(ctx, it.H, "vqe_batch_create");
+        if (rc)
+            return rc;
+        if (it.H->dtype != dtype)
+            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: states differ in dtype");
+        if (!it.pool || it.pool->M < 1 || !it.pool->ops || !it.pool->ops_host ||
+            it.pool->n_qubits != it.H->n_qubits || it.pool->dtype != dtype)
+            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: bad pool for state %d", s);
+        if (!it.pool->all_pairing)
+            return vqe_fail(ctx, VQE_ENOTSUP,
+                            "vqe_batch_create: state %d has a non-pairing generator", s);
+        if (!it.psi || !it.sigma)
+            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: null psi or sigma");
+        const int L = it.spmv_lanes;
+        if (L != 0 && L != 8 && L != 16 && L != 32 && L != 64)
+            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: bad spmv_lanes");
+    }
+
+    vqe_batch *p = new (std::nothrow) vqe_batch();
+    if (!p)
+        return VQE_ENOMEM;
+    p->ctx = ctx;
+    p->B = B;
+    p->dtype = dtype;
+    p->rel_tie = rel_tie;
+
+    // --- XCD assignment: largest H first onto the least loaded XCD
+    std::vector<int> order(B), xcd_of(B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return items[a].H->nnz > items[b].H->nnz; });
+    std::vector<double> load(kXcd, 0.0);
+    for (int s : order) {
+        int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        xcd_of[s] = x;
+        load[x] += (double)items[s].H->nnz * 12.0 + (double)items[s].H->dim * 20.0;
+    }
+
+    Arena A;
+    const size_t o_spmv = A.take(sizeof(SpmvState) * B);
+    const size_t o_sel = A.take(sizeof(SelectState) * B);
+    const size_t o_tay = A.take(sizeof(TaylorState) * B);
+    std::vector<int> lanes(B);
+    std::vector<size_t> o_epart(B), o_npart(B), o_gpart(B);
+    std::vector<int> nchunks(B), chunk_rows(B);
+    for (int s = 0; s < B; s++) {
+        const vqe_csr *H = items[s].H;
+        lanes[s] = items[s].spmv_lanes ? items[s].spmv_lanes : vqe_default_lanes(H);
+        o_epart[s] = A.take(vqe_spmv_partials_bytes(H->dim, lanes[s]));
+        const int64_t nn = (H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK;
+        o_npart[s] = A.take(nn * sizeof(double));
+        chunk_rows[s] = (int)std::min<int64_t>(H->dim, GRAD_CHUNK_ROWS);
+        nchunks[s] = (int)((H->dim + chunk_rows[s] - 1) / chunk_rows[s]);
+        o_gpart[s] = A.take((size_t)items[s].pool->M * nchunks[s] * sizeof(double));
+    }
+
+    // --- H product tasks, one table per lanes value
+    std::map<int, std::vector<std::vector<int2>>> per_lanes;
+    for (int s = 0; s < B; s++) {
+        auto &per = per_lanes[lanes[s]];
+        if (per.empty())
+            per.resize(kXcd);
+        const int rpb = spmv_rows_per_block(lanes[s]);
+        const int nb = (int)((items[s].H->dim + rpb - 1) / rpb);
+        for (int b = 0; b < nb; b++)
+            per[xcd_of[s]].push_back(make_int2(s, b));
+    }
+    std::vector<std::pair<int, size_t>> spmv_tab;
+    std::vector<std::vector<int2>> spmv_lists;
+    for (auto &kv : per_lanes) {
+        auto flat = interleave(kv.second, make_int2(-1, 0));
+        spmv_tab.push_back({kv.first, A.take(flat.size() * sizeof(int2))});
+        spmv_lists.push_back(std::move(flat));
+    }
+
+    // --- gradient groups: states sharing a pool on the same XCD, <= GRAD_MAX_GROUP each
+    std::map<std::pair<const void *, int>, std::vector<int>> by_pool;
+    for (int s = 0; s < B; s++)
+        by_pool[{(const void *)items[s].pool->ops, xcd_of[s]}].push_back(s);
+    struct GroupPlan {
+        int xcd;
+        std::vector<int> states;
+    };
+    std::vector<GroupPlan> groups;
+    for (auto &kv : by_pool)
+        for (size_t i = 0; i < kv.second.size(); i += GRAD_MAX_GROUP)
+            groups.push_back({kv.first.second,
+                              std::vector<int>(kv.second.begin() + i,
+                                               kv.second.begin() + std::min(kv.second.size(),
+                                                                            i + GRAD_MAX_GROUP))});
+    const size_t o_groups = A.take(sizeof(GradGroup) * groups.size());
+    std::vector<std::vector<int4>> grad_per(kXcd);
+    std::vector<int2> grad_items;
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        const int s0 = groups[gi].states[0];
+        const int M = items[s0].pool->M;
+        for (int j = 0; j < M; j++)
+            for (int c = 0; c < nchunks[s0]; c++)
+                grad_per[groups[gi].xcd].push_back(make_int4((int)gi, j, c, 0));
+        for (size_t k = 0; k < groups[gi].states.size(); k++)
+            grad_items.push_back(make_int2((int)gi, (int)k));
+    }
+    auto grad_flat = interleave(grad_per, make_int4(-1, 0, 0, 0));
+    const size_t o_gtasks = A.take(grad_flat.size() * sizeof(int4));
+    const size_t o_gitems = A.take(grad_items.size() * sizeof(int2));
+
+    // --- Taylor and norm tasks
+    std::vector<std::vector<int2>> tay_per(kXcd), norm_per(kXcd);
+    for (int s = 0; s < B; s++) {
+        const int64_t dim = items[s].H->dim;
+        const int nt = (int)((dim + TAYLOR_ROWS_PER_BLOCK - 1) / TAYLOR_ROWS_PER_BLOCK);
+        const int nn = (int)((dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
+        for (int b = 0; b < nt; b++)
+            tay_per[xcd_of[s]].push_back(make_int2(s, b));
+        for (int b = 0; b < nn; b++)
+            norm_per[xcd_of[s]].push_back(make_int2(s, b));
+    }
+    auto tay_flat = interleave(tay_per, make_int2(-1, 0));
+    auto norm_flat = interleave(norm_per, make_int2(-1, 0));
+    const size_t o_ttasks = A.take(tay_flat.size() * sizeof(int2));
+    const size_t o_ntasks = A.take(norm_flat.size() * sizeof(int2));
+
+    // --- allocate, then fill the host image with device addresses
+    p->dmem_bytes = A.host.size();
+    if (hipMalloc((void **)&p->dmem, p->dmem_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return vqe_fail(ctx, VQE_ENOMEM, "vqe_batch_create: allocation failed");
+    }
+    char *D = p->dmem;
+    for (int s = 0; s < B; s++) {
+        const vqe_batch_item &it = items[s];
+        SpmvState &st = A.at<SpmvState>(o_spmv)[s];
+        st.rowptr = it.H->rowptr;
+        st.col = it.H->col;
+        st.val = it.H->val;
+        st.psi = it.psi;
+        st.sigma = it.sigma;
+        st.partials = (double *)(D + o_epart[s]);
+        st.energy_out = io->energy_out + 3 * s;
+        st.dim = it.H->dim;
+        st.shift = it.H->diag_shift;
+        const int rpb = spmv_rows_per_block(lanes[s]);
+        st.nblocks = (int32_t)((it.H->dim + rpb - 1) / rpb);
+        st.lanes = lanes[s];
+
+        SelectState &se = A.at<SelectState>(o_sel)[s];
+        se.g = io->g_out + io->g_offset_host[s];
+        se.M = it.pool->M;
+        se.k_out = io->k_io + s;
+        se.gmax_out = io->gmax_out + s;
+
+        TaylorState &ts = A.at<TaylorState>(o_tay)[s];
+        ts.ops = it.pool->ops;
+        ts.k = io->k_io + s;
+        ts.M = it.pool->M;
+        ts.theta = io->theta + s;
+        ts.psi = it.psi;
+        ts.dim = it.H->dim;
+        ts.norm_partials = (double *)(D + o_npart[s]);
+        ts.norm2_out = nullptr;
+        ts.nblocks = (int32_t)((it.H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
+        ts.renorm = 1;
+    }
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        GradGroup &G = A.at<GradGroup>(o_groups)[gi];
+        const int s0 = groups[gi].states[0];
+        G.ops = items[s0].pool->ops;
+        G.M = items[s0].pool->M;
+        G.n_states = (int32_t)groups[gi].states.size();
+        G.nchunks = nchunks[s0];
+        G.chunk_rows = chunk_rows[s0];
+        G.dim = items[s0].H->dim;
+        for (size_t k = 0; k < groups[gi].states.size(); k++) {
+            const int s = groups[gi].states[k];
+            G.psi[k] = items[s].psi;
+            G.sigma[k] = items[s].sigma;
+            G.shift[k] = items[s].H->diag_shift;
+            G.partials[k] = (double *)(D + o_gpart[s]);
+            G.g_out[k] = io->g_out + io->g_offset_host[s];
+        }
+    }
+    for (size_t i = 0; i < spmv_tab.size(); i++) {
+        std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));
+        p->spmv.push_back({spmv_tab[i].first, (int2 *)(D + spmv_tab[i].second),
+                           (unsigned)spmv_lists[i].size()});
+    }
+    std::copy(grad_flat.begin(), grad_flat.end(), A.at<int4>(o_gtasks));
+    std::copy(grad_items.begin(), grad_items.end(), A.at<int2>(o_gitems));
+    std::copy(tay_flat.begin(), tay_flat.end(), A.at<int2>(o_ttasks));
+    std::copy(norm_flat.begin(), norm_flat.end(), A.at<int2>(o_ntasks));
+    p->d_spmv = (SpmvState *)(D + o_spmv);
+    p->d_sel = (SelectState *)(D + o_sel);
+    p->d_tay = (TaylorState *)(D + o_tay);
+    p->d_groups = (GradGroup *)(D + o_groups);
+    p->d_grad_tasks = (int4 *)(D + o_gtasks);
+    p->n_grad_tasks = (unsigned)grad_flat.size();
+    p->d_grad_items = (int2 *)(D + o_gitems);
+    p->n_grad_items = (unsigned)grad_items.size();
+    p->d_tay_tasks = (int2 *)(D + o_ttasks);
+    p->n_tay_tasks = (unsigned)tay_flat.size();
+    p->d_norm_tasks = (int2 *)(D + o_ntasks);
+    p->n_norm_tasks = (unsigned)norm_flat.size();
+    hipError_t e = hipMemcpyAsync(p->dmem, A.host.data(), p->dmem_bytes, hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        hipFree(p->dmem);
+        delete p;
+        return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_step(vqe_batch *p, uint32_t flags)
+{
+    if (!p)
+        return VQE_EINVAL;
+    vqe_ctx *ctx = p->ctx;
+    if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_step: unknown flags");
+    if (!(flags & VQE_STEP_GRAPH))
+        return enqueue_step(p, flags);
+    const unsigned key = flags & 7u;
+    if (!p->exec[key]) {
+        if (!ctx->stream)
+            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_step: graph capture needs a non-null stream");
+        VQE_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(p, flags);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        if (rc)
+            return rc;
+        if (e != hipSuccess)
+            return vqe_fail(ctx, VQE_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&p->exec[key], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            p->exec[key] = nullptr;
+            return vqe_fail(ctx, VQE_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        p->graph[key] = g;
+    }
+    VQE_HIP(ctx, hipGraphLaunch(p->exec[key], ctx->stream));
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_destroy(vqe_batch *p)
+{
+    if (!p)
+        return VQE_EINVAL;
+    hipStreamSynchronize(p->ctx->stream);
+    for (int i = 0; i < 16; i++) {
+        if (p->exec[i])
+            hipGraphExecDestroy(p->exec[i]);
+        if (p->graph[i])
+            hipGraphDestroy(p->graph[i]);
+    }
+    if (p->dmem)
+        hipFree(p->dmem);
+    delete p;
+    return VQE_OK;
+}
+
+extern "C" int64_t vqe_batch_workspace_bytes(const vqe_batch *p)
+{
+    return p ? (int64_t)p->dmem_bytes : -1;
+}

@@ -1,0 +1,95 @@
+// Device-side descriptors and launch helpers shared by the kernel sources and
+// the batch planner.
+#pragma once
+
+#include "common.hpp"
+
+// Rows per wave pass handled by one sub-group, and passes per workgroup.
+#define SPMV_RPT 2
+
+__host__ __device__ constexpr int spmv_rows_per_block(int lanes)
+{
+    return 4 * (VQE_WAVE / lanes) * SPMV_RPT;
+}
+
+// One state of an H product with the energy reduction.
+struct SpmvState {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const void *val;
+    const void *psi;
+    void *sigma;
+    double *partials;     // [nblocks * 3]
+    double *energy_out;   // [3]
+    int64_t dim;
+    double shift;
+    int32_t nblocks;
+    int32_t lanes;
+};
+
+// Rows of a pool operator handled by one workgroup of the gradient kernel.
+#define GRAD_CHUNK_ROWS 4096
+#define GRAD_MAX_GROUP 8
+
+// One group of states that share a pool and a dimension (gradient kernel).
+struct GradGroup {
+    const vqe_csr *ops;        // device array of the pool's descriptors
+    int32_t M;
+    int32_t n_states;          // <= GRAD_MAX_GROUP
+    int32_t nchunks;
+    int32_t chunk_rows;
+    int64_t dim;
+    const void *psi[GRAD_MAX_GROUP];
+    const void *sigma[GRAD_MAX_GROUP];
+    double shift[GRAD_MAX_GROUP];
+    double *partials[GRAD_MAX_GROUP];   // per state: [M * nchunks]
+    double *g_out[GRAD_MAX_GROUP];      // per state: [M]
+};
+
+// One state of the Taylor update.
+struct TaylorState {
+    const vqe_csr *ops;        // pool descriptors (device) when the index comes from k
+    const int32_t *k;          // device index into ops (nullable: use `op`)
+    int32_t M;                 // number of descriptors in ops (k outside [0, M) -> no update)
+    int32_t pad0;
+    vqe_csr op;                // the operator when k is null
+    const double *theta;       // device angle (nullable: use theta_value)
+    double theta_value;
+    void *psi;
+    int64_t dim;
+    double *norm_partials;     // [nblocks]
+    double *norm2_out;         // nullable
+    int32_t nblocks;
+    int32_t renorm;
+};
+
+// Per-state argmax.
+struct SelectState {
+    const double *g;
+    int32_t M;
+    int32_t *k_out;
+    double *gmax_out;
+};
+
+#define TAYLOR_ROWS_PER_BLOCK 256
+#define NORM_ROWS_PER_BLOCK 2048
+
+int check_csr(vqe_ctx *ctx, const vqe_csr *M, const char *what);
+int vqe_spmv_energy_core(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma,
+                         double *out, int lanes, double *partials);
+size_t vqe_spmv_partials_bytes(int64_t dim, int lanes);
+
+void launch_spmv(int dtype, int lanes, const SpmvState &single, const SpmvState *states,
+                 const int2 *tasks, unsigned grid, hipStream_t s);
+__global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
+
+void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, unsigned grid,
+                      hipStream_t s);
+void launch_grad_finalize(const GradGroup *groups, const int2 *items, unsigned n_items,
+                          hipStream_t s);
+void launch_select(const SelectState *states, unsigned n, double rel_tie, hipStream_t s);
+
+void launch_taylor_pair(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
+                        hipStream_t s);
+void launch_norm(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
+                 hipStream_t s);
