@@ -236,6 +236,15 @@ typedef struct vqe_batch vqe_batch;
 VQE_API int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *items,
                      const vqe_batch_io *io, double rel_tie, vqe_batch **out);
 VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
+/*
+ * The same step launched eagerly (VQE_STEP_GRAPH is rejected) while recording
+ * seven caller-created HIP events (hipEvent_t) on the context stream at the
+ * phase boundaries: [0] before the H products, [1] after them, [2] after the
+ * energy finalisation, [3] after the gradient screen, [4] after the selection,
+ * [5] after the Taylor update, [6] after the renormalisation.  Skipped phases
+ * record their events back to back.  n_events must be 7.
+ */
+VQE_API int vqe_batch_step_timed(vqe_batch *plan, uint32_t flags, void **events, int32_t n_events);
 VQE_API int vqe_batch_destroy(vqe_batch *plan);
 /* Bytes of device workspace the plan owns (for footprint accounting). */
 VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);

@@ -74,6 +74,7 @@ SIGNATURES = {
     "vqe_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_batch_item),
                                    C.POINTER(vqe_batch_io), C.c_double, C.POINTER(C.c_void_p)]),
     "vqe_batch_step": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "vqe_batch_step_timed": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p), C.c_int32]),
     "vqe_batch_destroy": (C.c_int, [C.c_void_p]),
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
@@ -362,6 +363,17 @@ class BatchPlan:
         flags = ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
                  | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0))
         self.ctx.check(lib().vqe_batch_step(self.handle, flags), "vqe_batch_step")
+
+    def step_timed(self, events, renorm: bool = True, forced: bool = False, update: bool = True):
+        """Eager step recording 7 torch.cuda.Event objects at the phase boundaries
+        on the context stream (see vqe_batch_step_timed)."""
+        flags = ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
+                 | (0 if update else VQE_STEP_NO_UPDATE))
+        for e in events:
+            if not e.cuda_event:          # torch creates the HIP event on first record
+                e.record(self.ctx.stream)
+        arr = (C.c_void_p * 7)(*[C.c_void_p(e.cuda_event) for e in events])
+        self.ctx.check(lib().vqe_batch_step_timed(self.handle, flags, arr, 7), "vqe_batch_step_timed")
 
     def gradients(self, s: int):
         M = self.states[s][1].M

@@ -178,25 +178,38 @@ std::vector<T> interleave(const std::vector<std::vector<T>> &per, const T &pad)
     return out;
 }
 
-int enqueue_step(vqe_batch *p, uint32_t flags)
+int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
 {
     vqe_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
+    auto mark = [&](int i) -> int {
+        if (ev)
+            VQE_HIP(ctx, hipEventRecord(ev[i], s));
+        return VQE_OK;
+    };
     SpmvState dummy{};
+    int rc = mark(0);
     for (auto &l : p->spmv)
         launch_spmv(p->dtype, l.lanes, dummy, p->d_spmv, l.tasks, l.grid, s);
+    rc = rc ? rc : mark(1);
     k_energy_finalize<<<(unsigned)p->B, 64, 0, s>>>(dummy, p->d_spmv, p->B);
+    rc = rc ? rc : mark(2);
     if (p->n_grad_tasks) {
         launch_pool_grad(p->dtype, p->d_groups, p->d_grad_tasks, p->n_grad_tasks, s);
         launch_grad_finalize(p->d_groups, p->d_grad_items, p->n_grad_items, s);
     }
+    rc = rc ? rc : mark(3);
     if (!(flags & VQE_STEP_FORCED))
         launch_select(p->d_sel, (unsigned)p->B, p->rel_tie, s);
-    if (!(flags & VQE_STEP_NO_UPDATE)) {
+    rc = rc ? rc : mark(4);
+    if (!(flags & VQE_STEP_NO_UPDATE))
         launch_taylor_pair(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
-        if (flags & VQE_STEP_RENORM)
-            launch_norm(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, s);
-    }
+    rc = rc ? rc : mark(5);
+    if (!(flags & VQE_STEP_NO_UPDATE) && (flags & VQE_STEP_RENORM))
+        launch_norm(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, s);
+    rc = rc ? rc : mark(6);
+    if (rc)
+        return rc;
     VQE_LAUNCH_CHECK(ctx);
     return VQE_OK;
 }
@@ -462,6 +475,20 @@ extern "C" int vqe_batch_step(vqe_batch *p, uint32_t flags)
     }
     VQE_HIP(ctx, hipGraphLaunch(p->exec[key], ctx->stream));
     return VQE_OK;
+}
+
+extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
+                                    int32_t n_events)
+{
+    if (!p)
+        return VQE_EINVAL;
+    if (!events || n_events != 7 || (flags & VQE_STEP_GRAPH) ||
+        (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE)))
+        return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step_timed: bad flags or events");
+    for (int i = 0; i < 7; i++)
+        if (!events[i])
+            return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step_timed: null event");
+    return enqueue_step(p, flags, reinterpret_cast<hipEvent_t *>(events));
 }
 
 extern "C" int vqe_batch_destroy(vqe_batch *p)

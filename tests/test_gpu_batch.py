@@ -1,0 +1,236 @@
+"""Batched steps (one launch sequence for many states, optionally a HIP graph).
+
+* batched results equal the single-call results bit for bit, whatever else is
+  in the batch (alone vs mixed);
+* every graph replay equals the eager step;
+* the FP32-storage batch matches the FP64 oracle (fidelity > 0.999999,
+  |dE| < 1e-6 Ha) at mixed register sizes;
+* at the benchmark's full size (64 states at 14 qubits, FP32 storage) sampled
+  energies and gradients match the oracle and invariants hold for all states.
+"""
+import numpy as np
+import pytest
+
+import vqe_system as vs
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2606_29692_amd import batch as PB  # noqa: E402
+from paper_2606_29692_amd import binding as B  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    # one non-default stream (graph capture needs one) shared by torch and the
+    # library, so torch's copies and the library's launches stay ordered
+    prev = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    c = B.Context(0, stream)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+    torch.cuda.set_stream(prev)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def mixed_specs():
+    specs = [vs.SystemSpec(8, 4, "jw", False, 101), vs.SystemSpec(10, 4, "bk", False, 102),
+             vs.SystemSpec(12, 8, "jw", True, 103), vs.SystemSpec(8, 4, "jw", False, 104),
+             vs.SystemSpec(12, 8, "bk", False, 105)]
+    return specs
+
+
+def single_step(ctx, ds, theta):
+    sigma = torch.empty_like(ds.psi)
+    out = B.energy(ctx, ds.H, ds.psi, sigma)
+    g = B.pool_gradients(ctx, ds.H, ds.pool, ds.psi, sigma)
+    k, gmax = B.vqe_select(ctx, g)
+    kk = int(host(k)[0])
+    B.taylor5_apply(ctx, ds.pool.ops[kk], float(theta), ds.psi, renormalize=True)
+    return host(out).copy(), host(g).copy(), kk, float(host(gmax)[0])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_equals_single_bitwise(ctx, dtype):
+    specs = mixed_specs()
+    pools = PB.PoolCache(ctx)
+    systems = [vs.make_system(s) for s in specs]
+    single = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+    batched = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+    plan = PB.make_batch(ctx, batched)
+    steps = 4
+    thetas = np.stack([vs.draw_thetas(s.seed, steps) for s in specs])
+    for t in range(steps):
+        print(f"batch vs single {dtype} step {t}", flush=True)
+        plan.theta.copy_(torch.from_numpy(thetas[:, t]))
+        plan.step(renorm=True)
+        e_b = host(plan.energies).reshape(-1, 3)
+        k_b = host(plan.k)
+        for i, ds in enumerate(single):
+            e, g, k, gm = single_step(ctx, ds, thetas[i, t])
+            np.testing.assert_array_equal(e_b[i], e)
+            np.testing.assert_array_equal(host(plan.gradients(i)), g)
+            assert int(k_b[i]) == k
+            assert float(host(plan.gmax)[i]) == gm
+    for ds_s, ds_b in zip(single, batched):
+        np.testing.assert_array_equal(host(ds_s.psi), host(ds_b.psi))
+    plan.close()
+
+
+def test_alone_vs_mixed_and_graph_replay(ctx):
+    specs = mixed_specs()
+    pools = PB.PoolCache(ctx)
+    systems = [vs.make_system(s) for s in specs]
+    mixed = [PB.device_system(ctx, s, "c64", pools) for s in systems]
+    alone = PB.device_system(ctx, systems[2], "c64", pools)
+    plan_m = PB.make_batch(ctx, mixed)
+    plan_a = PB.make_batch(ctx, [alone])
+    steps = 5
+    th = vs.draw_thetas(specs[2].seed, steps)
+    for t in range(steps):
+        plan_m.theta.fill_(0.05)
+        plan_m.theta[2] = float(th[t])
+        plan_a.theta.fill_(float(th[t]))
+        # graph replays for the mixed plan, eager launches for the single one
+        plan_m.step(renorm=True, graph=True)
+        plan_a.step(renorm=True, graph=False)
+        print(f"alone vs mixed step {t}", flush=True)
+        np.testing.assert_array_equal(host(plan_m.energies)[6:9], host(plan_a.energies)[0:3])
+        np.testing.assert_array_equal(host(plan_m.gradients(2)), host(plan_a.gradients(0)))
+        assert int(host(plan_m.k)[2]) == int(host(plan_a.k)[0])
+        np.testing.assert_array_equal(host(mixed[2].psi), host(alone.psi))
+    plan_m.close()
+    plan_a.close()
+
+
+def test_graph_replays_match_eager(ctx):
+    specs = mixed_specs()[:3]
+    pools = PB.PoolCache(ctx)
+    systems = [vs.make_system(s) for s in specs]
+    eager = [PB.device_system(ctx, s, "c128", pools) for s in systems]
+    graph = [PB.device_system(ctx, s, "c128", pools) for s in systems]
+    pe, pg = PB.make_batch(ctx, eager), PB.make_batch(ctx, graph)
+    for t in range(6):
+        th = torch.from_numpy(np.array([0.03, -0.07, 0.09]) * (t + 1) / 3)
+        pe.theta.copy_(th)
+        pg.theta.copy_(th)
+        pe.step(renorm=True)
+        pg.step(renorm=True, graph=True)
+        ctx.stream.synchronize()
+        # eager host work between replays
+        _ = host(pe.energies).sum()
+        np.testing.assert_array_equal(host(pg.energies), host(pe.energies))
+        np.testing.assert_array_equal(host(pg.g), host(pe.g))
+        np.testing.assert_array_equal(host(pg.k), host(pe.k))
+        for a, b in zip(eager, graph):
+            np.testing.assert_array_equal(host(a.psi), host(b.psi))
+    pe.close()
+    pg.close()
+
+
+def test_forced_and_screen_only(ctx):
+    spec = vs.SystemSpec(10, 4, "jw", False, 7)
+    s = vs.make_system(spec)
+    ds = PB.device_system(ctx, s, "c128")
+    plan = PB.make_batch(ctx, [ds])
+    plan.step(update=False)                           # screen only: psi unchanged
+    psi0 = host(ds.psi)
+    assert psi0[s.reference_index] == 1.0 and np.count_nonzero(psi0) == 1
+    plan.k.fill_(3)
+    plan.theta.fill_(0.1)
+    plan.step(forced=True, renorm=False)             # forced generator index 3
+    oA = orc.csr_from_pack(s.pool[3])
+    want = orc.taylor5(oA, 0.1, vs.reference_state(s))
+    assert np.linalg.norm(host(ds.psi) - want) <= 1e-12
+    plan.k.fill_(10_000)                              # out of range: no update
+    plan.step(forced=True, renorm=False)
+    assert np.linalg.norm(host(ds.psi) - want) <= 1e-12
+    plan.close()
+
+
+def _oracle_run(system, thetas, steps, forced=None):
+    oH = orc.csr_from_pack(system.hamiltonian)
+    return orc.adapt_run(oH, [orc.csr_from_pack(p) for p in system.pool],
+                         vs.reference_state(system), thetas, steps, forced=forced)
+
+
+def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
+    """Config C4 shape at reduced count: N cycling over 10/12/14, FP32 storage."""
+    specs, _ = vs.config_c4(n_states=6, mixed=True)
+    steps = 6
+    pools = PB.PoolCache(ctx)
+    systems = [vs.make_system(s) for s in specs]
+    ds = [PB.device_system(ctx, s, "c64", pools) for s in systems]
+    plan = PB.make_batch(ctx, ds)
+    thetas = np.stack([vs.draw_thetas(s.seed, steps) for s in specs])
+    E = np.zeros((steps + 1, len(specs)))
+    K = np.zeros((steps, len(specs)), dtype=np.int64)
+    G = []
+    for t in range(steps):
+        plan.theta.copy_(torch.from_numpy(thetas[:, t]))
+        plan.step(renorm=True, graph=True)
+        E[t] = host(plan.energies).reshape(-1, 3)[:, 0]
+        K[t] = host(plan.k)
+        G.append([host(plan.gradients(i)).copy() for i in range(len(specs))])
+    plan.step(update=False)
+    E[steps] = host(plan.energies).reshape(-1, 3)[:, 0]
+    for i, s in enumerate(systems):
+        tr = _oracle_run(s, thetas[i], steps, forced=K[:, i])
+        de = np.abs(E[:, i] - np.array(tr.energies)).max()
+        dg = max(np.abs(G[t][i] - tr.gradients[t]).max() for t in range(steps))
+        psi = host(ds[i].psi).astype(np.complex128)
+        fid = abs(np.vdot(psi, tr.psi)) ** 2 / (np.vdot(psi, psi).real * np.vdot(tr.psi, tr.psi).real)
+        print(f"state {i} N={specs[i].n_qubits}: max|dE|={de:.2e} max|dg|={dg:.2e} 1-F={1 - fid:.2e}")
+        assert de < 1e-6 and fid > 0.999999 and dg < 1e-5
+        # selection agrees with the oracle's rule applied to the oracle's gradients
+        for t in range(steps):
+            g_o = tr.gradients[t]
+            assert abs(g_o[K[t, i]]) >= np.abs(g_o).max() * (1 - 1e-5)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64"])
+def test_full_size_bench_config(ctx, dtype):
+    """64 states at 14 qubits (the benchmark workload): sampled states against
+    the oracle, invariants on every state."""
+    specs, _ = vs.config_c4(n_states=64, mixed=False)
+    pools = PB.PoolCache(ctx)
+    systems = [vs.make_system(s) for s in specs]
+    ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+    plan = PB.make_batch(ctx, ds)
+    thetas = np.stack([vs.draw_thetas(s.seed, 2) for s in specs])
+    snap_g, snap_e, snap_k = [], [], []
+    for t in range(2):
+        plan.theta.copy_(torch.from_numpy(thetas[:, t]))
+        plan.step(renorm=True, graph=True)
+        snap_e.append(host(plan.energies).reshape(-1, 3).copy())
+        snap_k.append(host(plan.k).copy())
+        snap_g.append(host(plan.g).copy())
+        print(f"full size step {t}", flush=True)
+    # invariants on every state: unit norm, amplitudes outside the sector exactly 0
+    for i, s in enumerate(systems):
+        psi = host(ds[i].psi).astype(np.complex128)
+        assert abs(np.linalg.norm(psi) - 1.0) < 1e-6
+        occ = np.arange(s.dim)
+        na = sum(((occ >> m) & 1) for m in range(0, 14, 2))
+        nb = sum(((occ >> m) & 1) for m in range(1, 14, 2))
+        outside = ~((na == 3) & (nb == 3))
+        assert np.all(psi[outside] == 0.0)
+    # sampled states against the oracle along the same selection
+    for i in (0, 21, 42, 63):
+        tr = _oracle_run(systems[i], thetas[i], 2, forced=[snap_k[0][i], snap_k[1][i]])
+        off = int(plan.g_offset[i])
+        for t in range(2):
+            assert abs(snap_e[t][i, 0] - tr.energies[t]) < 1e-6
+            np.testing.assert_allclose(snap_g[t][off:off + 204], tr.gradients[t], rtol=0, atol=1e-5)
+        psi = host(ds[i].psi).astype(np.complex128)
+        fid = abs(np.vdot(psi, tr.psi)) ** 2
+        assert fid > 0.999999
+    plan.close()
