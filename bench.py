@@ -108,7 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--states", type=int, default=64)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
-    ap.add_argument("--lanes", type=int, default=0, help="H product lanes per row (0: tuned/default)")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="H product schedule (lanes per row, | 256 for wide loads; 0: tuned)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -138,8 +139,11 @@ def main():
     ds = [PB.device_system(ctx, s, args.dtype, pools) for s in systems]
     torch.cuda.synchronize()
     log(f"setup: {len(ds)} systems built on the device in {time.perf_counter() - t0:.1f} s")
-    lanes = args.lanes or T.lanes_for(ctx, ds[0], systems=ds)
-    plan = PB.make_batch(ctx, ds, lanes=[lanes] * len(ds))
+    sched = args.schedule or T.schedule_for(ctx, ds[0], systems=ds)
+    if T._last_timings:
+        log("tuner (ms of the batched H product): " +
+            ", ".join(f"{k}: {v:.3f}" for k, v in sorted(T._last_timings.items())))
+    plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
     nbytes = PB.bytes_per_step(ds)
     K, W = args.steps, args.warmup
     rng = np.random.default_rng(np.random.SeedSequence([44, 1]))
@@ -221,7 +225,7 @@ def main():
                         f"launch sequence (H SpMV + FP64 energy, 204-generator gradient screen, "
                         f"argmax, fused Taylor-O(5), FP64 renorm)",
             "states": len(ds), "n_qubits": 14, "n_electrons": 6, "mapping": "jw",
-            "pool": 204, "storage": args.dtype, "spmv_lanes": lanes,
+            "pool": 204, "storage": args.dtype, "spmv_schedule": sched,
         },
         "pool_gradient_spmv_GBps": screen_gbs,
         "p50_step_ms": percentile(step_ms, 50),

@@ -212,7 +212,8 @@ typedef struct vqe_batch_item {
     const vqe_pool *pool;   /* host pointer to the state's pool */
     void *psi;
     void *sigma;
-    int32_t spmv_lanes;     /* lanes per row for the H product: 0 = default, else 8/16/32/64 */
+    int32_t spmv_schedule;  /* H product schedule: 0 = default, else lanes per row
+                               (8, 16, 32, 64), optionally | VQE_SPMV_VEC4 */
     int32_t reserved;
 } vqe_batch_item;
 
@@ -251,15 +252,26 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
 
 /* ------------------------------------------------------------------ tuning */
 /*
+ * H product schedules.  A schedule is the number of wave lanes that share one
+ * CSR row (8, 16, 32 or 64); with VQE_SPMV_VEC4 each lane reads four
+ * consecutive entries per pass with 16-byte index loads (16, 32 or 64 lanes;
+ * needs 16-byte aligned col and 32-byte aligned val, else the plain schedule
+ * with the same lanes is used).  The schedule fixes the summation order.
+ */
+#define VQE_SPMV_VEC4 0x100
+/* VQE_SPMV_LDS: wide loads plus the whole state vector staged in LDS by each
+ * workgroup (16, 32 or 64 lanes); needs dim * element size <= 156 KiB, else
+ * the VEC4 schedule with the same lanes is used. */
+#define VQE_SPMV_LDS 0x200
+/*
  * Time the H product (sigma = S psi with the energy reduction) with the given
- * lanes per row (8, 16, 32 or 64): `reps` back-to-back launches bracketed by
- * HIP events on the context stream; *ms_out = average milliseconds per launch.
- * Used by the schedule autotuner.
+ * schedule: `reps` back-to-back launches bracketed by HIP events on the
+ * context stream; *ms_out = average milliseconds per launch.
  */
 VQE_API int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma,
-                  int32_t lanes, int32_t reps, float *ms_out);
-/* Default lanes per row chosen for an operator when no tuning is given. */
-VQE_API int32_t vqe_default_lanes(const vqe_csr *H);
+                  int32_t schedule, int32_t reps, float *ms_out);
+/* Schedule used for an operator when none is given (energy(), pool_gradients()). */
+VQE_API int32_t vqe_default_schedule(const vqe_csr *H);
 
 #ifdef __cplusplus
 }

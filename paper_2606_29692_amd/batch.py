@@ -102,8 +102,8 @@ def device_system(ctx: B.Context, system, dtype: str = "c128", pools: PoolCache 
     return DeviceSystem(key, H, pool, psi, system.reference_index, dtype)
 
 
-def make_batch(ctx: B.Context, systems: list, lanes=None) -> B.BatchPlan:
-    return B.BatchPlan(ctx, [(s.H, s.pool, s.psi) for s in systems], lanes=lanes)
+def make_batch(ctx: B.Context, systems: list, schedules=None) -> B.BatchPlan:
+    return B.BatchPlan(ctx, [(s.H, s.pool, s.psi) for s in systems], schedules=schedules)
 
 
 def bytes_per_step(systems: list) -> dict:

@@ -20,6 +20,8 @@ VQE_OK, VQE_EINVAL, VQE_ESIZE, VQE_ENOMEM, VQE_EHIP, VQE_ENOTSUP = 0, -1, -2, -3
 VQE_C128, VQE_C64 = 0, 1
 VQE_PAIRING = 1
 VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_NO_UPDATE, VQE_STEP_GRAPH = 1, 2, 4, 8
+VQE_SPMV_VEC4 = 0x100
+VQE_SPMV_LDS = 0x200
 REL_TIE = 1e-6
 
 DTYPES = {"c128": VQE_C128, "c64": VQE_C64}
@@ -45,7 +47,7 @@ class vqe_pool(C.Structure):
 
 class vqe_batch_item(C.Structure):
     _fields_ = [("H", C.c_void_p), ("pool", C.c_void_p), ("psi", C.c_void_p),
-                ("sigma", C.c_void_p), ("spmv_lanes", C.c_int32), ("reserved", C.c_int32)]
+                ("sigma", C.c_void_p), ("spmv_schedule", C.c_int32), ("reserved", C.c_int32)]
 
 
 class vqe_batch_io(C.Structure):
@@ -79,7 +81,7 @@ SIGNATURES = {
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
-    "vqe_default_lanes": (C.c_int32, [C.POINTER(vqe_csr)]),
+    "vqe_default_schedule": (C.c_int32, [C.POINTER(vqe_csr)]),
 }
 
 _lib = None
@@ -301,15 +303,15 @@ def vqe_select(ctx: Context, g, rel_tie: float = REL_TIE, k_out=None, gmax_out=N
     return k_out, gmax_out
 
 
-def time_spmv(ctx: Context, H: DeviceCSR, psi, sigma, lanes: int, reps: int = 20) -> float:
+def time_spmv(ctx: Context, H: DeviceCSR, psi, sigma, schedule: int, reps: int = 20) -> float:
     ms = C.c_float()
-    ctx.check(lib().vqe_time_spmv(ctx.handle, C.byref(H.desc), _ptr(psi), _ptr(sigma), int(lanes),
+    ctx.check(lib().vqe_time_spmv(ctx.handle, C.byref(H.desc), _ptr(psi), _ptr(sigma), int(schedule),
                                   int(reps), C.byref(ms)), "vqe_time_spmv")
     return float(ms.value)
 
 
-def default_lanes(H: DeviceCSR) -> int:
-    return int(lib().vqe_default_lanes(C.byref(H.desc)))
+def default_schedule(H: DeviceCSR) -> int:
+    return int(lib().vqe_default_schedule(C.byref(H.desc)))
 
 
 class BatchPlan:
@@ -319,7 +321,7 @@ class BatchPlan:
     plan allocates sigma, theta, energies, gradients, indices and gmax as torch
     tensors that stay alive with it."""
 
-    def __init__(self, ctx: Context, states: list, lanes=None, rel_tie: float = REL_TIE):
+    def __init__(self, ctx: Context, states: list, schedules=None, rel_tie: float = REL_TIE):
         torch = _torch()
         self.ctx = ctx
         B = len(states)
@@ -343,7 +345,7 @@ class BatchPlan:
             items[s].pool = C.addressof(pool.desc)
             items[s].psi = psi.data_ptr()
             items[s].sigma = self.sigma[s].data_ptr()
-            items[s].spmv_lanes = int(lanes[s]) if lanes is not None else 0
+            items[s].spmv_schedule = int(schedules[s]) if schedules is not None else 0
         self._items = items
         io = vqe_batch_io()
         io.theta = self.theta.data_ptr()

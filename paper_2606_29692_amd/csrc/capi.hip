@@ -133,6 +133,7 @@ struct vqe_batch {
         int lanes;
         int2 *tasks;
         unsigned grid;
+        int64_t max_dim;
     };
     std::vector<SpmvLaunch> spmv;
     GradGroup *d_groups = nullptr;
@@ -190,7 +191,7 @@ int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
     SpmvState dummy{};
     int rc = mark(0);
     for (auto &l : p->spmv)
-        launch_spmv(p->dtype, l.lanes, dummy, p->d_spmv, l.tasks, l.grid, s);
+        launch_spmv(p->dtype, l.lanes, dummy, p->d_spmv, l.tasks, l.grid, s, l.max_dim);
     rc = rc ? rc : mark(1);
     k_energy_finalize<<<(unsigned)p->B, 64, 0, s>>>(dummy, p->d_spmv, p->B);
     rc = rc ? rc : mark(2);
@@ -241,9 +242,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
                             "vqe_batch_create: state %d has a non-pairing generator", s);
         if (!it.psi || !it.sigma)
             return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: null psi or sigma");
-        const int L = it.spmv_lanes;
-        if (L != 0 && L != 8 && L != 16 && L != 32 && L != 64)
-            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: bad spmv_lanes");
+        if (it.spmv_schedule != 0 && !vqe_valid_schedule(it.spmv_schedule))
+            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: bad spmv_schedule");
     }
 
     vqe_batch *p = new (std::nothrow) vqe_batch();
@@ -275,7 +275,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     std::vector<int> nchunks(B), chunk_rows(B);
     for (int s = 0; s < B; s++) {
         const vqe_csr *H = items[s].H;
-        lanes[s] = items[s].spmv_lanes ? items[s].spmv_lanes : vqe_default_lanes(H);
+        lanes[s] = vqe_effective_schedule(
+            H, items[s].spmv_schedule ? items[s].spmv_schedule : vqe_default_schedule(H));
         o_epart[s] = A.take(vqe_spmv_partials_bytes(H->dim, lanes[s]));
         const int64_t nn = (H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK;
         o_npart[s] = A.take(nn * sizeof(double));
@@ -290,17 +291,22 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         auto &per = per_lanes[lanes[s]];
         if (per.empty())
             per.resize(kXcd);
-        const int rpb = spmv_rows_per_block(lanes[s]);
-        const int nb = (int)((items[s].H->dim + rpb - 1) / rpb);
+        const int nb = (int)spmv_blocks(items[s].H->dim, lanes[s]);
         for (int b = 0; b < nb; b++)
             per[xcd_of[s]].push_back(make_int2(s, b));
     }
     std::vector<std::pair<int, size_t>> spmv_tab;
     std::vector<std::vector<int2>> spmv_lists;
+    std::vector<int64_t> spmv_maxdim;
     for (auto &kv : per_lanes) {
         auto flat = interleave(kv.second, make_int2(-1, 0));
         spmv_tab.push_back({kv.first, A.take(flat.size() * sizeof(int2))});
         spmv_lists.push_back(std::move(flat));
+        int64_t md = 0;
+        for (int s = 0; s < B; s++)
+            if (lanes[s] == kv.first)
+                md = std::max<int64_t>(md, items[s].H->dim);
+        spmv_maxdim.push_back(md);
     }
 
     // --- gradient groups: states sharing a pool on the same XCD, <= GRAD_MAX_GROUP each
@@ -370,9 +376,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         st.energy_out = io->energy_out + 3 * s;
         st.dim = it.H->dim;
         st.shift = it.H->diag_shift;
-        const int rpb = spmv_rows_per_block(lanes[s]);
-        st.nblocks = (int32_t)((it.H->dim + rpb - 1) / rpb);
+        st.nblocks = (int32_t)spmv_blocks(it.H->dim, lanes[s]);
         st.lanes = lanes[s];
+        st.nnz = it.H->nnz;
 
         SelectState &se = A.at<SelectState>(o_sel)[s];
         se.g = io->g_out + io->g_offset_host[s];
@@ -413,7 +419,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     for (size_t i = 0; i < spmv_tab.size(); i++) {
         std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));
         p->spmv.push_back({spmv_tab[i].first, (int2 *)(D + spmv_tab[i].second),
-                           (unsigned)spmv_lists[i].size()});
+                           (unsigned)spmv_lists[i].size(), spmv_maxdim[i]});
     }
     std::copy(grad_flat.begin(), grad_flat.end(), A.at<int4>(o_gtasks));
     std::copy(grad_items.begin(), grad_items.end(), A.at<int2>(o_gitems));

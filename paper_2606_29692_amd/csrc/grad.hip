@@ -47,10 +47,35 @@ k_pool_grad(GradGroup single, const GradGroup *__restrict__ groups, const int4 *
         shift[s] = s < ns ? G.shift[s] : 0.0;
         acc[s] = 0.0;
     }
+    const bool pairing = (op.flags & VQE_PAIRING) != 0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
         const int k0 = rowptr[r], k1 = rowptr[r + 1];
         if (k0 == k1)
             continue;
+        if (pairing) {
+            // pair {r, c} with A[r,c] = a, A[c,r] = b, handled by its lower row:
+            // conj(sigma_r) a psi_c + conj(sigma_c) b psi_r
+            const int64_t c = col[k0];
+            if (c < r)
+                continue;
+            const double2 a = Elem<DT>::ld(op.val, k0);
+            const double2 b = c == r ? make_double2(0.0, 0.0) : Elem<DT>::ld(op.val, rowptr[c]);
+#pragma unroll
+            for (int s = 0; s < GRAD_MAX_GROUP; s++) {
+                if (s < ns) {
+                    const double2 pr = Elem<DT>::ld(psi[s], r);
+                    const double2 pc = Elem<DT>::ld(psi[s], c);
+                    const double2 qr = Elem<DT>::ld(sig[s], r);
+                    const double2 qc = Elem<DT>::ld(sig[s], c);
+                    const double sr_x = qr.x + shift[s] * pr.x, sr_y = qr.y + shift[s] * pr.y;
+                    const double sc_x = qc.x + shift[s] * pc.x, sc_y = qc.y + shift[s] * pc.y;
+                    const double wr = a.x * pc.x - a.y * pc.y, wi = a.x * pc.y + a.y * pc.x;
+                    const double ur = b.x * pr.x - b.y * pr.y, ui = b.x * pr.y + b.y * pr.x;
+                    acc[s] += (sr_x * wr + sr_y * wi) + (sc_x * ur + sc_y * ui);
+                }
+            }
+            continue;
+        }
         double2 sg[GRAD_MAX_GROUP];
 #pragma unroll
         for (int s = 0; s < GRAD_MAX_GROUP; s++) {
@@ -188,7 +213,7 @@ int vqe_pool_grad_launch(vqe_ctx *ctx, const vqe_csr *H, const vqe_pool *pool, c
     if (M == 0)
         return VQE_OK;
     // workspace: [gradient partials][product partials][sigma][energy]
-    const int lanes = vqe_default_lanes(H);
+    const int lanes = vqe_effective_schedule(H, vqe_default_schedule(H));
     const size_t o_sp = vqe_align((size_t)M * nchunks * sizeof(double));
     const size_t o_sigma = o_sp + vqe_spmv_partials_bytes(dim, lanes);
     const size_t o_e = o_sigma + vqe_align(dim * vqe_elem_bytes(H->dtype));

@@ -7,9 +7,13 @@
 // Rows per wave pass handled by one sub-group, and passes per workgroup.
 #define SPMV_RPT 2
 
-__host__ __device__ constexpr int spmv_rows_per_block(int lanes)
+// A schedule is the lanes per row (8, 16, 32, 64), optionally | VQE_SPMV_VEC4
+// or | VQE_SPMV_LDS.  The LDS schedule gives each workgroup SPMV_LDS_ROWS rows.
+#define SPMV_LDS_ROWS 2048
+#define SPMV_LDS_MAX_BYTES (156 * 1024)
+__host__ __device__ constexpr int spmv_rows_per_block(int sched)
 {
-    return 4 * (VQE_WAVE / lanes) * SPMV_RPT;
+    return 4 * (VQE_WAVE / (sched & 0xff)) * SPMV_RPT;
 }
 
 // One state of an H product with the energy reduction.
@@ -22,13 +26,14 @@ struct SpmvState {
     double *partials;     // [nblocks * 3]
     double *energy_out;   // [3]
     int64_t dim;
+    int64_t nnz;
     double shift;
     int32_t nblocks;
     int32_t lanes;
 };
 
 // Rows of a pool operator handled by one workgroup of the gradient kernel.
-#define GRAD_CHUNK_ROWS 4096
+#define GRAD_CHUNK_ROWS 1024
 #define GRAD_MAX_GROUP 8
 
 // One group of states that share a pool and a dimension (gradient kernel).
@@ -78,9 +83,12 @@ int check_csr(vqe_ctx *ctx, const vqe_csr *M, const char *what);
 int vqe_spmv_energy_core(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma,
                          double *out, int lanes, double *partials);
 size_t vqe_spmv_partials_bytes(int64_t dim, int lanes);
+bool vqe_valid_schedule(int sched);
+int vqe_effective_schedule(const vqe_csr *H, int sched);
 
 void launch_spmv(int dtype, int lanes, const SpmvState &single, const SpmvState *states,
-                 const int2 *tasks, unsigned grid, hipStream_t s);
+                 const int2 *tasks, unsigned grid, hipStream_t s, int64_t max_dim);
+int64_t spmv_blocks(int64_t dim, int sched);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 
 void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, unsigned grid,

@@ -13,7 +13,78 @@
 
 namespace {
 
-template <int DT, int L, bool BATCH>
+// V = entries per lane per pass.  V = 1: lane l of the sub-group takes
+// entries k0 + l, k0 + l + L, ...  V = 4: lanes take aligned groups of four
+// consecutive entries (one 16-byte index load and 32- or 64-byte value loads),
+// masked to the row; a 64-lane sub-group covers 256 entries per pass.
+template <int DT, int V> struct RowLoad;
+
+template <int DT> struct RowLoad<DT, 1> {
+    using T = typename Elem<DT>::T;
+    static __device__ __forceinline__ void load(const int32_t *col, const T *val, int k, int k0,
+                                                int k1, int64_t nnz, int c[1], T v[1])
+    {
+        (void)k0;
+        (void)nnz;
+        if (k < k1) {
+            c[0] = __builtin_nontemporal_load(col + k);
+            v[0] = val[k];
+        } else {
+            c[0] = -1;
+        }
+    }
+};
+
+// Four consecutive values from a 32-byte (c64) or 64-byte (c128) aligned address.
+__device__ __forceinline__ void load4(const float2 *p, float2 v[4])
+{
+    const float4 a = reinterpret_cast<const float4 *>(p)[0];
+    const float4 b = reinterpret_cast<const float4 *>(p)[1];
+    v[0] = make_float2(a.x, a.y);
+    v[1] = make_float2(a.z, a.w);
+    v[2] = make_float2(b.x, b.y);
+    v[3] = make_float2(b.z, b.w);
+}
+
+__device__ __forceinline__ void load4(const double2 *p, double2 v[4])
+{
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        v[u] = p[u];
+}
+
+template <int DT> struct RowLoad<DT, 4> {
+    using T = typename Elem<DT>::T;
+    static __device__ __forceinline__ void load(const int32_t *col, const T *val, int k, int k0,
+                                                int k1, int64_t nnz, int c[4], T v[4])
+    {
+        if ((int64_t)k + 3 < nnz) {
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const v4i c4 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(col + k));
+            c[0] = c4.x;
+            c[1] = c4.y;
+            c[2] = c4.z;
+            c[3] = c4.w;
+            load4(val + k, v);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if ((int64_t)(k + u) < nnz) {
+                    c[u] = col[k + u];
+                    v[u] = val[k + u];
+                } else {
+                    c[u] = -1;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (k + u < k0 || k + u >= k1)
+                c[u] = -1;
+    }
+};
+
+template <int DT, int L, int V, bool BATCH>
 __global__ void __launch_bounds__(256)
 k_spmv_energy(SpmvState single, const SpmvState *__restrict__ states,
               const int2 *__restrict__ tasks)
@@ -32,35 +103,30 @@ k_spmv_energy(SpmvState single, const SpmvState *__restrict__ states,
     }
     constexpr int G = VQE_WAVE / L;
     constexpr int RPB = spmv_rows_per_block(L);
-    constexpr int U = 4;
+    constexpr int U = V == 1 ? 4 : 1;     // passes issued together
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int sub = lane / L, sl = lane % L;
     const int32_t *__restrict__ rowptr = st.rowptr;
     const int32_t *__restrict__ col = st.col;
-    using V = typename Elem<DT>::T;
-    const V *__restrict__ val = reinterpret_cast<const V *>(st.val);
+    using T = typename Elem<DT>::T;
+    const T *__restrict__ val = reinterpret_cast<const T *>(st.val);
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
 #pragma unroll
     for (int it = 0; it < SPMV_RPT; it++) {
         const int64_t r = (int64_t)blk * RPB + (it * 4 + wid) * G + sub;
         double are = 0.0, aim = 0.0;
         if (r < st.dim) {
-            const int k1 = rowptr[r + 1];
-            for (int k = rowptr[r] + sl; k < k1; k += U * L) {
-                int c[U];
-                V v[U];
+            const int k0 = rowptr[r], k1 = rowptr[r + 1];
+            const int first = V == 1 ? k0 + sl : (k0 & ~3) + 4 * sl;
+            for (int k = first; k < k1; k += U * V * L) {
+                int c[U * V];
+                T v[U * V];
 #pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const int kk = k + u * L;
-                    if (kk < k1) {
-                        c[u] = __builtin_nontemporal_load(col + kk);
-                        v[u] = val[kk];
-                    } else {
-                        c[u] = -1;
-                    }
-                }
+                for (int u = 0; u < U; u++)
+                    RowLoad<DT, V>::load(col, val, k + u * V * L, k0, k1, st.nnz, c + u * V,
+                                         v + u * V);
 #pragma unroll
-                for (int u = 0; u < U; u++) {
+                for (int u = 0; u < U * V; u++) {
                     if (c[u] >= 0) {
                         const double2 x = Elem<DT>::ld(st.psi, c[u]);
                         const double ar = (double)v[u].x, ai = (double)v[u].y;
@@ -97,6 +163,99 @@ k_spmv_energy(SpmvState single, const SpmvState *__restrict__ states,
     }
 }
 
+// The whole state vector staged in LDS (one 128 KB copy for 14 qubits in
+// FP32 storage), so every gather of the product is an LDS read instead of an
+// L2 request.  A workgroup of 16 waves owns SPMV_LDS_ROWS consecutive rows of
+// one state; sub-groups of L lanes read their rows with the four-entry wide
+// loads, U passes in flight.
+template <int DT, int L, int U, bool BATCH>
+__global__ void __launch_bounds__(1024)
+k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    SpmvState st;
+    int blk;
+    if (BATCH) {
+        int2 t = tasks[blockIdx.x];
+        if (t.x < 0)
+            return;
+        st = states[t.x];
+        blk = t.y;
+    } else {
+        st = single;
+        blk = blockIdx.x;
+    }
+    using T = typename Elem<DT>::T;
+    extern __shared__ unsigned char smem[];
+    T *s_x = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x;
+    const int64_t dim = st.dim;
+    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    for (int64_t i = tid; i < dim; i += 1024)
+        s_x[i] = psi[i];
+    __syncthreads();
+
+    constexpr int G = VQE_WAVE / L;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int sub = lane / L, sl = lane % L;
+    const int32_t *__restrict__ rowptr = st.rowptr;
+    const int32_t *__restrict__ col = st.col;
+    const T *__restrict__ val = reinterpret_cast<const T *>(st.val);
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
+    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
+    for (int64_t base = r0 + wid * G; base < r1; base += 16 * G) {
+        const int64_t r = base + sub;
+        double are = 0.0, aim = 0.0;
+        if (r < r1) {
+            const int k0 = rowptr[r], k1 = rowptr[r + 1];
+            for (int k = (k0 & ~3) + 4 * sl; k < k1; k += U * 4 * L) {
+                int c[U * 4];
+                T v[U * 4];
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0, k1, st.nnz, c + 4 * u,
+                                         v + 4 * u);
+#pragma unroll
+                for (int u = 0; u < U * 4; u++) {
+                    if (c[u] >= 0) {
+                        const T xs = s_x[c[u]];
+                        const double xr = (double)xs.x, xi = (double)xs.y;
+                        const double ar = (double)v[u].x, ai = (double)v[u].y;
+                        are += ar * xr - ai * xi;
+                        aim += ar * xi + ai * xr;
+                    }
+                }
+            }
+        }
+        are = group_sum<L>(are);
+        aim = group_sum<L>(aim);
+        if (sl == 0 && r < r1) {
+            Elem<DT>::st(st.sigma, r, make_double2(are, aim));
+            const T ps = s_x[r];
+            const double px = (double)ps.x, py = (double)ps.y;
+            e_re += px * are + py * aim;
+            e_im += px * aim - py * are;
+            e_n2 += px * px + py * py;
+        }
+    }
+    __shared__ double s_part[16][3];
+    e_re = wave_sum(e_re);
+    e_im = wave_sum(e_im);
+    e_n2 = wave_sum(e_n2);
+    if (lane == 0) {
+        s_part[wid][0] = e_re;
+        s_part[wid][1] = e_im;
+        s_part[wid][2] = e_n2;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double v = 0.0;
+        for (int w = 0; w < 16; w++)
+            v += s_part[w][tid];
+        st.partials[(int64_t)blk * 3 + tid] = v;
+    }
+}
+
 }  // namespace
 
 // One wave per state: fixed-order sum of the block partials, then
@@ -125,43 +284,102 @@ k_energy_finalize(SpmvState single, const SpmvState *__restrict__ states, int n_
     }
 }
 
-template <int DT, int L>
+template <int DT, int L, int V>
 static void launch_spmv_t(const SpmvState &single, const SpmvState *states, const int2 *tasks,
                           unsigned grid, hipStream_t s)
 {
     if (tasks)
-        k_spmv_energy<DT, L, true><<<grid, 256, 0, s>>>(single, states, tasks);
+        k_spmv_energy<DT, L, V, true><<<grid, 256, 0, s>>>(single, states, tasks);
     else
-        k_spmv_energy<DT, L, false><<<grid, 256, 0, s>>>(single, states, tasks);
+        k_spmv_energy<DT, L, V, false><<<grid, 256, 0, s>>>(single, states, tasks);
 }
 
-void launch_spmv(int dtype, int lanes, const SpmvState &single, const SpmvState *states,
-                 const int2 *tasks, unsigned grid, hipStream_t s)
+template <int DT, int L, int U>
+static void launch_spmv_lds_t(const SpmvState &single, const SpmvState *states, const int2 *tasks,
+                              unsigned grid, hipStream_t s, size_t lds)
 {
-    if (dtype == VQE_C128) {
-        switch (lanes) {
-        case 8: launch_spmv_t<VQE_C128, 8>(single, states, tasks, grid, s); break;
-        case 16: launch_spmv_t<VQE_C128, 16>(single, states, tasks, grid, s); break;
-        case 32: launch_spmv_t<VQE_C128, 32>(single, states, tasks, grid, s); break;
-        default: launch_spmv_t<VQE_C128, 64>(single, states, tasks, grid, s); break;
-        }
+    if (tasks) {
+        auto k = k_spmv_lds<DT, L, U, true>;
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        k<<<grid, 1024, lds, s>>>(single, states, tasks);
     } else {
-        switch (lanes) {
-        case 8: launch_spmv_t<VQE_C64, 8>(single, states, tasks, grid, s); break;
-        case 16: launch_spmv_t<VQE_C64, 16>(single, states, tasks, grid, s); break;
-        case 32: launch_spmv_t<VQE_C64, 32>(single, states, tasks, grid, s); break;
-        default: launch_spmv_t<VQE_C64, 64>(single, states, tasks, grid, s); break;
-        }
+        auto k = k_spmv_lds<DT, L, U, false>;
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        k<<<grid, 1024, lds, s>>>(single, states, tasks);
     }
 }
 
-extern "C" int32_t vqe_default_lanes(const vqe_csr *H)
+template <int DT>
+static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *states,
+                           const int2 *tasks, unsigned grid, hipStream_t s, size_t lds)
+{
+    switch (sched) {
+    case 16 | VQE_SPMV_LDS: launch_spmv_lds_t<DT, 16, 2>(single, states, tasks, grid, s, lds); return;
+    case 32 | VQE_SPMV_LDS: launch_spmv_lds_t<DT, 32, 2>(single, states, tasks, grid, s, lds); return;
+    case 64 | VQE_SPMV_LDS: launch_spmv_lds_t<DT, 64, 1>(single, states, tasks, grid, s, lds); return;
+    default: break;
+    }
+    switch (sched) {
+    case 8: launch_spmv_t<DT, 8, 1>(single, states, tasks, grid, s); break;
+    case 16: launch_spmv_t<DT, 16, 1>(single, states, tasks, grid, s); break;
+    case 32: launch_spmv_t<DT, 32, 1>(single, states, tasks, grid, s); break;
+    case 64: launch_spmv_t<DT, 64, 1>(single, states, tasks, grid, s); break;
+    case 16 | VQE_SPMV_VEC4: launch_spmv_t<DT, 16, 4>(single, states, tasks, grid, s); break;
+    case 32 | VQE_SPMV_VEC4: launch_spmv_t<DT, 32, 4>(single, states, tasks, grid, s); break;
+    default: launch_spmv_t<DT, 64, 4>(single, states, tasks, grid, s); break;
+    }
+}
+
+void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState *states,
+                 const int2 *tasks, unsigned grid, hipStream_t s, int64_t max_dim)
+{
+    const size_t lds = (size_t)max_dim * vqe_elem_bytes(dtype);
+    if (dtype == VQE_C128)
+        launch_spmv_dt<VQE_C128>(sched, single, states, tasks, grid, s, lds);
+    else
+        launch_spmv_dt<VQE_C64>(sched, single, states, tasks, grid, s, lds);
+}
+
+bool vqe_valid_schedule(int sched)
+{
+    switch (sched) {
+    case 8: case 16: case 32: case 64:
+    case 16 | VQE_SPMV_VEC4: case 32 | VQE_SPMV_VEC4: case 64 | VQE_SPMV_VEC4:
+    case 16 | VQE_SPMV_LDS: case 32 | VQE_SPMV_LDS: case 64 | VQE_SPMV_LDS:
+        return true;
+    default:
+        return false;
+    }
+}
+
+// Wide loads need 16-byte aligned column and 32-byte aligned value arrays; the
+// LDS schedule also needs the state to fit in LDS.  Otherwise the plain
+// schedule with the same lanes is used.
+int vqe_effective_schedule(const vqe_csr *H, int sched)
+{
+    const bool wide = (sched & (VQE_SPMV_VEC4 | VQE_SPMV_LDS)) != 0;
+    if (wide && ((((uintptr_t)H->col) & 15) != 0 || (((uintptr_t)H->val) & 31) != 0))
+        return sched & 0xff;
+    if ((sched & VQE_SPMV_LDS) && H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES)
+        return (sched & 0xff) | VQE_SPMV_VEC4;
+    return sched;
+}
+
+int64_t spmv_blocks(int64_t dim, int sched)
+{
+    const int64_t rpb = (sched & VQE_SPMV_LDS) ? SPMV_LDS_ROWS : spmv_rows_per_block(sched);
+    return (dim + rpb - 1) / rpb;
+}
+
+extern "C" int32_t vqe_default_schedule(const vqe_csr *H)
 {
     if (!H || H->dim <= 0)
         return 32;
     const double avg = (double)H->nnz / (double)H->dim;
     if (avg >= 96.0)
-        return 64;
+        return 64 | VQE_SPMV_VEC4;
     if (avg >= 40.0)
         return 32;
     if (avg >= 12.0)
@@ -188,8 +406,8 @@ int vqe_spmv_energy_core(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *
                          double *out, int lanes, double *partials)
 {
     const int64_t dim = H->dim;
-    const int rpb = spmv_rows_per_block(lanes);
-    const int64_t nblk = (dim + rpb - 1) / rpb;
+    lanes = vqe_effective_schedule(H, lanes);
+    const int64_t nblk = spmv_blocks(dim, lanes);
     SpmvState st{};
     st.rowptr = H->rowptr;
     st.col = H->col;
@@ -202,7 +420,8 @@ int vqe_spmv_energy_core(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *
     st.shift = H->diag_shift;
     st.nblocks = (int32_t)nblk;
     st.lanes = lanes;
-    launch_spmv(H->dtype, lanes, st, nullptr, nullptr, (unsigned)nblk, ctx->stream);
+    st.nnz = H->nnz;
+    launch_spmv(H->dtype, lanes, st, nullptr, nullptr, (unsigned)nblk, ctx->stream, dim);
     k_energy_finalize<<<1, 64, 0, ctx->stream>>>(st, nullptr, 1);
     VQE_LAUNCH_CHECK(ctx);
     return VQE_OK;
@@ -210,8 +429,9 @@ int vqe_spmv_energy_core(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *
 
 size_t vqe_spmv_partials_bytes(int64_t dim, int lanes)
 {
-    const int rpb = spmv_rows_per_block(lanes);
-    return vqe_align((size_t)((dim + rpb - 1) / rpb) * 3 * sizeof(double));
+    // the larger of the two block counts, so any schedule fits
+    const int64_t a = spmv_blocks(dim, lanes & 0xff), b = spmv_blocks(dim, lanes);
+    return vqe_align((size_t)(a > b ? a : b) * 3 * sizeof(double));
 }
 
 int vqe_spmv_energy_launch(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma,
@@ -238,11 +458,11 @@ extern "C" int energy(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sig
         return rc;
     if (!psi || !out)
         return vqe_fail(ctx, VQE_EINVAL, "energy: null psi or out");
-    return vqe_spmv_energy_launch(ctx, H, psi, sigma_out, out, vqe_default_lanes(H));
+    return vqe_spmv_energy_launch(ctx, H, psi, sigma_out, out, vqe_default_schedule(H));
 }
 
 extern "C" int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma,
-                             int32_t lanes, int32_t reps, float *ms_out)
+                             int32_t schedule, int32_t reps, float *ms_out)
 {
     if (!ctx)
         return VQE_EINVAL;
@@ -251,8 +471,9 @@ extern "C" int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, vo
         return rc;
     if (!psi || !sigma || !ms_out || reps < 1)
         return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: bad arguments");
-    if (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64)
-        return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: lanes must be 8, 16, 32 or 64");
+    if (!vqe_valid_schedule(schedule))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: unknown schedule %d", schedule);
+    const int lanes = schedule;
     // energy result goes after the partials in the workspace
     const size_t o_out = vqe_spmv_partials_bytes(H->dim, lanes);
     rc = vqe_ws_reserve(ctx, o_out + 256);
@@ -273,8 +494,8 @@ extern "C" int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, vo
     VQE_HIP(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
     VQE_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *ms_out = ms / (float)reps;
     return rc;
 }

@@ -1,8 +1,9 @@
-"""Schedule autotuner for the H product (lanes per row).
+"""Schedule autotuner for the H product.
 
-The lanes-per-row choice (8, 16, 32 or 64 lanes of a wave per CSR row) is
-picked per (register size, dtype, mapping, device) by timing the batched H
-product phase of a real plan over the candidates, and cached.  The choice is
+A schedule is the number of wave lanes per CSR row (8, 16, 32, 64), with or
+without the four-entries-per-lane wide loads (VQE_SPMV_VEC4).  It is picked
+per (register size, dtype, mapping, device) by timing the batched H product
+phase of a real plan over the candidates, and cached.  The choice is
 a function of that key alone, so a state gets the same schedule (and the same
 floating-point summation order) whether it runs alone or inside any batch.
 
@@ -18,10 +19,12 @@ import numpy as np
 
 from . import binding as B
 
-CANDIDATES = (8, 16, 32, 64)
+CANDIDATES = (8, 16, 32, 64, 16 | B.VQE_SPMV_VEC4, 32 | B.VQE_SPMV_VEC4, 64 | B.VQE_SPMV_VEC4,
+              16 | B.VQE_SPMV_LDS, 32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}
+_last_timings: dict = {}
 
 
 def _key(ctx, ds) -> str:
@@ -51,11 +54,11 @@ def _store(key: str, rec: dict):
         json.dump(data, f, indent=1, sort_keys=True)
 
 
-def time_batch_spmv(ctx, systems, lanes: int, reps: int = 10) -> float:
-    """Average milliseconds of the batched H-product phase with the given lanes."""
+def time_batch_spmv(ctx, systems, schedule: int, reps: int = 10) -> float:
+    """Median milliseconds of the batched H-product phase with the given schedule."""
     import torch
     from .batch import make_batch
-    plan = make_batch(ctx, systems, lanes=[lanes] * len(systems))
+    plan = make_batch(ctx, systems, schedules=[schedule] * len(systems))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
     for _ in range(3):
         plan.step(update=False)
@@ -68,15 +71,17 @@ def time_batch_spmv(ctx, systems, lanes: int, reps: int = 10) -> float:
     return float(np.median(times))
 
 
-def tune_lanes(ctx, systems, candidates=CANDIDATES) -> dict:
+def tune_schedule(ctx, systems, candidates=CANDIDATES) -> dict:
     """Time every candidate on the given (same-size) systems; return the record."""
-    res = {int(L): time_batch_spmv(ctx, systems, L) for L in candidates}
+    res = {int(c): time_batch_spmv(ctx, systems, c) for c in candidates}
+    _last_timings.clear()
+    _last_timings.update(res)
     best = min(res, key=res.get)
-    return {"lanes": best, "ms": res}
+    return {"schedule": best, "ms": {str(k): v for k, v in res.items()}}
 
 
-def lanes_for(ctx, ds, systems=None, retune: bool = False) -> int:
-    """Tuned lanes for systems shaped like ``ds`` (tuning on ``systems`` or
+def schedule_for(ctx, ds, systems=None, retune: bool = False) -> int:
+    """Tuned schedule for systems shaped like ``ds`` (tuning on ``systems`` or
     [ds] when no cached entry exists)."""
     key = _key(ctx, ds)
     if not retune:
@@ -84,13 +89,17 @@ def lanes_for(ctx, ds, systems=None, retune: bool = False) -> int:
             return _memo[key]
         cache = _load()
         if key in cache:
-            _memo[key] = int(cache[key]["lanes"])
+            _memo[key] = int(cache[key]["schedule"])
             return _memo[key]
-    rec = tune_lanes(ctx, systems or [ds])
-    _memo[key] = rec["lanes"]
+    rec = tune_schedule(ctx, systems or [ds])
+    _memo[key] = rec["schedule"]
     _store(key, rec)
-    return rec["lanes"]
+    return rec["schedule"]
 
 
-def default_lanes(ds) -> int:
-    return B.default_lanes(ds.H)
+def last_record(ctx, ds) -> dict | None:
+    return _load().get(_key(ctx, ds))
+
+
+def default_schedule(ds) -> int:
+    return B.default_schedule(ds.H)

@@ -196,15 +196,16 @@ def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
     plan.close()
 
 
-@pytest.mark.parametrize("dtype", ["c64"])
-def test_full_size_bench_config(ctx, dtype):
-    """64 states at 14 qubits (the benchmark workload): sampled states against
-    the oracle, invariants on every state."""
+@pytest.mark.parametrize("sched", [0, 32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS])
+def test_full_size_bench_config(ctx, sched):
+    """64 states at 14 qubits in FP32 storage (the benchmark workload):
+    sampled states against the oracle, invariants on every state."""
+    dtype = "c64"
     specs, _ = vs.config_c4(n_states=64, mixed=False)
     pools = PB.PoolCache(ctx)
     systems = [vs.make_system(s) for s in specs]
     ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
-    plan = PB.make_batch(ctx, ds)
+    plan = PB.make_batch(ctx, ds, schedules=[sched] * 64 if sched else None)
     thetas = np.stack([vs.draw_thetas(s.seed, 2) for s in specs])
     snap_g, snap_e, snap_k = [], [], []
     for t in range(2):
@@ -233,4 +234,35 @@ def test_full_size_bench_config(ctx, dtype):
         psi = host(ds[i].psi).astype(np.complex128)
         fid = abs(np.vdot(psi, tr.psi)) ** 2
         assert fid > 0.999999
+    plan.close()
+
+
+@pytest.mark.parametrize("sched", [8, 16, 32, 64, 16 | B.VQE_SPMV_VEC4, 32 | B.VQE_SPMV_VEC4,
+                                   64 | B.VQE_SPMV_VEC4, 16 | B.VQE_SPMV_LDS,
+                                   32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS])
+def test_every_spmv_schedule_matches_oracle(ctx, sched):
+    """Each H-product schedule, batched over mixed sizes, against the oracle."""
+    specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx)
+    ds = [PB.device_system(ctx, s, "c128", pools) for s in systems]
+    rng = np.random.default_rng(sched)
+    psis = []
+    for d in ds:
+        v = rng.standard_normal(d.H.dim) + 1j * rng.standard_normal(d.H.dim)
+        v /= np.linalg.norm(v)
+        d.psi.copy_(torch.from_numpy(v))
+        psis.append(v)
+    plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
+    plan.step(update=False)
+    e = host(plan.energies).reshape(-1, 3)
+    for i, s in enumerate(systems):
+        oH = orc.csr_from_pack(s.hamiltonian)
+        e_o, n2, im, sig = orc.energy(oH, psis[i])
+        assert abs(e[i, 0] - e_o) <= 1e-12 * max(1.0, abs(e_o))
+        sg = host(plan.sigma[i])
+        assert np.linalg.norm(sg - sig) <= 1e-12 * np.linalg.norm(sig)
+        g_o = orc.gradients([orc.csr_from_pack(p) for p in s.pool], psis[i], sig)
+        np.testing.assert_allclose(host(plan.gradients(i)), g_o, rtol=0,
+                                   atol=1e-12 * max(1.0, np.abs(g_o).max()))
     plan.close()
