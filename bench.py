@@ -193,6 +193,21 @@ def main():
     log(f"timed: {ms_per_step:.3f} ms/step eager+events, {graph_ms:.3f} ms/step graph; "
         f"H product {spmv_avg * 1e3:.1f} us ({achieved:.0f} GB/s), screen {screen_avg * 1e3:.1f} us")
 
+    # practical HBM ceiling for context: a plain device copy (read + write) of 2 GiB
+    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+
     plain = None
     if not args.no_plain:
         tr, sr = plain_fp64_path(ctx, systems[0], 200)
@@ -231,6 +246,7 @@ def main():
         "p50_step_ms": percentile(step_ms, 50),
         "p99_step_ms": percentile(step_ms, 99),
         "graph_ms_per_step": graph_ms,
+        "device_copy_GBps": copy_gbs,
         "phase_ms": {"h_spmv": spmv_avg, "screen": screen_avg,
                      "taylor": float(np.mean(taylor_ms)), "renorm": float(np.mean(norm_ms))},
         "algorithmic_bytes_per_step": nbytes,

@@ -136,11 +136,13 @@ struct vqe_batch {
         int64_t max_dim;
     };
     std::vector<SpmvLaunch> spmv;
-    GradGroup *d_groups = nullptr;
-    int4 *d_grad_tasks = nullptr;
-    unsigned n_grad_tasks = 0;
-    int2 *d_grad_items = nullptr;
-    unsigned n_grad_items = 0;
+    ScreenState *d_screen = nullptr;
+    PairTable *d_tables = nullptr;
+    int4 *d_screen_tasks = nullptr;
+    unsigned n_screen_tasks = 0;
+    size_t screen_lds = 0;
+    std::vector<void *> table_mem;   // one allocation per distinct pool
+    size_t table_bytes = 0;
     SelectState *d_sel = nullptr;
     TaylorState *d_tay = nullptr;
     int2 *d_tay_tasks = nullptr;
@@ -195,10 +197,9 @@ int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
     rc = rc ? rc : mark(1);
     k_energy_finalize<<<(unsigned)p->B, 64, 0, s>>>(dummy, p->d_spmv, p->B);
     rc = rc ? rc : mark(2);
-    if (p->n_grad_tasks) {
-        launch_pool_grad(p->dtype, p->d_groups, p->d_grad_tasks, p->n_grad_tasks, s);
-        launch_grad_finalize(p->d_groups, p->d_grad_items, p->n_grad_items, s);
-    }
+    if (p->n_screen_tasks)
+        launch_screen(p->dtype, p->d_screen, p->d_tables, p->d_screen_tasks, p->n_screen_tasks,
+                      (unsigned)p->B, p->screen_lds, s);
     rc = rc ? rc : mark(3);
     if (!(flags & VQE_STEP_FORCED))
         launch_select(p->d_sel, (unsigned)p->B, p->rel_tie, s);
@@ -272,7 +273,6 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     const size_t o_tay = A.take(sizeof(TaylorState) * B);
     std::vector<int> lanes(B);
     std::vector<size_t> o_epart(B), o_npart(B), o_gpart(B);
-    std::vector<int> nchunks(B), chunk_rows(B);
     for (int s = 0; s < B; s++) {
         const vqe_csr *H = items[s].H;
         lanes[s] = vqe_effective_schedule(
@@ -280,9 +280,6 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         o_epart[s] = A.take(vqe_spmv_partials_bytes(H->dim, lanes[s]));
         const int64_t nn = (H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK;
         o_npart[s] = A.take(nn * sizeof(double));
-        chunk_rows[s] = (int)std::min<int64_t>(H->dim, GRAD_CHUNK_ROWS);
-        nchunks[s] = (int)((H->dim + chunk_rows[s] - 1) / chunk_rows[s]);
-        o_gpart[s] = A.take((size_t)items[s].pool->M * nchunks[s] * sizeof(double));
     }
 
     // --- H product tasks, one table per lanes value
@@ -309,36 +306,48 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         spmv_maxdim.push_back(md);
     }
 
-    // --- gradient groups: states sharing a pool on the same XCD, <= GRAD_MAX_GROUP each
-    std::map<std::pair<const void *, int>, std::vector<int>> by_pool;
-    for (int s = 0; s < B; s++)
-        by_pool[{(const void *)items[s].pool->ops, xcd_of[s]}].push_back(s);
-    struct GroupPlan {
-        int xcd;
-        std::vector<int> states;
-    };
-    std::vector<GroupPlan> groups;
-    for (auto &kv : by_pool)
-        for (size_t i = 0; i < kv.second.size(); i += GRAD_MAX_GROUP)
-            groups.push_back({kv.first.second,
-                              std::vector<int>(kv.second.begin() + i,
-                                               kv.second.begin() + std::min(kv.second.size(),
-                                                                            i + GRAD_MAX_GROUP))});
-    const size_t o_groups = A.take(sizeof(GradGroup) * groups.size());
-    std::vector<std::vector<int4>> grad_per(kXcd);
-    std::vector<int2> grad_items;
-    for (size_t gi = 0; gi < groups.size(); gi++) {
-        const int s0 = groups[gi].states[0];
-        const int M = items[s0].pool->M;
-        for (int j = 0; j < M; j++)
-            for (int c = 0; c < nchunks[s0]; c++)
-                grad_per[groups[gi].xcd].push_back(make_int4((int)gi, j, c, 0));
-        for (size_t k = 0; k < groups[gi].states.size(); k++)
-            grad_items.push_back(make_int2((int)gi, (int)k));
+    // --- gradient screen: one pair table per distinct pool; tasks per
+    //     (state, row tile, generator range), on the state's XCD
+    std::map<const void *, int> table_of;
+    std::vector<PairTable> tables;
+    for (int s = 0; s < B; s++) {
+        const void *key = (const void *)items[s].pool->ops;
+        if (table_of.count(key))
+            continue;
+        PairTable tb{};
+        void *mem[2] = {nullptr, nullptr};
+        size_t bytes = 0;
+        int rc = pair_table_build(ctx, items[s].pool, items[s].H->dim, &tb, mem, &bytes);
+        if (rc) {
+            for (void *m : p->table_mem)
+                (void)hipFree(m);
+            delete p;
+            return rc;
+        }
+        table_of[key] = (int)tables.size();
+        tables.push_back(tb);
+        for (void *m : mem)
+            if (m)
+                p->table_mem.push_back(m);
+        p->table_bytes += bytes;
     }
-    auto grad_flat = interleave(grad_per, make_int4(-1, 0, 0, 0));
-    const size_t o_gtasks = A.take(grad_flat.size() * sizeof(int4));
-    const size_t o_gitems = A.take(grad_items.size() * sizeof(int2));
+    const size_t o_tables = A.take(sizeof(PairTable) * tables.size());
+    const size_t o_screen = A.take(sizeof(ScreenState) * B);
+    std::vector<std::vector<int4>> screen_per(kXcd);
+    const int n_ranges = 2;
+    for (int s = 0; s < B; s++) {
+        const PairTable &tb = tables[table_of[(const void *)items[s].pool->ops]];
+        const int M = tb.M;
+        const int per = (M + n_ranges - 1) / n_ranges;
+        for (int t = 0; t < tb.nt; t++)
+            for (int j0 = 0; j0 < M; j0 += per)
+                screen_per[xcd_of[s]].push_back(make_int4(s, t, j0, std::min(M, j0 + per)));
+        const int64_t rows = std::min<int64_t>(tb.tile_rows, items[s].H->dim);
+        p->screen_lds = std::max(p->screen_lds, (size_t)(2 * rows * vqe_elem_bytes(dtype)));
+        o_gpart[s] = A.take((size_t)M * tb.nt * sizeof(double));
+    }
+    auto screen_flat = interleave(screen_per, make_int4(-1, 0, 0, 0));
+    const size_t o_stasks = A.take(screen_flat.size() * sizeof(int4));
 
     // --- Taylor and norm tasks
     std::vector<std::vector<int2>> tay_per(kXcd), norm_per(kXcd);
@@ -360,6 +369,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     p->dmem_bytes = A.host.size();
     if (hipMalloc((void **)&p->dmem, p->dmem_bytes) != hipSuccess) {
         (void)hipGetLastError();
+        for (void *m : p->table_mem)
+            (void)hipFree(m);
         delete p;
         return vqe_fail(ctx, VQE_ENOMEM, "vqe_batch_create: allocation failed");
     }
@@ -398,41 +409,32 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ts.nblocks = (int32_t)((it.H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
         ts.renorm = 1;
     }
-    for (size_t gi = 0; gi < groups.size(); gi++) {
-        GradGroup &G = A.at<GradGroup>(o_groups)[gi];
-        const int s0 = groups[gi].states[0];
-        G.ops = items[s0].pool->ops;
-        G.M = items[s0].pool->M;
-        G.n_states = (int32_t)groups[gi].states.size();
-        G.nchunks = nchunks[s0];
-        G.chunk_rows = chunk_rows[s0];
-        G.dim = items[s0].H->dim;
-        for (size_t k = 0; k < groups[gi].states.size(); k++) {
-            const int s = groups[gi].states[k];
-            G.psi[k] = items[s].psi;
-            G.sigma[k] = items[s].sigma;
-            G.shift[k] = items[s].H->diag_shift;
-            G.partials[k] = (double *)(D + o_gpart[s]);
-            G.g_out[k] = io->g_out + io->g_offset_host[s];
-        }
+    std::copy(tables.begin(), tables.end(), A.at<PairTable>(o_tables));
+    for (int s = 0; s < B; s++) {
+        ScreenState &ss = A.at<ScreenState>(o_screen)[s];
+        ss.psi = items[s].psi;
+        ss.sigma = items[s].sigma;
+        ss.shift = items[s].H->diag_shift;
+        ss.partials = (double *)(D + o_gpart[s]);
+        ss.g_out = io->g_out + io->g_offset_host[s];
+        ss.dim = items[s].H->dim;
+        ss.table = table_of[(const void *)items[s].pool->ops];
     }
     for (size_t i = 0; i < spmv_tab.size(); i++) {
         std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));
         p->spmv.push_back({spmv_tab[i].first, (int2 *)(D + spmv_tab[i].second),
                            (unsigned)spmv_lists[i].size(), spmv_maxdim[i]});
     }
-    std::copy(grad_flat.begin(), grad_flat.end(), A.at<int4>(o_gtasks));
-    std::copy(grad_items.begin(), grad_items.end(), A.at<int2>(o_gitems));
+    std::copy(screen_flat.begin(), screen_flat.end(), A.at<int4>(o_stasks));
     std::copy(tay_flat.begin(), tay_flat.end(), A.at<int2>(o_ttasks));
     std::copy(norm_flat.begin(), norm_flat.end(), A.at<int2>(o_ntasks));
     p->d_spmv = (SpmvState *)(D + o_spmv);
     p->d_sel = (SelectState *)(D + o_sel);
     p->d_tay = (TaylorState *)(D + o_tay);
-    p->d_groups = (GradGroup *)(D + o_groups);
-    p->d_grad_tasks = (int4 *)(D + o_gtasks);
-    p->n_grad_tasks = (unsigned)grad_flat.size();
-    p->d_grad_items = (int2 *)(D + o_gitems);
-    p->n_grad_items = (unsigned)grad_items.size();
+    p->d_tables = (PairTable *)(D + o_tables);
+    p->d_screen = (ScreenState *)(D + o_screen);
+    p->d_screen_tasks = (int4 *)(D + o_stasks);
+    p->n_screen_tasks = (unsigned)screen_flat.size();
     p->d_tay_tasks = (int2 *)(D + o_ttasks);
     p->n_tay_tasks = (unsigned)tay_flat.size();
     p->d_norm_tasks = (int2 *)(D + o_ntasks);
@@ -442,7 +444,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     if (e == hipSuccess)
         e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
-        hipFree(p->dmem);
+        (void)hipFree(p->dmem);
+        for (void *m : p->table_mem)
+            (void)hipFree(m);
         delete p;
         return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: %s", hipGetErrorString(e));
     }
@@ -509,12 +513,14 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
             hipGraphDestroy(p->graph[i]);
     }
     if (p->dmem)
-        hipFree(p->dmem);
+        (void)hipFree(p->dmem);
+    for (void *m : p->table_mem)
+        (void)hipFree(m);
     delete p;
     return VQE_OK;
 }
 
 extern "C" int64_t vqe_batch_workspace_bytes(const vqe_batch *p)
 {
-    return p ? (int64_t)p->dmem_bytes : -1;
+    return p ? (int64_t)(p->dmem_bytes + p->table_bytes) : -1;
 }

@@ -76,6 +76,39 @@ struct SelectState {
     double *gmax_out;
 };
 
+// Pair table of a pool of pairing generators (built once per batch plan).
+#define SCREEN_LDS_BYTES (128 * 1024)
+struct PairTable {
+    const int32_t *pts;     // [M * nt + 1]: start of (generator j, tile t)
+    const int32_t *pr;      // lower row of each pair
+    const int32_t *pc;      // partner row
+    const void *pa;         // A[r, c]
+    const void *pb;         // A[c, r] (0 when c == r)
+    const uint32_t *words;  // compact form (nullable): r | sign(A[r,c]) << 30 | sign(A[c,r]) << 31
+    const int32_t *xmask;   // compact form: per generator, c = r ^ xmask[j]
+    int32_t M;
+    int32_t nt;             // row tiles
+    int32_t tile_rows;
+    int32_t pad;
+};
+
+struct ScreenState {
+    const void *psi;
+    const void *sigma;
+    double shift;
+    double *partials;       // [M * nt]
+    double *g_out;          // [M]
+    int64_t dim;
+    int32_t table;          // index into the plan's PairTable array
+    int32_t pad;
+};
+
+int32_t screen_tile_rows(int64_t dim, int dtype);
+int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable *tb,
+                     void **mem_out, size_t *bytes_out);
+void launch_screen(int dtype, const ScreenState *states, const PairTable *tables,
+                   const int4 *tasks, unsigned grid, unsigned n_states, size_t lds, hipStream_t s);
+
 #define TAYLOR_ROWS_PER_BLOCK 256
 #define NORM_ROWS_PER_BLOCK 2048
 
