@@ -149,64 +149,71 @@ def main():
     rng = np.random.default_rng(np.random.SeedSequence([44, 1]))
     thetas = torch.from_numpy(rng.uniform(-0.1, 0.1, size=(K + W, len(ds)))).to("cuda")
 
-    # warm-up (untimed), then the timed region: K eager steps, each recording
-    # its phase events on the library stream
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(K)]
+    # warm-up (untimed; also captures the two graphs), then the timed region:
+    # K steps, each the H-product graph and the rest-of-step graph, with HIP
+    # events recorded on the library stream around the H-product graph
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
     for t in range(W):
         plan.theta.copy_(thetas[t])
-        plan.step(renorm=True)
+        plan.step(renorm=True, graph=True)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
     t_host = time.perf_counter()
     for t in range(K):
         plan.theta.copy_(thetas[W + t])
-        plan.step_timed(ev[t], renorm=True)
+        plan.step_timed(ev[t], renorm=True, graph=True)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_host
     total_ms = start.elapsed_time(stop)
     ms_per_step = total_ms / K
-    step_ms = [e[0].elapsed_time(e[6]) for e in ev]
+    step_ms = [e[0].elapsed_time(e[2]) for e in ev]
     spmv_ms = [e[0].elapsed_time(e[1]) for e in ev]
-    screen_ms = [e[2].elapsed_time(e[3]) for e in ev]
-    taylor_ms = [e[4].elapsed_time(e[5]) for e in ev]
-    norm_ms = [e[5].elapsed_time(e[6]) for e in ev]
+    rest_ms = [e[1].elapsed_time(e[2]) for e in ev]
     spmv_avg = float(np.mean(spmv_ms))
-    screen_avg = float(np.mean(screen_ms))
     updates_per_s = len(ds) * K / (total_ms / 1e3)
     achieved = nbytes["h_spmv"] / (spmv_avg / 1e3) / 1e9
-    screen_gbs = (nbytes["h_spmv"] + nbytes["pool_screen"]) / ((spmv_avg + screen_avg) / 1e3) / 1e9
 
-    # the same step replayed as a HIP graph (context figure)
-    for t in range(3):
-        plan.step(renorm=True, graph=True)
+    # phase breakdown of the same step launched eagerly (context figures)
+    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(10)]
+    for t in range(10):
+        plan.step_timed(ev2[t], renorm=True)
     torch.cuda.synchronize()
-    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    g0.record(stream)
-    for t in range(K):
-        plan.theta.copy_(thetas[W + t])
-        plan.step(renorm=True, graph=True)
-    g1.record(stream)
-    torch.cuda.synchronize()
-    graph_ms = g0.elapsed_time(g1) / K
-    log(f"timed: {ms_per_step:.3f} ms/step eager+events, {graph_ms:.3f} ms/step graph; "
-        f"H product {spmv_avg * 1e3:.1f} us ({achieved:.0f} GB/s), screen {screen_avg * 1e3:.1f} us")
+    screen_avg = float(np.mean([e[2].elapsed_time(e[3]) for e in ev2]))
+    taylor_avg = float(np.mean([e[4].elapsed_time(e[5]) for e in ev2]))
+    norm_avg = float(np.mean([e[5].elapsed_time(e[6]) for e in ev2]))
+    eager_spmv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev2]))
+    eager_step = float(np.mean([e[0].elapsed_time(e[6]) for e in ev2]))
+    screen_gbs = (nbytes["h_spmv"] + nbytes["pool_screen"]) / ((spmv_avg + screen_avg) / 1e3) / 1e9
+    log(f"timed: {ms_per_step:.3f} ms/step (graphs); H product {spmv_avg * 1e3:.1f} us "
+        f"({achieved:.0f} GB/s), rest of step {np.mean(rest_ms) * 1e3:.1f} us; eager: step "
+        f"{eager_step * 1e3:.1f} us, H {eager_spmv * 1e3:.1f} us, screen {screen_avg * 1e3:.1f} us, "
+        f"Taylor {taylor_avg * 1e3:.1f} us, renorm {norm_avg * 1e3:.1f} us")
 
     # practical HBM ceiling for context: a plain device copy (read + write) of 2 GiB
-    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+    # (an elementwise kernel, dst = src * 1, so profilers see it as a kernel)
+    src = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     c0.record(stream)
     for _ in range(5):
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
     c1.record(stream)
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del src, dst
-    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    acc = src.sum()
+    s0.record(stream)
+    for _ in range(5):
+        acc = src.sum()
+    s1.record(stream)
+    torch.cuda.synchronize()
+    read_gbs = 5 * src.numel() * 8 / (s0.elapsed_time(s1) / 1e3) / 1e9
+    del src, dst, acc
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write); device sum: {read_gbs:.0f} GB/s (read)")
 
     plain = None
     if not args.no_plain:
@@ -245,14 +252,18 @@ def main():
         "pool_gradient_spmv_GBps": screen_gbs,
         "p50_step_ms": percentile(step_ms, 50),
         "p99_step_ms": percentile(step_ms, 99),
-        "graph_ms_per_step": graph_ms,
+        "eager_ms_per_step": eager_step,
         "device_copy_GBps": copy_gbs,
-        "phase_ms": {"h_spmv": spmv_avg, "screen": screen_avg,
-                     "taylor": float(np.mean(taylor_ms)), "renorm": float(np.mean(norm_ms))},
+        "device_read_GBps": read_gbs,
+        "phase_ms": {"h_spmv": spmv_avg, "rest_of_step": float(np.mean(rest_ms)),
+                     "screen_eager": screen_avg, "taylor_eager": taylor_avg,
+                     "renorm_eager": norm_avg},
         "algorithmic_bytes_per_step": nbytes,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_spmv_energy (64 H products, one launch)"},
+                     "kernel": "H product of all 64 states (one launch of k_spmv_lds or "
+                               "k_spmv_energy, per the schedule)",
+                     "bytes_per_launch": nbytes["h_spmv"]},
         "plain_fp64_single_request": plain,
         "cpu_baseline": cpu,
         "host_wall_s": wall,

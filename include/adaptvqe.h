@@ -229,8 +229,9 @@ typedef struct vqe_batch_io {
 #define VQE_STEP_RENORM 1u      /* renormalise every state after its update */
 #define VQE_STEP_FORCED 2u      /* take k from k_io instead of selecting */
 #define VQE_STEP_NO_UPDATE 4u   /* screen only: energy, gradients, selection */
-#define VQE_STEP_GRAPH 8u       /* launch through a captured HIP graph (captured
-                                   once per flag set, then replayed) */
+#define VQE_STEP_GRAPH 8u       /* launch through captured HIP graphs: one for the
+                                   H products, one per flag set for the rest
+                                   (captured on first use, then replayed) */
 
 typedef struct vqe_batch vqe_batch;
 
@@ -238,12 +239,14 @@ VQE_API int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *item
                      const vqe_batch_io *io, double rel_tie, vqe_batch **out);
 VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
 /*
- * The same step launched eagerly (VQE_STEP_GRAPH is rejected) while recording
- * seven caller-created HIP events (hipEvent_t) on the context stream at the
- * phase boundaries: [0] before the H products, [1] after them, [2] after the
- * energy finalisation, [3] after the gradient screen, [4] after the selection,
- * [5] after the Taylor update, [6] after the renormalisation.  Skipped phases
- * record their events back to back.  n_events must be 7.
+ * The same step while recording caller-created HIP events (hipEvent_t) on the
+ * context stream.  n_events = 3: [0] before the H products, [1] after them,
+ * [2] at the end of the step (eager, or with VQE_STEP_GRAPH the H-product
+ * graph and the rest-of-step graph with the events between them).
+ * n_events = 7 (eager only): [0] before the H products, [1] after them,
+ * [2] after the energy finalisation, [3] after the gradient screen, [4] after
+ * the selection, [5] after the Taylor update, [6] after the renormalisation;
+ * skipped phases record their events back to back.
  */
 VQE_API int vqe_batch_step_timed(vqe_batch *plan, uint32_t flags, void **events, int32_t n_events);
 VQE_API int vqe_batch_destroy(vqe_batch *plan);
@@ -260,9 +263,14 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  */
 #define VQE_SPMV_VEC4 0x100
 /* VQE_SPMV_LDS: wide loads plus the whole state vector staged in LDS by each
- * workgroup (16, 32 or 64 lanes); needs dim * element size <= 156 KiB, else
- * the VEC4 schedule with the same lanes is used. */
+ * workgroup (8, 16, 32 or 64 lanes; VQE_SPMV_DEEP doubles the loads kept in
+ * flight per lane); needs dim * element size <= 156 KiB, else the VEC4
+ * schedule with the same lanes (16 for 8) is used. */
 #define VQE_SPMV_LDS 0x200
+#define VQE_SPMV_DEEP 0x400
+/* VQE_SPMV_PREFETCH (with VQE_SPMV_LDS; 32 or 64 lanes): each sub-group
+ * issues the loads of its next row before multiplying the current one. */
+#define VQE_SPMV_PREFETCH 0x800
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given
  * schedule: `reps` back-to-back launches bracketed by HIP events on the

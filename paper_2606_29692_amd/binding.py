@@ -22,6 +22,8 @@ VQE_PAIRING = 1
 VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_NO_UPDATE, VQE_STEP_GRAPH = 1, 2, 4, 8
 VQE_SPMV_VEC4 = 0x100
 VQE_SPMV_LDS = 0x200
+VQE_SPMV_DEEP = 0x400
+VQE_SPMV_PREFETCH = 0x800
 REL_TIE = 1e-6
 
 DTYPES = {"c128": VQE_C128, "c64": VQE_C64}
@@ -366,16 +368,18 @@ class BatchPlan:
                  | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0))
         self.ctx.check(lib().vqe_batch_step(self.handle, flags), "vqe_batch_step")
 
-    def step_timed(self, events, renorm: bool = True, forced: bool = False, update: bool = True):
-        """Eager step recording 7 torch.cuda.Event objects at the phase boundaries
-        on the context stream (see vqe_batch_step_timed)."""
+    def step_timed(self, events, renorm: bool = True, forced: bool = False, update: bool = True,
+                   graph: bool = False):
+        """Step recording 3 or 7 torch.cuda.Event objects on the context stream
+        (see vqe_batch_step_timed)."""
         flags = ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
-                 | (0 if update else VQE_STEP_NO_UPDATE))
+                 | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0))
         for e in events:
             if not e.cuda_event:          # torch creates the HIP event on first record
                 e.record(self.ctx.stream)
-        arr = (C.c_void_p * 7)(*[C.c_void_p(e.cuda_event) for e in events])
-        self.ctx.check(lib().vqe_batch_step_timed(self.handle, flags, arr, 7), "vqe_batch_step_timed")
+        n = len(events)
+        arr = (C.c_void_p * n)(*[C.c_void_p(e.cuda_event) for e in events])
+        self.ctx.check(lib().vqe_batch_step_timed(self.handle, flags, arr, n), "vqe_batch_step_timed")
 
     def gradients(self, s: int):
         M = self.states[s][1].M

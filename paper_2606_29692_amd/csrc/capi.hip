@@ -151,6 +151,9 @@ struct vqe_batch {
     unsigned n_norm_tasks = 0;
     hipGraphExec_t exec[16] = {};
     hipGraph_t graph[16] = {};
+    bool compact_taylor = false;   // every pool has a compact pair table
+    hipGraphExec_t exec_spmv = nullptr;
+    hipGraph_t graph_spmv = nullptr;
 };
 
 namespace {
@@ -181,7 +184,19 @@ std::vector<T> interleave(const std::vector<std::vector<T>> &per, const T &pad)
     return out;
 }
 
-int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
+// The step is two launch sequences: the H products (sequence A) and the rest
+// (sequence B: energy finalisation, screen, selection, Taylor update,
+// renormalisation).  `ev` (nullable) receives the phase events.
+int enqueue_spmv(vqe_batch *p)
+{
+    SpmvState dummy{};
+    for (auto &l : p->spmv)
+        launch_spmv(p->dtype, l.lanes, dummy, p->d_spmv, l.tasks, l.grid, p->ctx->stream, l.max_dim);
+    VQE_LAUNCH_CHECK(p->ctx);
+    return VQE_OK;
+}
+
+int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
 {
     vqe_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
@@ -191,12 +206,8 @@ int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
         return VQE_OK;
     };
     SpmvState dummy{};
-    int rc = mark(0);
-    for (auto &l : p->spmv)
-        launch_spmv(p->dtype, l.lanes, dummy, p->d_spmv, l.tasks, l.grid, s, l.max_dim);
-    rc = rc ? rc : mark(1);
     k_energy_finalize<<<(unsigned)p->B, 64, 0, s>>>(dummy, p->d_spmv, p->B);
-    rc = rc ? rc : mark(2);
+    int rc = mark(2);
     if (p->n_screen_tasks)
         launch_screen(p->dtype, p->d_screen, p->d_tables, p->d_screen_tasks, p->n_screen_tasks,
                       (unsigned)p->B, p->screen_lds, s);
@@ -204,8 +215,12 @@ int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
     if (!(flags & VQE_STEP_FORCED))
         launch_select(p->d_sel, (unsigned)p->B, p->rel_tie, s);
     rc = rc ? rc : mark(4);
-    if (!(flags & VQE_STEP_NO_UPDATE))
-        launch_taylor_pair(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
+    if (!(flags & VQE_STEP_NO_UPDATE)) {
+        if (p->compact_taylor)
+            launch_taylor_compact(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
+        else
+            launch_taylor_pair(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
+    }
     rc = rc ? rc : mark(5);
     if (!(flags & VQE_STEP_NO_UPDATE) && (flags & VQE_STEP_RENORM))
         launch_norm(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, s);
@@ -213,6 +228,84 @@ int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
     if (rc)
         return rc;
     VQE_LAUNCH_CHECK(ctx);
+    return VQE_OK;
+}
+
+int enqueue_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev = nullptr)
+{
+    if (ev)
+        VQE_HIP(p->ctx, hipEventRecord(ev[0], p->ctx->stream));
+    int rc = enqueue_spmv(p);
+    if (rc)
+        return rc;
+    if (ev)
+        VQE_HIP(p->ctx, hipEventRecord(ev[1], p->ctx->stream));
+    return enqueue_rest(p, flags, ev);
+}
+
+// Capture `fn` on the context stream into an executable graph.
+template <class F> int capture(vqe_ctx *ctx, F fn, hipGraph_t *g_out, hipGraphExec_t *x_out)
+{
+    if (!ctx->stream)
+        return vqe_fail(ctx, VQE_EINVAL, "graph capture needs a non-null stream");
+    VQE_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    int rc = fn();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (rc) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return vqe_fail(ctx, VQE_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(x_out, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        *x_out = nullptr;
+        return vqe_fail(ctx, VQE_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    *g_out = g;
+    return VQE_OK;
+}
+
+// Graph launch of the step: sequence A, then sequence B for this flag set
+// (each captured on first use).  Events 0 and 1 bracket sequence A, event 2
+// follows sequence B.
+int graph_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
+{
+    vqe_ctx *ctx = p->ctx;
+    const unsigned key = flags & 7u;
+    int rc;
+    if (!p->exec_spmv && (rc = capture(ctx, [&] { return enqueue_spmv(p); }, &p->graph_spmv,
+                                       &p->exec_spmv)))
+        return rc;
+    if (!p->exec[key] && (rc = capture(ctx, [&] { return enqueue_rest(p, flags, nullptr); },
+                                       &p->graph[key], &p->exec[key])))
+        return rc;
+    if (ev)
+        VQE_HIP(ctx, hipEventRecord(ev[0], ctx->stream));
+    VQE_HIP(ctx, hipGraphLaunch(p->exec_spmv, ctx->stream));
+    if (ev)
+        VQE_HIP(ctx, hipEventRecord(ev[1], ctx->stream));
+    VQE_HIP(ctx, hipGraphLaunch(p->exec[key], ctx->stream));
+    if (ev)
+        VQE_HIP(ctx, hipEventRecord(ev[2], ctx->stream));
+    return VQE_OK;
+}
+
+// Eager step with three events: before the H products, after them, at the end.
+int enqueue_step3(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
+{
+    VQE_HIP(p->ctx, hipEventRecord(ev[0], p->ctx->stream));
+    int rc = enqueue_spmv(p);
+    if (rc)
+        return rc;
+    VQE_HIP(p->ctx, hipEventRecord(ev[1], p->ctx->stream));
+    rc = enqueue_rest(p, flags, nullptr);
+    if (rc)
+        return rc;
+    VQE_HIP(p->ctx, hipEventRecord(ev[2], p->ctx->stream));
     return VQE_OK;
 }
 
@@ -338,10 +431,10 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     for (int s = 0; s < B; s++) {
         const PairTable &tb = tables[table_of[(const void *)items[s].pool->ops]];
         const int M = tb.M;
-        const int per = (M + n_ranges - 1) / n_ranges;
+        const int nr = std::min(n_ranges, M);
         for (int t = 0; t < tb.nt; t++)
-            for (int j0 = 0; j0 < M; j0 += per)
-                screen_per[xcd_of[s]].push_back(make_int4(s, t, j0, std::min(M, j0 + per)));
+            for (int r = 0; r < nr; r++)
+                screen_per[xcd_of[s]].push_back(make_int4(s, t, r, nr));
         const int64_t rows = std::min<int64_t>(tb.tile_rows, items[s].H->dim);
         p->screen_lds = std::max(p->screen_lds, (size_t)(2 * rows * vqe_elem_bytes(dtype)));
         o_gpart[s] = A.take((size_t)M * tb.nt * sizeof(double));
@@ -349,11 +442,30 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     auto screen_flat = interleave(screen_per, make_int4(-1, 0, 0, 0));
     const size_t o_stasks = A.take(screen_flat.size() * sizeof(int4));
 
-    // --- Taylor and norm tasks
+    // --- Taylor and norm tasks (compact tables: blocks cover the largest
+    //     generator's pairs; otherwise the CSR rows)
+    p->compact_taylor = true;
+    std::vector<int> max_pairs(tables.size(), 0);
+    for (size_t i = 0; i < tables.size(); i++) {
+        p->compact_taylor = p->compact_taylor && tables[i].words != nullptr;
+        const PairTable &tb = tables[i];
+        std::vector<int32_t> pts((size_t)tb.M * tb.nt + 1);
+        if (hipMemcpy(pts.data(), tb.pts, pts.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            for (void *m : p->table_mem)
+                (void)hipFree(m);
+            delete p;
+            return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: reading the pair table failed");
+        }
+        for (int j = 0; j < tb.M; j++)
+            max_pairs[i] = std::max(max_pairs[i], pts[(size_t)(j + 1) * tb.nt] - pts[(size_t)j * tb.nt]);
+    }
     std::vector<std::vector<int2>> tay_per(kXcd), norm_per(kXcd);
     for (int s = 0; s < B; s++) {
         const int64_t dim = items[s].H->dim;
-        const int nt = (int)((dim + TAYLOR_ROWS_PER_BLOCK - 1) / TAYLOR_ROWS_PER_BLOCK);
+        const int mp = max_pairs[table_of[(const void *)items[s].pool->ops]];
+        const int nt = p->compact_taylor
+                           ? std::max(1, (mp + TAYLOR_ROWS_PER_BLOCK - 1) / TAYLOR_ROWS_PER_BLOCK)
+                           : (int)((dim + TAYLOR_ROWS_PER_BLOCK - 1) / TAYLOR_ROWS_PER_BLOCK);
         const int nn = (int)((dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
         for (int b = 0; b < nt; b++)
             tay_per[xcd_of[s]].push_back(make_int2(s, b));
@@ -408,6 +520,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ts.norm2_out = nullptr;
         ts.nblocks = (int32_t)((it.H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
         ts.renorm = 1;
+        ts.table = (const PairTable *)(D + o_tables) + table_of[(const void *)it.pool->ops];
     }
     std::copy(tables.begin(), tables.end(), A.at<PairTable>(o_tables));
     for (int s = 0; s < B; s++) {
@@ -458,33 +571,11 @@ extern "C" int vqe_batch_step(vqe_batch *p, uint32_t flags)
 {
     if (!p)
         return VQE_EINVAL;
-    vqe_ctx *ctx = p->ctx;
     if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH))
-        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_step: unknown flags");
-    if (!(flags & VQE_STEP_GRAPH))
-        return enqueue_step(p, flags);
-    const unsigned key = flags & 7u;
-    if (!p->exec[key]) {
-        if (!ctx->stream)
-            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_step: graph capture needs a non-null stream");
-        VQE_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_step(p, flags);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(ctx->stream, &g);
-        if (rc)
-            return rc;
-        if (e != hipSuccess)
-            return vqe_fail(ctx, VQE_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&p->exec[key], g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            hipGraphDestroy(g);
-            p->exec[key] = nullptr;
-            return vqe_fail(ctx, VQE_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
-        }
-        p->graph[key] = g;
-    }
-    VQE_HIP(ctx, hipGraphLaunch(p->exec[key], ctx->stream));
-    return VQE_OK;
+        return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step: unknown flags");
+    if (flags & VQE_STEP_GRAPH)
+        return graph_step(p, flags, nullptr);
+    return enqueue_step(p, flags);
 }
 
 extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
@@ -492,13 +583,19 @@ extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
 {
     if (!p)
         return VQE_EINVAL;
-    if (!events || n_events != 7 || (flags & VQE_STEP_GRAPH) ||
-        (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE)))
+    if (!events || (n_events != 3 && n_events != 7) ||
+        (n_events == 7 && (flags & VQE_STEP_GRAPH)) ||
+        (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH)))
         return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step_timed: bad flags or events");
-    for (int i = 0; i < 7; i++)
+    for (int i = 0; i < n_events; i++)
         if (!events[i])
             return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step_timed: null event");
-    return enqueue_step(p, flags, reinterpret_cast<hipEvent_t *>(events));
+    hipEvent_t *ev = reinterpret_cast<hipEvent_t *>(events);
+    if (flags & VQE_STEP_GRAPH)
+        return graph_step(p, flags, ev);
+    if (n_events == 3)
+        return enqueue_step3(p, flags, ev);
+    return enqueue_step(p, flags, ev);
 }
 
 extern "C" int vqe_batch_destroy(vqe_batch *p)
@@ -508,10 +605,14 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
     hipStreamSynchronize(p->ctx->stream);
     for (int i = 0; i < 16; i++) {
         if (p->exec[i])
-            hipGraphExecDestroy(p->exec[i]);
+            (void)hipGraphExecDestroy(p->exec[i]);
         if (p->graph[i])
-            hipGraphDestroy(p->graph[i]);
+            (void)hipGraphDestroy(p->graph[i]);
     }
+    if (p->exec_spmv)
+        (void)hipGraphExecDestroy(p->exec_spmv);
+    if (p->graph_spmv)
+        (void)hipGraphDestroy(p->graph_spmv);
     if (p->dmem)
         (void)hipFree(p->dmem);
     for (void *m : p->table_mem)

@@ -51,6 +51,8 @@ struct GradGroup {
     double *g_out[GRAD_MAX_GROUP];      // per state: [M]
 };
 
+struct PairTable;
+
 // One state of the Taylor update.
 struct TaylorState {
     const vqe_csr *ops;        // pool descriptors (device) when the index comes from k
@@ -64,6 +66,7 @@ struct TaylorState {
     int64_t dim;
     double *norm_partials;     // [nblocks]
     double *norm2_out;         // nullable
+    const PairTable *table;    // device pair table of the pool (compact form), nullable
     int32_t nblocks;
     int32_t renorm;
 };
@@ -86,6 +89,7 @@ struct PairTable {
     const void *pb;         // A[c, r] (0 when c == r)
     const uint32_t *words;  // compact form (nullable): r | sign(A[r,c]) << 30 | sign(A[c,r]) << 31
     const int32_t *xmask;   // compact form: per generator, c = r ^ xmask[j]
+    const int32_t *order;   // generators by descending pair count
     int32_t M;
     int32_t nt;             // row tiles
     int32_t tile_rows;
@@ -134,3 +138,5 @@ void launch_taylor_pair(int dtype, const TaylorState *states, const int2 *tasks,
                         hipStream_t s);
 void launch_norm(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                  hipStream_t s);
+void launch_taylor_compact(int dtype, const TaylorState *states, const int2 *tasks,
+                           unsigned grid, hipStream_t s);

@@ -16,6 +16,7 @@
 // then a butterfly), then tiles in ascending order.
 #include "kernels.hpp"
 
+#include <algorithm>
 #include <vector>
 
 namespace {
@@ -141,7 +142,10 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     const ScreenState st = states[task.x];
     const PairTable tb = tables[st.table];
     const int t = task.y;
-    const int j0 = task.z, j1 = task.w;
+    // this workgroup's generators: order[range], order[range + n_ranges], ...
+    // (order = descending pair count)
+    const int range = task.z, n_ranges = task.w;
+    const int n_mine = (tb.M - range + n_ranges - 1) / n_ranges;
     using T = typename Elem<DT>::T;
     extern __shared__ unsigned char smem[];
     const int64_t rows = (int64_t)tb.tile_rows < st.dim ? tb.tile_rows : st.dim;
@@ -162,8 +166,16 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     // one wave per generator (waves are independent: no barriers), four
     // pairs in flight per lane
     constexpr int U = 4;
+    // wave w takes entries w, w + 16, ... of this workgroup's list, which is
+    // ordered by descending pair count
+    int widx = wid;
+    auto next_op = [&]() -> int {
+        const int idx = widx;
+        widx += 16;
+        return idx < n_mine ? tb.order[range + idx * n_ranges] : -1;
+    };
     if (tb.words) {
-        for (int j = j0 + wid; j < j1; j += 16) {
+        for (int j = next_op(); j >= 0; j = next_op()) {
             const int p0 = tb.pts[j * tb.nt + t], p1 = tb.pts[j * tb.nt + t + 1];
             const int64_t x = tb.xmask[j];
             double acc = 0.0;
@@ -203,7 +215,7 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
         }
         return;
     }
-    for (int j = j0 + wid; j < j1; j += 16) {
+    for (int j = next_op(); j >= 0; j = next_op()) {
         const int p0 = tb.pts[j * tb.nt + t], p1 = tb.pts[j * tb.nt + t + 1];
         double acc = 0.0;
         for (int pbase = p0 + lane; pbase < p1; pbase += U * 64) {
@@ -305,8 +317,19 @@ int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable 
         return vqe_fail(ctx, VQE_ESIZE, "pair table too large");
     }
     pts[n_cnt] = (int32_t)total;
+    // generators by descending pair count (ties by index), for load balance
+    std::vector<int32_t> order(M);
+    std::vector<int64_t> per_op(M, 0);
+    for (int j = 0; j < M; j++) {
+        order[j] = j;
+        for (int t = 0; t < nt; t++)
+            per_op[j] += cnt[(size_t)j * nt + t];
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return per_op[a] > per_op[b]; });
     const size_t eb = vqe_elem_bytes(pool->dtype);
-    const size_t o_pts = 0, o_pr = vqe_align((n_cnt + 1) * 4), o_pc = o_pr + vqe_align(total * 4 + 4);
+    const size_t o_ord = vqe_align((n_cnt + 1) * 4);
+    const size_t o_pts = 0, o_pr = o_ord + vqe_align((size_t)M * 4), o_pc = o_pr + vqe_align(total * 4 + 4);
     const size_t o_pa = o_pc + vqe_align(total * 4 + 4), o_pb = o_pa + vqe_align(total * eb + eb);
     const size_t bytes = o_pb + vqe_align(total * eb + eb);
     char *mem = nullptr;
@@ -317,6 +340,8 @@ int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable 
         return vqe_fail(ctx, VQE_ENOMEM, "pair table allocation failed");
     }
     e = hipMemcpyAsync(mem + o_pts, pts.data(), pts.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && M > 0)
+        e = hipMemcpyAsync(mem + o_ord, order.data(), (size_t)M * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         if (pool->dtype == VQE_C128)
             k_pair_fill<VQE_C128><<<(unsigned)n_cnt, 256, 0, s>>>(
@@ -393,6 +418,7 @@ int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable 
         }
     }
     tb->pts = (const int32_t *)(mem + o_pts);
+    tb->order = (const int32_t *)(mem + o_ord);
     tb->pr = (const int32_t *)(mem + o_pr);
     tb->pc = (const int32_t *)(mem + o_pc);
     tb->pa = mem + o_pa;

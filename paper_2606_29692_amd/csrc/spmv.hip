@@ -58,6 +58,13 @@ template <int DT> struct RowLoad<DT, 4> {
     static __device__ __forceinline__ void load(const int32_t *col, const T *val, int k, int k0,
                                                 int k1, int64_t nnz, int c[4], T v[4])
     {
+        if (k >= k1) {
+            // the whole group lies past the row: no load at all
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                c[u] = -1;
+            return;
+        }
         if ((int64_t)k + 3 < nnz) {
             typedef int v4i __attribute__((ext_vector_type(4)));
             const v4i c4 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(col + k));
@@ -256,6 +263,138 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
     }
 }
 
+// Prefetching variant of the LDS schedule: each sub-group covers a row of up
+// to 256 entries in one pass (U * 4 * L = 256) and issues the loads of its
+// next row while it gathers and multiplies the current one, so two rows per
+// sub-group are in flight.  Longer rows finish with synchronous passes.
+template <int DT, int L, bool BATCH>
+__global__ void __launch_bounds__(1024)
+k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
+              const int2 *__restrict__ tasks)
+{
+    SpmvState st;
+    int blk;
+    if (BATCH) {
+        int2 t = tasks[blockIdx.x];
+        if (t.x < 0)
+            return;
+        st = states[t.x];
+        blk = t.y;
+    } else {
+        st = single;
+        blk = blockIdx.x;
+    }
+    using T = typename Elem<DT>::T;
+    constexpr int U = 64 / L;
+    constexpr int W = U * 4;                 // entries per lane per pass
+    extern __shared__ unsigned char smem[];
+    T *s_x = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x;
+    const int64_t dim = st.dim;
+    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    for (int64_t i = tid; i < dim; i += 1024)
+        s_x[i] = psi[i];
+    __syncthreads();
+
+    constexpr int G = VQE_WAVE / L;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int sub = lane / L, sl = lane % L;
+    const int32_t *__restrict__ rowptr = st.rowptr;
+    const int32_t *__restrict__ col = st.col;
+    const T *__restrict__ val = reinterpret_cast<const T *>(st.val);
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
+    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
+
+    int c_cur[W], c_nxt[W];
+    T v_cur[W], v_nxt[W];
+    int k0_cur = 0, k1_cur = 0, k0_nxt = 0, k1_nxt = 0;
+    auto issue = [&](int64_t r, int c[W], T v[W], int &k0, int &k1) {
+        if (r < r1) {
+            k0 = rowptr[r];
+            k1 = rowptr[r + 1];
+            const int k = (k0 & ~3) + 4 * sl;
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0, k1, st.nnz, c + 4 * u, v + 4 * u);
+        } else {
+            k0 = k1 = 0;
+#pragma unroll
+            for (int u = 0; u < W; u++)
+                c[u] = -1;
+        }
+    };
+    int64_t base = r0 + wid * G;
+    issue(base + sub, c_cur, v_cur, k0_cur, k1_cur);
+    for (; base < r1; base += 16 * G) {
+        const int64_t r = base + sub;
+        issue(base + 16 * G + sub, c_nxt, v_nxt, k0_nxt, k1_nxt);
+        double are = 0.0, aim = 0.0;
+#pragma unroll
+        for (int u = 0; u < W; u++) {
+            if (c_cur[u] >= 0) {
+                const T xs = s_x[c_cur[u]];
+                const double xr = (double)xs.x, xi = (double)xs.y;
+                const double ar = (double)v_cur[u].x, ai = (double)v_cur[u].y;
+                are += ar * xr - ai * xi;
+                aim += ar * xi + ai * xr;
+            }
+        }
+        // rows longer than one pass
+        for (int k = (k0_cur & ~3) + 4 * sl + W * L; k < k1_cur; k += W * L) {
+            int c[W];
+            T v[W];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0_cur, k1_cur, st.nnz, c + 4 * u,
+                                     v + 4 * u);
+#pragma unroll
+            for (int u = 0; u < W; u++) {
+                if (c[u] >= 0) {
+                    const T xs = s_x[c[u]];
+                    const double xr = (double)xs.x, xi = (double)xs.y;
+                    const double ar = (double)v[u].x, ai = (double)v[u].y;
+                    are += ar * xr - ai * xi;
+                    aim += ar * xi + ai * xr;
+                }
+            }
+        }
+        are = group_sum<L>(are);
+        aim = group_sum<L>(aim);
+        if (sl == 0 && r < r1) {
+            Elem<DT>::st(st.sigma, r, make_double2(are, aim));
+            const T ps = s_x[r];
+            const double px = (double)ps.x, py = (double)ps.y;
+            e_re += px * are + py * aim;
+            e_im += px * aim - py * are;
+            e_n2 += px * px + py * py;
+        }
+#pragma unroll
+        for (int u = 0; u < W; u++) {
+            c_cur[u] = c_nxt[u];
+            v_cur[u] = v_nxt[u];
+        }
+        k0_cur = k0_nxt;
+        k1_cur = k1_nxt;
+    }
+    __shared__ double s_part[16][3];
+    e_re = wave_sum(e_re);
+    e_im = wave_sum(e_im);
+    e_n2 = wave_sum(e_n2);
+    if (lane == 0) {
+        s_part[wid][0] = e_re;
+        s_part[wid][1] = e_im;
+        s_part[wid][2] = e_n2;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double v = 0.0;
+        for (int w = 0; w < 16; w++)
+            v += s_part[w][tid];
+        st.partials[(int64_t)blk * 3 + tid] = v;
+    }
+}
+
 }  // namespace
 
 // One wave per state: fixed-order sum of the block partials, then
@@ -311,14 +450,43 @@ static void launch_spmv_lds_t(const SpmvState &single, const SpmvState *states, 
     }
 }
 
+template <int DT, int L>
+static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, const int2 *tasks,
+                             unsigned grid, hipStream_t s, size_t lds)
+{
+    if (tasks) {
+        auto k = k_spmv_lds_pf<DT, L, true>;
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        k<<<grid, 1024, lds, s>>>(single, states, tasks);
+    } else {
+        auto k = k_spmv_lds_pf<DT, L, false>;
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        k<<<grid, 1024, lds, s>>>(single, states, tasks);
+    }
+}
+
 template <int DT>
 static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *states,
                            const int2 *tasks, unsigned grid, hipStream_t s, size_t lds)
 {
+    constexpr int D = VQE_SPMV_LDS | VQE_SPMV_DEEP;
+    constexpr int P = VQE_SPMV_LDS | VQE_SPMV_PREFETCH;
     switch (sched) {
+    case 32 | P: launch_spmv_pf_t<DT, 32>(single, states, tasks, grid, s, lds); return;
+    case 64 | P: launch_spmv_pf_t<DT, 64>(single, states, tasks, grid, s, lds); return;
+    default: break;
+    }
+    switch (sched) {
+    case 8 | VQE_SPMV_LDS: launch_spmv_lds_t<DT, 8, 2>(single, states, tasks, grid, s, lds); return;
     case 16 | VQE_SPMV_LDS: launch_spmv_lds_t<DT, 16, 2>(single, states, tasks, grid, s, lds); return;
     case 32 | VQE_SPMV_LDS: launch_spmv_lds_t<DT, 32, 2>(single, states, tasks, grid, s, lds); return;
     case 64 | VQE_SPMV_LDS: launch_spmv_lds_t<DT, 64, 1>(single, states, tasks, grid, s, lds); return;
+    case 8 | D: launch_spmv_lds_t<DT, 8, 4>(single, states, tasks, grid, s, lds); return;
+    case 16 | D: launch_spmv_lds_t<DT, 16, 4>(single, states, tasks, grid, s, lds); return;
+    case 32 | D: launch_spmv_lds_t<DT, 32, 4>(single, states, tasks, grid, s, lds); return;
+    case 64 | D: launch_spmv_lds_t<DT, 64, 2>(single, states, tasks, grid, s, lds); return;
     default: break;
     }
     switch (sched) {
@@ -347,7 +515,10 @@ bool vqe_valid_schedule(int sched)
     switch (sched) {
     case 8: case 16: case 32: case 64:
     case 16 | VQE_SPMV_VEC4: case 32 | VQE_SPMV_VEC4: case 64 | VQE_SPMV_VEC4:
-    case 16 | VQE_SPMV_LDS: case 32 | VQE_SPMV_LDS: case 64 | VQE_SPMV_LDS:
+    case 8 | VQE_SPMV_LDS: case 16 | VQE_SPMV_LDS: case 32 | VQE_SPMV_LDS: case 64 | VQE_SPMV_LDS:
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_DEEP: case 16 | VQE_SPMV_LDS | VQE_SPMV_DEEP:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_DEEP: case 64 | VQE_SPMV_LDS | VQE_SPMV_DEEP:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH: case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH:
         return true;
     default:
         return false;
@@ -363,7 +534,9 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
     if (wide && ((((uintptr_t)H->col) & 15) != 0 || (((uintptr_t)H->val) & 31) != 0))
         return sched & 0xff;
     if ((sched & VQE_SPMV_LDS) && H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES)
-        return (sched & 0xff) | VQE_SPMV_VEC4;
+        return (sched & 0xff) == 8 ? 16 | VQE_SPMV_VEC4 : (sched & 0xff) | VQE_SPMV_VEC4;
+    if ((sched & VQE_SPMV_PREFETCH) && !(sched & VQE_SPMV_LDS))
+        return sched & ~VQE_SPMV_PREFETCH;
     return sched;
 }
 

@@ -12,6 +12,9 @@
 // separated by workgroup barriers, vectors in L2-resident scratch) or, when
 // large, five chained grid-wide launches.
 //
+// In a batch plan whose pools have compact pair tables, the update walks the
+// selected generator's pairs instead of its CSR rows.
+//
 // Renormalisation: an FP64 fixed-order norm (per-block partials, then every
 // block re-sums the partials of its state) followed by the rescale.
 #include "kernels.hpp"
@@ -99,6 +102,50 @@ k_taylor_pair(TaylorState single, const TaylorState *__restrict__ states,
     for (int n = 1; n <= 5; n++) {
         const double2 nr = cmul(a, vc);   // (A v)_r = A[r,c] v_c
         const double2 nc = cmul(b, vr);   // (A v)_c = A[c,r] v_r
+        vr = nr;
+        vc = nc;
+        ar.x += cf[n] * vr.x;
+        ar.y += cf[n] * vr.y;
+        ac.x += cf[n] * vc.x;
+        ac.y += cf[n] * vc.y;
+    }
+    Elem<DT>::st(psi, r, ar);
+    Elem<DT>::st(psi, c, ac);
+}
+
+// Batched update through the compact pair table of the state's pool: one
+// thread per pair {r, c = r ^ x_k} of the selected generator k, entries +-1.
+template <int DT>
+__global__ void __launch_bounds__(TAYLOR_ROWS_PER_BLOCK)
+k_taylor_compact(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const TaylorState *stp = states + task.x;
+    const int32_t k = *stp->k;
+    if (k < 0 || k >= stp->M)
+        return;
+    const PairTable *tb = stp->table;
+    const int p0 = tb->pts[k * tb->nt], p1 = tb->pts[(k + 1) * tb->nt];
+    const int p = p0 + task.y * TAYLOR_ROWS_PER_BLOCK + threadIdx.x;
+    if (p >= p1)
+        return;
+    const uint32_t w = tb->words[p];
+    const int64_t r = w & 0x3fffffffu;
+    const int64_t c = r ^ (int64_t)tb->xmask[k];
+    const double sa = (w >> 30) & 1u ? -1.0 : 1.0;   // A[r,c]
+    const double sb = (w >> 31) ? -1.0 : 1.0;         // A[c,r]
+    const double theta = *stp->theta;
+    double cf[6];
+    taylor_coeffs(theta, cf);
+    void *psi = stp->psi;
+    double2 vr = Elem<DT>::ld(psi, r), vc = Elem<DT>::ld(psi, c);
+    double2 ar = vr, ac = vc;
+#pragma unroll
+    for (int n = 1; n <= 5; n++) {
+        const double2 nr = make_double2(sa * vc.x, sa * vc.y);
+        const double2 nc = make_double2(sb * vr.x, sb * vr.y);
         vr = nr;
         vc = nc;
         ar.x += cf[n] * vr.x;
@@ -277,6 +324,15 @@ void launch_taylor_pair(int dtype, const TaylorState *states, const int2 *tasks,
         k_taylor_pair<VQE_C128, true><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(dummy, states, tasks);
     else
         k_taylor_pair<VQE_C64, true><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(dummy, states, tasks);
+}
+
+void launch_taylor_compact(int dtype, const TaylorState *states, const int2 *tasks,
+                           unsigned grid, hipStream_t s)
+{
+    if (dtype == VQE_C128)
+        k_taylor_compact<VQE_C128><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(states, tasks);
+    else
+        k_taylor_compact<VQE_C64><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(states, tasks);
 }
 
 void launch_norm(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,

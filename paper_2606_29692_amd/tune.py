@@ -19,8 +19,10 @@ import numpy as np
 
 from . import binding as B
 
-CANDIDATES = (8, 16, 32, 64, 16 | B.VQE_SPMV_VEC4, 32 | B.VQE_SPMV_VEC4, 64 | B.VQE_SPMV_VEC4,
-              16 | B.VQE_SPMV_LDS, 32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS)
+_L, _V, _D, _P = B.VQE_SPMV_LDS, B.VQE_SPMV_VEC4, B.VQE_SPMV_DEEP, B.VQE_SPMV_PREFETCH
+CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
+              8 | _L, 16 | _L, 32 | _L, 64 | _L, 8 | _L | _D, 16 | _L | _D, 32 | _L | _D, 64 | _L | _D,
+              32 | _L | _P, 64 | _L | _P)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}

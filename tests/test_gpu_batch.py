@@ -201,7 +201,7 @@ def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
     plan.close()
 
 
-@pytest.mark.parametrize("sched", [0, 32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS])
+@pytest.mark.parametrize("sched", [0, 16 | B.VQE_SPMV_LDS, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH])
 def test_full_size_bench_config(ctx, sched):
     """64 states at 14 qubits in FP32 storage (the benchmark workload):
     sampled states against the oracle, invariants on every state."""
@@ -243,8 +243,11 @@ def test_full_size_bench_config(ctx, sched):
 
 
 @pytest.mark.parametrize("sched", [8, 16, 32, 64, 16 | B.VQE_SPMV_VEC4, 32 | B.VQE_SPMV_VEC4,
-                                   64 | B.VQE_SPMV_VEC4, 16 | B.VQE_SPMV_LDS,
-                                   32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS])
+                                   64 | B.VQE_SPMV_VEC4, 8 | B.VQE_SPMV_LDS, 16 | B.VQE_SPMV_LDS,
+                                   32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS,
+                                   16 | B.VQE_SPMV_LDS | B.VQE_SPMV_DEEP,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
+                                   64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
@@ -293,4 +296,10 @@ def test_screen_full_pair_table(ctx):
     g_o = orc.gradients([orc.csr_from_pack(p) for p in scaled], v, sig)
     np.testing.assert_allclose(host(plan.gradients(0)), g_o, rtol=0,
                                atol=1e-12 * max(1.0, np.abs(g_o).max()))
+    # the update then runs over CSR rows (no compact table)
+    plan.k.fill_(7)
+    plan.theta.fill_(0.3)
+    plan.step(forced=True, renorm=False)
+    want = orc.taylor5(orc.csr_from_pack(scaled[7]), 0.3, v)
+    assert np.linalg.norm(host(psi) - want) <= 1e-12
     plan.close()
