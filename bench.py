@@ -101,6 +101,58 @@ def plain_fp64_path(ctx, system, n_req: int):
     return taylor_rate, step_rate
 
 
+def serving_bench(n_requests: int, warm: int, log_fn=log):
+    """Config C5: 64 resident runs with register sizes drawn from {8,...,16};
+    Poisson request streams at 0.8x and 2x the capacity of the plain
+    sequential FP64 single-request path; continuous batching (FP32 storage,
+    slot groups per register size, one stream each) against that path."""
+    import torch
+    import vqe_system as vs
+    from paper_2606_29692_amd import binding as B
+    from paper_2606_29692_amd import serve as S
+
+    specs, _ = vs.config_c5(n_runs=64)
+    systems = {r: vs.make_system(sp) for r, sp in enumerate(specs)}
+    thetas = {r: vs.draw_thetas(sp.seed, 4096) for r, sp in enumerate(specs)}
+    sizes = sorted({sp.n_qubits for sp in specs})
+    ctx = B.Context(0, torch.cuda.Stream())
+    # capacity of the sequential FP64 path: a burst served back to back
+    burst = [S.Request(i, i % len(systems), 0.0) for i in range(256)]
+    done = S.run_sequential(ctx, systems, burst, thetas)
+    cap = len(done) / max(q.t_done for q in done)
+    log_fn(f"serving: sequential FP64 capacity {cap:.0f} requests/s ({len(systems)} runs, "
+           f"N in {sizes})")
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.5 * free)
+    out = {"runs": len(systems), "register_sizes": sizes, "requests": n_requests,
+           "warmup_requests": warm, "sequential_fp64_capacity_per_s": cap,
+           "budget_bytes": budget}
+    for factor in (0.8, 2.0):
+        rate = factor * cap
+        trace = S.poisson_trace(n_requests, rate, len(systems), seed=int(factor * 10))
+        t_cold = time.perf_counter()
+        ex = S.DeviceExecutor(systems, slots_per_group=16, dtype="c64")
+        server = S.Server(ex, thetas, budget_bytes=budget)
+        resident = server.prewarm()
+        torch.cuda.synchronize()
+        t_cold = time.perf_counter() - t_cold
+        served = server.run_trace([S.Request(q.rid, q.run, q.t_arrival) for q in trace])
+        cb = S.latency_summary(sorted(served, key=lambda q: q.rid), skip=warm)
+        seq = S.run_sequential(ctx, systems, [S.Request(q.rid, q.run, q.t_arrival) for q in trace],
+                               thetas)
+        sq = S.latency_summary(sorted(seq, key=lambda q: q.rid), skip=warm)
+        out[f"x{factor}"] = {"rate_per_s": rate, "continuous_batching": cb,
+                             "sequential_fp64": sq, "evictions": server.evictions,
+                             "resident_runs": resident, "cold_start_s": t_cold}
+        log_fn(f"serving at {factor}x ({rate:.0f}/s): batched p50 {cb['p50_ms']:.3f} ms p99 "
+               f"{cb['p99_ms']:.3f} ms {cb['updates_per_s']:.0f}/s; sequential p50 "
+               f"{sq['p50_ms']:.3f} ms p99 {sq['p99_ms']:.3f} ms")
+        del ex, server
+        torch.cuda.synchronize()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +165,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests per serving point (0: skip the serving measurement)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): states are "
@@ -226,6 +280,10 @@ def main():
         cpu = cpu_baseline(systems, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.2f} updates/s on {cpu['cores']} threads")
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_bench(args.serve_requests, min(128, args.serve_requests // 4))
+
     hnnz = ds[0].H.nnz
     out = {
         "metric": "Taylor-O(5) updates/s + pool-gradient SpMV HBM GB/s at 14 qubits; p99 latency",
@@ -265,6 +323,9 @@ def main():
                                "k_spmv_energy, per the schedule)",
                      "bytes_per_launch": nbytes["h_spmv"]},
         "plain_fp64_single_request": plain,
+        "serving": serving,
+        "p99_latency_ms": (serving["x0.8"]["continuous_batching"]["p99_ms"] if serving
+                           else None),
         "cpu_baseline": cpu,
         "host_wall_s": wall,
     }

@@ -224,6 +224,9 @@ typedef struct vqe_batch_io {
     const int64_t *g_offset_host;   /* host int64[B]: offset of state s in g_out */
     int32_t *k_io;
     double *gmax_out;
+    const int32_t *active;          /* device int32[B], nullable: a slot whose flag is 0
+                                       is skipped by every kernel of the step (its
+                                       outputs keep their previous values) */
 } vqe_batch_io;
 
 #define VQE_STEP_RENORM 1u      /* renormalise every state after its update */
@@ -238,6 +241,15 @@ typedef struct vqe_batch vqe_batch;
 VQE_API int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *items,
                      const vqe_batch_io *io, double rel_tie, vqe_batch **out);
 VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
+/*
+ * Bind another state to slot `slot` of a plan (continuous batching): the new
+ * item must have the same dimension, dtype and H-product schedule as the
+ * slot's state at creation and use the same pool (same ops array).  The new
+ * descriptors are copied on the context stream, so they apply to every step
+ * enqueued afterwards, graph replays included; steps already enqueued keep
+ * the old binding.  Errors: VQE_EINVAL (slot out of range, mismatch).
+ */
+VQE_API int vqe_batch_rebind(vqe_batch *plan, int32_t slot, const vqe_batch_item *item);
 /*
  * The same step while recording caller-created HIP events (hipEvent_t) on the
  * context stream.  n_events = 3: [0] before the H products, [1] after them,

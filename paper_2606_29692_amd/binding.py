@@ -54,7 +54,8 @@ class vqe_batch_item(C.Structure):
 
 class vqe_batch_io(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("energy_out", C.c_void_p), ("g_out", C.c_void_p),
-                ("g_offset_host", C.c_void_p), ("k_io", C.c_void_p), ("gmax_out", C.c_void_p)]
+                ("g_offset_host", C.c_void_p), ("k_io", C.c_void_p), ("gmax_out", C.c_void_p),
+                ("active", C.c_void_p)]
 
 
 # name -> (restype, argtypes); the full exported surface of adaptvqe.h
@@ -78,6 +79,7 @@ SIGNATURES = {
     "vqe_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_batch_item),
                                    C.POINTER(vqe_batch_io), C.c_double, C.POINTER(C.c_void_p)]),
     "vqe_batch_step": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "vqe_batch_rebind": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_batch_item)]),
     "vqe_batch_step_timed": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p), C.c_int32]),
     "vqe_batch_destroy": (C.c_int, [C.c_void_p]),
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
@@ -323,7 +325,8 @@ class BatchPlan:
     plan allocates sigma, theta, energies, gradients, indices and gmax as torch
     tensors that stay alive with it."""
 
-    def __init__(self, ctx: Context, states: list, schedules=None, rel_tie: float = REL_TIE):
+    def __init__(self, ctx: Context, states: list, schedules=None, rel_tie: float = REL_TIE,
+                 with_active: bool = False):
         torch = _torch()
         self.ctx = ctx
         B = len(states)
@@ -341,6 +344,9 @@ class BatchPlan:
         self.g = torch.zeros(max(off, 1), dtype=torch.float64, device=dev)
         self.k = torch.zeros(B, dtype=torch.int32, device=dev)
         self.gmax = torch.zeros(B, dtype=torch.float64, device=dev)
+        # per-slot activity flags (continuous batching); all on by default
+        self.active = torch.ones(B, dtype=torch.int32, device=dev) if with_active else None
+        self.schedules = schedules
         items = (vqe_batch_item * B)()
         for s, (H, pool, psi) in enumerate(states):
             items[s].H = C.addressof(H.desc)
@@ -356,6 +362,7 @@ class BatchPlan:
         io.g_offset_host = self.g_offset.ctypes.data
         io.k_io = self.k.data_ptr()
         io.gmax_out = self.gmax.data_ptr()
+        io.active = self.active.data_ptr() if self.active is not None else None
         self._io = io
         h = C.c_void_p()
         ctx.check(lib().vqe_batch_create(ctx.handle, B, items, C.byref(io), float(rel_tie),
@@ -380,6 +387,20 @@ class BatchPlan:
         n = len(events)
         arr = (C.c_void_p * n)(*[C.c_void_p(e.cuda_event) for e in events])
         self.ctx.check(lib().vqe_batch_step_timed(self.handle, flags, arr, n), "vqe_batch_step_timed")
+
+    def rebind(self, slot: int, H: DeviceCSR, pool: DevicePool, psi):
+        """Bind another state (same size, dtype, pool) to a slot; the slot keeps
+        its sigma buffer."""
+        it = vqe_batch_item()
+        it.H = C.addressof(H.desc)
+        it.pool = C.addressof(pool.desc)
+        it.psi = psi.data_ptr()
+        it.sigma = self.sigma[slot].data_ptr()
+        it.spmv_schedule = int(self.schedules[slot]) if self.schedules is not None else 0
+        self.ctx.check(lib().vqe_batch_rebind(self.handle, int(slot), C.byref(it)), "vqe_batch_rebind")
+        # keep the bound objects alive while the slot refers to them
+        self._bound = getattr(self, "_bound", {})
+        self._bound[slot] = (H, pool, psi)
 
     def gradients(self, s: int):
         M = self.states[s][1].M

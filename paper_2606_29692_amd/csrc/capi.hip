@@ -152,6 +152,12 @@ struct vqe_batch {
     hipGraphExec_t exec[16] = {};
     hipGraph_t graph[16] = {};
     bool compact_taylor = false;   // every pool has a compact pair table
+    // host image of the descriptors (for rebinding slots)
+    std::vector<char> image;
+    size_t o_spmv = 0, o_screen = 0, o_tay = 0;
+    std::vector<int> sched;            // effective H-product schedule per slot
+    std::vector<const void *> pool_ops;  // pool of each slot
+    std::vector<int64_t> dims;
     hipGraphExec_t exec_spmv = nullptr;
     hipGraph_t graph_spmv = nullptr;
 };
@@ -502,12 +508,14 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         st.nblocks = (int32_t)spmv_blocks(it.H->dim, lanes[s]);
         st.lanes = lanes[s];
         st.nnz = it.H->nnz;
+        st.active = io->active ? io->active + s : nullptr;
 
         SelectState &se = A.at<SelectState>(o_sel)[s];
         se.g = io->g_out + io->g_offset_host[s];
         se.M = it.pool->M;
         se.k_out = io->k_io + s;
         se.gmax_out = io->gmax_out + s;
+        se.active = io->active ? io->active + s : nullptr;
 
         TaylorState &ts = A.at<TaylorState>(o_tay)[s];
         ts.ops = it.pool->ops;
@@ -521,6 +529,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ts.nblocks = (int32_t)((it.H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
         ts.renorm = 1;
         ts.table = (const PairTable *)(D + o_tables) + table_of[(const void *)it.pool->ops];
+        ts.active = io->active ? io->active + s : nullptr;
     }
     std::copy(tables.begin(), tables.end(), A.at<PairTable>(o_tables));
     for (int s = 0; s < B; s++) {
@@ -532,6 +541,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ss.g_out = io->g_out + io->g_offset_host[s];
         ss.dim = items[s].H->dim;
         ss.table = table_of[(const void *)items[s].pool->ops];
+        ss.active = io->active ? io->active + s : nullptr;
     }
     for (size_t i = 0; i < spmv_tab.size(); i++) {
         std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));
@@ -552,6 +562,14 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     p->n_tay_tasks = (unsigned)tay_flat.size();
     p->d_norm_tasks = (int2 *)(D + o_ntasks);
     p->n_norm_tasks = (unsigned)norm_flat.size();
+    p->o_spmv = o_spmv;
+    p->o_screen = o_screen;
+    p->o_tay = o_tay;
+    p->sched = lanes;
+    for (int s = 0; s < B; s++) {
+        p->pool_ops.push_back((const void *)items[s].pool->ops);
+        p->dims.push_back(items[s].H->dim);
+    }
     hipError_t e = hipMemcpyAsync(p->dmem, A.host.data(), p->dmem_bytes, hipMemcpyHostToDevice,
                                   ctx->stream);
     if (e == hipSuccess)
@@ -563,7 +581,49 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         delete p;
         return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: %s", hipGetErrorString(e));
     }
+    p->image = std::move(A.host);
     *out = p;
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item *it)
+{
+    if (!p)
+        return VQE_EINVAL;
+    vqe_ctx *ctx = p->ctx;
+    if (slot < 0 || slot >= p->B || !it)
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: bad slot or item");
+    int rc = check_csr(ctx, it->H, "vqe_batch_rebind");
+    if (rc)
+        return rc;
+    if (!it->pool || !it->psi || !it->sigma || it->H->dtype != p->dtype ||
+        it->H->dim != p->dims[slot] || (const void *)it->pool->ops != p->pool_ops[slot])
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: item does not match slot %d", slot);
+    const int sched = vqe_effective_schedule(
+        it->H, it->spmv_schedule ? it->spmv_schedule : vqe_default_schedule(it->H));
+    if (sched != p->sched[slot])
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: schedule differs from slot %d", slot);
+    SpmvState *st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv) + slot;
+    st->rowptr = it->H->rowptr;
+    st->col = it->H->col;
+    st->val = it->H->val;
+    st->psi = it->psi;
+    st->sigma = it->sigma;
+    st->shift = it->H->diag_shift;
+    st->nnz = it->H->nnz;
+    ScreenState *ss = reinterpret_cast<ScreenState *>(p->image.data() + p->o_screen) + slot;
+    ss->psi = it->psi;
+    ss->sigma = it->sigma;
+    ss->shift = it->H->diag_shift;
+    TaylorState *ts = reinterpret_cast<TaylorState *>(p->image.data() + p->o_tay) + slot;
+    ts->psi = it->psi;
+    hipStream_t s = ctx->stream;
+    VQE_HIP(ctx, hipMemcpyAsync(p->dmem + ((char *)st - p->image.data()), st, sizeof(*st),
+                                hipMemcpyHostToDevice, s));
+    VQE_HIP(ctx, hipMemcpyAsync(p->dmem + ((char *)ss - p->image.data()), ss, sizeof(*ss),
+                                hipMemcpyHostToDevice, s));
+    VQE_HIP(ctx, hipMemcpyAsync(p->dmem + ((char *)ts - p->image.data()), ts, sizeof(*ts),
+                                hipMemcpyHostToDevice, s));
     return VQE_OK;
 }
 

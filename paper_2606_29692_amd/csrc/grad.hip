@@ -143,6 +143,8 @@ __global__ void __launch_bounds__(64)
 k_select_t(SelectState single, const SelectState *__restrict__ states, double rel_tie)
 {
     const SelectState st = BATCH ? states[blockIdx.x] : single;
+    if (VQE_SKIP(st))
+        return;
     const int lane = threadIdx.x;
     double gmax = 0.0;
     for (int j = lane; j < st.M; j += 64)

@@ -4,6 +4,9 @@
 
 #include "common.hpp"
 
+// True when a batch slot is switched off for this step (uniform per workgroup).
+#define VQE_SKIP(st) ((st).active && !*(st).active)
+
 // Rows per wave pass handled by one sub-group, and passes per workgroup.
 #define SPMV_RPT 2
 
@@ -28,6 +31,7 @@ struct SpmvState {
     int64_t dim;
     int64_t nnz;
     double shift;
+    const int32_t *active;     // batch slot flag (nullable): 0 = skip this state
     int32_t nblocks;
     int32_t lanes;
 };
@@ -67,6 +71,7 @@ struct TaylorState {
     double *norm_partials;     // [nblocks]
     double *norm2_out;         // nullable
     const PairTable *table;    // device pair table of the pool (compact form), nullable
+    const int32_t *active;     // batch slot flag (nullable): 0 = skip this state
     int32_t nblocks;
     int32_t renorm;
 };
@@ -77,6 +82,7 @@ struct SelectState {
     int32_t M;
     int32_t *k_out;
     double *gmax_out;
+    const int32_t *active;     // batch slot flag (nullable): 0 = skip this state
 };
 
 // Pair table of a pool of pairing generators (built once per batch plan).
@@ -103,6 +109,7 @@ struct ScreenState {
     double *partials;       // [M * nt]
     double *g_out;          // [M]
     int64_t dim;
+    const int32_t *active;  // batch slot flag (nullable): 0 = skip this state
     int32_t table;          // index into the plan's PairTable array
     int32_t pad;
 };

@@ -140,6 +140,8 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     if (task.x < 0)
         return;
     const ScreenState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
     const PairTable tb = tables[st.table];
     const int t = task.y;
     // this workgroup's generators: order[range], order[range + n_ranges], ...
@@ -265,6 +267,8 @@ __global__ void __launch_bounds__(256)
 k_screen_fin(const ScreenState *__restrict__ states, const PairTable *__restrict__ tables)
 {
     const ScreenState st = states[blockIdx.x];
+    if (VQE_SKIP(st))
+        return;
     const PairTable tb = tables[st.table];
     for (int j = threadIdx.x; j < tb.M; j += 256) {
         double s = 0.0;

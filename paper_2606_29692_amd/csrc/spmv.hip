@@ -104,6 +104,8 @@ k_spmv_energy(SpmvState single, const SpmvState *__restrict__ states,
             return;
         st = states[t.x];
         blk = t.y;
+        if (VQE_SKIP(st))
+            return;
     } else {
         st = single;
         blk = blockIdx.x;
@@ -187,6 +189,8 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
             return;
         st = states[t.x];
         blk = t.y;
+        if (VQE_SKIP(st))
+            return;
     } else {
         st = single;
         blk = blockIdx.x;
@@ -280,6 +284,8 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
             return;
         st = states[t.x];
         blk = t.y;
+        if (VQE_SKIP(st))
+            return;
     } else {
         st = single;
         blk = blockIdx.x;
@@ -406,6 +412,8 @@ k_energy_finalize(SpmvState single, const SpmvState *__restrict__ states, int n_
     if (s >= n_states)
         return;
     const SpmvState st = states ? states[s] : single;
+    if (VQE_SKIP(st))
+        return;
     const int lane = threadIdx.x;
     double re = 0.0, im = 0.0, n2 = 0.0;
     for (int b = lane; b < st.nblocks; b += 64) {

@@ -47,6 +47,8 @@ k_taylor_pair(TaylorState single, const TaylorState *__restrict__ states,
             return;
         stp = states + t.x;
         blk = t.y;
+        if (VQE_SKIP(*stp))
+            return;
     } else {
         stp = &single;
         blk = blockIdx.x;
@@ -123,6 +125,8 @@ k_taylor_compact(const TaylorState *__restrict__ states, const int2 *__restrict_
     if (task.x < 0)
         return;
     const TaylorState *stp = states + task.x;
+    if (VQE_SKIP(*stp))
+        return;
     const int32_t k = *stp->k;
     if (k < 0 || k >= stp->M)
         return;
@@ -170,6 +174,8 @@ k_norm_partials(TaylorState single, const TaylorState *__restrict__ states,
             return;
         stp = states + t.x;
         blk = t.y;
+        if (VQE_SKIP(*stp))
+            return;
     } else {
         stp = &single;
         blk = blockIdx.x;
@@ -203,6 +209,8 @@ k_norm_scale(TaylorState single, const TaylorState *__restrict__ states,
             return;
         stp = states + t.x;
         blk = t.y;
+        if (VQE_SKIP(*stp))
+            return;
     } else {
         stp = &single;
         blk = blockIdx.x;

@@ -1,0 +1,88 @@
+"""Continuous-batching server on the GPU.
+
+Each request's result is the same whether its run is served alone or inside
+the mixed trace (bit for bit: a run's slot schedule and reduction order do not
+depend on what else is in the micro-batch), also when a small HBM budget
+forces evictions and resumes; sampled runs match the FP64 oracle along the
+served operator sequence.
+"""
+import numpy as np
+import pytest
+
+import vqe_system as vs
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2606_29692_amd import binding as B  # noqa: E402
+from paper_2606_29692_amd import serve as S  # noqa: E402
+
+SCHED = {(8, 4, "jw"): 16, (10, 4, "jw"): 32, (12, 8, "jw"): 32 | B.VQE_SPMV_LDS}
+
+
+def make_runs():
+    specs = {}
+    for r in range(9):
+        n = (8, 10, 12)[r % 3]
+        specs[r] = vs.SystemSpec(n, vs.ELECTRONS[n], "jw", False, vs.system_seed(77, r))
+    systems = {r: vs.make_system(s) for r, s in specs.items()}
+    thetas = {r: vs.draw_thetas(specs[r].seed, 64) for r in specs}
+    return systems, thetas
+
+
+def serve(systems, thetas, reqs, budget=10**12, slots=4):
+    ex = S.DeviceExecutor(systems, slots_per_group=slots, dtype="c64", schedules=SCHED)
+    server = S.Server(ex, thetas, budget_bytes=budget)
+    out = server.run_trace([S.Request(q.rid, q.run, q.t_arrival) for q in reqs])
+    torch.cuda.synchronize()
+    psi = {r: ex.psi(r) for r in systems}
+    return out, psi, server
+
+
+def by_run(reqs):
+    d = {}
+    for q in sorted(reqs, key=lambda q: q.rid):
+        d.setdefault(q.run, []).append((q.energy, q.selected, q.gmax))
+    return d
+
+
+def test_alone_vs_mixed_and_eviction():
+    systems, thetas = make_runs()
+    trace = S.poisson_trace(150, rate=3000.0, n_runs=len(systems), seed=5)
+    mixed, psi_mixed, srv = serve(systems, thetas, trace)
+    assert all(q.t_done >= q.t_arrival for q in mixed)
+    res_mixed = by_run(mixed)
+    # alone: each of three runs with only its own requests
+    for r in (0, 4, 8):
+        mine = [q for q in trace if q.run == r]
+        alone, psi_alone, _ = serve({r: systems[r]}, {r: thetas[r]}, mine)
+        print(f"run {r}: {len(mine)} requests", flush=True)
+        assert by_run(alone)[r] == res_mixed[r]
+        np.testing.assert_array_equal(psi_alone[r], psi_mixed[r])
+    # a budget that holds only a few runs: evictions and resumes, same results
+    small, psi_small, srv_small = serve(systems, thetas, trace, budget=srv.ex.fixed_bytes() + 6_000_000)
+    assert srv_small.evictions > 0
+    assert by_run(small) == res_mixed
+    for r in systems:
+        np.testing.assert_array_equal(psi_small[r], psi_mixed[r])
+
+
+def test_served_runs_match_oracle():
+    systems, thetas = make_runs()
+    trace = S.poisson_trace(120, rate=3000.0, n_runs=len(systems), seed=9)
+    out, psi, _ = serve(systems, thetas, trace)
+    res = by_run(out)
+    for r in (2, 5):
+        s = systems[r]
+        steps = len(res[r])
+        forced = [k for _, k, _ in res[r]]
+        tr = orc.adapt_run(orc.csr_from_pack(s.hamiltonian), [orc.csr_from_pack(p) for p in s.pool],
+                           vs.reference_state(s), thetas[r], steps, forced=forced)
+        for t in range(steps):
+            assert abs(res[r][t][0] - tr.energies[t]) < 1e-6
+            g_o = tr.gradients[t]
+            assert abs(g_o[forced[t]]) >= np.abs(g_o).max() * (1 - 1e-5)
+        p = psi[r].astype(np.complex128)
+        fid = abs(np.vdot(p, tr.psi)) ** 2 / (np.vdot(p, p).real * np.vdot(tr.psi, tr.psi).real)
+        assert fid > 0.999999
