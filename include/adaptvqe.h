@@ -276,7 +276,7 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
 #define VQE_SPMV_VEC4 0x100
 /* VQE_SPMV_LDS: wide loads plus the whole state vector staged in LDS by each
  * workgroup (8, 16, 32 or 64 lanes; VQE_SPMV_DEEP doubles the loads kept in
- * flight per lane); needs dim * element size <= 156 KiB, else the VEC4
+ * flight per lane); needs dim * element size <= 147 KiB, else the VEC4
  * schedule with the same lanes (16 for 8) is used. */
 #define VQE_SPMV_LDS 0x200
 #define VQE_SPMV_DEEP 0x400

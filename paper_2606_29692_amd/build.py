@@ -39,7 +39,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
-    flags = list(BASE_FLAGS)
+    flags = list(BASE_FLAGS) + os.environ.get("ADAPTVQE_EXTRA_FLAGS", "").split()
     if src in NO_CONTRACT:
         flags.append("-ffp-contract=off")
     cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]

@@ -71,11 +71,11 @@ extern "C" int vqe_destroy(vqe_ctx *ctx)
 {
     if (!ctx)
         return VQE_EINVAL;
-    hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws)
-        hipFree(ctx->ws);
+        (void)hipFree(ctx->ws);
     if (ctx->host_scalars)
-        hipHostFree(ctx->host_scalars);
+        (void)hipHostFree(ctx->host_scalars);
     delete ctx;
     return VQE_OK;
 }
@@ -106,7 +106,7 @@ int vqe_ws_reserve(vqe_ctx *ctx, size_t bytes)
     // earlier work may still read the old scratch
     VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->ws) {
-        hipFree(ctx->ws);
+        (void)hipFree(ctx->ws);
         ctx->ws = nullptr;
         ctx->ws_bytes = 0;
     }
@@ -662,7 +662,7 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
 {
     if (!p)
         return VQE_EINVAL;
-    hipStreamSynchronize(p->ctx->stream);
+    (void)hipStreamSynchronize(p->ctx->stream);
     for (int i = 0; i < 16; i++) {
         if (p->exec[i])
             (void)hipGraphExecDestroy(p->exec[i]);

@@ -60,6 +60,53 @@ int vqe_ws_reserve(vqe_ctx *ctx, size_t bytes);
 
 __host__ __device__ static inline size_t vqe_align(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// ------------------------------------------------------------------ address spaces
+// Pointers read from descriptor tables are generic; the compiler then emits
+// flat loads, which count against both the memory and the LDS wait counters
+// and so serialise LDS traffic behind global loads.  Every global access of
+// the kernels goes through these casts to the global address space.
+#define VQE_GLOBAL __attribute__((address_space(1)))
+
+template <typename T> __device__ __forceinline__ const VQE_GLOBAL T *gmem(const T *p)
+{
+    return (const VQE_GLOBAL T *)p;
+}
+template <typename T> __device__ __forceinline__ VQE_GLOBAL T *gmem(T *p)
+{
+    return (VQE_GLOBAL T *)p;
+}
+
+// Element loads and stores through the global address space (clang vector
+// types carry the address space; HIP's float2/double2 classes do not).
+typedef double vqe_v2d __attribute__((ext_vector_type(2)));
+typedef float vqe_v2f __attribute__((ext_vector_type(2)));
+typedef float vqe_v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float2 ldg(const float2 *p, int64_t i)
+{
+    const vqe_v2f t = gmem(reinterpret_cast<const vqe_v2f *>(p))[i];
+    return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ double2 ldg(const double2 *p, int64_t i)
+{
+    const vqe_v2d t = gmem(reinterpret_cast<const vqe_v2d *>(p))[i];
+    return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ void stg(float2 *p, int64_t i, float2 v)
+{
+    vqe_v2f t;
+    t.x = v.x;
+    t.y = v.y;
+    gmem(reinterpret_cast<vqe_v2f *>(p))[i] = t;
+}
+__device__ __forceinline__ void stg(double2 *p, int64_t i, double2 v)
+{
+    vqe_v2d t;
+    t.x = v.x;
+    t.y = v.y;
+    gmem(reinterpret_cast<vqe_v2d *>(p))[i] = t;
+}
+
 // ------------------------------------------------------------------ complex I/O
 // Elements are loaded into FP64 registers whatever the storage type.
 template <int DT> struct Elem;
@@ -68,11 +115,11 @@ template <> struct Elem<VQE_C128> {
     using T = double2;
     static __device__ __forceinline__ double2 ld(const void *p, int64_t i)
     {
-        return reinterpret_cast<const double2 *>(p)[i];
+        return ldg(reinterpret_cast<const double2 *>(p), i);
     }
     static __device__ __forceinline__ void st(void *p, int64_t i, double2 v)
     {
-        reinterpret_cast<double2 *>(p)[i] = v;
+        stg(reinterpret_cast<double2 *>(p), i, v);
     }
 };
 
@@ -80,12 +127,12 @@ template <> struct Elem<VQE_C64> {
     using T = float2;
     static __device__ __forceinline__ double2 ld(const void *p, int64_t i)
     {
-        float2 v = reinterpret_cast<const float2 *>(p)[i];
+        const float2 v = ldg(reinterpret_cast<const float2 *>(p), i);
         return make_double2((double)v.x, (double)v.y);
     }
     static __device__ __forceinline__ void st(void *p, int64_t i, double2 v)
     {
-        reinterpret_cast<float2 *>(p)[i] = make_float2((float)v.x, (float)v.y);
+        stg(reinterpret_cast<float2 *>(p), i, make_float2((float)v.x, (float)v.y));
     }
 };
 
@@ -101,12 +148,32 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum over aligned groups of `width` lanes; every lane of a group gets the total.
+// A double moved between lanes with a DPP pattern (two 32-bit moves).
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of `width` lanes; every lane of a group gets the
+// same total (each step adds a partner's partial, a + b = b + a exactly, so
+// the order is fixed and deterministic).  Within a 16-lane row the steps are
+// DPP moves (two quad swaps, the half-row mirror, the row mirror), which stay
+// out of the LDS pipeline; wider groups add cross-row shuffles.
 template <int WIDTH> __device__ __forceinline__ double group_sum(double v)
 {
-#pragma unroll
-    for (int o = WIDTH / 2; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, VQE_WAVE);
+    v += dpp_f64<0xB1>(v);                 // quad_perm [1,0,3,2]: lane ^ 1
+    if (WIDTH > 2)
+        v += dpp_f64<0x4E>(v);             // quad_perm [2,3,0,1]: lane ^ 2
+    if (WIDTH > 4)
+        v += dpp_f64<0x141>(v);            // row_half_mirror: the other quad of 8 lanes
+    if (WIDTH > 8)
+        v += dpp_f64<0x140>(v);            // row_mirror: the other half of 16 lanes
+    if (WIDTH > 16)
+        v += __shfl_xor(v, 16, VQE_WAVE);
+    if (WIDTH > 32)
+        v += __shfl_xor(v, 32, VQE_WAVE);
     return v;
 }
 

@@ -5,15 +5,18 @@
 #include "common.hpp"
 
 // True when a batch slot is switched off for this step (uniform per workgroup).
-#define VQE_SKIP(st) ((st).active && !*(st).active)
+#define VQE_SKIP(st) ((st).active && !*gmem((st).active))
 
 // Rows per wave pass handled by one sub-group, and passes per workgroup.
 #define SPMV_RPT 2
 
 // A schedule is the lanes per row (8, 16, 32, 64), optionally | VQE_SPMV_VEC4
 // or | VQE_SPMV_LDS.  The LDS schedule gives each workgroup SPMV_LDS_ROWS rows.
+#ifndef SPMV_LDS_ROWS
 #define SPMV_LDS_ROWS 2048
-#define SPMV_LDS_MAX_BYTES (156 * 1024)
+#endif
+// state bytes that fit next to the staged row pointers
+#define SPMV_LDS_MAX_BYTES (147 * 1024)
 __host__ __device__ constexpr int spmv_rows_per_block(int sched)
 {
     return 4 * (VQE_WAVE / (sched & 0xff)) * SPMV_RPT;

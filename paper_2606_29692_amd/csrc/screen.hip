@@ -157,8 +157,8 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     const T *psi = reinterpret_cast<const T *>(st.psi);
     const T *sig = reinterpret_cast<const T *>(st.sigma);
     for (int64_t i = threadIdx.x; i < rows; i += 1024) {
-        s_psi[i] = psi[base + i];
-        s_sig[i] = sig[base + i];
+        s_psi[i] = ldg(psi, base + i);
+        s_sig[i] = ldg(sig, base + i);
     }
     __syncthreads();
     const double shift = st.shift;
@@ -174,19 +174,19 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     auto next_op = [&]() -> int {
         const int idx = widx;
         widx += 16;
-        return idx < n_mine ? tb.order[range + idx * n_ranges] : -1;
+        return idx < n_mine ? gmem(tb.order)[range + idx * n_ranges] : -1;
     };
     if (tb.words) {
         for (int j = next_op(); j >= 0; j = next_op()) {
-            const int p0 = tb.pts[j * tb.nt + t], p1 = tb.pts[j * tb.nt + t + 1];
-            const int64_t x = tb.xmask[j];
+            const int p0 = gmem(tb.pts)[j * tb.nt + t], p1 = gmem(tb.pts)[j * tb.nt + t + 1];
+            const int64_t x = gmem(tb.xmask)[j];
             double acc = 0.0;
             for (int pbase = p0 + lane; pbase < p1; pbase += U * 64) {
                 uint32_t w[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int p = pbase + u * 64;
-                    w[u] = p < p1 ? tb.words[p] : 0xffffffffu;
+                    w[u] = p < p1 ? gmem(tb.words)[p] : 0xffffffffu;
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++) {
@@ -200,8 +200,8 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
                         pc_ = s_psi[c - base];
                         qc_ = s_sig[c - base];
                     } else {
-                        pc_ = psi[c];
-                        qc_ = sig[c];
+                        pc_ = ldg(psi, c);
+                        qc_ = ldg(sig, c);
                     }
                     const double prx = pr_.x, pry = pr_.y, pcx = pc_.x, pcy = pc_.y;
                     const double srx = (double)qr_.x + shift * prx, sry = (double)qr_.y + shift * pry;
@@ -213,12 +213,12 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
             }
             acc = wave_sum(acc);
             if (lane == 0)
-                st.partials[(int64_t)j * tb.nt + t] = acc;
+                gmem(st.partials)[(int64_t)j * tb.nt + t] = acc;
         }
         return;
     }
     for (int j = next_op(); j >= 0; j = next_op()) {
-        const int p0 = tb.pts[j * tb.nt + t], p1 = tb.pts[j * tb.nt + t + 1];
+        const int p0 = gmem(tb.pts)[j * tb.nt + t], p1 = gmem(tb.pts)[j * tb.nt + t + 1];
         double acc = 0.0;
         for (int pbase = p0 + lane; pbase < p1; pbase += U * 64) {
             int64_t r[U], c[U];
@@ -227,10 +227,10 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
             for (int u = 0; u < U; u++) {
                 const int p = pbase + u * 64;
                 if (p < p1) {
-                    r[u] = tb.pr[p];
-                    c[u] = tb.pc[p];
-                    av[u] = pa[p];
-                    bv[u] = pb[p];
+                    r[u] = gmem(tb.pr)[p];
+                    c[u] = gmem(tb.pc)[p];
+                    av[u] = ldg(pa, p);
+                    bv[u] = ldg(pb, p);
                 } else {
                     r[u] = -1;
                 }
@@ -245,8 +245,8 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
                     pc_ = s_psi[c[u] - base];
                     qc_ = s_sig[c[u] - base];
                 } else {
-                    pc_ = psi[c[u]];
-                    qc_ = sig[c[u]];
+                    pc_ = ldg(psi, c[u]);
+                    qc_ = ldg(sig, c[u]);
                 }
                 const double prx = pr_.x, pry = pr_.y, pcx = pc_.x, pcy = pc_.y;
                 const double srx = (double)qr_.x + shift * prx, sry = (double)qr_.y + shift * pry;
@@ -259,7 +259,7 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
         }
         acc = wave_sum(acc);
         if (lane == 0)
-            st.partials[(int64_t)j * tb.nt + t] = acc;
+            gmem(st.partials)[(int64_t)j * tb.nt + t] = acc;
     }
 }
 

@@ -27,8 +27,8 @@ template <int DT> struct RowLoad<DT, 1> {
         (void)k0;
         (void)nnz;
         if (k < k1) {
-            c[0] = __builtin_nontemporal_load(col + k);
-            v[0] = val[k];
+            c[0] = __builtin_nontemporal_load(gmem(col) + k);
+            v[0] = ldg(val, k);
         } else {
             c[0] = -1;
         }
@@ -38,8 +38,8 @@ template <int DT> struct RowLoad<DT, 1> {
 // Four consecutive values from a 32-byte (c64) or 64-byte (c128) aligned address.
 __device__ __forceinline__ void load4(const float2 *p, float2 v[4])
 {
-    const float4 a = reinterpret_cast<const float4 *>(p)[0];
-    const float4 b = reinterpret_cast<const float4 *>(p)[1];
+    const vqe_v4f a = gmem(reinterpret_cast<const vqe_v4f *>(p))[0];
+    const vqe_v4f b = gmem(reinterpret_cast<const vqe_v4f *>(p))[1];
     v[0] = make_float2(a.x, a.y);
     v[1] = make_float2(a.z, a.w);
     v[2] = make_float2(b.x, b.y);
@@ -50,7 +50,7 @@ __device__ __forceinline__ void load4(const double2 *p, double2 v[4])
 {
 #pragma unroll
     for (int u = 0; u < 4; u++)
-        v[u] = p[u];
+        v[u] = ldg(p, u);
 }
 
 template <int DT> struct RowLoad<DT, 4> {
@@ -67,7 +67,7 @@ template <int DT> struct RowLoad<DT, 4> {
         }
         if ((int64_t)k + 3 < nnz) {
             typedef int v4i __attribute__((ext_vector_type(4)));
-            const v4i c4 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(col + k));
+            const v4i c4 = __builtin_nontemporal_load(gmem(reinterpret_cast<const v4i *>(col + k)));
             c[0] = c4.x;
             c[1] = c4.y;
             c[2] = c4.z;
@@ -77,8 +77,8 @@ template <int DT> struct RowLoad<DT, 4> {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 if ((int64_t)(k + u) < nnz) {
-                    c[u] = col[k + u];
-                    v[u] = val[k + u];
+                    c[u] = gmem(col)[k + u];
+                    v[u] = ldg(val, k + u);
                 } else {
                     c[u] = -1;
                 }
@@ -125,7 +125,7 @@ k_spmv_energy(SpmvState single, const SpmvState *__restrict__ states,
         const int64_t r = (int64_t)blk * RPB + (it * 4 + wid) * G + sub;
         double are = 0.0, aim = 0.0;
         if (r < st.dim) {
-            const int k0 = rowptr[r], k1 = rowptr[r + 1];
+            const int k0 = gmem(rowptr)[r], k1 = gmem(rowptr)[r + 1];
             const int first = V == 1 ? k0 + sl : (k0 & ~3) + 4 * sl;
             for (int k = first; k < k1; k += U * V * L) {
                 int c[U * V];
@@ -168,7 +168,28 @@ k_spmv_energy(SpmvState single, const SpmvState *__restrict__ states,
     if (threadIdx.x < 3) {
         const int q = threadIdx.x;
         const double v = ((s_part[0][q] + s_part[1][q]) + s_part[2][q]) + s_part[3][q];
-        st.partials[(int64_t)blk * 3 + q] = v;
+        gmem(st.partials)[(int64_t)blk * 3 + q] = v;
+    }
+}
+
+// Gathers from the LDS copy of the state and FP64 multiply-accumulate, branch
+// free: masked entries (c < 0) read element 0 and contribute exactly zero, so
+// all LDS reads issue back to back behind a single wait.
+template <typename T, int N>
+__device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], const T v[N],
+                                               double &are, double &aim)
+{
+    T xs[N];
+#pragma unroll
+    for (int u = 0; u < N; u++)
+        xs[u] = s_x[c[u] >= 0 ? c[u] : 0];
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        const bool on = c[u] >= 0;
+        const double ar = on ? (double)v[u].x : 0.0, ai = on ? (double)v[u].y : 0.0;
+        const double xr = (double)xs[u].x, xi = (double)xs[u].y;
+        are += ar * xr - ai * xi;
+        aim += ar * xi + ai * xr;
     }
 }
 
@@ -201,24 +222,27 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
     const int tid = threadIdx.x;
     const int64_t dim = st.dim;
     const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
+    // the workgroup's row pointers follow the state in LDS
+    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)dim * sizeof(T));
     for (int64_t i = tid; i < dim; i += 1024)
-        s_x[i] = psi[i];
+        s_x[i] = ldg(psi, i);
+    for (int64_t i = tid; i <= r1 - r0; i += 1024)
+        s_rp[i] = gmem(st.rowptr)[r0 + i];
     __syncthreads();
 
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
-    const int32_t *__restrict__ rowptr = st.rowptr;
     const int32_t *__restrict__ col = st.col;
     const T *__restrict__ val = reinterpret_cast<const T *>(st.val);
-    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
-    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
     for (int64_t base = r0 + wid * G; base < r1; base += 16 * G) {
         const int64_t r = base + sub;
         double are = 0.0, aim = 0.0;
         if (r < r1) {
-            const int k0 = rowptr[r], k1 = rowptr[r + 1];
+            const int k0 = s_rp[r - r0], k1 = s_rp[r - r0 + 1];
             for (int k = (k0 & ~3) + 4 * sl; k < k1; k += U * 4 * L) {
                 int c[U * 4];
                 T v[U * 4];
@@ -226,16 +250,7 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
                 for (int u = 0; u < U; u++)
                     RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0, k1, st.nnz, c + 4 * u,
                                          v + 4 * u);
-#pragma unroll
-                for (int u = 0; u < U * 4; u++) {
-                    if (c[u] >= 0) {
-                        const T xs = s_x[c[u]];
-                        const double xr = (double)xs.x, xi = (double)xs.y;
-                        const double ar = (double)v[u].x, ai = (double)v[u].y;
-                        are += ar * xr - ai * xi;
-                        aim += ar * xi + ai * xr;
-                    }
-                }
+                lds_gather_fma<T, U * 4>(s_x, c, v, are, aim);
             }
         }
         are = group_sum<L>(are);
@@ -263,7 +278,7 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
         double v = 0.0;
         for (int w = 0; w < 16; w++)
             v += s_part[w][tid];
-        st.partials[(int64_t)blk * 3 + tid] = v;
+        gmem(st.partials)[(int64_t)blk * 3 + tid] = v;
     }
 }
 
@@ -298,18 +313,20 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     const int tid = threadIdx.x;
     const int64_t dim = st.dim;
     const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
+    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)dim * sizeof(T));
     for (int64_t i = tid; i < dim; i += 1024)
-        s_x[i] = psi[i];
+        s_x[i] = ldg(psi, i);
+    for (int64_t i = tid; i <= r1 - r0; i += 1024)
+        s_rp[i] = gmem(st.rowptr)[r0 + i];
     __syncthreads();
 
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
-    const int32_t *__restrict__ rowptr = st.rowptr;
     const int32_t *__restrict__ col = st.col;
     const T *__restrict__ val = reinterpret_cast<const T *>(st.val);
-    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
-    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
 
     int c_cur[W], c_nxt[W];
@@ -317,8 +334,8 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     int k0_cur = 0, k1_cur = 0, k0_nxt = 0, k1_nxt = 0;
     auto issue = [&](int64_t r, int c[W], T v[W], int &k0, int &k1) {
         if (r < r1) {
-            k0 = rowptr[r];
-            k1 = rowptr[r + 1];
+            k0 = s_rp[r - r0];
+            k1 = s_rp[r - r0 + 1];
             const int k = (k0 & ~3) + 4 * sl;
 #pragma unroll
             for (int u = 0; u < U; u++)
@@ -336,16 +353,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         const int64_t r = base + sub;
         issue(base + 16 * G + sub, c_nxt, v_nxt, k0_nxt, k1_nxt);
         double are = 0.0, aim = 0.0;
-#pragma unroll
-        for (int u = 0; u < W; u++) {
-            if (c_cur[u] >= 0) {
-                const T xs = s_x[c_cur[u]];
-                const double xr = (double)xs.x, xi = (double)xs.y;
-                const double ar = (double)v_cur[u].x, ai = (double)v_cur[u].y;
-                are += ar * xr - ai * xi;
-                aim += ar * xi + ai * xr;
-            }
-        }
+        lds_gather_fma<T, W>(s_x, c_cur, v_cur, are, aim);
         // rows longer than one pass
         for (int k = (k0_cur & ~3) + 4 * sl + W * L; k < k1_cur; k += W * L) {
             int c[W];
@@ -354,16 +362,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
             for (int u = 0; u < U; u++)
                 RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0_cur, k1_cur, st.nnz, c + 4 * u,
                                      v + 4 * u);
-#pragma unroll
-            for (int u = 0; u < W; u++) {
-                if (c[u] >= 0) {
-                    const T xs = s_x[c[u]];
-                    const double xr = (double)xs.x, xi = (double)xs.y;
-                    const double ar = (double)v[u].x, ai = (double)v[u].y;
-                    are += ar * xr - ai * xi;
-                    aim += ar * xi + ai * xr;
-                }
-            }
+            lds_gather_fma<T, W>(s_x, c, v, are, aim);
         }
         are = group_sum<L>(are);
         aim = group_sum<L>(aim);
@@ -397,7 +396,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         double v = 0.0;
         for (int w = 0; w < 16; w++)
             v += s_part[w][tid];
-        st.partials[(int64_t)blk * 3 + tid] = v;
+        gmem(st.partials)[(int64_t)blk * 3 + tid] = v;
     }
 }
 
@@ -511,7 +510,7 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
 void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState *states,
                  const int2 *tasks, unsigned grid, hipStream_t s, int64_t max_dim)
 {
-    const size_t lds = (size_t)max_dim * vqe_elem_bytes(dtype);
+    const size_t lds = (size_t)max_dim * vqe_elem_bytes(dtype) + (SPMV_LDS_ROWS + 1) * sizeof(int32_t);
     if (dtype == VQE_C128)
         launch_spmv_dt<VQE_C128>(sched, single, states, tasks, grid, s, lds);
     else

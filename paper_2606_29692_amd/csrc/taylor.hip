@@ -73,10 +73,10 @@ k_taylor_pair(TaylorState single, const TaylorState *__restrict__ states,
         col = stp->op.col;
         val = stp->op.val;
     }
-    const int k0 = rowptr[r];
-    if (rowptr[r + 1] - k0 != 1)
+    const int k0 = gmem(rowptr)[r];
+    if (gmem(rowptr)[r + 1] - k0 != 1)
         return;
-    const int64_t c = col[k0];
+    const int64_t c = gmem(col)[k0];
     if (c < r)
         return;   // the partner row owns the pair
     const double theta = stp->theta ? *stp->theta : stp->theta_value;
@@ -97,7 +97,7 @@ k_taylor_pair(TaylorState single, const TaylorState *__restrict__ states,
         Elem<DT>::st(psi, r, acc);
         return;
     }
-    const double2 b = Elem<DT>::ld(val, rowptr[c]);
+    const double2 b = Elem<DT>::ld(val, gmem(rowptr)[c]);
     double2 vr = Elem<DT>::ld(psi, r), vc = Elem<DT>::ld(psi, c);
     double2 ar = vr, ac = vc;
 #pragma unroll
@@ -131,13 +131,13 @@ k_taylor_compact(const TaylorState *__restrict__ states, const int2 *__restrict_
     if (k < 0 || k >= stp->M)
         return;
     const PairTable *tb = stp->table;
-    const int p0 = tb->pts[k * tb->nt], p1 = tb->pts[(k + 1) * tb->nt];
+    const int p0 = gmem(tb->pts)[k * tb->nt], p1 = gmem(tb->pts)[(k + 1) * tb->nt];
     const int p = p0 + task.y * TAYLOR_ROWS_PER_BLOCK + threadIdx.x;
     if (p >= p1)
         return;
-    const uint32_t w = tb->words[p];
+    const uint32_t w = gmem(tb->words)[p];
     const int64_t r = w & 0x3fffffffu;
-    const int64_t c = r ^ (int64_t)tb->xmask[k];
+    const int64_t c = r ^ (int64_t)gmem(tb->xmask)[k];
     const double sa = (w >> 30) & 1u ? -1.0 : 1.0;   // A[r,c]
     const double sb = (w >> 31) ? -1.0 : 1.0;         // A[c,r]
     const double theta = *stp->theta;
@@ -193,7 +193,7 @@ k_norm_partials(TaylorState single, const TaylorState *__restrict__ states,
         red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0)
-        stp->norm_partials[blk] = ((red[0] + red[1]) + red[2]) + red[3];
+        gmem(stp->norm_partials)[blk] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 template <int DT, bool BATCH>
@@ -219,7 +219,7 @@ k_norm_scale(TaylorState single, const TaylorState *__restrict__ states,
     if (threadIdx.x < 64) {
         double s = 0.0;
         for (int b = threadIdx.x; b < stp->nblocks; b += 64)
-            s += stp->norm_partials[b];
+            s += gmem(stp->norm_partials)[b];
         s = wave_sum(s);
         if (threadIdx.x == 0)
             s_n2 = s;
