@@ -33,6 +33,37 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 
 
+PMC_PROFILE = os.path.join(ROOT, "profiles", "h_product_14q_64states_pmc.md")
+
+
+def measured_traffic(schedule: int):
+    """HBM bytes per H-product launch from the committed FETCH_SIZE/WRITE_SIZE
+    profile (calibrated against a copy kernel of known size), or None when the
+    profile is absent, was taken with another schedule, or the kernel sources
+    have changed since it was taken."""
+    import hashlib
+    if not os.path.exists(PMC_PROFILE):
+        return None
+    rec = {}
+    with open(PMC_PROFILE) as f:
+        for line in f:
+            if ": " in line and not line.startswith((" ", "#", "|")):
+                k, v = line.rstrip("\n").split(": ", 1)
+                rec[k] = v
+    try:
+        if int(rec["schedule"]) != int(schedule):
+            return None
+        h = hashlib.sha256()
+        for src in rec["kernel_sources"].split():
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["kernel_sources_sha256"]:
+            return None
+        return int(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError, OSError):
+        return None
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -318,7 +349,8 @@ def main():
                      "renorm_eager": norm_avg},
         "algorithmic_bytes_per_step": nbytes,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(sched),
+                     "traffic_unit": "bytes per launch (HBM read + write, PMC-calibrated)",
                      "kernel": "H product of all 64 states (one launch of k_spmv_lds or "
                                "k_spmv_energy, per the schedule)",
                      "bytes_per_launch": nbytes["h_spmv"]},
