@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=0,
                     help="H product schedule (lanes per row, | 256 for wide loads; 0: tuned)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--retune", action="store_true",
+                    help="time every H product schedule even when a tuned one is cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512,
@@ -224,7 +226,7 @@ def main():
     ds = [PB.device_system(ctx, s, args.dtype, pools) for s in systems]
     torch.cuda.synchronize()
     log(f"setup: {len(ds)} systems built on the device in {time.perf_counter() - t0:.1f} s")
-    sched = args.schedule or T.schedule_for(ctx, ds[0], systems=ds)
+    sched = args.schedule or T.schedule_for(ctx, ds[0], systems=ds, retune=args.retune)
     if T._last_timings:
         log("tuner (ms of the batched H product): " +
             ", ".join(f"{k}: {v:.3f}" for k, v in sorted(T._last_timings.items())))

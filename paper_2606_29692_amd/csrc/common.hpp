@@ -149,10 +149,12 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // A double moved between lanes with a DPP pattern (two 32-bit moves).
+// Every control used here has a valid source lane for every lane, so the
+// moves need no previous destination value (bound_ctrl set).
 template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 

@@ -172,9 +172,58 @@ k_spmv_energy(SpmvState single, const SpmvState *__restrict__ states,
     }
 }
 
-// Gathers from the LDS copy of the state and FP64 multiply-accumulate, branch
-// free: masked entries (c < 0) read element 0 and contribute exactly zero, so
-// all LDS reads issue back to back behind a single wait.
+// Loads of the LDS schedules: four consecutive entries from an aligned group
+// k (16-byte index load, 32- or 64-byte value load).  Entries outside the
+// row [k0, k1) get column zc, the index of a zero element kept after the
+// state in LDS, so the multiply needs no per-entry select: their values are
+// finite (entries of a neighbouring row, or zero) and multiply that zero.
+// Only groups that reach past the end of the arrays (k + 4 > nnz) take the
+// entry-by-entry path.  All index arithmetic is 32-bit (nnz < 2^31).
+template <int DT>
+__device__ __forceinline__ void lds_group_load(const int32_t *col, const typename Elem<DT>::T *val,
+                                               int k, int k0, int k1, int nnz, int zc, int c[4],
+                                               typename Elem<DT>::T v[4])
+{
+    using T = typename Elem<DT>::T;
+    if (k >= k1) {
+        // the whole group lies past the row: no load at all
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            c[u] = zc;
+            v[u] = T{};
+        }
+        return;
+    }
+    if (k + 4 <= nnz) {
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        const v4i c4 = __builtin_nontemporal_load(gmem(reinterpret_cast<const v4i *>(col + k)));
+        c[0] = c4.x;
+        c[1] = c4.y;
+        c[2] = c4.z;
+        c[3] = c4.w;
+        load4(val + k, v);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (k + u < nnz) {
+                c[u] = gmem(col)[k + u];
+                v[u] = ldg(val, k + u);
+            } else {
+                c[u] = zc;
+                v[u] = T{};
+            }
+        }
+    }
+    // entry k + u belongs to the row iff 0 <= k + u - k0 < k1 - k0
+    const unsigned len = (unsigned)(k1 - k0);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        c[u] = (unsigned)(k + u - k0) < len ? c[u] : zc;
+}
+
+// Gathers from the LDS copy of the state and FP64 multiply-accumulate.  All
+// LDS reads issue back to back behind a single wait; masked entries read the
+// zero element.
 template <typename T, int N>
 __device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], const T v[N],
                                                double &are, double &aim)
@@ -182,11 +231,10 @@ __device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], con
     T xs[N];
 #pragma unroll
     for (int u = 0; u < N; u++)
-        xs[u] = s_x[c[u] >= 0 ? c[u] : 0];
+        xs[u] = s_x[c[u]];
 #pragma unroll
     for (int u = 0; u < N; u++) {
-        const bool on = c[u] >= 0;
-        const double ar = on ? (double)v[u].x : 0.0, ai = on ? (double)v[u].y : 0.0;
+        const double ar = (double)v[u].x, ai = (double)v[u].y;
         const double xr = (double)xs[u].x, xi = (double)xs[u].y;
         are += ar * xr - ai * xi;
         aim += ar * xi + ai * xr;
@@ -224,10 +272,12 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
     const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
     const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
     const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
-    // the workgroup's row pointers follow the state in LDS
-    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)dim * sizeof(T));
+    // the state, one zero element (index dim), then the workgroup's row pointers
+    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)(dim + 1) * sizeof(T));
     for (int64_t i = tid; i < dim; i += 1024)
         s_x[i] = ldg(psi, i);
+    if (tid == 0)
+        s_x[dim] = T{};
     for (int64_t i = tid; i <= r1 - r0; i += 1024)
         s_rp[i] = gmem(st.rowptr)[r0 + i];
     __syncthreads();
@@ -237,6 +287,7 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
     const int sub = lane / L, sl = lane % L;
     const int32_t *__restrict__ col = st.col;
     const T *__restrict__ val = reinterpret_cast<const T *>(st.val);
+    const int nnz = (int)st.nnz, zc = (int)dim;
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
     for (int64_t base = r0 + wid * G; base < r1; base += 16 * G) {
         const int64_t r = base + sub;
@@ -248,8 +299,8 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
                 T v[U * 4];
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0, k1, st.nnz, c + 4 * u,
-                                         v + 4 * u);
+                    lds_group_load<DT>(col, val, k + u * 4 * L, k0, k1, nnz, zc, c + 4 * u,
+                                       v + 4 * u);
                 lds_gather_fma<T, U * 4>(s_x, c, v, are, aim);
             }
         }
@@ -282,10 +333,48 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
     }
 }
 
-// Prefetching variant of the LDS schedule: each sub-group covers a row of up
-// to 256 entries in one pass (U * 4 * L = 256) and issues the loads of its
-// next row while it gathers and multiplies the current one, so two rows per
-// sub-group are in flight.  Longer rows finish with synchronous passes.
+// Raw buffer resources (gfx9 descriptor word 3): a load whose offset lies at
+// or past num_records returns zero and makes no memory request.
+#define VQE_BUF_WORD3 0x00020000
+#define VQE_BUF_OOB 0x80000000u
+
+template <int DT> struct BufVal;
+template <> struct BufVal<VQE_C64> {
+    // four consecutive complex64 values: two 16-byte loads
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off, float2 v[4])
+    {
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        const v4f a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const v4f b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+        v[0] = make_float2(a.x, a.y);
+        v[1] = make_float2(a.z, a.w);
+        v[2] = make_float2(b.x, b.y);
+        v[3] = make_float2(b.z, b.w);
+    }
+};
+template <> struct BufVal<VQE_C128> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v[4])
+    {
+        typedef double v2d __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const v2d a = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16 * u, 0, 0);
+            v[u] = make_double2(a.x, a.y);
+        }
+    }
+};
+
+// Pipelined variant of the LDS schedule.  A sub-group of L lanes covers a row
+// of up to U * 4 * L = 256 entries in one pass, and it issues the loads of
+// its next row before it gathers and multiplies the current one, so two rows
+// per sub-group are in flight.  The loads are raw buffer loads issued by every
+// lane without branches: groups past the row (or past the last whole group of
+// the arrays) get an out-of-range offset and return zero without a memory
+// request.  Because the number of loads per row is fixed, the wait before one
+// row's products leaves the other row's loads outstanding (the scheduling
+// barriers keep each row's loads issued before the other row is consumed).  Rows
+// longer than one pass finish with further passes, and the last nnz % 4
+// entries of the arrays are added entry by entry.
 template <int DT, int L, bool BATCH>
 __global__ void __launch_bounds__(1024)
 k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
@@ -308,6 +397,8 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     using T = typename Elem<DT>::T;
     constexpr int U = 64 / L;
     constexpr int W = U * 4;                 // entries per lane per pass
+    constexpr int PASS = W * L;              // entries per sub-group per pass
+    constexpr unsigned EB = sizeof(T);
     extern __shared__ unsigned char smem[];
     T *s_x = reinterpret_cast<T *>(smem);
     const int tid = threadIdx.x;
@@ -315,9 +406,11 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
     const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
     const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
-    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)dim * sizeof(T));
+    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)(dim + 1) * sizeof(T));
     for (int64_t i = tid; i < dim; i += 1024)
         s_x[i] = ldg(psi, i);
+    if (tid == 0)
+        s_x[dim] = T{};
     for (int64_t i = tid; i <= r1 - r0; i += 1024)
         s_rp[i] = gmem(st.rowptr)[r0 + i];
     __syncthreads();
@@ -325,44 +418,68 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
-    const int32_t *__restrict__ col = st.col;
-    const T *__restrict__ val = reinterpret_cast<const T *>(st.val);
+    const int nnz = (int)st.nnz, zc = (int)dim;
+    const int whole = nnz & ~3;              // groups starting below this are whole
+    const __amdgpu_buffer_rsrc_t rc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
+    const __amdgpu_buffer_rsrc_t rv =
+        __builtin_amdgcn_make_buffer_rsrc((void *)st.val, (short)0, (int)(nnz * EB), VQE_BUF_WORD3);
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
 
-    int c_cur[W], c_nxt[W];
-    T v_cur[W], v_nxt[W];
-    int k0_cur = 0, k1_cur = 0, k0_nxt = 0, k1_nxt = 0;
-    auto issue = [&](int64_t r, int c[W], T v[W], int &k0, int &k1) {
+    // issue the loads of the pass starting at group kb of a row [k0, k1)
+    auto issue = [&](int kb, int k1, int c[W], T v[W]) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int k = kb + u * 4 * L;
+            const bool ok = k < k1 && k < whole;
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const v4i c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 4u : VQE_BUF_OOB, 0, 0);
+            c[4 * u + 0] = c4.x;
+            c[4 * u + 1] = c4.y;
+            c[4 * u + 2] = c4.z;
+            c[4 * u + 3] = c4.w;
+            BufVal<DT>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
+        }
+    };
+    // products of one pass; entries outside [k0, k1) read the zero element
+    auto consume = [&](int kb, int k0, int k1, const int c[W], const T v[W], double &are,
+                       double &aim) {
+        int cm[W];
+        const unsigned len = (unsigned)(k1 - k0);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int k = kb + u * 4 * L + q;
+                cm[4 * u + q] = (unsigned)(k - k0) < len ? c[4 * u + q] : zc;
+            }
+        lds_gather_fma<T, W>(s_x, cm, v, are, aim);
+    };
+    auto row_bounds = [&](int64_t r, int &k0, int &k1) {
         if (r < r1) {
             k0 = s_rp[r - r0];
             k1 = s_rp[r - r0 + 1];
-            const int k = (k0 & ~3) + 4 * sl;
-#pragma unroll
-            for (int u = 0; u < U; u++)
-                RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0, k1, st.nnz, c + 4 * u, v + 4 * u);
         } else {
             k0 = k1 = 0;
-#pragma unroll
-            for (int u = 0; u < W; u++)
-                c[u] = -1;
         }
     };
-    int64_t base = r0 + wid * G;
-    issue(base + sub, c_cur, v_cur, k0_cur, k1_cur);
-    for (; base < r1; base += 16 * G) {
-        const int64_t r = base + sub;
-        issue(base + 16 * G + sub, c_nxt, v_nxt, k0_nxt, k1_nxt);
-        double are = 0.0, aim = 0.0;
-        lds_gather_fma<T, W>(s_x, c_cur, v_cur, are, aim);
-        // rows longer than one pass
-        for (int k = (k0_cur & ~3) + 4 * sl + W * L; k < k1_cur; k += W * L) {
+    auto finish = [&](int64_t r, int k0, int k1, double are, double aim) {
+        // further passes of a long row
+        for (int kb = (k0 & ~3) + 4 * sl + PASS; kb - 4 * sl < k1; kb += PASS) {
             int c[W];
             T v[W];
-#pragma unroll
-            for (int u = 0; u < U; u++)
-                RowLoad<DT, 4>::load(col, val, k + u * 4 * L, k0_cur, k1_cur, st.nnz, c + 4 * u,
-                                     v + 4 * u);
-            lds_gather_fma<T, W>(s_x, c, v, are, aim);
+            issue(kb, k1, c, v);
+            consume(kb, k0, k1, c, v, are, aim);
+        }
+        // the entries after the last whole group of the arrays
+        if (k1 > whole) {
+            const int k = (k0 > whole ? k0 : whole) + sl;
+            if (k < k1) {
+                const T a = ldg(reinterpret_cast<const T *>(st.val), k);
+                const T x = s_x[gmem(st.col)[k]];
+                are += (double)a.x * (double)x.x - (double)a.y * (double)x.y;
+                aim += (double)a.x * (double)x.y + (double)a.y * (double)x.x;
+            }
         }
         are = group_sum<L>(are);
         aim = group_sum<L>(aim);
@@ -374,13 +491,37 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
             e_im += px * aim - py * are;
             e_n2 += px * px + py * py;
         }
-#pragma unroll
-        for (int u = 0; u < W; u++) {
-            c_cur[u] = c_nxt[u];
-            v_cur[u] = v_nxt[u];
+    };
+
+    // two rows per sub-group in flight: A and B alternate
+    int cA[W], cB[W];
+    T vA[W], vB[W];
+    int a0, a1, b0, b1;
+    int64_t rA = r0 + wid * G + sub, rB = rA + 16 * G;
+    row_bounds(rA, a0, a1);
+    issue((a0 & ~3) + 4 * sl, a1, cA, vA);
+    row_bounds(rB, b0, b1);
+    issue((b0 & ~3) + 4 * sl, b1, cB, vB);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int64_t base = r0 + wid * G; base < r1; base += 32 * G) {
+        {
+            double are = 0.0, aim = 0.0;
+            consume((a0 & ~3) + 4 * sl, a0, a1, cA, vA, are, aim);
+            finish(rA, a0, a1, are, aim);
         }
-        k0_cur = k0_nxt;
-        k1_cur = k1_nxt;
+        rA += 32 * G;
+        row_bounds(rA, a0, a1);
+        issue((a0 & ~3) + 4 * sl, a1, cA, vA);
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            double are = 0.0, aim = 0.0;
+            consume((b0 & ~3) + 4 * sl, b0, b1, cB, vB, are, aim);
+            finish(rB, b0, b1, are, aim);
+        }
+        rB += 32 * G;
+        row_bounds(rB, b0, b1);
+        issue((b0 & ~3) + 4 * sl, b1, cB, vB);
+        __builtin_amdgcn_sched_barrier(0);
     }
     __shared__ double s_part[16][3];
     e_re = wave_sum(e_re);
@@ -510,7 +651,7 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
 void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState *states,
                  const int2 *tasks, unsigned grid, hipStream_t s, int64_t max_dim)
 {
-    const size_t lds = (size_t)max_dim * vqe_elem_bytes(dtype) + (SPMV_LDS_ROWS + 1) * sizeof(int32_t);
+    const size_t lds = (size_t)(max_dim + 1) * vqe_elem_bytes(dtype) + (SPMV_LDS_ROWS + 1) * sizeof(int32_t);
     if (dtype == VQE_C128)
         launch_spmv_dt<VQE_C128>(sched, single, states, tasks, grid, s, lds);
     else
@@ -542,7 +683,9 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
         return sched & 0xff;
     if ((sched & VQE_SPMV_LDS) && H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES)
         return (sched & 0xff) == 8 ? 16 | VQE_SPMV_VEC4 : (sched & 0xff) | VQE_SPMV_VEC4;
-    if ((sched & VQE_SPMV_PREFETCH) && !(sched & VQE_SPMV_LDS))
+    // the pipelined schedule addresses the arrays with 31-bit buffer offsets
+    if ((sched & VQE_SPMV_PREFETCH) &&
+        (!(sched & VQE_SPMV_LDS) || H->nnz * (int64_t)vqe_elem_bytes(H->dtype) > 0x7fffff00LL))
         return sched & ~VQE_SPMV_PREFETCH;
     return sched;
 }
