@@ -280,8 +280,10 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * schedule with the same lanes (16 for 8) is used. */
 #define VQE_SPMV_LDS 0x200
 #define VQE_SPMV_DEEP 0x400
-/* VQE_SPMV_PREFETCH (with VQE_SPMV_LDS; 32 or 64 lanes): each sub-group
- * issues the loads of its next row before multiplying the current one. */
+/* VQE_SPMV_PREFETCH (with VQE_SPMV_LDS; 32 or 64 lanes): each sub-group keeps
+ * the loads of its next rows in flight while it multiplies the current one
+ * (two rows, or three with VQE_SPMV_DEEP); needs nnz * element size below
+ * 2^31 bytes (raw buffer offsets), else the LDS schedule is used. */
 #define VQE_SPMV_PREFETCH 0x800
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given

@@ -11,6 +11,10 @@
 // on the same XCD (workgroup IDs are dealt round-robin over the 8 XCDs).
 #include "kernels.hpp"
 
+// The LDS schedules hold the state in LDS, so one 16-wave workgroup fills a
+// CU (4 waves per SIMD): the register allocator may use the whole budget.
+#define VQE_LDS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 4)))
+
 namespace {
 
 // V = entries per lane per pass.  V = 1: lane l of the sub-group takes
@@ -247,7 +251,7 @@ __device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], con
 // one state; sub-groups of L lanes read their rows with the four-entry wide
 // loads, U passes in flight.
 template <int DT, int L, int U, bool BATCH>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
 {
     SpmvState st;
@@ -365,18 +369,18 @@ template <> struct BufVal<VQE_C128> {
 };
 
 // Pipelined variant of the LDS schedule.  A sub-group of L lanes covers a row
-// of up to U * 4 * L = 256 entries in one pass, and it issues the loads of
-// its next row before it gathers and multiplies the current one, so two rows
-// per sub-group are in flight.  The loads are raw buffer loads issued by every
+// of up to U * 4 * L = 256 entries in one pass and keeps the loads of its next
+// D rows in flight: after a row's products it refills that row's registers
+// with the row D sweeps ahead.  The loads are raw buffer loads issued by every
 // lane without branches: groups past the row (or past the last whole group of
 // the arrays) get an out-of-range offset and return zero without a memory
 // request.  Because the number of loads per row is fixed, the wait before one
-// row's products leaves the other row's loads outstanding (the scheduling
-// barriers keep each row's loads issued before the other row is consumed).  Rows
+// row's products leaves the other rows' loads outstanding (the scheduling
+// barriers keep each refill issued before the next row is consumed).  Rows
 // longer than one pass finish with further passes, and the last nnz % 4
 // entries of the arrays are added entry by entry.
-template <int DT, int L, bool BATCH>
-__global__ void __launch_bounds__(1024)
+template <int DT, int L, int D, bool BATCH>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
               const int2 *__restrict__ tasks)
 {
@@ -493,35 +497,33 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         }
     };
 
-    // two rows per sub-group in flight: A and B alternate
-    int cA[W], cB[W];
-    T vA[W], vB[W];
-    int a0, a1, b0, b1;
-    int64_t rA = r0 + wid * G + sub, rB = rA + 16 * G;
-    row_bounds(rA, a0, a1);
-    issue((a0 & ~3) + 4 * sl, a1, cA, vA);
-    row_bounds(rB, b0, b1);
-    issue((b0 & ~3) + 4 * sl, b1, cB, vB);
+    // D rows per sub-group in flight: each row's buffer is consumed and then
+    // refilled with the sub-group's row D sweeps later
+    int cb[D][W];
+    T vb[D][W];
+    int kb0[D], kb1[D];
+    int64_t rr[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        rr[d] = r0 + (wid + 16 * d) * G + sub;
+        row_bounds(rr[d], kb0[d], kb1[d]);
+        issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+    }
     __builtin_amdgcn_sched_barrier(0);
-    for (int64_t base = r0 + wid * G; base < r1; base += 32 * G) {
-        {
-            double are = 0.0, aim = 0.0;
-            consume((a0 & ~3) + 4 * sl, a0, a1, cA, vA, are, aim);
-            finish(rA, a0, a1, are, aim);
+    for (int64_t base = r0 + wid * G; base < r1; base += 16 * D * G) {
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            {
+                double are = 0.0, aim = 0.0;
+                consume((kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
+                finish(rr[d], kb0[d], kb1[d], are, aim);
+            }
+            rr[d] += 16 * D * G;
+            row_bounds(rr[d], kb0[d], kb1[d]);
+            issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+            // keep the refill ahead of the next row's products
+            __builtin_amdgcn_sched_barrier(0);
         }
-        rA += 32 * G;
-        row_bounds(rA, a0, a1);
-        issue((a0 & ~3) + 4 * sl, a1, cA, vA);
-        __builtin_amdgcn_sched_barrier(0);
-        {
-            double are = 0.0, aim = 0.0;
-            consume((b0 & ~3) + 4 * sl, b0, b1, cB, vB, are, aim);
-            finish(rB, b0, b1, are, aim);
-        }
-        rB += 32 * G;
-        row_bounds(rB, b0, b1);
-        issue((b0 & ~3) + 4 * sl, b1, cB, vB);
-        __builtin_amdgcn_sched_barrier(0);
     }
     __shared__ double s_part[16][3];
     e_re = wave_sum(e_re);
@@ -598,17 +600,17 @@ static void launch_spmv_lds_t(const SpmvState &single, const SpmvState *states, 
     }
 }
 
-template <int DT, int L>
+template <int DT, int L, int D>
 static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, const int2 *tasks,
                              unsigned grid, hipStream_t s, size_t lds)
 {
     if (tasks) {
-        auto k = k_spmv_lds_pf<DT, L, true>;
+        auto k = k_spmv_lds_pf<DT, L, D, true>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
     } else {
-        auto k = k_spmv_lds_pf<DT, L, false>;
+        auto k = k_spmv_lds_pf<DT, L, D, false>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
@@ -622,8 +624,10 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
     constexpr int D = VQE_SPMV_LDS | VQE_SPMV_DEEP;
     constexpr int P = VQE_SPMV_LDS | VQE_SPMV_PREFETCH;
     switch (sched) {
-    case 32 | P: launch_spmv_pf_t<DT, 32>(single, states, tasks, grid, s, lds); return;
-    case 64 | P: launch_spmv_pf_t<DT, 64>(single, states, tasks, grid, s, lds); return;
+    case 32 | P: launch_spmv_pf_t<DT, 32, 2>(single, states, tasks, grid, s, lds); return;
+    case 64 | P: launch_spmv_pf_t<DT, 64, 2>(single, states, tasks, grid, s, lds); return;
+    case 32 | P | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 32, 3>(single, states, tasks, grid, s, lds); return;
+    case 64 | P | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 64, 3>(single, states, tasks, grid, s, lds); return;
     default: break;
     }
     switch (sched) {
@@ -667,6 +671,8 @@ bool vqe_valid_schedule(int sched)
     case 8 | VQE_SPMV_LDS | VQE_SPMV_DEEP: case 16 | VQE_SPMV_LDS | VQE_SPMV_DEEP:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_DEEP: case 64 | VQE_SPMV_LDS | VQE_SPMV_DEEP:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH: case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
+    case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
         return true;
     default:
         return false;

@@ -201,7 +201,8 @@ def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
     plan.close()
 
 
-@pytest.mark.parametrize("sched", [0, 16 | B.VQE_SPMV_LDS, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH])
+@pytest.mark.parametrize("sched", [0, 16 | B.VQE_SPMV_LDS, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP])
 def test_full_size_bench_config(ctx, sched):
     """64 states at 14 qubits in FP32 storage (the benchmark workload):
     sampled states against the oracle, invariants on every state."""
@@ -247,7 +248,8 @@ def test_full_size_bench_config(ctx, sched):
                                    32 | B.VQE_SPMV_LDS, 64 | B.VQE_SPMV_LDS,
                                    16 | B.VQE_SPMV_LDS | B.VQE_SPMV_DEEP,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
-                                   64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH])
+                                   64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
