@@ -194,6 +194,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=0,
                     help="H product schedule (lanes per row, | 256 for wide loads; 0: tuned)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--matrix-free", action=argparse.BooleanOptionalAction, default=False,
+                    help="screen and update from the generators' matrix-free records "
+                         "(no pool CSR) instead of the pool's pair tables")
     ap.add_argument("--retune", action="store_true",
                     help="time every H product schedule even when a tuned one is cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -222,7 +225,7 @@ def main():
     specs, _ = vs.config_c4(n_states=args.states, mixed=False)
     t0 = time.perf_counter()
     systems = [vs.make_system(s) for s in specs]
-    pools = PB.PoolCache(ctx)
+    pools = PB.PoolCache(ctx, matrix_free=args.matrix_free)
     ds = [PB.device_system(ctx, s, args.dtype, pools) for s in systems]
     torch.cuda.synchronize()
     log(f"setup: {len(ds)} systems built on the device in {time.perf_counter() - t0:.1f} s")
@@ -339,6 +342,7 @@ def main():
                         f"argmax, fused Taylor-O(5), FP64 renorm)",
             "states": len(ds), "n_qubits": 14, "n_electrons": 6, "mapping": "jw",
             "pool": 204, "storage": args.dtype, "spmv_schedule": sched,
+            "pool_form": "matrix-free records" if args.matrix_free else "pair tables from the pool CSR",
         },
         "pool_gradient_spmv_GBps": screen_gbs,
         "p50_step_ms": percentile(step_ms, 50),

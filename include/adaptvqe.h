@@ -85,11 +85,82 @@ typedef struct vqe_csr {
     uint32_t reserved;
 } vqe_csr;
 
+/* ------------------------------------------------------------------ matrix-free generators */
+/*
+ * Matrix-free form of a generator given as a Pauli sum A = sum_t c_t P(x_t, z_t)
+ * (Eq. 3), for the on-the-fly treatment of Sec. III-E carried one step further:
+ * the operator is applied straight from its Pauli terms, with no CSR.
+ *
+ * It applies when every term flips the same bits x != 0.  Column c then has
+ * the single entry A[c ^ x, c] = f(c) = sum_t c_t i^{|x & z_t|} (-1)^{|z_t & c|};
+ * f depends on c only through the parities y_i = |beta_i & c| mod 2 for a
+ * basis beta_1..beta_d of span{z_t ^ z_0}, times the sign (-1)^{|z_0 & c|}.
+ * When f vanishes on every parity pattern but one (k), the operator is
+ *     A[c ^ x, c] = v * (-1)^{|zsign & c|}   if |beta_i & c| = k_i mod 2 for all i,
+ *                   0                          otherwise,
+ * with zsign = z_0 and v the value of the sum on pattern k.  Every fermionic
+ * single or double excitation generator under JW or BK has this form (d = 1
+ * or 3 under JW).  The value is the same ordered FP64 sum as the CSR builder's
+ * (term order, from +0.0, up to a sign flip that is exact) and the same drop
+ * rule decides which patterns vanish, so the represented entries equal
+ * csr_build_from_pauli's bit for bit.
+ */
+#define VQE_MF_MAX_CON 8
+typedef struct vqe_mf_desc {
+    uint64_t x;                      /* common flip mask */
+    uint64_t zsign;                  /* sign mask (z of the first term) */
+    double v_re, v_im;               /* value on the support */
+    int32_t n_qubits;
+    int32_t n_con;                   /* d, at most VQE_MF_MAX_CON */
+    uint64_t beta[VQE_MF_MAX_CON];   /* support constraints (reduced echelon form) */
+    uint32_t kbits;                  /* bit i = required parity k_i */
+    uint32_t reserved;
+} vqe_mf_desc;
+/*
+ * Derive the matrix-free form of one generator from its Pauli terms (HOST
+ * arrays: xmask, zmask [n_terms], coeff [2*n_terms] interleaved re, im).
+ * A pattern's value is dropped when |re| <= drop_tol and |im| <= drop_tol.
+ * Host computation only (no device, no context).  Errors: VQE_EINVAL (bad
+ * arguments, a mask bit >= n_qubits); VQE_ENOTSUP (terms with different x,
+ * x = 0, more than VQE_MF_MAX_CON constraints, zero or several nonvanishing
+ * patterns, or a support not closed under c -> c ^ x).
+ */
+VQE_API int vqe_mf_describe(int32_t n_qubits, int64_t n_terms, const uint64_t *xmask,
+                            const uint64_t *zmask, const double *coeff, double drop_tol,
+                            vqe_mf_desc *out);
+/*
+ * A pool in matrix-free form: M generators, generator j made of the terms
+ * [term_offset[j], term_offset[j+1]) of the HOST arrays xmask, zmask, coeff.
+ * drop_tol: host double[M], or NULL for 1e-12 * max_t |c_t| per generator.
+ * The object holds host descriptors only; plans that use it build their
+ * device records.  Errors as vqe_mf_describe (the message names the generator).
+ */
+typedef struct vqe_mf_pool vqe_mf_pool;
+VQE_API int vqe_mf_pool_create(int32_t n_qubits, int32_t M, const int64_t *term_offset,
+                               const uint64_t *xmask, const uint64_t *zmask, const double *coeff,
+                               const double *drop_tol, vqe_mf_pool **out);
+VQE_API int vqe_mf_pool_destroy(vqe_mf_pool *pool);
+/* Copy generator j's descriptor (host); VQE_EINVAL if j is out of range. */
+VQE_API int vqe_mf_pool_get(const vqe_mf_pool *pool, int32_t j, vqe_mf_desc *out);
+/*
+ * Host mirror of the device enumeration, for checking without a GPU: the
+ * owner rows r (the lower row of each pair {r, r ^ x}) of generator j on row
+ * tile `tile` of a screen whose tiles hold tile_rows rows (tile = -1: the
+ * whole state, as the update enumerates them), in the order the device visits
+ * them.  *count receives the number of rows; rows_out (host uint32[*count],
+ * nullable) the rows; lds_index_out (nullable) each row's index in the tile.
+ */
+VQE_API int vqe_mf_owner_rows(const vqe_mf_pool *pool, int32_t j, int64_t tile_rows, int32_t tile,
+                              int64_t *count, uint32_t *rows_out, uint32_t *lds_index_out);
+
 /*
  * An operator pool (Sec. III-A): M generators of one dimension and dtype.
  * ops is a DEVICE array of M descriptors (each pointing to device CSR
  * arrays); ops_host is the same array in host memory (read for sizes and
  * flags, never dereferenced on the device).  Both are owned by the caller.
+ * mf (nullable) is the same pool in matrix-free form; a batch plan then
+ * screens and updates from it and reads no pool CSR, so ops and ops_host may
+ * be NULL when mf is set.
  */
 typedef struct vqe_pool {
     int32_t M;
@@ -98,6 +169,7 @@ typedef struct vqe_pool {
     int32_t all_pairing;  /* 1 if every generator has VQE_PAIRING */
     const vqe_csr *ops;
     const vqe_csr *ops_host;
+    const vqe_mf_pool *mf;
 } vqe_pool;
 
 typedef struct vqe_ctx vqe_ctx;

@@ -50,16 +50,20 @@ class DeviceSystem:
 
 
 class PoolCache:
-    """One device pool per (n_qubits, n_electrons, mapping, dtype)."""
+    """One device pool per (n_qubits, n_electrons, mapping, dtype).  With
+    matrix_free=True the pools are matrix-free (no generator CSR on the
+    device; batch plans screen and update from the Pauli-derived records)."""
 
-    def __init__(self, ctx: B.Context):
+    def __init__(self, ctx: B.Context, matrix_free: bool = False):
         self.ctx = ctx
+        self.matrix_free = matrix_free
         self._pools: dict = {}
 
-    def get(self, key: tuple, packs, dtype: str) -> B.DevicePool:
+    def get(self, key: tuple, packs, dtype: str):
         k = key + (dtype,)
         if k not in self._pools:
-            self._pools[k] = B.pool_from_packs(self.ctx, packs, dtype)
+            self._pools[k] = (B.MatrixFreePool(packs, dtype) if self.matrix_free
+                              else B.pool_from_packs(self.ctx, packs, dtype))
         return self._pools[k]
 
     def drop(self, key: tuple, dtype: str):
@@ -117,12 +121,17 @@ def bytes_per_step(systems: list) -> dict:
         sx = s.psi.element_size()
         sv = s.H.val.element_size()
         out["h_spmv"] += 4 * (dim + 1) + s.H.nnz * (4 + sv) + 2 * dim * sx
+        out["pool_screen"] += 2 * dim * sx + 8 * s.pool.M
+        if isinstance(s.pool, B.MatrixFreePool):
+            # no generator arrays: the update reads and writes the support of
+            # a single excitation (2^(N-1) amplitudes)
+            out["taylor"] += 2 * (dim // 2) * sx
+            continue
         pid = id(s.pool)
         if pid not in seen:
             seen.add(pid)
             out["pool_screen"] += sum(4 * (dim + 1) + o.nnz * (4 + o.val.element_size())
                                       for o in s.pool.ops)
-        out["pool_screen"] += 2 * dim * sx + 8 * s.pool.M
         nnz_single = max(o.nnz for o in s.pool.ops)
         out["taylor"] += 4 * (dim + 1) + nnz_single * (4 + sv) + 2 * dim * sx
     return out

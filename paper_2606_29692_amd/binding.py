@@ -42,9 +42,20 @@ class vqe_csr(C.Structure):
                 ("reserved", C.c_uint32)]
 
 
+VQE_MF_MAX_CON = 8
+
+
+class vqe_mf_desc(C.Structure):
+    _fields_ = [("x", C.c_uint64), ("zsign", C.c_uint64), ("v_re", C.c_double),
+                ("v_im", C.c_double), ("n_qubits", C.c_int32), ("n_con", C.c_int32),
+                ("beta", C.c_uint64 * VQE_MF_MAX_CON), ("kbits", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
 class vqe_pool(C.Structure):
     _fields_ = [("M", C.c_int32), ("n_qubits", C.c_int32), ("dtype", C.c_int32),
-                ("all_pairing", C.c_int32), ("ops", C.c_void_p), ("ops_host", C.c_void_p)]
+                ("all_pairing", C.c_int32), ("ops", C.c_void_p), ("ops_host", C.c_void_p),
+                ("mf", C.c_void_p)]
 
 
 class vqe_batch_item(C.Structure):
@@ -86,6 +97,14 @@ SIGNATURES = {
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
     "vqe_default_schedule": (C.c_int32, [C.POINTER(vqe_csr)]),
+    "vqe_mf_describe": (C.c_int, [C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_double, C.POINTER(vqe_mf_desc)]),
+    "vqe_mf_pool_create": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "vqe_mf_pool_destroy": (C.c_int, [C.c_void_p]),
+    "vqe_mf_pool_get": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_mf_desc)]),
+    "vqe_mf_owner_rows": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
+                                    C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
 }
 
 _lib = None
@@ -283,6 +302,125 @@ class DevicePool:
 
 def pool_from_packs(ctx: Context, packs, dtype: str = "c128") -> DevicePool:
     return DevicePool(ctx, [csr_from_pack(ctx, p, dtype) for p in packs])
+
+
+# ---------------------------------------------------------------- matrix-free generators
+def _desc_dict(d: vqe_mf_desc) -> dict:
+    return {"x": int(d.x), "zsign": int(d.zsign), "v": complex(d.v_re, d.v_im),
+            "n_qubits": int(d.n_qubits), "beta": [int(d.beta[i]) for i in range(d.n_con)],
+            "kbits": int(d.kbits)}
+
+
+def _pack_arrays(packs):
+    xs, zs, cs, off = [], [], [], [0]
+    for p in packs:
+        xs.append(np.asarray(p.xmask, dtype=np.uint64))
+        zs.append(np.asarray(p.zmask, dtype=np.uint64))
+        c = np.asarray(p.coeff, dtype=np.complex128)
+        cs.append(np.ascontiguousarray(np.stack([c.real, c.imag], axis=1)).reshape(-1))
+        off.append(off[-1] + len(c))
+    return (np.ascontiguousarray(np.concatenate(xs)), np.ascontiguousarray(np.concatenate(zs)),
+            np.ascontiguousarray(np.concatenate(cs)), np.asarray(off, dtype=np.int64))
+
+
+def mf_describe(pack, drop_tol: float | None = None) -> dict:
+    """Matrix-free form of one generator (host computation, no GPU): the
+    flip mask x, sign mask zsign, value v and support constraints
+    (|beta_i & c| mod 2 = bit i of kbits).  Raises VqeError when the
+    generator has no such form."""
+    x, z, c, _ = _pack_arrays([pack])
+    if drop_tol is None:
+        drop_tol = default_tol(pack.coeff)
+    d = vqe_mf_desc()
+    rc = lib().vqe_mf_describe(int(pack.n_qubits), len(x), x.ctypes.data, z.ctypes.data,
+                               c.ctypes.data, float(drop_tol), C.byref(d))
+    if rc != 0:
+        raise VqeError(rc, f"vqe_mf_describe: {lib().vqe_strerror(rc).decode()}")
+    return _desc_dict(d)
+
+
+class MfPool:
+    """A pool in matrix-free form (host descriptors; no GPU needed to build)."""
+
+    def __init__(self, packs, drop_tol=None):
+        packs = list(packs)
+        if not packs:
+            raise ValueError("empty pool")
+        x, z, c, off = _pack_arrays(packs)
+        tol = None
+        if drop_tol is not None:
+            tol = np.ascontiguousarray(np.broadcast_to(np.asarray(drop_tol, dtype=np.float64),
+                                                       (len(packs),)))
+        h = C.c_void_p()
+        rc = lib().vqe_mf_pool_create(int(packs[0].n_qubits), len(packs), off.ctypes.data,
+                                      x.ctypes.data, z.ctypes.data, c.ctypes.data,
+                                      tol.ctypes.data if tol is not None else None, C.byref(h))
+        if rc != 0:
+            raise VqeError(rc, f"vqe_mf_pool_create: {lib().vqe_strerror(rc).decode()}")
+        self.handle = h.value
+        self.M = len(packs)
+        self.n_qubits = int(packs[0].n_qubits)
+
+    def get(self, j: int) -> dict:
+        d = vqe_mf_desc()
+        rc = lib().vqe_mf_pool_get(self.handle, int(j), C.byref(d))
+        if rc != 0:
+            raise VqeError(rc, "vqe_mf_pool_get")
+        return _desc_dict(d)
+
+    def owner_rows(self, j: int, tile_rows: int, tile: int = -1):
+        """(rows, tile indices) of generator j on one screen tile (tile = -1:
+        the whole state), in the device's enumeration order."""
+        n = C.c_int64()
+        rc = lib().vqe_mf_owner_rows(self.handle, int(j), int(tile_rows), int(tile), C.byref(n),
+                                     None, None)
+        if rc != 0:
+            raise VqeError(rc, "vqe_mf_owner_rows")
+        rows = np.zeros(n.value, dtype=np.uint32)
+        idx = np.zeros(n.value, dtype=np.uint32)
+        rc = lib().vqe_mf_owner_rows(self.handle, int(j), int(tile_rows), int(tile), C.byref(n),
+                                     rows.ctypes.data, idx.ctypes.data)
+        if rc != 0:
+            raise VqeError(rc, "vqe_mf_owner_rows")
+        return rows, idx
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().vqe_mf_pool_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MatrixFreePool:
+    """A pool for batch plans that is applied from its matrix-free form only:
+    no generator CSR exists on the device."""
+
+    def __init__(self, packs, dtype: str = "c128", drop_tol=None):
+        self.mf = MfPool(packs, drop_tol)
+        self.desc = vqe_pool()
+        self.desc.M = self.mf.M
+        self.desc.n_qubits = self.mf.n_qubits
+        self.desc.dtype = DTYPES[dtype]
+        self.desc.all_pairing = 1
+        self.desc.ops = None
+        self.desc.ops_host = None
+        self.desc.mf = self.mf.handle
+
+    @property
+    def M(self) -> int:
+        return self.mf.M
+
+    @property
+    def ops(self) -> list:
+        return []
+
+    def nbytes(self) -> int:
+        return 0
 
 
 def pool_gradients(ctx: Context, H: DeviceCSR, pool: DevicePool, psi, sigma=None, g_out=None):

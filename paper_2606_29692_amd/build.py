@@ -22,7 +22,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libadaptvqe.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["capi.hip", "csr_build.hip", "spmv.hip", "grad.hip", "screen.hip", "taylor.hip"]
+SOURCES = ["capi.hip", "csr_build.hip", "spmv.hip", "grad.hip", "screen.hip", "taylor.hip",
+           "mfree.hip"]
 NO_CONTRACT = {"csr_build.hip"}
 
 BASE_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -152,6 +152,7 @@ struct vqe_batch {
     hipGraphExec_t exec[16] = {};
     hipGraph_t graph[16] = {};
     bool compact_taylor = false;   // every pool has a compact pair table
+    bool mf = false;               // every pool is matrix-free: screen and update from records
     // host image of the descriptors (for rebinding slots)
     std::vector<char> image;
     size_t o_spmv = 0, o_screen = 0, o_tay = 0;
@@ -214,15 +215,22 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
     SpmvState dummy{};
     k_energy_finalize<<<(unsigned)p->B, 64, 0, s>>>(dummy, p->d_spmv, p->B);
     int rc = mark(2);
-    if (p->n_screen_tasks)
+    if (p->mf) {
+        launch_screen_mf(p->dtype, p->d_screen, p->d_screen_tasks, p->n_screen_tasks,
+                         p->screen_lds, s);
+        launch_screen_fin(p->d_screen, p->d_tables, (unsigned)p->B, s);
+    } else if (p->n_screen_tasks) {
         launch_screen(p->dtype, p->d_screen, p->d_tables, p->d_screen_tasks, p->n_screen_tasks,
                       (unsigned)p->B, p->screen_lds, s);
+    }
     rc = rc ? rc : mark(3);
     if (!(flags & VQE_STEP_FORCED))
         launch_select(p->d_sel, (unsigned)p->B, p->rel_tie, s);
     rc = rc ? rc : mark(4);
     if (!(flags & VQE_STEP_NO_UPDATE)) {
-        if (p->compact_taylor)
+        if (p->mf)
+            launch_taylor_mf(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
+        else if (p->compact_taylor)
             launch_taylor_compact(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
         else
             launch_taylor_pair(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
@@ -334,12 +342,28 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             return rc;
         if (it.H->dtype != dtype)
             return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: states differ in dtype");
-        if (!it.pool || it.pool->M < 1 || !it.pool->ops || !it.pool->ops_host ||
-            it.pool->n_qubits != it.H->n_qubits || it.pool->dtype != dtype)
+        if (!it.pool || it.pool->M < 1 || it.pool->n_qubits != it.H->n_qubits ||
+            it.pool->dtype != dtype)
             return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: bad pool for state %d", s);
-        if (!it.pool->all_pairing)
-            return vqe_fail(ctx, VQE_ENOTSUP,
-                            "vqe_batch_create: state %d has a non-pairing generator", s);
+        if (!(it.pool->mf ? true : false) != !(items[0].pool && items[0].pool->mf))
+            return vqe_fail(ctx, VQE_EINVAL,
+                            "vqe_batch_create: either every pool or none is matrix-free");
+        if (it.pool->mf) {
+            // the matrix-free screen stages row pairs with 16-byte loads
+            if ((((uintptr_t)it.psi) & 15) || (((uintptr_t)it.sigma) & 15))
+                return vqe_fail(ctx, VQE_EINVAL,
+                                "vqe_batch_create: psi and sigma must be 16-byte aligned");
+            if (vqe_mf_pool_size(it.pool->mf) != it.pool->M ||
+                vqe_mf_pool_qubits(it.pool->mf) != it.pool->n_qubits)
+                return vqe_fail(ctx, VQE_EINVAL,
+                                "vqe_batch_create: matrix-free pool of state %d does not match", s);
+        } else {
+            if (!it.pool->ops || !it.pool->ops_host)
+                return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: bad pool for state %d", s);
+            if (!it.pool->all_pairing)
+                return vqe_fail(ctx, VQE_ENOTSUP,
+                                "vqe_batch_create: state %d has a non-pairing generator", s);
+        }
         if (!it.psi || !it.sigma)
             return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_create: null psi or sigma");
         if (it.spmv_schedule != 0 && !vqe_valid_schedule(it.spmv_schedule))
@@ -405,71 +429,146 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         spmv_maxdim.push_back(md);
     }
 
-    // --- gradient screen: one pair table per distinct pool; tasks per
-    //     (state, row tile, generator range), on the state's XCD
+    const bool mf_mode = items[0].pool->mf != nullptr;
+    p->mf = mf_mode;
+    // pool identity: the matrix-free object, or the CSR descriptor array
+    auto pool_key = [&](const vqe_pool *pl) -> const void * {
+        return mf_mode ? (const void *)pl->mf : (const void *)pl->ops;
+    };
+    auto fail_free = [&](int rc) {
+        for (void *m : p->table_mem)
+            (void)hipFree(m);
+        delete p;
+        return rc;
+    };
+
+    // --- gradient screen: one table per distinct pool (pair table, or the
+    //     matrix-free records); tasks per (state, row tile, generator range),
+    //     on the state's XCD
     std::map<const void *, int> table_of;
     std::vector<PairTable> tables;
+    std::vector<const MfTable *> mf_dev;        // device header per table (mf mode)
+    std::vector<MfHostPlan> mf_plans;
     for (int s = 0; s < B; s++) {
-        const void *key = (const void *)items[s].pool->ops;
+        const void *key = pool_key(items[s].pool);
         if (table_of.count(key))
             continue;
         PairTable tb{};
-        void *mem[2] = {nullptr, nullptr};
-        size_t bytes = 0;
-        int rc = pair_table_build(ctx, items[s].pool, items[s].H->dim, &tb, mem, &bytes);
-        if (rc) {
-            for (void *m : p->table_mem)
-                (void)hipFree(m);
-            delete p;
-            return rc;
+        if (mf_mode) {
+            MfHostPlan hp;
+            char err[160] = {0};
+            const int32_t tile = screen_tile_rows(items[s].H->dim, dtype);
+            int rc = mf_host_plan(items[s].pool->mf, tile, &hp, err, sizeof(err));
+            if (rc)
+                return fail_free(vqe_fail(ctx, rc, "vqe_batch_create: %s", err));
+            // one allocation: header, tile records, whole-state records, lists
+            const size_t o_h = 0, o_t = vqe_align(sizeof(MfTable));
+            const size_t o_f = o_t + vqe_align(hp.tile_recs.size() * sizeof(MfRec));
+            const size_t o_l = o_f + vqe_align(hp.full_recs.size() * sizeof(MfRec));
+            const size_t bytes = o_l + vqe_align(hp.lists.size() * sizeof(int32_t) + 4);
+            char *mem = nullptr;
+            if (hipMalloc((void **)&mem, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail_free(vqe_fail(ctx, VQE_ENOMEM, "vqe_batch_create: record allocation failed"));
+            }
+            p->table_mem.push_back(mem);
+            p->table_bytes += bytes;
+            MfTable h{};
+            h.tile_recs = (const MfRec *)(mem + o_t);
+            h.full_recs = (const MfRec *)(mem + o_f);
+            h.lists = (const int32_t *)(mem + o_l);
+            h.M = hp.M;
+            h.ntile = hp.ntile;
+            h.tile_rows = hp.tile_rows;
+            hipError_t e = hipMemcpy(mem + o_h, &h, sizeof(h), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(mem + o_t, hp.tile_recs.data(), hp.tile_recs.size() * sizeof(MfRec),
+                              hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(mem + o_f, hp.full_recs.data(), hp.full_recs.size() * sizeof(MfRec),
+                              hipMemcpyHostToDevice);
+            if (e == hipSuccess && !hp.lists.empty())
+                e = hipMemcpy(mem + o_l, hp.lists.data(), hp.lists.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice);
+            if (e != hipSuccess)
+                return fail_free(vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: record upload: %s",
+                                          hipGetErrorString(e)));
+            tb.M = hp.M;
+            tb.nt = hp.ntile;
+            tb.tile_rows = hp.tile_rows;
+            mf_dev.push_back((const MfTable *)(mem + o_h));
+            mf_plans.push_back(std::move(hp));
+        } else {
+            void *mem[2] = {nullptr, nullptr};
+            size_t bytes = 0;
+            int rc = pair_table_build(ctx, items[s].pool, items[s].H->dim, &tb, mem, &bytes);
+            if (rc)
+                return fail_free(rc);
+            for (void *m : mem)
+                if (m)
+                    p->table_mem.push_back(m);
+            p->table_bytes += bytes;
         }
         table_of[key] = (int)tables.size();
         tables.push_back(tb);
-        for (void *m : mem)
-            if (m)
-                p->table_mem.push_back(m);
-        p->table_bytes += bytes;
     }
     const size_t o_tables = A.take(sizeof(PairTable) * tables.size());
     const size_t o_screen = A.take(sizeof(ScreenState) * B);
     std::vector<std::vector<int4>> screen_per(kXcd);
     const int n_ranges = 2;
     for (int s = 0; s < B; s++) {
-        const PairTable &tb = tables[table_of[(const void *)items[s].pool->ops]];
+        const int ti = table_of[pool_key(items[s].pool)];
+        const PairTable &tb = tables[ti];
         const int M = tb.M;
-        const int nr = std::min(n_ranges, M);
-        for (int t = 0; t < tb.nt; t++)
-            for (int r = 0; r < nr; r++)
-                screen_per[xcd_of[s]].push_back(make_int4(s, t, r, nr));
-        const int64_t rows = std::min<int64_t>(tb.tile_rows, items[s].H->dim);
-        p->screen_lds = std::max(p->screen_lds, (size_t)(2 * rows * vqe_elem_bytes(dtype)));
+        if (mf_mode) {
+            // about eight workgroups per state, split over the lists by work
+            const MfHostPlan &hp = mf_plans[ti];
+            double W = 0.0;
+            for (auto &L : hp.list_info)
+                W += L.work;
+            for (auto &L : hp.list_info) {
+                const int nr = std::max(1, std::min({L.len, 255, (int)std::lround(8.0 * L.work / W)}));
+                for (int r = 0; r < nr; r++)
+                    screen_per[xcd_of[s]].push_back(make_int4(s, L.off, L.len, r | (nr << 8) | (L.v << 16)));
+            }
+            const size_t elem = 2 * vqe_elem_bytes(dtype);
+            p->screen_lds = std::max(p->screen_lds, (size_t)hp.tile_rows * elem);
+        } else {
+            const int nr = std::min(n_ranges, M);
+            for (int t = 0; t < tb.nt; t++)
+                for (int r = 0; r < nr; r++)
+                    screen_per[xcd_of[s]].push_back(make_int4(s, t, r, nr));
+            const int64_t rows = std::min<int64_t>(tb.tile_rows, items[s].H->dim);
+            p->screen_lds = std::max(p->screen_lds, (size_t)(2 * rows * vqe_elem_bytes(dtype)));
+        }
         o_gpart[s] = A.take((size_t)M * tb.nt * sizeof(double));
     }
     auto screen_flat = interleave(screen_per, make_int4(-1, 0, 0, 0));
     const size_t o_stasks = A.take(screen_flat.size() * sizeof(int4));
 
-    // --- Taylor and norm tasks (compact tables: blocks cover the largest
-    //     generator's pairs; otherwise the CSR rows)
-    p->compact_taylor = true;
+    // --- Taylor and norm tasks (matrix-free records or compact tables: blocks
+    //     cover the largest generator's pairs; otherwise the CSR rows)
+    p->compact_taylor = !mf_mode;
     std::vector<int> max_pairs(tables.size(), 0);
     for (size_t i = 0; i < tables.size(); i++) {
+        if (mf_mode) {
+            for (const MfRec &r : mf_plans[i].full_recs)
+                max_pairs[i] = std::max(max_pairs[i], r.nfree < 0 ? 0 : 1 << r.nfree);
+            continue;
+        }
         p->compact_taylor = p->compact_taylor && tables[i].words != nullptr;
         const PairTable &tb = tables[i];
         std::vector<int32_t> pts((size_t)tb.M * tb.nt + 1);
-        if (hipMemcpy(pts.data(), tb.pts, pts.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
-            for (void *m : p->table_mem)
-                (void)hipFree(m);
-            delete p;
-            return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: reading the pair table failed");
-        }
+        if (hipMemcpy(pts.data(), tb.pts, pts.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail_free(vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: reading the pair table failed"));
         for (int j = 0; j < tb.M; j++)
             max_pairs[i] = std::max(max_pairs[i], pts[(size_t)(j + 1) * tb.nt] - pts[(size_t)j * tb.nt]);
     }
     std::vector<std::vector<int2>> tay_per(kXcd), norm_per(kXcd);
     for (int s = 0; s < B; s++) {
         const int64_t dim = items[s].H->dim;
-        const int mp = max_pairs[table_of[(const void *)items[s].pool->ops]];
-        const int nt = p->compact_taylor
+        const int mp = max_pairs[table_of[pool_key(items[s].pool)]];
+        const int nt = (mf_mode || p->compact_taylor)
                            ? std::max(1, (mp + TAYLOR_ROWS_PER_BLOCK - 1) / TAYLOR_ROWS_PER_BLOCK)
                            : (int)((dim + TAYLOR_ROWS_PER_BLOCK - 1) / TAYLOR_ROWS_PER_BLOCK);
         const int nn = (int)((dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
@@ -528,8 +627,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ts.norm2_out = nullptr;
         ts.nblocks = (int32_t)((it.H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
         ts.renorm = 1;
-        ts.table = (const PairTable *)(D + o_tables) + table_of[(const void *)it.pool->ops];
+        ts.table = (const PairTable *)(D + o_tables) + table_of[pool_key(it.pool)];
         ts.active = io->active ? io->active + s : nullptr;
+        ts.mf = mf_mode ? mf_dev[table_of[pool_key(it.pool)]] : nullptr;
     }
     std::copy(tables.begin(), tables.end(), A.at<PairTable>(o_tables));
     for (int s = 0; s < B; s++) {
@@ -540,8 +640,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ss.partials = (double *)(D + o_gpart[s]);
         ss.g_out = io->g_out + io->g_offset_host[s];
         ss.dim = items[s].H->dim;
-        ss.table = table_of[(const void *)items[s].pool->ops];
+        ss.table = table_of[pool_key(items[s].pool)];
         ss.active = io->active ? io->active + s : nullptr;
+        ss.mf = mf_mode ? mf_dev[table_of[pool_key(items[s].pool)]] : nullptr;
     }
     for (size_t i = 0; i < spmv_tab.size(); i++) {
         std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));
@@ -567,7 +668,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     p->o_tay = o_tay;
     p->sched = lanes;
     for (int s = 0; s < B; s++) {
-        p->pool_ops.push_back((const void *)items[s].pool->ops);
+        p->pool_ops.push_back(pool_key(items[s].pool));
         p->dims.push_back(items[s].H->dim);
     }
     hipError_t e = hipMemcpyAsync(p->dmem, A.host.data(), p->dmem_bytes, hipMemcpyHostToDevice,
@@ -597,7 +698,8 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
     if (rc)
         return rc;
     if (!it->pool || !it->psi || !it->sigma || it->H->dtype != p->dtype ||
-        it->H->dim != p->dims[slot] || (const void *)it->pool->ops != p->pool_ops[slot])
+        it->H->dim != p->dims[slot] ||
+        (p->mf ? (const void *)it->pool->mf : (const void *)it->pool->ops) != p->pool_ops[slot])
         return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: item does not match slot %d", slot);
     const int sched = vqe_effective_schedule(
         it->H, it->spmv_schedule ? it->spmv_schedule : vqe_default_schedule(it->H));

@@ -4,6 +4,8 @@
 
 #include "common.hpp"
 
+#include <vector>
+
 // True when a batch slot is switched off for this step (uniform per workgroup).
 #define VQE_SKIP(st) ((st).active && !*gmem((st).active))
 
@@ -59,6 +61,7 @@ struct GradGroup {
 };
 
 struct PairTable;
+struct MfTable;
 
 // One state of the Taylor update.
 struct TaylorState {
@@ -77,6 +80,7 @@ struct TaylorState {
     const int32_t *active;     // batch slot flag (nullable): 0 = skip this state
     int32_t nblocks;
     int32_t renorm;
+    const MfTable *mf;         // matrix-free records of the pool (nullable)
 };
 
 // Per-state argmax.
@@ -115,13 +119,71 @@ struct ScreenState {
     const int32_t *active;  // batch slot flag (nullable): 0 = skip this state
     int32_t table;          // index into the plan's PairTable array
     int32_t pad;
+    const MfTable *mf;      // matrix-free records of the pool (nullable)
 };
+
+// Matrix-free enumeration of a generator's pairs {r, c = r ^ x} on a row set
+// (one row tile of the screen, or the whole state for the update).  The
+// owner rows r (bit h = top bit of x clear) of the row set are
+//     r = D(e) ^ P(D(e)) ^ base,  e in [0, 2^nfree),
+// where D deposits the bits of e into the free bit positions, base holds the
+// tile's fixed bits, and P sets every pivot bit piv_i to k_i ^ |beta_i & r|.
+#define MF_LANE_BITS 8     // screen: 64 lanes x 4 elements cover the lowest free bits
+#define MF_MAX_TB 4
+struct MfRec {
+    uint32_t x, zsign;      // flip mask, sign mask: A[r ^ x, r] = v (-1)^{|zsign & r|}
+    uint32_t cx;            // x with the tile bits removed (LDS index offset)
+    uint32_t ex;            // |zsign & x| mod 2
+    uint32_t base;          // fixed tile bits of this row set
+    uint32_t free_mask;     // all free bits
+    uint32_t hi_mask;       // free bits above the lowest nlow
+    int32_t nfree;          // owner rows on the row set = 2^nfree; -1: none
+    int32_t nlow;           // min(nfree, MF_LANE_BITS)
+    int32_t ncon;           // pivots
+    uint32_t kbits;
+    int32_t j;              // generator index
+    int32_t ntb;            // tile bits
+    int32_t antiherm;       // A[c, r] = -conj(A[r, c]) on every pair
+    uint8_t lowpos[MF_LANE_BITS];   // positions of the lowest nlow free bits
+    uint8_t piv[VQE_MF_MAX_CON];
+    uint8_t tbpos[MF_MAX_TB];   // tile bit positions, descending
+    uint32_t pad;
+    uint32_t beta[VQE_MF_MAX_CON];
+    double v_re, v_im;
+};
+
+struct MfTable {
+    const MfRec *tile_recs;   // [M * ntile]: generator j on tile v at j * ntile + v
+    const MfRec *full_recs;   // [M]: generator j on the whole state
+    const int32_t *lists;     // generator indices per (tile-bit group, tile), by descending cost
+    int32_t M, ntile, tile_rows, pad;
+};
+
+struct vqe_mf_pool;
+// Host: records of every generator of a pool for a state of 2^n rows whose
+// screen tiles hold tile_rows rows.  Returns VQE_OK or VQE_ENOTSUP.
+struct MfHostPlan {
+    std::vector<MfRec> tile_recs, full_recs;
+    std::vector<int32_t> lists;                    // concatenated
+    struct List { int32_t off, len, v; double work; };
+    std::vector<List> list_info;
+    int32_t M = 0, ntile = 1, tile_rows = 0;
+};
+int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, char *err, size_t n_err);
+void launch_screen_mf(int dtype, const ScreenState *states, const int4 *tasks, unsigned grid,
+                      size_t lds, hipStream_t s);
+void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
+                      hipStream_t s);
 
 int32_t screen_tile_rows(int64_t dim, int dtype);
 int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable *tb,
                      void **mem_out, size_t *bytes_out);
 void launch_screen(int dtype, const ScreenState *states, const PairTable *tables,
                    const int4 *tasks, unsigned grid, unsigned n_states, size_t lds, hipStream_t s);
+void launch_screen_fin(const ScreenState *states, const PairTable *tables, unsigned n_states,
+                       hipStream_t s);
+int32_t vqe_mf_pool_size(const vqe_mf_pool *pool);
+int32_t vqe_mf_pool_qubits(const vqe_mf_pool *pool);
 
 #define TAYLOR_ROWS_PER_BLOCK 256
 #define NORM_ROWS_PER_BLOCK 2048

@@ -1,0 +1,769 @@
+// Matrix-free generators: a pool of excitation-type generators applied
+// straight from their Pauli terms (Eq. 3), with no CSR and no pair table.
+//
+// Derivation (host).  Every term of generator A flips the same bits x, so
+// column c holds the single entry A[c ^ x, c] = f(c) with
+//     f(c) = sum_t w_t (-1)^{|z_t & c|},   w_t = c_t i^{|x & z_t|}.
+// Writing z_t = z_0 ^ D_t and taking a reduced echelon basis beta_1..beta_d
+// of span{D_t}, D_t = XOR_i lambda_ti beta_i, so
+//     f(c) = (-1)^{|z_0 & c|} g(y),  y_i = |beta_i & c| mod 2,
+//     g(y) = sum_t w_t (-1)^{lambda_t . y}.
+// g is evaluated on all 2^d patterns in term order from +0.0, the sum the
+// CSR builder forms (up to the common sign, which rounding respects); when
+// one pattern k survives the drop rule the support is the coset
+// {c : |beta_i & c| = k_i}, closed under c -> c ^ x when every beta_i . x = 0.
+//
+// Enumeration (device).  A pair {r, c = r ^ x} is owned by the row with bit
+// h (the top bit of x) clear.  Fixing h, the screen's tile bits (bits outside
+// x, so a pair never leaves its tile) and the pivots of the reduced
+// constraints leaves free bits; owner rows are enumerated by depositing a
+// counter into them and setting every pivot from its parity constraint.  All
+// of it is XOR-linear, so the screen splits each row index into a per-lane
+// part (the lowest free bits, computed once per generator) and a per-iteration
+// part (wave-uniform, on the scalar unit): the inner loop is two XORs and two
+// LDS reads per pair.
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+struct vqe_mf_pool {
+    int32_t n_qubits = 0;
+    std::vector<vqe_mf_desc> desc;
+};
+
+namespace {
+
+inline int parity64(uint64_t v) { return __builtin_popcountll(v) & 1; }
+inline int top_bit(uint64_t v) { return 63 - __builtin_clzll(v); }
+
+// ------------------------------------------------------------------ derivation
+int describe(int32_t n_qubits, int64_t n_terms, const uint64_t *xm, const uint64_t *zm,
+             const double *coeff, double tol, vqe_mf_desc *out)
+{
+    if (n_qubits < 1 || n_qubits > 30 || n_terms < 1 || !xm || !zm || !coeff || !out ||
+        !(tol >= 0.0))
+        return VQE_EINVAL;
+    const uint64_t lim = ((uint64_t)1 << n_qubits) - 1;
+    const uint64_t x = xm[0];
+    for (int64_t t = 0; t < n_terms; t++) {
+        if ((xm[t] | zm[t]) & ~lim)
+            return VQE_EINVAL;
+        if (xm[t] != x)
+            return VQE_ENOTSUP;
+    }
+    if (x == 0)
+        return VQE_ENOTSUP;
+    // reduced echelon basis of span{z_t ^ z_0}; pivot = highest bit
+    const uint64_t z0 = zm[0];
+    uint64_t basis[64];
+    int piv[64];
+    int d = 0;
+    for (int64_t t = 1; t < n_terms; t++) {
+        uint64_t v = zm[t] ^ z0;
+        for (int i = 0; i < d; i++)
+            if ((v >> piv[i]) & 1)
+                v ^= basis[i];
+        if (!v)
+            continue;
+        if (d == VQE_MF_MAX_CON)
+            return VQE_ENOTSUP;
+        const int p = top_bit(v);
+        for (int i = 0; i < d; i++)
+            if ((basis[i] >> p) & 1)
+                basis[i] ^= v;
+        basis[d] = v;
+        piv[d] = p;
+        d++;
+    }
+    // pattern sums g(y), y in [0, 2^d): lambda_t,i = bit piv_i of D_t
+    std::vector<double> gre((size_t)1 << d, 0.0), gim((size_t)1 << d, 0.0);
+    for (int64_t t = 0; t < n_terms; t++) {
+        const uint64_t D = zm[t] ^ z0;
+        uint32_t lam = 0;
+        for (int i = 0; i < d; i++)
+            lam |= (uint32_t)((D >> piv[i]) & 1) << i;
+        // w_t = c_t i^{|x & z_t|}
+        double wr = coeff[2 * t], wi = coeff[2 * t + 1];
+        switch (__builtin_popcountll(x & zm[t]) & 3) {
+        case 1: { const double a = wr; wr = -wi; wi = a; break; }
+        case 2: wr = -wr; wi = -wi; break;
+        case 3: { const double a = wr; wr = wi; wi = -a; break; }
+        default: break;
+        }
+        for (uint32_t y = 0; y < ((uint32_t)1 << d); y++) {
+            const bool neg = __builtin_popcount(lam & y) & 1;
+            gre[y] += neg ? -wr : wr;
+            gim[y] += neg ? -wi : wi;
+        }
+    }
+    int found = -1;
+    for (uint32_t y = 0; y < ((uint32_t)1 << d); y++) {
+        if (std::fabs(gre[y]) <= tol && std::fabs(gim[y]) <= tol)
+            continue;
+        if (found >= 0)
+            return VQE_ENOTSUP;   // several cosets
+        found = (int)y;
+    }
+    if (found < 0)
+        return VQE_ENOTSUP;       // the operator vanishes
+    for (int i = 0; i < d; i++)
+        if (parity64(basis[i] & x))
+            return VQE_ENOTSUP;   // support not closed under c -> c ^ x
+    vqe_mf_desc o{};
+    o.x = x;
+    o.zsign = z0;
+    o.v_re = gre[found];
+    o.v_im = gim[found];
+    o.n_qubits = n_qubits;
+    o.n_con = d;
+    for (int i = 0; i < d; i++)
+        o.beta[i] = basis[i];
+    o.kbits = (uint32_t)found;
+    *out = o;
+    return VQE_OK;
+}
+
+// ------------------------------------------------------------------ host records
+uint32_t compress_bits(uint32_t a, const uint8_t *tbpos, int ntb)
+{
+    for (int i = 0; i < ntb; i++) {   // descending positions
+        const int p = tbpos[i];
+        a = ((a >> (p + 1)) << p) | (a & ((1u << p) - 1u));
+    }
+    return a;
+}
+
+// Record of generator d on the row set with tile bits tb (value bits vbits).
+// Returns false when the constraints leave no owner row on the set.
+void make_rec(const vqe_mf_desc &d, int j, int n, uint32_t tb, uint32_t vbits, MfRec *rec)
+{
+    MfRec r{};
+    r.x = (uint32_t)d.x;
+    r.zsign = (uint32_t)d.zsign;
+    r.ex = (uint32_t)parity64(d.zsign & d.x);
+    r.base = vbits;
+    r.j = j;
+    r.v_re = d.v_re;
+    r.v_im = d.v_im;
+    // anti-Hermitian on every pair: A[c, r] = -conj(A[r, c]), i.e.
+    // v (-1)^ex = -conj(v)
+    const double s = r.ex ? -1.0 : 1.0;
+    r.antiherm = (s * d.v_re == -d.v_re && s * d.v_im == d.v_im) ? 1 : 0;
+    const int h = top_bit(d.x);
+    // tile bit positions, descending
+    r.ntb = 0;
+    for (int p = n - 1; p >= 0; p--)
+        if ((tb >> p) & 1)
+            r.tbpos[r.ntb++] = (uint8_t)p;
+    r.cx = compress_bits(r.x, r.tbpos, r.ntb);
+    // constraints with bit h (= 0 on owner rows) and the tile bits substituted
+    uint32_t beta[VQE_MF_MAX_CON];
+    uint32_t kb[VQE_MF_MAX_CON];
+    int m = 0;
+    bool empty = false;
+    for (int i = 0; i < d.n_con; i++) {
+        uint32_t b = (uint32_t)d.beta[i] & ~(1u << h);
+        uint32_t k = (d.kbits >> i) & 1u;
+        k ^= (uint32_t)__builtin_popcount(b & vbits) & 1u;
+        b &= ~tb;
+        for (int q = 0; q < m; q++)
+            if ((b >> r.piv[q]) & 1) {
+                b ^= beta[q];
+                k ^= kb[q];
+            }
+        if (!b) {
+            if (k)
+                empty = true;
+            continue;
+        }
+        const int p = 31 - __builtin_clz(b);
+        for (int q = 0; q < m; q++)
+            if ((beta[q] >> p) & 1) {
+                beta[q] ^= b;
+                kb[q] ^= k;
+            }
+        beta[m] = b;
+        kb[m] = k;
+        r.piv[m] = (uint8_t)p;
+        m++;
+    }
+    r.ncon = m;
+    uint32_t pivmask = 0;
+    for (int q = 0; q < m; q++) {
+        r.beta[q] = beta[q];
+        r.kbits |= kb[q] << q;
+        pivmask |= 1u << r.piv[q];
+    }
+    const uint32_t all = n == 32 ? 0xffffffffu : ((1u << n) - 1u);
+    r.free_mask = all & ~(1u << h) & ~tb & ~pivmask;
+    r.nfree = empty ? -1 : __builtin_popcount(r.free_mask);
+    r.nlow = empty ? 0 : std::min(r.nfree, MF_LANE_BITS);
+    uint32_t low = 0;
+    int c = 0;
+    for (int p = 0; p < n && c < r.nlow; p++)
+        if ((r.free_mask >> p) & 1) {
+            r.lowpos[c++] = (uint8_t)p;
+            low |= 1u << p;
+        }
+    r.hi_mask = r.free_mask & ~low;
+    *rec = r;
+}
+
+}  // namespace
+
+int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, char *err,
+                 size_t n_err)
+{
+    const int n = pool->n_qubits;
+    const int64_t dim = (int64_t)1 << n;
+    const int M = (int)pool->desc.size();
+    int kt = 0;
+    while (((int64_t)tile_rows << kt) < dim)
+        kt++;
+    if (kt > MF_MAX_TB) {
+        std::snprintf(err, n_err, "matrix-free screen: too many row tiles");
+        return VQE_ENOTSUP;
+    }
+    const int ntile = 1 << kt;
+    out->M = M;
+    out->ntile = ntile;
+    out->tile_rows = (int32_t)std::min<int64_t>(tile_rows, dim);
+    out->tile_recs.assign((size_t)M * ntile, MfRec{});
+    out->full_recs.assign((size_t)M, MfRec{});
+    out->lists.clear();
+    out->list_info.clear();
+    std::vector<uint32_t> tbs(M);
+    for (int j = 0; j < M; j++) {
+        const vqe_mf_desc &d = pool->desc[j];
+        // tile bits: the kt highest bits outside x
+        uint32_t tb = 0;
+        int got = 0;
+        for (int p = n - 1; p >= 0 && got < kt; p--)
+            if (!((d.x >> p) & 1)) {
+                tb |= 1u << p;
+                got++;
+            }
+        if (got < kt || (tb & 1u)) {
+            // (the staging reads row pairs {2i, 2i + 1}, so bit 0 is never a tile bit)
+            std::snprintf(err, n_err, "matrix-free screen: generator %d leaves no tile bit", j);
+            return VQE_ENOTSUP;
+        }
+        tbs[j] = tb;
+        int64_t owners = 0;
+        for (int v = 0; v < ntile; v++) {
+            uint32_t vbits = 0;
+            int b = 0;
+            for (int p = 0; p < n; p++)
+                if ((tb >> p) & 1) {
+                    if ((v >> b) & 1)
+                        vbits |= 1u << p;
+                    b++;
+                }
+            MfRec &rec = out->tile_recs[(size_t)j * ntile + v];
+            make_rec(d, j, n, tb, vbits, &rec);
+            if (rec.nfree >= 0)
+                owners += (int64_t)1 << rec.nfree;
+        }
+        make_rec(d, j, n, 0u, 0u, &out->full_recs[j]);
+        const int64_t expect = (int64_t)1 << (n - 1 - d.n_con);
+        if (owners != expect || out->full_recs[j].nfree < 0 ||
+            ((int64_t)1 << out->full_recs[j].nfree) != expect) {
+            std::snprintf(err, n_err, "matrix-free records of generator %d are inconsistent", j);
+            return VQE_ENOTSUP;
+        }
+    }
+    // lists per (tile-bit group, tile): generators by descending cost
+    std::vector<uint32_t> groups(tbs);
+    std::sort(groups.begin(), groups.end());
+    groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
+    for (uint32_t tb : groups)
+        for (int v = 0; v < ntile; v++) {
+            std::vector<int32_t> js;
+            for (int j = 0; j < M; j++)
+                if (tbs[j] == tb)
+                    js.push_back(j);
+            auto cost = [&](int32_t j) {
+                const MfRec &r = out->tile_recs[(size_t)j * ntile + v];
+                return r.nfree < 0 ? 0.0 : std::ldexp(1.0, r.nfree);
+            };
+            std::stable_sort(js.begin(), js.end(),
+                             [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+            double work = 0.0;
+            for (int32_t j : js)
+                work += cost(j) + 64.0;   // a generator costs at least one wave pass
+            out->list_info.push_back({(int32_t)out->lists.size(), (int32_t)js.size(), v, work});
+            out->lists.insert(out->lists.end(), js.begin(), js.end());
+        }
+    return VQE_OK;
+}
+
+// ------------------------------------------------------------------ kernels
+namespace {
+
+// A record's enumeration fields held in registers: every loop below runs to
+// the compile-time maximum with a predicate, so no array is indexed
+// dynamically (which would move it to scratch memory).
+struct MfRegs {
+    uint32_t beta[VQE_MF_MAX_CON];
+    uint32_t piv[VQE_MF_MAX_CON];
+    uint32_t tbpos[MF_MAX_TB];
+    uint32_t lowpos[MF_LANE_BITS];
+    uint32_t kbits;
+    int ncon, ntb, nlow;
+};
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ MfRegs load_regs(const MfRec &r)
+{
+    MfRegs m;
+    m.ncon = (int)uni((uint32_t)r.ncon);
+    m.ntb = (int)uni((uint32_t)r.ntb);
+    m.nlow = (int)uni((uint32_t)r.nlow);
+    m.kbits = uni(r.kbits);
+#pragma unroll
+    for (int i = 0; i < VQE_MF_MAX_CON; i++) {
+        m.beta[i] = uni(r.beta[i]);
+        m.piv[i] = uni(r.piv[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < MF_MAX_TB; i++)
+        m.tbpos[i] = uni(r.tbpos[i]);
+#pragma unroll
+    for (int i = 0; i < MF_LANE_BITS; i++)
+        m.lowpos[i] = uni(r.lowpos[i]);
+    return m;
+}
+
+// remove the tile bits (descending positions) from a row index
+__device__ __forceinline__ uint32_t dev_compress(uint32_t a, const MfRegs &m)
+{
+#pragma unroll
+    for (int i = 0; i < MF_MAX_TB; i++)
+        if (i < m.ntb) {
+            const uint32_t p = m.tbpos[i];
+            a = ((a >> (p + 1)) << p) | (a & ((1u << p) - 1u));
+        }
+    return a;
+}
+
+// pivot bits of a partial row index a (free bits only): sum_i (k_i ^ |beta_i & a|) << piv_i,
+// with the k_i included when withk
+__device__ __forceinline__ uint32_t dev_pivots(uint32_t a, const MfRegs &m, bool withk)
+{
+    uint32_t p = 0;
+#pragma unroll
+    for (int i = 0; i < VQE_MF_MAX_CON; i++)
+        if (i < m.ncon) {
+            const uint32_t bit =
+                ((uint32_t)__popc(m.beta[i] & a) ^ (withk ? (m.kbits >> i) : 0u)) & 1u;
+            p |= bit << m.piv[i];
+        }
+    return p;
+}
+
+// Tile element: psi and sigma of one row.
+template <int DT> struct TileElem;
+template <> struct TileElem<VQE_C64> {
+    using T = float4;   // psi.re, psi.im, sigma.re, sigma.im
+    static __device__ __forceinline__ T load(const void *psi, const void *sig, int64_t r)
+    {
+        const float2 a = ldg(reinterpret_cast<const float2 *>(psi), r);
+        const float2 b = ldg(reinterpret_cast<const float2 *>(sig), r);
+        return make_float4(a.x, a.y, b.x, b.y);
+    }
+    static __device__ __forceinline__ void get(const T *t, uint32_t i, double2 &p, double2 &s)
+    {
+        const float4 e = t[i];
+        p = make_double2(e.x, e.y);
+        s = make_double2(e.z, e.w);
+    }
+};
+template <> struct TileElem<VQE_C128> {
+    struct T { double2 p, s; };
+    static __device__ __forceinline__ T load(const void *psi, const void *sig, int64_t r)
+    {
+        T e;
+        e.p = ldg(reinterpret_cast<const double2 *>(psi), r);
+        e.s = ldg(reinterpret_cast<const double2 *>(sig), r);
+        return e;
+    }
+    static __device__ __forceinline__ void get(const T *t, uint32_t i, double2 &p, double2 &s)
+    {
+        p = t[i].p;
+        s = t[i].s;
+    }
+};
+
+// Sum over the owner rows of one generator on the staged tile of
+// (-1)^{|zsign & r|} [(-1)^ex conj(s_r) psi_c + conj(s_c) psi_r],  s = sigma (+ shift psi).
+// Lane l takes the elements e = l + 64 u (u < MF_LANE_UNROLL) of the lowest
+// free bits; the wave-uniform parts of the row index for up to 64 loop
+// iterations are computed once, one iteration per lane, and read back with
+// readlane, so the inner loop issues no scalar arithmetic.
+#define MF_LANE_UNROLL 4
+template <int DT, bool SHIFT>
+__device__ __forceinline__ double2 mf_tile_sum(const typename TileElem<DT>::T *tile, const MfRec &rec,
+                                               double shift, int lane)
+{
+    const MfRegs m = load_regs(rec);
+    const uint32_t zsign = uni(rec.zsign), cx = uni(rec.cx), base = uni(rec.base);
+    double sre = 0.0, sim = 0.0;
+    constexpr int U = MF_LANE_UNROLL;
+    uint32_t cl[U], sl[U];
+    bool on[U];
+    // element e = lane + 64 u: the six lane bits per lane, the two u bits as
+    // wave-uniform corrections (deposit, pivots, compression and sign are all
+    // XOR-linear in e)
+    uint32_t L0 = 0;
+#pragma unroll
+    for (int b = 0; b < 6; b++)
+        if (b < m.nlow)
+            L0 |= (((uint32_t)lane >> b) & 1u) << m.lowpos[b];
+    const uint32_t RL0 = L0 ^ dev_pivots(L0, m, false);
+    const uint32_t cl0 = dev_compress(RL0, m);
+    const uint32_t sl0 = (uint32_t)__popc(zsign & RL0) & 1u;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        on[u] = (uint32_t)lane + 64u * u < (1u << m.nlow);
+        uint32_t Lu = 0;
+        if ((u & 1) && m.nlow > 6)
+            Lu |= 1u << m.lowpos[6];
+        if ((u & 2) && m.nlow > 7)
+            Lu |= 1u << m.lowpos[7];
+        const uint32_t RU = uni(Lu ^ dev_pivots(Lu, m, false));
+        cl[u] = cl0 ^ uni(dev_compress(RU, m));
+        sl[u] = sl0 ^ ((uint32_t)__popc(zsign & RU) & 1u);
+    }
+    const double e1 = uni(rec.ex) ? -1.0 : 1.0;
+    const uint32_t hi = uni(rec.hi_mask);
+    const int n_it = 1 << ((int)uni((uint32_t)rec.nfree) - m.nlow);
+    for (int c0 = 0; c0 < n_it; c0 += 64) {
+        // iteration c0 + lane: deposit into the loop bits, pivots, tile index, sign
+        uint32_t chv = 0, shv = 0;
+        {
+            uint32_t H = 0, bits = (uint32_t)(c0 + lane);
+            for (uint32_t mm = hi; mm; mm &= mm - 1u) {
+                if (bits & 1u)
+                    H |= mm & (0u - mm);
+                bits >>= 1;
+            }
+            const uint32_t RH = H ^ dev_pivots(H, m, true) ^ base;
+            chv = dev_compress(RH, m);
+            shv = (uint32_t)__popc(zsign & RH) & 1u;
+        }
+        const int nin = n_it - c0 < 64 ? n_it - c0 : 64;
+        for (int i = 0; i < nin; i++) {
+            const uint32_t ch = __builtin_amdgcn_readlane(chv, i);
+            const uint32_t sh = __builtin_amdgcn_readlane(shv, i);
+            double2 pr[U], sr[U], pc[U], sc[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t ir = on[u] ? (cl[u] ^ ch) : 0u, ic = on[u] ? (ir ^ cx) : 0u;
+                TileElem<DT>::get(tile, ir, pr[u], sr[u]);
+                TileElem<DT>::get(tile, ic, pc[u], sc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                if (SHIFT) {
+                    sr[u].x += shift * pr[u].x;
+                    sr[u].y += shift * pr[u].y;
+                    sc[u].x += shift * pc[u].x;
+                    sc[u].y += shift * pc[u].y;
+                }
+                // conj(s_r) psi_c and conj(s_c) psi_r
+                const double u1r = sr[u].x * pc[u].x + sr[u].y * pc[u].y;
+                const double u1i = sr[u].x * pc[u].y - sr[u].y * pc[u].x;
+                const double u2r = sc[u].x * pr[u].x + sc[u].y * pr[u].y;
+                const double u2i = sc[u].x * pr[u].y - sc[u].y * pr[u].x;
+                const double tr = e1 * u1r + u2r, ti = e1 * u1i + u2i;
+                const bool neg = (sl[u] ^ sh) & 1u;
+                const double w = on[u] ? (neg ? -1.0 : 1.0) : 0.0;
+                sre += w * tr;
+                sim += w * ti;
+            }
+        }
+    }
+    return make_double2(sre, sim);
+}
+
+// One workgroup per (state, tile-bit group, tile, generator range): stage the
+// tile's psi and sigma in LDS, then one wave per generator.
+template <int DT>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tasks)
+{
+    const int4 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const ScreenState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    const MfTable tb = *st.mf;
+    const int32_t *list = tb.lists + task.y;
+    const int n = task.z;
+    const int range = task.w & 0xff, n_ranges = (task.w >> 8) & 0xff, v = task.w >> 16;
+    using T = typename TileElem<DT>::T;
+    extern __shared__ unsigned char smem[];
+    T *tile = reinterpret_cast<T *>(smem);
+    const MfRec &r0 = tb.tile_recs[(int64_t)list[0] * tb.ntile + v];
+    const int64_t rows = tb.tile_rows;
+    const int ntb = (int)uni((uint32_t)r0.ntb);
+    const uint32_t base = uni(r0.base);
+    uint32_t tbp[MF_MAX_TB];
+#pragma unroll
+    for (int q = 0; q < MF_MAX_TB; q++)
+        tbp[q] = uni(r0.tbpos[q]);
+    // staging: each thread issues the loads of SU rows before its LDS writes
+    constexpr int SU = 8;
+    for (int64_t i0 = threadIdx.x; i0 < rows; i0 += 1024 * SU) {
+        typename TileElem<DT>::T e[SU];
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+            const int64_t i = i0 + 1024 * u;
+            if (i < rows) {
+                // insert the tile bits (ascending positions) into i
+                uint32_t r = (uint32_t)i;
+#pragma unroll
+                for (int q = MF_MAX_TB - 1; q >= 0; q--)
+                    if (q < ntb) {
+                        const uint32_t p = tbp[q];
+                        r = ((r >> p) << (p + 1)) | (r & ((1u << p) - 1u)) | (base & (1u << p));
+                    }
+                e[u] = TileElem<DT>::load(st.psi, st.sigma, (int64_t)r);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; u++)
+            if (i0 + 1024 * u < rows)
+                tile[i0 + 1024 * u] = e[u];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int idx = wid;; idx += 16) {
+        const int e = range + idx * n_ranges;
+        if (e >= n)
+            break;
+        const int j = __builtin_amdgcn_readfirstlane(gmem(list)[e]);
+        const MfRec &rec = tb.tile_recs[(int64_t)j * tb.ntile + v];
+        double part = 0.0;
+        if (rec.nfree >= 0) {
+            const double2 S = (st.shift != 0.0 && !rec.antiherm)
+                                  ? mf_tile_sum<DT, true>(tile, rec, st.shift, lane)
+                                  : mf_tile_sum<DT, false>(tile, rec, 0.0, lane);
+            const double re = group_sum<64>(S.x), im = group_sum<64>(S.y);
+            part = rec.v_re * re - rec.v_im * im;
+        }
+        if (lane == 0)
+            gmem(st.partials)[(int64_t)j * tb.ntile + v] = part;
+    }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Fused Taylor-5 update on the selected generator's pairs, one thread per
+// owner row, enumerated from the generator's whole-state record.
+template <int DT>
+__global__ void __launch_bounds__(TAYLOR_ROWS_PER_BLOCK)
+k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const TaylorState *stp = states + task.x;
+    if (VQE_SKIP(*stp))
+        return;
+    const int32_t k = *stp->k;
+    if (k < 0 || k >= stp->M)
+        return;
+    const MfRec &rec = stp->mf->full_recs[k];
+    const int64_t e = (int64_t)task.y * TAYLOR_ROWS_PER_BLOCK + threadIdx.x;
+    if (rec.nfree < 0 || e >= ((int64_t)1 << rec.nfree))
+        return;
+    // deposit e into the free bits, then the pivots
+    uint32_t a = 0, fm = rec.free_mask, ee = (uint32_t)e;
+    while (fm) {
+        const uint32_t low = fm & (0u - fm);
+        if (ee & 1u)
+            a |= low;
+        ee >>= 1;
+        fm ^= low;
+    }
+    const uint32_t r = a ^ dev_pivots(a, load_regs(rec), true);
+    const uint32_t c = r ^ rec.x;
+    const double2 v = make_double2(rec.v_re, rec.v_im);
+    // A[r, c] = v (-1)^{|zsign & c|}, A[c, r] = v (-1)^{|zsign & r|}
+    const double sa = (__popc(rec.zsign & c) & 1) ? -1.0 : 1.0;
+    const double sb = (__popc(rec.zsign & r) & 1) ? -1.0 : 1.0;
+    const double2 A = make_double2(sa * v.x, sa * v.y), Bv = make_double2(sb * v.x, sb * v.y);
+    const double theta = *stp->theta;
+    double cf[6];
+    cf[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= 5; q++)
+        cf[q] = cf[q - 1] * theta / (double)q;
+    void *psi = stp->psi;
+    double2 vr = Elem<DT>::ld(psi, r), vc = Elem<DT>::ld(psi, c);
+    double2 ar = vr, ac = vc;
+#pragma unroll
+    for (int q = 1; q <= 5; q++) {
+        const double2 nr = cmul(A, vc);
+        const double2 nc = cmul(Bv, vr);
+        vr = nr;
+        vc = nc;
+        ar.x += cf[q] * vr.x;
+        ar.y += cf[q] * vr.y;
+        ac.x += cf[q] * vc.x;
+        ac.y += cf[q] * vc.y;
+    }
+    Elem<DT>::st(psi, r, ar);
+    Elem<DT>::st(psi, c, ac);
+}
+
+}  // namespace
+
+void launch_screen_mf(int dtype, const ScreenState *states, const int4 *tasks, unsigned grid,
+                      size_t lds, hipStream_t s)
+{
+    if (dtype == VQE_C128) {
+        (void)hipFuncSetAttribute((const void *)k_screen_mf<VQE_C128>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_screen_mf<VQE_C128><<<grid, 1024, lds, s>>>(states, tasks);
+    } else {
+        (void)hipFuncSetAttribute((const void *)k_screen_mf<VQE_C64>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_screen_mf<VQE_C64><<<grid, 1024, lds, s>>>(states, tasks);
+    }
+}
+
+void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
+                      hipStream_t s)
+{
+    if (dtype == VQE_C128)
+        k_taylor_mf<VQE_C128><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(states, tasks);
+    else
+        k_taylor_mf<VQE_C64><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(states, tasks);
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" int vqe_mf_describe(int32_t n_qubits, int64_t n_terms, const uint64_t *xmask,
+                               const uint64_t *zmask, const double *coeff, double drop_tol,
+                               vqe_mf_desc *out)
+{
+    return describe(n_qubits, n_terms, xmask, zmask, coeff, drop_tol, out);
+}
+
+extern "C" int vqe_mf_pool_create(int32_t n_qubits, int32_t M, const int64_t *term_offset,
+                                  const uint64_t *xmask, const uint64_t *zmask,
+                                  const double *coeff, const double *drop_tol, vqe_mf_pool **out)
+{
+    if (!out)
+        return VQE_EINVAL;
+    *out = nullptr;
+    if (M < 1 || !term_offset || !xmask || !zmask || !coeff || n_qubits < 1 || n_qubits > 30)
+        return VQE_EINVAL;
+    vqe_mf_pool *p = new (std::nothrow) vqe_mf_pool();
+    if (!p)
+        return VQE_ENOMEM;
+    p->n_qubits = n_qubits;
+    p->desc.resize(M);
+    for (int j = 0; j < M; j++) {
+        const int64_t t0 = term_offset[j], t1 = term_offset[j + 1];
+        if (t0 < 0 || t1 <= t0) {
+            delete p;
+            return VQE_EINVAL;
+        }
+        double tol;
+        if (drop_tol) {
+            tol = drop_tol[j];
+        } else {
+            double mx = 0.0;
+            for (int64_t t = t0; t < t1; t++)
+                mx = std::max(mx, std::hypot(coeff[2 * t], coeff[2 * t + 1]));
+            tol = 1e-12 * mx;
+        }
+        const int rc = describe(n_qubits, t1 - t0, xmask + t0, zmask + t0, coeff + 2 * t0, tol,
+                                &p->desc[j]);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+    }
+    *out = p;
+    return VQE_OK;
+}
+
+extern "C" int vqe_mf_pool_destroy(vqe_mf_pool *pool)
+{
+    delete pool;
+    return VQE_OK;
+}
+
+extern "C" int vqe_mf_pool_get(const vqe_mf_pool *pool, int32_t j, vqe_mf_desc *out)
+{
+    if (!pool || !out || j < 0 || j >= (int32_t)pool->desc.size())
+        return VQE_EINVAL;
+    *out = pool->desc[j];
+    return VQE_OK;
+}
+
+// Host mirror of the device enumeration (same record, same lane/iteration
+// split), for tests without a GPU.
+extern "C" int vqe_mf_owner_rows(const vqe_mf_pool *pool, int32_t j, int64_t tile_rows,
+                                 int32_t tile, int64_t *count, uint32_t *rows_out,
+                                 uint32_t *lds_index_out)
+{
+    if (!pool || !count || j < 0 || j >= (int32_t)pool->desc.size() || tile_rows < 1)
+        return VQE_EINVAL;
+    MfHostPlan hp;
+    char err[160];
+    int rc = mf_host_plan(pool, tile_rows, &hp, err, sizeof(err));
+    if (rc)
+        return rc;
+    if (tile < -1 || tile >= hp.ntile)
+        return VQE_EINVAL;
+    const MfRec &rec = tile < 0 ? hp.full_recs[j] : hp.tile_recs[(size_t)j * hp.ntile + tile];
+    if (rec.nfree < 0) {
+        *count = 0;
+        return VQE_OK;
+    }
+    auto pivots = [&](uint32_t a, bool withk) {
+        uint32_t p = 0;
+        for (int i = 0; i < rec.ncon; i++)
+            p |= ((uint32_t)(__builtin_popcount(rec.beta[i] & a) ^ (withk ? (rec.kbits >> i) : 0u)) & 1u)
+                 << rec.piv[i];
+        return p;
+    };
+    const int64_t n = (int64_t)1 << rec.nfree;
+    *count = n;
+    if (!rows_out)
+        return VQE_OK;
+    int64_t o = 0;
+    const int n_it = 1 << (rec.nfree - rec.nlow);
+    uint32_t H = 0;
+    for (int it = 0; it < n_it; it++) {
+        const uint32_t RH = H ^ pivots(H, true) ^ rec.base;
+        for (uint32_t e = 0; e < (1u << rec.nlow); e++) {
+            uint32_t L = 0;
+            for (int b = 0; b < rec.nlow; b++)
+                L |= ((e >> b) & 1u) << rec.lowpos[b];
+            const uint32_t RL = L ^ pivots(L, false);
+            rows_out[o] = RL ^ RH;
+            if (lds_index_out)
+                lds_index_out[o] = compress_bits(RL, rec.tbpos, rec.ntb) ^
+                                   compress_bits(RH, rec.tbpos, rec.ntb);
+            o++;
+        }
+        H = ((H | ~rec.hi_mask) + 1u) & rec.hi_mask;
+    }
+    return VQE_OK;
+}
+
+int32_t vqe_mf_pool_size(const vqe_mf_pool *pool) { return (int32_t)pool->desc.size(); }
+int32_t vqe_mf_pool_qubits(const vqe_mf_pool *pool) { return pool->n_qubits; }

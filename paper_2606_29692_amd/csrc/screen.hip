@@ -156,9 +156,22 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     const int64_t base = (int64_t)t * tb.tile_rows;
     const T *psi = reinterpret_cast<const T *>(st.psi);
     const T *sig = reinterpret_cast<const T *>(st.sigma);
-    for (int64_t i = threadIdx.x; i < rows; i += 1024) {
-        s_psi[i] = ldg(psi, base + i);
-        s_sig[i] = ldg(sig, base + i);
+    // each thread issues the loads of SU rows before its LDS writes
+    constexpr int SU = 8;
+    for (int64_t i0 = threadIdx.x; i0 < rows; i0 += 1024 * SU) {
+        T a[SU], b[SU];
+#pragma unroll
+        for (int u = 0; u < SU; u++)
+            if (i0 + 1024 * u < rows) {
+                a[u] = ldg(psi, base + i0 + 1024 * u);
+                b[u] = ldg(sig, base + i0 + 1024 * u);
+            }
+#pragma unroll
+        for (int u = 0; u < SU; u++)
+            if (i0 + 1024 * u < rows) {
+                s_psi[i0 + 1024 * u] = a[u];
+                s_sig[i0 + 1024 * u] = b[u];
+            }
     }
     __syncthreads();
     const double shift = st.shift;
@@ -436,6 +449,12 @@ int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable 
     mem_out[1] = compact ? (void *)d_words : nullptr;
     *bytes_out = bytes + (compact ? (size_t)total * 4 + (size_t)M * 4 : 0);
     return VQE_OK;
+}
+
+void launch_screen_fin(const ScreenState *states, const PairTable *tables, unsigned n_states,
+                       hipStream_t s)
+{
+    k_screen_fin<<<n_states, 256, 0, s>>>(states, tables);
 }
 
 void launch_screen(int dtype, const ScreenState *states, const PairTable *tables,

@@ -1,0 +1,176 @@
+"""Matrix-free batch plans: pools applied from their Pauli-derived records.
+
+* the matrix-free screen and update agree with the CSR-pool plan on the same
+  states (energies bit for bit, since the H product is shared; gradients to
+  FP64 rounding; the same selections; states to rounding);
+* against the FP64 oracle: FP64 storage to 1e-12 along forced trajectories
+  (JW and BK, equilibrium and stretched), FP32 storage at 14 qubits (row
+  tiles of one and two tile bits) within the FP32 bars;
+* alone vs inside a mixed batch bit for bit, graph replays equal to eager.
+"""
+import numpy as np
+import pytest
+
+import vqe_system as vs
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2606_29692_amd import batch as PB  # noqa: E402
+from paper_2606_29692_amd import binding as B  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    prev = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    c = B.Context(0, stream)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+    torch.cuda.set_stream(prev)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def mixed_specs():
+    return [vs.SystemSpec(8, 4, "jw", False, 201), vs.SystemSpec(10, 4, "bk", False, 202),
+            vs.SystemSpec(12, 8, "jw", True, 203), vs.SystemSpec(8, 4, "bk", True, 204),
+            vs.SystemSpec(12, 8, "bk", False, 205)]
+
+
+def oracle_run(system, thetas, steps, forced):
+    oH = orc.csr_from_pack(system.hamiltonian)
+    return orc.adapt_run(oH, [orc.csr_from_pack(p) for p in system.pool],
+                         vs.reference_state(system), thetas, steps, forced=forced)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_matrix_free_equals_csr_plan(ctx, dtype):
+    specs = mixed_specs()
+    systems = [vs.make_system(s) for s in specs]
+    csr_pools, mf_pools = PB.PoolCache(ctx), PB.PoolCache(ctx, matrix_free=True)
+    a = [PB.device_system(ctx, s, dtype, csr_pools) for s in systems]
+    b = [PB.device_system(ctx, s, dtype, mf_pools) for s in systems]
+    pa, pb = PB.make_batch(ctx, a), PB.make_batch(ctx, b)
+    steps = 4
+    thetas = np.stack([vs.draw_thetas(s.seed, steps) for s in specs])
+    # FP32 storage: the matrix-free screen drops the diagonal-shift terms of
+    # each pair, which cancel exactly for anti-Hermitian generators
+    gtol = 1e-12 if dtype == "c128" else 1e-9
+    ptol = 1e-14 if dtype == "c128" else 1e-6
+    for t in range(steps):
+        print(f"matrix-free vs CSR plan {dtype} step {t}", flush=True)
+        th = torch.from_numpy(thetas[:, t])
+        pa.theta.copy_(th)
+        pb.theta.copy_(th)
+        pa.step(renorm=True)
+        pb.step(renorm=True)
+        np.testing.assert_array_equal(host(pb.energies), host(pa.energies))
+        np.testing.assert_array_equal(host(pb.k), host(pa.k))
+        for i in range(len(specs)):
+            ga, gb = host(pa.gradients(i)), host(pb.gradients(i))
+            np.testing.assert_allclose(gb, ga, rtol=0, atol=gtol * max(1.0, np.abs(ga).max()))
+        for x, y in zip(a, b):
+            np.testing.assert_allclose(host(y.psi), host(x.psi), rtol=0, atol=ptol)
+    pa.close()
+    pb.close()
+
+
+def test_matrix_free_fp64_vs_oracle(ctx):
+    specs = mixed_specs()
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx, matrix_free=True)
+    ds = [PB.device_system(ctx, s, "c128", pools) for s in systems]
+    plan = PB.make_batch(ctx, ds)
+    steps = 5
+    thetas = np.stack([vs.draw_thetas(s.seed, steps) for s in specs])
+    E, K, G = [], [], []
+    for t in range(steps):
+        plan.theta.copy_(torch.from_numpy(thetas[:, t]))
+        plan.step(renorm=True, graph=True)
+        E.append(host(plan.energies).reshape(-1, 3)[:, 0].copy())
+        K.append(host(plan.k).copy())
+        G.append([host(plan.gradients(i)).copy() for i in range(len(specs))])
+    K = np.array(K)
+    for i, s in enumerate(systems):
+        tr = oracle_run(s, thetas[i], steps, forced=K[:, i])
+        for t in range(steps):
+            assert abs(E[t][i] - tr.energies[t]) <= 1e-12 * max(1.0, abs(tr.energies[t]))
+            g_o = tr.gradients[t]
+            np.testing.assert_allclose(G[t][i], g_o, rtol=0, atol=1e-12 * max(1.0, np.abs(g_o).max()))
+            assert abs(g_o[K[t, i]]) >= np.abs(g_o).max() * (1 - 1e-6)
+        psi = host(ds[i].psi)
+        assert np.linalg.norm(psi - tr.psi) <= 1e-12 * np.linalg.norm(tr.psi)
+        print(f"state {i} ({specs[i].mapping}, N={specs[i].n_qubits}) matches the oracle")
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype,n_states", [("c64", 8), ("c128", 3)])
+def test_matrix_free_14_qubits_vs_oracle(ctx, dtype, n_states):
+    """14 qubits: FP32 storage tiles the state by one bit, FP64 by two."""
+    specs, _ = vs.config_c4(n_states=n_states, mixed=False)
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx, matrix_free=True)
+    ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+    plan = PB.make_batch(ctx, ds)
+    steps = 2
+    thetas = np.stack([vs.draw_thetas(s.seed, steps) for s in specs])
+    E, K, G = [], [], []
+    for t in range(steps):
+        plan.theta.copy_(torch.from_numpy(thetas[:, t]))
+        plan.step(renorm=True, graph=True)
+        E.append(host(plan.energies).reshape(-1, 3)[:, 0].copy())
+        K.append(host(plan.k).copy())
+        G.append([host(plan.gradients(i)).copy() for i in range(len(specs))])
+    K = np.array(K)
+    for i in (0, len(specs) - 1):
+        tr = oracle_run(systems[i], thetas[i], steps, forced=K[:, i])
+        psi = host(ds[i].psi).astype(np.complex128)
+        fid = abs(np.vdot(psi, tr.psi)) ** 2 / (np.vdot(psi, psi).real * np.vdot(tr.psi, tr.psi).real)
+        for t in range(steps):
+            g_o = tr.gradients[t]
+            dg = np.abs(G[t][i] - g_o).max()
+            de = abs(E[t][i] - tr.energies[t])
+            print(f"{dtype} state {i} step {t}: |dE|={de:.2e} max|dg|={dg:.2e}", flush=True)
+            if dtype == "c128":
+                assert de <= 1e-12 * max(1.0, abs(tr.energies[t]))
+                assert dg <= 1e-12 * max(1.0, np.abs(g_o).max())
+            else:
+                assert de < 1e-6 and dg < 1e-5
+        assert fid > (1 - 1e-12 if dtype == "c128" else 0.999999)
+    plan.close()
+
+
+def test_matrix_free_alone_vs_mixed_and_graph(ctx):
+    specs = mixed_specs()
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx, matrix_free=True)
+    mixed = [PB.device_system(ctx, s, "c64", pools) for s in systems]
+    alone = PB.device_system(ctx, systems[4], "c64", pools)
+    eager = [PB.device_system(ctx, s, "c64", pools) for s in systems]
+    pm, pa, pe = PB.make_batch(ctx, mixed), PB.make_batch(ctx, [alone]), PB.make_batch(ctx, eager)
+    th = vs.draw_thetas(specs[4].seed, 5)
+    for t in range(5):
+        pm.theta.fill_(0.04)
+        pm.theta[4] = float(th[t])
+        pe.theta.copy_(pm.theta)
+        pa.theta.fill_(float(th[t]))
+        pm.step(renorm=True, graph=True)
+        pe.step(renorm=True, graph=False)
+        pa.step(renorm=True, graph=False)
+        print(f"matrix-free alone vs mixed step {t}", flush=True)
+        np.testing.assert_array_equal(host(pm.energies)[12:15], host(pa.energies)[0:3])
+        np.testing.assert_array_equal(host(pm.gradients(4)), host(pa.gradients(0)))
+        np.testing.assert_array_equal(host(mixed[4].psi), host(alone.psi))
+        # graph replay equals the eager step
+        np.testing.assert_array_equal(host(pm.g), host(pe.g))
+        for x, y in zip(mixed, eager):
+            np.testing.assert_array_equal(host(x.psi), host(y.psi))
+    for p in (pm, pa, pe):
+        p.close()
