@@ -13,6 +13,9 @@ Every function follows a passage of the paper:
   gradients  -- pool gradients (Eq. 5) as 2 Re <H psi|A_j psi>
   select     -- argmax |g_j| with a stated tie rule (Sec. III-D)
   adapt_run  -- the adaptive loop of Sec. III-D with fixed step count
+  step_energy, line_search -- the energy of the updated state as a function
+                of the angle, and its minimiser (parameter optimisation, which
+                Sec. III-D leaves implicit; see the readings)
 """
 from __future__ import annotations
 
@@ -200,6 +203,29 @@ def select(g, rel_tie: float = REL_TIE) -> tuple[int, float]:
     return int(k), float(gm.value)
 
 
+def step_energy(h: CSR, a: CSR, psi, theta: float) -> float:
+    """Energy (Eq. 1) of the state the update of Eq. 6-8 makes from psi with
+    generator a and angle theta, after renormalisation."""
+    phi, _ = normalize(taylor5(a, float(theta), psi))
+    return energy(h, phi)[0]
+
+
+def line_search(h: CSR, a: CSR, psi, theta_max: float = 1.0, n_grid: int = 201):
+    """The angle in [-theta_max, theta_max] that minimises step_energy: the
+    best point of a uniform grid, refined by a bounded scalar minimisation
+    (Brent's method, scipy) on the bracket around it.  Returns (theta, E)."""
+    from scipy.optimize import minimize_scalar
+    grid = np.linspace(-theta_max, theta_max, n_grid)
+    vals = np.array([step_energy(h, a, psi, t) for t in grid])
+    i = int(np.argmin(vals))
+    lo, hi = grid[max(i - 1, 0)], grid[min(i + 1, n_grid - 1)]
+    res = minimize_scalar(lambda t: step_energy(h, a, psi, t), bounds=(lo, hi),
+                          method="bounded", options={"xatol": 1e-13})
+    if res.fun <= vals[i]:
+        return float(res.x), float(res.fun)
+    return float(grid[i]), float(vals[i])
+
+
 @dataclass
 class AdaptTrace:
     energies: list        # energy at psi_t before each update, then the final one
@@ -210,11 +236,14 @@ class AdaptTrace:
 
 
 def adapt_run(h: CSR, pool: list, psi0, thetas, steps: int, renormalize: bool = True,
-              forced=None, eps: float = 0.0) -> AdaptTrace:
+              forced=None, eps: float = 0.0, line_search_max: float | None = None) -> AdaptTrace:
     """Adaptive loop (Sec. III-D): screen, select, check convergence, update.
 
     ``forced`` (optional sequence of indices) replaces the selection, so that
-    another implementation can be compared along the same trajectory.
+    another implementation can be compared along the same trajectory.  With
+    ``line_search_max`` the angle of each update is line_search's minimiser
+    over [-line_search_max, line_search_max] instead of thetas[t] (thetas may
+    then be None).
     """
     psi = _c128(psi0).copy()
     tr = AdaptTrace([], [], [], [], psi)
@@ -229,8 +258,12 @@ def adapt_run(h: CSR, pool: list, psi0, thetas, steps: int, renormalize: bool = 
         if forced is not None:
             k = int(forced[t])
         tr.selected.append(k)
-        tr.thetas.append(float(thetas[t]))
-        psi = taylor5(pool[k], float(thetas[t]), psi)
+        if line_search_max is not None:
+            theta = line_search(h, pool[k], psi, line_search_max)[0]
+        else:
+            theta = float(thetas[t])
+        tr.thetas.append(theta)
+        psi = taylor5(pool[k], theta, psi)
         if renormalize:
             psi, _ = normalize(psi)
     tr.energies.append(energy(h, psi)[0])
