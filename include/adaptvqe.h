@@ -307,6 +307,9 @@ typedef struct vqe_batch_io {
 #define VQE_STEP_GRAPH 8u       /* launch through captured HIP graphs: one for the
                                    H products, one per flag set for the rest
                                    (captured on first use, then replayed) */
+#define VQE_STEP_LINESEARCH 16u /* choose each state's angle by line search before
+                                   the update (see vqe_batch_set_line_search); the
+                                   chosen angle is written to theta */
 
 typedef struct vqe_batch vqe_batch;
 
@@ -333,6 +336,23 @@ VQE_API int vqe_batch_rebind(vqe_batch *plan, int32_t slot, const vqe_batch_item
  * skipped phases record their events back to back.
  */
 VQE_API int vqe_batch_step_timed(vqe_batch *plan, uint32_t flags, void **events, int32_t n_events);
+/*
+ * Parameter optimisation (the adaptive loop of Sec. III-D leaves the choice of
+ * the angle open).  Enables steps with VQE_STEP_LINESEARCH: after the
+ * selection, each state's angle is the theta in [-theta_max, theta_max] that
+ * minimises the energy (Eq. 1) of the renormalised fifth-order update
+ * (Eq. 6-8).  For generators with A^3 = -A (every fermionic single or double
+ * excitation) the update is psi + s(theta) A psi + c(theta) A^2 psi with
+ * s = theta - theta^3/6 + theta^5/120 and c = theta^2/2 - theta^4/24, so the
+ * energy is a ratio of quadratic forms in (1, s, c) built from psi, A psi,
+ * A^2 psi and two more H products per state; it is minimised in FP64 over a
+ * 256-point grid and refined by golden-section search.  The chosen angle is
+ * written to the plan's theta before the update.  Allocates the plan's
+ * line-search workspace (4 vectors per state) on first use; theta_max = 0
+ * disables.  Errors: VQE_EINVAL (bad theta_max), VQE_ENOTSUP (a generator of
+ * a pool does not satisfy A[r,c] A[c,r] = -1 on every pair), VQE_ENOMEM.
+ */
+VQE_API int vqe_batch_set_line_search(vqe_batch *plan, double theta_max);
 VQE_API int vqe_batch_destroy(vqe_batch *plan);
 /* Bytes of device workspace the plan owns (for footprint accounting). */
 VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);

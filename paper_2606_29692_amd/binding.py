@@ -20,6 +20,7 @@ VQE_OK, VQE_EINVAL, VQE_ESIZE, VQE_ENOMEM, VQE_EHIP, VQE_ENOTSUP = 0, -1, -2, -3
 VQE_C128, VQE_C64 = 0, 1
 VQE_PAIRING = 1
 VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_NO_UPDATE, VQE_STEP_GRAPH = 1, 2, 4, 8
+VQE_STEP_LINESEARCH = 16
 VQE_SPMV_VEC4 = 0x100
 VQE_SPMV_LDS = 0x200
 VQE_SPMV_DEEP = 0x400
@@ -93,6 +94,7 @@ SIGNATURES = {
     "vqe_batch_rebind": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_batch_item)]),
     "vqe_batch_step_timed": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p), C.c_int32]),
     "vqe_batch_destroy": (C.c_int, [C.c_void_p]),
+    "vqe_batch_set_line_search": (C.c_int, [C.c_void_p, C.c_double]),
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
@@ -507,18 +509,28 @@ class BatchPlan:
                                          C.byref(h)), "vqe_batch_create")
         self.handle = h
 
+    @staticmethod
+    def _flags(renorm, forced, update, graph, line_search):
+        return ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
+                | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0)
+                | (VQE_STEP_LINESEARCH if line_search else 0))
+
+    def set_line_search(self, theta_max: float):
+        """Enable (theta_max > 0) or disable steps whose angle is chosen by line
+        search (see vqe_batch_set_line_search); the chosen angles land in theta."""
+        self.ctx.check(lib().vqe_batch_set_line_search(self.handle, float(theta_max)),
+                       "vqe_batch_set_line_search")
+
     def step(self, renorm: bool = True, forced: bool = False, update: bool = True,
-             graph: bool = False):
-        flags = ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
-                 | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0))
+             graph: bool = False, line_search: bool = False):
+        flags = self._flags(renorm, forced, update, graph, line_search)
         self.ctx.check(lib().vqe_batch_step(self.handle, flags), "vqe_batch_step")
 
     def step_timed(self, events, renorm: bool = True, forced: bool = False, update: bool = True,
-                   graph: bool = False):
+                   graph: bool = False, line_search: bool = False):
         """Step recording 3 or 7 torch.cuda.Event objects on the context stream
         (see vqe_batch_step_timed)."""
-        flags = ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
-                 | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0))
+        flags = self._flags(renorm, forced, update, graph, line_search)
         for e in events:
             if not e.cuda_event:          # torch creates the HIP event on first record
                 e.record(self.ctx.stream)

@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <numeric>
 #include <vector>
@@ -149,7 +150,7 @@ struct vqe_batch {
     unsigned n_tay_tasks = 0;
     int2 *d_norm_tasks = nullptr;
     unsigned n_norm_tasks = 0;
-    hipGraphExec_t exec[16] = {};
+    hipGraphExec_t exec[16] = {};  // rest-of-step graphs by flag set (step_key)
     hipGraph_t graph[16] = {};
     bool compact_taylor = false;   // every pool has a compact pair table
     bool mf = false;               // every pool is matrix-free: screen and update from records
@@ -161,6 +162,22 @@ struct vqe_batch {
     std::vector<int64_t> dims;
     hipGraphExec_t exec_spmv = nullptr;
     hipGraph_t graph_spmv = nullptr;
+    // line search (vqe_batch_set_line_search)
+    std::vector<PairTable> tables_host;            // CSR mode: pair tables (host copy)
+    std::vector<const vqe_mf_pool *> mf_host;      // mf mode: pool of each table
+    std::vector<const vqe_mf_desc *> mf_desc_dev;  // mf mode: device descriptors of each table
+    std::vector<int> table_idx;                    // table of each slot
+    std::vector<int> xcd;                          // XCD of each slot
+    int ls_checked = 0;                            // 0 unknown, 1 every generator has A^3 = -A, -1 not
+    bool ls_ready = false;
+    char *ls_mem = nullptr;
+    size_t ls_bytes = 0;
+    std::vector<char> ls_image;
+    size_t o_ls = 0, o_ls1 = 0, o_ls2 = 0;
+    LsState *d_ls = nullptr;
+    SpmvState *d_ls1 = nullptr, *d_ls2 = nullptr;
+    int2 *d_ls_tasks = nullptr;
+    unsigned n_ls_tasks = 0;
 };
 
 namespace {
@@ -227,6 +244,17 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
     if (!(flags & VQE_STEP_FORCED))
         launch_select(p->d_sel, (unsigned)p->B, p->rel_tie, s);
     rc = rc ? rc : mark(4);
+    if ((flags & VQE_STEP_LINESEARCH) && !(flags & VQE_STEP_NO_UPDATE)) {
+        // v1 = A psi, v2 = A^2 psi; S v1 and S v2 with the plan's schedules;
+        // Re<v1|S v2>; then the angle
+        launch_ls_vectors(p->dtype, p->d_ls, p->d_ls_tasks, p->n_ls_tasks, s);
+        for (auto &l : p->spmv) {
+            launch_spmv(p->dtype, l.lanes, dummy, p->d_ls1, l.tasks, l.grid, s, l.max_dim);
+            launch_spmv(p->dtype, l.lanes, dummy, p->d_ls2, l.tasks, l.grid, s, l.max_dim);
+        }
+        launch_ls_dot(p->dtype, p->d_ls, p->d_ls_tasks, p->n_ls_tasks, s);
+        launch_ls_solve(p->d_ls, (unsigned)p->B, s);
+    }
     if (!(flags & VQE_STEP_NO_UPDATE)) {
         if (p->mf)
             launch_taylor_mf(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
@@ -289,7 +317,7 @@ template <class F> int capture(vqe_ctx *ctx, F fn, hipGraph_t *g_out, hipGraphEx
 int graph_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
 {
     vqe_ctx *ctx = p->ctx;
-    const unsigned key = flags & 7u;
+    const unsigned key = (flags & 7u) | ((flags & VQE_STEP_LINESEARCH) ? 8u : 0u);
     int rc;
     if (!p->exec_spmv && (rc = capture(ctx, [&] { return enqueue_spmv(p); }, &p->graph_spmv,
                                        &p->exec_spmv)))
@@ -448,6 +476,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     std::map<const void *, int> table_of;
     std::vector<PairTable> tables;
     std::vector<const MfTable *> mf_dev;        // device header per table (mf mode)
+    std::vector<const vqe_mf_desc *> mf_desc_ptrs;  // device descriptors per table (mf mode)
     std::vector<MfHostPlan> mf_plans;
     for (int s = 0; s < B; s++) {
         const void *key = pool_key(items[s].pool);
@@ -465,7 +494,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             const size_t o_h = 0, o_t = vqe_align(sizeof(MfTable));
             const size_t o_f = o_t + vqe_align(hp.tile_recs.size() * sizeof(MfRec));
             const size_t o_l = o_f + vqe_align(hp.full_recs.size() * sizeof(MfRec));
-            const size_t bytes = o_l + vqe_align(hp.lists.size() * sizeof(int32_t) + 4);
+            const size_t o_d = o_l + vqe_align(hp.lists.size() * sizeof(int32_t) + 4);
+            const size_t bytes = o_d + vqe_align((size_t)hp.M * sizeof(vqe_mf_desc));
             char *mem = nullptr;
             if (hipMalloc((void **)&mem, bytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -477,6 +507,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             h.tile_recs = (const MfRec *)(mem + o_t);
             h.full_recs = (const MfRec *)(mem + o_f);
             h.lists = (const int32_t *)(mem + o_l);
+            h.desc = (const vqe_mf_desc *)(mem + o_d);
             h.M = hp.M;
             h.ntile = hp.ntile;
             h.tile_rows = hp.tile_rows;
@@ -490,6 +521,13 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             if (e == hipSuccess && !hp.lists.empty())
                 e = hipMemcpy(mem + o_l, hp.lists.data(), hp.lists.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice);
+            if (e == hipSuccess) {
+                std::vector<vqe_mf_desc> dd(hp.M);
+                for (int j = 0; j < hp.M; j++)
+                    (void)vqe_mf_pool_get(items[s].pool->mf, j, &dd[j]);
+                e = hipMemcpy(mem + o_d, dd.data(), dd.size() * sizeof(vqe_mf_desc),
+                              hipMemcpyHostToDevice);
+            }
             if (e != hipSuccess)
                 return fail_free(vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: record upload: %s",
                                           hipGetErrorString(e)));
@@ -497,6 +535,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             tb.nt = hp.ntile;
             tb.tile_rows = hp.tile_rows;
             mf_dev.push_back((const MfTable *)(mem + o_h));
+            mf_desc_ptrs.push_back((const vqe_mf_desc *)(mem + o_d));
             mf_plans.push_back(std::move(hp));
         } else {
             void *mem[2] = {nullptr, nullptr};
@@ -670,6 +709,15 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     for (int s = 0; s < B; s++) {
         p->pool_ops.push_back(pool_key(items[s].pool));
         p->dims.push_back(items[s].H->dim);
+        p->table_idx.push_back(table_of[pool_key(items[s].pool)]);
+        p->xcd.push_back(xcd_of[s]);
+    }
+    p->tables_host = tables;
+    if (mf_mode) {
+        p->mf_host.assign(tables.size(), nullptr);
+        for (int s = 0; s < B; s++)
+            p->mf_host[table_of[pool_key(items[s].pool)]] = items[s].pool->mf;
+        p->mf_desc_dev = mf_desc_ptrs;
     }
     hipError_t e = hipMemcpyAsync(p->dmem, A.host.data(), p->dmem_bytes, hipMemcpyHostToDevice,
                                   ctx->stream);
@@ -685,6 +733,10 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     p->image = std::move(A.host);
     *out = p;
     return VQE_OK;
+}
+
+namespace {
+void ls_fill_slot(vqe_batch *p, int s, double theta_max, char *D);
 }
 
 extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item *it)
@@ -726,6 +778,16 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
                                 hipMemcpyHostToDevice, s));
     VQE_HIP(ctx, hipMemcpyAsync(p->dmem + ((char *)ts - p->image.data()), ts, sizeof(*ts),
                                 hipMemcpyHostToDevice, s));
+    if (p->ls_mem) {
+        const double tm = reinterpret_cast<LsState *>(p->ls_image.data() + p->o_ls)[slot].theta_max;
+        ls_fill_slot(p, slot, tm, p->ls_mem);
+        const size_t offs[3] = {p->o_ls + slot * sizeof(LsState), p->o_ls1 + slot * sizeof(SpmvState),
+                                p->o_ls2 + slot * sizeof(SpmvState)};
+        const size_t sizes[3] = {sizeof(LsState), sizeof(SpmvState), sizeof(SpmvState)};
+        for (int i = 0; i < 3; i++)
+            VQE_HIP(ctx, hipMemcpyAsync(p->ls_mem + offs[i], p->ls_image.data() + offs[i], sizes[i],
+                                        hipMemcpyHostToDevice, s));
+    }
     return VQE_OK;
 }
 
@@ -733,8 +795,12 @@ extern "C" int vqe_batch_step(vqe_batch *p, uint32_t flags)
 {
     if (!p)
         return VQE_EINVAL;
-    if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH))
+    if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH |
+                            VQE_STEP_LINESEARCH))
         return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step: unknown flags");
+    if ((flags & VQE_STEP_LINESEARCH) && !p->ls_ready)
+        return vqe_fail(p->ctx, VQE_EINVAL,
+                        "vqe_batch_step: line search not enabled (vqe_batch_set_line_search)");
     if (flags & VQE_STEP_GRAPH)
         return graph_step(p, flags, nullptr);
     return enqueue_step(p, flags);
@@ -747,7 +813,9 @@ extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
         return VQE_EINVAL;
     if (!events || (n_events != 3 && n_events != 7) ||
         (n_events == 7 && (flags & VQE_STEP_GRAPH)) ||
-        (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH)))
+        (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH |
+                             VQE_STEP_LINESEARCH)) ||
+        ((flags & VQE_STEP_LINESEARCH) && !p->ls_ready))
         return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step_timed: bad flags or events");
     for (int i = 0; i < n_events; i++)
         if (!events[i])
@@ -777,6 +845,8 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
         (void)hipGraphDestroy(p->graph_spmv);
     if (p->dmem)
         (void)hipFree(p->dmem);
+    if (p->ls_mem)
+        (void)hipFree(p->ls_mem);
     for (void *m : p->table_mem)
         (void)hipFree(m);
     delete p;
@@ -785,5 +855,187 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
 
 extern "C" int64_t vqe_batch_workspace_bytes(const vqe_batch *p)
 {
-    return p ? (int64_t)(p->dmem_bytes + p->table_bytes) : -1;
+    return p ? (int64_t)(p->dmem_bytes + p->table_bytes + p->ls_bytes) : -1;
+}
+
+namespace {
+
+// Every generator of every pool of the plan satisfies A^2 = -(projector on
+// its support), i.e. A[r, c] A[c, r] = -1 on every pair.
+int ls_check(vqe_batch *p)
+{
+    if (p->ls_checked)
+        return p->ls_checked > 0 ? VQE_OK : VQE_ENOTSUP;
+    bool ok = true;
+    if (p->mf) {
+        for (const vqe_mf_pool *mp : p->mf_host) {
+            for (int j = 0; mp && j < vqe_mf_pool_size(mp) && ok; j++) {
+                vqe_mf_desc d;
+                (void)vqe_mf_pool_get(mp, j, &d);
+                // A[r,c] A[c,r] = v^2 (-1)^{|zsign & x|}
+                const double sg = (__builtin_popcountll(d.zsign & d.x) & 1) ? -1.0 : 1.0;
+                ok = sg * (d.v_re * d.v_re - d.v_im * d.v_im) == -1.0 && d.v_re * d.v_im == 0.0;
+            }
+        }
+    } else {
+        for (const PairTable &tb : p->tables_host) {
+            const int64_t n = [&] {
+                int32_t last = 0;
+                (void)hipMemcpy(&last, tb.pts + (size_t)tb.M * tb.nt, 4, hipMemcpyDeviceToHost);
+                return (int64_t)last;
+            }();
+            const size_t eb = vqe_elem_bytes(p->dtype);
+            std::vector<char> a(n * eb), b(n * eb);
+            if (n > 0 && (hipMemcpy(a.data(), tb.pa, n * eb, hipMemcpyDeviceToHost) != hipSuccess ||
+                          hipMemcpy(b.data(), tb.pb, n * eb, hipMemcpyDeviceToHost) != hipSuccess))
+                return vqe_fail(p->ctx, VQE_EHIP, "vqe_batch_set_line_search: reading the pair table");
+            for (int64_t i = 0; i < n && ok; i++) {
+                double ar, ai, br, bi;
+                if (p->dtype == VQE_C128) {
+                    ar = ((const double *)a.data())[2 * i];
+                    ai = ((const double *)a.data())[2 * i + 1];
+                    br = ((const double *)b.data())[2 * i];
+                    bi = ((const double *)b.data())[2 * i + 1];
+                } else {
+                    ar = ((const float *)a.data())[2 * i];
+                    ai = ((const float *)a.data())[2 * i + 1];
+                    br = ((const float *)b.data())[2 * i];
+                    bi = ((const float *)b.data())[2 * i + 1];
+                }
+                ok = ar * br - ai * bi == -1.0 && ar * bi + ai * br == 0.0;
+            }
+        }
+    }
+    p->ls_checked = ok ? 1 : -1;
+    return ok ? VQE_OK : VQE_ENOTSUP;
+}
+
+// Line-search descriptors of slot s from the plan's descriptors.
+void ls_fill_slot(vqe_batch *p, int s, double theta_max, char *D)
+{
+    const SpmvState &hs = reinterpret_cast<const SpmvState *>(p->image.data() + p->o_spmv)[s];
+    const TaylorState &ts = reinterpret_cast<const TaylorState *>(p->image.data() + p->o_tay)[s];
+    LsState &ls = reinterpret_cast<LsState *>(p->ls_image.data() + p->o_ls)[s];
+    SpmvState &s1 = reinterpret_cast<SpmvState *>(p->ls_image.data() + p->o_ls1)[s];
+    SpmvState &s2 = reinterpret_cast<SpmvState *>(p->ls_image.data() + p->o_ls2)[s];
+    // vectors and partials keep the addresses assigned at allocation
+    void *v1 = ls.v1, *v2 = ls.v2, *w2 = ls.w2;
+    void *w1 = s1.sigma;
+    double *pv = ls.part_vec, *pd = ls.part_dot;
+    double *h1 = const_cast<double *>(ls.part_h1), *h2 = const_cast<double *>(ls.part_h2);
+    ls.psi = hs.psi;
+    ls.sigma = hs.sigma;
+    ls.v1 = v1;
+    ls.v2 = v2;
+    ls.w2 = w2;
+    ls.k = ts.k;
+    ls.theta = const_cast<double *>(ts.theta);
+    ls.energy = hs.energy_out;
+    ls.shift = hs.shift;
+    ls.dim = hs.dim;
+    ls.ops = ts.ops;
+    ls.mf = p->mf ? p->mf_desc_dev[p->table_idx[s]] : nullptr;
+    ls.M = ts.M;
+    ls.nb_rows = (int32_t)((hs.dim + LS_ROWS_PER_BLOCK - 1) / LS_ROWS_PER_BLOCK);
+    ls.part_vec = pv;
+    ls.part_dot = pd;
+    ls.part_h1 = h1;
+    ls.part_h2 = h2;
+    ls.nb_spmv = hs.nblocks;
+    ls.theta_max = theta_max;
+    ls.active = hs.active;
+    s1 = hs;
+    s1.psi = v1;
+    s1.sigma = w1;
+    s1.partials = h1;
+    s1.energy_out = nullptr;
+    s2 = hs;
+    s2.psi = v2;
+    s2.sigma = w2;
+    s2.partials = h2;
+    s2.energy_out = nullptr;
+    (void)D;
+}
+
+}  // namespace
+
+extern "C" int vqe_batch_set_line_search(vqe_batch *p, double theta_max)
+{
+    if (!p)
+        return VQE_EINVAL;
+    vqe_ctx *ctx = p->ctx;
+    if (!(theta_max >= 0.0) || !std::isfinite(theta_max))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_set_line_search: bad theta_max");
+    if (theta_max == 0.0) {
+        p->ls_ready = false;
+        return VQE_OK;
+    }
+    int rc = ls_check(p);
+    if (rc)
+        return rc == VQE_ENOTSUP
+                   ? vqe_fail(ctx, VQE_ENOTSUP,
+                              "vqe_batch_set_line_search: a generator does not satisfy A^3 = -A")
+                   : rc;
+    const int B = p->B;
+    if (!p->ls_mem) {
+        // layout: descriptors, tasks, then per slot v1, v2, w1, w2 and partials
+        Arena A;
+        p->o_ls = A.take(sizeof(LsState) * B);
+        p->o_ls1 = A.take(sizeof(SpmvState) * B);
+        p->o_ls2 = A.take(sizeof(SpmvState) * B);
+        std::vector<std::vector<int2>> per(kXcd);
+        for (int s = 0; s < B; s++) {
+            const int nb = (int)((p->dims[s] + LS_ROWS_PER_BLOCK - 1) / LS_ROWS_PER_BLOCK);
+            for (int b = 0; b < nb; b++)
+                per[p->xcd[s]].push_back(make_int2(s, b));
+        }
+        auto flat = interleave(per, make_int2(-1, 0));
+        const size_t o_tasks = A.take(flat.size() * sizeof(int2));
+        const size_t eb = vqe_elem_bytes(p->dtype);
+        std::vector<size_t> o_vec(B), o_part(B);
+        for (int s = 0; s < B; s++) {
+            const SpmvState &hs = reinterpret_cast<const SpmvState *>(p->image.data() + p->o_spmv)[s];
+            const int64_t nb = (p->dims[s] + LS_ROWS_PER_BLOCK - 1) / LS_ROWS_PER_BLOCK;
+            o_vec[s] = A.take(4 * vqe_align(p->dims[s] * eb));
+            o_part[s] = A.take(((size_t)nb * (LS_NVEC + 1) + 2 * (size_t)hs.nblocks * 3) * sizeof(double));
+        }
+        p->ls_bytes = A.host.size();
+        if (hipMalloc((void **)&p->ls_mem, p->ls_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p->ls_mem = nullptr;
+            p->ls_bytes = 0;
+            return vqe_fail(ctx, VQE_ENOMEM, "vqe_batch_set_line_search: allocation failed");
+        }
+        char *D = p->ls_mem;
+        std::copy(flat.begin(), flat.end(), A.at<int2>(o_tasks));
+        for (int s = 0; s < B; s++) {
+            const SpmvState &hs = reinterpret_cast<const SpmvState *>(p->image.data() + p->o_spmv)[s];
+            const int64_t nb = (p->dims[s] + LS_ROWS_PER_BLOCK - 1) / LS_ROWS_PER_BLOCK;
+            const size_t vb = vqe_align(p->dims[s] * eb);
+            LsState &ls = A.at<LsState>(p->o_ls)[s];
+            SpmvState &s1 = A.at<SpmvState>(p->o_ls1)[s];
+            ls.v1 = D + o_vec[s];
+            ls.v2 = D + o_vec[s] + vb;
+            s1.sigma = D + o_vec[s] + 2 * vb;   // w1
+            ls.w2 = D + o_vec[s] + 3 * vb;
+            double *pp = (double *)(D + o_part[s]);
+            ls.part_vec = pp;
+            ls.part_dot = pp + nb * LS_NVEC;
+            ls.part_h1 = pp + nb * (LS_NVEC + 1);
+            ls.part_h2 = pp + nb * (LS_NVEC + 1) + (size_t)hs.nblocks * 3;
+        }
+        p->ls_image = std::move(A.host);
+        p->d_ls = (LsState *)(D + p->o_ls);
+        p->d_ls1 = (SpmvState *)(D + p->o_ls1);
+        p->d_ls2 = (SpmvState *)(D + p->o_ls2);
+        p->d_ls_tasks = (int2 *)(D + o_tasks);
+        p->n_ls_tasks = (unsigned)flat.size();
+    }
+    for (int s = 0; s < B; s++)
+        ls_fill_slot(p, s, theta_max, p->ls_mem);
+    VQE_HIP(ctx, hipMemcpyAsync(p->ls_mem, p->ls_image.data(), p->ls_image.size(),
+                                hipMemcpyHostToDevice, ctx->stream));
+    VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    p->ls_ready = true;
+    return VQE_OK;
 }

@@ -156,8 +156,42 @@ struct MfTable {
     const MfRec *tile_recs;   // [M * ntile]: generator j on tile v at j * ntile + v
     const MfRec *full_recs;   // [M]: generator j on the whole state
     const int32_t *lists;     // generator indices per (tile-bit group, tile), by descending cost
+    const vqe_mf_desc *desc;  // [M]: the descriptors (support tests)
     int32_t M, ntile, tile_rows, pad;
 };
+
+// One state of the line search over the selected generator's angle.
+#define LS_ROWS_PER_BLOCK 2048
+#define LS_NVEC 7             // partial sums of the vector kernel
+#define LS_GRID 256           // angles of the coarse search
+struct LsState {
+    const void *psi;
+    const void *sigma;        // stored S psi
+    void *v1, *v2;            // A psi, A^2 psi
+    void *w2;                 // S v2
+    const int32_t *k;         // selected generator
+    double *theta;            // out: the chosen angle
+    const double *energy;     // this step's (E, <psi|psi>, Im)
+    double shift;
+    int64_t dim;
+    const vqe_csr *ops;       // CSR pool (device descriptors), or
+    const vqe_mf_desc *mf;    // matrix-free descriptors
+    int32_t M;
+    int32_t nb_rows;          // blocks of the vector and dot kernels
+    double *part_vec;         // [nb_rows * LS_NVEC]
+    double *part_dot;         // [nb_rows]
+    const double *part_h1;    // partial triples of S v1 [nb_spmv * 3]
+    const double *part_h2;    // partial triples of S v2
+    int32_t nb_spmv;
+    int32_t pad;
+    double theta_max;
+    const int32_t *active;
+};
+void launch_ls_vectors(int dtype, const LsState *states, const int2 *tasks, unsigned grid,
+                       hipStream_t s);
+void launch_ls_dot(int dtype, const LsState *states, const int2 *tasks, unsigned grid,
+                   hipStream_t s);
+void launch_ls_solve(const LsState *states, unsigned n_states, hipStream_t s);
 
 struct vqe_mf_pool;
 // Host: records of every generator of a pool for a state of 2^n rows whose
