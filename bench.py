@@ -194,9 +194,11 @@ def main():
     ap.add_argument("--schedule", type=int, default=0,
                     help="H product schedule (lanes per row, | 256 for wide loads; 0: tuned)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--matrix-free", action=argparse.BooleanOptionalAction, default=False,
+    ap.add_argument("--matrix-free", action=argparse.BooleanOptionalAction, default=True,
                     help="screen and update from the generators' matrix-free records "
                          "(no pool CSR) instead of the pool's pair tables")
+    ap.add_argument("--line-search-steps", type=int, default=20,
+                    help="also time this many steps with the angle chosen by line search (0: skip)")
     ap.add_argument("--retune", action="store_true",
                     help="time every H product schedule even when a tuned one is cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -264,6 +266,32 @@ def main():
     spmv_avg = float(np.mean(spmv_ms))
     updates_per_s = len(ds) * K / (total_ms / 1e3)
     achieved = nbytes["h_spmv"] / (spmv_avg / 1e3) / 1e9
+
+    # the same step with the angle chosen by line search (two more H products
+    # per state); a separate figure, not the headline value
+    line_search = None
+    if args.line_search_steps > 0:
+        plan.set_line_search(1.0)
+        for _ in range(2):
+            plan.step(renorm=True, graph=True, line_search=True)
+        torch.cuda.synchronize()
+        e_before = plan.energies.view(-1, 3)[:, 0].clone()
+        l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        l0.record(stream)
+        for _ in range(args.line_search_steps):
+            plan.step(renorm=True, graph=True, line_search=True)
+        l1.record(stream)
+        torch.cuda.synchronize()
+        ls_ms = l0.elapsed_time(l1) / args.line_search_steps
+        plan.step(update=False)
+        torch.cuda.synchronize()
+        drop = float((e_before - plan.energies.view(-1, 3)[:, 0]).mean())
+        plan.set_line_search(0.0)
+        line_search = {"ms_per_step": ls_ms, "updates_per_s": len(ds) / (ls_ms / 1e3),
+                       "steps": args.line_search_steps, "theta_max": 1.0,
+                       "mean_energy_drop_Ha": drop}
+        log(f"line search: {ls_ms:.3f} ms/step ({len(ds) / (ls_ms / 1e3):.0f} updates/s), "
+            f"mean energy drop over {args.line_search_steps} steps {drop:.4f} Ha")
 
     # phase breakdown of the same step launched eagerly (context figures)
     ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(10)]
@@ -361,6 +389,7 @@ def main():
                                "k_spmv_energy, per the schedule)",
                      "bytes_per_launch": nbytes["h_spmv"]},
         "plain_fp64_single_request": plain,
+        "line_search": line_search,
         "serving": serving,
         "p99_latency_ms": (serving["x0.8"]["continuous_batching"]["p99_ms"] if serving
                            else None),
