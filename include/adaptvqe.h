@@ -154,6 +154,23 @@ VQE_API int vqe_mf_owner_rows(const vqe_mf_pool *pool, int32_t j, int64_t tile_r
                               int64_t *count, uint32_t *rows_out, uint32_t *lds_index_out);
 
 /*
+ * Commuting-family partition (Sec. III-F, Alg. 1).
+ * vqe_mf_noncommutation: the complementary graph of Alg. 1 for a matrix-free
+ * pool, adj[i*M + j] = 1 iff [A_i, A_j] != 0 as operators (full commutation),
+ * 0 otherwise and on the diagonal.  adj is a DEVICE uint8[M*M]; the call
+ * returns after the kernel has finished.  Exact integer work: A_i A_j and
+ * A_j A_i map column c to the same basis state, and the generators commute
+ * iff for every c both terms are absent or both present with equal sign.
+ * vqe_partition_greedy (host only): Alg. 1 on a HOST uint8[M*M] adjacency:
+ * vertices by descending degree (ties by index), each to the lowest-indexed
+ * family holding none of its neighbours, else a new family; family[v]
+ * (host int32[M]) and *n_families receive the result.
+ */
+VQE_API int vqe_mf_noncommutation(struct vqe_ctx *ctx, const vqe_mf_pool *pool, uint8_t *adj);
+VQE_API int vqe_partition_greedy(int32_t M, const uint8_t *adj, int32_t *family,
+                                 int32_t *n_families);
+
+/*
  * An operator pool (Sec. III-A): M generators of one dimension and dtype.
  * ops is a DEVICE array of M descriptors (each pointing to device CSR
  * arrays); ops_host is the same array in host memory (read for sizes and

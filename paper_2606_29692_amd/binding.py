@@ -107,6 +107,8 @@ SIGNATURES = {
     "vqe_mf_pool_get": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_mf_desc)]),
     "vqe_mf_owner_rows": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
                                     C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
+    "vqe_mf_noncommutation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vqe_partition_greedy": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
 }
 
 _lib = None
@@ -396,6 +398,27 @@ class MfPool:
             self.close()
         except Exception:
             pass
+
+
+def noncommutation_graph(ctx: "Context", pool: "MfPool"):
+    """Alg. 1's complementary graph on the device: bool M x M (host copy)."""
+    torch = _torch()
+    adj = torch.empty(pool.M * pool.M, dtype=torch.uint8, device=ctx.torch_device)
+    ctx.check(lib().vqe_mf_noncommutation(ctx.handle, pool.handle, adj.data_ptr()),
+              "vqe_mf_noncommutation")
+    return adj.cpu().numpy().reshape(pool.M, pool.M).astype(bool)
+
+
+def partition_greedy(adj) -> np.ndarray:
+    """Alg. 1 (host): family index of every vertex of a boolean adjacency matrix."""
+    a = np.ascontiguousarray(np.asarray(adj, dtype=np.uint8))
+    M = a.shape[0]
+    fam = np.zeros(M, dtype=np.int32)
+    nf = C.c_int32()
+    rc = lib().vqe_partition_greedy(M, a.ctypes.data, fam.ctypes.data, C.byref(nf))
+    if rc != 0:
+        raise VqeError(rc, "vqe_partition_greedy")
+    return fam
 
 
 class MatrixFreePool:

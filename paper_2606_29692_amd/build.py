@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libadaptvqe.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["capi.hip", "csr_build.hip", "spmv.hip", "grad.hip", "screen.hip", "taylor.hip",
-           "mfree.hip", "linesearch.hip"]
+           "mfree.hip", "linesearch.hip", "partition.hip"]
 NO_CONTRACT = {"csr_build.hip"}
 
 BASE_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
