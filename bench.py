@@ -199,6 +199,8 @@ def main():
                          "(no pool CSR) instead of the pool's pair tables")
     ap.add_argument("--line-search-steps", type=int, default=20,
                     help="also time this many steps with the angle chosen by line search (0: skip)")
+    ap.add_argument("--pool-order", choices=["canonical", "family"], default="canonical",
+                    help="pool order: canonical, or grouped by commuting family (Alg. 1)")
     ap.add_argument("--retune", action="store_true",
                     help="time every H product schedule even when a tuned one is cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -227,6 +229,25 @@ def main():
     specs, _ = vs.config_c4(n_states=args.states, mixed=False)
     t0 = time.perf_counter()
     systems = [vs.make_system(s) for s in specs]
+    # commuting-family partition of the pool (Alg. 1): graph on the device,
+    # greedy colouring on the host; optionally reorder the pool so that
+    # families are contiguous
+    mfp = B.MfPool(systems[0].pool)
+    g0 = time.perf_counter()
+    adj = B.noncommutation_graph(ctx, mfp)
+    fam = B.partition_greedy(adj)
+    partition = {"generators": int(mfp.M), "noncommuting_pairs": int(adj.sum()) // 2,
+                 "families": int(fam.max()) + 1,
+                 "graph_and_colouring_ms": (time.perf_counter() - g0) * 1e3,
+                 "pool_order": args.pool_order}
+    mfp.close()
+    log(f"partition: {partition['families']} commuting families of {partition['generators']} "
+        f"generators ({partition['noncommuting_pairs']} non-commuting pairs), "
+        f"{partition['graph_and_colouring_ms']:.1f} ms")
+    if args.pool_order == "family":
+        perm = np.argsort(fam, kind="stable")
+        for s in systems:
+            s.pool = [s.pool[j] for j in perm]
     pools = PB.PoolCache(ctx, matrix_free=args.matrix_free)
     ds = [PB.device_system(ctx, s, args.dtype, pools) for s in systems]
     torch.cuda.synchronize()
@@ -390,6 +411,7 @@ def main():
                      "bytes_per_launch": nbytes["h_spmv"]},
         "plain_fp64_single_request": plain,
         "line_search": line_search,
+        "partition": partition,
         "serving": serving,
         "p99_latency_ms": (serving["x0.8"]["continuous_batching"]["p99_ms"] if serving
                            else None),
