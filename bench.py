@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 PMC_PROFILE = os.path.join(ROOT, "profiles", "h_product_14q_64states_pmc.md")
 
 
-def measured_traffic(schedule: int):
+def measured_traffic(schedule: int, workload: str):
     """HBM bytes per H-product launch from the committed FETCH_SIZE/WRITE_SIZE
     profile (calibrated against a copy kernel of known size), or None when the
     profile is absent, was taken with another schedule, or the kernel sources
@@ -51,7 +51,7 @@ def measured_traffic(schedule: int):
                 k, v = line.rstrip("\n").split(": ", 1)
                 rec[k] = v
     try:
-        if int(rec["schedule"]) != int(schedule):
+        if int(rec["schedule"]) != int(schedule) or rec.get("workload_key") != workload:
             return None
         h = hashlib.sha256()
         for src in rec["kernel_sources"].split():
@@ -62,6 +62,11 @@ def measured_traffic(schedule: int):
         return int(rec["traffic_bytes_per_launch"])
     except (KeyError, ValueError, OSError):
         return None
+
+
+def vs_electrons() -> dict:
+    import vqe_system as vs
+    return vs.ELECTRONS
 
 
 def log(msg: str):
@@ -199,6 +204,9 @@ def main():
                          "(no pool CSR) instead of the pool's pair tables")
     ap.add_argument("--line-search-steps", type=int, default=20,
                     help="also time this many steps with the angle chosen by line search (0: skip)")
+    ap.add_argument("--qubits", type=int, default=14, choices=sorted(vs_electrons()),
+                    help="register size of every state (the headline workload is 14)")
+    ap.add_argument("--mapping", choices=["jw", "bk"], default="jw")
     ap.add_argument("--pool-order", choices=["canonical", "family"], default="canonical",
                     help="pool order: canonical, or grouped by commuting family (Alg. 1)")
     ap.add_argument("--retune", action="store_true",
@@ -226,7 +234,12 @@ def main():
     n_cu, devname = ctx.info()
     log(f"device {devname}, {n_cu} CUs")
 
-    specs, _ = vs.config_c4(n_states=args.states, mixed=False)
+    if args.qubits == 14 and args.mapping == "jw":
+        specs, _ = vs.config_c4(n_states=args.states, mixed=False)
+    else:
+        # the same seeds as the 14-qubit workload, at another size or mapping
+        specs = [vs.SystemSpec(args.qubits, vs.ELECTRONS[args.qubits], args.mapping, False,
+                               vs.system_seed(44, i)) for i in range(args.states)]
     t0 = time.perf_counter()
     systems = [vs.make_system(s) for s in specs]
     # commuting-family partition of the pool (Alg. 1): graph on the device,
@@ -371,7 +384,8 @@ def main():
 
     hnnz = ds[0].H.nnz
     out = {
-        "metric": "Taylor-O(5) updates/s + pool-gradient SpMV HBM GB/s at 14 qubits; p99 latency",
+        "metric": f"Taylor-O(5) updates/s + pool-gradient SpMV HBM GB/s at {args.qubits} qubits; "
+                  f"p99 latency",
         "value": updates_per_s,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -385,12 +399,14 @@ def main():
         "accumulate": "f64",
         "data": "synthetic (seeded molecule-shaped random integrals; no molecular data)",
         "config": {
-            "workload": f"{len(ds)} independent states x 14 qubits (7 orbitals, 6 electrons, JW), "
-                        f"H nnz {hnnz} each, pool 204 shared; one adaptive step per state per "
+            "workload": f"{len(ds)} independent states x {args.qubits} qubits ({args.qubits // 2} "
+                        f"orbitals, {vs.ELECTRONS[args.qubits]} electrons, {args.mapping.upper()}), "
+                        f"H nnz {hnnz} each, pool {ds[0].pool.M} shared; one adaptive step per state per "
                         f"launch sequence (H SpMV + FP64 energy, 204-generator gradient screen, "
                         f"argmax, fused Taylor-O(5), FP64 renorm)",
-            "states": len(ds), "n_qubits": 14, "n_electrons": 6, "mapping": "jw",
-            "pool": 204, "storage": args.dtype, "spmv_schedule": sched,
+            "states": len(ds), "n_qubits": args.qubits, "n_electrons": vs.ELECTRONS[args.qubits],
+            "mapping": args.mapping, "pool": ds[0].pool.M, "storage": args.dtype,
+            "spmv_schedule": sched,
             "pool_form": "matrix-free records" if args.matrix_free else "pair tables from the pool CSR",
         },
         "pool_gradient_spmv_GBps": screen_gbs,
@@ -404,10 +420,11 @@ def main():
                      "renorm_eager": norm_avg},
         "algorithmic_bytes_per_step": nbytes,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(sched),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(sched, f"{len(ds)}x{args.qubits}q-{args.mapping}-{args.dtype}"),
                      "traffic_unit": "bytes per launch (HBM read + write, PMC-calibrated)",
-                     "kernel": "H product of all 64 states (one launch of k_spmv_lds or "
-                               "k_spmv_energy, per the schedule)",
+                     "kernel": f"H product of all {len(ds)} states (one launch of the schedule's "
+                               f"kernel: k_spmv_lds_pf, k_spmv_lds or k_spmv_energy)",
                      "bytes_per_launch": nbytes["h_spmv"]},
         "plain_fp64_single_request": plain,
         "line_search": line_search,
