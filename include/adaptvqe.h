@@ -389,10 +389,17 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * schedule with the same lanes (16 for 8) is used. */
 #define VQE_SPMV_LDS 0x200
 #define VQE_SPMV_DEEP 0x400
-/* VQE_SPMV_PREFETCH (with VQE_SPMV_LDS; 32 or 64 lanes): each sub-group keeps
- * the loads of its next rows in flight while it multiplies the current one
- * (two rows, or three with VQE_SPMV_DEEP); needs nnz * element size below
- * 2^31 bytes (raw buffer offsets), else the LDS schedule is used. */
+/* VQE_SPMV_PREFETCH (with VQE_SPMV_LDS): each sub-group keeps the loads of its
+ * next rows in flight while it multiplies the current one (two rows, or three
+ * with VQE_SPMV_DEEP); needs nnz * element size below 2^31 bytes (raw buffer
+ * offsets), else the LDS schedule is used.  32 or 64 lanes when the state fits
+ * LDS (8 or 16 lanes then run the plain LDS schedule).
+ * In a batch plan, a state larger than the LDS limit runs such a schedule
+ * column-tiled: per 128 KiB tile of the state, every row's entries in that
+ * tile (a contiguous sub-range of the row) against the tile staged in LDS,
+ * with FP64 per-tile row sums added in ascending tile order (8, 16, 32 or 64
+ * lanes).  The plan keeps per-tile row bounds ((tiles + 1) * dim int32) and
+ * the per-tile sums (tiles * dim complex FP64) for such states. */
 #define VQE_SPMV_PREFETCH 0x800
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given

@@ -135,7 +135,11 @@ struct vqe_batch {
         int2 *tasks;
         unsigned grid;
         int64_t max_dim;
+        int2 *sum_tasks;    // column-tiled schedules: the tile-sum tasks
+        unsigned sum_grid;
     };
+    int2 *d_bounds_tasks = nullptr;       // per-tile row bounds (tiled states)
+    std::vector<std::pair<unsigned, unsigned>> bounds_range;   // per slot: first task, count
     std::vector<SpmvLaunch> spmv;
     ScreenState *d_screen = nullptr;
     PairTable *d_tables = nullptr;
@@ -211,11 +215,21 @@ std::vector<T> interleave(const std::vector<std::vector<T>> &per, const T &pad)
 // The step is two launch sequences: the H products (sequence A) and the rest
 // (sequence B: energy finalisation, screen, selection, Taylor update,
 // renormalisation).  `ev` (nullable) receives the phase events.
-int enqueue_spmv(vqe_batch *p)
+void launch_products(vqe_batch *p, const SpmvState *states)
 {
     SpmvState dummy{};
-    for (auto &l : p->spmv)
-        launch_spmv(p->dtype, l.lanes, dummy, p->d_spmv, l.tasks, l.grid, p->ctx->stream, l.max_dim);
+    for (auto &l : p->spmv) {
+        if (l.lanes & VQE_SPMV_TILED)
+            launch_spmv_tiled(p->dtype, l.lanes, states, l.tasks, l.grid, l.sum_tasks, l.sum_grid,
+                              p->ctx->stream);
+        else
+            launch_spmv(p->dtype, l.lanes, dummy, states, l.tasks, l.grid, p->ctx->stream, l.max_dim);
+    }
+}
+
+int enqueue_spmv(vqe_batch *p)
+{
+    launch_products(p, p->d_spmv);
     VQE_LAUNCH_CHECK(p->ctx);
     return VQE_OK;
 }
@@ -248,10 +262,8 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
         // v1 = A psi, v2 = A^2 psi; S v1 and S v2 with the plan's schedules;
         // Re<v1|S v2>; then the angle
         launch_ls_vectors(p->dtype, p->d_ls, p->d_ls_tasks, p->n_ls_tasks, s);
-        for (auto &l : p->spmv) {
-            launch_spmv(p->dtype, l.lanes, dummy, p->d_ls1, l.tasks, l.grid, s, l.max_dim);
-            launch_spmv(p->dtype, l.lanes, dummy, p->d_ls2, l.tasks, l.grid, s, l.max_dim);
-        }
+        launch_products(p, p->d_ls1);
+        launch_products(p, p->d_ls2);
         launch_ls_dot(p->dtype, p->d_ls, p->d_ls_tasks, p->n_ls_tasks, s);
         launch_ls_solve(p->d_ls, (unsigned)p->B, s);
     }
@@ -424,38 +436,74 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     const size_t o_tay = A.take(sizeof(TaylorState) * B);
     std::vector<int> lanes(B);
     std::vector<size_t> o_epart(B), o_npart(B), o_gpart(B);
+    std::vector<size_t> o_tptr(B, 0), o_tpart(B, 0);
+    std::vector<int> ntiles(B, 0);
+    const int tile_cols = spmv_tile_cols(dtype);
     for (int s = 0; s < B; s++) {
         const vqe_csr *H = items[s].H;
-        lanes[s] = vqe_effective_schedule(
-            H, items[s].spmv_schedule ? items[s].spmv_schedule : vqe_default_schedule(H));
-        o_epart[s] = A.take(vqe_spmv_partials_bytes(H->dim, lanes[s]));
+        const int req = items[s].spmv_schedule ? items[s].spmv_schedule : vqe_default_schedule(H);
+        lanes[s] = vqe_batch_schedule(H, req);
+        int64_t nblk = spmv_blocks(H->dim, lanes[s]);
+        if (lanes[s] & VQE_SPMV_TILED) {
+            ntiles[s] = (int)((H->dim + tile_cols - 1) / tile_cols);
+            o_tptr[s] = A.take((size_t)(ntiles[s] + 1) * H->dim * sizeof(int32_t));
+            o_tpart[s] = A.take((size_t)ntiles[s] * H->dim * 2 * sizeof(double));
+            nblk = (H->dim + SPMV_SUM_ROWS - 1) / SPMV_SUM_ROWS;
+        }
+        o_epart[s] = A.take(std::max(vqe_spmv_partials_bytes(H->dim, lanes[s] & ~VQE_SPMV_TILED),
+                                     (size_t)nblk * 3 * sizeof(double)));
         const int64_t nn = (H->dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK;
         o_npart[s] = A.take(nn * sizeof(double));
     }
 
     // --- H product tasks, one table per lanes value
-    std::map<int, std::vector<std::vector<int2>>> per_lanes;
+    std::map<int, std::vector<std::vector<int2>>> per_lanes, per_sum;
+    std::vector<int2> bounds_list;
+    std::vector<std::pair<unsigned, unsigned>> bounds_range(B, {0u, 0u});
     for (int s = 0; s < B; s++) {
         auto &per = per_lanes[lanes[s]];
         if (per.empty())
             per.resize(kXcd);
-        const int nb = (int)spmv_blocks(items[s].H->dim, lanes[s]);
+        const int64_t dim = items[s].H->dim;
+        if (lanes[s] & VQE_SPMV_TILED) {
+            const int nb = (int)((dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS);
+            for (int b = 0; b < nb; b++)
+                for (int t = 0; t < ntiles[s]; t++)
+                    per[xcd_of[s]].push_back(make_int2(s, (b << 8) | t));
+            auto &ps = per_sum[lanes[s]];
+            if (ps.empty())
+                ps.resize(kXcd);
+            for (int b = 0; b < (int)((dim + SPMV_SUM_ROWS - 1) / SPMV_SUM_ROWS); b++)
+                ps[xcd_of[s]].push_back(make_int2(s, b));
+            bounds_range[s] = {(unsigned)bounds_list.size(), (unsigned)((dim + 255) / 256)};
+            for (int b = 0; b < (int)((dim + 255) / 256); b++)
+                bounds_list.push_back(make_int2(s, b));
+            continue;
+        }
+        const int nb = (int)spmv_blocks(dim, lanes[s]);
         for (int b = 0; b < nb; b++)
             per[xcd_of[s]].push_back(make_int2(s, b));
     }
     std::vector<std::pair<int, size_t>> spmv_tab;
-    std::vector<std::vector<int2>> spmv_lists;
+    std::vector<std::vector<int2>> spmv_lists, sum_lists;
+    std::vector<size_t> sum_tab;
     std::vector<int64_t> spmv_maxdim;
     for (auto &kv : per_lanes) {
         auto flat = interleave(kv.second, make_int2(-1, 0));
         spmv_tab.push_back({kv.first, A.take(flat.size() * sizeof(int2))});
         spmv_lists.push_back(std::move(flat));
+        std::vector<int2> sflat;
+        if (kv.first & VQE_SPMV_TILED)
+            sflat = interleave(per_sum[kv.first], make_int2(-1, 0));
+        sum_tab.push_back(A.take(sflat.size() * sizeof(int2) + 8));
+        sum_lists.push_back(std::move(sflat));
         int64_t md = 0;
         for (int s = 0; s < B; s++)
             if (lanes[s] == kv.first)
                 md = std::max<int64_t>(md, items[s].H->dim);
         spmv_maxdim.push_back(md);
     }
+    const size_t o_btasks = A.take(bounds_list.size() * sizeof(int2) + 8);
 
     const bool mf_mode = items[0].pool->mf != nullptr;
     p->mf = mf_mode;
@@ -645,6 +693,13 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         st.shift = it.H->diag_shift;
         st.nblocks = (int32_t)spmv_blocks(it.H->dim, lanes[s]);
         st.lanes = lanes[s];
+        if (lanes[s] & VQE_SPMV_TILED) {
+            st.tptr = (const int32_t *)(D + o_tptr[s]);
+            st.tile_part = (double *)(D + o_tpart[s]);
+            st.ntiles = ntiles[s];
+            st.tile_cols = tile_cols;
+            st.nblocks = (int32_t)((it.H->dim + SPMV_SUM_ROWS - 1) / SPMV_SUM_ROWS);
+        }
         st.nnz = it.H->nnz;
         st.active = io->active ? io->active + s : nullptr;
 
@@ -685,9 +740,12 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     }
     for (size_t i = 0; i < spmv_tab.size(); i++) {
         std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));
+        std::copy(sum_lists[i].begin(), sum_lists[i].end(), A.at<int2>(sum_tab[i]));
         p->spmv.push_back({spmv_tab[i].first, (int2 *)(D + spmv_tab[i].second),
-                           (unsigned)spmv_lists[i].size(), spmv_maxdim[i]});
+                           (unsigned)spmv_lists[i].size(), spmv_maxdim[i],
+                           (int2 *)(D + sum_tab[i]), (unsigned)sum_lists[i].size()});
     }
+    std::copy(bounds_list.begin(), bounds_list.end(), A.at<int2>(o_btasks));
     std::copy(screen_flat.begin(), screen_flat.end(), A.at<int4>(o_stasks));
     std::copy(tay_flat.begin(), tay_flat.end(), A.at<int2>(o_ttasks));
     std::copy(norm_flat.begin(), norm_flat.end(), A.at<int2>(o_ntasks));
@@ -731,6 +789,20 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: %s", hipGetErrorString(e));
     }
     p->image = std::move(A.host);
+    if (!bounds_list.empty()) {
+        p->d_bounds_tasks = (int2 *)(D + o_btasks);
+        p->bounds_range = bounds_range;
+        launch_tile_bounds(p->d_spmv, p->d_bounds_tasks, (unsigned)bounds_list.size(), ctx->stream);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            const int rc = vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: tile bounds: %s",
+                                    hipGetErrorString(e));
+            vqe_batch_destroy(p);
+            return rc;
+        }
+    }
     *out = p;
     return VQE_OK;
 }
@@ -753,7 +825,7 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
         it->H->dim != p->dims[slot] ||
         (p->mf ? (const void *)it->pool->mf : (const void *)it->pool->ops) != p->pool_ops[slot])
         return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: item does not match slot %d", slot);
-    const int sched = vqe_effective_schedule(
+    const int sched = vqe_batch_schedule(
         it->H, it->spmv_schedule ? it->spmv_schedule : vqe_default_schedule(it->H));
     if (sched != p->sched[slot])
         return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: schedule differs from slot %d", slot);
@@ -778,6 +850,12 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
                                 hipMemcpyHostToDevice, s));
     VQE_HIP(ctx, hipMemcpyAsync(p->dmem + ((char *)ts - p->image.data()), ts, sizeof(*ts),
                                 hipMemcpyHostToDevice, s));
+    if (p->bounds_range.size() > (size_t)slot && p->bounds_range[slot].second > 0) {
+        // the new H's per-tile row bounds
+        launch_tile_bounds(p->d_spmv, p->d_bounds_tasks + p->bounds_range[slot].first,
+                           p->bounds_range[slot].second, s);
+        VQE_LAUNCH_CHECK(ctx);
+    }
     if (p->ls_mem) {
         const double tm = reinterpret_cast<LsState *>(p->ls_image.data() + p->o_ls)[slot].theta_max;
         ls_fill_slot(p, slot, tm, p->ls_mem);

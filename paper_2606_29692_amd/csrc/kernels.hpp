@@ -39,7 +39,19 @@ struct SpmvState {
     const int32_t *active;     // batch slot flag (nullable): 0 = skip this state
     int32_t nblocks;
     int32_t lanes;
+    // column-tiled schedule (states larger than LDS): per tile t the entries of
+    // row r with columns in tile t are [tptr[t*dim + r], tptr[(t+1)*dim + r])
+    const int32_t *tptr;       // [(ntiles + 1) * dim]
+    double *tile_part;         // [ntiles * dim] FP64 complex partial rows
+    int32_t ntiles;            // 0: not tiled
+    int32_t tile_cols;
 };
+
+// Column-tiled H product: tile width (state elements staged in LDS per pass)
+// and rows per workgroup of the tile-sum kernel.
+#define VQE_SPMV_TILED 0x1000
+#define SPMV_TILE_BYTES (128 * 1024)
+#define SPMV_SUM_ROWS 1024
 
 // Rows of a pool operator handled by one workgroup of the gradient kernel.
 #define GRAD_CHUNK_ROWS 1024
@@ -228,9 +240,16 @@ int vqe_spmv_energy_core(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *
 size_t vqe_spmv_partials_bytes(int64_t dim, int lanes);
 bool vqe_valid_schedule(int sched);
 int vqe_effective_schedule(const vqe_csr *H, int sched);
+int vqe_batch_schedule(const vqe_csr *H, int sched);
 
 void launch_spmv(int dtype, int lanes, const SpmvState &single, const SpmvState *states,
                  const int2 *tasks, unsigned grid, hipStream_t s, int64_t max_dim);
+// column-tiled schedule: the tile passes (tasks {state, block << 8 | tile}),
+// then the fixed-order tile sum with the energy epilogue (tasks {state, block})
+void launch_spmv_tiled(int dtype, int sched, const SpmvState *states, const int2 *tasks,
+                       unsigned grid, const int2 *sum_tasks, unsigned sum_grid, hipStream_t s);
+void launch_tile_bounds(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s);
+int32_t spmv_tile_cols(int dtype);
 int64_t spmv_blocks(int64_t dim, int sched);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 

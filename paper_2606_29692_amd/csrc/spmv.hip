@@ -543,6 +543,224 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     }
 }
 
+// Column-tiled variant of the pipelined LDS schedule, for states larger than
+// LDS.  A workgroup takes one block of rows and one column tile: it stages
+// that tile of the state (SPMV_TILE_BYTES) and, per row, streams only the
+// row's entries in the tile -- a contiguous sub-range, since columns are
+// sorted within a row, bounded by the per-tile row pointers.  The row sums of
+// a tile go to an FP64 partial array; the tile-sum kernel adds the tiles in
+// ascending order and applies the energy epilogue.
+template <int DT, int L, int D, int U>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
+k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const SpmvState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    const int blk = task.y >> 8, t = task.y & 0xff;
+    using T = typename Elem<DT>::T;
+    constexpr int W = U * 4;
+    constexpr int PASS = W * L;
+    constexpr unsigned EB = sizeof(T);
+    extern __shared__ unsigned char smem[];
+    T *s_x = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x;
+    const int64_t dim = st.dim;
+    const int tc = st.tile_cols;
+    const int c_lo = t * tc;
+    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
+    // the tile, one zero element (index tc), then the block's tile bounds
+    int32_t *s_k0 = reinterpret_cast<int32_t *>(smem + (size_t)(tc + 1) * sizeof(T));
+    int32_t *s_k1 = s_k0 + SPMV_LDS_ROWS;
+    for (int i = tid; i < tc; i += 1024)
+        s_x[i] = ldg(psi, (int64_t)c_lo + i);
+    if (tid == 0)
+        s_x[tc] = T{};
+    for (int64_t i = tid; i < r1 - r0; i += 1024) {
+        s_k0[i] = gmem(st.tptr)[(int64_t)t * dim + r0 + i];
+        s_k1[i] = gmem(st.tptr)[(int64_t)(t + 1) * dim + r0 + i];
+    }
+    __syncthreads();
+
+    constexpr int G = VQE_WAVE / L;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int sub = lane / L, sl = lane % L;
+    const int nnz = (int)st.nnz, zc = tc;
+    const int whole = nnz & ~3;
+    const __amdgpu_buffer_rsrc_t rc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
+    const __amdgpu_buffer_rsrc_t rv =
+        __builtin_amdgcn_make_buffer_rsrc((void *)st.val, (short)0, (int)(nnz * EB), VQE_BUF_WORD3);
+    double *__restrict__ part = st.tile_part + (int64_t)t * dim * 2;
+
+    auto issue = [&](int kb, int k1, int c[W], T v[W]) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int k = kb + u * 4 * L;
+            const bool ok = k < k1 && k < whole;
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const v4i c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 4u : VQE_BUF_OOB, 0, 0);
+            c[4 * u + 0] = c4.x;
+            c[4 * u + 1] = c4.y;
+            c[4 * u + 2] = c4.z;
+            c[4 * u + 3] = c4.w;
+            BufVal<DT>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
+        }
+    };
+    // entries outside [k0, k1) (or not loaded) read the zero element; the
+    // column test keeps every LDS index inside the tile
+    auto consume = [&](int kb, int k0, int k1, const int c[W], const T v[W], double &are,
+                       double &aim) {
+        int cm[W];
+        const unsigned len = (unsigned)(k1 - k0);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int k = kb + u * 4 * L + q;
+                const int cl = c[4 * u + q] - c_lo;
+                cm[4 * u + q] = ((unsigned)(k - k0) < len && (unsigned)cl < (unsigned)tc) ? cl : zc;
+            }
+        lds_gather_fma<T, W>(s_x, cm, v, are, aim);
+    };
+    auto row_bounds = [&](int64_t r, int &k0, int &k1) {
+        if (r < r1) {
+            k0 = s_k0[r - r0];
+            k1 = s_k1[r - r0];
+        } else {
+            k0 = k1 = 0;
+        }
+    };
+    auto finish = [&](int64_t r, int k0, int k1, double are, double aim) {
+        for (int kb = (k0 & ~3) + 4 * sl + PASS; kb - 4 * sl < k1; kb += PASS) {
+            int c[W];
+            T v[W];
+            issue(kb, k1, c, v);
+            consume(kb, k0, k1, c, v, are, aim);
+        }
+        if (k1 > whole) {
+            const int k = (k0 > whole ? k0 : whole) + sl;
+            if (k < k1) {
+                const T a = ldg(reinterpret_cast<const T *>(st.val), k);
+                const T x = s_x[gmem(st.col)[k] - c_lo];
+                are += (double)a.x * (double)x.x - (double)a.y * (double)x.y;
+                aim += (double)a.x * (double)x.y + (double)a.y * (double)x.x;
+            }
+        }
+        are = group_sum<L>(are);
+        aim = group_sum<L>(aim);
+        if (sl == 0 && r < r1) {
+            gmem(part)[2 * r] = are;
+            gmem(part)[2 * r + 1] = aim;
+        }
+    };
+
+    int cb[D][W];
+    T vb[D][W];
+    int kb0[D], kb1[D];
+    int64_t rr[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        rr[d] = r0 + (wid + 16 * d) * G + sub;
+        row_bounds(rr[d], kb0[d], kb1[d]);
+        issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    for (int64_t base = r0 + wid * G; base < r1; base += 16 * D * G) {
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            {
+                double are = 0.0, aim = 0.0;
+                consume((kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
+                finish(rr[d], kb0[d], kb1[d], are, aim);
+            }
+            rr[d] += 16 * D * G;
+            row_bounds(rr[d], kb0[d], kb1[d]);
+            issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// sigma_r = sum over tiles (ascending) of the tile partials; the energy sums.
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_spmv_tile_sum(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const SpmvState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    const int64_t dim = st.dim;
+    const int64_t r0 = (int64_t)task.y * SPMV_SUM_ROWS;
+    const int64_t r1 = r0 + SPMV_SUM_ROWS < dim ? r0 + SPMV_SUM_ROWS : dim;
+    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+        double sr = 0.0, si = 0.0;
+        for (int t = 0; t < st.ntiles; t++) {
+            sr += gmem(st.tile_part)[((int64_t)t * dim + r) * 2];
+            si += gmem(st.tile_part)[((int64_t)t * dim + r) * 2 + 1];
+        }
+        Elem<DT>::st(st.sigma, r, make_double2(sr, si));
+        const double2 p = Elem<DT>::ld(st.psi, r);
+        e_re += p.x * sr + p.y * si;
+        e_im += p.x * si - p.y * sr;
+        e_n2 += p.x * p.x + p.y * p.y;
+    }
+    __shared__ double s_part[4][3];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    e_re = wave_sum(e_re);
+    e_im = wave_sum(e_im);
+    e_n2 = wave_sum(e_n2);
+    if (lane == 0) {
+        s_part[wid][0] = e_re;
+        s_part[wid][1] = e_im;
+        s_part[wid][2] = e_n2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int q = threadIdx.x;
+        gmem(st.partials)[(int64_t)task.y * 3 + q] =
+            ((s_part[0][q] + s_part[1][q]) + s_part[2][q]) + s_part[3][q];
+    }
+}
+
+// Per-tile row bounds: the first entry of row r with column >= t * tile_cols.
+__global__ void __launch_bounds__(256)
+k_tile_bounds(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const SpmvState st = states[task.x];
+    const int64_t r = (int64_t)task.y * 256 + threadIdx.x;
+    if (r >= st.dim)
+        return;
+    const int k0 = st.rowptr[r], k1 = st.rowptr[r + 1];
+    int32_t *tp = const_cast<int32_t *>(st.tptr);
+    tp[r] = k0;
+    for (int t = 1; t < st.ntiles; t++) {
+        const int lim = t * st.tile_cols;
+        int lo = k0, hi = k1;   // first k in [k0, k1) with col[k] >= lim
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (st.col[mid] < lim)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        tp[(int64_t)t * st.dim + r] = lo;
+    }
+    tp[(int64_t)st.ntiles * st.dim + r] = k1;
+}
+
 }  // namespace
 
 // One wave per state: fixed-order sum of the block partials, then
@@ -662,6 +880,52 @@ void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState 
         launch_spmv_dt<VQE_C64>(sched, single, states, tasks, grid, s, lds);
 }
 
+int32_t spmv_tile_cols(int dtype) { return (int32_t)(SPMV_TILE_BYTES / vqe_elem_bytes(dtype)); }
+
+// Tile passes see short row segments, so narrow sub-groups keep two groups of
+// four entries per lane (U = 2) instead of covering 256 entries per pass.
+template <int DT, int L, int D>
+static void launch_tiled_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s)
+{
+    const size_t lds = (size_t)(spmv_tile_cols(DT) + 1) * vqe_elem_bytes(DT) +
+                       2 * SPMV_LDS_ROWS * sizeof(int32_t);
+    auto k = k_spmv_tiled<DT, L, D, (L >= 32 ? 64 / L : 2)>;
+    (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k<<<grid, 1024, lds, s>>>(states, tasks);
+}
+
+template <int DT>
+static void launch_tiled_dt(int sched, const SpmvState *states, const int2 *tasks, unsigned grid,
+                            const int2 *sum_tasks, unsigned sum_grid, hipStream_t s)
+{
+    const bool deep = (sched & VQE_SPMV_DEEP) != 0;
+    switch (sched & 0xff) {
+    case 8: deep ? launch_tiled_t<DT, 8, 3>(states, tasks, grid, s)
+                 : launch_tiled_t<DT, 8, 2>(states, tasks, grid, s); break;
+    case 16: deep ? launch_tiled_t<DT, 16, 3>(states, tasks, grid, s)
+                  : launch_tiled_t<DT, 16, 2>(states, tasks, grid, s); break;
+    case 64: deep ? launch_tiled_t<DT, 64, 3>(states, tasks, grid, s)
+                  : launch_tiled_t<DT, 64, 2>(states, tasks, grid, s); break;
+    default: deep ? launch_tiled_t<DT, 32, 3>(states, tasks, grid, s)
+                  : launch_tiled_t<DT, 32, 2>(states, tasks, grid, s); break;
+    }
+    k_spmv_tile_sum<DT><<<sum_grid, 256, 0, s>>>(states, sum_tasks);
+}
+
+void launch_spmv_tiled(int dtype, int sched, const SpmvState *states, const int2 *tasks,
+                       unsigned grid, const int2 *sum_tasks, unsigned sum_grid, hipStream_t s)
+{
+    if (dtype == VQE_C128)
+        launch_tiled_dt<VQE_C128>(sched, states, tasks, grid, sum_tasks, sum_grid, s);
+    else
+        launch_tiled_dt<VQE_C64>(sched, states, tasks, grid, sum_tasks, sum_grid, s);
+}
+
+void launch_tile_bounds(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s)
+{
+    k_tile_bounds<<<grid, 256, 0, s>>>(states, tasks);
+}
+
 bool vqe_valid_schedule(int sched)
 {
     switch (sched) {
@@ -673,6 +937,9 @@ bool vqe_valid_schedule(int sched)
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH: case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
+    // 8 and 16 lanes: pipelined only in the column-tiled form (else plain LDS)
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH: case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH:
+    case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
         return true;
     default:
         return false;
@@ -689,11 +956,25 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
         return sched & 0xff;
     if ((sched & VQE_SPMV_LDS) && H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES)
         return (sched & 0xff) == 8 ? 16 | VQE_SPMV_VEC4 : (sched & 0xff) | VQE_SPMV_VEC4;
-    // the pipelined schedule addresses the arrays with 31-bit buffer offsets
+    // the pipelined schedule addresses the arrays with 31-bit buffer offsets,
+    // and runs with 32 or 64 lanes when the state fits LDS
     if ((sched & VQE_SPMV_PREFETCH) &&
-        (!(sched & VQE_SPMV_LDS) || H->nnz * (int64_t)vqe_elem_bytes(H->dtype) > 0x7fffff00LL))
-        return sched & ~VQE_SPMV_PREFETCH;
+        (!(sched & VQE_SPMV_LDS) || H->nnz * (int64_t)vqe_elem_bytes(H->dtype) > 0x7fffff00LL ||
+         (sched & 0xff) < 32))
+        return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP);
     return sched;
+}
+
+// In a batch plan, a pipelined LDS schedule on a state too large for LDS
+// becomes the column-tiled schedule with the same lanes and depth.
+int vqe_batch_schedule(const vqe_csr *H, int sched)
+{
+    const bool big = H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES;
+    const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
+    if (big && aligned && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) &&
+        H->nnz * (int64_t)vqe_elem_bytes(H->dtype) <= 0x7fffff00LL && H->dim <= ((int64_t)1 << 30))
+        return sched | VQE_SPMV_TILED;
+    return vqe_effective_schedule(H, sched);
 }
 
 int64_t spmv_blocks(int64_t dim, int sched)
