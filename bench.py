@@ -402,7 +402,7 @@ def main():
             "workload": f"{len(ds)} independent states x {args.qubits} qubits ({args.qubits // 2} "
                         f"orbitals, {vs.ELECTRONS[args.qubits]} electrons, {args.mapping.upper()}), "
                         f"H nnz {hnnz} each, pool {ds[0].pool.M} shared; one adaptive step per state per "
-                        f"launch sequence (H SpMV + FP64 energy, 204-generator gradient screen, "
+                        f"launch sequence (H SpMV + FP64 energy, {ds[0].pool.M}-generator gradient screen, "
                         f"argmax, fused Taylor-O(5), FP64 renorm)",
             "states": len(ds), "n_qubits": args.qubits, "n_electrons": vs.ELECTRONS[args.qubits],
             "mapping": args.mapping, "pool": ds[0].pool.M, "storage": args.dtype,

@@ -243,20 +243,19 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
             VQE_HIP(ctx, hipEventRecord(ev[i], s));
         return VQE_OK;
     };
-    SpmvState dummy{};
-    k_energy_finalize<<<(unsigned)p->B, 64, 0, s>>>(dummy, p->d_spmv, p->B);
+    // the screen, then one per-state kernel for the energy, the gradient sums
+    // and the selection (the energy phase event coincides with the start)
     int rc = mark(2);
-    if (p->mf) {
+    const bool grad = p->mf || p->n_screen_tasks;
+    if (p->mf)
         launch_screen_mf(p->dtype, p->d_screen, p->d_screen_tasks, p->n_screen_tasks,
                          p->screen_lds, s);
-        launch_screen_fin(p->d_screen, p->d_tables, (unsigned)p->B, s);
-    } else if (p->n_screen_tasks) {
+    else if (p->n_screen_tasks)
         launch_screen(p->dtype, p->d_screen, p->d_tables, p->d_screen_tasks, p->n_screen_tasks,
                       (unsigned)p->B, p->screen_lds, s);
-    }
+    launch_step_fin(p->d_spmv, p->d_screen, p->d_tables, p->d_sel, (unsigned)p->B, grad,
+                    !(flags & VQE_STEP_FORCED), p->rel_tie, s);
     rc = rc ? rc : mark(3);
-    if (!(flags & VQE_STEP_FORCED))
-        launch_select(p->d_sel, (unsigned)p->B, p->rel_tie, s);
     rc = rc ? rc : mark(4);
     if ((flags & VQE_STEP_LINESEARCH) && !(flags & VQE_STEP_NO_UPDATE)) {
         // v1 = A psi, v2 = A^2 psi; S v1 and S v2 with the plan's schedules;

@@ -185,12 +185,6 @@ void launch_grad_finalize(const GradGroup *groups, const int2 *items, unsigned n
     k_grad_fin<true><<<n_items, 256, 0, s>>>(dummy, groups, items);
 }
 
-void launch_select(const SelectState *states, unsigned n, double rel_tie, hipStream_t s)
-{
-    SelectState dummy{};
-    k_select_t<true><<<n, 64, 0, s>>>(dummy, states, rel_tie);
-}
-
 static int check_pool(vqe_ctx *ctx, const vqe_pool *pool, const vqe_csr *H)
 {
     if (!pool || pool->M < 0 || (pool->M > 0 && (!pool->ops || !pool->ops_host)))

@@ -226,8 +226,10 @@ int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable 
                      void **mem_out, size_t *bytes_out);
 void launch_screen(int dtype, const ScreenState *states, const PairTable *tables,
                    const int4 *tasks, unsigned grid, unsigned n_states, size_t lds, hipStream_t s);
-void launch_screen_fin(const ScreenState *states, const PairTable *tables, unsigned n_states,
-                       hipStream_t s);
+// Per-state energy finalisation, gradient sums (grad) and selection (select).
+void launch_step_fin(const SpmvState *spmv, const ScreenState *screen, const PairTable *tables,
+                     const SelectState *sel, unsigned n_states, bool grad, bool select,
+                     double rel_tie, hipStream_t s);
 int32_t vqe_mf_pool_size(const vqe_mf_pool *pool);
 int32_t vqe_mf_pool_qubits(const vqe_mf_pool *pool);
 
@@ -257,7 +259,6 @@ void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, uns
                       hipStream_t s);
 void launch_grad_finalize(const GradGroup *groups, const int2 *items, unsigned n_items,
                           hipStream_t s);
-void launch_select(const SelectState *states, unsigned n, double rel_tie, hipStream_t s);
 
 void launch_taylor_pair(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                         hipStream_t s);

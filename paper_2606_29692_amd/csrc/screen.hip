@@ -276,18 +276,70 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     }
 }
 
+// End of a batched step's screen, one workgroup per state: the energy from
+// the H product's block partials (Eq. 1), the gradients from the screen's
+// tile partials (Eq. 5), then the largest |g_j| with the lowest index among
+// the near-ties.  The energy is summed exactly as the single-call energy
+// finalisation sums it, and g_j adds its tile partials in tile order.
 __global__ void __launch_bounds__(256)
-k_screen_fin(const ScreenState *__restrict__ states, const PairTable *__restrict__ tables)
+k_step_fin(const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ screen,
+           const PairTable *__restrict__ tables, const SelectState *__restrict__ sel,
+           int do_grad, int do_select, double rel_tie)
 {
-    const ScreenState st = states[blockIdx.x];
-    if (VQE_SKIP(st))
+    const int s = blockIdx.x;
+    const SpmvState hs = spmv[s];
+    if (VQE_SKIP(hs))
         return;
-    const PairTable tb = tables[st.table];
-    for (int j = threadIdx.x; j < tb.M; j += 256) {
-        double s = 0.0;
-        for (int t = 0; t < tb.nt; t++)
-            s += st.partials[(int64_t)j * tb.nt + t];
-        st.g_out[j] = 2.0 * s;
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        double re = 0.0, im = 0.0, n2 = 0.0;
+        for (int b = tid; b < hs.nblocks; b += 64) {
+            re += hs.partials[(int64_t)b * 3 + 0];
+            im += hs.partials[(int64_t)b * 3 + 1];
+            n2 += hs.partials[(int64_t)b * 3 + 2];
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        n2 = wave_sum(n2);
+        if (tid == 0 && hs.energy_out) {
+            hs.energy_out[0] = hs.shift + re / n2;
+            hs.energy_out[1] = n2;
+            hs.energy_out[2] = im;
+        }
+    }
+    if (do_grad) {
+        const ScreenState st = screen[s];
+        const PairTable tb = tables[st.table];
+        for (int j = tid; j < tb.M; j += 256) {
+            double acc = 0.0;
+            for (int t = 0; t < tb.nt; t++)
+                acc += st.partials[(int64_t)j * tb.nt + t];
+            st.g_out[j] = 2.0 * acc;
+        }
+    }
+    if (!do_select)
+        return;
+    __syncthreads();      // the gradients written above are read below
+    if (tid >= 64)
+        return;
+    const SelectState ss = sel[s];
+    double gmax = 0.0;
+    for (int j = tid; j < ss.M; j += 64)
+        gmax = fmax(gmax, fabs(ss.g[j]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+    const double thr = gmax * (1.0 - rel_tie);
+    int best = 0x7fffffff;
+    for (int j = tid; j < ss.M; j += 64)
+        if (fabs(ss.g[j]) >= thr && j < best)
+            best = j;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        best = min(best, __shfl_xor(best, o, 64));
+    if (tid == 0) {
+        ss.k_out[0] = best == 0x7fffffff ? 0 : best;
+        ss.gmax_out[0] = gmax;
     }
 }
 
@@ -451,10 +503,12 @@ int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable 
     return VQE_OK;
 }
 
-void launch_screen_fin(const ScreenState *states, const PairTable *tables, unsigned n_states,
-                       hipStream_t s)
+void launch_step_fin(const SpmvState *spmv, const ScreenState *screen, const PairTable *tables,
+                     const SelectState *sel, unsigned n_states, bool grad, bool select,
+                     double rel_tie, hipStream_t s)
 {
-    k_screen_fin<<<n_states, 256, 0, s>>>(states, tables);
+    k_step_fin<<<n_states, 256, 0, s>>>(spmv, screen, tables, sel, grad ? 1 : 0, select ? 1 : 0,
+                                        rel_tie);
 }
 
 void launch_screen(int dtype, const ScreenState *states, const PairTable *tables,
@@ -469,5 +523,5 @@ void launch_screen(int dtype, const ScreenState *states, const PairTable *tables
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k_screen<VQE_C64><<<grid, 1024, lds, s>>>(states, tables, tasks);
     }
-    k_screen_fin<<<n_states, 256, 0, s>>>(states, tables);
+    (void)n_states;
 }
