@@ -16,6 +16,10 @@ Every function follows a passage of the paper:
   step_energy, line_search -- the energy of the updated state as a function
                 of the angle, and its minimiser (parameter optimisation, which
                 Sec. III-D leaves implicit; see the readings)
+  ansatz_state, ansatz_energy, reoptimize -- the state of the whole adaptive
+                ansatz (every selected generator's update applied in order to
+                the reference) and the cyclic coordinate minimisation of its
+                energy over all angles (re-optimisation of the parameters)
 """
 from __future__ import annotations
 
@@ -210,20 +214,67 @@ def step_energy(h: CSR, a: CSR, psi, theta: float) -> float:
     return energy(h, phi)[0]
 
 
-def line_search(h: CSR, a: CSR, psi, theta_max: float = 1.0, n_grid: int = 201):
-    """The angle in [-theta_max, theta_max] that minimises step_energy: the
-    best point of a uniform grid, refined by a bounded scalar minimisation
-    (Brent's method, scipy) on the bracket around it.  Returns (theta, E)."""
+def _minimise_1d(f, theta_max: float, n_grid: int):
+    """Minimiser of f over [-theta_max, theta_max]: the best point of a
+    uniform grid, refined by a bounded scalar minimisation (Brent's method,
+    scipy) on the bracket around it.  Returns (theta, f(theta))."""
     from scipy.optimize import minimize_scalar
     grid = np.linspace(-theta_max, theta_max, n_grid)
-    vals = np.array([step_energy(h, a, psi, t) for t in grid])
+    vals = np.array([f(t) for t in grid])
     i = int(np.argmin(vals))
     lo, hi = grid[max(i - 1, 0)], grid[min(i + 1, n_grid - 1)]
-    res = minimize_scalar(lambda t: step_energy(h, a, psi, t), bounds=(lo, hi),
-                          method="bounded", options={"xatol": 1e-13})
+    res = minimize_scalar(f, bounds=(lo, hi), method="bounded", options={"xatol": 1e-13})
     if res.fun <= vals[i]:
         return float(res.x), float(res.fun)
     return float(grid[i]), float(vals[i])
+
+
+def line_search(h: CSR, a: CSR, psi, theta_max: float = 1.0, n_grid: int = 201):
+    """The angle in [-theta_max, theta_max] that minimises step_energy (grid,
+    then Brent's method on the bracket around the best point).  Returns
+    (theta, E)."""
+    return _minimise_1d(lambda t: step_energy(h, a, psi, t), theta_max, n_grid)
+
+
+def ansatz_state(pool: list, ref, ks, thetas) -> np.ndarray:
+    """The adaptive ansatz: starting from the reference, the update of
+    Eq. 6-8 with generator pool[ks[m]] and angle thetas[m] for m = 0, 1, ...
+    in order, each followed by renormalisation."""
+    psi = _c128(ref).copy()
+    for k, t in zip(ks, thetas):
+        psi, _ = normalize(taylor5(pool[int(k)], float(t), psi))
+    return psi
+
+
+def ansatz_energy(h: CSR, pool: list, ref, ks, thetas) -> float:
+    """Energy (Eq. 1) of the ansatz state."""
+    return energy(h, ansatz_state(pool, ref, ks, thetas))[0]
+
+
+def reoptimize(h: CSR, pool: list, ref, ks, thetas, sweeps: int = 1, theta_max: float = 1.0,
+               n_grid: int = 201, trace: list | None = None) -> np.ndarray:
+    """Re-optimise every angle of the ansatz by cyclic coordinate descent:
+    each sweep visits m = 0, 1, ..., n-1 in order and replaces thetas[m] by
+    the minimiser over [-theta_max, theta_max] of ansatz_energy as a function
+    of that angle alone, the others held at their current values (the angles
+    before m already updated in this sweep).  With ``trace`` each visited
+    coordinate appends (m, the angles before the visit, the new angle, its
+    energy).  Returns the new angles."""
+    th = np.array(thetas, dtype=np.float64).copy()
+    for _ in range(sweeps):
+        for m in range(len(ks)):
+            before = th.copy()
+
+            def f(t, m=m):
+                trial = th.copy()
+                trial[m] = t
+                return ansatz_energy(h, pool, ref, ks, trial)
+
+            t_new, e_new = _minimise_1d(f, theta_max, n_grid)
+            th[m] = t_new
+            if trace is not None:
+                trace.append((m, before, t_new, e_new))
+    return th
 
 
 @dataclass
@@ -236,14 +287,17 @@ class AdaptTrace:
 
 
 def adapt_run(h: CSR, pool: list, psi0, thetas, steps: int, renormalize: bool = True,
-              forced=None, eps: float = 0.0, line_search_max: float | None = None) -> AdaptTrace:
+              forced=None, eps: float = 0.0, line_search_max: float | None = None,
+              reopt_sweeps: int = 0) -> AdaptTrace:
     """Adaptive loop (Sec. III-D): screen, select, check convergence, update.
 
     ``forced`` (optional sequence of indices) replaces the selection, so that
     another implementation can be compared along the same trajectory.  With
     ``line_search_max`` the angle of each update is line_search's minimiser
     over [-line_search_max, line_search_max] instead of thetas[t] (thetas may
-    then be None).
+    then be None).  With ``reopt_sweeps`` > 0, after each update every angle
+    chosen so far is re-optimised (reoptimize, over the same range) and the
+    state is rebuilt from psi0; tr.thetas then holds the final angles.
     """
     psi = _c128(psi0).copy()
     tr = AdaptTrace([], [], [], [], psi)
@@ -266,6 +320,10 @@ def adapt_run(h: CSR, pool: list, psi0, thetas, steps: int, renormalize: bool = 
         psi = taylor5(pool[k], theta, psi)
         if renormalize:
             psi, _ = normalize(psi)
+        if reopt_sweeps > 0:
+            tm = line_search_max if line_search_max is not None else 1.0
+            tr.thetas = list(reoptimize(h, pool, psi0, tr.selected, tr.thetas, reopt_sweeps, tm))
+            psi = ansatz_state(pool, psi0, tr.selected, tr.thetas)
     tr.energies.append(energy(h, psi)[0])
     tr.psi = psi
     return tr
