@@ -370,6 +370,40 @@ VQE_API int vqe_batch_step_timed(vqe_batch *plan, uint32_t flags, void **events,
  * a pool does not satisfy A[r,c] A[c,r] = -1 on every pair), VQE_ENOMEM.
  */
 VQE_API int vqe_batch_set_line_search(vqe_batch *plan, double theta_max);
+/*
+ * Re-optimisation of every angle of each slot's adaptive ansatz (the
+ * parameter optimisation of the adaptive loop, Sec. III-D, over the updates
+ * of Eq. 6-8).  The ansatz state of slot s is
+ *     psi = T5(t_{n-1} A_{k_{n-1}}) ... T5(t_0 A_{k_0}) ref_s   (renormalised),
+ * and each sweep visits m = 0, 1, ..., n-1 in order, replacing t_m by the
+ * angle in [-theta_max, theta_max] that minimises the energy (Eq. 1) with
+ * the other angles held (cyclic coordinate descent; the angles before m are
+ * already the sweep's new ones).  As in the line search, with L the state
+ * before update m and R the later updates, the ansatz is
+ * R L + s(t) R A L + c(t) R A^2 L, so each visit costs three H products and
+ * the later updates applied to three vectors; the energy ratio is minimised
+ * in FP64 (256-point grid, golden-section refinement; the current angle is
+ * kept unless something is lower).
+ *   ks      DEVICE int32 [B * ld]: row s holds slot s's generator indices
+ *           (indices outside [0, M) leave that update out)
+ *   thetas  DEVICE FP64 [B * ld]: the angles, updated in place
+ *   ld, n   row stride and number of updates per slot, 0 <= n <= ld
+ *   refs    HOST array of B DEVICE pointers: each slot's reference state
+ *           (dim elements of the plan's dtype; read only)
+ *   sweeps  number of sweeps (0: nothing is done)
+ *   energies_out  DEVICE FP64 [B] (nullable): the energy after the last visit
+ * On completion (stream order) each slot's psi holds the renormalised ansatz
+ * state at the new angles; sigma and the plan's energy buffers are left for
+ * the next step to recompute.  Slots switched off by the plan's active flags
+ * are left unchanged.  Every generator of every pool must satisfy
+ * A[r,c] A[c,r] = -1 on its pairs (VQE_ENOTSUP otherwise).  Allocates nine
+ * state vectors per slot on the first call (VQE_ENOMEM); synchronises the
+ * stream once to upload the call's descriptors, otherwise asynchronous.
+ * Errors: VQE_EINVAL (null plan arrays, n > ld, bad theta_max or sweeps).
+ */
+VQE_API int vqe_batch_reoptimize(vqe_batch *plan, const int32_t *ks, double *thetas, int32_t ld,
+                                 int32_t n, const void *const *refs, int32_t sweeps,
+                                 double theta_max, double *energies_out);
 VQE_API int vqe_batch_destroy(vqe_batch *plan);
 /* Bytes of device workspace the plan owns (for footprint accounting). */
 VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);

@@ -214,7 +214,7 @@ def step_energy(h: CSR, a: CSR, psi, theta: float) -> float:
     return energy(h, phi)[0]
 
 
-def _minimise_1d(f, theta_max: float, n_grid: int):
+def minimise_angle(f, theta_max: float, n_grid: int):
     """Minimiser of f over [-theta_max, theta_max]: the best point of a
     uniform grid, refined by a bounded scalar minimisation (Brent's method,
     scipy) on the bracket around it.  Returns (theta, f(theta))."""
@@ -233,7 +233,7 @@ def line_search(h: CSR, a: CSR, psi, theta_max: float = 1.0, n_grid: int = 201):
     """The angle in [-theta_max, theta_max] that minimises step_energy (grid,
     then Brent's method on the bracket around the best point).  Returns
     (theta, E)."""
-    return _minimise_1d(lambda t: step_energy(h, a, psi, t), theta_max, n_grid)
+    return minimise_angle(lambda t: step_energy(h, a, psi, t), theta_max, n_grid)
 
 
 def ansatz_state(pool: list, ref, ks, thetas) -> np.ndarray:
@@ -270,7 +270,7 @@ def reoptimize(h: CSR, pool: list, ref, ks, thetas, sweeps: int = 1, theta_max: 
                 trial[m] = t
                 return ansatz_energy(h, pool, ref, ks, trial)
 
-            t_new, e_new = _minimise_1d(f, theta_max, n_grid)
+            t_new, e_new = minimise_angle(f, theta_max, n_grid)
             th[m] = t_new
             if trace is not None:
                 trace.append((m, before, t_new, e_new))

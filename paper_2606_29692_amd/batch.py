@@ -135,3 +135,29 @@ def bytes_per_step(systems: list) -> dict:
         nnz_single = max(o.nnz for o in s.pool.ops)
         out["taylor"] += 4 * (dim + 1) + nnz_single * (4 + sv) + 2 * dim * sx
     return out
+
+
+class AnsatzHistory:
+    """The generator and angle of every update applied so far to each slot of
+    a batch plan (device tensors [B, max_steps]), with each slot's reference
+    state, for the re-optimisation of every angle (vqe_batch_reoptimize)."""
+
+    def __init__(self, plan: B.BatchPlan, max_steps: int):
+        torch = _torch()
+        dev = plan.k.device
+        self.plan = plan
+        self.ks = torch.full((plan.B, max_steps), -1, dtype=torch.int32, device=dev)
+        self.thetas = torch.zeros((plan.B, max_steps), dtype=torch.float64, device=dev)
+        self.refs = [psi.clone() for (_, _, psi) in plan.states]
+        self.n = 0
+
+    def record(self):
+        """Append the plan's last selection and angle (device copies)."""
+        if self.n >= self.ks.shape[1]:
+            raise ValueError("AnsatzHistory: more updates than max_steps")
+        self.ks[:, self.n].copy_(self.plan.k)
+        self.thetas[:, self.n].copy_(self.plan.theta)
+        self.n += 1
+
+    def reoptimize(self, sweeps: int = 1, theta_max: float = 1.0, energies=None):
+        self.plan.reoptimize(self.ks, self.thetas, self.n, self.refs, sweeps, theta_max, energies)

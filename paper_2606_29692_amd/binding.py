@@ -95,6 +95,8 @@ SIGNATURES = {
     "vqe_batch_step_timed": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p), C.c_int32]),
     "vqe_batch_destroy": (C.c_int, [C.c_void_p]),
     "vqe_batch_set_line_search": (C.c_int, [C.c_void_p, C.c_double]),
+    "vqe_batch_reoptimize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                       C.c_void_p, C.c_int32, C.c_double, C.c_void_p]),
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
@@ -543,6 +545,29 @@ class BatchPlan:
         search (see vqe_batch_set_line_search); the chosen angles land in theta."""
         self.ctx.check(lib().vqe_batch_set_line_search(self.handle, float(theta_max)),
                        "vqe_batch_set_line_search")
+
+    def reoptimize(self, ks, thetas, n: int, refs: list, sweeps: int = 1,
+                   theta_max: float = 1.0, energies=None):
+        """Re-optimise every angle of each slot's ansatz (vqe_batch_reoptimize).
+        ks: device int32 [B, ld] generator indices; thetas: device float64
+        [B, ld] angles, updated in place; n: updates per slot; refs: B device
+        tensors (reference states); energies: optional device float64 [B]."""
+        torch = _torch()
+        if ks.dtype != torch.int32 or thetas.dtype != torch.float64 or ks.dim() != 2 or \
+                thetas.shape != ks.shape or ks.shape[0] != self.B or not ks.is_contiguous() or \
+                not thetas.is_contiguous() or len(refs) != self.B or not 0 <= n <= ks.shape[1]:
+            raise ValueError("reoptimize: ks and thetas must be contiguous [B, ld] int32 / "
+                             "float64 device tensors with n <= ld, and refs one per slot")
+        if energies is not None and (energies.dtype != torch.float64 or energies.numel() < self.B):
+            raise ValueError("reoptimize: energies must be a float64 device tensor of B entries")
+        for r, (_, _, psi) in zip(refs, self.states):
+            if r.dtype != psi.dtype or r.numel() != psi.numel() or not r.is_contiguous():
+                raise ValueError("reoptimize: each reference must match its slot's state")
+        ptrs = (C.c_void_p * self.B)(*[r.data_ptr() for r in refs])
+        self.ctx.check(lib().vqe_batch_reoptimize(
+            self.handle, ks.data_ptr(), thetas.data_ptr(), int(ks.shape[1]), int(n), ptrs,
+            int(sweeps), float(theta_max), energies.data_ptr() if energies is not None else None),
+            "vqe_batch_reoptimize")
 
     def step(self, renorm: bool = True, forced: bool = False, update: bool = True,
              graph: bool = False, line_search: bool = False):

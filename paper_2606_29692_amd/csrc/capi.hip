@@ -182,6 +182,16 @@ struct vqe_batch {
     SpmvState *d_ls1 = nullptr, *d_ls2 = nullptr;
     int2 *d_ls_tasks = nullptr;
     unsigned n_ls_tasks = 0;
+    // re-optimisation (vqe_batch_reoptimize): descriptors, three product
+    // descriptor arrays, tasks, then per slot nine vectors and partials
+    char *ro_mem = nullptr;
+    size_t ro_bytes = 0;
+    std::vector<char> ro_image;
+    size_t o_ro = 0, o_roh[3] = {0, 0, 0};
+    RoState *d_ro = nullptr;
+    SpmvState *d_roh[3] = {nullptr, nullptr, nullptr};
+    int2 *d_ro_tasks = nullptr;
+    unsigned n_ro_tasks = 0;
 };
 
 namespace {
@@ -924,6 +934,8 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
         (void)hipFree(p->dmem);
     if (p->ls_mem)
         (void)hipFree(p->ls_mem);
+    if (p->ro_mem)
+        (void)hipFree(p->ro_mem);
     for (void *m : p->table_mem)
         (void)hipFree(m);
     delete p;
@@ -932,7 +944,7 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
 
 extern "C" int64_t vqe_batch_workspace_bytes(const vqe_batch *p)
 {
-    return p ? (int64_t)(p->dmem_bytes + p->table_bytes + p->ls_bytes) : -1;
+    return p ? (int64_t)(p->dmem_bytes + p->table_bytes + p->ls_bytes + p->ro_bytes) : -1;
 }
 
 namespace {
@@ -1114,5 +1126,136 @@ extern "C" int vqe_batch_set_line_search(vqe_batch *p, double theta_max)
                                 hipMemcpyHostToDevice, ctx->stream));
     VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     p->ls_ready = true;
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_reoptimize(vqe_batch *p, const int32_t *ks, double *thetas, int32_t ld,
+                                    int32_t n, const void *const *refs, int32_t sweeps,
+                                    double theta_max, double *energies_out)
+{
+    if (!p)
+        return VQE_EINVAL;
+    vqe_ctx *ctx = p->ctx;
+    if (n < 0 || ld < n || sweeps < 0 || !(theta_max > 0.0) || !std::isfinite(theta_max) ||
+        (n > 0 && (!ks || !thetas || !refs)))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_reoptimize: bad arguments");
+    const int B = p->B;
+    for (int s = 0; s < B && n > 0; s++)
+        if (!refs[s])
+            return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_reoptimize: null reference for slot %d", s);
+    if (n == 0 || sweeps == 0)
+        return VQE_OK;
+    int rc = ls_check(p);
+    if (rc)
+        return rc == VQE_ENOTSUP
+                   ? vqe_fail(ctx, VQE_ENOTSUP,
+                              "vqe_batch_reoptimize: a generator does not satisfy A^3 = -A")
+                   : rc;
+    const size_t eb = vqe_elem_bytes(p->dtype);
+    const SpmvState *hsv = reinterpret_cast<const SpmvState *>(p->image.data() + p->o_spmv);
+    const TaylorState *tsv = reinterpret_cast<const TaylorState *>(p->image.data() + p->o_tay);
+    std::vector<size_t> o_vec(B), o_part(B), o_hp(B);
+    if (!p->ro_mem) {
+        Arena A;
+        p->o_ro = A.take(sizeof(RoState) * B);
+        for (int i = 0; i < 3; i++)
+            p->o_roh[i] = A.take(sizeof(SpmvState) * B);
+        std::vector<std::vector<int2>> per(kXcd);
+        for (int s = 0; s < B; s++) {
+            const int nb = (int)((p->dims[s] + LS_ROWS_PER_BLOCK - 1) / LS_ROWS_PER_BLOCK);
+            for (int b = 0; b < nb; b++)
+                per[p->xcd[s]].push_back(make_int2(s, b));
+        }
+        auto flat = interleave(per, make_int2(-1, 0));
+        const size_t o_tasks = A.take(flat.size() * sizeof(int2));
+        for (int s = 0; s < B; s++) {
+            const int64_t nb = (p->dims[s] + LS_ROWS_PER_BLOCK - 1) / LS_ROWS_PER_BLOCK;
+            o_vec[s] = A.take(9 * vqe_align(p->dims[s] * eb));
+            o_part[s] = A.take((size_t)nb * RO_NDOT * sizeof(double));
+            o_hp[s] = A.take(3 * (size_t)hsv[s].nblocks * 3 * sizeof(double));
+        }
+        p->ro_bytes = A.host.size();
+        if (hipMalloc((void **)&p->ro_mem, p->ro_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p->ro_mem = nullptr;
+            p->ro_bytes = 0;
+            return vqe_fail(ctx, VQE_ENOMEM, "vqe_batch_reoptimize: allocation failed");
+        }
+        char *D = p->ro_mem;
+        std::copy(flat.begin(), flat.end(), A.at<int2>(o_tasks));
+        // fixed addresses: vectors and partials
+        for (int s = 0; s < B; s++) {
+            const size_t vb = vqe_align(p->dims[s] * eb);
+            RoState &ro = A.at<RoState>(p->o_ro)[s];
+            char *v = D + o_vec[s];
+            ro.L = v;
+            ro.v1 = v + vb;
+            ro.v2 = v + 2 * vb;
+            for (int i = 0; i < 3; i++) {
+                ro.w[i] = v + (3 + i) * vb;
+                ro.h[i] = v + (6 + i) * vb;
+                SpmvState &hs = A.at<SpmvState>(p->o_roh[i])[s];
+                hs.partials = (double *)(D + o_hp[s]) + (size_t)i * hsv[s].nblocks * 3;
+            }
+            ro.part = (double *)(D + o_part[s]);
+        }
+        p->ro_image = std::move(A.host);
+        p->d_ro = (RoState *)(D + p->o_ro);
+        for (int i = 0; i < 3; i++)
+            p->d_roh[i] = (SpmvState *)(D + p->o_roh[i]);
+        p->d_ro_tasks = (int2 *)(D + o_tasks);
+        p->n_ro_tasks = (unsigned)flat.size();
+    }
+    // this call's descriptors (the plan's current slots, the caller's arrays)
+    for (int s = 0; s < B; s++) {
+        const SpmvState &hs = hsv[s];
+        const TaylorState &ts = tsv[s];
+        RoState &ro = reinterpret_cast<RoState *>(p->ro_image.data() + p->o_ro)[s];
+        ro.psi = const_cast<void *>(hs.psi);
+        ro.ks = ks + (size_t)s * ld;
+        ro.thetas = thetas + (size_t)s * ld;
+        ro.e_out = energies_out ? energies_out + s : nullptr;
+        ro.shift = hs.shift;
+        ro.dim = hs.dim;
+        ro.ops = ts.ops;
+        ro.mf = p->mf ? p->mf_desc_dev[p->table_idx[s]] : nullptr;
+        ro.M = ts.M;
+        ro.nb_rows = (int32_t)((hs.dim + LS_ROWS_PER_BLOCK - 1) / LS_ROWS_PER_BLOCK);
+        ro.theta_max = theta_max;
+        ro.active = hs.active;
+        for (int i = 0; i < 3; i++) {
+            SpmvState &h = reinterpret_cast<SpmvState *>(p->ro_image.data() + p->o_roh[i])[s];
+            double *part = h.partials;
+            h = hs;
+            h.psi = ro.w[i];
+            h.sigma = const_cast<void *>(ro.h[i]);
+            h.partials = part;
+            h.energy_out = nullptr;
+        }
+    }
+    hipStream_t st = ctx->stream;
+    VQE_HIP(ctx, hipMemcpyAsync(p->ro_mem, p->ro_image.data(), p->ro_image.size(),
+                                hipMemcpyHostToDevice, st));
+    VQE_HIP(ctx, hipStreamSynchronize(st));
+    const RoState *ro_host = reinterpret_cast<const RoState *>(p->ro_image.data() + p->o_ro);
+    for (int sw = 0; sw < sweeps; sw++) {
+        // every sweep starts from the reference
+        for (int s = 0; s < B; s++)
+            VQE_HIP(ctx, hipMemcpyAsync(ro_host[s].L, refs[s], p->dims[s] * eb,
+                                        hipMemcpyDeviceToDevice, st));
+        for (int m = 0; m < n; m++) {
+            launch_ro_vectors(p->dtype, p->d_ro, p->d_ro_tasks, p->n_ro_tasks, m, st);
+            for (int q = m + 1; q < n; q++)
+                launch_ro_taylor(p->dtype, p->d_ro, p->d_ro_tasks, p->n_ro_tasks, q, false, st);
+            for (int i = 0; i < 3; i++)
+                launch_products(p, p->d_roh[i]);
+            launch_ro_dots(p->dtype, p->d_ro, p->d_ro_tasks, p->n_ro_tasks, st);
+            launch_ro_solve(p->d_ro, (unsigned)B, m, st);
+            launch_ro_taylor(p->dtype, p->d_ro, p->d_ro_tasks, p->n_ro_tasks, m, true, st);
+        }
+    }
+    launch_ro_finish(p->dtype, p->d_ro, p->d_ro_tasks, p->n_ro_tasks, st);
+    launch_norm(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, st);
+    VQE_LAUNCH_CHECK(ctx);
     return VQE_OK;
 }

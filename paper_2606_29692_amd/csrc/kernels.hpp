@@ -199,10 +199,42 @@ struct LsState {
     double theta_max;
     const int32_t *active;
 };
+
+// Re-optimisation of every angle of one slot's ansatz (cyclic coordinate line
+// search over the updates ks[0..n), angles thetas[0..n)).
+#define RO_NDOT 12            // partial sums of the inner-product kernel
+struct RoState {
+    void *psi;                // out: the slot's state at the final angles
+    void *L;                  // the state before the visited update
+    void *v1, *v2;            // A L, A^2 L
+    void *w[3];               // (L, A L, A^2 L) with the later updates applied
+    const void *h[3];         // S w_i (written by the H products)
+    const int32_t *ks;        // [n] generator of each update
+    double *thetas;           // [n] angles (in/out)
+    double *e_out;            // energy after the last visit (nullable)
+    double shift;
+    int64_t dim;
+    const vqe_csr *ops;       // CSR pool (device descriptors), or
+    const vqe_mf_desc *mf;    // matrix-free descriptors
+    int32_t M;
+    int32_t nb_rows;          // blocks of the vector, update and dot kernels
+    double *part;             // [nb_rows * RO_NDOT]
+    double theta_max;
+    const int32_t *active;
+};
 void launch_ls_vectors(int dtype, const LsState *states, const int2 *tasks, unsigned grid,
                        hipStream_t s);
 void launch_ls_dot(int dtype, const LsState *states, const int2 *tasks, unsigned grid,
                    hipStream_t s);
+void launch_ro_vectors(int dtype, const RoState *states, const int2 *tasks, unsigned grid, int m,
+                       hipStream_t s);
+void launch_ro_taylor(int dtype, const RoState *states, const int2 *tasks, unsigned grid, int m,
+                      bool advance, hipStream_t s);
+void launch_ro_dots(int dtype, const RoState *states, const int2 *tasks, unsigned grid,
+                    hipStream_t s);
+void launch_ro_solve(const RoState *states, unsigned n_states, int m, hipStream_t s);
+void launch_ro_finish(int dtype, const RoState *states, const int2 *tasks, unsigned grid,
+                      hipStream_t s);
 void launch_ls_solve(const LsState *states, unsigned n_states, hipStream_t s);
 
 struct vqe_mf_pool;
