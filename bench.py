@@ -204,6 +204,9 @@ def main():
                          "(no pool CSR) instead of the pool's pair tables")
     ap.add_argument("--line-search-steps", type=int, default=20,
                     help="also time this many steps with the angle chosen by line search (0: skip)")
+    ap.add_argument("--adapt-steps", type=int, default=12,
+                    help="also run this many adaptive steps from the reference with line "
+                         "search, without and with re-optimisation of every angle (0: skip)")
     ap.add_argument("--qubits", type=int, default=14, choices=sorted(vs_electrons()),
                     help="register size of every state (the headline workload is 14)")
     ap.add_argument("--mapping", choices=["jw", "bk"], default="jw")
@@ -327,6 +330,56 @@ def main():
         log(f"line search: {ls_ms:.3f} ms/step ({len(ds) / (ls_ms / 1e3):.0f} updates/s), "
             f"mean energy drop over {args.line_search_steps} steps {drop:.4f} Ha")
 
+    # adaptive runs from the reference: the angle of each new update by line
+    # search, then optionally one sweep re-optimising every angle (cyclic
+    # coordinate line search); separate figures, not the headline value
+    adapt = None
+    if args.adapt_steps > 0:
+        S, eps = args.adapt_steps, 1e-3
+        adapt = {"steps": S, "epsilon": eps, "theta_max": 1.0}
+        for mode in ("line_search", "line_search+reoptimization"):
+            for d in ds:
+                d.reset()
+            plan.set_line_search(1.0)
+            hist = PB.AnsatzHistory(plan, S)
+            gm = torch.zeros((S, len(ds)), dtype=torch.float64, device="cuda")
+            en = torch.zeros((S + 1, len(ds)), dtype=torch.float64, device="cuda")
+            r_ms = 0.0
+            torch.cuda.synchronize()
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            for t in range(S):
+                plan.step(renorm=True, line_search=True)
+                gm[t].copy_(plan.gmax)
+                en[t].copy_(plan.energies.view(-1, 3)[:, 0])
+                hist.record()
+                if mode != "line_search":
+                    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    r0.record(stream)
+                    hist.reoptimize(1, 1.0)
+                    r1.record(stream)
+                    r1.synchronize()
+                    r_ms += r0.elapsed_time(r1)
+            a1.record(stream)
+            plan.step(update=False)
+            en[S].copy_(plan.energies.view(-1, 3)[:, 0])
+            torch.cuda.synchronize()
+            total = a0.elapsed_time(a1)
+            g = gm.cpu().numpy()
+            e = en.cpu().numpy()
+            below = g < eps
+            conv = [int(np.argmax(below[:, i])) if below[:, i].any() else None
+                    for i in range(len(ds))]
+            adapt[mode] = {"ms_total": total, "reoptimization_ms_total": r_ms if r_ms else None,
+                           "mean_energy_drop_Ha": float((e[0] - e[S]).mean()),
+                           "mean_final_gmax": float(np.abs(plan.gmax.cpu().numpy()).mean()),
+                           "states_converged": int(sum(c is not None for c in conv))}
+            log(f"adaptive run ({mode}): {S} steps in {total:.1f} ms, mean energy drop "
+                f"{(e[0] - e[S]).mean():.4f} Ha, mean final max|g| "
+                f"{adapt[mode]['mean_final_gmax']:.2e}, {adapt[mode]['states_converged']} of "
+                f"{len(ds)} states reached max|g| < {eps:g}")
+        plan.set_line_search(0.0)
+
     # phase breakdown of the same step launched eagerly (context figures)
     ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(10)]
     for t in range(10):
@@ -428,6 +481,7 @@ def main():
                      "bytes_per_launch": nbytes["h_spmv"]},
         "plain_fp64_single_request": plain,
         "line_search": line_search,
+        "adaptive_runs": adapt,
         "partition": partition,
         "serving": serving,
         "p99_latency_ms": (serving["x0.8"]["continuous_batching"]["p99_ms"] if serving
