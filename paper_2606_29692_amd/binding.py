@@ -25,6 +25,7 @@ VQE_SPMV_VEC4 = 0x100
 VQE_SPMV_LDS = 0x200
 VQE_SPMV_DEEP = 0x400
 VQE_SPMV_PREFETCH = 0x800
+VQE_SPMV_X16 = 0x4000
 REL_TIE = 1e-6
 
 DTYPES = {"c128": VQE_C128, "c64": VQE_C64}

@@ -182,6 +182,9 @@ struct vqe_batch {
     SpmvState *d_ls1 = nullptr, *d_ls2 = nullptr;
     int2 *d_ls_tasks = nullptr;
     unsigned n_ls_tasks = 0;
+    // 16-bit column codes of slots whose schedule reads them (VQE_SPMV_X16)
+    std::vector<uint16_t *> col16;
+    std::vector<int64_t> col16_cap;
     // re-optimisation (vqe_batch_reoptimize): descriptors, three product
     // descriptor arrays, tasks, then per slot nine vectors and partials
     char *ro_mem = nullptr;
@@ -220,6 +223,32 @@ std::vector<T> interleave(const std::vector<std::vector<T>> &per, const T &pad)
         for (auto &v : per)
             out.push_back(i < v.size() ? v[i] : pad);
     return out;
+}
+
+// (Re)build slot s's 16-bit column codes for H: reuse the slot's buffer when
+// it is large enough, and point the slot's host descriptor at it (the caller
+// uploads the descriptor).
+int x16_fill(vqe_batch *p, int s, const vqe_csr *H)
+{
+    vqe_ctx *ctx = p->ctx;
+    const int64_t need = H->nnz > 0 ? H->nnz : 1;
+    if (p->col16_cap[s] < need) {
+        if (p->col16[s]) {
+            VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            (void)hipFree(p->col16[s]);
+            p->col16[s] = nullptr;
+            p->col16_cap[s] = 0;
+        }
+        if (hipMalloc((void **)&p->col16[s], (size_t)need * sizeof(uint16_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            p->col16[s] = nullptr;
+            return vqe_fail(ctx, VQE_ENOMEM, "column codes of slot %d: allocation failed", s);
+        }
+        p->col16_cap[s] = need;
+    }
+    launch_col_xor16(H, p->col16[s], ctx->stream);
+    reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s].col16 = p->col16[s];
+    return VQE_OK;
 }
 
 // The step is two launch sequences: the H products (sequence A) and the rest
@@ -798,6 +827,30 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: %s", hipGetErrorString(e));
     }
     p->image = std::move(A.host);
+    // 16-bit column codes for the slots whose schedule reads them
+    p->col16.assign(B, nullptr);
+    p->col16_cap.assign(B, 0);
+    bool any16 = false;
+    for (int s = 0; s < B; s++) {
+        if (!(lanes[s] & VQE_SPMV_X16))
+            continue;
+        any16 = true;
+        const int rc16 = x16_fill(p, s, items[s].H);
+        if (rc16) {
+            vqe_batch_destroy(p);
+            return rc16;
+        }
+    }
+    if (any16) {
+        e = hipMemcpyAsync(p->dmem + p->o_spmv, p->image.data() + p->o_spmv, sizeof(SpmvState) * B,
+                           hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            vqe_batch_destroy(p);
+            return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: %s", hipGetErrorString(e));
+        }
+    }
     if (!bounds_list.empty()) {
         p->d_bounds_tasks = (int2 *)(D + o_btasks);
         p->bounds_range = bounds_range;
@@ -852,6 +905,11 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
     ss->shift = it->H->diag_shift;
     TaylorState *ts = reinterpret_cast<TaylorState *>(p->image.data() + p->o_tay) + slot;
     ts->psi = it->psi;
+    if (sched & VQE_SPMV_X16) {
+        rc = x16_fill(p, slot, it->H);
+        if (rc)
+            return rc;
+    }
     hipStream_t s = ctx->stream;
     VQE_HIP(ctx, hipMemcpyAsync(p->dmem + ((char *)st - p->image.data()), st, sizeof(*st),
                                 hipMemcpyHostToDevice, s));
@@ -936,6 +994,9 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
         (void)hipFree(p->ls_mem);
     if (p->ro_mem)
         (void)hipFree(p->ro_mem);
+    for (uint16_t *c : p->col16)
+        if (c)
+            (void)hipFree(c);
     for (void *m : p->table_mem)
         (void)hipFree(m);
     delete p;
@@ -944,7 +1005,12 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
 
 extern "C" int64_t vqe_batch_workspace_bytes(const vqe_batch *p)
 {
-    return p ? (int64_t)(p->dmem_bytes + p->table_bytes + p->ls_bytes + p->ro_bytes) : -1;
+    if (!p)
+        return -1;
+    int64_t c16 = 0;
+    for (int64_t c : p->col16_cap)
+        c16 += c * (int64_t)sizeof(uint16_t);
+    return (int64_t)(p->dmem_bytes + p->table_bytes + p->ls_bytes + p->ro_bytes) + c16;
 }
 
 namespace {

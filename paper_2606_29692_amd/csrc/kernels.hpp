@@ -45,11 +45,15 @@ struct SpmvState {
     double *tile_part;         // [ntiles * dim] FP64 complex partial rows
     int32_t ntiles;            // 0: not tiled
     int32_t tile_cols;
+    // 16-bit column form (schedules with VQE_SPMV_X16): col16[k] = col[k] ^ row
+    const uint16_t *col16;
 };
 
 // Column-tiled H product: tile width (state elements staged in LDS per pass)
 // and rows per workgroup of the tile-sum kernel.
 #define VQE_SPMV_TILED 0x1000
+// largest dimension whose column XOR row fits 16 bits
+#define SPMV_X16_MAX_DIM 65536
 #define SPMV_TILE_BYTES (128 * 1024)
 #define SPMV_SUM_ROWS 1024
 
@@ -285,6 +289,8 @@ void launch_spmv_tiled(int dtype, int sched, const SpmvState *states, const int2
 void launch_tile_bounds(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s);
 int32_t spmv_tile_cols(int dtype);
 int64_t spmv_blocks(int64_t dim, int sched);
+// col16[k] = col[k] ^ row(k) for every entry of H (dim <= SPMV_X16_MAX_DIM)
+void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 
 void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, unsigned grid,

@@ -368,6 +368,18 @@ template <> struct BufVal<VQE_C128> {
     }
 };
 
+// Column codes of the 16-bit form: one thread per row.
+__global__ void __launch_bounds__(256)
+k_col_xor16(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+            uint16_t *__restrict__ col16, int64_t dim)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= dim)
+        return;
+    for (int32_t k = rowptr[r]; k < rowptr[r + 1]; k++)
+        col16[k] = (uint16_t)((uint32_t)col[k] ^ (uint32_t)r);
+}
+
 // Pipelined variant of the LDS schedule.  A sub-group of L lanes covers a row
 // of up to U * 4 * L = 256 entries in one pass and keeps the loads of its next
 // D rows in flight: after a row's products it refills that row's registers
@@ -378,8 +390,10 @@ template <> struct BufVal<VQE_C128> {
 // row's products leaves the other rows' loads outstanding (the scheduling
 // barriers keep each refill issued before the next row is consumed).  Rows
 // longer than one pass finish with further passes, and the last nnz % 4
-// entries of the arrays are added entry by entry.
-template <int DT, int L, int D, bool BATCH>
+// entries of the arrays are added entry by entry.  With X16 the column of
+// entry k of row r is read as the 16-bit code col16[k] = col[k] ^ r (8 bytes
+// per group of four instead of 16), for states of at most 2^16 rows.
+template <int DT, int L, int D, bool BATCH, bool X16>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
               const int2 *__restrict__ tasks)
@@ -425,7 +439,8 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     const int nnz = (int)st.nnz, zc = (int)dim;
     const int whole = nnz & ~3;              // groups starting below this are whole
     const __amdgpu_buffer_rsrc_t rc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
+        X16 ? __builtin_amdgcn_make_buffer_rsrc((void *)st.col16, (short)0, nnz * 2, VQE_BUF_WORD3)
+            : __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
     const __amdgpu_buffer_rsrc_t rv =
         __builtin_amdgcn_make_buffer_rsrc((void *)st.val, (short)0, (int)(nnz * EB), VQE_BUF_WORD3);
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
@@ -436,26 +451,38 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         for (int u = 0; u < U; u++) {
             const int k = kb + u * 4 * L;
             const bool ok = k < k1 && k < whole;
-            typedef int v4i __attribute__((ext_vector_type(4)));
-            const v4i c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 4u : VQE_BUF_OOB, 0, 0);
-            c[4 * u + 0] = c4.x;
-            c[4 * u + 1] = c4.y;
-            c[4 * u + 2] = c4.z;
-            c[4 * u + 3] = c4.w;
+            if (X16) {
+                typedef unsigned v2u __attribute__((ext_vector_type(2)));
+                const v2u c2 = __builtin_amdgcn_raw_buffer_load_b64(rc, ok ? (unsigned)k * 2u : VQE_BUF_OOB, 0, 0);
+                c[4 * u + 0] = (int)(c2.x & 0xffffu);
+                c[4 * u + 1] = (int)(c2.x >> 16);
+                c[4 * u + 2] = (int)(c2.y & 0xffffu);
+                c[4 * u + 3] = (int)(c2.y >> 16);
+            } else {
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                const v4i c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 4u : VQE_BUF_OOB, 0, 0);
+                c[4 * u + 0] = c4.x;
+                c[4 * u + 1] = c4.y;
+                c[4 * u + 2] = c4.z;
+                c[4 * u + 3] = c4.w;
+            }
             BufVal<DT>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
         }
     };
-    // products of one pass; entries outside [k0, k1) read the zero element
-    auto consume = [&](int kb, int k0, int k1, const int c[W], const T v[W], double &are,
-                       double &aim) {
+    // products of one pass of row r; entries outside [k0, k1) read the zero
+    // element
+    auto consume = [&](int64_t r, int kb, int k0, int k1, const int c[W], const T v[W],
+                       double &are, double &aim) {
         int cm[W];
         const unsigned len = (unsigned)(k1 - k0);
+        const int rx = (int)r;
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int k = kb + u * 4 * L + q;
-                cm[4 * u + q] = (unsigned)(k - k0) < len ? c[4 * u + q] : zc;
+                const int col = X16 ? (rx ^ c[4 * u + q]) : c[4 * u + q];
+                cm[4 * u + q] = (unsigned)(k - k0) < len ? col : zc;
             }
         lds_gather_fma<T, W>(s_x, cm, v, are, aim);
     };
@@ -473,14 +500,15 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
             int c[W];
             T v[W];
             issue(kb, k1, c, v);
-            consume(kb, k0, k1, c, v, are, aim);
+            consume(r, kb, k0, k1, c, v, are, aim);
         }
         // the entries after the last whole group of the arrays
         if (k1 > whole) {
             const int k = (k0 > whole ? k0 : whole) + sl;
             if (k < k1) {
                 const T a = ldg(reinterpret_cast<const T *>(st.val), k);
-                const T x = s_x[gmem(st.col)[k]];
+                const int col = X16 ? ((int)r ^ (int)gmem(st.col16)[k]) : gmem(st.col)[k];
+                const T x = s_x[col];
                 are += (double)a.x * (double)x.x - (double)a.y * (double)x.y;
                 aim += (double)a.x * (double)x.y + (double)a.y * (double)x.x;
             }
@@ -515,7 +543,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         for (int d = 0; d < D; d++) {
             {
                 double are = 0.0, aim = 0.0;
-                consume((kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
+                consume(rr[d], (kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
                 finish(rr[d], kb0[d], kb1[d], are, aim);
             }
             rr[d] += 16 * D * G;
@@ -818,17 +846,17 @@ static void launch_spmv_lds_t(const SpmvState &single, const SpmvState *states, 
     }
 }
 
-template <int DT, int L, int D>
+template <int DT, int L, int D, bool X16 = false>
 static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, const int2 *tasks,
                              unsigned grid, hipStream_t s, size_t lds)
 {
     if (tasks) {
-        auto k = k_spmv_lds_pf<DT, L, D, true>;
+        auto k = k_spmv_lds_pf<DT, L, D, true, X16>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
     } else {
-        auto k = k_spmv_lds_pf<DT, L, D, false>;
+        auto k = k_spmv_lds_pf<DT, L, D, false, false>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
@@ -841,7 +869,13 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
 {
     constexpr int D = VQE_SPMV_LDS | VQE_SPMV_DEEP;
     constexpr int P = VQE_SPMV_LDS | VQE_SPMV_PREFETCH;
+    constexpr int X = P | VQE_SPMV_X16;
     switch (sched) {
+    // the 16-bit column form exists only in batch plans (tasks non-null)
+    case 32 | X: launch_spmv_pf_t<DT, 32, 2, true>(single, states, tasks, grid, s, lds); return;
+    case 64 | X: launch_spmv_pf_t<DT, 64, 2, true>(single, states, tasks, grid, s, lds); return;
+    case 32 | X | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 32, 3, true>(single, states, tasks, grid, s, lds); return;
+    case 64 | X | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 64, 3, true>(single, states, tasks, grid, s, lds); return;
     case 32 | P: launch_spmv_pf_t<DT, 32, 2>(single, states, tasks, grid, s, lds); return;
     case 64 | P: launch_spmv_pf_t<DT, 64, 2>(single, states, tasks, grid, s, lds); return;
     case 32 | P | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 32, 3>(single, states, tasks, grid, s, lds); return;
@@ -940,6 +974,10 @@ bool vqe_valid_schedule(int sched)
     // 8 and 16 lanes: pipelined only in the column-tiled form (else plain LDS)
     case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH: case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH:
     case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
+    case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
+    case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
         return true;
     default:
         return false;
@@ -961,7 +999,10 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
     if ((sched & VQE_SPMV_PREFETCH) &&
         (!(sched & VQE_SPMV_LDS) || H->nnz * (int64_t)vqe_elem_bytes(H->dtype) > 0x7fffff00LL ||
          (sched & 0xff) < 32))
-        return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP);
+        return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16);
+    // the 16-bit column form needs column XOR row below 2^16
+    if ((sched & VQE_SPMV_X16) && H->dim > SPMV_X16_MAX_DIM)
+        return sched & ~VQE_SPMV_X16;
     return sched;
 }
 
@@ -973,8 +1014,14 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
     if (big && aligned && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) &&
         H->nnz * (int64_t)vqe_elem_bytes(H->dtype) <= 0x7fffff00LL && H->dim <= ((int64_t)1 << 30))
-        return sched | VQE_SPMV_TILED;
+        return (sched & ~VQE_SPMV_X16) | VQE_SPMV_TILED;
     return vqe_effective_schedule(H, sched);
+}
+
+void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((H->dim + 255) / 256);
+    k_col_xor16<<<grid, 256, 0, s>>>(H->rowptr, H->col, col16, H->dim);
 }
 
 int64_t spmv_blocks(int64_t dim, int sched)
@@ -1083,7 +1130,8 @@ extern "C" int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, vo
         return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: bad arguments");
     if (!vqe_valid_schedule(schedule))
         return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: unknown schedule %d", schedule);
-    const int lanes = schedule;
+    // a single call has no 16-bit column codes: the same schedule without them
+    const int lanes = schedule & ~VQE_SPMV_X16;
     // energy result goes after the partials in the workspace
     const size_t o_out = vqe_spmv_partials_bytes(H->dim, lanes);
     rc = vqe_ws_reserve(ctx, o_out + 256);

@@ -202,7 +202,9 @@ def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
 
 
 @pytest.mark.parametrize("sched", [0, 16 | B.VQE_SPMV_LDS, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
-                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP])
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
+                                   B.VQE_SPMV_X16])
 def test_full_size_bench_config(ctx, sched):
     """64 states at 14 qubits in FP32 storage (the benchmark workload):
     sampled states against the oracle, invariants on every state."""
@@ -249,7 +251,13 @@ def test_full_size_bench_config(ctx, sched):
                                    16 | B.VQE_SPMV_LDS | B.VQE_SPMV_DEEP,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
                                    64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
-                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP])
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16,
+                                   64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
+                                   B.VQE_SPMV_X16,
+                                   64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
+                                   B.VQE_SPMV_X16])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
@@ -305,3 +313,86 @@ def test_screen_full_pair_table(ctx):
     want = orc.taylor5(orc.csr_from_pack(scaled[7]), 0.3, v)
     assert np.linalg.norm(host(psi) - want) <= 1e-12
     plan.close()
+
+
+@pytest.mark.parametrize("sched", [32 | B.VQE_SPMV_LDS,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
+                                   64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("op", ["half", "zero"])
+def test_spmv_rows_without_entries(ctx, sched, dtype, op):
+    """Operators whose CSR has empty rows, against the oracle (sigma and
+    energy): (I + Z_0)/2 + (X_3 + X_3 Z_0)/4 keeps only the rows with qubit 0
+    clear; Z_0 - Z_0 has no entries at all."""
+    n = 10
+    s = vs.make_system(vs.SystemSpec(n, 4, "jw", False, 77))
+    if op == "half":
+        x = np.array([0, 0, 1 << 3, 1 << 3], dtype=np.uint64)
+        z = np.array([0, 1, 0, 1], dtype=np.uint64)
+        c = np.array([0.5, 0.5, 0.25, 0.25], dtype=np.complex128)
+    else:
+        x = np.array([0, 0], dtype=np.uint64)
+        z = np.array([1, 1], dtype=np.uint64)
+        c = np.array([1.0, -1.0], dtype=np.complex128)
+    pack = vs.PauliPack(n, x, z, c)
+    oH = orc.csr_from_pack(pack)
+    rows = np.diff(np.asarray(oH.rowptr))
+    assert (rows == 0).sum() == ((1 << n) // 2 if op == "half" else 1 << n)
+    H = B.csr_from_pack(ctx, pack, dtype)
+    pool = B.pool_from_packs(ctx, s.pool, dtype)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    v /= np.linalg.norm(v)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    psi = torch.from_numpy(v).to(tdt).to(ctx.torch_device)
+    plan = B.BatchPlan(ctx, [(H, pool, psi)], schedules=[sched])
+    plan.step(update=False)
+    e = host(plan.energies).reshape(-1, 3)[0]
+    vin = host(psi).astype(np.complex128)
+    e_o, _, _, sig = orc.energy(oH, vin)
+    tol = 1e-12 if dtype == "c128" else 1e-6
+    assert abs(e[0] - e_o) <= tol
+    sg = host(plan.sigma[0]).astype(np.complex128)
+    assert np.linalg.norm(sg - sig) <= tol * max(1.0, np.linalg.norm(sig))
+    assert np.all(sg[rows == 0] == 0)
+    plan.close()
+
+
+def test_x16_rebind_rebuilds_codes(ctx):
+    """A slot with the 16-bit column form rebound to a Hamiltonian with more
+    entries (its codes are rebuilt in a larger buffer) gives the energies and
+    sigma of that Hamiltonian's own plan, bit for bit; both match the oracle."""
+    sched = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP | B.VQE_SPMV_X16
+    s = vs.make_system(vs.SystemSpec(12, 8, "jw", False, 91))
+    ha = s.hamiltonian
+    # two thirds of the terms: exact cancellations of the full sum are lost,
+    # so this operator has more entries
+    keep = np.arange(ha.xmask.size) % 3 != 0
+    hb = vs.PauliPack(12, ha.xmask[keep], ha.zmask[keep], ha.coeff[keep])
+    pool = B.pool_from_packs(ctx, s.pool, "c64")
+    Ha = B.csr_from_pack(ctx, ha, "c64")
+    Hb = B.csr_from_pack(ctx, hb, "c64")
+    assert Hb.nnz > Ha.nnz
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(1 << 12) + 1j * rng.standard_normal(1 << 12)
+    v /= np.linalg.norm(v)
+    psi_a = torch.from_numpy(v).to(torch.complex64).to(ctx.torch_device)
+    psi_b = psi_a.clone()
+    plan = B.BatchPlan(ctx, [(Ha, pool, psi_a)], schedules=[sched])
+    plan.step(update=False)
+    e_a = host(plan.energies)[:3].copy()
+    plan.rebind(0, Hb, pool, psi_b)
+    plan.step(update=False)
+    e_r = host(plan.energies)[:3].copy()
+    sg_r = host(plan.sigma[0]).copy()
+    own = B.BatchPlan(ctx, [(Hb, pool, psi_b)], schedules=[sched])
+    own.step(update=False)
+    np.testing.assert_array_equal(e_r, host(own.energies)[:3])
+    np.testing.assert_array_equal(sg_r, host(own.sigma[0]))
+    vin = host(psi_a).astype(np.complex128)
+    for pack, e in ((ha, e_a), (hb, e_r)):
+        e_o = orc.energy(orc.csr_from_pack(pack), vin)[0]
+        assert abs(e[0] - e_o) <= 1e-5 * max(1.0, abs(e_o))
+    plan.close()
+    own.close()
