@@ -70,11 +70,12 @@ def vs_electrons() -> dict:
 
 
 def plan_sched_x16(sched: int, ds) -> bool:
-    """True when the batch plan reads 16-bit column codes for every state
-    (the schedule asks for them and every state has at most 2^16 rows)."""
+    """True when the batch plan reads 16-bit column codes for every state:
+    the pipelined schedule asks for them and every state has at most 2^16
+    rows (states larger than LDS take the column-tiled form with the codes)."""
     from paper_2606_29692_amd import binding as B
     return bool(sched & B.VQE_SPMV_X16) and bool(sched & B.VQE_SPMV_PREFETCH) and \
-        all(d.H.dim <= 65536 and d.H.dim * d.psi.element_size() <= 147 * 1024 for d in ds)
+        bool(sched & B.VQE_SPMV_LDS) and all(d.H.dim <= 65536 for d in ds)
 
 
 def log(msg: str):

@@ -439,9 +439,9 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * plans only): the product reads each column as the 16-bit code
  * col[k] ^ row, which the plan derives from the CSR once (2 bytes per entry,
  * plan-owned, rebuilt by vqe_batch_rebind), instead of the 4-byte index:
- * 10 instead of 12 bytes per entry in FP32 storage.  States with more than
- * 2^16 rows use the schedule without it; single calls (vqe_time_spmv) ignore
- * it. */
+ * 10 instead of 12 bytes per entry in FP32 storage; the column-tiled form of
+ * larger-than-LDS states reads them too.  States with more than 2^16 rows
+ * use the schedule without it; single calls (vqe_time_spmv) ignore it. */
 #define VQE_SPMV_X16 0x4000
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given

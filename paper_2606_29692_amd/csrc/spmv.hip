@@ -578,7 +578,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
 // sorted within a row, bounded by the per-tile row pointers.  The row sums of
 // a tile go to an FP64 partial array; the tile-sum kernel adds the tiles in
 // ascending order and applies the energy epilogue.
-template <int DT, int L, int D, int U>
+template <int DT, int L, int D, int U, bool X16>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
 {
@@ -621,7 +621,8 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     const int nnz = (int)st.nnz, zc = tc;
     const int whole = nnz & ~3;
     const __amdgpu_buffer_rsrc_t rc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
+        X16 ? __builtin_amdgcn_make_buffer_rsrc((void *)st.col16, (short)0, nnz * 2, VQE_BUF_WORD3)
+            : __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
     const __amdgpu_buffer_rsrc_t rv =
         __builtin_amdgcn_make_buffer_rsrc((void *)st.val, (short)0, (int)(nnz * EB), VQE_BUF_WORD3);
     double *__restrict__ part = st.tile_part + (int64_t)t * dim * 2;
@@ -631,27 +632,37 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
         for (int u = 0; u < U; u++) {
             const int k = kb + u * 4 * L;
             const bool ok = k < k1 && k < whole;
-            typedef int v4i __attribute__((ext_vector_type(4)));
-            const v4i c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 4u : VQE_BUF_OOB, 0, 0);
-            c[4 * u + 0] = c4.x;
-            c[4 * u + 1] = c4.y;
-            c[4 * u + 2] = c4.z;
-            c[4 * u + 3] = c4.w;
+            if (X16) {
+                typedef unsigned v2u __attribute__((ext_vector_type(2)));
+                const v2u c2 = __builtin_amdgcn_raw_buffer_load_b64(rc, ok ? (unsigned)k * 2u : VQE_BUF_OOB, 0, 0);
+                c[4 * u + 0] = (int)(c2.x & 0xffffu);
+                c[4 * u + 1] = (int)(c2.x >> 16);
+                c[4 * u + 2] = (int)(c2.y & 0xffffu);
+                c[4 * u + 3] = (int)(c2.y >> 16);
+            } else {
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                const v4i c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 4u : VQE_BUF_OOB, 0, 0);
+                c[4 * u + 0] = c4.x;
+                c[4 * u + 1] = c4.y;
+                c[4 * u + 2] = c4.z;
+                c[4 * u + 3] = c4.w;
+            }
             BufVal<DT>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
         }
     };
     // entries outside [k0, k1) (or not loaded) read the zero element; the
     // column test keeps every LDS index inside the tile
-    auto consume = [&](int kb, int k0, int k1, const int c[W], const T v[W], double &are,
-                       double &aim) {
+    auto consume = [&](int64_t r, int kb, int k0, int k1, const int c[W], const T v[W],
+                       double &are, double &aim) {
         int cm[W];
         const unsigned len = (unsigned)(k1 - k0);
+        const int rx = (int)r;
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int k = kb + u * 4 * L + q;
-                const int cl = c[4 * u + q] - c_lo;
+                const int cl = (X16 ? (rx ^ c[4 * u + q]) : c[4 * u + q]) - c_lo;
                 cm[4 * u + q] = ((unsigned)(k - k0) < len && (unsigned)cl < (unsigned)tc) ? cl : zc;
             }
         lds_gather_fma<T, W>(s_x, cm, v, are, aim);
@@ -669,13 +680,14 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
             int c[W];
             T v[W];
             issue(kb, k1, c, v);
-            consume(kb, k0, k1, c, v, are, aim);
+            consume(r, kb, k0, k1, c, v, are, aim);
         }
         if (k1 > whole) {
             const int k = (k0 > whole ? k0 : whole) + sl;
             if (k < k1) {
                 const T a = ldg(reinterpret_cast<const T *>(st.val), k);
-                const T x = s_x[gmem(st.col)[k] - c_lo];
+                const int col = X16 ? ((int)r ^ (int)gmem(st.col16)[k]) : gmem(st.col)[k];
+                const T x = s_x[col - c_lo];
                 are += (double)a.x * (double)x.x - (double)a.y * (double)x.y;
                 aim += (double)a.x * (double)x.y + (double)a.y * (double)x.x;
             }
@@ -704,7 +716,7 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
         for (int d = 0; d < D; d++) {
             {
                 double are = 0.0, aim = 0.0;
-                consume((kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
+                consume(rr[d], (kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
                 finish(rr[d], kb0[d], kb1[d], are, aim);
             }
             rr[d] += 16 * D * G;
@@ -919,11 +931,13 @@ int32_t spmv_tile_cols(int dtype) { return (int32_t)(SPMV_TILE_BYTES / vqe_elem_
 // Tile passes see short row segments, so narrow sub-groups keep two groups of
 // four entries per lane (U = 2) instead of covering 256 entries per pass.
 template <int DT, int L, int D>
-static void launch_tiled_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s)
+static void launch_tiled_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
+                           bool x16)
 {
     const size_t lds = (size_t)(spmv_tile_cols(DT) + 1) * vqe_elem_bytes(DT) +
                        2 * SPMV_LDS_ROWS * sizeof(int32_t);
-    auto k = k_spmv_tiled<DT, L, D, (L >= 32 ? 64 / L : 2)>;
+    auto k = x16 ? k_spmv_tiled<DT, L, D, (L >= 32 ? 64 / L : 2), true>
+                 : k_spmv_tiled<DT, L, D, (L >= 32 ? 64 / L : 2), false>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);
 }
@@ -933,15 +947,16 @@ static void launch_tiled_dt(int sched, const SpmvState *states, const int2 *task
                             const int2 *sum_tasks, unsigned sum_grid, hipStream_t s)
 {
     const bool deep = (sched & VQE_SPMV_DEEP) != 0;
+    const bool x = (sched & VQE_SPMV_X16) != 0;
     switch (sched & 0xff) {
-    case 8: deep ? launch_tiled_t<DT, 8, 3>(states, tasks, grid, s)
-                 : launch_tiled_t<DT, 8, 2>(states, tasks, grid, s); break;
-    case 16: deep ? launch_tiled_t<DT, 16, 3>(states, tasks, grid, s)
-                  : launch_tiled_t<DT, 16, 2>(states, tasks, grid, s); break;
-    case 64: deep ? launch_tiled_t<DT, 64, 3>(states, tasks, grid, s)
-                  : launch_tiled_t<DT, 64, 2>(states, tasks, grid, s); break;
-    default: deep ? launch_tiled_t<DT, 32, 3>(states, tasks, grid, s)
-                  : launch_tiled_t<DT, 32, 2>(states, tasks, grid, s); break;
+    case 8: deep ? launch_tiled_t<DT, 8, 3>(states, tasks, grid, s, x)
+                 : launch_tiled_t<DT, 8, 2>(states, tasks, grid, s, x); break;
+    case 16: deep ? launch_tiled_t<DT, 16, 3>(states, tasks, grid, s, x)
+                  : launch_tiled_t<DT, 16, 2>(states, tasks, grid, s, x); break;
+    case 64: deep ? launch_tiled_t<DT, 64, 3>(states, tasks, grid, s, x)
+                  : launch_tiled_t<DT, 64, 2>(states, tasks, grid, s, x); break;
+    default: deep ? launch_tiled_t<DT, 32, 3>(states, tasks, grid, s, x)
+                  : launch_tiled_t<DT, 32, 2>(states, tasks, grid, s, x); break;
     }
     k_spmv_tile_sum<DT><<<sum_grid, 256, 0, s>>>(states, sum_tasks);
 }
@@ -1014,7 +1029,7 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
     if (big && aligned && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) &&
         H->nnz * (int64_t)vqe_elem_bytes(H->dtype) <= 0x7fffff00LL && H->dim <= ((int64_t)1 << 30))
-        return (sched & ~VQE_SPMV_X16) | VQE_SPMV_TILED;
+        return (H->dim > SPMV_X16_MAX_DIM ? sched & ~VQE_SPMV_X16 : sched) | VQE_SPMV_TILED;
     return vqe_effective_schedule(H, sched);
 }
 

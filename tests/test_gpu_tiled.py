@@ -18,6 +18,8 @@ from paper_2606_29692_amd import batch as PB  # noqa: E402
 from paper_2606_29692_amd import binding as B  # noqa: E402
 
 SCHED = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH
+# the same tile passes reading 16-bit column codes (col ^ row)
+SCHED_X16 = SCHED | B.VQE_SPMV_X16
 
 
 @pytest.fixture(scope="module")
@@ -62,11 +64,11 @@ def oracle_run(system, thetas, K):
                          vs.reference_state(system), thetas, len(K), forced=K)
 
 
-@pytest.mark.parametrize("matrix_free", [False, True])
-def test_tiled_fp64_14_qubits(ctx, matrix_free):
+@pytest.mark.parametrize("matrix_free,sched", [(False, SCHED), (True, SCHED), (True, SCHED_X16)])
+def test_tiled_fp64_14_qubits(ctx, matrix_free, sched):
     specs = [vs.SystemSpec(14, 6, m, False, vs.system_seed(60, i)) for i, m in enumerate(["jw", "bk"])]
     systems = [vs.make_system(s) for s in specs]
-    E, K, G, psi, th = run(ctx, systems, "c128", 2, matrix_free)
+    E, K, G, psi, th = run(ctx, systems, "c128", 2, matrix_free, sched)
     for i, s in enumerate(systems):
         tr = oracle_run(s, th[i], K[:, i])
         np.testing.assert_allclose(E[:, i], tr.energies, rtol=0, atol=1e-12 * 10)
@@ -76,10 +78,11 @@ def test_tiled_fp64_14_qubits(ctx, matrix_free):
         assert np.linalg.norm(psi[i] - tr.psi) <= 1e-12 * np.linalg.norm(tr.psi)
 
 
-def test_tiled_fp32_16_qubits(ctx):
+@pytest.mark.parametrize("sched", [SCHED, SCHED_X16])
+def test_tiled_fp32_16_qubits(ctx, sched):
     specs = [vs.SystemSpec(16, 8, "jw", False, vs.system_seed(61, i)) for i in range(2)]
     systems = [vs.make_system(s) for s in specs]
-    E, K, G, psi, th = run(ctx, systems, "c64", 1, True)
+    E, K, G, psi, th = run(ctx, systems, "c64", 1, True, sched)
     tr = oracle_run(systems[0], th[0], K[:, 0])
     de = np.abs(E[:, 0] - np.array(tr.energies)).max()
     dg = np.abs(G[0][0] - tr.gradients[0]).max()
@@ -89,18 +92,19 @@ def test_tiled_fp32_16_qubits(ctx):
     assert de < 1e-6 and dg < 1e-5 and fid > 0.999999
 
 
-def test_tiled_rebind(ctx):
+@pytest.mark.parametrize("sched", [SCHED, SCHED_X16])
+def test_tiled_rebind(ctx, sched):
     """Slot 0 rebound to another Hamiltonian of the same size: its tile
     bounds are rebuilt, and the energy matches that system's own plan."""
     specs = [vs.SystemSpec(14, 6, "jw", False, vs.system_seed(62, i)) for i in range(2)]
     systems = [vs.make_system(s) for s in specs]
     pools = PB.PoolCache(ctx, matrix_free=True)
     a, b = (PB.device_system(ctx, s, "c128", pools) for s in systems)
-    plan = PB.make_batch(ctx, [a], schedules=[SCHED])
+    plan = PB.make_batch(ctx, [a], schedules=[sched])
     plan.rebind(0, b.H, b.pool, b.psi)
     plan.step(update=False)
     e_rebound = host(plan.energies)[:3].copy()
-    own = PB.make_batch(ctx, [b], schedules=[SCHED])
+    own = PB.make_batch(ctx, [b], schedules=[sched])
     own.step(update=False)
     np.testing.assert_array_equal(e_rebound, host(own.energies)[:3])
     plan.close()
