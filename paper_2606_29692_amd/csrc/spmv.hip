@@ -368,15 +368,16 @@ template <> struct BufVal<VQE_C128> {
     }
 };
 
-// Column codes of the 16-bit form: one thread per row.
+// Column codes of the 16-bit form: one wave per row, lanes over its entries.
 __global__ void __launch_bounds__(256)
 k_col_xor16(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
             uint16_t *__restrict__ col16, int64_t dim)
 {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= dim)
         return;
-    for (int32_t k = rowptr[r]; k < rowptr[r + 1]; k++)
+    const int32_t k1 = rowptr[r + 1];
+    for (int32_t k = rowptr[r] + (int32_t)(threadIdx.x & 63); k < k1; k += 64)
         col16[k] = (uint16_t)((uint32_t)col[k] ^ (uint32_t)r);
 }
 
@@ -1035,7 +1036,7 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
 
 void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s)
 {
-    const unsigned grid = (unsigned)((H->dim + 255) / 256);
+    const unsigned grid = (unsigned)((H->dim + 3) / 4);
     k_col_xor16<<<grid, 256, 0, s>>>(H->rowptr, H->col, col16, H->dim);
 }
 
