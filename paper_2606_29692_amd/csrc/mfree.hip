@@ -405,7 +405,10 @@ template <> struct TileElem<VQE_C128> {
 // iterations are computed once, one iteration per lane, and read back with
 // readlane, so the inner loop issues no scalar arithmetic.
 #define MF_LANE_UNROLL 4
-template <int DT, bool SHIFT>
+// With RE_ONLY (generators whose value v is real) only the real part of the
+// sum is formed: the generator's contribution v_re Re(S) - v_im Im(S) needs
+// no more.
+template <int DT, bool SHIFT, bool RE_ONLY>
 __device__ __forceinline__ double2 mf_tile_sum(const typename TileElem<DT>::T *tile, const MfRec &rec,
                                                double shift, int lane)
 {
@@ -476,14 +479,17 @@ __device__ __forceinline__ double2 mf_tile_sum(const typename TileElem<DT>::T *t
                 }
                 // conj(s_r) psi_c and conj(s_c) psi_r
                 const double u1r = sr[u].x * pc[u].x + sr[u].y * pc[u].y;
-                const double u1i = sr[u].x * pc[u].y - sr[u].y * pc[u].x;
                 const double u2r = sc[u].x * pr[u].x + sc[u].y * pr[u].y;
-                const double u2i = sc[u].x * pr[u].y - sc[u].y * pr[u].x;
-                const double tr = e1 * u1r + u2r, ti = e1 * u1i + u2i;
+                const double tr = e1 * u1r + u2r;
                 const bool neg = (sl[u] ^ sh) & 1u;
                 const double w = on[u] ? (neg ? -1.0 : 1.0) : 0.0;
                 sre += w * tr;
-                sim += w * ti;
+                if (!RE_ONLY) {
+                    const double u1i = sr[u].x * pc[u].y - sr[u].y * pc[u].x;
+                    const double u2i = sc[u].x * pr[u].y - sc[u].y * pr[u].x;
+                    const double ti = e1 * u1i + u2i;
+                    sim += w * ti;
+                }
             }
         }
     }
@@ -551,11 +557,17 @@ k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tas
         const MfRec &rec = tb.tile_recs[(int64_t)j * tb.ntile + v];
         double part = 0.0;
         if (rec.nfree >= 0) {
-            const double2 S = (st.shift != 0.0 && !rec.antiherm)
-                                  ? mf_tile_sum<DT, true>(tile, rec, st.shift, lane)
-                                  : mf_tile_sum<DT, false>(tile, rec, 0.0, lane);
-            const double re = group_sum<64>(S.x), im = group_sum<64>(S.y);
-            part = rec.v_re * re - rec.v_im * im;
+            const bool shifted = st.shift != 0.0 && !rec.antiherm;
+            if (rec.v_im == 0.0 && !shifted) {
+                // a real generator value: only Re(S) enters (v_re Re(S) - 0 Im(S))
+                const double2 S = mf_tile_sum<DT, false, true>(tile, rec, 0.0, lane);
+                part = rec.v_re * group_sum<64>(S.x) - rec.v_im * 0.0;
+            } else {
+                const double2 S = shifted ? mf_tile_sum<DT, true, false>(tile, rec, st.shift, lane)
+                                          : mf_tile_sum<DT, false, false>(tile, rec, 0.0, lane);
+                const double re = group_sum<64>(S.x), im = group_sum<64>(S.y);
+                part = rec.v_re * re - rec.v_im * im;
+            }
         }
         if (lane == 0)
             gmem(st.partials)[(int64_t)j * tb.ntile + v] = part;
