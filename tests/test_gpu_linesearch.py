@@ -47,10 +47,10 @@ def specs():
             vs.SystemSpec(12, 8, "jw", True, 303)]
 
 
-def run_gpu(ctx, systems, dtype, steps, matrix_free=False, graph=False):
+def run_gpu(ctx, systems, dtype, steps, matrix_free=False, graph=False, sched=0):
     pools = PB.PoolCache(ctx, matrix_free=matrix_free)
     ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
-    plan = PB.make_batch(ctx, ds)
+    plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds) if sched else None)
     plan.set_line_search(THETA_MAX)
     E, K, T = [], [], []
     for t in range(steps):
@@ -121,11 +121,13 @@ def test_line_search_matrix_free_equals_csr_and_graph(ctx):
             np.testing.assert_array_equal(x, y)
 
 
-def test_line_search_fp32_14_qubits(ctx):
+# the default schedule, and the benchmark's (pipelined, 16-bit column codes)
+@pytest.mark.parametrize("sched", [0, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16])
+def test_line_search_fp32_14_qubits(ctx, sched):
     sp, _ = vs.config_c4(n_states=4, mixed=False)
     systems = [vs.make_system(s) for s in sp]
     steps = 2
-    E, K, T, psi = run_gpu(ctx, systems, "c64", steps, matrix_free=True, graph=True)
+    E, K, T, psi = run_gpu(ctx, systems, "c64", steps, matrix_free=True, graph=True, sched=sched)
     fid = check_against_oracle(systems[0], E[:, 0], K[:, 0], T[:, 0], psi[0], 1e-4, 1e-6, 1e-9)
     assert fid > 0.999999
 

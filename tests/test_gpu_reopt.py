@@ -44,14 +44,14 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def run_gpu(ctx, systems, dtype, steps, sweeps, matrix_free=False, reopt_each_step=False):
+def run_gpu(ctx, systems, dtype, steps, sweeps, matrix_free=False, reopt_each_step=False, sched=0):
     """ADAPT steps with line search on the GPU, recording the history; then
     (or after each step) one re-optimisation.  Returns the angles before the
     final re-optimisation, the final angles, the selections, the energies
     after it and the final states."""
     pools = PB.PoolCache(ctx, matrix_free=matrix_free)
     ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
-    plan = PB.make_batch(ctx, ds)
+    plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds) if sched else None)
     plan.set_line_search(THETA_MAX)
     hist = PB.AnsatzHistory(plan, steps)
     e_out = torch.zeros(plan.B, dtype=torch.float64, device=ctx.torch_device)
@@ -144,11 +144,13 @@ def test_adapt_with_reopt_reaches_sector_ground_state(ctx):
     assert e_next[0] >= e_exact - 1e-12
 
 
-def test_reopt_fp32_14_qubits(ctx):
+# the default schedule, and the benchmark's (pipelined, 16-bit column codes)
+@pytest.mark.parametrize("sched", [0, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16])
+def test_reopt_fp32_14_qubits(ctx, sched):
     sp, _ = vs.config_c4(n_states=2, mixed=False)
     systems = [vs.make_system(s) for s in sp]
     before, after, ks, e, psi, e_next = run_gpu(ctx, systems, "c64", 3, sweeps=1,
-                                                matrix_free=True)
+                                                matrix_free=True, sched=sched)
     for i, s in enumerate(systems):
         h, pool, ref = oracle_parts(s)
         e_o = orc.ansatz_energy(h, pool, ref, ks[i], after[i])
