@@ -12,6 +12,12 @@
  *   - the selection of the largest |g_j| (Sec. III-D);
  *   - the fifth-order Taylor state update of Eq. 6, i.e. the five chained
  *     sparse products v_n = A v_{n-1} of Eq. 7 and the accumulation of Eq. 8.
+ * Batch plans run that step for many independent states per launch sequence
+ * (optionally through captured HIP graphs), with the angle chosen by line
+ * search and every angle of the ansatz re-optimised on request (the
+ * parameter optimisation of Sec. III-D); pools can be applied matrix-free,
+ * straight from their Pauli terms; and a pool can be split into commuting
+ * families (Sec. III-F, Alg. 1).
  *
  * Conventions shared by every entry point
  *   - Complex numbers are interleaved (re, im) pairs: VQE_C128 uses two

@@ -2,9 +2,10 @@
 //
 // The batch planner turns B independent adaptive steps into a fixed list of
 // launches over device task tables:
-//   H products with the energy reduction (one launch per lanes-per-row value),
-//   energy finalisation, pool gradients, gradient finalisation, selection,
-//   the fused pairing Taylor update and the renormalisation.
+//   H products with the energy reduction (one launch per schedule in use),
+//   the pool-gradient screen, one per-state kernel for the energy, the
+//   gradient sums and the selection, the optional line search, the fused
+//   pairing Taylor update and the renormalisation.
 // States are assigned to the 8 XCDs of the device (balanced by H bytes) and
 // every task table is interleaved so that workgroup i runs on XCD i % 8 and
 // only touches states of that XCD: each state's psi and sigma stay in one L2.
@@ -252,7 +253,7 @@ int x16_fill(vqe_batch *p, int s, const vqe_csr *H)
 }
 
 // The step is two launch sequences: the H products (sequence A) and the rest
-// (sequence B: energy finalisation, screen, selection, Taylor update,
+// (sequence B: screen, per-state finalisation and selection, Taylor update,
 // renormalisation).  `ev` (nullable) receives the phase events.
 void launch_products(vqe_batch *p, const SpmvState *states)
 {
