@@ -63,6 +63,9 @@ enum {
 
 typedef enum { VQE_C128 = 0, VQE_C64 = 1 } vqe_dtype;
 
+/* Opaque context: device, HIP stream, workspace (created by vqe_create). */
+typedef struct vqe_ctx vqe_ctx;
+
 /* vqe_csr.flags, set by csr_build_from_pauli */
 #define VQE_PAIRING 1u   /* every row holds at most one entry and col(col(r)) = r:
                             true of every fermionic single or double excitation
@@ -172,7 +175,7 @@ VQE_API int vqe_mf_owner_rows(const vqe_mf_pool *pool, int32_t j, int64_t tile_r
  * family holding none of its neighbours, else a new family; family[v]
  * (host int32[M]) and *n_families receive the result.
  */
-VQE_API int vqe_mf_noncommutation(struct vqe_ctx *ctx, const vqe_mf_pool *pool, uint8_t *adj);
+VQE_API int vqe_mf_noncommutation(vqe_ctx *ctx, const vqe_mf_pool *pool, uint8_t *adj);
 VQE_API int vqe_partition_greedy(int32_t M, const uint8_t *adj, int32_t *family,
                                  int32_t *n_families);
 
@@ -194,8 +197,6 @@ typedef struct vqe_pool {
     const vqe_csr *ops_host;
     const vqe_mf_pool *mf;
 } vqe_pool;
-
-typedef struct vqe_ctx vqe_ctx;
 
 /* ------------------------------------------------------------------ context */
 /* Create a context bound to HIP device `device` and stream `hip_stream`
@@ -308,7 +309,8 @@ typedef struct vqe_batch_item {
     void *psi;
     void *sigma;
     int32_t spmv_schedule;  /* H product schedule: 0 = default, else lanes per row
-                               (8, 16, 32, 64), optionally | VQE_SPMV_VEC4 */
+                               (8, 16, 32, 64) with the VQE_SPMV_* options of the
+                               tuning section below */
     int32_t reserved;
 } vqe_batch_item;
 
