@@ -582,7 +582,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             const size_t o_f = o_t + vqe_align(hp.tile_recs.size() * sizeof(MfRec));
             const size_t o_l = o_f + vqe_align(hp.full_recs.size() * sizeof(MfRec));
             const size_t o_d = o_l + vqe_align(hp.lists.size() * sizeof(int32_t) + 4);
-            const size_t bytes = o_d + vqe_align((size_t)hp.M * sizeof(vqe_mf_desc));
+            const size_t o_x = o_d + vqe_align((size_t)hp.M * sizeof(vqe_mf_desc));
+            const size_t bytes = o_x + vqe_align(hp.tabs.size() * sizeof(uint32_t) + 4);
             char *mem = nullptr;
             if (hipMalloc((void **)&mem, bytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -595,6 +596,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             h.full_recs = (const MfRec *)(mem + o_f);
             h.lists = (const int32_t *)(mem + o_l);
             h.desc = (const vqe_mf_desc *)(mem + o_d);
+            h.tabs = (const uint32_t *)(mem + o_x);
             h.M = hp.M;
             h.ntile = hp.ntile;
             h.tile_rows = hp.tile_rows;
@@ -607,6 +609,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
                               hipMemcpyHostToDevice);
             if (e == hipSuccess && !hp.lists.empty())
                 e = hipMemcpy(mem + o_l, hp.lists.data(), hp.lists.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice);
+            if (e == hipSuccess && !hp.tabs.empty())
+                e = hipMemcpy(mem + o_x, hp.tabs.data(), hp.tabs.size() * sizeof(uint32_t),
                               hipMemcpyHostToDevice);
             if (e == hipSuccess) {
                 std::vector<vqe_mf_desc> dd(hp.M);

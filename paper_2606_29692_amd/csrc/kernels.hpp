@@ -163,7 +163,7 @@ struct MfRec {
     uint8_t lowpos[MF_LANE_BITS];   // positions of the lowest nlow free bits
     uint8_t piv[VQE_MF_MAX_CON];
     uint8_t tbpos[MF_MAX_TB];   // tile bit positions, descending
-    uint32_t pad;
+    uint32_t tab_off;       // tile records: offset of the screen's index tables
     uint32_t beta[VQE_MF_MAX_CON];
     double v_re, v_im;
 };
@@ -173,8 +173,15 @@ struct MfTable {
     const MfRec *full_recs;   // [M]: generator j on the whole state
     const int32_t *lists;     // generator indices per (tile-bit group, tile), by descending cost
     const vqe_mf_desc *desc;  // [M]: the descriptors (support tests)
+    // screen index tables of the tile records (see MF_TAB_ITER): per record,
+    // MF_TAB_ITER entries then one per loop iteration; an entry is a
+    // compressed (tile) row index part with its sign parity in bit 31
+    const uint32_t *tabs;
     int32_t M, ntile, tile_rows, pad;
 };
+// table layout of one tile record: 64 lane parts, MF_LANE_UNROLL unroll parts,
+// then the iteration parts
+#define MF_TAB_ITER (64 + 4)
 
 // One state of the line search over the selected generator's angle.
 #define LS_ROWS_PER_BLOCK 2048
@@ -246,6 +253,7 @@ struct vqe_mf_pool;
 // screen tiles hold tile_rows rows.  Returns VQE_OK or VQE_ENOTSUP.
 struct MfHostPlan {
     std::vector<MfRec> tile_recs, full_recs;
+    std::vector<uint32_t> tabs;                    // screen index tables of tile_recs
     std::vector<int32_t> lists;                    // concatenated
     struct List { int32_t off, len, v; double work; };
     std::vector<List> list_info;

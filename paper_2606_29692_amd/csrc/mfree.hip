@@ -212,6 +212,49 @@ void make_rec(const vqe_mf_desc &d, int j, int n, uint32_t tb, uint32_t vbits, M
     *rec = r;
 }
 
+// Screen index tables of a tile record, appended to tabs: for lane l < 64 the
+// part of element e = l of the lowest free bits, for u < 4 the part of
+// element e = 64 u, then the part of every loop iteration (the higher free
+// bits, the pivots with their parities k_i and the tile's fixed bits).  An
+// entry is the part's compressed (tile) row index with |zsign & r| mod 2 in
+// bit 31.  Deposit, pivots, compression and parity are all XOR-linear, so
+// the entry of element l + 64 u in iteration t is lane[l] ^ unroll[u] ^ iter[t],
+// the row the enumeration of vqe_mf_owner_rows derives from the same record.
+void rec_tables(MfRec &rec, std::vector<uint32_t> &tabs)
+{
+    rec.tab_off = (uint32_t)tabs.size();
+    auto pivots = [&](uint32_t a, bool withk) {
+        uint32_t p = 0;
+        for (int i = 0; i < rec.ncon; i++)
+            p |= ((uint32_t)(__builtin_popcount(rec.beta[i] & a) ^ (withk ? (rec.kbits >> i) : 0u)) & 1u)
+                 << rec.piv[i];
+        return p;
+    };
+    auto entry = [&](uint32_t R) {
+        return compress_bits(R, rec.tbpos, rec.ntb) |
+               ((uint32_t)(__builtin_popcount(rec.zsign & R) & 1) << 31);
+    };
+    auto low = [&](uint32_t e) {
+        uint32_t L = 0;
+        for (int b = 0; b < rec.nlow; b++)
+            L |= ((e >> b) & 1u) << rec.lowpos[b];
+        return L ^ pivots(L, false);
+    };
+    const uint32_t nel = rec.nfree >= 0 ? 1u << rec.nlow : 0u;
+    for (uint32_t l = 0; l < 64; l++)
+        tabs.push_back(l < nel ? entry(low(l)) : 0u);
+    for (uint32_t u = 0; u < 4; u++)
+        tabs.push_back(64 * u < nel ? entry(low(64 * u)) : 0u);
+    if (rec.nfree < 0)
+        return;
+    const int n_it = 1 << (rec.nfree - rec.nlow);
+    uint32_t H = 0;
+    for (int it = 0; it < n_it; it++) {
+        tabs.push_back(entry(H ^ pivots(H, true) ^ rec.base));
+        H = ((H | ~rec.hi_mask) + 1u) & rec.hi_mask;
+    }
+}
+
 }  // namespace
 
 int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, char *err,
@@ -233,6 +276,7 @@ int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, ch
     out->tile_rows = (int32_t)std::min<int64_t>(tile_rows, dim);
     out->tile_recs.assign((size_t)M * ntile, MfRec{});
     out->full_recs.assign((size_t)M, MfRec{});
+    out->tabs.clear();
     out->lists.clear();
     out->list_info.clear();
     std::vector<uint32_t> tbs(M);
@@ -264,6 +308,7 @@ int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, ch
                 }
             MfRec &rec = out->tile_recs[(size_t)j * ntile + v];
             make_rec(d, j, n, tb, vbits, &rec);
+            rec_tables(rec, out->tabs);
             if (rec.nfree >= 0)
                 owners += (int64_t)1 << rec.nfree;
         }
@@ -410,58 +455,34 @@ template <> struct TileElem<VQE_C128> {
 // no more.
 template <int DT, bool SHIFT, bool RE_ONLY>
 __device__ __forceinline__ double2 mf_tile_sum(const typename TileElem<DT>::T *tile, const MfRec &rec,
-                                               double shift, int lane)
+                                               const uint32_t *tabs, double shift, int lane)
 {
-    const MfRegs m = load_regs(rec);
-    const uint32_t zsign = uni(rec.zsign), cx = uni(rec.cx), base = uni(rec.base);
+    // the lane, unroll and iteration parts of the row index come from the
+    // record's tables (the host derives them once per record)
+    const uint32_t cx = uni(rec.cx);
+    const int nlow = (int)uni((uint32_t)rec.nlow);
+    const uint32_t *__restrict__ t = tabs + uni(rec.tab_off);
     double sre = 0.0, sim = 0.0;
     constexpr int U = MF_LANE_UNROLL;
     uint32_t cl[U], sl[U];
     bool on[U];
-    // element e = lane + 64 u: the six lane bits per lane, the two u bits as
-    // wave-uniform corrections (deposit, pivots, compression and sign are all
-    // XOR-linear in e)
-    uint32_t L0 = 0;
-#pragma unroll
-    for (int b = 0; b < 6; b++)
-        if (b < m.nlow)
-            L0 |= (((uint32_t)lane >> b) & 1u) << m.lowpos[b];
-    const uint32_t RL0 = L0 ^ dev_pivots(L0, m, false);
-    const uint32_t cl0 = dev_compress(RL0, m);
-    const uint32_t sl0 = (uint32_t)__popc(zsign & RL0) & 1u;
+    const uint32_t lv = gmem(t)[lane];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-        on[u] = (uint32_t)lane + 64u * u < (1u << m.nlow);
-        uint32_t Lu = 0;
-        if ((u & 1) && m.nlow > 6)
-            Lu |= 1u << m.lowpos[6];
-        if ((u & 2) && m.nlow > 7)
-            Lu |= 1u << m.lowpos[7];
-        const uint32_t RU = uni(Lu ^ dev_pivots(Lu, m, false));
-        cl[u] = cl0 ^ uni(dev_compress(RU, m));
-        sl[u] = sl0 ^ ((uint32_t)__popc(zsign & RU) & 1u);
+        const uint32_t ev = lv ^ uni(gmem(t)[64 + u]);
+        cl[u] = ev & 0x7fffffffu;
+        sl[u] = ev >> 31;
+        on[u] = (uint32_t)lane + 64u * u < (1u << nlow);
     }
     const double e1 = uni(rec.ex) ? -1.0 : 1.0;
-    const uint32_t hi = uni(rec.hi_mask);
-    const int n_it = 1 << ((int)uni((uint32_t)rec.nfree) - m.nlow);
+    const int n_it = 1 << ((int)uni((uint32_t)rec.nfree) - nlow);
     for (int c0 = 0; c0 < n_it; c0 += 64) {
-        // iteration c0 + lane: deposit into the loop bits, pivots, tile index, sign
-        uint32_t chv = 0, shv = 0;
-        {
-            uint32_t H = 0, bits = (uint32_t)(c0 + lane);
-            for (uint32_t mm = hi; mm; mm &= mm - 1u) {
-                if (bits & 1u)
-                    H |= mm & (0u - mm);
-                bits >>= 1;
-            }
-            const uint32_t RH = H ^ dev_pivots(H, m, true) ^ base;
-            chv = dev_compress(RH, m);
-            shv = (uint32_t)__popc(zsign & RH) & 1u;
-        }
+        // iteration c0 + lane's part, read back per iteration with readlane
+        const uint32_t hv = c0 + lane < n_it ? gmem(t)[MF_TAB_ITER + c0 + lane] : 0u;
         const int nin = n_it - c0 < 64 ? n_it - c0 : 64;
         for (int i = 0; i < nin; i++) {
-            const uint32_t ch = __builtin_amdgcn_readlane(chv, i);
-            const uint32_t sh = __builtin_amdgcn_readlane(shv, i);
+            const uint32_t hi = __builtin_amdgcn_readlane(hv, i);
+            const uint32_t ch = hi & 0x7fffffffu, sh = hi >> 31;
             double2 pr[U], sr[U], pc[U], sc[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
@@ -560,11 +581,11 @@ k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tas
             const bool shifted = st.shift != 0.0 && !rec.antiherm;
             if (rec.v_im == 0.0 && !shifted) {
                 // a real generator value: only Re(S) enters (v_re Re(S) - 0 Im(S))
-                const double2 S = mf_tile_sum<DT, false, true>(tile, rec, 0.0, lane);
+                const double2 S = mf_tile_sum<DT, false, true>(tile, rec, tb.tabs, 0.0, lane);
                 part = rec.v_re * group_sum<64>(S.x) - rec.v_im * 0.0;
             } else {
-                const double2 S = shifted ? mf_tile_sum<DT, true, false>(tile, rec, st.shift, lane)
-                                          : mf_tile_sum<DT, false, false>(tile, rec, 0.0, lane);
+                const double2 S = shifted ? mf_tile_sum<DT, true, false>(tile, rec, tb.tabs, st.shift, lane)
+                                          : mf_tile_sum<DT, false, false>(tile, rec, tb.tabs, 0.0, lane);
                 const double re = group_sum<64>(S.x), im = group_sum<64>(S.y);
                 part = rec.v_re * re - rec.v_im * im;
             }
