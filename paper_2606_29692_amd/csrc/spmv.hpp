@@ -1,0 +1,56 @@
+// Descriptors and constants of the H product (the kernels of spmv.hip and
+// the batch planner).
+#pragma once
+
+#include "common.hpp"
+
+// True when a batch slot is switched off for this step (uniform per workgroup).
+#define VQE_SKIP(st) ((st).active && !*gmem((st).active))
+
+// Rows per wave pass handled by one sub-group, and passes per workgroup.
+#define SPMV_RPT 2
+
+// A schedule is the lanes per row (8, 16, 32, 64), optionally | VQE_SPMV_VEC4
+// or | VQE_SPMV_LDS.  The LDS schedule gives each workgroup SPMV_LDS_ROWS rows.
+#ifndef SPMV_LDS_ROWS
+#define SPMV_LDS_ROWS 2048
+#endif
+// state bytes that fit next to the staged row pointers
+#define SPMV_LDS_MAX_BYTES (147 * 1024)
+__host__ __device__ constexpr int spmv_rows_per_block(int sched)
+{
+    return 4 * (VQE_WAVE / (sched & 0xff)) * SPMV_RPT;
+}
+
+// One state of an H product with the energy reduction.
+struct SpmvState {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const void *val;
+    const void *psi;
+    void *sigma;
+    double *partials;     // [nblocks * 3]
+    double *energy_out;   // [3]
+    int64_t dim;
+    int64_t nnz;
+    double shift;
+    const int32_t *active;     // batch slot flag (nullable): 0 = skip this state
+    int32_t nblocks;
+    int32_t lanes;
+    // column-tiled schedule (states larger than LDS): per tile t the entries of
+    // row r with columns in tile t are [tptr[t*dim + r], tptr[(t+1)*dim + r])
+    const int32_t *tptr;       // [(ntiles + 1) * dim]
+    double *tile_part;         // [ntiles * dim] FP64 complex partial rows
+    int32_t ntiles;            // 0: not tiled
+    int32_t tile_cols;
+    // 16-bit column form (schedules with VQE_SPMV_X16): col16[k] = col[k] ^ row
+    const uint16_t *col16;
+};
+
+// Column-tiled H product: tile width (state elements staged in LDS per pass)
+// and rows per workgroup of the tile-sum kernel.
+#define VQE_SPMV_TILED 0x1000
+// largest dimension whose column XOR row fits 16 bits
+#define SPMV_X16_MAX_DIM 65536
+#define SPMV_TILE_BYTES (128 * 1024)
+#define SPMV_SUM_ROWS 1024
