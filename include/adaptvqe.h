@@ -329,9 +329,12 @@ typedef struct vqe_batch_io {
 #define VQE_STEP_RENORM 1u      /* renormalise every state after its update */
 #define VQE_STEP_FORCED 2u      /* take k from k_io instead of selecting */
 #define VQE_STEP_NO_UPDATE 4u   /* screen only: energy, gradients, selection */
-#define VQE_STEP_GRAPH 8u       /* launch through captured HIP graphs: one for the
-                                   H products, one per flag set for the rest
-                                   (captured on first use, then replayed) */
+#define VQE_STEP_GRAPH 8u       /* launch through captured HIP graphs, captured on
+                                   first use and then replayed: one per flag set
+                                   holding the whole step (vqe_batch_step), or one
+                                   for the H products and one per flag set for the
+                                   rest, with the events between them
+                                   (vqe_batch_step_timed) */
 #define VQE_STEP_LINESEARCH 16u /* choose each state's angle by line search before
                                    the update (see vqe_batch_set_line_search); the
                                    chosen angle is written to theta */

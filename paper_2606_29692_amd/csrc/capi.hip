@@ -167,6 +167,8 @@ struct vqe_batch {
     std::vector<int64_t> dims;
     hipGraphExec_t exec_spmv = nullptr;
     hipGraph_t graph_spmv = nullptr;
+    hipGraphExec_t exec_all[16] = {};  // whole-step graphs by flag set (steps without events)
+    hipGraph_t graph_all[16] = {};
     // line search (vqe_batch_set_line_search)
     std::vector<PairTable> tables_host;            // CSR mode: pair tables (host copy)
     std::vector<const vqe_mf_pool *> mf_host;      // mf mode: pool of each table
@@ -362,14 +364,25 @@ template <class F> int capture(vqe_ctx *ctx, F fn, hipGraph_t *g_out, hipGraphEx
     return VQE_OK;
 }
 
-// Graph launch of the step: sequence A, then sequence B for this flag set
-// (each captured on first use).  Events 0 and 1 bracket sequence A, event 2
-// follows sequence B.
+// Graph launch of the step (graphs captured on first use).  Without events,
+// one graph holds the whole step for this flag set; with events, sequence A
+// and sequence B are separate graphs: events 0 and 1 bracket sequence A,
+// event 2 follows sequence B.
 int graph_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
 {
     vqe_ctx *ctx = p->ctx;
     const unsigned key = (flags & 7u) | ((flags & VQE_STEP_LINESEARCH) ? 8u : 0u);
     int rc;
+    if (!ev) {
+        if (!p->exec_all[key] &&
+            (rc = capture(ctx, [&] {
+                 const int r = enqueue_spmv(p);
+                 return r ? r : enqueue_rest(p, flags, nullptr);
+             }, &p->graph_all[key], &p->exec_all[key])))
+            return rc;
+        VQE_HIP(ctx, hipGraphLaunch(p->exec_all[key], ctx->stream));
+        return VQE_OK;
+    }
     if (!p->exec_spmv && (rc = capture(ctx, [&] { return enqueue_spmv(p); }, &p->graph_spmv,
                                        &p->exec_spmv)))
         return rc;
@@ -989,6 +1002,12 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
             (void)hipGraphExecDestroy(p->exec[i]);
         if (p->graph[i])
             (void)hipGraphDestroy(p->graph[i]);
+    }
+    for (int i = 0; i < 16; i++) {
+        if (p->exec_all[i])
+            (void)hipGraphExecDestroy(p->exec_all[i]);
+        if (p->graph_all[i])
+            (void)hipGraphDestroy(p->graph_all[i]);
     }
     if (p->exec_spmv)
         (void)hipGraphExecDestroy(p->exec_spmv);
