@@ -228,6 +228,33 @@ __device__ __forceinline__ void lds_group_load(const int32_t *col, const typenam
 // Gathers from the LDS copy of the state and FP64 multiply-accumulate.  All
 // LDS reads issue back to back behind a single wait; masked entries read the
 // zero element.
+__device__ __forceinline__ float2 stage_load(const float2 *p, int64_t i) { return ldg(p, i); }
+__device__ __forceinline__ double2 stage_load(const double2 *p, int64_t i) { return ldg(p, i); }
+__device__ __forceinline__ int32_t stage_load(const int32_t *p, int64_t i) { return gmem(p)[i]; }
+
+// Copy n elements from global memory to LDS with the workgroup's 1024
+// threads: each thread issues SB loads before the batch's LDS writes, so it
+// waits for memory once per batch instead of once per element.
+template <int SB, typename T>
+__device__ __forceinline__ void stage_lds(T *dst, const T *src, int64_t n, int tid)
+{
+    for (int64_t i0 = tid; i0 < n; i0 += 1024 * SB) {
+        T v[SB];
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const int64_t i = i0 + 1024 * (int64_t)u;
+            if (i < n)
+                v[u] = stage_load(src, i);
+        }
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const int64_t i = i0 + 1024 * (int64_t)u;
+            if (i < n)
+                dst[i] = v[u];
+        }
+    }
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], const T v[N],
                                                double &are, double &aim)
@@ -278,12 +305,10 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
     const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
     // the state, one zero element (index dim), then the workgroup's row pointers
     int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)(dim + 1) * sizeof(T));
-    for (int64_t i = tid; i < dim; i += 1024)
-        s_x[i] = ldg(psi, i);
+    stage_lds<8>(s_x, psi, dim, tid);
     if (tid == 0)
         s_x[dim] = T{};
-    for (int64_t i = tid; i <= r1 - r0; i += 1024)
-        s_rp[i] = gmem(st.rowptr)[r0 + i];
+    stage_lds<4>(s_rp, st.rowptr + r0, r1 - r0 + 1, tid);
     __syncthreads();
 
     constexpr int G = VQE_WAVE / L;
@@ -426,12 +451,10 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
     const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
     int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)(dim + 1) * sizeof(T));
-    for (int64_t i = tid; i < dim; i += 1024)
-        s_x[i] = ldg(psi, i);
+    stage_lds<8>(s_x, psi, dim, tid);
     if (tid == 0)
         s_x[dim] = T{};
-    for (int64_t i = tid; i <= r1 - r0; i += 1024)
-        s_rp[i] = gmem(st.rowptr)[r0 + i];
+    stage_lds<4>(s_rp, st.rowptr + r0, r1 - r0 + 1, tid);
     __syncthreads();
 
     constexpr int G = VQE_WAVE / L;
@@ -606,14 +629,11 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     // the tile, one zero element (index tc), then the block's tile bounds
     int32_t *s_k0 = reinterpret_cast<int32_t *>(smem + (size_t)(tc + 1) * sizeof(T));
     int32_t *s_k1 = s_k0 + SPMV_LDS_ROWS;
-    for (int i = tid; i < tc; i += 1024)
-        s_x[i] = ldg(psi, (int64_t)c_lo + i);
+    stage_lds<8>(s_x, psi + c_lo, (int64_t)tc, tid);
     if (tid == 0)
         s_x[tc] = T{};
-    for (int64_t i = tid; i < r1 - r0; i += 1024) {
-        s_k0[i] = gmem(st.tptr)[(int64_t)t * dim + r0 + i];
-        s_k1[i] = gmem(st.tptr)[(int64_t)(t + 1) * dim + r0 + i];
-    }
+    stage_lds<2>(s_k0, st.tptr + (int64_t)t * dim + r0, r1 - r0, tid);
+    stage_lds<2>(s_k1, st.tptr + (int64_t)(t + 1) * dim + r0, r1 - r0, tid);
     __syncthreads();
 
     constexpr int G = VQE_WAVE / L;
