@@ -71,6 +71,13 @@ typedef struct vqe_ctx vqe_ctx;
                             true of every fermionic single or double excitation
                             generator under JW or BK.  Enables the fused
                             register-resident Taylor kernel. */
+#define VQE_REAL 2u      /* every entry is real: each term's c_t i^{|x_t & z_t|}
+                            is real (Eq. 3 with the real coefficients of a
+                            molecular Hamiltonian: strings with an even number
+                            of Y factors).  Set from the terms, exactly; a
+                            caller that sets it on a CSR of its own asserts
+                            that every imaginary part is zero.  Enables
+                            VQE_SPMV_REAL. */
 
 /*
  * A square CSR operator of dimension dim = 2^n_qubits.  Device arrays:
@@ -454,6 +461,20 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * larger-than-LDS states reads them too.  States with more than 2^16 rows
  * use the schedule without it; single calls (vqe_time_spmv) ignore it. */
 #define VQE_SPMV_X16 0x4000
+/* VQE_SPMV_REAL (with VQE_SPMV_X16; batch plans only): for an H flagged
+ * VQE_REAL the product streams the real parts of its values, which the plan
+ * copies from the CSR once (4 bytes per entry in FP32 storage, 8 in FP64;
+ * plan-owned, rebuilt by vqe_batch_rebind): 6 instead of 10 bytes per entry
+ * in FP32 storage.  For a state that fits LDS the plan lays the codes and
+ * values out with every row padded to a multiple of four entries (zero
+ * values; at most 3 pads per row, plus dim + 1 int32 row pointers), so the
+ * product needs no row masks.  Dropped for an H without the flag and
+ * wherever the codes are dropped; single calls (vqe_time_spmv) ignore it.
+ * The row sums are the same FP64 sums of exact-in-FP64 products as without
+ * it, grouped over the lanes differently in the padded layout: results agree
+ * to the rounding of FP64 sums (bit for bit in the column-tiled form with
+ * FP32 storage). */
+#define VQE_SPMV_REAL 0x8000
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given
  * schedule: `reps` back-to-back launches bracketed by HIP events on the

@@ -113,13 +113,19 @@ def make_batch(ctx: B.Context, systems: list, schedules=None) -> B.BatchPlan:
 def bytes_per_step(systems: list) -> dict:
     """Algorithmic HBM bytes of one adaptive step (canonical CSR, each vector
     once): the H product and the pool screen (pool CSR counted once per
-    distinct pool), and the Taylor update of a single-excitation generator."""
+    distinct pool), and the Taylor update of a single-excitation generator.
+    A CSR's values count in the operator's own field: real values (half the
+    complex element) for an operator whose entries are all real."""
     out = {"h_spmv": 0, "pool_screen": 0, "taylor": 0}
     seen = set()
+
+    def vsize(op):
+        return op.val.element_size() // (2 if op.real else 1)
+
     for s in systems:
         dim = s.H.dim
         sx = s.psi.element_size()
-        sv = s.H.val.element_size()
+        sv = vsize(s.H)
         out["h_spmv"] += 4 * (dim + 1) + s.H.nnz * (4 + sv) + 2 * dim * sx
         out["pool_screen"] += 2 * dim * sx + 8 * s.pool.M
         if isinstance(s.pool, B.MatrixFreePool):
@@ -130,10 +136,9 @@ def bytes_per_step(systems: list) -> dict:
         pid = id(s.pool)
         if pid not in seen:
             seen.add(pid)
-            out["pool_screen"] += sum(4 * (dim + 1) + o.nnz * (4 + o.val.element_size())
-                                      for o in s.pool.ops)
-        nnz_single = max(o.nnz for o in s.pool.ops)
-        out["taylor"] += 4 * (dim + 1) + nnz_single * (4 + sv) + 2 * dim * sx
+            out["pool_screen"] += sum(4 * (dim + 1) + o.nnz * (4 + vsize(o)) for o in s.pool.ops)
+        single = max(s.pool.ops, key=lambda o: o.nnz)
+        out["taylor"] += 4 * (dim + 1) + single.nnz * (4 + vsize(single)) + 2 * dim * sx
     return out
 
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libadaptvqe.so")
 VQE_OK, VQE_EINVAL, VQE_ESIZE, VQE_ENOMEM, VQE_EHIP, VQE_ENOTSUP = 0, -1, -2, -3, -4, -5
 VQE_C128, VQE_C64 = 0, 1
 VQE_PAIRING = 1
+VQE_REAL = 2
 VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_NO_UPDATE, VQE_STEP_GRAPH = 1, 2, 4, 8
 VQE_STEP_LINESEARCH = 16
 VQE_SPMV_VEC4 = 0x100
@@ -26,6 +27,7 @@ VQE_SPMV_LDS = 0x200
 VQE_SPMV_DEEP = 0x400
 VQE_SPMV_PREFETCH = 0x800
 VQE_SPMV_X16 = 0x4000
+VQE_SPMV_REAL = 0x8000
 REL_TIE = 1e-6
 
 DTYPES = {"c128": VQE_C128, "c64": VQE_C64}
@@ -209,6 +211,11 @@ class DeviceCSR:
     @property
     def pairing(self) -> bool:
         return bool(self.desc.flags & VQE_PAIRING)
+
+    @property
+    def real(self) -> bool:
+        """Every entry is real (set by the builder from the terms)."""
+        return bool(self.desc.flags & VQE_REAL)
 
     @property
     def diag_shift(self) -> float:

@@ -185,9 +185,11 @@ struct vqe_batch {
     SpmvState *d_ls1 = nullptr, *d_ls2 = nullptr;
     int2 *d_ls_tasks = nullptr;
     unsigned n_ls_tasks = 0;
-    // 16-bit column codes of slots whose schedule reads them (VQE_SPMV_X16)
-    std::vector<uint16_t *> col16;
-    std::vector<int64_t> col16_cap;
+    // per slot, the plan-owned forms of H its schedule reads: 16-bit column
+    // codes (VQE_SPMV_X16), real parts of the values (VQE_SPMV_REAL) and the
+    // padded layout's row pointers; capacities in bytes
+    std::vector<void *> col16, vre, prow;
+    std::vector<int64_t> col16_cap, vre_cap, prow_cap;
     // re-optimisation (vqe_batch_reoptimize): descriptors, three product
     // descriptor arrays, tasks, then per slot nine vectors and partials
     char *ro_mem = nullptr;
@@ -228,29 +230,62 @@ std::vector<T> interleave(const std::vector<std::vector<T>> &per, const T &pad)
     return out;
 }
 
-// (Re)build slot s's 16-bit column codes for H: reuse the slot's buffer when
-// it is large enough, and point the slot's host descriptor at it (the caller
-// uploads the descriptor).
-int x16_fill(vqe_batch *p, int s, const vqe_csr *H)
+// Grow one of slot s's plan-owned buffers to at least `need` bytes (the
+// caller rebuilds the contents).
+int grow(vqe_batch *p, void **buf, int64_t *cap, int64_t need, const char *what, int s)
 {
     vqe_ctx *ctx = p->ctx;
-    const int64_t need = H->nnz > 0 ? H->nnz : 1;
-    if (p->col16_cap[s] < need) {
-        if (p->col16[s]) {
-            VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            (void)hipFree(p->col16[s]);
-            p->col16[s] = nullptr;
-            p->col16_cap[s] = 0;
-        }
-        if (hipMalloc((void **)&p->col16[s], (size_t)need * sizeof(uint16_t)) != hipSuccess) {
-            (void)hipGetLastError();
-            p->col16[s] = nullptr;
-            return vqe_fail(ctx, VQE_ENOMEM, "column codes of slot %d: allocation failed", s);
-        }
-        p->col16_cap[s] = need;
+    if (*cap >= need)
+        return VQE_OK;
+    if (*buf) {
+        VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
     }
-    launch_col_xor16(H, p->col16[s], ctx->stream);
-    reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s].col16 = p->col16[s];
+    if (hipMalloc(buf, (size_t)need) != hipSuccess) {
+        (void)hipGetLastError();
+        *buf = nullptr;
+        return vqe_fail(ctx, VQE_ENOMEM, "%s of slot %d: allocation failed", what, s);
+    }
+    *cap = need;
+    return VQE_OK;
+}
+
+// (Re)build slot s's plan-owned forms of H for its schedule -- the 16-bit
+// column codes, and with VQE_SPMV_REAL the real parts of the values, in the
+// padded layout unless the slot is column-tiled -- and point the slot's host
+// descriptor at them (the caller uploads the descriptor).
+int codes_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
+{
+    vqe_ctx *ctx = p->ctx;
+    SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
+    const int64_t rb = (int64_t)vqe_elem_bytes(H->dtype) / 2;
+    int rc;
+    if ((sched & VQE_SPMV_REAL) && !(sched & VQE_SPMV_TILED)) {
+        const int64_t cap = H->nnz + 3 * H->dim + 4;
+        if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], cap * 2, "column codes", s)) ||
+            (rc = grow(p, &p->vre[s], &p->vre_cap[s], cap * rb, "real values", s)) ||
+            (rc = grow(p, &p->prow[s], &p->prow_cap[s], (H->dim + 1) * 4, "row pointers", s)))
+            return rc;
+        launch_pad_layout(H, (int32_t *)p->prow[s], (uint16_t *)p->col16[s], p->vre[s], ctx->stream);
+        st.col16 = (const uint16_t *)p->col16[s];
+        st.vre = p->vre[s];
+        st.prow = (const int32_t *)p->prow[s];
+        st.cap = cap;
+        return VQE_OK;
+    }
+    const int64_t nnz = H->nnz > 0 ? H->nnz : 1;
+    if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], nnz * 2, "column codes", s)))
+        return rc;
+    launch_col_xor16(H, (uint16_t *)p->col16[s], ctx->stream);
+    st.col16 = (const uint16_t *)p->col16[s];
+    if (sched & VQE_SPMV_REAL) {
+        if ((rc = grow(p, &p->vre[s], &p->vre_cap[s], nnz * rb, "real values", s)))
+            return rc;
+        launch_val_real(H, p->vre[s], ctx->stream);
+        st.vre = p->vre[s];
+    }
     return VQE_OK;
 }
 
@@ -847,14 +882,16 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     }
     p->image = std::move(A.host);
     // 16-bit column codes for the slots whose schedule reads them
-    p->col16.assign(B, nullptr);
-    p->col16_cap.assign(B, 0);
+    for (auto *v : {&p->col16, &p->vre, &p->prow})
+        v->assign(B, nullptr);
+    for (auto *v : {&p->col16_cap, &p->vre_cap, &p->prow_cap})
+        v->assign(B, 0);
     bool any16 = false;
     for (int s = 0; s < B; s++) {
         if (!(lanes[s] & VQE_SPMV_X16))
             continue;
         any16 = true;
-        const int rc16 = x16_fill(p, s, items[s].H);
+        const int rc16 = codes_fill(p, s, items[s].H, lanes[s]);
         if (rc16) {
             vqe_batch_destroy(p);
             return rc16;
@@ -925,7 +962,7 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
     TaylorState *ts = reinterpret_cast<TaylorState *>(p->image.data() + p->o_tay) + slot;
     ts->psi = it->psi;
     if (sched & VQE_SPMV_X16) {
-        rc = x16_fill(p, slot, it->H);
+        rc = codes_fill(p, slot, it->H, sched);
         if (rc)
             return rc;
     }
@@ -1019,9 +1056,10 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
         (void)hipFree(p->ls_mem);
     if (p->ro_mem)
         (void)hipFree(p->ro_mem);
-    for (uint16_t *c : p->col16)
-        if (c)
-            (void)hipFree(c);
+    for (const auto *v : {&p->col16, &p->vre, &p->prow})
+        for (void *m : *v)
+            if (m)
+                (void)hipFree(m);
     for (void *m : p->table_mem)
         (void)hipFree(m);
     delete p;
@@ -1033,8 +1071,9 @@ extern "C" int64_t vqe_batch_workspace_bytes(const vqe_batch *p)
     if (!p)
         return -1;
     int64_t c16 = 0;
-    for (int64_t c : p->col16_cap)
-        c16 += c * (int64_t)sizeof(uint16_t);
+    for (const auto *v : {&p->col16_cap, &p->vre_cap, &p->prow_cap})
+        for (int64_t c : *v)
+            c16 += c;
     return (int64_t)(p->dmem_bytes + p->table_bytes + p->ls_bytes + p->ro_bytes) + c16;
 }
 

@@ -491,7 +491,13 @@ extern "C" int csr_build_from_pauli(vqe_ctx *ctx, int32_t n_qubits, int64_t n_te
         inout->dim = dim;
         inout->nnz = nnz;
         inout->diag_shift = diag_shift;
-        inout->flags = violations == 0 ? VQE_PAIRING : 0u;
+        // every entry is real when every term's c_t i^{|x_t & z_t|} is real
+        bool real = true;
+        for (int64_t t = 0; t < T && real; t++) {
+            const int k = __builtin_popcountll(hx[t] & hz[t]) & 3;
+            real = (k & 1) ? hc[2 * t] == 0.0 : hc[2 * t + 1] == 0.0;
+        }
+        inout->flags = (violations == 0 ? VQE_PAIRING : 0u) | (real ? VQE_REAL : 0u);
         if (nnz_out)
             *nnz_out = nnz;
         return VQE_OK;

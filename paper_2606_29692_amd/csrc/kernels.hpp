@@ -249,6 +249,12 @@ int32_t spmv_tile_cols(int dtype);
 int64_t spmv_blocks(int64_t dim, int sched);
 // col16[k] = col[k] ^ row(k) for every entry of H (dim <= SPMV_X16_MAX_DIM)
 void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s);
+// out[k] = Re val[k] (FP32 or FP64 by H's dtype) for every entry of H
+void launch_val_real(const vqe_csr *H, void *out, hipStream_t s);
+// padded layout of H (dim <= SPMV_X16_MAX_DIM): prow[dim + 1], the 16-bit
+// codes and the real parts of the values with every row rounded up to a
+// multiple of four entries (room for nnz + 3 dim entries)
+void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vre, hipStream_t s);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 
 void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, unsigned grid,

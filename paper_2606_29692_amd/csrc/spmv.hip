@@ -255,8 +255,37 @@ __device__ __forceinline__ void stage_lds(T *dst, const T *src, int64_t n, int t
     }
 }
 
-template <typename T, int N>
-__device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], const T v[N],
+// One entry's product a * x added to (are, aim) in FP64: a complex value, or
+// the real part alone when the operator is stored with real values.
+template <typename T>
+__device__ __forceinline__ void entry_fma(const float2 a, const T x, double &are, double &aim)
+{
+    const double ar = (double)a.x, ai = (double)a.y, xr = (double)x.x, xi = (double)x.y;
+    are += ar * xr - ai * xi;
+    aim += ar * xi + ai * xr;
+}
+template <typename T>
+__device__ __forceinline__ void entry_fma(const double2 a, const T x, double &are, double &aim)
+{
+    const double ar = a.x, ai = a.y, xr = (double)x.x, xi = (double)x.y;
+    are += ar * xr - ai * xi;
+    aim += ar * xi + ai * xr;
+}
+template <typename T>
+__device__ __forceinline__ void entry_fma(const float a, const T x, double &are, double &aim)
+{
+    are += (double)a * (double)x.x;
+    aim += (double)a * (double)x.y;
+}
+template <typename T>
+__device__ __forceinline__ void entry_fma(const double a, const T x, double &are, double &aim)
+{
+    are += a * (double)x.x;
+    aim += a * (double)x.y;
+}
+
+template <typename T, typename V, int N>
+__device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], const V v[N],
                                                double &are, double &aim)
 {
     T xs[N];
@@ -264,12 +293,8 @@ __device__ __forceinline__ void lds_gather_fma(const T *s_x, const int c[N], con
     for (int u = 0; u < N; u++)
         xs[u] = s_x[c[u]];
 #pragma unroll
-    for (int u = 0; u < N; u++) {
-        const double ar = (double)v[u].x, ai = (double)v[u].y;
-        const double xr = (double)xs[u].x, xi = (double)xs[u].y;
-        are += ar * xr - ai * xi;
-        aim += ar * xi + ai * xr;
-    }
+    for (int u = 0; u < N; u++)
+        entry_fma(v[u], xs[u], are, aim);
 }
 
 // The whole state vector staged in LDS (one 128 KB copy for 14 qubits in
@@ -330,7 +355,7 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
                 for (int u = 0; u < U; u++)
                     lds_group_load<DT>(col, val, k + u * 4 * L, k0, k1, nnz, zc, c + 4 * u,
                                        v + 4 * u);
-                lds_gather_fma<T, U * 4>(s_x, c, v, are, aim);
+                lds_gather_fma<T, T, U * 4>(s_x, c, v, are, aim);
             }
         }
         are = group_sum<L>(are);
@@ -367,8 +392,20 @@ k_spmv_lds(SpmvState single, const SpmvState *__restrict__ states, const int2 *_
 #define VQE_BUF_WORD3 0x00020000
 #define VQE_BUF_OOB 0x80000000u
 
-template <int DT> struct BufVal;
-template <> struct BufVal<VQE_C64> {
+// Value streamed per entry: the complex value, or its real part alone (RV)
+// when the plan stores the operator's real parts (an operator whose entries
+// are all real).
+template <int DT, bool RV> struct ValOf { using T = typename Elem<DT>::T; };
+template <> struct ValOf<VQE_C64, true> { using T = float; };
+template <> struct ValOf<VQE_C128, true> { using T = double; };
+
+__device__ __forceinline__ float2 ldv(const float2 *p, int64_t i) { return ldg(p, i); }
+__device__ __forceinline__ double2 ldv(const double2 *p, int64_t i) { return ldg(p, i); }
+__device__ __forceinline__ float ldv(const float *p, int64_t i) { return gmem(p)[i]; }
+__device__ __forceinline__ double ldv(const double *p, int64_t i) { return gmem(p)[i]; }
+
+template <int DT, bool RV> struct BufVal;
+template <> struct BufVal<VQE_C64, false> {
     // four consecutive complex64 values: two 16-byte loads
     static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off, float2 v[4])
     {
@@ -381,7 +418,7 @@ template <> struct BufVal<VQE_C64> {
         v[3] = make_float2(b.z, b.w);
     }
 };
-template <> struct BufVal<VQE_C128> {
+template <> struct BufVal<VQE_C128, false> {
     static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v[4])
     {
         typedef double v2d __attribute__((ext_vector_type(2)));
@@ -392,6 +429,42 @@ template <> struct BufVal<VQE_C128> {
         }
     }
 };
+template <> struct BufVal<VQE_C64, true> {
+    // four consecutive real FP32 values: one 16-byte load
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off, float v[4])
+    {
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        const v4f a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = a.z;
+        v[3] = a.w;
+    }
+};
+template <> struct BufVal<VQE_C128, true> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off, double v[4])
+    {
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        const v2d a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const v2d b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = b.x;
+        v[3] = b.y;
+    }
+};
+
+// Real parts of an operator's values (for operators whose entries are all real).
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_val_real(const void *__restrict__ val, void *__restrict__ out, int64_t nnz)
+{
+    using T = typename Elem<DT>::T;
+    using R = typename ValOf<DT, true>::T;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < nnz)
+        reinterpret_cast<R *>(out)[k] = ldg(reinterpret_cast<const T *>(val), k).x;
+}
 
 // Column codes of the 16-bit form: one wave per row, lanes over its entries.
 __global__ void __launch_bounds__(256)
@@ -406,6 +479,60 @@ k_col_xor16(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
         col16[k] = (uint16_t)((uint32_t)col[k] ^ (uint32_t)r);
 }
 
+// Row pointers of the padded layout, in which every row's length is rounded up
+// to a multiple of four.  One workgroup: each thread takes a contiguous run of
+// rows, the workgroup scans the run totals, and each thread writes its run.
+__global__ void __launch_bounds__(1024)
+k_pad_rowptr(const int32_t *__restrict__ rowptr, int32_t *__restrict__ prow, int64_t dim)
+{
+    __shared__ int64_t s_sum[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (dim + 1023) / 1024;
+    const int64_t a = (int64_t)tid * per < dim ? (int64_t)tid * per : dim;
+    const int64_t b = a + per < dim ? a + per : dim;
+    int64_t tot = 0;
+    for (int64_t r = a; r < b; r++)
+        tot += (rowptr[r + 1] - rowptr[r] + 3) & ~3;
+    s_sum[tid] = tot;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = tid >= off ? s_sum[tid - off] : 0;
+        __syncthreads();
+        s_sum[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = s_sum[tid] - tot;
+    for (int64_t r = a; r < b; r++) {
+        prow[r] = (int32_t)run;
+        run += (rowptr[r + 1] - rowptr[r] + 3) & ~3;
+    }
+    if (tid == 1023)
+        prow[dim] = (int32_t)s_sum[1023];
+}
+
+// Column codes and real values in the padded layout, one wave per row; a
+// row's pad entries repeat its last column with the value zero.
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+           const void *__restrict__ val, const int32_t *__restrict__ prow,
+           uint16_t *__restrict__ code, void *__restrict__ vre, int64_t dim)
+{
+    using T = typename Elem<DT>::T;
+    using R = typename ValOf<DT, true>::T;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= dim)
+        return;
+    const int32_t k0 = rowptr[r], len = rowptr[r + 1] - k0;
+    const int32_t p0 = prow[r], plen = prow[r + 1] - p0;
+    for (int32_t j = (int32_t)(threadIdx.x & 63); j < plen; j += 64) {
+        const int32_t k = k0 + (j < len ? j : len - 1);
+        code[p0 + j] = (uint16_t)((uint32_t)col[k] ^ (uint32_t)r);
+        reinterpret_cast<R *>(vre)[p0 + j] =
+            j < len ? (R)ldg(reinterpret_cast<const T *>(val), k).x : (R)0;
+    }
+}
+
 // Pipelined variant of the LDS schedule.  A sub-group of L lanes covers a row
 // of up to U * 4 * L = 256 entries in one pass and keeps the loads of its next
 // D rows in flight: after a row's products it refills that row's registers
@@ -418,8 +545,13 @@ k_col_xor16(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
 // longer than one pass finish with further passes, and the last nnz % 4
 // entries of the arrays are added entry by entry.  With X16 the column of
 // entry k of row r is read as the 16-bit code col16[k] = col[k] ^ r (8 bytes
-// per group of four instead of 16), for states of at most 2^16 rows.
-template <int DT, int L, int D, bool BATCH, bool X16>
+// per group of four instead of 16), for states of at most 2^16 rows.  With
+// RV (operators whose entries are all real) the codes and values are the
+// plan's padded layout: each row starts at a multiple of four and is padded
+// with zero values to whole groups (row pointers st.prow), so no entry needs
+// a row mask and there is no tail; the values are the real parts, 4 instead
+// of 8 bytes per entry in FP32 storage.
+template <int DT, int L, int D, bool BATCH, bool X16, bool RV>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
               const int2 *__restrict__ tasks)
@@ -442,7 +574,8 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     constexpr int U = 64 / L;
     constexpr int W = U * 4;                 // entries per lane per pass
     constexpr int PASS = W * L;              // entries per sub-group per pass
-    constexpr unsigned EB = sizeof(T);
+    using V = typename ValOf<DT, RV>::T;
+    constexpr unsigned EB = sizeof(V);
     extern __shared__ unsigned char smem[];
     T *s_x = reinterpret_cast<T *>(smem);
     const int tid = threadIdx.x;
@@ -454,23 +587,25 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     stage_lds<8>(s_x, psi, dim, tid);
     if (tid == 0)
         s_x[dim] = T{};
-    stage_lds<4>(s_rp, st.rowptr + r0, r1 - r0 + 1, tid);
+    stage_lds<4>(s_rp, (RV ? st.prow : st.rowptr) + r0, r1 - r0 + 1, tid);
     __syncthreads();
 
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
-    const int nnz = (int)st.nnz, zc = (int)dim;
-    const int whole = nnz & ~3;              // groups starting below this are whole
+    // the padded layout (RV) holds whole groups only, up to st.cap entries
+    const int nnz = (int)(RV ? st.cap : st.nnz), zc = (int)dim;
+    const int whole = RV ? 0x7fffffff : nnz & ~3;   // groups starting below this are whole
     const __amdgpu_buffer_rsrc_t rc =
         X16 ? __builtin_amdgcn_make_buffer_rsrc((void *)st.col16, (short)0, nnz * 2, VQE_BUF_WORD3)
             : __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
     const __amdgpu_buffer_rsrc_t rv =
-        __builtin_amdgcn_make_buffer_rsrc((void *)st.val, (short)0, (int)(nnz * EB), VQE_BUF_WORD3);
+        __builtin_amdgcn_make_buffer_rsrc((void *)(RV ? st.vre : st.val), (short)0, (int)(nnz * EB),
+                                          VQE_BUF_WORD3);
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
 
     // issue the loads of the pass starting at group kb of a row [k0, k1)
-    auto issue = [&](int kb, int k1, int c[W], T v[W]) {
+    auto issue = [&](int kb, int k1, int c[W], V v[W]) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int k = kb + u * 4 * L;
@@ -490,12 +625,12 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
                 c[4 * u + 2] = c4.z;
                 c[4 * u + 3] = c4.w;
             }
-            BufVal<DT>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
+            BufVal<DT, RV>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
         }
     };
     // products of one pass of row r; entries outside [k0, k1) read the zero
     // element
-    auto consume = [&](int64_t r, int kb, int k0, int k1, const int c[W], const T v[W],
+    auto consume = [&](int64_t r, int kb, int k0, int k1, const int c[W], const V v[W],
                        double &are, double &aim) {
         int cm[W];
         const unsigned len = (unsigned)(k1 - k0);
@@ -506,9 +641,9 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
             for (int q = 0; q < 4; q++) {
                 const int k = kb + u * 4 * L + q;
                 const int col = X16 ? (rx ^ c[4 * u + q]) : c[4 * u + q];
-                cm[4 * u + q] = (unsigned)(k - k0) < len ? col : zc;
+                cm[4 * u + q] = RV || (unsigned)(k - k0) < len ? col : zc;
             }
-        lds_gather_fma<T, W>(s_x, cm, v, are, aim);
+        lds_gather_fma<T, V, W>(s_x, cm, v, are, aim);
     };
     auto row_bounds = [&](int64_t r, int &k0, int &k1) {
         if (r < r1) {
@@ -522,7 +657,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         // further passes of a long row
         for (int kb = (k0 & ~3) + 4 * sl + PASS; kb - 4 * sl < k1; kb += PASS) {
             int c[W];
-            T v[W];
+            V v[W];
             issue(kb, k1, c, v);
             consume(r, kb, k0, k1, c, v, are, aim);
         }
@@ -530,11 +665,9 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         if (k1 > whole) {
             const int k = (k0 > whole ? k0 : whole) + sl;
             if (k < k1) {
-                const T a = ldg(reinterpret_cast<const T *>(st.val), k);
+                const V a = ldv(reinterpret_cast<const V *>(RV ? st.vre : st.val), k);
                 const int col = X16 ? ((int)r ^ (int)gmem(st.col16)[k]) : gmem(st.col)[k];
-                const T x = s_x[col];
-                are += (double)a.x * (double)x.x - (double)a.y * (double)x.y;
-                aim += (double)a.x * (double)x.y + (double)a.y * (double)x.x;
+                entry_fma(a, s_x[col], are, aim);
             }
         }
         are = group_sum<L>(are);
@@ -552,7 +685,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     // D rows per sub-group in flight: each row's buffer is consumed and then
     // refilled with the sub-group's row D sweeps later
     int cb[D][W];
-    T vb[D][W];
+    V vb[D][W];
     int kb0[D], kb1[D];
     int64_t rr[D];
 #pragma unroll
@@ -602,7 +735,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
 // sorted within a row, bounded by the per-tile row pointers.  The row sums of
 // a tile go to an FP64 partial array; the tile-sum kernel adds the tiles in
 // ascending order and applies the energy epilogue.
-template <int DT, int L, int D, int U, bool X16>
+template <int DT, int L, int D, int U, bool X16, bool RV>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
 {
@@ -616,7 +749,8 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     using T = typename Elem<DT>::T;
     constexpr int W = U * 4;
     constexpr int PASS = W * L;
-    constexpr unsigned EB = sizeof(T);
+    using V = typename ValOf<DT, RV>::T;
+    constexpr unsigned EB = sizeof(V);
     extern __shared__ unsigned char smem[];
     T *s_x = reinterpret_cast<T *>(smem);
     const int tid = threadIdx.x;
@@ -645,10 +779,11 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
         X16 ? __builtin_amdgcn_make_buffer_rsrc((void *)st.col16, (short)0, nnz * 2, VQE_BUF_WORD3)
             : __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
     const __amdgpu_buffer_rsrc_t rv =
-        __builtin_amdgcn_make_buffer_rsrc((void *)st.val, (short)0, (int)(nnz * EB), VQE_BUF_WORD3);
+        __builtin_amdgcn_make_buffer_rsrc((void *)(RV ? st.vre : st.val), (short)0, (int)(nnz * EB),
+                                          VQE_BUF_WORD3);
     double *__restrict__ part = st.tile_part + (int64_t)t * dim * 2;
 
-    auto issue = [&](int kb, int k1, int c[W], T v[W]) {
+    auto issue = [&](int kb, int k1, int c[W], V v[W]) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int k = kb + u * 4 * L;
@@ -668,12 +803,12 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
                 c[4 * u + 2] = c4.z;
                 c[4 * u + 3] = c4.w;
             }
-            BufVal<DT>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
+            BufVal<DT, RV>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
         }
     };
     // entries outside [k0, k1) (or not loaded) read the zero element; the
     // column test keeps every LDS index inside the tile
-    auto consume = [&](int64_t r, int kb, int k0, int k1, const int c[W], const T v[W],
+    auto consume = [&](int64_t r, int kb, int k0, int k1, const int c[W], const V v[W],
                        double &are, double &aim) {
         int cm[W];
         const unsigned len = (unsigned)(k1 - k0);
@@ -686,7 +821,7 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
                 const int cl = (X16 ? (rx ^ c[4 * u + q]) : c[4 * u + q]) - c_lo;
                 cm[4 * u + q] = ((unsigned)(k - k0) < len && (unsigned)cl < (unsigned)tc) ? cl : zc;
             }
-        lds_gather_fma<T, W>(s_x, cm, v, are, aim);
+        lds_gather_fma<T, V, W>(s_x, cm, v, are, aim);
     };
     auto row_bounds = [&](int64_t r, int &k0, int &k1) {
         if (r < r1) {
@@ -699,18 +834,16 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     auto finish = [&](int64_t r, int k0, int k1, double are, double aim) {
         for (int kb = (k0 & ~3) + 4 * sl + PASS; kb - 4 * sl < k1; kb += PASS) {
             int c[W];
-            T v[W];
+            V v[W];
             issue(kb, k1, c, v);
             consume(r, kb, k0, k1, c, v, are, aim);
         }
         if (k1 > whole) {
             const int k = (k0 > whole ? k0 : whole) + sl;
             if (k < k1) {
-                const T a = ldg(reinterpret_cast<const T *>(st.val), k);
+                const V a = ldv(reinterpret_cast<const V *>(RV ? st.vre : st.val), k);
                 const int col = X16 ? ((int)r ^ (int)gmem(st.col16)[k]) : gmem(st.col)[k];
-                const T x = s_x[col - c_lo];
-                are += (double)a.x * (double)x.x - (double)a.y * (double)x.y;
-                aim += (double)a.x * (double)x.y + (double)a.y * (double)x.x;
+                entry_fma(a, s_x[col - c_lo], are, aim);
             }
         }
         are = group_sum<L>(are);
@@ -722,7 +855,7 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     };
 
     int cb[D][W];
-    T vb[D][W];
+    V vb[D][W];
     int kb0[D], kb1[D];
     int64_t rr[D];
 #pragma unroll
@@ -879,17 +1012,17 @@ static void launch_spmv_lds_t(const SpmvState &single, const SpmvState *states, 
     }
 }
 
-template <int DT, int L, int D, bool X16 = false>
+template <int DT, int L, int D, bool X16 = false, bool RV = false>
 static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, const int2 *tasks,
                              unsigned grid, hipStream_t s, size_t lds)
 {
     if (tasks) {
-        auto k = k_spmv_lds_pf<DT, L, D, true, X16>;
+        auto k = k_spmv_lds_pf<DT, L, D, true, X16, RV>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
     } else {
-        auto k = k_spmv_lds_pf<DT, L, D, false, false>;
+        auto k = k_spmv_lds_pf<DT, L, D, false, false, false>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
@@ -903,8 +1036,14 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
     constexpr int D = VQE_SPMV_LDS | VQE_SPMV_DEEP;
     constexpr int P = VQE_SPMV_LDS | VQE_SPMV_PREFETCH;
     constexpr int X = P | VQE_SPMV_X16;
+    constexpr int R = X | VQE_SPMV_REAL;
     switch (sched) {
-    // the 16-bit column form exists only in batch plans (tasks non-null)
+    // the 16-bit column form and the real values exist only in batch plans
+    // (tasks non-null)
+    case 32 | R: launch_spmv_pf_t<DT, 32, 2, true, true>(single, states, tasks, grid, s, lds); return;
+    case 64 | R: launch_spmv_pf_t<DT, 64, 2, true, true>(single, states, tasks, grid, s, lds); return;
+    case 32 | R | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 32, 3, true, true>(single, states, tasks, grid, s, lds); return;
+    case 64 | R | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 64, 3, true, true>(single, states, tasks, grid, s, lds); return;
     case 32 | X: launch_spmv_pf_t<DT, 32, 2, true>(single, states, tasks, grid, s, lds); return;
     case 64 | X: launch_spmv_pf_t<DT, 64, 2, true>(single, states, tasks, grid, s, lds); return;
     case 32 | X | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 32, 3, true>(single, states, tasks, grid, s, lds); return;
@@ -951,14 +1090,16 @@ int32_t spmv_tile_cols(int dtype) { return (int32_t)(SPMV_TILE_BYTES / vqe_elem_
 
 // Tile passes see short row segments, so narrow sub-groups keep two groups of
 // four entries per lane (U = 2) instead of covering 256 entries per pass.
+// The real-value form comes only with the 16-bit codes.
 template <int DT, int L, int D>
 static void launch_tiled_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
-                           bool x16)
+                           bool x16, bool rv)
 {
     const size_t lds = (size_t)(spmv_tile_cols(DT) + 1) * vqe_elem_bytes(DT) +
                        2 * SPMV_LDS_ROWS * sizeof(int32_t);
-    auto k = x16 ? k_spmv_tiled<DT, L, D, (L >= 32 ? 64 / L : 2), true>
-                 : k_spmv_tiled<DT, L, D, (L >= 32 ? 64 / L : 2), false>;
+    constexpr int U = L >= 32 ? 64 / L : 2;
+    auto k = rv ? k_spmv_tiled<DT, L, D, U, true, true>
+                : x16 ? k_spmv_tiled<DT, L, D, U, true, false> : k_spmv_tiled<DT, L, D, U, false, false>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);
 }
@@ -969,15 +1110,16 @@ static void launch_tiled_dt(int sched, const SpmvState *states, const int2 *task
 {
     const bool deep = (sched & VQE_SPMV_DEEP) != 0;
     const bool x = (sched & VQE_SPMV_X16) != 0;
+    const bool r = (sched & VQE_SPMV_REAL) != 0;
     switch (sched & 0xff) {
-    case 8: deep ? launch_tiled_t<DT, 8, 3>(states, tasks, grid, s, x)
-                 : launch_tiled_t<DT, 8, 2>(states, tasks, grid, s, x); break;
-    case 16: deep ? launch_tiled_t<DT, 16, 3>(states, tasks, grid, s, x)
-                  : launch_tiled_t<DT, 16, 2>(states, tasks, grid, s, x); break;
-    case 64: deep ? launch_tiled_t<DT, 64, 3>(states, tasks, grid, s, x)
-                  : launch_tiled_t<DT, 64, 2>(states, tasks, grid, s, x); break;
-    default: deep ? launch_tiled_t<DT, 32, 3>(states, tasks, grid, s, x)
-                  : launch_tiled_t<DT, 32, 2>(states, tasks, grid, s, x); break;
+    case 8: deep ? launch_tiled_t<DT, 8, 3>(states, tasks, grid, s, x, r)
+                 : launch_tiled_t<DT, 8, 2>(states, tasks, grid, s, x, r); break;
+    case 16: deep ? launch_tiled_t<DT, 16, 3>(states, tasks, grid, s, x, r)
+                  : launch_tiled_t<DT, 16, 2>(states, tasks, grid, s, x, r); break;
+    case 64: deep ? launch_tiled_t<DT, 64, 3>(states, tasks, grid, s, x, r)
+                  : launch_tiled_t<DT, 64, 2>(states, tasks, grid, s, x, r); break;
+    default: deep ? launch_tiled_t<DT, 32, 3>(states, tasks, grid, s, x, r)
+                  : launch_tiled_t<DT, 32, 2>(states, tasks, grid, s, x, r); break;
     }
     k_spmv_tile_sum<DT><<<sum_grid, 256, 0, s>>>(states, sum_tasks);
 }
@@ -1014,6 +1156,10 @@ bool vqe_valid_schedule(int sched)
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_REAL:
+    case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_REAL:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
+    case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
         return true;
     default:
         return false;
@@ -1025,6 +1171,9 @@ bool vqe_valid_schedule(int sched)
 // schedule with the same lanes is used.
 int vqe_effective_schedule(const vqe_csr *H, int sched)
 {
+    // the real-value form needs an operator flagged real, and the codes
+    if (!(H->flags & VQE_REAL))
+        sched &= ~VQE_SPMV_REAL;
     const bool wide = (sched & (VQE_SPMV_VEC4 | VQE_SPMV_LDS)) != 0;
     if (wide && ((((uintptr_t)H->col) & 15) != 0 || (((uintptr_t)H->val) & 31) != 0))
         return sched & 0xff;
@@ -1035,10 +1184,10 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
     if ((sched & VQE_SPMV_PREFETCH) &&
         (!(sched & VQE_SPMV_LDS) || H->nnz * (int64_t)vqe_elem_bytes(H->dtype) > 0x7fffff00LL ||
          (sched & 0xff) < 32))
-        return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16);
+        return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL);
     // the 16-bit column form needs column XOR row below 2^16
     if ((sched & VQE_SPMV_X16) && H->dim > SPMV_X16_MAX_DIM)
-        return sched & ~VQE_SPMV_X16;
+        return sched & ~(VQE_SPMV_X16 | VQE_SPMV_REAL);
     return sched;
 }
 
@@ -1050,8 +1199,30 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
     if (big && aligned && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) &&
         H->nnz * (int64_t)vqe_elem_bytes(H->dtype) <= 0x7fffff00LL && H->dim <= ((int64_t)1 << 30))
-        return (H->dim > SPMV_X16_MAX_DIM ? sched & ~VQE_SPMV_X16 : sched) | VQE_SPMV_TILED;
+        return (H->dim > SPMV_X16_MAX_DIM ? sched & ~(VQE_SPMV_X16 | VQE_SPMV_REAL)
+                : (H->flags & VQE_REAL) ? sched : sched & ~VQE_SPMV_REAL) | VQE_SPMV_TILED;
     return vqe_effective_schedule(H, sched);
+}
+
+void launch_val_real(const vqe_csr *H, void *out, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((H->nnz + 255) / 256);
+    if (grid == 0)
+        return;
+    if (H->dtype == VQE_C128)
+        k_val_real<VQE_C128><<<grid, 256, 0, s>>>(H->val, out, H->nnz);
+    else
+        k_val_real<VQE_C64><<<grid, 256, 0, s>>>(H->val, out, H->nnz);
+}
+
+void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vre, hipStream_t s)
+{
+    k_pad_rowptr<<<1, 1024, 0, s>>>(H->rowptr, prow, H->dim);
+    const unsigned grid = (unsigned)((H->dim + 3) / 4);
+    if (H->dtype == VQE_C128)
+        k_pad_fill<VQE_C128><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vre, H->dim);
+    else
+        k_pad_fill<VQE_C64><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vre, H->dim);
 }
 
 void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s)
@@ -1166,8 +1337,9 @@ extern "C" int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, vo
         return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: bad arguments");
     if (!vqe_valid_schedule(schedule))
         return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: unknown schedule %d", schedule);
-    // a single call has no 16-bit column codes: the same schedule without them
-    const int lanes = schedule & ~VQE_SPMV_X16;
+    // a single call has no 16-bit column codes or real values: the same
+    // schedule without them
+    const int lanes = schedule & ~(VQE_SPMV_X16 | VQE_SPMV_REAL);
     // energy result goes after the partials in the workspace
     const size_t o_out = vqe_spmv_partials_bytes(H->dim, lanes);
     rc = vqe_ws_reserve(ctx, o_out + 256);

@@ -45,6 +45,14 @@ struct SpmvState {
     int32_t tile_cols;
     // 16-bit column form (schedules with VQE_SPMV_X16): col16[k] = col[k] ^ row
     const uint16_t *col16;
+    // real parts of val (schedules with VQE_SPMV_REAL): FP32 or FP64.  For
+    // the column-tiled form [nnz], with col16 in the CSR's layout; otherwise
+    // col16 and vre hold the padded layout (rows rounded up to whole groups
+    // of four, zero values in the pads) with row pointers prow[dim + 1] and
+    // room for cap entries
+    const void *vre;
+    const int32_t *prow;
+    int64_t cap;
 };
 
 // Column-tiled H product: tile width (state elements staged in LDS per pass)

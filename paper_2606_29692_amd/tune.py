@@ -20,12 +20,14 @@ import numpy as np
 from . import binding as B
 
 _L, _V, _D, _P = B.VQE_SPMV_LDS, B.VQE_SPMV_VEC4, B.VQE_SPMV_DEEP, B.VQE_SPMV_PREFETCH
-_X = B.VQE_SPMV_X16
+_X, _R = B.VQE_SPMV_X16, B.VQE_SPMV_REAL
 CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               8 | _L, 16 | _L, 32 | _L, 64 | _L, 8 | _L | _D, 16 | _L | _D, 32 | _L | _D, 64 | _L | _D,
               32 | _L | _P, 64 | _L | _P, 32 | _L | _P | _D, 64 | _L | _P | _D,
               8 | _L | _P, 16 | _L | _P, 16 | _L | _P | _D,
-              32 | _L | _P | _X, 64 | _L | _P | _X, 32 | _L | _P | _D | _X, 64 | _L | _P | _D | _X)
+              32 | _L | _P | _X, 64 | _L | _P | _X, 32 | _L | _P | _D | _X, 64 | _L | _P | _D | _X,
+              32 | _L | _P | _X | _R, 64 | _L | _P | _X | _R, 32 | _L | _P | _D | _X | _R,
+              64 | _L | _P | _D | _X | _R)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}

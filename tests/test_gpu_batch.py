@@ -204,7 +204,9 @@ def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
 @pytest.mark.parametrize("sched", [0, 16 | B.VQE_SPMV_LDS, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
-                                   B.VQE_SPMV_X16])
+                                   B.VQE_SPMV_X16,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
+                                   B.VQE_SPMV_REAL])
 def test_full_size_bench_config(ctx, sched):
     """64 states at 14 qubits in FP32 storage (the benchmark workload):
     sampled states against the oracle, invariants on every state."""
@@ -257,7 +259,11 @@ def test_full_size_bench_config(ctx, sched):
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
                                    B.VQE_SPMV_X16,
                                    64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
-                                   B.VQE_SPMV_X16])
+                                   B.VQE_SPMV_X16,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
+                                   B.VQE_SPMV_REAL,
+                                   64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
+                                   B.VQE_SPMV_X16 | B.VQE_SPMV_REAL])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
@@ -318,7 +324,9 @@ def test_screen_full_pair_table(ctx):
 @pytest.mark.parametrize("sched", [32 | B.VQE_SPMV_LDS,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
                                    64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP,
-                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16])
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
+                                   B.VQE_SPMV_REAL])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("op", ["half", "zero"])
 def test_spmv_rows_without_entries(ctx, sched, dtype, op):
@@ -359,11 +367,15 @@ def test_spmv_rows_without_entries(ctx, sched, dtype, op):
     plan.close()
 
 
-def test_x16_rebind_rebuilds_codes(ctx):
-    """A slot with the 16-bit column form rebound to a Hamiltonian with more
-    entries (its codes are rebuilt in a larger buffer) gives the energies and
-    sigma of that Hamiltonian's own plan, bit for bit; both match the oracle."""
+@pytest.mark.parametrize("real", [False, True])
+def test_x16_rebind_rebuilds_codes(ctx, real):
+    """A slot with the 16-bit column form (and the real values) rebound to a
+    Hamiltonian with more entries (its codes and values are rebuilt in larger
+    buffers) gives the energies and sigma of that Hamiltonian's own plan, bit
+    for bit; both match the oracle."""
     sched = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP | B.VQE_SPMV_X16
+    if real:
+        sched |= B.VQE_SPMV_REAL
     s = vs.make_system(vs.SystemSpec(12, 8, "jw", False, 91))
     ha = s.hamiltonian
     # two thirds of the terms: exact cancellations of the full sum are lost,
@@ -396,3 +408,98 @@ def test_x16_rebind_rebuilds_codes(ctx):
         assert abs(e[0] - e_o) <= 1e-5 * max(1.0, abs(e_o))
     plan.close()
     own.close()
+
+
+def _y_pack(n, x, z, c):
+    return vs.PauliPack(n, np.array(x, dtype=np.uint64), np.array(z, dtype=np.uint64),
+                        np.array(c, dtype=np.complex128))
+
+
+def test_real_flag_from_terms(ctx):
+    """The builder flags an operator real exactly when the oracle's matrix has
+    no imaginary part: molecular Hamiltonians (JW and BK) and excitation
+    generators are real; a Y string with a real coefficient, or an X string
+    with an imaginary one, is not; a Y string with an imaginary coefficient is."""
+    n = 8
+    cases = [vs.make_system(vs.SystemSpec(n, 4, m, False, 12)).hamiltonian for m in ("jw", "bk")]
+    cases += vs.make_system(vs.SystemSpec(n, 4, "jw", False, 12)).pool[:3]
+    cases += [_y_pack(n, [0, 4], [1, 4], [0.5, 0.25]),          # Z0 + 0.25 Y2
+              _y_pack(n, [0, 4], [1, 0], [0.5, 0.25j]),         # Z0 + 0.25i X2
+              _y_pack(n, [0, 4], [1, 4], [0.5, 0.25j]),         # Z0 + 0.25i Y2
+              _y_pack(n, [12], [12], [0.3])]                    # Y2 Y3
+    want = [True, True, True, True, True, False, False, True, True]
+    for pack, w in zip(cases, want):
+        dense = orc.csr_from_pack(pack).dense()
+        assert (np.abs(dense.imag).max() == 0.0) == w
+        for dt in ("c128", "c64"):
+            assert B.csr_from_pack(ctx, pack, dt).real == w
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_real_values_match_complex_values(ctx, dtype):
+    """The real-value form against the complex-value form of the same
+    schedule on the same states: bit for bit in FP32 storage (every product
+    is exact in FP64), to rounding in FP64 storage; both against the oracle."""
+    x = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16
+    specs = [vs.SystemSpec(12, 6, "jw", False, 130), vs.SystemSpec(12, 4, "bk", False, 131),
+             vs.SystemSpec(14, 6, "jw", True, 132)]
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx)
+    out = {}
+    for sched in (x, x | B.VQE_SPMV_REAL):
+        ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+        assert all(d.H.real for d in ds)
+        plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
+        plan.theta.fill_(0.2)
+        for _ in range(3):
+            plan.step(renorm=True, graph=True)
+        plan.step(update=False)
+        out[sched] = (host(plan.energies).copy(), [host(plan.sigma[i]).copy() for i in range(3)],
+                      [host(d.psi).copy() for d in ds], host(plan.k).copy())
+        plan.close()
+    a, b = out[x], out[x | B.VQE_SPMV_REAL]
+    np.testing.assert_array_equal(a[3], b[3])
+    if dtype == "c64":
+        np.testing.assert_array_equal(a[0], b[0])
+        for i in range(3):
+            np.testing.assert_array_equal(a[1][i], b[1][i])
+            np.testing.assert_array_equal(a[2][i], b[2][i])
+    else:
+        np.testing.assert_allclose(b[0], a[0], rtol=1e-13, atol=1e-13)
+        for i in range(3):
+            assert np.linalg.norm(b[1][i] - a[1][i]) <= 1e-13 * np.linalg.norm(a[1][i])
+    for i, s in enumerate(systems):
+        e_o = orc.energy(orc.csr_from_pack(s.hamiltonian), b[2][i].astype(np.complex128))[0]
+        tol = 1e-5 if dtype == "c64" else 1e-12
+        assert abs(b[0].reshape(-1, 3)[i, 0] - e_o) <= tol * max(1.0, abs(e_o))
+
+
+def test_real_schedule_on_complex_hamiltonian(ctx):
+    """An H with imaginary entries is not flagged real: a plan asked for the
+    real-value form runs the complex-value form (oracle parity), and a slot
+    holding the real-value form refuses to be rebound to it."""
+    n = 10
+    s = vs.make_system(vs.SystemSpec(n, 4, "jw", False, 140))
+    h = s.hamiltonian
+    hy = vs.PauliPack(n, np.append(h.xmask, np.uint64(1 << 3)), np.append(h.zmask, np.uint64(1 << 3)),
+                      np.append(h.coeff, 0.05))                     # + 0.05 Y3
+    sched = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 | B.VQE_SPMV_REAL
+    pool = B.pool_from_packs(ctx, s.pool, "c128")
+    Hy = B.csr_from_pack(ctx, hy, "c128")
+    Hr = B.csr_from_pack(ctx, h, "c128")
+    assert not Hy.real and Hr.real
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    v /= np.linalg.norm(v)
+    psi = torch.from_numpy(v).to(ctx.torch_device)
+    plan = B.BatchPlan(ctx, [(Hy, pool, psi)], schedules=[sched])
+    plan.step(update=False)
+    e_o, _, im_o, sig = orc.energy(orc.csr_from_pack(hy), v)
+    assert abs(host(plan.energies)[0] - e_o) <= 1e-12 * max(1.0, abs(e_o))
+    assert np.linalg.norm(host(plan.sigma[0]) - sig) <= 1e-12 * np.linalg.norm(sig)
+    plan.close()
+    plan = B.BatchPlan(ctx, [(Hr, pool, psi)], schedules=[sched])
+    with pytest.raises(B.VqeError) as e:
+        plan.rebind(0, Hy, pool, psi)
+    assert e.value.status == B.VQE_EINVAL
+    plan.close()

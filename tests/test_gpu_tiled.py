@@ -20,6 +20,8 @@ from paper_2606_29692_amd import binding as B  # noqa: E402
 SCHED = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH
 # the same tile passes reading 16-bit column codes (col ^ row)
 SCHED_X16 = SCHED | B.VQE_SPMV_X16
+# and the real parts of the values (every Hamiltonian here is real)
+SCHED_R = SCHED_X16 | B.VQE_SPMV_REAL
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +66,8 @@ def oracle_run(system, thetas, K):
                          vs.reference_state(system), thetas, len(K), forced=K)
 
 
-@pytest.mark.parametrize("matrix_free,sched", [(False, SCHED), (True, SCHED), (True, SCHED_X16)])
+@pytest.mark.parametrize("matrix_free,sched", [(False, SCHED), (True, SCHED), (True, SCHED_X16),
+                                                (True, SCHED_R)])
 def test_tiled_fp64_14_qubits(ctx, matrix_free, sched):
     specs = [vs.SystemSpec(14, 6, m, False, vs.system_seed(60, i)) for i, m in enumerate(["jw", "bk"])]
     systems = [vs.make_system(s) for s in specs]
@@ -78,7 +81,7 @@ def test_tiled_fp64_14_qubits(ctx, matrix_free, sched):
         assert np.linalg.norm(psi[i] - tr.psi) <= 1e-12 * np.linalg.norm(tr.psi)
 
 
-@pytest.mark.parametrize("sched", [SCHED, SCHED_X16])
+@pytest.mark.parametrize("sched", [SCHED, SCHED_X16, SCHED_R])
 def test_tiled_fp32_16_qubits(ctx, sched):
     specs = [vs.SystemSpec(16, 8, "jw", False, vs.system_seed(61, i)) for i in range(2)]
     systems = [vs.make_system(s) for s in specs]
@@ -92,7 +95,7 @@ def test_tiled_fp32_16_qubits(ctx, sched):
     assert de < 1e-6 and dg < 1e-5 and fid > 0.999999
 
 
-@pytest.mark.parametrize("sched", [SCHED, SCHED_X16])
+@pytest.mark.parametrize("sched", [SCHED, SCHED_X16, SCHED_R])
 def test_tiled_rebind(ctx, sched):
     """Slot 0 rebound to another Hamiltonian of the same size: its tile
     bounds are rebuilt, and the energy matches that system's own plan."""
