@@ -255,6 +255,32 @@ __device__ __forceinline__ void stage_lds(T *dst, const T *src, int64_t n, int t
     }
 }
 
+// The real parts of a state staged in LDS as FP64; returns nonzero when an
+// element of this thread's share has a nonzero imaginary part.
+template <int SB, typename T>
+__device__ __forceinline__ int stage_real(double *dst, const T *src, int64_t n, int tid)
+{
+    int cplx = 0;
+    for (int64_t i0 = tid; i0 < n; i0 += 1024 * SB) {
+        T v[SB];
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const int64_t i = i0 + (int64_t)u * 1024;
+            if (i < n)
+                v[u] = stage_load(src, i);
+        }
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const int64_t i = i0 + (int64_t)u * 1024;
+            if (i < n) {
+                dst[i] = (double)v[u].x;
+                cplx |= v[u].y != 0;
+            }
+        }
+    }
+    return cplx;
+}
+
 // One entry's product a * x added to (are, aim) in FP64: a complex value, or
 // the real part alone when the operator is stored with real values.
 template <typename T>
@@ -282,6 +308,38 @@ __device__ __forceinline__ void entry_fma(const double a, const T x, double &are
 {
     are += a * (double)x.x;
     aim += a * (double)x.y;
+}
+
+// Entries against a real state (its real parts in FP64): the imaginary sum
+// stays zero.
+__device__ __forceinline__ void entry_fma(const float a, const double x, double &are, double &aim)
+{
+    (void)aim;
+    are += (double)a * x;
+}
+__device__ __forceinline__ void entry_fma(const double a, const double x, double &are, double &aim)
+{
+    (void)aim;
+    are += a * x;
+}
+
+// A row's terms of <psi|sigma> and <psi|psi> from its state element.
+template <typename T>
+__device__ __forceinline__ void energy_terms(const T ps, double are, double aim, double &e_re,
+                                             double &e_im, double &e_n2)
+{
+    const double px = (double)ps.x, py = (double)ps.y;
+    e_re += px * are + py * aim;
+    e_im += px * aim - py * are;
+    e_n2 += px * px + py * py;
+}
+__device__ __forceinline__ void energy_terms(const double px, double are, double aim, double &e_re,
+                                             double &e_im, double &e_n2)
+{
+    (void)aim;
+    (void)e_im;
+    e_re += px * are;
+    e_n2 += px * px;
 }
 
 template <typename T, typename V, int N>
@@ -551,45 +609,24 @@ k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
 // with zero values to whole groups (row pointers st.prow), so no entry needs
 // a row mask and there is no tail; the values are the real parts, 4 instead
 // of 8 bytes per entry in FP32 storage.
-template <int DT, int L, int D, bool BATCH, bool X16, bool RV>
-__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
-k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
-              const int2 *__restrict__ tasks)
+// The rows [r0, r1) of one workgroup of the pipelined LDS schedule, the state
+// already staged in LDS at smem (complex, or with RX its real parts in FP64)
+// and the row pointers at s_rp; writes sigma and the workgroup's energy
+// partials.
+template <int DT, int L, int D, bool X16, bool RV, bool RX>
+__device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsigned char *smem,
+                                        const int32_t *s_rp, int64_t r0, int64_t r1)
 {
-    SpmvState st;
-    int blk;
-    if (BATCH) {
-        int2 t = tasks[blockIdx.x];
-        if (t.x < 0)
-            return;
-        st = states[t.x];
-        blk = t.y;
-        if (VQE_SKIP(st))
-            return;
-    } else {
-        st = single;
-        blk = blockIdx.x;
-    }
     using T = typename Elem<DT>::T;
+    using X = typename std::conditional<RX, double, T>::type;
     constexpr int U = 64 / L;
     constexpr int W = U * 4;                 // entries per lane per pass
     constexpr int PASS = W * L;              // entries per sub-group per pass
     using V = typename ValOf<DT, RV>::T;
     constexpr unsigned EB = sizeof(V);
-    extern __shared__ unsigned char smem[];
-    T *s_x = reinterpret_cast<T *>(smem);
+    const X *s_x = reinterpret_cast<const X *>(smem);
     const int tid = threadIdx.x;
     const int64_t dim = st.dim;
-    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
-    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
-    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
-    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)(dim + 1) * sizeof(T));
-    stage_lds<8>(s_x, psi, dim, tid);
-    if (tid == 0)
-        s_x[dim] = T{};
-    stage_lds<4>(s_rp, (RV ? st.prow : st.rowptr) + r0, r1 - r0 + 1, tid);
-    __syncthreads();
-
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
@@ -643,7 +680,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
                 const int col = X16 ? (rx ^ c[4 * u + q]) : c[4 * u + q];
                 cm[4 * u + q] = RV || (unsigned)(k - k0) < len ? col : zc;
             }
-        lds_gather_fma<T, V, W>(s_x, cm, v, are, aim);
+        lds_gather_fma<X, V, W>(s_x, cm, v, are, aim);
     };
     auto row_bounds = [&](int64_t r, int &k0, int &k1) {
         if (r < r1) {
@@ -671,14 +708,11 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
             }
         }
         are = group_sum<L>(are);
-        aim = group_sum<L>(aim);
+        if (!RX)
+            aim = group_sum<L>(aim);
         if (sl == 0 && r < r1) {
             Elem<DT>::st(st.sigma, r, make_double2(are, aim));
-            const T ps = s_x[r];
-            const double px = (double)ps.x, py = (double)ps.y;
-            e_re += px * are + py * aim;
-            e_im += px * aim - py * are;
-            e_n2 += px * px + py * py;
+            energy_terms(s_x[r], are, aim, e_re, e_im, e_n2);
         }
     };
 
@@ -727,6 +761,55 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         gmem(st.partials)[(int64_t)blk * 3 + tid] = v;
     }
 }
+
+
+template <int DT, int L, int D, bool BATCH, bool X16, bool RV>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
+k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
+              const int2 *__restrict__ tasks)
+{
+    SpmvState st;
+    int blk;
+    if (BATCH) {
+        int2 t = tasks[blockIdx.x];
+        if (t.x < 0)
+            return;
+        st = states[t.x];
+        blk = t.y;
+        if (VQE_SKIP(st))
+            return;
+    } else {
+        st = single;
+        blk = blockIdx.x;
+    }
+    using T = typename Elem<DT>::T;
+    extern __shared__ unsigned char smem[];
+    T *s_x = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x;
+    const int64_t dim = st.dim;
+    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
+    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)(dim + 1) * sizeof(T));
+    stage_lds<4>(s_rp, (RV ? st.prow : st.rowptr) + r0, r1 - r0 + 1, tid);
+    if constexpr (RV) {
+        // a real state (every imaginary part zero) runs in real arithmetic
+        double *s_xr = reinterpret_cast<double *>(smem);
+        const int cplx = stage_real<8>(s_xr, psi, dim, tid);
+        if (tid == 0)
+            s_xr[dim] = 0.0;
+        if (!__syncthreads_or(cplx)) {
+            pf_rows<DT, L, D, X16, RV, true>(st, blk, smem, s_rp, r0, r1);
+            return;
+        }
+    }
+    stage_lds<8>(s_x, psi, dim, tid);
+    if (tid == 0)
+        s_x[dim] = T{};
+    __syncthreads();
+    pf_rows<DT, L, D, X16, RV, false>(st, blk, smem, s_rp, r0, r1);
+}
+
 
 // Column-tiled variant of the pipelined LDS schedule, for states larger than
 // LDS.  A workgroup takes one block of rows and one column tile: it stages
