@@ -147,6 +147,11 @@ struct vqe_batch {
     int4 *d_screen_tasks = nullptr;
     unsigned n_screen_tasks = 0;
     size_t screen_lds = 0;
+    // real-state screen (matrix-free pools of real anti-Hermitian generators
+    // whose states fit one LDS tile as reals): tasks per (state, range)
+    int4 *d_screen1_tasks = nullptr;
+    unsigned n_screen1_tasks = 0;
+    size_t screen1_lds = 0;
     std::vector<void *> table_mem;   // one allocation per distinct pool
     size_t table_bytes = 0;
     SelectState *d_sel = nullptr;
@@ -324,6 +329,9 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
     // and the selection (the energy phase event coincides with the start)
     int rc = mark(2);
     const bool grad = p->mf || p->n_screen_tasks;
+    if (p->mf && p->n_screen1_tasks)
+        launch_screen_mf_real(p->dtype, p->d_screen, p->d_screen1_tasks, p->n_screen1_tasks,
+                              p->screen1_lds, s);
     if (p->mf)
         launch_screen_mf(p->dtype, p->d_screen, p->d_screen_tasks, p->n_screen_tasks,
                          p->screen_lds, s);
@@ -612,7 +620,75 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     std::vector<PairTable> tables;
     std::vector<const MfTable *> mf_dev;        // device header per table (mf mode)
     std::vector<const vqe_mf_desc *> mf_desc_ptrs;  // device descriptors per table (mf mode)
-    std::vector<MfHostPlan> mf_plans;
+    std::vector<MfHostPlan> mf_plans, mf_plans1;
+    std::vector<const MfTable *> mf_dev1;       // whole-state tables (real-state screen)
+    // one allocation per table: header, tile records, whole-state records,
+    // lists, descriptors, index tables
+    auto upload_mf = [&](const MfHostPlan &hp, const vqe_mf_pool *pool, const MfTable **dev,
+                 const vqe_mf_desc **ddesc) -> int {
+    const size_t o_h = 0, o_t = vqe_align(sizeof(MfTable));
+    const size_t o_f = o_t + vqe_align(hp.tile_recs.size() * sizeof(MfRec));
+    const size_t o_l = o_f + vqe_align(hp.full_recs.size() * sizeof(MfRec));
+    const size_t o_d = o_l + vqe_align(hp.lists.size() * sizeof(int32_t) + 4);
+    const size_t o_x = o_d + vqe_align((size_t)hp.M * sizeof(vqe_mf_desc));
+    const size_t bytes = o_x + vqe_align(hp.tabs.size() * sizeof(uint32_t) + 4);
+    char *mem = nullptr;
+    if (hipMalloc((void **)&mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return vqe_fail(ctx, VQE_ENOMEM, "vqe_batch_create: record allocation failed");
+    }
+    p->table_mem.push_back(mem);
+    p->table_bytes += bytes;
+    MfTable h{};
+    h.tile_recs = (const MfRec *)(mem + o_t);
+    h.full_recs = (const MfRec *)(mem + o_f);
+    h.lists = (const int32_t *)(mem + o_l);
+    h.desc = (const vqe_mf_desc *)(mem + o_d);
+    h.tabs = (const uint32_t *)(mem + o_x);
+    h.M = hp.M;
+    h.ntile = hp.ntile;
+    h.tile_rows = hp.tile_rows;
+    hipError_t e = hipMemcpy(mem + o_h, &h, sizeof(h), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(mem + o_t, hp.tile_recs.data(), hp.tile_recs.size() * sizeof(MfRec),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(mem + o_f, hp.full_recs.data(), hp.full_recs.size() * sizeof(MfRec),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hp.lists.empty())
+        e = hipMemcpy(mem + o_l, hp.lists.data(), hp.lists.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hp.tabs.empty())
+        e = hipMemcpy(mem + o_x, hp.tabs.data(), hp.tabs.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        std::vector<vqe_mf_desc> dd(hp.M);
+        for (int j = 0; j < hp.M; j++)
+            (void)vqe_mf_pool_get(pool, j, &dd[j]);
+        e = hipMemcpy(mem + o_d, dd.data(), dd.size() * sizeof(vqe_mf_desc),
+                      hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess)
+        return vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: record upload: %s",
+                        hipGetErrorString(e));
+    *dev = (const MfTable *)(mem + o_h);
+    *ddesc = (const vqe_mf_desc *)(mem + o_d);
+    return VQE_OK;
+    };
+
+    // the real-state screen applies when every generator of every pool has a
+    // real value and is anti-Hermitian (so the diagonal shift drops out) and
+    // every state fits one LDS tile as reals
+    bool real_screen = mf_mode;
+    for (int s = 0; s < B && real_screen; s++) {
+        real_screen = screen_real_lds(items[s].H->dim, dtype) <= SCREEN_LDS_BYTES;
+        const vqe_mf_pool *pl = items[s].pool->mf;
+        for (int j = 0; j < items[s].pool->M && real_screen; j++) {
+            vqe_mf_desc d;
+            real_screen = vqe_mf_pool_get(pl, j, &d) == VQE_OK && d.v_im == 0.0 &&
+                          mf_antihermitian(d);
+        }
+    }
     for (int s = 0; s < B; s++) {
         const void *key = pool_key(items[s].pool);
         if (table_of.count(key))
@@ -625,57 +701,29 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             int rc = mf_host_plan(items[s].pool->mf, tile, &hp, err, sizeof(err));
             if (rc)
                 return fail_free(vqe_fail(ctx, rc, "vqe_batch_create: %s", err));
-            // one allocation: header, tile records, whole-state records, lists
-            const size_t o_h = 0, o_t = vqe_align(sizeof(MfTable));
-            const size_t o_f = o_t + vqe_align(hp.tile_recs.size() * sizeof(MfRec));
-            const size_t o_l = o_f + vqe_align(hp.full_recs.size() * sizeof(MfRec));
-            const size_t o_d = o_l + vqe_align(hp.lists.size() * sizeof(int32_t) + 4);
-            const size_t o_x = o_d + vqe_align((size_t)hp.M * sizeof(vqe_mf_desc));
-            const size_t bytes = o_x + vqe_align(hp.tabs.size() * sizeof(uint32_t) + 4);
-            char *mem = nullptr;
-            if (hipMalloc((void **)&mem, bytes) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail_free(vqe_fail(ctx, VQE_ENOMEM, "vqe_batch_create: record allocation failed"));
+            const MfTable *dev = nullptr;
+            const vqe_mf_desc *ddesc = nullptr;
+            if ((rc = upload_mf(hp, items[s].pool->mf, &dev, &ddesc)))
+                return fail_free(rc);
+            // the real-state screen: the same records on one whole-state tile
+            const MfTable *dev1 = nullptr;
+            if (real_screen) {
+                MfHostPlan hp1;
+                if ((rc = mf_host_plan(items[s].pool->mf, items[s].H->dim, &hp1, err, sizeof(err))))
+                    return fail_free(vqe_fail(ctx, rc, "vqe_batch_create: %s", err));
+                const vqe_mf_desc *unused = nullptr;
+                if ((rc = upload_mf(hp1, items[s].pool->mf, &dev1, &unused)))
+                    return fail_free(rc);
+                mf_plans1.push_back(std::move(hp1));
+            } else {
+                mf_plans1.emplace_back();
             }
-            p->table_mem.push_back(mem);
-            p->table_bytes += bytes;
-            MfTable h{};
-            h.tile_recs = (const MfRec *)(mem + o_t);
-            h.full_recs = (const MfRec *)(mem + o_f);
-            h.lists = (const int32_t *)(mem + o_l);
-            h.desc = (const vqe_mf_desc *)(mem + o_d);
-            h.tabs = (const uint32_t *)(mem + o_x);
-            h.M = hp.M;
-            h.ntile = hp.ntile;
-            h.tile_rows = hp.tile_rows;
-            hipError_t e = hipMemcpy(mem + o_h, &h, sizeof(h), hipMemcpyHostToDevice);
-            if (e == hipSuccess)
-                e = hipMemcpy(mem + o_t, hp.tile_recs.data(), hp.tile_recs.size() * sizeof(MfRec),
-                              hipMemcpyHostToDevice);
-            if (e == hipSuccess)
-                e = hipMemcpy(mem + o_f, hp.full_recs.data(), hp.full_recs.size() * sizeof(MfRec),
-                              hipMemcpyHostToDevice);
-            if (e == hipSuccess && !hp.lists.empty())
-                e = hipMemcpy(mem + o_l, hp.lists.data(), hp.lists.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice);
-            if (e == hipSuccess && !hp.tabs.empty())
-                e = hipMemcpy(mem + o_x, hp.tabs.data(), hp.tabs.size() * sizeof(uint32_t),
-                              hipMemcpyHostToDevice);
-            if (e == hipSuccess) {
-                std::vector<vqe_mf_desc> dd(hp.M);
-                for (int j = 0; j < hp.M; j++)
-                    (void)vqe_mf_pool_get(items[s].pool->mf, j, &dd[j]);
-                e = hipMemcpy(mem + o_d, dd.data(), dd.size() * sizeof(vqe_mf_desc),
-                              hipMemcpyHostToDevice);
-            }
-            if (e != hipSuccess)
-                return fail_free(vqe_fail(ctx, VQE_EHIP, "vqe_batch_create: record upload: %s",
-                                          hipGetErrorString(e)));
+            mf_dev1.push_back(dev1);
             tb.M = hp.M;
             tb.nt = hp.ntile;
             tb.tile_rows = hp.tile_rows;
-            mf_dev.push_back((const MfTable *)(mem + o_h));
-            mf_desc_ptrs.push_back((const vqe_mf_desc *)(mem + o_d));
+            mf_dev.push_back(dev);
+            mf_desc_ptrs.push_back(ddesc);
             mf_plans.push_back(std::move(hp));
         } else {
             void *mem[2] = {nullptr, nullptr};
@@ -724,6 +772,22 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     }
     auto screen_flat = interleave(screen_per, make_int4(-1, 0, 0, 0));
     const size_t o_stasks = A.take(screen_flat.size() * sizeof(int4));
+    // real-state screen: four workgroups per state (one per CU for 64
+    // states), generators dealt over them by descending cost; a flag per state
+    std::vector<std::vector<int4>> screen1_per(kXcd);
+    if (real_screen)
+        for (int s = 0; s < B; s++) {
+            const MfHostPlan &hp1 = mf_plans1[table_of[pool_key(items[s].pool)]];
+            for (auto &L : hp1.list_info) {
+                const int nr = std::max(1, std::min(L.len, 4));
+                for (int r = 0; r < nr; r++)
+                    screen1_per[xcd_of[s]].push_back(make_int4(s, L.off, L.len, r | (nr << 8)));
+            }
+            p->screen1_lds = std::max(p->screen1_lds, screen_real_lds(items[s].H->dim, dtype));
+        }
+    auto screen1_flat = interleave(screen1_per, make_int4(-1, 0, 0, 0));
+    const size_t o_s1tasks = A.take(screen1_flat.size() * sizeof(int4) + 16);
+    const size_t o_cplx = A.take((size_t)B * sizeof(int32_t));
 
     // --- Taylor and norm tasks (matrix-free records or compact tables: blocks
     //     cover the largest generator's pairs; otherwise the CSR rows)
@@ -829,6 +893,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ss.table = table_of[pool_key(items[s].pool)];
         ss.active = io->active ? io->active + s : nullptr;
         ss.mf = mf_mode ? mf_dev[table_of[pool_key(items[s].pool)]] : nullptr;
+        ss.mf_ntile = tables[table_of[pool_key(items[s].pool)]].nt;
+        ss.mf1 = real_screen ? mf_dev1[table_of[pool_key(items[s].pool)]] : nullptr;
+        ss.cplx = real_screen ? (int32_t *)(D + o_cplx) + s : nullptr;
     }
     for (size_t i = 0; i < spmv_tab.size(); i++) {
         std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));
@@ -839,6 +906,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     }
     std::copy(bounds_list.begin(), bounds_list.end(), A.at<int2>(o_btasks));
     std::copy(screen_flat.begin(), screen_flat.end(), A.at<int4>(o_stasks));
+    std::copy(screen1_flat.begin(), screen1_flat.end(), A.at<int4>(o_s1tasks));
     std::copy(tay_flat.begin(), tay_flat.end(), A.at<int2>(o_ttasks));
     std::copy(norm_flat.begin(), norm_flat.end(), A.at<int2>(o_ntasks));
     p->d_spmv = (SpmvState *)(D + o_spmv);
@@ -848,6 +916,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     p->d_screen = (ScreenState *)(D + o_screen);
     p->d_screen_tasks = (int4 *)(D + o_stasks);
     p->n_screen_tasks = (unsigned)screen_flat.size();
+    p->d_screen1_tasks = (int4 *)(D + o_s1tasks);
+    p->n_screen1_tasks = (unsigned)screen1_flat.size();
     p->d_tay_tasks = (int2 *)(D + o_ttasks);
     p->n_tay_tasks = (unsigned)tay_flat.size();
     p->d_norm_tasks = (int2 *)(D + o_ntasks);

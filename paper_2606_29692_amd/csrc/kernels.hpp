@@ -84,8 +84,13 @@ struct ScreenState {
     int64_t dim;
     const int32_t *active;  // batch slot flag (nullable): 0 = skip this state
     int32_t table;          // index into the plan's PairTable array
-    int32_t pad;
+    int32_t mf_ntile;       // row tiles of the matrix-free screen (partials per generator)
     const MfTable *mf;      // matrix-free records of the pool (nullable)
+    // real-state screen (nullable): the pool's records on one whole-state
+    // tile, and the state's flag, set by that screen when psi or sigma has a
+    // nonzero imaginary part (the tiled screen then covers the state)
+    const MfTable *mf1;
+    int32_t *cplx;
 };
 
 // Matrix-free enumeration of a generator's pairs {r, c = r ^ x} on a row set
@@ -210,8 +215,16 @@ struct MfHostPlan {
     int32_t M = 0, ntile = 1, tile_rows = 0;
 };
 int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, char *err, size_t n_err);
+bool mf_antihermitian(const vqe_mf_desc &d);
 void launch_screen_mf(int dtype, const ScreenState *states, const int4 *tasks, unsigned grid,
                       size_t lds, hipStream_t s);
+void launch_screen_mf_real(int dtype, const ScreenState *states, const int4 *tasks, unsigned grid,
+                           size_t lds, hipStream_t s);
+// LDS bytes of the real-state screen's whole-state tile (psi.re, sigma.re)
+inline size_t screen_real_lds(int64_t dim, int dtype)
+{
+    return (size_t)dim * (dtype == VQE_C64 ? 2 * sizeof(float) : 2 * sizeof(double));
+}
 void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                       hipStream_t s);
 

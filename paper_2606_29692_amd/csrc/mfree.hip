@@ -148,10 +148,7 @@ void make_rec(const vqe_mf_desc &d, int j, int n, uint32_t tb, uint32_t vbits, M
     r.j = j;
     r.v_re = d.v_re;
     r.v_im = d.v_im;
-    // anti-Hermitian on every pair: A[c, r] = -conj(A[r, c]), i.e.
-    // v (-1)^ex = -conj(v)
-    const double s = r.ex ? -1.0 : 1.0;
-    r.antiherm = (s * d.v_re == -d.v_re && s * d.v_im == d.v_im) ? 1 : 0;
+    r.antiherm = mf_antihermitian(d) ? 1 : 0;
     const int h = top_bit(d.x);
     // tile bit positions, descending
     r.ntb = 0;
@@ -256,6 +253,14 @@ void rec_tables(MfRec &rec, std::vector<uint32_t> &tabs)
 }
 
 }  // namespace
+
+// Anti-Hermitian on every pair: A[c, r] = -conj(A[r, c]), i.e.
+// v (-1)^{|zsign & x|} = -conj(v).
+bool mf_antihermitian(const vqe_mf_desc &d)
+{
+    const double s = parity64(d.zsign & d.x) ? -1.0 : 1.0;
+    return s * d.v_re == -d.v_re && s * d.v_im == d.v_im;
+}
 
 int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, char *err,
                  size_t n_err)
@@ -517,6 +522,55 @@ __device__ __forceinline__ double2 mf_tile_sum(const typename TileElem<DT>::T *t
     return make_double2(sre, sim);
 }
 
+// The same sum for a real state: the tile holds (psi_r, sigma_r) as reals, so
+// S = sum of (-1)^{|zsign & r|} [(-1)^ex s_r psi_c + s_c psi_r] (generators of
+// real value, unshifted or anti-Hermitian).
+template <typename R2>
+__device__ __forceinline__ double mf_tile_sum_real(const R2 *tile, const MfRec &rec,
+                                                   const uint32_t *tabs, int lane)
+{
+    const uint32_t cx = uni(rec.cx);
+    const int nlow = (int)uni((uint32_t)rec.nlow);
+    const uint32_t *__restrict__ t = tabs + uni(rec.tab_off);
+    double sre = 0.0;
+    constexpr int U = MF_LANE_UNROLL;
+    uint32_t cl[U], sl[U];
+    bool on[U];
+    const uint32_t lv = gmem(t)[lane];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const uint32_t ev = lv ^ uni(gmem(t)[64 + u]);
+        cl[u] = ev & 0x7fffffffu;
+        sl[u] = ev >> 31;
+        on[u] = (uint32_t)lane + 64u * u < (1u << nlow);
+    }
+    const double e1 = uni(rec.ex) ? -1.0 : 1.0;
+    const int n_it = 1 << ((int)uni((uint32_t)rec.nfree) - nlow);
+    for (int c0 = 0; c0 < n_it; c0 += 64) {
+        const uint32_t hv = c0 + lane < n_it ? gmem(t)[MF_TAB_ITER + c0 + lane] : 0u;
+        const int nin = n_it - c0 < 64 ? n_it - c0 : 64;
+        for (int i = 0; i < nin; i++) {
+            const uint32_t hi = __builtin_amdgcn_readlane(hv, i);
+            const uint32_t ch = hi & 0x7fffffffu, sh = hi >> 31;
+            R2 er[U], ec[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t ir = on[u] ? (cl[u] ^ ch) : 0u, ic = on[u] ? (ir ^ cx) : 0u;
+                er[u] = tile[ir];
+                ec[u] = tile[ic];
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const double tr = e1 * ((double)er[u].y * (double)ec[u].x) +
+                                  (double)ec[u].y * (double)er[u].x;
+                const bool neg = (sl[u] ^ sh) & 1u;
+                sre += (on[u] ? (neg ? -1.0 : 1.0) : 0.0) * tr;
+            }
+        }
+    }
+    return sre;
+}
+
 // One workgroup per (state, tile-bit group, tile, generator range): stage the
 // tile's psi and sigma in LDS, then one wave per generator.
 template <int DT>
@@ -528,6 +582,9 @@ k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tas
         return;
     const ScreenState st = states[task.x];
     if (VQE_SKIP(st))
+        return;
+    // a state the real-state screen has covered
+    if (st.cplx && *st.cplx == 0)
         return;
     const MfTable tb = *st.mf;
     const int32_t *list = tb.lists + task.y;
@@ -592,6 +649,77 @@ k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tas
         }
         if (lane == 0)
             gmem(st.partials)[(int64_t)j * tb.ntile + v] = part;
+    }
+}
+
+// Real-state screen: one workgroup per (state, generator range) stages the
+// whole state as (psi.re, sigma.re) pairs; when every imaginary part is zero
+// one wave per generator forms its gradient in real arithmetic and writes it
+// as the tiled screen's tile-0 partial (the other tiles' partials zero).  A
+// state with a nonzero imaginary part is flagged and left to the tiled screen.
+template <int DT>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_screen_mf_real(const ScreenState *__restrict__ states, const int4 *__restrict__ tasks)
+{
+    const int4 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const ScreenState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    using T = typename Elem<DT>::T;
+    using R2 = typename std::conditional<DT == VQE_C64, float2, double2>::type;
+    const MfTable tb = *st.mf1;
+    const int32_t *list = tb.lists + task.y;
+    const int n = task.z;
+    const int range = task.w & 0xff, n_ranges = (task.w >> 8) & 0xff;
+    extern __shared__ unsigned char smem[];
+    R2 *tile = reinterpret_cast<R2 *>(smem);
+    const T *psi = reinterpret_cast<const T *>(st.psi);
+    const T *sig = reinterpret_cast<const T *>(st.sigma);
+    const int64_t rows = st.dim;
+    int cplx = 0;
+    constexpr int SU = 8;
+    for (int64_t i0 = threadIdx.x; i0 < rows; i0 += 1024 * SU) {
+        T a[SU], b[SU];
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+            const int64_t i = i0 + 1024 * u;
+            if (i < rows) {
+                a[u] = ldg(psi, i);
+                b[u] = ldg(sig, i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+            const int64_t i = i0 + 1024 * u;
+            if (i < rows) {
+                R2 e;
+                e.x = a[u].x;
+                e.y = b[u].x;
+                tile[i] = e;
+                cplx |= (a[u].y != 0) | (b[u].y != 0);
+            }
+        }
+    }
+    cplx = __syncthreads_or(cplx);
+    if (threadIdx.x == 0 && range == 0)
+        *st.cplx = cplx ? 1 : 0;
+    if (cplx)
+        return;
+    const int ntc = st.mf_ntile;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int idx = wid;; idx += 16) {
+        const int e = range + idx * n_ranges;
+        if (e >= n)
+            break;
+        const int j = __builtin_amdgcn_readfirstlane(gmem(list)[e]);
+        const MfRec &rec = tb.tile_recs[j];
+        double part = 0.0;
+        if (rec.nfree >= 0)
+            part = rec.v_re * group_sum<64>(mf_tile_sum_real<R2>(tile, rec, tb.tabs, lane));
+        if (lane < ntc)
+            gmem(st.partials)[(int64_t)j * ntc + lane] = lane == 0 ? part : 0.0;
     }
 }
 
@@ -672,6 +800,20 @@ void launch_screen_mf(int dtype, const ScreenState *states, const int4 *tasks, u
         (void)hipFuncSetAttribute((const void *)k_screen_mf<VQE_C64>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k_screen_mf<VQE_C64><<<grid, 1024, lds, s>>>(states, tasks);
+    }
+}
+
+void launch_screen_mf_real(int dtype, const ScreenState *states, const int4 *tasks, unsigned grid,
+                           size_t lds, hipStream_t s)
+{
+    if (dtype == VQE_C128) {
+        (void)hipFuncSetAttribute((const void *)k_screen_mf_real<VQE_C128>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_screen_mf_real<VQE_C128><<<grid, 1024, lds, s>>>(states, tasks);
+    } else {
+        (void)hipFuncSetAttribute((const void *)k_screen_mf_real<VQE_C64>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_screen_mf_real<VQE_C64><<<grid, 1024, lds, s>>>(states, tasks);
     }
 }
 

@@ -503,3 +503,42 @@ def test_real_schedule_on_complex_hamiltonian(ctx):
         plan.rebind(0, Hy, pool, psi)
     assert e.value.status == B.VQE_EINVAL
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_screen_real_and_complex_states(ctx, dtype):
+    """Matrix-free screen over states that are real (screened in real
+    arithmetic on one whole-state tile) and complex (the tiled screen) in one
+    plan, against the oracle; then states switch between real and complex and
+    the next screen follows them."""
+    specs = [vs.SystemSpec(10, 4, "jw", False, 150), vs.SystemSpec(12, 6, "bk", False, 151),
+             vs.SystemSpec(12, 8, "jw", True, 152), vs.SystemSpec(10, 4, "bk", True, 153)]
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx, matrix_free=True)
+    ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+    rng = np.random.default_rng(15)
+
+    def set_state(i, complex_):
+        d = ds[i].H.dim
+        v = rng.standard_normal(d) + (1j * rng.standard_normal(d) if complex_ else 0)
+        v = v / np.linalg.norm(v)
+        ds[i].psi.copy_(torch.from_numpy(v.astype(np.complex128)))
+
+    for i in range(4):
+        set_state(i, i % 2 == 1)
+    plan = PB.make_batch(ctx, ds)
+    tol = 1e-12 if dtype == "c128" else 2e-5
+    for phase in range(2):
+        plan.step(update=False)
+        for i, s in enumerate(systems):
+            v = host(ds[i].psi).astype(np.complex128)
+            _, _, _, sig = orc.energy(orc.csr_from_pack(s.hamiltonian), v)
+            g_o = orc.gradients([orc.csr_from_pack(p) for p in s.pool], v, sig)
+            g = host(plan.gradients(i))
+            err = np.abs(g - g_o).max() / max(1.0, np.abs(g_o).max())
+            print(f"phase {phase} state {i} ({'complex' if np.abs(v.imag).max() else 'real'}): "
+                  f"max rel |dg| {err:.2e}")
+            assert err <= tol
+        for i in range(4):
+            set_state(i, i % 2 == 0)
+    plan.close()
