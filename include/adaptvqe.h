@@ -210,6 +210,8 @@ typedef struct vqe_pool {
  * (a hipStream_t, or NULL for the null stream).  Returns VQE_EINVAL for a bad
  * device, VQE_EHIP if the device cannot be used. */
 VQE_API int vqe_create(int device, void *hip_stream, vqe_ctx **out);
+/* Destroy a context.  Every batch plan created on it must be destroyed first
+ * (a plan uses its context's stream until vqe_batch_destroy returns). */
 VQE_API int vqe_destroy(vqe_ctx *ctx);
 /* Re-bind the context to another stream of the same device. */
 VQE_API int vqe_set_stream(vqe_ctx *ctx, void *hip_stream);
@@ -461,7 +463,8 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * larger-than-LDS states reads them too.  States with more than 2^16 rows
  * use the schedule without it; single calls (vqe_time_spmv) ignore it. */
 #define VQE_SPMV_X16 0x4000
-/* VQE_SPMV_REAL (with VQE_SPMV_X16; batch plans only): for an H flagged
+/* VQE_SPMV_REAL (with VQE_SPMV_X16, and then also with 16 lanes; batch
+ * plans only): for an H flagged
  * VQE_REAL the product streams the real parts of its values, which the plan
  * copies from the CSR once (4 bytes per entry in FP32 storage, 8 in FP64;
  * plan-owned, rebuilt by vqe_batch_rebind): 6 instead of 10 bytes per entry

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -161,6 +162,9 @@ class Context:
         if st != VQE_OK:
             raise VqeError(st, f"vqe_create: {lib().vqe_strerror(st).decode()}")
         self.handle = h
+        # batch plans made on this context: destroyed before the context,
+        # since a plan uses its context's stream until it is destroyed
+        self._plans = weakref.WeakSet()
 
     def check(self, status: int, what: str):
         if status != VQE_OK:
@@ -179,6 +183,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for plan in list(getattr(self, "_plans", ())):
+                plan.close()
             lib().vqe_destroy(self.handle)
             self.handle = None
 
@@ -502,6 +508,7 @@ class BatchPlan:
                  with_active: bool = False):
         torch = _torch()
         self.ctx = ctx
+        ctx._plans.add(self)
         B = len(states)
         self.B = B
         self.states = states

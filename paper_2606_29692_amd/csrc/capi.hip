@@ -360,8 +360,12 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
             launch_taylor_pair(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
     }
     rc = rc ? rc : mark(5);
-    if (!(flags & VQE_STEP_NO_UPDATE) && (flags & VQE_STEP_RENORM))
-        launch_norm(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, s);
+    if (!(flags & VQE_STEP_NO_UPDATE) && (flags & VQE_STEP_RENORM)) {
+        if (p->mf)
+            launch_norm_mf(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, s);
+        else
+            launch_norm(p->dtype, p->d_tay, p->d_norm_tasks, p->n_norm_tasks, s);
+    }
     rc = rc ? rc : mark(6);
     if (rc)
         return rc;
@@ -808,6 +812,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             max_pairs[i] = std::max(max_pairs[i], pts[(size_t)(j + 1) * tb.nt] - pts[(size_t)j * tb.nt]);
     }
     std::vector<std::vector<int2>> tay_per(kXcd), norm_per(kXcd);
+    std::vector<size_t> o_taypart(B, 0);
+    std::vector<int32_t> ntay(B, 0);
     for (int s = 0; s < B; s++) {
         const int64_t dim = items[s].H->dim;
         const int mp = max_pairs[table_of[pool_key(items[s].pool)]];
@@ -817,6 +823,11 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         const int nn = (int)((dim + NORM_ROWS_PER_BLOCK - 1) / NORM_ROWS_PER_BLOCK);
         for (int b = 0; b < nt; b++)
             tay_per[xcd_of[s]].push_back(make_int2(s, b));
+        if (mf_mode) {
+            // the update blocks' changes of |psi|^2, for the renormalisation
+            o_taypart[s] = A.take((size_t)nt * sizeof(double));
+            ntay[s] = nt;
+        }
         for (int b = 0; b < nn; b++)
             norm_per[xcd_of[s]].push_back(make_int2(s, b));
     }
@@ -880,6 +891,12 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ts.table = (const PairTable *)(D + o_tables) + table_of[pool_key(it.pool)];
         ts.active = io->active ? io->active + s : nullptr;
         ts.mf = mf_mode ? mf_dev[table_of[pool_key(it.pool)]] : nullptr;
+        if (mf_mode) {
+            // |psi|^2 before the update: this step's energy reduction
+            ts.n2_prev = io->energy_out + 3 * s + 1;
+            ts.tay_partials = (double *)(D + o_taypart[s]);
+            ts.ntay = ntay[s];
+        }
     }
     std::copy(tables.begin(), tables.end(), A.at<PairTable>(o_tables));
     for (int s = 0; s < B; s++) {

@@ -47,6 +47,12 @@ struct TaylorState {
     int32_t nblocks;
     int32_t renorm;
     const MfTable *mf;         // matrix-free records of the pool (nullable)
+    // renormalisation after the matrix-free update (nullable): |psi|^2 before
+    // the update, and the update blocks' changes of |psi|^2 [ntay]
+    const double *n2_prev;
+    double *tay_partials;
+    int32_t ntay;
+    int32_t pad1;
 };
 
 // Per-state argmax.
@@ -227,6 +233,10 @@ inline size_t screen_real_lds(int64_t dim, int dtype)
 }
 void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                       hipStream_t s);
+// renormalisation after launch_taylor_mf from the pre-update norm and the
+// update's changes (states with n2_prev and tay_partials set)
+void launch_norm_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
+                    hipStream_t s);
 
 int32_t screen_tile_rows(int64_t dim, int dtype);
 int pair_table_build(vqe_ctx *ctx, const vqe_pool *pool, int64_t dim, PairTable *tb,

@@ -728,27 +728,13 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Fused Taylor-5 update on the selected generator's pairs, one thread per
-// owner row, enumerated from the generator's whole-state record.
+// The update of one owner pair e of the record (Eq. 6-8 on the 2x2 block);
+// returns the change of |psi_r|^2 + |psi_c|^2 between the stored values.
 template <int DT>
-__global__ void __launch_bounds__(TAYLOR_ROWS_PER_BLOCK)
-k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks)
+__device__ __forceinline__ double taylor_pair(const TaylorState *stp, const MfRec &rec, uint32_t e)
 {
-    const int2 task = tasks[blockIdx.x];
-    if (task.x < 0)
-        return;
-    const TaylorState *stp = states + task.x;
-    if (VQE_SKIP(*stp))
-        return;
-    const int32_t k = *stp->k;
-    if (k < 0 || k >= stp->M)
-        return;
-    const MfRec &rec = stp->mf->full_recs[k];
-    const int64_t e = (int64_t)task.y * TAYLOR_ROWS_PER_BLOCK + threadIdx.x;
-    if (rec.nfree < 0 || e >= ((int64_t)1 << rec.nfree))
-        return;
     // deposit e into the free bits, then the pivots
-    uint32_t a = 0, fm = rec.free_mask, ee = (uint32_t)e;
+    uint32_t a = 0, fm = rec.free_mask, ee = e;
     while (fm) {
         const uint32_t low = fm & (0u - fm);
         if (ee & 1u)
@@ -771,6 +757,7 @@ k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tas
         cf[q] = cf[q - 1] * theta / (double)q;
     void *psi = stp->psi;
     double2 vr = Elem<DT>::ld(psi, r), vc = Elem<DT>::ld(psi, c);
+    const double before = (vr.x * vr.x + vr.y * vr.y) + (vc.x * vc.x + vc.y * vc.y);
     double2 ar = vr, ac = vc;
 #pragma unroll
     for (int q = 1; q <= 5; q++) {
@@ -785,6 +772,86 @@ k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tas
     }
     Elem<DT>::st(psi, r, ar);
     Elem<DT>::st(psi, c, ac);
+    if (DT == VQE_C64) {
+        // the stored values: FP32 storage rounds
+        ar = make_double2((double)(float)ar.x, (double)(float)ar.y);
+        ac = make_double2((double)(float)ac.x, (double)(float)ac.y);
+    }
+    return (ar.x * ar.x + ar.y * ar.y) + (ac.x * ac.x + ac.y * ac.y) - before;
+}
+
+// Fused Taylor-5 update on the selected generator's pairs, one thread per
+// owner row, enumerated from the generator's whole-state record.  With
+// tay_partials set, each block also writes the change of |psi|^2 over its
+// pairs (from the stored values), so that the renormalisation can take the
+// norm as the pre-update norm plus these changes.
+template <int DT>
+__global__ void __launch_bounds__(TAYLOR_ROWS_PER_BLOCK)
+k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const TaylorState *stp = states + task.x;
+    if (VQE_SKIP(*stp))
+        return;
+    const int32_t k = *stp->k;
+    double dn = 0.0;
+    if (k >= 0 && k < stp->M) {
+        const MfRec &rec = stp->mf->full_recs[k];
+        const int64_t e = (int64_t)task.y * TAYLOR_ROWS_PER_BLOCK + threadIdx.x;
+        if (rec.nfree >= 0 && e < ((int64_t)1 << rec.nfree))
+            dn = taylor_pair<DT>(stp, rec, (uint32_t)e);
+    }
+    if (!stp->tay_partials)
+        return;
+    __shared__ double red[TAYLOR_ROWS_PER_BLOCK / 64];
+    dn = wave_sum(dn);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = dn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < TAYLOR_ROWS_PER_BLOCK / 64; w++)
+            t += red[w];
+        gmem(stp->tay_partials)[task.y] = t;
+    }
+}
+
+// Renormalisation after the fused update: |psi'|^2 = |psi|^2 (from this
+// step's H product) plus the update blocks' changes, summed in block order.
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_norm_scale_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 t = tasks[blockIdx.x];
+    if (t.x < 0)
+        return;
+    const TaylorState *stp = states + t.x;
+    if (VQE_SKIP(*stp))
+        return;
+    __shared__ double s_n2;
+    if (threadIdx.x < 64) {
+        double d = 0.0;
+        for (int b = threadIdx.x; b < stp->ntay; b += 64)
+            d += gmem(stp->tay_partials)[b];
+        d = wave_sum(d);
+        if (threadIdx.x == 0)
+            s_n2 = *stp->n2_prev + d;
+    }
+    __syncthreads();
+    const double n2 = s_n2;
+    if (t.y == 0 && threadIdx.x == 0 && stp->norm2_out)
+        stp->norm2_out[0] = n2;
+    if (!stp->renorm)
+        return;
+    const double inv = 1.0 / sqrt(n2);
+    const int64_t r0 = (int64_t)t.y * NORM_ROWS_PER_BLOCK;
+    const int64_t r1 = r0 + NORM_ROWS_PER_BLOCK < stp->dim ? r0 + NORM_ROWS_PER_BLOCK : stp->dim;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+        const double2 p = Elem<DT>::ld(stp->psi, r);
+        Elem<DT>::st(stp->psi, r, make_double2(p.x * inv, p.y * inv));
+    }
 }
 
 }  // namespace
@@ -815,6 +882,15 @@ void launch_screen_mf_real(int dtype, const ScreenState *states, const int4 *tas
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k_screen_mf_real<VQE_C64><<<grid, 1024, lds, s>>>(states, tasks);
     }
+}
+
+void launch_norm_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
+                    hipStream_t s)
+{
+    if (dtype == VQE_C128)
+        k_norm_scale_mf<VQE_C128><<<grid, 256, 0, s>>>(states, tasks);
+    else
+        k_norm_scale_mf<VQE_C64><<<grid, 256, 0, s>>>(states, tasks);
 }
 
 void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,

@@ -276,6 +276,8 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     }
 }
 
+#define FIN_LDS_G 2048   // gradients per state kept in LDS for the selection
+
 // End of a batched step's screen, one workgroup per state: the energy from
 // the H product's block partials (Eq. 1), the gradients from the screen's
 // tile partials (Eq. 5), then the largest |g_j| with the lowest index among
@@ -307,6 +309,10 @@ k_step_fin(const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ s
             hs.energy_out[2] = im;
         }
     }
+    // the gradients also go to LDS when they fit, for the selection below
+    __shared__ double s_g[FIN_LDS_G];
+    const SelectState ss = sel[s];
+    const bool in_lds = do_grad && ss.M <= FIN_LDS_G;
     if (do_grad) {
         const ScreenState st = screen[s];
         const PairTable tb = tables[st.table];
@@ -315,6 +321,8 @@ k_step_fin(const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ s
             for (int t = 0; t < tb.nt; t++)
                 acc += st.partials[(int64_t)j * tb.nt + t];
             st.g_out[j] = 2.0 * acc;
+            if (in_lds)
+                s_g[j] = 2.0 * acc;
         }
     }
     if (!do_select)
@@ -322,17 +330,17 @@ k_step_fin(const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ s
     __syncthreads();      // the gradients written above are read below
     if (tid >= 64)
         return;
-    const SelectState ss = sel[s];
+    const double *g = in_lds ? s_g : ss.g;
     double gmax = 0.0;
     for (int j = tid; j < ss.M; j += 64)
-        gmax = fmax(gmax, fabs(ss.g[j]));
+        gmax = fmax(gmax, fabs(g[j]));
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
     const double thr = gmax * (1.0 - rel_tie);
     int best = 0x7fffffff;
     for (int j = tid; j < ss.M; j += 64)
-        if (fabs(ss.g[j]) >= thr && j < best)
+        if (fabs(g[j]) >= thr && j < best)
             best = j;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)

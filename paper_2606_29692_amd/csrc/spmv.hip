@@ -1123,6 +1123,7 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
     switch (sched) {
     // the 16-bit column form and the real values exist only in batch plans
     // (tasks non-null)
+    case 16 | R: launch_spmv_pf_t<DT, 16, 2, true, true>(single, states, tasks, grid, s, lds); return;
     case 32 | R: launch_spmv_pf_t<DT, 32, 2, true, true>(single, states, tasks, grid, s, lds); return;
     case 64 | R: launch_spmv_pf_t<DT, 64, 2, true, true>(single, states, tasks, grid, s, lds); return;
     case 32 | R | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 32, 3, true, true>(single, states, tasks, grid, s, lds); return;
@@ -1239,6 +1240,7 @@ bool vqe_valid_schedule(int sched)
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
+    case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
@@ -1266,7 +1268,7 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
     // and runs with 32 or 64 lanes when the state fits LDS
     if ((sched & VQE_SPMV_PREFETCH) &&
         (!(sched & VQE_SPMV_LDS) || H->nnz * (int64_t)vqe_elem_bytes(H->dtype) > 0x7fffff00LL ||
-         (sched & 0xff) < 32))
+         (sched & 0xff) < ((sched & VQE_SPMV_REAL) ? 16 : 32)))
         return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL);
     // the 16-bit column form needs column XOR row below 2^16
     if ((sched & VQE_SPMV_X16) && H->dim > SPMV_X16_MAX_DIM)

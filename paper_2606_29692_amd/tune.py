@@ -26,7 +26,8 @@ CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               32 | _L | _P, 64 | _L | _P, 32 | _L | _P | _D, 64 | _L | _P | _D,
               8 | _L | _P, 16 | _L | _P, 16 | _L | _P | _D,
               32 | _L | _P | _X, 64 | _L | _P | _X, 32 | _L | _P | _D | _X, 64 | _L | _P | _D | _X,
-              32 | _L | _P | _X | _R, 64 | _L | _P | _X | _R, 32 | _L | _P | _D | _X | _R,
+              16 | _L | _P | _X | _R, 32 | _L | _P | _X | _R, 64 | _L | _P | _X | _R,
+              32 | _L | _P | _D | _X | _R,
               64 | _L | _P | _D | _X | _R)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")

@@ -542,3 +542,23 @@ def test_screen_real_and_complex_states(ctx, dtype):
         for i in range(4):
             set_state(i, i % 2 == 0)
     plan.close()
+
+
+def test_context_close_destroys_its_plans():
+    """Closing a context first destroys the batch plans made on it (a plan
+    uses its context's stream until destroyed), so a plan that outlives its
+    context -- say, held by a traceback -- is never destroyed afterwards."""
+    prev = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    c = B.Context(0, stream)
+    s = vs.make_system(vs.SystemSpec(8, 4, "jw", False, 160))
+    d = PB.device_system(c, s, "c128", PB.PoolCache(c, matrix_free=True))
+    plan = PB.make_batch(c, [d])
+    plan.step(update=False)
+    torch.cuda.synchronize()
+    c.close()
+    assert plan.handle is None
+    plan.close()
+    del plan
+    torch.cuda.set_stream(prev)

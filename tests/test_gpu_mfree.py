@@ -1,8 +1,9 @@
 """Matrix-free batch plans: pools applied from their Pauli-derived records.
 
 * the matrix-free screen and update agree with the CSR-pool plan on the same
-  states (energies bit for bit, since the H product is shared; gradients to
-  FP64 rounding; the same selections; states to rounding);
+  states (energies, gradients and states to rounding -- the H product is
+  shared, but the matrix-free plan renormalises with the pre-update norm plus
+  the update's changes instead of a full sum; the same selections);
 * against the FP64 oracle: FP64 storage to 1e-12 along forced trajectories
   (JW and BK, equilibrium and stretched), FP32 storage at 14 qubits (row
   tiles of one and two tile bits) within the FP32 bars;
@@ -64,6 +65,7 @@ def test_matrix_free_equals_csr_plan(ctx, dtype):
     # each pair, which cancel exactly for anti-Hermitian generators
     gtol = 1e-12 if dtype == "c128" else 1e-9
     ptol = 1e-14 if dtype == "c128" else 1e-6
+    etol = 1e-13 if dtype == "c128" else 1e-6
     for t in range(steps):
         print(f"matrix-free vs CSR plan {dtype} step {t}", flush=True)
         th = torch.from_numpy(thetas[:, t])
@@ -71,7 +73,8 @@ def test_matrix_free_equals_csr_plan(ctx, dtype):
         pb.theta.copy_(th)
         pa.step(renorm=True)
         pb.step(renorm=True)
-        np.testing.assert_array_equal(host(pb.energies), host(pa.energies))
+        ea, eb = host(pa.energies), host(pb.energies)
+        np.testing.assert_allclose(eb, ea, rtol=0, atol=etol * max(1.0, np.abs(ea).max()))
         np.testing.assert_array_equal(host(pb.k), host(pa.k))
         for i in range(len(specs)):
             ga, gb = host(pa.gradients(i)), host(pb.gradients(i))
