@@ -332,7 +332,7 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
     if (p->mf && p->n_screen1_tasks)
         launch_screen_mf_real(p->dtype, p->d_screen, p->d_screen1_tasks, p->n_screen1_tasks,
                               p->screen1_lds, s);
-    if (p->mf)
+    else if (p->mf)
         launch_screen_mf(p->dtype, p->d_screen, p->d_screen_tasks, p->n_screen_tasks,
                          p->screen_lds, s);
     else if (p->n_screen_tasks)
@@ -635,7 +635,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     const size_t o_l = o_f + vqe_align(hp.full_recs.size() * sizeof(MfRec));
     const size_t o_d = o_l + vqe_align(hp.lists.size() * sizeof(int32_t) + 4);
     const size_t o_x = o_d + vqe_align((size_t)hp.M * sizeof(vqe_mf_desc));
-    const size_t bytes = o_x + vqe_align(hp.tabs.size() * sizeof(uint32_t) + 4);
+    const size_t o_i = o_x + vqe_align(hp.tabs.size() * sizeof(uint32_t) + 4);
+    const size_t bytes = o_i + vqe_align(hp.list_info.size() * sizeof(int4) + 16);
     char *mem = nullptr;
     if (hipMalloc((void **)&mem, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -649,6 +650,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     h.lists = (const int32_t *)(mem + o_l);
     h.desc = (const vqe_mf_desc *)(mem + o_d);
     h.tabs = (const uint32_t *)(mem + o_x);
+    h.linfo = (const int4 *)(mem + o_i);
+    h.nlists = (int32_t)hp.list_info.size();
     h.M = hp.M;
     h.ntile = hp.ntile;
     h.tile_rows = hp.tile_rows;
@@ -665,6 +668,12 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     if (e == hipSuccess && !hp.tabs.empty())
         e = hipMemcpy(mem + o_x, hp.tabs.data(), hp.tabs.size() * sizeof(uint32_t),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hp.list_info.empty()) {
+        std::vector<int4> li;
+        for (const auto &L : hp.list_info)
+            li.push_back(make_int4(L.off, L.len, L.v, 0));
+        e = hipMemcpy(mem + o_i, li.data(), li.size() * sizeof(int4), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) {
         std::vector<vqe_mf_desc> dd(hp.M);
         for (int j = 0; j < hp.M; j++)
@@ -777,7 +786,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     auto screen_flat = interleave(screen_per, make_int4(-1, 0, 0, 0));
     const size_t o_stasks = A.take(screen_flat.size() * sizeof(int4));
     // real-state screen: four workgroups per state (one per CU for 64
-    // states), generators dealt over them by descending cost; a flag per state
+    // states), generators dealt over them by descending cost; a complex state
+    // runs the tiled screen's lists in the same workgroups, so the LDS holds
+    // either form
     std::vector<std::vector<int4>> screen1_per(kXcd);
     if (real_screen)
         for (int s = 0; s < B; s++) {
@@ -787,11 +798,11 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
                 for (int r = 0; r < nr; r++)
                     screen1_per[xcd_of[s]].push_back(make_int4(s, L.off, L.len, r | (nr << 8)));
             }
-            p->screen1_lds = std::max(p->screen1_lds, screen_real_lds(items[s].H->dim, dtype));
+            p->screen1_lds = std::max({p->screen1_lds, screen_real_lds(items[s].H->dim, dtype),
+                                       p->screen_lds});
         }
     auto screen1_flat = interleave(screen1_per, make_int4(-1, 0, 0, 0));
     const size_t o_s1tasks = A.take(screen1_flat.size() * sizeof(int4) + 16);
-    const size_t o_cplx = A.take((size_t)B * sizeof(int32_t));
 
     // --- Taylor and norm tasks (matrix-free records or compact tables: blocks
     //     cover the largest generator's pairs; otherwise the CSR rows)
@@ -912,7 +923,6 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         ss.mf = mf_mode ? mf_dev[table_of[pool_key(items[s].pool)]] : nullptr;
         ss.mf_ntile = tables[table_of[pool_key(items[s].pool)]].nt;
         ss.mf1 = real_screen ? mf_dev1[table_of[pool_key(items[s].pool)]] : nullptr;
-        ss.cplx = real_screen ? (int32_t *)(D + o_cplx) + s : nullptr;
     }
     for (size_t i = 0; i < spmv_tab.size(); i++) {
         std::copy(spmv_lists[i].begin(), spmv_lists[i].end(), A.at<int2>(spmv_tab[i].second));

@@ -92,11 +92,8 @@ struct ScreenState {
     int32_t table;          // index into the plan's PairTable array
     int32_t mf_ntile;       // row tiles of the matrix-free screen (partials per generator)
     const MfTable *mf;      // matrix-free records of the pool (nullable)
-    // real-state screen (nullable): the pool's records on one whole-state
-    // tile, and the state's flag, set by that screen when psi or sigma has a
-    // nonzero imaginary part (the tiled screen then covers the state)
+    // real-state screen (nullable): the pool's records on one whole-state tile
     const MfTable *mf1;
-    int32_t *cplx;
 };
 
 // Matrix-free enumeration of a generator's pairs {r, c = r ^ x} on a row set
@@ -138,7 +135,8 @@ struct MfTable {
     // MF_TAB_ITER entries then one per loop iteration; an entry is a
     // compressed (tile) row index part with its sign parity in bit 31
     const uint32_t *tabs;
-    int32_t M, ntile, tile_rows, pad;
+    const int4 *linfo;        // per list: offset into lists, length, tile, 0
+    int32_t M, ntile, tile_rows, nlists;
 };
 // table layout of one tile record: 64 lane parts, MF_LANE_UNROLL unroll parts,
 // then the iteration parts

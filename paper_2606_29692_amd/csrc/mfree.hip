@@ -571,27 +571,17 @@ __device__ __forceinline__ double mf_tile_sum_real(const R2 *tile, const MfRec &
     return sre;
 }
 
-// One workgroup per (state, tile-bit group, tile, generator range): stage the
-// tile's psi and sigma in LDS, then one wave per generator.
+// One list of the tiled screen (generators sharing their tile bits, on tile
+// v of those bits) for one workgroup: stage the tile's psi and sigma in LDS,
+// then one wave per generator of the workgroup's share (range, range +
+// n_ranges, ...) writes that generator's tile partial.
 template <int DT>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
-k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tasks)
+__device__ __forceinline__ void screen_list(const ScreenState &st, int off, int n, int range,
+                                            int n_ranges, int v, unsigned char *smem)
 {
-    const int4 task = tasks[blockIdx.x];
-    if (task.x < 0)
-        return;
-    const ScreenState st = states[task.x];
-    if (VQE_SKIP(st))
-        return;
-    // a state the real-state screen has covered
-    if (st.cplx && *st.cplx == 0)
-        return;
-    const MfTable tb = *st.mf;
-    const int32_t *list = tb.lists + task.y;
-    const int n = task.z;
-    const int range = task.w & 0xff, n_ranges = (task.w >> 8) & 0xff, v = task.w >> 16;
+    const MfTable &tb = *st.mf;
+    const int32_t *list = tb.lists + off;
     using T = typename TileElem<DT>::T;
-    extern __shared__ unsigned char smem[];
     T *tile = reinterpret_cast<T *>(smem);
     const MfRec &r0 = tb.tile_recs[(int64_t)list[0] * tb.ntile + v];
     const int64_t rows = tb.tile_rows;
@@ -652,11 +642,28 @@ k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tas
     }
 }
 
+
+// One workgroup per (state, tile-bit group, tile, generator range).
+template <int DT>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_screen_mf(const ScreenState *__restrict__ states, const int4 *__restrict__ tasks)
+{
+    const int4 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const ScreenState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    extern __shared__ unsigned char smem[];
+    screen_list<DT>(st, task.y, task.z, task.w & 0xff, (task.w >> 8) & 0xff, task.w >> 16, smem);
+}
+
 // Real-state screen: one workgroup per (state, generator range) stages the
 // whole state as (psi.re, sigma.re) pairs; when every imaginary part is zero
 // one wave per generator forms its gradient in real arithmetic and writes it
-// as the tiled screen's tile-0 partial (the other tiles' partials zero).  A
-// state with a nonzero imaginary part is flagged and left to the tiled screen.
+// as the tiled screen's tile-0 partial (the other tiles' partials zero).  For
+// a state with a nonzero imaginary part the state's workgroups run the tiled
+// screen instead, every list of it, each taking its share of each list.
 template <int DT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_screen_mf_real(const ScreenState *__restrict__ states, const int4 *__restrict__ tasks)
@@ -703,10 +710,15 @@ k_screen_mf_real(const ScreenState *__restrict__ states, const int4 *__restrict_
         }
     }
     cplx = __syncthreads_or(cplx);
-    if (threadIdx.x == 0 && range == 0)
-        *st.cplx = cplx ? 1 : 0;
-    if (cplx)
+    if (cplx) {
+        const MfTable &tc = *st.mf;
+        for (int i = 0; i < tc.nlists; i++) {
+            const int4 L = tc.linfo[i];
+            __syncthreads();      // every wave is done with the previous tile
+            screen_list<DT>(st, L.x, L.y, range, n_ranges, L.z, smem);
+        }
         return;
+    }
     const int ntc = st.mf_ntile;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int idx = wid;; idx += 16) {
