@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <numeric>
@@ -790,11 +791,14 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     // runs the tiled screen's lists in the same workgroups, so the LDS holds
     // either form
     std::vector<std::vector<int4>> screen1_per(kXcd);
+    int split = 4;
+    if (const char *e = std::getenv("ADAPTVQE_SCREEN_WG"))
+        split = std::max(1, std::min(64, std::atoi(e)));
     if (real_screen)
         for (int s = 0; s < B; s++) {
             const MfHostPlan &hp1 = mf_plans1[table_of[pool_key(items[s].pool)]];
             for (auto &L : hp1.list_info) {
-                const int nr = std::max(1, std::min(L.len, 4));
+                const int nr = std::max(1, std::min(L.len, split));
                 for (int r = 0; r < nr; r++)
                     screen1_per[xcd_of[s]].push_back(make_int4(s, L.off, L.len, r | (nr << 8)));
             }

@@ -546,29 +546,49 @@ __device__ __forceinline__ double mf_tile_sum_real(const R2 *tile, const MfRec &
     }
     const double e1 = uni(rec.ex) ? -1.0 : 1.0;
     const int n_it = 1 << ((int)uni((uint32_t)rec.nfree) - nlow);
+    // two loop iterations per pass (their gathers in flight together), each
+    // with its own accumulator
+    double sre1 = 0.0;
+    auto iter = [&](uint32_t hi, R2 er[U], R2 ec[U]) {
+        const uint32_t ch = hi & 0x7fffffffu;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t ir = on[u] ? (cl[u] ^ ch) : 0u, ic = on[u] ? (ir ^ cx) : 0u;
+            er[u] = tile[ir];
+            ec[u] = tile[ic];
+        }
+    };
+    auto acc = [&](uint32_t hi, const R2 er[U], const R2 ec[U], double &a) {
+        const uint32_t sh = hi >> 31;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const double tr = e1 * ((double)er[u].y * (double)ec[u].x) +
+                              (double)ec[u].y * (double)er[u].x;
+            const bool neg = (sl[u] ^ sh) & 1u;
+            a += (on[u] ? (neg ? -1.0 : 1.0) : 0.0) * tr;
+        }
+    };
     for (int c0 = 0; c0 < n_it; c0 += 64) {
         const uint32_t hv = c0 + lane < n_it ? gmem(t)[MF_TAB_ITER + c0 + lane] : 0u;
         const int nin = n_it - c0 < 64 ? n_it - c0 : 64;
-        for (int i = 0; i < nin; i++) {
-            const uint32_t hi = __builtin_amdgcn_readlane(hv, i);
-            const uint32_t ch = hi & 0x7fffffffu, sh = hi >> 31;
-            R2 er[U], ec[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const uint32_t ir = on[u] ? (cl[u] ^ ch) : 0u, ic = on[u] ? (ir ^ cx) : 0u;
-                er[u] = tile[ir];
-                ec[u] = tile[ic];
-            }
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const double tr = e1 * ((double)er[u].y * (double)ec[u].x) +
-                                  (double)ec[u].y * (double)er[u].x;
-                const bool neg = (sl[u] ^ sh) & 1u;
-                sre += (on[u] ? (neg ? -1.0 : 1.0) : 0.0) * tr;
-            }
+        int i = 0;
+        for (; i + 1 < nin; i += 2) {
+            const uint32_t h0 = __builtin_amdgcn_readlane(hv, i);
+            const uint32_t h1 = __builtin_amdgcn_readlane(hv, i + 1);
+            R2 er0[U], ec0[U], er1[U], ec1[U];
+            iter(h0, er0, ec0);
+            iter(h1, er1, ec1);
+            acc(h0, er0, ec0, sre);
+            acc(h1, er1, ec1, sre1);
+        }
+        if (i < nin) {
+            const uint32_t h0 = __builtin_amdgcn_readlane(hv, i);
+            R2 er0[U], ec0[U];
+            iter(h0, er0, ec0);
+            acc(h0, er0, ec0, sre);
         }
     }
-    return sre;
+    return sre + sre1;
 }
 
 // One list of the tiled screen (generators sharing their tile bits, on tile
@@ -685,6 +705,9 @@ k_screen_mf_real(const ScreenState *__restrict__ states, const int4 *__restrict_
     const T *psi = reinterpret_cast<const T *>(st.psi);
     const T *sig = reinterpret_cast<const T *>(st.sigma);
     const int64_t rows = st.dim;
+    __shared__ int s_next;
+    if (threadIdx.x == 0)
+        s_next = 0;
     int cplx = 0;
     constexpr int SU = 8;
     for (int64_t i0 = threadIdx.x; i0 < rows; i0 += 1024 * SU) {
@@ -720,8 +743,14 @@ k_screen_mf_real(const ScreenState *__restrict__ states, const int4 *__restrict_
         return;
     }
     const int ntc = st.mf_ntile;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int idx = wid;; idx += 16) {
+    const int lane = threadIdx.x & 63;
+    // waves take the workgroup's generators from a counter, in the list's
+    // descending-cost order, so that they finish together
+    for (;;) {
+        int idx = 0;
+        if (lane == 0)
+            idx = atomicAdd(&s_next, 1);
+        idx = __builtin_amdgcn_readfirstlane(idx);
         const int e = range + idx * n_ranges;
         if (e >= n)
             break;
