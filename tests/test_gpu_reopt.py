@@ -144,8 +144,11 @@ def test_adapt_with_reopt_reaches_sector_ground_state(ctx):
     assert e_next[0] >= e_exact - 1e-12
 
 
-# the default schedule, and the benchmark's (pipelined, 16-bit column codes)
-@pytest.mark.parametrize("sched", [0, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16])
+# the default schedule, the pipelined one with 16-bit column codes, and the
+# benchmark's (the same with the real values of the real H)
+@pytest.mark.parametrize("sched", [0, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16,
+                                   32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
+                                   B.VQE_SPMV_REAL])
 def test_reopt_fp32_14_qubits(ctx, sched):
     sp, _ = vs.config_c4(n_states=2, mixed=False)
     systems = [vs.make_system(s) for s in sp]

@@ -18,7 +18,10 @@ torch = pytest.importorskip("torch")
 from paper_2606_29692_amd import binding as B  # noqa: E402
 from paper_2606_29692_amd import serve as S  # noqa: E402
 
-SCHED = {(8, 4, "jw"): 16, (10, 4, "jw"): 32, (12, 8, "jw"): 32 | B.VQE_SPMV_LDS}
+# (10 qubits: codes and real values, rebuilt on every rebind of a slot)
+SCHED = {(8, 4, "jw"): 16,
+         (10, 4, "jw"): 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 | B.VQE_SPMV_REAL,
+         (12, 8, "jw"): 32 | B.VQE_SPMV_LDS}
 
 
 def make_runs():
