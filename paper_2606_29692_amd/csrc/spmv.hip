@@ -818,41 +818,24 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
 // sorted within a row, bounded by the per-tile row pointers.  The row sums of
 // a tile go to an FP64 partial array; the tile-sum kernel adds the tiles in
 // ascending order and applies the energy epilogue.
-template <int DT, int L, int D, int U, bool X16, bool RV>
-__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
-k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+// The rows [r0, r1) of one column tile t of the column-tiled schedule, the
+// tile staged in LDS at smem (complex, or with RX its real parts in FP64) and
+// the rows' tile bounds at s_k0, s_k1; writes the FP64 tile partials.
+template <int DT, int L, int D, int U, bool X16, bool RV, bool RX>
+__device__ __forceinline__ void tiled_rows(const SpmvState &st, int t, const unsigned char *smem,
+                                           const int32_t *s_k0, const int32_t *s_k1, int64_t r0,
+                                           int64_t r1)
 {
-    const int2 task = tasks[blockIdx.x];
-    if (task.x < 0)
-        return;
-    const SpmvState st = states[task.x];
-    if (VQE_SKIP(st))
-        return;
-    const int blk = task.y >> 8, t = task.y & 0xff;
-    using T = typename Elem<DT>::T;
+    using X = typename std::conditional<RX, double, typename Elem<DT>::T>::type;
     constexpr int W = U * 4;
     constexpr int PASS = W * L;
     using V = typename ValOf<DT, RV>::T;
     constexpr unsigned EB = sizeof(V);
-    extern __shared__ unsigned char smem[];
-    T *s_x = reinterpret_cast<T *>(smem);
+    const X *s_x = reinterpret_cast<const X *>(smem);
     const int tid = threadIdx.x;
     const int64_t dim = st.dim;
     const int tc = st.tile_cols;
     const int c_lo = t * tc;
-    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
-    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
-    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
-    // the tile, one zero element (index tc), then the block's tile bounds
-    int32_t *s_k0 = reinterpret_cast<int32_t *>(smem + (size_t)(tc + 1) * sizeof(T));
-    int32_t *s_k1 = s_k0 + SPMV_LDS_ROWS;
-    stage_lds<8>(s_x, psi + c_lo, (int64_t)tc, tid);
-    if (tid == 0)
-        s_x[tc] = T{};
-    stage_lds<2>(s_k0, st.tptr + (int64_t)t * dim + r0, r1 - r0, tid);
-    stage_lds<2>(s_k1, st.tptr + (int64_t)(t + 1) * dim + r0, r1 - r0, tid);
-    __syncthreads();
-
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
@@ -904,7 +887,7 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
                 const int cl = (X16 ? (rx ^ c[4 * u + q]) : c[4 * u + q]) - c_lo;
                 cm[4 * u + q] = ((unsigned)(k - k0) < len && (unsigned)cl < (unsigned)tc) ? cl : zc;
             }
-        lds_gather_fma<T, V, W>(s_x, cm, v, are, aim);
+        lds_gather_fma<X, V, W>(s_x, cm, v, are, aim);
     };
     auto row_bounds = [&](int64_t r, int &k0, int &k1) {
         if (r < r1) {
@@ -930,7 +913,8 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
             }
         }
         are = group_sum<L>(are);
-        aim = group_sum<L>(aim);
+        if (!RX)
+            aim = group_sum<L>(aim);
         if (sl == 0 && r < r1) {
             gmem(part)[2 * r] = are;
             gmem(part)[2 * r + 1] = aim;
@@ -963,6 +947,53 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
         }
     }
 }
+
+
+template <int DT, int L, int D, int U, bool X16, bool RV>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
+k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const SpmvState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    const int blk = task.y >> 8, t = task.y & 0xff;
+    using T = typename Elem<DT>::T;
+    extern __shared__ unsigned char smem[];
+    T *s_x = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x;
+    const int64_t dim = st.dim;
+    const int tc = st.tile_cols;
+    const int c_lo = t * tc;
+    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
+    // the tile, one zero element (index tc), then the block's tile bounds
+    int32_t *s_k0 = reinterpret_cast<int32_t *>(smem + (size_t)(tc + 1) * sizeof(T));
+    int32_t *s_k1 = s_k0 + SPMV_LDS_ROWS;
+    stage_lds<2>(s_k0, st.tptr + (int64_t)t * dim + r0, r1 - r0, tid);
+    stage_lds<2>(s_k1, st.tptr + (int64_t)(t + 1) * dim + r0, r1 - r0, tid);
+    if constexpr (RV) {
+        // a tile with no imaginary part runs in real arithmetic (the tile's
+        // partial sums involve only its own columns)
+        double *s_xr = reinterpret_cast<double *>(smem);
+        const int cplx = stage_real<8>(s_xr, psi + c_lo, (int64_t)tc, tid);
+        if (tid == 0)
+            s_xr[tc] = 0.0;
+        if (!__syncthreads_or(cplx)) {
+            tiled_rows<DT, L, D, U, X16, RV, true>(st, t, smem, s_k0, s_k1, r0, r1);
+            return;
+        }
+    }
+    stage_lds<8>(s_x, psi + c_lo, (int64_t)tc, tid);
+    if (tid == 0)
+        s_x[tc] = T{};
+    __syncthreads();
+    tiled_rows<DT, L, D, U, X16, RV, false>(st, t, smem, s_k0, s_k1, r0, r1);
+}
+
 
 // sigma_r = sum over tiles (ascending) of the tile partials; the energy sums.
 template <int DT>
