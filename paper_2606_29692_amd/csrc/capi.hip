@@ -13,6 +13,7 @@
 // the selected index and every result live in caller-owned device buffers, so
 // a replay needs no host round trip.
 #include "kernels.hpp"
+#include "step_fin.hpp"
 
 #include <algorithm>
 #include <cstdlib>
@@ -147,6 +148,7 @@ struct vqe_batch {
     PairTable *d_tables = nullptr;
     int4 *d_screen_tasks = nullptr;
     unsigned n_screen_tasks = 0;
+    int32_t max_m = 0;          // largest pool of the plan
     size_t screen_lds = 0;
     // real-state screen (matrix-free pools of real anti-Hermitian generators
     // whose states fit one LDS tile as reals): tasks per (state, range)
@@ -339,8 +341,13 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
     else if (p->n_screen_tasks)
         launch_screen(p->dtype, p->d_screen, p->d_tables, p->d_screen_tasks, p->n_screen_tasks,
                       (unsigned)p->B, p->screen_lds, s);
-    launch_step_fin(p->d_spmv, p->d_screen, p->d_tables, p->d_sel, (unsigned)p->B, grad,
-                    !(flags & VQE_STEP_FORCED), p->rel_tie, s);
+    // without a line search the matrix-free update does the finalisation
+    // itself (one kernel boundary less)
+    const bool fused_fin = p->mf && p->max_m <= FIN_LDS_G && !(flags & VQE_STEP_NO_UPDATE) &&
+                           !(flags & VQE_STEP_LINESEARCH);
+    if (!fused_fin)
+        launch_step_fin(p->d_spmv, p->d_screen, p->d_tables, p->d_sel, (unsigned)p->B, grad,
+                        !(flags & VQE_STEP_FORCED), p->rel_tie, s);
     rc = rc ? rc : mark(3);
     rc = rc ? rc : mark(4);
     if ((flags & VQE_STEP_LINESEARCH) && !(flags & VQE_STEP_NO_UPDATE)) {
@@ -353,7 +360,11 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
         launch_ls_solve(p->d_ls, (unsigned)p->B, s);
     }
     if (!(flags & VQE_STEP_NO_UPDATE)) {
-        if (p->mf)
+        if (fused_fin)
+            launch_taylor_mf_fin(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, p->d_spmv,
+                                 p->d_screen, p->d_tables, p->d_sel, !(flags & VQE_STEP_FORCED),
+                                 p->rel_tie, s);
+        else if (p->mf)
             launch_taylor_mf(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
         else if (p->compact_taylor)
             launch_taylor_compact(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
@@ -964,6 +975,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         p->xcd.push_back(xcd_of[s]);
     }
     p->tables_host = tables;
+    for (const PairTable &t : tables)
+        p->max_m = std::max(p->max_m, t.M);
     if (mf_mode) {
         p->mf_host.assign(tables.size(), nullptr);
         for (int s = 0; s < B; s++)

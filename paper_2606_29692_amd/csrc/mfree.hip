@@ -23,6 +23,7 @@
 // part (wave-uniform, on the scalar unit): the inner loop is two XORs and two
 // LDS reads per pair.
 #include "kernels.hpp"
+#include "step_fin.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -825,10 +826,16 @@ __device__ __forceinline__ double taylor_pair(const TaylorState *stp, const MfRe
 // owner row, enumerated from the generator's whole-state record.  With
 // tay_partials set, each block also writes the change of |psi|^2 over its
 // pairs (from the stored values), so that the renormalisation can take the
-// norm as the pre-update norm plus these changes.
-template <int DT>
+// norm as the pre-update norm plus these changes.  With FIN every workgroup
+// first forms the step's finalisation for its state (energy, gradients,
+// selection; stored by the state's first workgroup) and updates along the
+// generator it selects.
+template <int DT, bool FIN>
 __global__ void __launch_bounds__(TAYLOR_ROWS_PER_BLOCK)
-k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks)
+k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks,
+            const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ screen,
+            const PairTable *__restrict__ tables, const SelectState *__restrict__ sel,
+            int do_select, double rel_tie)
 {
     const int2 task = tasks[blockIdx.x];
     if (task.x < 0)
@@ -836,7 +843,16 @@ k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tas
     const TaylorState *stp = states + task.x;
     if (VQE_SKIP(*stp))
         return;
-    const int32_t k = *stp->k;
+    int32_t k;
+    if (FIN) {
+        const SpmvState hs = spmv[task.x];
+        k = step_fin_block(hs, screen, tables, sel[task.x], task.x, true, do_select != 0,
+                           rel_tie, task.y == 0);
+        if (!do_select)
+            k = *stp->k;
+    } else {
+        k = *stp->k;
+    }
     double dn = 0.0;
     if (k >= 0 && k < stp->M) {
         const MfRec &rec = stp->mf->full_recs[k];
@@ -938,9 +954,24 @@ void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, u
                       hipStream_t s)
 {
     if (dtype == VQE_C128)
-        k_taylor_mf<VQE_C128><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(states, tasks);
+        k_taylor_mf<VQE_C128, false><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
+            states, tasks, nullptr, nullptr, nullptr, nullptr, 0, 0.0);
     else
-        k_taylor_mf<VQE_C64><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(states, tasks);
+        k_taylor_mf<VQE_C64, false><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
+            states, tasks, nullptr, nullptr, nullptr, nullptr, 0, 0.0);
+}
+
+void launch_taylor_mf_fin(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
+                          const SpmvState *spmv, const ScreenState *screen,
+                          const PairTable *tables, const SelectState *sel, bool select,
+                          double rel_tie, hipStream_t s)
+{
+    if (dtype == VQE_C128)
+        k_taylor_mf<VQE_C128, true><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
+            states, tasks, spmv, screen, tables, sel, select ? 1 : 0, rel_tie);
+    else
+        k_taylor_mf<VQE_C64, true><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
+            states, tasks, spmv, screen, tables, sel, select ? 1 : 0, rel_tie);
 }
 
 // ------------------------------------------------------------------ C ABI

@@ -15,6 +15,7 @@
 // Sums are FP64: per generator and tile, one wave (lane-strided partial sums,
 // then a butterfly), then tiles in ascending order.
 #include "kernels.hpp"
+#include "step_fin.hpp"
 
 #include <algorithm>
 #include <vector>
@@ -276,13 +277,7 @@ k_screen(const ScreenState *__restrict__ states, const PairTable *__restrict__ t
     }
 }
 
-#define FIN_LDS_G 2048   // gradients per state kept in LDS for the selection
-
-// End of a batched step's screen, one workgroup per state: the energy from
-// the H product's block partials (Eq. 1), the gradients from the screen's
-// tile partials (Eq. 5), then the largest |g_j| with the lowest index among
-// the near-ties.  The energy is summed exactly as the single-call energy
-// finalisation sums it, and g_j adds its tile partials in tile order.
+// One workgroup per state.
 __global__ void __launch_bounds__(256)
 k_step_fin(const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ screen,
            const PairTable *__restrict__ tables, const SelectState *__restrict__ sel,
@@ -292,63 +287,7 @@ k_step_fin(const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ s
     const SpmvState hs = spmv[s];
     if (VQE_SKIP(hs))
         return;
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        double re = 0.0, im = 0.0, n2 = 0.0;
-        for (int b = tid; b < hs.nblocks; b += 64) {
-            re += hs.partials[(int64_t)b * 3 + 0];
-            im += hs.partials[(int64_t)b * 3 + 1];
-            n2 += hs.partials[(int64_t)b * 3 + 2];
-        }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        n2 = wave_sum(n2);
-        if (tid == 0 && hs.energy_out) {
-            hs.energy_out[0] = hs.shift + re / n2;
-            hs.energy_out[1] = n2;
-            hs.energy_out[2] = im;
-        }
-    }
-    // the gradients also go to LDS when they fit, for the selection below
-    __shared__ double s_g[FIN_LDS_G];
-    const SelectState ss = sel[s];
-    const bool in_lds = do_grad && ss.M <= FIN_LDS_G;
-    if (do_grad) {
-        const ScreenState st = screen[s];
-        const PairTable tb = tables[st.table];
-        for (int j = tid; j < tb.M; j += 256) {
-            double acc = 0.0;
-            for (int t = 0; t < tb.nt; t++)
-                acc += st.partials[(int64_t)j * tb.nt + t];
-            st.g_out[j] = 2.0 * acc;
-            if (in_lds)
-                s_g[j] = 2.0 * acc;
-        }
-    }
-    if (!do_select)
-        return;
-    __syncthreads();      // the gradients written above are read below
-    if (tid >= 64)
-        return;
-    const double *g = in_lds ? s_g : ss.g;
-    double gmax = 0.0;
-    for (int j = tid; j < ss.M; j += 64)
-        gmax = fmax(gmax, fabs(g[j]));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
-    const double thr = gmax * (1.0 - rel_tie);
-    int best = 0x7fffffff;
-    for (int j = tid; j < ss.M; j += 64)
-        if (fabs(g[j]) >= thr && j < best)
-            best = j;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        best = min(best, __shfl_xor(best, o, 64));
-    if (tid == 0) {
-        ss.k_out[0] = best == 0x7fffffff ? 0 : best;
-        ss.gmax_out[0] = gmax;
-    }
+    (void)step_fin_block(hs, screen, tables, sel[s], s, do_grad != 0, do_select != 0, rel_tie, true);
 }
 
 }  // namespace
