@@ -96,9 +96,9 @@ def stored_h_bytes(sched: int, ds) -> int:
         vb = d.H.val.element_size() // (2 if rv else 1)
         nnz = d.H.nnz
         if rv and d.H.dim * d.psi.element_size() <= 147 * 1024:
-            # the padded layout: every row rounded up to a multiple of four
+            # the padded layout: every row rounded up to a multiple of eight
             lens = np.diff(d.H.rowptr.cpu().numpy().astype(np.int64))
-            nnz = int(((lens + 3) // 4 * 4).sum())
+            nnz = int(((lens + 7) // 8 * 8).sum())
         tot += 4 * (d.H.dim + 1) + nnz * (cb + vb) + 2 * d.H.dim * d.psi.element_size()
     return tot
 

@@ -271,7 +271,7 @@ int codes_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     const int64_t rb = (int64_t)vqe_elem_bytes(H->dtype) / 2;
     int rc;
     if ((sched & VQE_SPMV_REAL) && !(sched & VQE_SPMV_TILED)) {
-        const int64_t cap = H->nnz + 3 * H->dim + 4;
+        const int64_t cap = H->nnz + (SPMV_PAD - 1) * H->dim + SPMV_PAD;
         if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], cap * 2, "column codes", s)) ||
             (rc = grow(p, &p->vre[s], &p->vre_cap[s], cap * rb, "real values", s)) ||
             (rc = grow(p, &p->prow[s], &p->prow_cap[s], (H->dim + 1) * 4, "row pointers", s)))

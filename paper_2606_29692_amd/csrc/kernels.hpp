@@ -280,7 +280,7 @@ void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s);
 void launch_val_real(const vqe_csr *H, void *out, hipStream_t s);
 // padded layout of H (dim <= SPMV_X16_MAX_DIM): prow[dim + 1], the 16-bit
 // codes and the real parts of the values with every row rounded up to a
-// multiple of four entries (room for nnz + 3 dim entries)
+// multiple of SPMV_PAD entries (room for nnz + (SPMV_PAD - 1) dim entries)
 void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vre, hipStream_t s);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 

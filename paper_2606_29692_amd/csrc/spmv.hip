@@ -538,7 +538,7 @@ k_col_xor16(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
 }
 
 // Row pointers of the padded layout, in which every row's length is rounded up
-// to a multiple of four.  One workgroup: each thread takes a contiguous run of
+// to a multiple of SPMV_PAD.  One workgroup: each thread takes a contiguous run of
 // rows, the workgroup scans the run totals, and each thread writes its run.
 __global__ void __launch_bounds__(1024)
 k_pad_rowptr(const int32_t *__restrict__ rowptr, int32_t *__restrict__ prow, int64_t dim)
@@ -550,7 +550,7 @@ k_pad_rowptr(const int32_t *__restrict__ rowptr, int32_t *__restrict__ prow, int
     const int64_t b = a + per < dim ? a + per : dim;
     int64_t tot = 0;
     for (int64_t r = a; r < b; r++)
-        tot += (rowptr[r + 1] - rowptr[r] + 3) & ~3;
+        tot += (rowptr[r + 1] - rowptr[r] + SPMV_PAD - 1) & ~(SPMV_PAD - 1);
     s_sum[tid] = tot;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -562,7 +562,7 @@ k_pad_rowptr(const int32_t *__restrict__ rowptr, int32_t *__restrict__ prow, int
     int64_t run = s_sum[tid] - tot;
     for (int64_t r = a; r < b; r++) {
         prow[r] = (int32_t)run;
-        run += (rowptr[r + 1] - rowptr[r] + 3) & ~3;
+        run += (rowptr[r + 1] - rowptr[r] + SPMV_PAD - 1) & ~(SPMV_PAD - 1);
     }
     if (tid == 1023)
         prow[dim] = (int32_t)s_sum[1023];
@@ -605,10 +605,11 @@ k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
 // entry k of row r is read as the 16-bit code col16[k] = col[k] ^ r (8 bytes
 // per group of four instead of 16), for states of at most 2^16 rows.  With
 // RV (operators whose entries are all real) the codes and values are the
-// plan's padded layout: each row starts at a multiple of four and is padded
+// plan's padded layout: each row starts at a multiple of eight and is padded
 // with zero values to whole groups (row pointers st.prow), so no entry needs
-// a row mask and there is no tail; the values are the real parts, 4 instead
-// of 8 bytes per entry in FP32 storage.
+// a row mask and there is no tail, and a lane takes eight entries with one
+// 16-byte code load; the values are the real parts, 4 instead of 8 bytes per
+// entry in FP32 storage.
 // The rows [r0, r1) of one workgroup of the pipelined LDS schedule, the state
 // already staged in LDS at smem (complex, or with RX its real parts in FP64)
 // and the row pointers at s_rp; writes sigma and the workgroup's energy
@@ -619,8 +620,11 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
 {
     using T = typename Elem<DT>::T;
     using X = typename std::conditional<RX, double, T>::type;
-    constexpr int U = 64 / L;
-    constexpr int W = U * 4;                 // entries per lane per pass
+    // a lane's group: 4 entries, or 8 in the padded layout (one 16-byte code
+    // load and 16-byte value loads)
+    constexpr int GE = RV ? SPMV_PAD : 4;
+    constexpr int U = 256 / (L * GE) > 0 ? 256 / (L * GE) : 1;
+    constexpr int W = U * GE;                // entries per lane per pass
     constexpr int PASS = W * L;              // entries per sub-group per pass
     using V = typename ValOf<DT, RV>::T;
     constexpr unsigned EB = sizeof(V);
@@ -645,24 +649,35 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
     auto issue = [&](int kb, int k1, int c[W], V v[W]) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int k = kb + u * 4 * L;
+            const int k = kb + u * GE * L;
             const bool ok = k < k1 && k < whole;
-            if (X16) {
+            if (X16 && GE == 8) {
+                typedef unsigned v4u __attribute__((ext_vector_type(4)));
+                const v4u c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 2u : VQE_BUF_OOB, 0, 0);
+                const unsigned cw[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    c[GE * u + 2 * q] = (int)(cw[q] & 0xffffu);
+                    c[GE * u + 2 * q + 1] = (int)(cw[q] >> 16);
+                }
+            } else if (X16) {
                 typedef unsigned v2u __attribute__((ext_vector_type(2)));
                 const v2u c2 = __builtin_amdgcn_raw_buffer_load_b64(rc, ok ? (unsigned)k * 2u : VQE_BUF_OOB, 0, 0);
-                c[4 * u + 0] = (int)(c2.x & 0xffffu);
-                c[4 * u + 1] = (int)(c2.x >> 16);
-                c[4 * u + 2] = (int)(c2.y & 0xffffu);
-                c[4 * u + 3] = (int)(c2.y >> 16);
+                c[GE * u + 0] = (int)(c2.x & 0xffffu);
+                c[GE * u + 1] = (int)(c2.x >> 16);
+                c[GE * u + 2] = (int)(c2.y & 0xffffu);
+                c[GE * u + 3] = (int)(c2.y >> 16);
             } else {
                 typedef int v4i __attribute__((ext_vector_type(4)));
                 const v4i c4 = __builtin_amdgcn_raw_buffer_load_b128(rc, ok ? (unsigned)k * 4u : VQE_BUF_OOB, 0, 0);
-                c[4 * u + 0] = c4.x;
-                c[4 * u + 1] = c4.y;
-                c[4 * u + 2] = c4.z;
-                c[4 * u + 3] = c4.w;
+                c[GE * u + 0] = c4.x;
+                c[GE * u + 1] = c4.y;
+                c[GE * u + 2] = c4.z;
+                c[GE * u + 3] = c4.w;
             }
-            BufVal<DT, RV>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
+#pragma unroll
+            for (int h = 0; h < GE / 4; h++)
+                BufVal<DT, RV>::load(rv, ok ? (unsigned)(k + 4 * h) * EB : VQE_BUF_OOB, v + GE * u + 4 * h);
         }
     };
     // products of one pass of row r; entries outside [k0, k1) read the zero
@@ -675,10 +690,10 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int k = kb + u * 4 * L + q;
-                const int col = X16 ? (rx ^ c[4 * u + q]) : c[4 * u + q];
-                cm[4 * u + q] = RV || (unsigned)(k - k0) < len ? col : zc;
+            for (int q = 0; q < GE; q++) {
+                const int k = kb + u * GE * L + q;
+                const int col = X16 ? (rx ^ c[GE * u + q]) : c[GE * u + q];
+                cm[GE * u + q] = RV || (unsigned)(k - k0) < len ? col : zc;
             }
         lds_gather_fma<X, V, W>(s_x, cm, v, are, aim);
     };
@@ -692,7 +707,7 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
     };
     auto finish = [&](int64_t r, int k0, int k1, double are, double aim) {
         // further passes of a long row
-        for (int kb = (k0 & ~3) + 4 * sl + PASS; kb - 4 * sl < k1; kb += PASS) {
+        for (int kb = (k0 & ~(GE - 1)) + GE * sl + PASS; kb - GE * sl < k1; kb += PASS) {
             int c[W];
             V v[W];
             issue(kb, k1, c, v);
@@ -726,7 +741,7 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
     for (int d = 0; d < D; d++) {
         rr[d] = r0 + (wid + 16 * d) * G + sub;
         row_bounds(rr[d], kb0[d], kb1[d]);
-        issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+        issue((kb0[d] & ~(GE - 1)) + GE * sl, kb1[d], cb[d], vb[d]);
     }
     __builtin_amdgcn_sched_barrier(0);
     for (int64_t base = r0 + wid * G; base < r1; base += 16 * D * G) {
@@ -734,12 +749,12 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
         for (int d = 0; d < D; d++) {
             {
                 double are = 0.0, aim = 0.0;
-                consume(rr[d], (kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
+                consume(rr[d], (kb0[d] & ~(GE - 1)) + GE * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
                 finish(rr[d], kb0[d], kb1[d], are, aim);
             }
             rr[d] += 16 * D * G;
             row_bounds(rr[d], kb0[d], kb1[d]);
-            issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+            issue((kb0[d] & ~(GE - 1)) + GE * sl, kb1[d], cb[d], vb[d]);
             // keep the refill ahead of the next row's products
             __builtin_amdgcn_sched_barrier(0);
         }

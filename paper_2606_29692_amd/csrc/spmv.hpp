@@ -47,9 +47,9 @@ struct SpmvState {
     const uint16_t *col16;
     // real parts of val (schedules with VQE_SPMV_REAL): FP32 or FP64.  For
     // the column-tiled form [nnz], with col16 in the CSR's layout; otherwise
-    // col16 and vre hold the padded layout (rows rounded up to whole groups
-    // of four, zero values in the pads) with row pointers prow[dim + 1] and
-    // room for cap entries
+    // col16 and vre hold the padded layout (rows rounded up to a multiple of
+    // SPMV_PAD entries, zero values in the pads) with row pointers
+    // prow[dim + 1] and room for cap entries
     const void *vre;
     const int32_t *prow;
     int64_t cap;
@@ -60,5 +60,7 @@ struct SpmvState {
 #define VQE_SPMV_TILED 0x1000
 // largest dimension whose column XOR row fits 16 bits
 #define SPMV_X16_MAX_DIM 65536
+// row length granule of the padded layout (real values, states that fit LDS)
+#define SPMV_PAD 8
 #define SPMV_TILE_BYTES (128 * 1024)
 #define SPMV_SUM_ROWS 1024
