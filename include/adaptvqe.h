@@ -469,9 +469,9 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * copies from the CSR once (4 bytes per entry in FP32 storage, 8 in FP64;
  * plan-owned, rebuilt by vqe_batch_rebind): 6 instead of 10 bytes per entry
  * in FP32 storage.  For a state that fits LDS the plan lays the codes and
- * values out with every row padded to a multiple of four entries (zero
- * values; at most 3 pads per row, plus dim + 1 int32 row pointers), so the
- * product needs no row masks.  Dropped for an H without the flag and
+ * values out with every row padded to a multiple of eight entries (zero
+ * values; at most 7 pads per row, plus dim + 1 int32 row pointers), so the
+ * product needs no row masks and reads each lane's eight codes at once.  Dropped for an H without the flag and
  * wherever the codes are dropped; single calls (vqe_time_spmv) ignore it.
  * The row sums are the same FP64 sums of exact-in-FP64 products as without
  * it, grouped over the lanes differently in the padded layout: results agree
