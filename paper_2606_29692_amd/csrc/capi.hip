@@ -802,6 +802,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     // runs the tiled screen's lists in the same workgroups, so the LDS holds
     // either form
     std::vector<std::vector<int4>> screen1_per(kXcd);
+    // (ADAPTVQE_SCREEN_WG overrides the four, 1..64, for tuning)
     int split = 4;
     if (const char *e = std::getenv("ADAPTVQE_SCREEN_WG"))
         split = std::max(1, std::min(64, std::atoi(e)));

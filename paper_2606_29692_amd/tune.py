@@ -1,7 +1,9 @@
 """Schedule autotuner for the H product.
 
-A schedule is the number of wave lanes per CSR row (8, 16, 32, 64), with or
-without the four-entries-per-lane wide loads (VQE_SPMV_VEC4).  It is picked
+A schedule is the number of wave lanes per CSR row (8, 16, 32, 64) with the
+VQE_SPMV_* options: wide loads (VEC4), the state staged in LDS (LDS, DEEP),
+the pipelined loads (PREFETCH), 16-bit column codes (X16) and, for a real H,
+the real values in the row-padded layout (REAL).  It is picked
 per (register size, dtype, mapping, device) by timing the batched H product
 phase of a real plan over the candidates, and cached.  The choice is
 a function of that key alone, so a state gets the same schedule (and the same
