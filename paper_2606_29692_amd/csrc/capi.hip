@@ -548,15 +548,16 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     std::vector<int> lanes(B);
     std::vector<size_t> o_epart(B), o_npart(B), o_gpart(B);
     std::vector<size_t> o_tptr(B, 0), o_tpart(B, 0);
-    std::vector<int> ntiles(B, 0);
-    const int tile_cols = spmv_tile_cols(dtype);
+    std::vector<int> ntiles(B, 0), tcols(B, 0);
     for (int s = 0; s < B; s++) {
         const vqe_csr *H = items[s].H;
         const int req = items[s].spmv_schedule ? items[s].spmv_schedule : vqe_default_schedule(H);
         lanes[s] = vqe_batch_schedule(H, req);
         int64_t nblk = spmv_blocks(H->dim, lanes[s]);
         if (lanes[s] & VQE_SPMV_TILED) {
-            ntiles[s] = (int)((H->dim + tile_cols - 1) / tile_cols);
+            // real-value tiles are twice as wide (real parts in storage precision)
+            tcols[s] = (lanes[s] & VQE_SPMV_REAL) ? spmv_tile_cols_real(dtype) : spmv_tile_cols(dtype);
+            ntiles[s] = (int)((H->dim + tcols[s] - 1) / tcols[s]);
             o_tptr[s] = A.take((size_t)(ntiles[s] + 1) * H->dim * sizeof(int32_t));
             o_tpart[s] = A.take((size_t)ntiles[s] * H->dim * 2 * sizeof(double));
             nblk = (H->dim + SPMV_SUM_ROWS - 1) / SPMV_SUM_ROWS;
@@ -891,7 +892,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             st.tptr = (const int32_t *)(D + o_tptr[s]);
             st.tile_part = (double *)(D + o_tpart[s]);
             st.ntiles = ntiles[s];
-            st.tile_cols = tile_cols;
+            st.tile_cols = tcols[s];
             st.nblocks = (int32_t)((it.H->dim + SPMV_SUM_ROWS - 1) / SPMV_SUM_ROWS);
         }
         st.nnz = it.H->nnz;

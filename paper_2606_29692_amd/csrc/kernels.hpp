@@ -273,6 +273,9 @@ void launch_spmv_tiled(int dtype, int sched, const SpmvState *states, const int2
                        unsigned grid, const int2 *sum_tasks, unsigned sum_grid, hipStream_t s);
 void launch_tile_bounds(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s);
 int32_t spmv_tile_cols(int dtype);
+// tile width of the column-tiled form with real values (VQE_SPMV_REAL): twice
+// as many columns, since a real tile holds storage-precision real parts
+int32_t spmv_tile_cols_real(int dtype);
 int64_t spmv_blocks(int64_t dim, int sched);
 // col16[k] = col[k] ^ row(k) for every entry of H (dim <= SPMV_X16_MAX_DIM)
 void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s);

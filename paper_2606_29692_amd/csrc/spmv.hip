@@ -281,6 +281,33 @@ __device__ __forceinline__ int stage_real(double *dst, const T *src, int64_t n, 
     return cplx;
 }
 
+// The real parts of a state staged in LDS in a given precision (FP32 real
+// parts of FP32 storage stay exact); returns nonzero when an element of this
+// thread's share has a nonzero imaginary part.
+template <int SB, typename R, typename T>
+__device__ __forceinline__ int stage_real_as(R *dst, const T *src, int64_t n, int tid)
+{
+    int cplx = 0;
+    for (int64_t i0 = tid; i0 < n; i0 += 1024 * SB) {
+        T v[SB];
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const int64_t i = i0 + (int64_t)u * 1024;
+            if (i < n)
+                v[u] = stage_load(src, i);
+        }
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+            const int64_t i = i0 + (int64_t)u * 1024;
+            if (i < n) {
+                dst[i] = (R)v[u].x;
+                cplx |= v[u].y != 0;
+            }
+        }
+    }
+    return cplx;
+}
+
 // One entry's product a * x added to (are, aim) in FP64: a complex value, or
 // the real part alone when the operator is stored with real values.
 template <typename T>
@@ -321,6 +348,11 @@ __device__ __forceinline__ void entry_fma(const double a, const double x, double
 {
     (void)aim;
     are += a * x;
+}
+__device__ __forceinline__ void entry_fma(const float a, const float x, double &are, double &aim)
+{
+    (void)aim;
+    are += (double)a * (double)x;
 }
 
 // A row's terms of <psi|sigma> and <psi|psi> from its state element.
@@ -837,11 +869,13 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
 // tile staged in LDS at smem (complex, or with RX its real parts in FP64) and
 // the rows' tile bounds at s_k0, s_k1; writes the FP64 tile partials.
 template <int DT, int L, int D, int U, bool X16, bool RV, bool RX>
-__device__ __forceinline__ void tiled_rows(const SpmvState &st, int t, const unsigned char *smem,
+__device__ __forceinline__ void tiled_rows(const SpmvState &st, int t, int c_lo, int tc,
+                                           bool accumulate, const unsigned char *smem,
                                            const int32_t *s_k0, const int32_t *s_k1, int64_t r0,
                                            int64_t r1)
 {
-    using X = typename std::conditional<RX, double, typename Elem<DT>::T>::type;
+    using X = typename std::conditional<RX, typename ValOf<DT, true>::T,
+                                        typename Elem<DT>::T>::type;
     constexpr int W = U * 4;
     constexpr int PASS = W * L;
     using V = typename ValOf<DT, RV>::T;
@@ -849,8 +883,6 @@ __device__ __forceinline__ void tiled_rows(const SpmvState &st, int t, const uns
     const X *s_x = reinterpret_cast<const X *>(smem);
     const int tid = threadIdx.x;
     const int64_t dim = st.dim;
-    const int tc = st.tile_cols;
-    const int c_lo = t * tc;
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
@@ -924,13 +956,18 @@ __device__ __forceinline__ void tiled_rows(const SpmvState &st, int t, const uns
             if (k < k1) {
                 const V a = ldv(reinterpret_cast<const V *>(RV ? st.vre : st.val), k);
                 const int col = X16 ? ((int)r ^ (int)gmem(st.col16)[k]) : gmem(st.col)[k];
-                entry_fma(a, s_x[col - c_lo], are, aim);
+                if ((unsigned)(col - c_lo) < (unsigned)tc)
+                    entry_fma(a, s_x[col - c_lo], are, aim);
             }
         }
         are = group_sum<L>(are);
         if (!RX)
             aim = group_sum<L>(aim);
         if (sl == 0 && r < r1) {
+            if (accumulate) {
+                are += gmem(part)[2 * r];
+                aim += gmem(part)[2 * r + 1];
+            }
             gmem(part)[2 * r] = are;
             gmem(part)[2 * r + 1] = aim;
         }
@@ -985,30 +1022,45 @@ k_spmv_tiled(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
     const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
     const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
-    // the tile, one zero element (index tc), then the block's tile bounds
-    int32_t *s_k0 = reinterpret_cast<int32_t *>(smem + (size_t)(tc + 1) * sizeof(T));
+    // the tile, one zero element (index tc), then the block's tile bounds.
+    // With real values (RV) the plan's tiles are twice as wide: a tile with no
+    // imaginary part is staged as its real parts in storage precision; a
+    // complex one runs as two half-width passes (complex elements), each over
+    // the rows' whole segments with the columns outside its half masked, the
+    // second adding to the first's partials
+    const size_t x_bytes = (size_t)((RV ? tc / 2 : tc) + 1) * sizeof(T);
+    int32_t *s_k0 = reinterpret_cast<int32_t *>(smem + x_bytes);
     int32_t *s_k1 = s_k0 + SPMV_LDS_ROWS;
     stage_lds<2>(s_k0, st.tptr + (int64_t)t * dim + r0, r1 - r0, tid);
     stage_lds<2>(s_k1, st.tptr + (int64_t)(t + 1) * dim + r0, r1 - r0, tid);
     if constexpr (RV) {
-        // a tile with no imaginary part runs in real arithmetic (the tile's
-        // partial sums involve only its own columns)
-        double *s_xr = reinterpret_cast<double *>(smem);
-        const int cplx = stage_real<8>(s_xr, psi + c_lo, (int64_t)tc, tid);
+        using R = typename ValOf<DT, true>::T;
+        R *s_xr = reinterpret_cast<R *>(smem);
+        const int cplx = stage_real_as<8, R>(s_xr, psi + c_lo, (int64_t)tc, tid);
         if (tid == 0)
-            s_xr[tc] = 0.0;
+            s_xr[tc] = (R)0;
         if (!__syncthreads_or(cplx)) {
-            tiled_rows<DT, L, D, U, X16, RV, true>(st, t, smem, s_k0, s_k1, r0, r1);
+            tiled_rows<DT, L, D, U, X16, RV, true>(st, t, c_lo, tc, false, smem, s_k0, s_k1, r0, r1);
             return;
         }
+        const int th = tc / 2;
+        for (int h = 0; h < 2; h++) {
+            stage_lds<8>(s_x, psi + c_lo + h * th, (int64_t)th, tid);
+            if (tid == 0)
+                s_x[th] = T{};
+            __syncthreads();
+            tiled_rows<DT, L, D, U, X16, RV, false>(st, t, c_lo + h * th, th, h == 1, smem, s_k0,
+                                                    s_k1, r0, r1);
+            __syncthreads();      // every wave is done with this half
+        }
+        return;
     }
     stage_lds<8>(s_x, psi + c_lo, (int64_t)tc, tid);
     if (tid == 0)
         s_x[tc] = T{};
     __syncthreads();
-    tiled_rows<DT, L, D, U, X16, RV, false>(st, t, smem, s_k0, s_k1, r0, r1);
+    tiled_rows<DT, L, D, U, X16, RV, false>(st, t, c_lo, tc, false, smem, s_k0, s_k1, r0, r1);
 }
-
 
 // sigma_r = sum over tiles (ascending) of the tile partials; the energy sums.
 template <int DT>
@@ -1217,6 +1269,7 @@ void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState 
 }
 
 int32_t spmv_tile_cols(int dtype) { return (int32_t)(SPMV_TILE_BYTES / vqe_elem_bytes(dtype)); }
+int32_t spmv_tile_cols_real(int dtype) { return 2 * spmv_tile_cols(dtype); }
 
 // Tile passes see short row segments, so narrow sub-groups keep two groups of
 // four entries per lane (U = 2) instead of covering 256 entries per pass.
