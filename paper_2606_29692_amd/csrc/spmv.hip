@@ -581,8 +581,18 @@ k_pad_rowptr(const int32_t *__restrict__ rowptr, int32_t *__restrict__ prow, int
     const int64_t a = (int64_t)tid * per < dim ? (int64_t)tid * per : dim;
     const int64_t b = a + per < dim ? a + per : dim;
     int64_t tot = 0;
-    for (int64_t r = a; r < b; r++)
-        tot += (rowptr[r + 1] - rowptr[r] + SPMV_PAD - 1) & ~(SPMV_PAD - 1);
+    // the run's row pointers a batch at a time (independent loads)
+    constexpr int NB = 16;
+    for (int64_t r0 = a; r0 < b; r0 += NB) {
+        int32_t p[NB + 1];
+#pragma unroll
+        for (int i = 0; i <= NB; i++)
+            p[i] = r0 + i <= b ? rowptr[r0 + i] : 0;
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (r0 + i < b)
+                tot += (p[i + 1] - p[i] + SPMV_PAD - 1) & ~(SPMV_PAD - 1);
+    }
     s_sum[tid] = tot;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -592,9 +602,17 @@ k_pad_rowptr(const int32_t *__restrict__ rowptr, int32_t *__restrict__ prow, int
         __syncthreads();
     }
     int64_t run = s_sum[tid] - tot;
-    for (int64_t r = a; r < b; r++) {
-        prow[r] = (int32_t)run;
-        run += (rowptr[r + 1] - rowptr[r] + SPMV_PAD - 1) & ~(SPMV_PAD - 1);
+    for (int64_t r0 = a; r0 < b; r0 += NB) {
+        int32_t p[NB + 1];
+#pragma unroll
+        for (int i = 0; i <= NB; i++)
+            p[i] = r0 + i <= b ? rowptr[r0 + i] : 0;
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (r0 + i < b) {
+                prow[r0 + i] = (int32_t)run;
+                run += (p[i + 1] - p[i] + SPMV_PAD - 1) & ~(SPMV_PAD - 1);
+            }
     }
     if (tid == 1023)
         prow[dim] = (int32_t)s_sum[1023];
