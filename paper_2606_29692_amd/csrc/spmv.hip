@@ -642,7 +642,8 @@ k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
 }
 
 // Pipelined variant of the LDS schedule.  A sub-group of L lanes covers a row
-// of up to U * 4 * L = 256 entries in one pass and keeps the loads of its next
+// of up to U * GE * L = 256 entries in one pass (GE entries per lane group: 4,
+// or 8 in the padded layout) and keeps the loads of its next
 // D rows in flight: after a row's products it refills that row's registers
 // with the row D sweeps ahead.  The loads are raw buffer loads issued by every
 // lane without branches: groups past the row (or past the last whole group of
@@ -659,7 +660,10 @@ k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
 // with zero values to whole groups (row pointers st.prow), so no entry needs
 // a row mask and there is no tail, and a lane takes eight entries with one
 // 16-byte code load; the values are the real parts, 4 instead of 8 bytes per
-// entry in FP32 storage.
+// entry in FP32 storage, and a workgroup whose staged state has no imaginary
+// part multiplies in real arithmetic (RX).  The kernel, k_spmv_lds_pf, stages
+// and then runs pf_rows.
+
 // The rows [r0, r1) of one workgroup of the pipelined LDS schedule, the state
 // already staged in LDS at smem (complex, or with RX its real parts in FP64)
 // and the row pointers at s_rp; writes sigma and the workgroup's energy
@@ -827,7 +831,8 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
     }
 }
 
-
+// The pipelined LDS schedule's kernel (described above pf_rows): one
+// workgroup per (state, block of rows).
 template <int DT, int L, int D, bool BATCH, bool X16, bool RV>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
@@ -883,9 +888,12 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
 // sorted within a row, bounded by the per-tile row pointers.  The row sums of
 // a tile go to an FP64 partial array; the tile-sum kernel adds the tiles in
 // ascending order and applies the energy epilogue.
+
 // The rows [r0, r1) of one column tile t of the column-tiled schedule, the
-// tile staged in LDS at smem (complex, or with RX its real parts in FP64) and
-// the rows' tile bounds at s_k0, s_k1; writes the FP64 tile partials.
+// columns [c_lo, c_lo + tc) staged in LDS at smem (complex, or with RX the
+// real parts in storage precision) and the rows' tile bounds at s_k0, s_k1;
+// entries outside those columns are masked.  Writes the FP64 tile partials,
+// or adds to them (accumulate).
 template <int DT, int L, int D, int U, bool X16, bool RV, bool RX>
 __device__ __forceinline__ void tiled_rows(const SpmvState &st, int t, int c_lo, int tc,
                                            bool accumulate, const unsigned char *smem,
