@@ -711,25 +711,58 @@ k_screen_mf_real(const ScreenState *__restrict__ states, const int4 *__restrict_
         s_next = 0;
     int cplx = 0;
     constexpr int SU = 8;
-    for (int64_t i0 = threadIdx.x; i0 < rows; i0 += 1024 * SU) {
-        T a[SU], b[SU];
+    if (DT == VQE_C64 && (rows & 1) == 0 &&
+        ((reinterpret_cast<uintptr_t>(psi) | reinterpret_cast<uintptr_t>(sig)) & 15) == 0) {
+        // two rows per 16-byte load
+        const vqe_v4f *psi4 = reinterpret_cast<const vqe_v4f *>(psi);
+        const vqe_v4f *sig4 = reinterpret_cast<const vqe_v4f *>(sig);
+        const int64_t pairs = rows / 2;
+        for (int64_t i0 = threadIdx.x; i0 < pairs; i0 += 1024 * SU) {
+            vqe_v4f a[SU], b[SU];
 #pragma unroll
-        for (int u = 0; u < SU; u++) {
-            const int64_t i = i0 + 1024 * u;
-            if (i < rows) {
-                a[u] = ldg(psi, i);
-                b[u] = ldg(sig, i);
+            for (int u = 0; u < SU; u++) {
+                const int64_t i = i0 + 1024 * u;
+                if (i < pairs) {
+                    a[u] = gmem(psi4)[i];
+                    b[u] = gmem(sig4)[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                const int64_t i = i0 + 1024 * u;
+                if (i < pairs) {
+                    R2 e0, e1;
+                    e0.x = a[u].x;
+                    e0.y = b[u].x;
+                    e1.x = a[u].z;
+                    e1.y = b[u].z;
+                    tile[2 * i] = e0;
+                    tile[2 * i + 1] = e1;
+                    cplx |= (a[u].y != 0) | (a[u].w != 0) | (b[u].y != 0) | (b[u].w != 0);
+                }
             }
         }
+    } else {
+        for (int64_t i0 = threadIdx.x; i0 < rows; i0 += 1024 * SU) {
+            T a[SU], b[SU];
 #pragma unroll
-        for (int u = 0; u < SU; u++) {
-            const int64_t i = i0 + 1024 * u;
-            if (i < rows) {
-                R2 e;
-                e.x = a[u].x;
-                e.y = b[u].x;
-                tile[i] = e;
-                cplx |= (a[u].y != 0) | (b[u].y != 0);
+            for (int u = 0; u < SU; u++) {
+                const int64_t i = i0 + 1024 * u;
+                if (i < rows) {
+                    a[u] = ldg(psi, i);
+                    b[u] = ldg(sig, i);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                const int64_t i = i0 + 1024 * u;
+                if (i < rows) {
+                    R2 e;
+                    e.x = a[u].x;
+                    e.y = b[u].x;
+                    tile[i] = e;
+                    cplx |= (a[u].y != 0) | (b[u].y != 0);
+                }
             }
         }
     }
