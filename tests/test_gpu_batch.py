@@ -262,6 +262,8 @@ def test_full_size_bench_config(ctx, sched):
                                    B.VQE_SPMV_X16,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
                                    B.VQE_SPMV_REAL,
+                                   16 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
+                                   B.VQE_SPMV_REAL,
                                    64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
                                    B.VQE_SPMV_X16 | B.VQE_SPMV_REAL])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
@@ -562,3 +564,59 @@ def test_context_close_destroys_its_plans():
     plan.close()
     del plan
     torch.cuda.set_stream(prev)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_real_schedule_mixed_plan(ctx, dtype):
+    """One plan asked for the real-value schedule on a real and a complex
+    Hamiltonian of the same size: the real one takes the real values, the
+    complex one the complex-value form (separate launches); both adaptive
+    steps against the oracle, and each state equals its own single-state plan
+    bit for bit."""
+    n = 10
+    s = vs.make_system(vs.SystemSpec(n, 4, "jw", False, 180))
+    h = s.hamiltonian
+    hy = vs.PauliPack(n, np.append(h.xmask, np.uint64(1 << 3)), np.append(h.zmask, np.uint64(1 << 3)),
+                      np.append(h.coeff, 0.05))                     # + 0.05 Y3
+    sched = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 | B.VQE_SPMV_REAL
+    pool = B.pool_from_packs(ctx, s.pool, dtype)
+    shift = 0.0
+    if dtype == "c64":
+        shift = float(orc.csr_from_pack(h).dense()[s.reference_index, s.reference_index].real)
+    Hr = B.csr_from_pack(ctx, h, dtype, diag_shift=shift)
+    Hy = B.csr_from_pack(ctx, hy, dtype, diag_shift=shift)
+    assert Hr.real and not Hy.real
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+
+    def ref_state():
+        p = torch.zeros(1 << n, dtype=tdt, device=ctx.torch_device)
+        p[s.reference_index] = 1.0
+        return p
+
+    pa, pb = ref_state(), ref_state()
+    plan = B.BatchPlan(ctx, [(Hr, pool, pa), (Hy, pool, pb)], schedules=[sched, sched])
+    alone = [B.BatchPlan(ctx, [(H, pool, p)], schedules=[sched])
+             for H, p in ((Hr, ref_state()), (Hy, ref_state()))]
+    thetas = [0.11, -0.07, 0.05]
+    for t, th in enumerate(thetas):
+        for pl in [plan] + alone:
+            pl.theta.fill_(th)
+            pl.step(renorm=True)
+        torch.cuda.synchronize()
+        e = host(plan.energies).reshape(-1, 3)
+        for i, pl in enumerate(alone):
+            np.testing.assert_array_equal(e[i], host(pl.energies).reshape(-1, 3)[0])
+            np.testing.assert_array_equal(host(plan.states[i][2]), host(pl.states[0][2]))
+    # the final states' energies against the oracle
+    ks = host(plan.k).copy()
+    plan.step(update=False)
+    for i, pack in enumerate((h, hy)):
+        oH = orc.csr_from_pack(pack)
+        psi = host(plan.states[i][2]).astype(np.complex128)
+        e_o = orc.energy(oH, psi)[0]
+        e = host(plan.energies).reshape(-1, 3)[i, 0]
+        assert abs(e - e_o) <= (1e-12 if dtype == "c128" else 1e-5) * max(1.0, abs(e_o))
+    assert ks.shape == (2,)
+    plan.close()
+    for pl in alone:
+        pl.close()
