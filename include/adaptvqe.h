@@ -471,7 +471,13 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * in FP32 storage.  For a state that fits LDS the plan lays the codes and
  * values out with every row padded to a multiple of eight entries (zero
  * values; at most 7 pads per row, plus dim + 1 int32 row pointers), so the
- * product needs no row masks and reads each lane's eight codes at once.  Dropped for an H without the flag and
+ * product needs no row masks and reads each lane's eight codes at once.
+ * A column-tiled state keeps the CSR order and the per-tile row bounds, with
+ * tiles twice as wide (real parts in storage precision).  Whether the state
+ * is real is decided at run time: a state (or, column-tiled, a tile) whose
+ * imaginary parts are all zero multiplies in real arithmetic; any other runs
+ * the same launch in complex arithmetic (a wide tile as two half-width
+ * passes).  Dropped for an H without the flag and
  * wherever the codes are dropped; single calls (vqe_time_spmv) ignore it.
  * The row sums are the same FP64 sums of exact-in-FP64 products as without
  * it, grouped over the lanes differently in the padded layout: results agree
