@@ -33,19 +33,16 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 
 
-PMC_PROFILE = os.path.join(ROOT, "profiles", "h_product_14q_64states_pmc.md")
+# state bytes that fit in LDS beside the staged row pointers (larger states are
+# column-tiled)
+LDS_STATE_BYTES = 147 * 1024
+PMC_PROFILES = ("h_product_14q_64states_pmc.md", "h_product_16q_16states_pmc.md")
 
 
-def measured_traffic(schedule: int, workload: str):
-    """HBM bytes per H-product launch from the committed FETCH_SIZE/WRITE_SIZE
-    profile (calibrated against a copy kernel of known size), or None when the
-    profile is absent, was taken with another schedule, or the kernel sources
-    have changed since it was taken."""
+def _traffic_record(path: str, schedule: int, workload: str):
     import hashlib
-    if not os.path.exists(PMC_PROFILE):
-        return None
     rec = {}
-    with open(PMC_PROFILE) as f:
+    with open(path) as f:
         for line in f:
             if ": " in line and not line.startswith((" ", "#", "|")):
                 k, v = line.rstrip("\n").split(": ", 1)
@@ -62,6 +59,20 @@ def measured_traffic(schedule: int, workload: str):
         return int(rec["traffic_bytes_per_launch"])
     except (KeyError, ValueError, OSError):
         return None
+
+
+def measured_traffic(schedule: int, workload: str):
+    """HBM bytes per H-product launch from a committed FETCH_SIZE/WRITE_SIZE
+    profile of this workload and schedule (calibrated against a copy kernel of
+    known size), or None when there is none or the kernel sources have changed
+    since it was taken."""
+    for name in PMC_PROFILES:
+        path = os.path.join(ROOT, "profiles", name)
+        if os.path.exists(path):
+            t = _traffic_record(path, schedule, workload)
+            if t is not None:
+                return t
+    return None
 
 
 def vs_electrons() -> dict:
@@ -85,6 +96,12 @@ def plan_sched_real(sched: int, ds) -> bool:
     return plan_sched_x16(sched, ds) and bool(sched & B.VQE_SPMV_REAL) and all(d.H.real for d in ds)
 
 
+def plan_tiled(ds) -> bool:
+    """True when some state is larger than the LDS state limit, so that the
+    plan runs the column-tiled H product."""
+    return any(d.H.dim * d.psi.element_size() > LDS_STATE_BYTES for d in ds)
+
+
 def stored_h_bytes(sched: int, ds) -> int:
     """Bytes the H-product kernel has to read and write per launch in the
     form it reads: row pointers, 2- or 4-byte columns, complex or real
@@ -95,7 +112,7 @@ def stored_h_bytes(sched: int, ds) -> int:
         cb = 2 if x16 else 4
         vb = d.H.val.element_size() // (2 if rv else 1)
         nnz = d.H.nnz
-        if rv and d.H.dim * d.psi.element_size() <= 147 * 1024:
+        if rv and d.H.dim * d.psi.element_size() <= LDS_STATE_BYTES:
             # the padded layout: every row rounded up to a multiple of eight
             lens = np.diff(d.H.rowptr.cpu().numpy().astype(np.int64))
             nnz = int(((lens + 7) // 8 * 8).sum())
@@ -530,8 +547,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(sched, f"{len(ds)}x{args.qubits}q-{args.mapping}-{args.dtype}"),
                      "traffic_unit": "bytes per launch (HBM read + write, PMC-calibrated)",
-                     "kernel": f"H product of all {len(ds)} states (one launch of the schedule's "
-                               f"kernel: k_spmv_lds_pf, k_spmv_lds or k_spmv_energy)",
+                     "kernel": (f"column-tiled H product of all {len(ds)} states (k_spmv_tiled, "
+                                f"then k_spmv_tile_sum)" if plan_tiled(ds) else
+                                f"H product of all {len(ds)} states (one launch of the schedule's "
+                                f"kernel: k_spmv_lds_pf, k_spmv_lds or k_spmv_energy)"),
                      "bytes_per_launch": nbytes["h_spmv"],
                      "stored_bytes_per_launch": stored,
                      "stored_GBps": stored / (spmv_avg / 1e3) / 1e9,
