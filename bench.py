@@ -11,10 +11,19 @@ FP64 renormalisation.  Storage is FP32 (complex64, with an FP64 diagonal
 shift); products and reductions are FP64.  Inputs are resident in HBM before
 the timed region.
 
+The headline leg keeps the interleaved complex layout end to end: the
+Hamiltonians' complex values are streamed, and every state starts from a
+seeded complex state of its particle sector, so the H product and the screen
+run in complex arithmetic.  Its algorithmic bytes count the canonical CSR with
+complex values (int32 column + complex value per entry, each vector once).
+The real-value specialisation (real parts of a real H, real states from the
+reference) is timed as a separate block with its own accounting.
+
 Printed (one JSON line): Taylor-O(5) updates/s (each with its full screen),
-the pool-gradient SpMV HBM GB/s, p50/p99 step latency, the roofline of the
-dominant kernel (the H product), the plain FP64 single-request GPU path, and
-the FP64 oracle timed on the host cores.
+the pool-gradient SpMV HBM GB/s, p50/p99 step latency over a dedicated
+latency leg, the roofline of the dominant kernel (the H product), the mixed
+10/12/14-qubit batch, the plain FP64 single-request GPU path, the serving
+stream, and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -36,7 +45,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # state bytes that fit in LDS beside the staged row pointers (larger states are
 # column-tiled)
 LDS_STATE_BYTES = 147 * 1024
-PMC_PROFILES = ("h_product_14q_64states_pmc.md", "h_product_16q_16states_pmc.md")
+PMC_PROFILES = ("h_product_14q_64states_complex_pmc.md", "h_product_14q_64states_pmc.md",
+                "h_product_16q_16states_pmc.md", "h_product_18q_pmc.md")
 
 
 def _traffic_record(path: str, schedule: int, workload: str):
@@ -128,39 +138,92 @@ def percentile(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def cpu_baseline(systems, seconds: float):
-    """The FP64 oracle (test infrastructure, untuned) on a bounded sample: whole
-    adaptive steps (energy, screen, selection, Taylor update, renormalisation)
-    for a few of the benchmark's states, CSR built beforehand (untimed)."""
+def lat_stats(ms) -> dict:
+    a = np.asarray(ms, dtype=np.float64)
+    return {"p50_ms": percentile(a, 50), "p99_ms": percentile(a, 99),
+            "p999_ms": percentile(a, 99.9), "mean_ms": float(a.mean()),
+            "max_ms": float(a.max()), "n": int(a.size)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(system, psi0, reps: int, warm: int):
+    """The FP64 oracle (test infrastructure, untuned) on one state of the
+    benchmark workload (14 qubits, 6 electrons, JW, 204 generators; CSR built
+    beforehand, untimed): medians over `reps` repetitions after `warm`
+    warm-ups of the H product (sigma = H psi with the energy), the 204-generator
+    screen (sigma reused), one Taylor-5 update and one whole adaptive step
+    (energy, screen, selection, update, renormalisation), at one thread and at
+    the process's thread count.  The headline rate is one whole step per
+    update at the larger thread count."""
     from oracle import oracle as orc
-    import vqe_system as vs
-    sample = systems[:4]
-    ready = []
-    for s in sample:
-        ready.append((orc.csr_from_pack(s.hamiltonian), [orc.csr_from_pack(p) for p in s.pool],
-                      vs.reference_state(s)))
-    done = 0
+    t_b = time.perf_counter()
+    oH = orc.csr_from_pack(system.hamiltonian)
+    pool = [orc.csr_from_pack(p) for p in system.pool]
+    build_s = time.perf_counter() - t_b
+    psi = np.asarray(psi0, dtype=np.complex128)
+    _, _, _, sigma = orc.energy(oH, psi)
+    k_sel, _ = orc.select(orc.gradients(pool, psi, sigma))
+    theta = 0.05
+
+    def step():
+        e, _, _, sg = orc.energy(oH, psi)
+        g = orc.gradients(pool, psi, sg)
+        k, _ = orc.select(g)
+        orc.normalize(orc.taylor5(pool[k], theta, psi))
+
+    phases = {"h_spmv_energy": lambda: orc.energy(oH, psi),
+              "pool_screen": lambda: orc.gradients(pool, psi, sigma),
+              "taylor5": lambda: orc.taylor5(pool[k_sel], theta, psi),
+              "adaptive_step": step}
+    n_max = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
-    while True:
-        for H, pool, psi in ready:
-            e, _, _, sigma = orc.energy(H, psi)
-            g = orc.gradients(pool, psi, sigma)
-            k, _ = orc.select(g)
-            out, _ = orc.normalize(orc.taylor5(pool[k], 0.05, psi))
-            done += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": done / el, "unit": "updates/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"{done} single-state adaptive steps (energy + 204-generator screen + "
-                      f"selection + Taylor-5 + renormalisation) over {len(sample)} of the 64 "
-                      f"14-qubit states, FP64, {el:.1f} s"}
+    per_threads = {}
+    for nt in sorted({1, n_max}):
+        orc.set_threads(nt)
+        used = orc.threads()
+        res = {}
+        for name, fn in phases.items():
+            for _ in range(warm):
+                fn()
+            ts = []
+            for _ in range(reps):
+                a = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - a)
+            res[name] = {"median_ms": float(np.median(ts)) * 1e3,
+                         "min_ms": float(np.min(ts)) * 1e3}
+        per_threads[str(used)] = res
+    orc.set_threads(n_max)
+    el = time.perf_counter() - t0
+    top = per_threads[str(max(int(k) for k in per_threads))]
+    return {"value": 1e3 / top["adaptive_step"]["median_ms"], "unit": "updates/s",
+            "cores": max(int(k) for k in per_threads), "kind": "oracle",
+            "sample": f"one 14-qubit state of the workload (2,596,863-entry H, 204 generators, "
+                      f"complex start state), FP64; per phase the median of {reps} repetitions "
+                      f"after {warm} warm-ups at 1 and {n_max} threads; {el:.1f} s of timing, "
+                      f"CSR build {build_s:.2f} s untimed",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "timer": "time.perf_counter (monotonic) around each oracle call",
+            "phases_by_threads": per_threads,
+            "paper_context": "the paper reports only memory for its CPU runs: 208.75 MB peak "
+                             "resident set for the whole 14-qubit BeH2 pipeline on an Ubuntu "
+                             "24.04 desktop (Sec. IV-C); no speed figure"}
 
 
 def plain_fp64_path(ctx, system, n_req: int):
     """The plain FP64 single-request GPU path at 14 qubits: one request at a
     time, synchronised per request.  Returns (Taylor-only updates/s, full
-    single-state adaptive steps/s)."""
+    single-state adaptive steps/s, per-request latency statistics)."""
     import torch
     from paper_2606_29692_amd import batch as PB
     from paper_2606_29692_amd import binding as B
@@ -170,22 +233,28 @@ def plain_fp64_path(ctx, system, n_req: int):
     for _ in range(5):
         B.taylor5_apply(ctx, A, 0.01, ds.psi, renormalize=True)
     ctx.stream.synchronize()
+    lat = []
     t0 = time.perf_counter()
     for i in range(n_req):
+        a = time.perf_counter()
         B.taylor5_apply(ctx, ds.pool.ops[i % ds.pool.M], 0.01, ds.psi, renormalize=True)
         ctx.stream.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
     taylor_rate = n_req / (time.perf_counter() - t0)
     t0 = time.perf_counter()
-    n_step = max(n_req // 4, 10)
+    n_step = max(n_req // 2, 100)
+    slat = []
     for i in range(n_step):
+        a = time.perf_counter()
         B.energy(ctx, ds.H, ds.psi, sigma)
         g = B.pool_gradients(ctx, ds.H, ds.pool, ds.psi, sigma)
         k, _ = B.vqe_select(ctx, g)
         kk = int(k.cpu()[0])
         B.taylor5_apply(ctx, ds.pool.ops[kk], 0.01, ds.psi, renormalize=True)
         ctx.stream.synchronize()
+        slat.append((time.perf_counter() - a) * 1e3)
     step_rate = n_step / (time.perf_counter() - t0)
-    return taylor_rate, step_rate
+    return taylor_rate, step_rate, lat_stats(lat), lat_stats(slat)
 
 
 def serving_bench(n_requests: int, warm: int, log_fn=log):
@@ -230,13 +299,127 @@ def serving_bench(n_requests: int, warm: int, log_fn=log):
         sq = S.latency_summary(sorted(seq, key=lambda q: q.rid), skip=warm)
         out[f"x{factor}"] = {"rate_per_s": rate, "continuous_batching": cb,
                              "sequential_fp64": sq, "evictions": server.evictions,
-                             "resident_runs": resident, "cold_start_s": t_cold}
+                             "failed": server.failed_count, "resident_runs": resident,
+                             "cold_start_s": t_cold}
         log_fn(f"serving at {factor}x ({rate:.0f}/s): batched p50 {cb['p50_ms']:.3f} ms p99 "
-               f"{cb['p99_ms']:.3f} ms {cb['updates_per_s']:.0f}/s; sequential p50 "
-               f"{sq['p50_ms']:.3f} ms p99 {sq['p99_ms']:.3f} ms")
+               f"{cb['p99_ms']:.3f} ms p99.9 {cb['p999_ms']:.3f} ms {cb['updates_per_s']:.0f}/s "
+               f"(n={cb['n']}); sequential p50 {sq['p50_ms']:.3f} ms p99 {sq['p99_ms']:.3f} ms")
         del ex, server
         torch.cuda.synchronize()
     ctx.close()
+    return out
+
+
+def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: int):
+    """Time one batch plan's whole adaptive step (captured graphs):
+      throughput  K steps between two events (whole-step graph, no events
+                  inside), after W warm-up steps;
+      latency     L steps with an event at every step boundary;
+      H product   R steps recording events before and after the H-product
+                  graph (the roofline's kernel duration) and at the end.
+    thetas: device float64 [W + K + L + R + 1, n_states]."""
+    import torch
+    Ev = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
+    t = 0
+
+    def next_theta():
+        nonlocal t
+        plan.theta.copy_(thetas[t % thetas.shape[0]])
+        t += 1
+
+    for _ in range(W):
+        next_theta()
+        plan.step(renorm=True, graph=True)
+    ev3 = [Ev() for _ in range(3)]
+    next_theta()
+    plan.step_timed(ev3, renorm=True, graph=True)      # captures the split graphs
+    torch.cuda.synchronize()
+    start, stop = Ev(), Ev()
+    start.record(stream)
+    t_host = time.perf_counter()
+    for _ in range(K):
+        next_theta()
+        plan.step(renorm=True, graph=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_host
+    ms_per_step = start.elapsed_time(stop) / K
+    bounds = [Ev() for _ in range(L + 1)]
+    bounds[0].record(stream)
+    for i in range(L):
+        next_theta()
+        plan.step(renorm=True, graph=True)
+        bounds[i + 1].record(stream)
+    torch.cuda.synchronize()
+    step_lat = [bounds[i].elapsed_time(bounds[i + 1]) for i in range(L)]
+    evs = [[Ev() for _ in range(3)] for _ in range(R)]
+    for i in range(R):
+        next_theta()
+        plan.step_timed(evs[i], renorm=True, graph=True)
+    torch.cuda.synchronize()
+    h_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    rest_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    return {"ms_per_step": ms_per_step, "updates_per_s": n_states * K / (ms_per_step * K / 1e3),
+            "steps": K, "warmup": W, "host_wall_s": wall,
+            "step_latency": lat_stats(step_lat),
+            "h_product_ms": float(np.mean(h_ms)), "h_product_ms_median": float(np.median(h_ms)),
+            "h_product_launches_timed": R, "rest_of_step_ms": float(np.mean(rest_ms))}
+
+
+def eager_phases(plan, n: int = 10) -> dict:
+    """Phase breakdown of the same step launched eagerly (7 events)."""
+    import torch
+    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(n)]
+    for t in range(n):
+        plan.step_timed(ev2[t], renorm=True)
+    torch.cuda.synchronize()
+    m = lambda a, b: float(np.mean([e[a].elapsed_time(e[b]) for e in ev2]))   # noqa: E731
+    return {"h_spmv": m(0, 1), "screen": m(2, 3), "taylor": m(4, 5), "renorm": m(5, 6),
+            "step": m(0, 6)}
+
+
+def set_states(ds, systems, form: str):
+    """Start every state from the reference (real) or from its seeded complex
+    start state (FP32 storage rounds it)."""
+    import torch
+    import vqe_system as vs
+    for d, s in zip(ds, systems):
+        if form == "complex":
+            d.psi.copy_(torch.from_numpy(vs.complex_start_state(s)).to(d.psi.dtype))
+        else:
+            d.reset()
+
+
+def mixed_batch_leg(ctx, stream, pools_mf: bool, K: int, W: int, L: int, R: int):
+    """Config C4: 64 states with N cycling over 10/12/14 (n_e 4/8/6), each with
+    its own pool, one launch sequence per step, complex start states, the
+    complex-value schedule tuned per register size."""
+    import torch
+    import vqe_system as vs
+    from paper_2606_29692_amd import batch as PB
+    from paper_2606_29692_amd import tune as T
+    specs, _ = vs.config_c4(n_states=64, mixed=True)
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx, matrix_free=pools_mf)
+    ds = [PB.device_system(ctx, s, "c64", pools) for s in systems]
+    set_states(ds, systems, "complex")
+    scheds = {}
+    for n in sorted({d.n_qubits for d in ds}):
+        same = [d for d in ds if d.n_qubits == n]
+        scheds[n] = T.schedule_for(ctx, same[0], systems=same, value_form="complex")
+    plan = PB.make_batch(ctx, ds, schedules=[scheds[d.n_qubits] for d in ds])
+    rng = np.random.default_rng(np.random.SeedSequence([4, 1]))
+    th = torch.from_numpy(rng.uniform(-0.1, 0.1, size=(W + K + L + R + 1, len(ds)))).to("cuda")
+    leg = timed_leg(plan, stream, len(ds), th, K, W, L, R)
+    nb = PB.bytes_per_step(ds)
+    plan.close()
+    by_n = {str(n): sum(1 for d in ds if d.n_qubits == n) for n in scheds}
+    out = {"workload": "64 states, N = (10, 12, 14)[i mod 3] (22/21/21), n_e 4/8/6, JW, own "
+                       "pool per size (54/92/204), complex start states, FP32 storage",
+           "states_by_qubits": by_n, "schedules": {str(k): v for k, v in scheds.items()},
+           "algorithmic_bytes_per_step": nb,
+           "h_product_GBps": nb["h_spmv"] / (leg["h_product_ms"] / 1e3) / 1e9, **leg}
+    del ds, pools
     return out
 
 
@@ -245,11 +428,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--latency-steps", type=int, default=200,
+                    help="steps of the latency leg (an event at every step boundary)")
+    ap.add_argument("--h-timed-steps", type=int, default=100,
+                    help="steps whose H-product graph is bracketed by events (roofline)")
     ap.add_argument("--states", type=int, default=64)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--value-form", choices=["complex", "real"], default="complex",
+                    help="headline leg: interleaved complex values and complex states (the "
+                         "contract), or the real-value specialisation")
+    ap.add_argument("--real-block", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the real-value specialisation as a separate block")
     ap.add_argument("--schedule", type=int, default=0,
-                    help="H product schedule (lanes per row, | 256 for wide loads; 0: tuned)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+                    help="H product schedule of the headline leg (0: tuned)")
+    ap.add_argument("--cpu-reps", type=int, default=20)
+    ap.add_argument("--cpu-warmup", type=int, default=3)
     ap.add_argument("--matrix-free", action=argparse.BooleanOptionalAction, default=True,
                     help="screen and update from the generators' matrix-free records "
                          "(no pool CSR) instead of the pool's pair tables")
@@ -258,6 +451,8 @@ def main():
     ap.add_argument("--adapt-steps", type=int, default=12,
                     help="also run this many adaptive steps from the reference with line "
                          "search, without and with re-optimisation of every angle (0: skip)")
+    ap.add_argument("--mixed-batch", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the mixed 10/12/14-qubit 64-state batch")
     ap.add_argument("--qubits", type=int, default=14, choices=sorted(vs_electrons()),
                     help="register size of every state (the headline workload is 14)")
     ap.add_argument("--mapping", choices=["jw", "bk"], default="jw")
@@ -267,8 +462,9 @@ def main():
                     help="time every H product schedule even when a tuned one is cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=512,
+    ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests per serving point (0: skip the serving measurement)")
+    ap.add_argument("--serve-warmup", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): states are "
@@ -319,78 +515,98 @@ def main():
     ds = [PB.device_system(ctx, s, args.dtype, pools) for s in systems]
     torch.cuda.synchronize()
     log(f"setup: {len(ds)} systems built on the device in {time.perf_counter() - t0:.1f} s")
-    sched = args.schedule or T.schedule_for(ctx, ds[0], systems=ds, retune=args.retune)
-    if T._last_timings:
-        log("tuner (ms of the batched H product): " +
-            ", ".join(f"{k}: {v:.3f}" for k, v in sorted(T._last_timings.items())))
-    plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
-    nbytes = PB.bytes_per_step(ds)
-    K, W = args.steps, args.warmup
+    K, W, L, R = args.steps, args.warmup, args.latency_steps, args.h_timed_steps
     rng = np.random.default_rng(np.random.SeedSequence([44, 1]))
-    thetas = torch.from_numpy(rng.uniform(-0.1, 0.1, size=(K + W, len(ds)))).to("cuda")
+    thetas = torch.from_numpy(rng.uniform(-0.1, 0.1, size=(W + K + L + R + 1, len(ds)))).to("cuda")
+    wl = f"{len(ds)}x{args.qubits}q-{args.mapping}-{args.dtype}"
 
-    # warm-up (untimed; also captures the graphs), then the timed region: K
-    # steps, each one captured graph of the whole step; every SAMPLE-th step
-    # instead runs the H-product graph and the rest-of-step graph with HIP
-    # events recorded on the library stream around each (a timing event costs
-    # about 9 us, so timing every step would slow the loop it measures)
-    SAMPLE = 10
-    timed = [t for t in range(K) if t % SAMPLE == 0]
-    ev = {t: [torch.cuda.Event(enable_timing=True) for _ in range(3)] for t in timed}
-    for t in range(W):
-        plan.theta.copy_(thetas[t])
-        if t % SAMPLE == 0:
-            plan.step_timed([torch.cuda.Event(enable_timing=True) for _ in range(3)], renorm=True,
-                            graph=True)
-        else:
-            plan.step(renorm=True, graph=True)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    t_host = time.perf_counter()
-    for t in range(K):
-        plan.theta.copy_(thetas[W + t])
-        if t in ev:
-            plan.step_timed(ev[t], renorm=True, graph=True)
-        else:
-            plan.step(renorm=True, graph=True)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_host
-    total_ms = start.elapsed_time(stop)
-    ms_per_step = total_ms / K
-    step_ms = [ev[t][0].elapsed_time(ev[t][2]) for t in timed]
-    spmv_ms = [ev[t][0].elapsed_time(ev[t][1]) for t in timed]
-    rest_ms = [ev[t][1].elapsed_time(ev[t][2]) for t in timed]
-    spmv_avg = float(np.mean(spmv_ms))
-    updates_per_s = len(ds) * K / (total_ms / 1e3)
-    achieved = nbytes["h_spmv"] / (spmv_avg / 1e3) / 1e9
-    # bytes the kernel actually has to read in the form it reads (16-bit
-    # column codes, complex or real values); the algorithmic figure counts
-    # the canonical CSR
-    x16, rv = plan_sched_x16(sched, ds), plan_sched_real(sched, ds)
-    stored = stored_h_bytes(sched, ds)
+    def run_form(form: str, sched_given: int = 0):
+        """Tune (or take) the schedule for a value form, set the states, and
+        time the leg; returns (schedule, leg record, eager phases, plan)."""
+        vf = "complex" if form == "complex" else "any"
+        sched = sched_given or T.schedule_for(ctx, ds[0], systems=ds, retune=args.retune,
+                                              value_form=vf)
+        if T._last_timings:
+            log(f"tuner ({form}; ms of the batched H product): " +
+                ", ".join(f"{k}: {v:.3f}" for k, v in sorted(T._last_timings.items())))
+            T._last_timings.clear()
+        set_states(ds, systems, form)
+        plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
+        leg = timed_leg(plan, stream, len(ds), thetas, K, W, L, R)
+        ph = eager_phases(plan)
+        return sched, leg, ph, plan
+
+    def form_record(form: str, sched: int, leg: dict, ph: dict) -> dict:
+        acc = "complex" if form == "complex" else "real"
+        nb = PB.bytes_per_step(ds, value_form=acc)
+        stored = stored_h_bytes(sched, ds)
+        h_s = leg["h_product_ms"] / 1e3
+        achieved = nb["h_spmv"] / h_s / 1e9
+        x16, rv = plan_sched_x16(sched, ds), plan_sched_real(sched, ds)
+        return {
+            "schedule": sched, "value_form": "real parts" if rv else "complex",
+            "state_form": form, "algorithmic_bytes_per_step": nb,
+            "byte_accounting": ("canonical CSR: int32 column + complex value per entry, each "
+                                "vector once" if acc == "complex" else
+                                "canonical CSR with real values (half the complex element) "
+                                "for a real H: the specialisation's own accounting, not the "
+                                "contract's"),
+            "h_product_GBps": achieved, "h_product_frac_of_peak": achieved / HBM_PEAK_GBS,
+            "stored_bytes_per_launch": stored, "stored_GBps": stored / h_s / 1e9,
+            "column_form": "16-bit col^row codes" if x16 else "int32 CSR columns",
+            "pool_gradient_spmv_GBps": (nb["h_spmv"] + nb["pool_screen"]) /
+                                       ((leg["h_product_ms"] + ph["screen"]) / 1e3) / 1e9,
+            "eager_phase_ms": ph, **leg}
+
+    form = args.value_form
+    sched, leg, ph, plan = run_form(form, args.schedule)
+    head = form_record(form, sched, leg, ph)
+    nbytes = head["algorithmic_bytes_per_step"]
+    log(f"{form} form (schedule {sched}): {leg['ms_per_step']:.3f} ms/step = "
+        f"{leg['updates_per_s']:.0f} updates/s; step latency p50 "
+        f"{leg['step_latency']['p50_ms']:.3f} p99 {leg['step_latency']['p99_ms']:.3f} ms "
+        f"(n={leg['step_latency']['n']}); H product {leg['h_product_ms'] * 1e3:.1f} us "
+        f"({head['h_product_GBps']:.0f} GB/s algorithmic, frac "
+        f"{head['h_product_frac_of_peak']:.3f}; {head['stored_GBps']:.0f} GB/s stored); eager "
+        f"screen {ph['screen'] * 1e3:.1f} us, Taylor {ph['taylor'] * 1e3:.1f} us, renorm "
+        f"{ph['renorm'] * 1e3:.1f} us")
+    plan.close()
+
+    real_block = None
+    if args.real_block and form == "complex" and all(d.H.real for d in ds):
+        rs, rleg, rph, rplan = run_form("real")
+        real_block = form_record("real", rs, rleg, rph)
+        real_block["note"] = ("real-value specialisation: the real parts of a real H streamed "
+                              "in a row-padded layout, real states from the reference screened "
+                              "and multiplied in real arithmetic; reported apart from the "
+                              "complex contract")
+        log(f"real-value form (schedule {rs}): {rleg['ms_per_step']:.3f} ms/step = "
+            f"{rleg['updates_per_s']:.0f} updates/s; H product {rleg['h_product_ms'] * 1e3:.1f} us")
+    else:
+        rplan = None
 
     # the same step with the angle chosen by line search (two more H products
-    # per state); a separate figure, not the headline value
+    # per state); a separate figure, not the headline value.  Runs on the
+    # real-value plan (states from the reference) when there is one.
+    lplan = rplan if rplan is not None else PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
     line_search = None
     if args.line_search_steps > 0:
-        plan.set_line_search(1.0)
+        lplan.set_line_search(1.0)
         for _ in range(2):
-            plan.step(renorm=True, graph=True, line_search=True)
+            lplan.step(renorm=True, graph=True, line_search=True)
         torch.cuda.synchronize()
-        e_before = plan.energies.view(-1, 3)[:, 0].clone()
+        e_before = lplan.energies.view(-1, 3)[:, 0].clone()
         l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         l0.record(stream)
         for _ in range(args.line_search_steps):
-            plan.step(renorm=True, graph=True, line_search=True)
+            lplan.step(renorm=True, graph=True, line_search=True)
         l1.record(stream)
         torch.cuda.synchronize()
         ls_ms = l0.elapsed_time(l1) / args.line_search_steps
-        plan.step(update=False)
+        lplan.step(update=False)
         torch.cuda.synchronize()
-        drop = float((e_before - plan.energies.view(-1, 3)[:, 0]).mean())
-        plan.set_line_search(0.0)
+        drop = float((e_before - lplan.energies.view(-1, 3)[:, 0]).mean())
+        lplan.set_line_search(0.0)
         line_search = {"ms_per_step": ls_ms, "updates_per_s": len(ds) / (ls_ms / 1e3),
                        "steps": args.line_search_steps, "theta_max": 1.0,
                        "mean_energy_drop_Ha": drop}
@@ -407,8 +623,8 @@ def main():
         for mode in ("line_search", "line_search+reoptimization"):
             for d in ds:
                 d.reset()
-            plan.set_line_search(1.0)
-            hist = PB.AnsatzHistory(plan, S)
+            lplan.set_line_search(1.0)
+            hist = PB.AnsatzHistory(lplan, S)
             gm = torch.zeros((S, len(ds)), dtype=torch.float64, device="cuda")
             en = torch.zeros((S + 1, len(ds)), dtype=torch.float64, device="cuda")
             r_ms = 0.0
@@ -416,9 +632,9 @@ def main():
             a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a0.record(stream)
             for t in range(S):
-                plan.step(renorm=True, line_search=True)
-                gm[t].copy_(plan.gmax)
-                en[t].copy_(plan.energies.view(-1, 3)[:, 0])
+                lplan.step(renorm=True, line_search=True)
+                gm[t].copy_(lplan.gmax)
+                en[t].copy_(lplan.energies.view(-1, 3)[:, 0])
                 hist.record()
                 if mode != "line_search":
                     r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -428,8 +644,8 @@ def main():
                     r1.synchronize()
                     r_ms += r0.elapsed_time(r1)
             a1.record(stream)
-            plan.step(update=False)
-            en[S].copy_(plan.energies.view(-1, 3)[:, 0])
+            lplan.step(update=False)
+            en[S].copy_(lplan.energies.view(-1, 3)[:, 0])
             torch.cuda.synchronize()
             total = a0.elapsed_time(a1)
             g = gm.cpu().numpy()
@@ -439,30 +655,21 @@ def main():
                     for i in range(len(ds))]
             adapt[mode] = {"ms_total": total, "reoptimization_ms_total": r_ms if r_ms else None,
                            "mean_energy_drop_Ha": float((e[0] - e[S]).mean()),
-                           "mean_final_gmax": float(np.abs(plan.gmax.cpu().numpy()).mean()),
+                           "mean_final_gmax": float(np.abs(lplan.gmax.cpu().numpy()).mean()),
                            "states_converged": int(sum(c is not None for c in conv))}
             log(f"adaptive run ({mode}): {S} steps in {total:.1f} ms, mean energy drop "
                 f"{(e[0] - e[S]).mean():.4f} Ha, mean final max|g| "
                 f"{adapt[mode]['mean_final_gmax']:.2e}, {adapt[mode]['states_converged']} of "
                 f"{len(ds)} states reached max|g| < {eps:g}")
-        plan.set_line_search(0.0)
+        lplan.set_line_search(0.0)
+    lplan.close()
 
-    # phase breakdown of the same step launched eagerly (context figures)
-    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(10)]
-    for t in range(10):
-        plan.step_timed(ev2[t], renorm=True)
-    torch.cuda.synchronize()
-    screen_avg = float(np.mean([e[2].elapsed_time(e[3]) for e in ev2]))
-    taylor_avg = float(np.mean([e[4].elapsed_time(e[5]) for e in ev2]))
-    norm_avg = float(np.mean([e[5].elapsed_time(e[6]) for e in ev2]))
-    eager_spmv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev2]))
-    eager_step = float(np.mean([e[0].elapsed_time(e[6]) for e in ev2]))
-    screen_gbs = (nbytes["h_spmv"] + nbytes["pool_screen"]) / ((spmv_avg + screen_avg) / 1e3) / 1e9
-    log(f"timed: {ms_per_step:.3f} ms/step (graphs); H product {spmv_avg * 1e3:.1f} us "
-        f"({achieved:.0f} GB/s algorithmic, {stored / (spmv_avg / 1e3) / 1e9:.0f} GB/s of stored "
-        f"bytes), rest of step {np.mean(rest_ms) * 1e3:.1f} us; eager: step "
-        f"{eager_step * 1e3:.1f} us, H {eager_spmv * 1e3:.1f} us, screen {screen_avg * 1e3:.1f} us, "
-        f"Taylor {taylor_avg * 1e3:.1f} us, renorm {norm_avg * 1e3:.1f} us")
+    mixed = None
+    if args.mixed_batch and args.qubits == 14 and args.dtype == "c64":
+        mixed = mixed_batch_leg(ctx, stream, args.matrix_free, K, W, L, R)
+        log(f"mixed 10/12/14 batch: {mixed['ms_per_step']:.3f} ms/step = "
+            f"{mixed['updates_per_s']:.0f} updates/s, H product {mixed['h_product_ms'] * 1e3:.1f} us "
+            f"({mixed['h_product_GBps']:.0f} GB/s), step p99 {mixed['step_latency']['p99_ms']:.3f} ms")
 
     # practical HBM ceiling for context: a plain device copy (read + write) of 2 GiB
     # (an elementwise kernel, dst = src * 1, so profilers see it as a kernel)
@@ -490,72 +697,84 @@ def main():
 
     plain = None
     if not args.no_plain:
-        tr, sr = plain_fp64_path(ctx, systems[0], 200)
-        plain = {"taylor_updates_per_s": tr, "adaptive_steps_per_s": sr}
-        log(f"plain FP64 single-request path: {tr:.0f} Taylor updates/s, {sr:.0f} steps/s")
+        tr, sr, tlat, slat = plain_fp64_path(ctx, systems[0], 200)
+        plain = {"taylor_updates_per_s": tr, "adaptive_steps_per_s": sr,
+                 "taylor_request_latency": tlat, "step_request_latency": slat,
+                 "batched_speedup_updates": head["updates_per_s"] / tr}
+        log(f"plain FP64 single-request path: {tr:.0f} Taylor updates/s "
+            f"(p50 {tlat['p50_ms'] * 1e3:.0f} us), {sr:.0f} steps/s (p50 "
+            f"{slat['p50_ms']:.3f} ms)")
 
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(systems, args.cpu_seconds)
-        log(f"cpu baseline: {cpu['value']:.2f} updates/s on {cpu['cores']} threads")
+    if not args.no_cpu_baseline and args.qubits == 14:
+        psi0 = vs.complex_start_state(systems[0]).astype(np.complex64).astype(np.complex128)
+        cpu = cpu_baseline(systems[0], psi0, args.cpu_reps, args.cpu_warmup)
+        ph1 = cpu["phases_by_threads"]
+        log(f"cpu baseline ({cpu['cpu_model']}): {cpu['value']:.1f} updates/s on {cpu['cores']} "
+            f"threads; medians " + "; ".join(
+                f"{nt} thr: " + ", ".join(f"{k} {v['median_ms']:.2f} ms" for k, v in r.items())
+                for nt, r in ph1.items()))
 
     serving = None
     if args.serve_requests > 0:
-        serving = serving_bench(args.serve_requests, min(128, args.serve_requests // 4))
+        serving = serving_bench(args.serve_requests, min(args.serve_warmup,
+                                                         args.serve_requests // 4))
 
     hnnz = ds[0].H.nnz
+    tiled = plan_tiled(ds)
     out = {
         "metric": f"Taylor-O(5) updates/s + pool-gradient SpMV HBM GB/s at {args.qubits} qubits; "
                   f"p99 latency",
-        "value": updates_per_s,
+        "value": head["updates_per_s"],
         "unit": "updates/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.dtype == "c64" else "f64",
         "accumulate": "f64",
-        "data": "synthetic (seeded molecule-shaped random integrals; no molecular data)",
+        "data": "synthetic (seeded molecule-shaped random integrals; seeded complex start "
+                "states in each state's particle sector; no molecular data)",
         "config": {
             "workload": f"{len(ds)} independent states x {args.qubits} qubits ({args.qubits // 2} "
                         f"orbitals, {vs.ELECTRONS[args.qubits]} electrons, {args.mapping.upper()}), "
                         f"H nnz {hnnz} each, pool {ds[0].pool.M} shared; one adaptive step per state per "
                         f"launch sequence (H SpMV + FP64 energy, {ds[0].pool.M}-generator gradient screen, "
-                        f"argmax, fused Taylor-O(5), FP64 renorm)",
+                        f"argmax, fused Taylor-O(5), FP64 renorm); {head['value_form']} values, "
+                        f"{form} states",
             "states": len(ds), "n_qubits": args.qubits, "n_electrons": vs.ELECTRONS[args.qubits],
             "mapping": args.mapping, "pool": ds[0].pool.M, "storage": args.dtype,
+            "value_form": head["value_form"], "state_form": form,
             "spmv_schedule": sched,
             "pool_form": "matrix-free records" if args.matrix_free else "pair tables from the pool CSR",
         },
-        "pool_gradient_spmv_GBps": screen_gbs,
-        "p50_step_ms": percentile(step_ms, 50),
-        "p99_step_ms": percentile(step_ms, 99),
-        "event_timed_steps": {"every": SAMPLE, "count": len(timed),
-                              "note": "H-product and step durations (roofline, p50/p99) come "
-                                      "from these steps of the timed region"},
-        "eager_ms_per_step": eager_step,
-        "device_copy_GBps": copy_gbs,
-        "device_read_GBps": read_gbs,
-        "phase_ms": {"h_spmv": spmv_avg, "rest_of_step": float(np.mean(rest_ms)),
-                     "screen_eager": screen_avg, "taylor_eager": taylor_avg,
-                     "renorm_eager": norm_avg},
+        "pool_gradient_spmv_GBps": head["pool_gradient_spmv_GBps"],
+        "p50_step_ms": head["step_latency"]["p50_ms"],
+        "p99_step_ms": head["step_latency"]["p99_ms"],
+        "step_latency": head["step_latency"],
+        "eager_phase_ms": head["eager_phase_ms"],
         "algorithmic_bytes_per_step": nbytes,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(sched, f"{len(ds)}x{args.qubits}q-{args.mapping}-{args.dtype}"),
+        "roofline": {"bound": "hbm", "achieved": head["h_product_GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["h_product_frac_of_peak"],
+                     "traffic": measured_traffic(sched, wl),
                      "traffic_unit": "bytes per launch (HBM read + write, PMC-calibrated)",
                      "kernel": (f"column-tiled H product of all {len(ds)} states (k_spmv_tiled, "
-                                f"then k_spmv_tile_sum)" if plan_tiled(ds) else
+                                f"then k_spmv_tile_sum)" if tiled else
                                 f"H product of all {len(ds)} states (one launch of the schedule's "
                                 f"kernel: k_spmv_lds_pf, k_spmv_lds or k_spmv_energy)"),
                      "bytes_per_launch": nbytes["h_spmv"],
-                     "stored_bytes_per_launch": stored,
-                     "stored_GBps": stored / (spmv_avg / 1e3) / 1e9,
-                     "column_form": "16-bit col^row codes" if x16 else "int32 CSR columns",
-                     "value_form": "real parts" if rv else "complex"},
+                     "launch_ms": head["h_product_ms"],
+                     "launches_timed": head["h_product_launches_timed"],
+                     "stored_bytes_per_launch": head["stored_bytes_per_launch"],
+                     "stored_GBps": head["stored_GBps"],
+                     "column_form": head["column_form"],
+                     "value_form": head["value_form"]},
+        "headline_leg": head,
+        "real_value_form": real_block,
+        "mixed_batch_c4": mixed,
         "plain_fp64_single_request": plain,
         "line_search": line_search,
         "adaptive_runs": adapt,
@@ -563,11 +782,12 @@ def main():
         "serving": serving,
         "p99_latency_ms": (serving["x0.8"]["continuous_batching"]["p99_ms"] if serving
                            else None),
+        "device_copy_GBps": copy_gbs,
+        "device_read_GBps": read_gbs,
         "cpu_baseline": cpu,
-        "host_wall_s": wall,
+        "host_wall_s": head["host_wall_s"],
     }
     print(json.dumps(out), flush=True)
-    plan.close()
     ctx.close()
 
 

@@ -39,6 +39,19 @@ int orc_threads(void)
 #endif
 }
 
+/* Threads used by the parallel loops from now on (for timing the oracle at a
+ * given core count; results do not depend on it, since every row is computed
+ * by one thread in the order written). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static int popcount64(uint64_t v)
 {
     int n = 0;

@@ -63,6 +63,8 @@ def lib():
         build()
         L = C.CDLL(LIB_PATH)
         L.orc_threads.restype = C.c_int
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_csr_build.restype = C.c_int64
         L.orc_csr_build.argtypes = [C.c_int, C.c_int64, _U64, _U64, _D, C.c_double, _I64,
                                     C.c_void_p, C.c_void_p]
@@ -85,6 +87,11 @@ def lib():
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 @dataclass

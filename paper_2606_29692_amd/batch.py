@@ -110,17 +110,21 @@ def make_batch(ctx: B.Context, systems: list, schedules=None) -> B.BatchPlan:
     return B.BatchPlan(ctx, [(s.H, s.pool, s.psi) for s in systems], schedules=schedules)
 
 
-def bytes_per_step(systems: list) -> dict:
-    """Algorithmic HBM bytes of one adaptive step (canonical CSR, each vector
-    once): the H product and the pool screen (pool CSR counted once per
-    distinct pool), and the Taylor update of a single-excitation generator.
-    A CSR's values count in the operator's own field: real values (half the
-    complex element) for an operator whose entries are all real."""
+def bytes_per_step(systems: list, value_form: str = "complex") -> dict:
+    """Algorithmic HBM bytes of one adaptive step (canonical CSR with
+    interleaved complex values, each vector once): the H product and the pool
+    screen (pool CSR counted once per distinct pool), and the Taylor update of
+    a single-excitation generator.  value_form "real" counts the values of an
+    operator whose entries are all real at half the complex element (the
+    accounting of the real-value specialisation, reported apart from the
+    complex contract)."""
+    if value_form not in ("complex", "real"):
+        raise ValueError(f"value form {value_form!r}")
     out = {"h_spmv": 0, "pool_screen": 0, "taylor": 0}
     seen = set()
 
     def vsize(op):
-        return op.val.element_size() // (2 if op.real else 1)
+        return op.val.element_size() // (2 if value_form == "real" and op.real else 1)
 
     for s in systems:
         dim = s.H.dim

@@ -40,6 +40,38 @@ class VqeError(RuntimeError):
         self.status = status
 
 
+# Injected failures, for tests of failure handling: kind -> failures left.
+# "alloc": the binding's next device allocations raise VqeError(VQE_ENOMEM)
+# before touching the device, as the library reports a failed allocation.
+# The environment variable ADAPTVQE_FAULT=alloc:N arms N of them at import.
+_FAULTS: dict = {}
+_FAULT_STATUS = {"alloc": VQE_ENOMEM}
+
+
+def inject_fault(kind: str, count: int = 1):
+    if kind not in _FAULT_STATUS:
+        raise ValueError(f"unknown fault kind {kind!r}")
+    _FAULTS[kind] = int(count)
+
+
+def check_fault(kind: str):
+    """Raise the injected failure of this kind if one is armed."""
+    n = _FAULTS.get(kind, 0)
+    if n > 0:
+        _FAULTS[kind] = n - 1
+        raise VqeError(_FAULT_STATUS[kind], f"injected {kind} failure")
+
+
+def _arm_from_env():
+    spec = os.environ.get("ADAPTVQE_FAULT", "")
+    if spec:
+        kind, _, n = spec.partition(":")
+        inject_fault(kind, int(n or 1))
+
+
+_arm_from_env()
+
+
 class vqe_csr(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("dtype", C.c_int32), ("dim", C.c_int64),
                 ("nnz", C.c_int64), ("rowptr", C.c_void_p), ("col", C.c_void_p),
@@ -248,6 +280,7 @@ def csr_build_from_pauli(ctx: Context, n_qubits: int, xmask, zmask, coeff,
         drop_tol = default_tol(c)
     dt = DTYPES[dtype]
     dim = 1 << n_qubits
+    check_fault("alloc")
     rowptr = torch.empty(dim + 1, dtype=torch.int32, device=ctx.torch_device)
     desc = vqe_csr()
     desc.rowptr = rowptr.data_ptr()
@@ -257,6 +290,7 @@ def csr_build_from_pauli(ctx: Context, n_qubits: int, xmask, zmask, coeff,
     ctx.check(lib().csr_build_from_pauli(*args, C.byref(desc), C.byref(nnz)),
               "csr_build_from_pauli (sizing)")
     n = max(int(nnz.value), 1)
+    check_fault("alloc")
     col = torch.empty(n, dtype=torch.int32, device=ctx.torch_device)
     val = torch.empty(n, dtype=torch.complex128 if dt == VQE_C128 else torch.complex64,
                       device=ctx.torch_device)

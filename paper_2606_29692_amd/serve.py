@@ -18,6 +18,14 @@ slot group launches a micro-batch of the oldest ready requests as soon as its
 previous micro-batch completes, and completions are polled without blocking.
 Latencies are host-observed (arrival to completion seen by the loop).
 
+Failures: a request whose angle is not finite is failed on the host before
+any launch (status EINVAL, as the library would return); a run whose
+admission raises (its operator cannot be built: bad masks, out of memory) is
+marked failed with all its queued requests, and later requests for it fail at
+once; a launch or result read-back that raises fails the requests of that
+micro-batch, frees their slots and leaves every other run serving.  Failed
+requests complete with ``error`` set and are kept out of the latency figures.
+
 The scheduling logic is written against the ``Executor`` interface so it can
 be exercised without a GPU; ``DeviceExecutor`` is the HIP implementation.
 """
@@ -41,10 +49,17 @@ class Request:
     selected: int | None = None
     gmax: float | None = None
     cold: bool = False              # the run had to be (re)built on the device first
+    theta: float | None = None      # angle of this step (default: the run's next angle)
+    error: str | None = None        # set when the request failed
+    status: int = 0                 # library status of a failure (negative), else 0
 
     @property
     def latency(self) -> float:
         return self.t_done - self.t_arrival
+
+    @property
+    def failed(self) -> bool:
+        return self.error is not None
 
 
 @dataclass
@@ -58,6 +73,8 @@ class RunState:
     busy: bool = False
     queue: collections.deque = field(default_factory=collections.deque)
     last_used: float = 0.0
+    failed: str | None = None       # admission failed: the run serves no more requests
+    failed_status: int = 0
 
 
 class Executor:
@@ -90,6 +107,9 @@ class Executor:
     def results(self, key: tuple, batch: list) -> list:   # [(energy, k, gmax)]
         raise NotImplementedError
 
+    def release(self, key: tuple, slot: int):       # a failed slot: unbind it (optional)
+        pass
+
 
 class Server:
     """Continuous batching over slot groups with admission by HBM footprint."""
@@ -108,12 +128,46 @@ class Server:
             self.by_key[r.key].append(r)
         self.inflight: dict = {}            # key -> list of (req, slot)
         self.completed: list = []
+        self.failed: list = []
         self.admission_waits = 0
         self.evictions = 0
 
+    @property
+    def failed_count(self) -> int:
+        return len(self.failed)
+
+    # ------------------------------------------------------------------ failures
+    def _fail(self, req: Request, msg: str, status: int):
+        now = self.clock()
+        if req.t_start is None:
+            req.t_start = now
+        req.t_done = now
+        req.error, req.status = msg, int(status)
+        self.completed.append(req)
+        self.failed.append(req)
+
+    def _fail_run(self, r: RunState, msg: str, status: int):
+        """Mark a run failed and fail every request queued for it."""
+        r.failed, r.failed_status = msg, int(status)
+        r.busy = False
+        while r.queue:
+            self._fail(r.queue.popleft(), msg, status)
+
+    def _release(self, key: tuple, slot: int):
+        slots = self.slots[key]
+        slots[slot] = None
+        try:
+            self.ex.release(key, slot)
+        except Exception:       # noqa: BLE001 (a release failure must not stop serving)
+            pass
+
     # ------------------------------------------------------------------ requests
     def submit(self, req: Request):
-        self.runs[req.run].queue.append(req)
+        r = self.runs[req.run]
+        if r.failed is not None:
+            self._fail(req, r.failed, r.failed_status)
+            return
+        r.queue.append(req)
 
     def pending(self) -> int:
         return sum(len(r.queue) for r in self.runs.values()) + sum(
@@ -142,12 +196,18 @@ class Server:
         if r.resident:
             return True
         if r.footprint > self.budget - self.ex.fixed_bytes():
-            raise RuntimeError(f"run {r.run} needs {r.footprint} bytes: more than the budget "
-                               f"leaves after the fixed {self.ex.fixed_bytes()} bytes")
+            self._fail_run(r, f"run {r.run} needs {r.footprint} bytes: more than the budget "
+                              f"leaves after the fixed {self.ex.fixed_bytes()} bytes",
+                           STATUS_ENOMEM)
+            return False
         if not self._make_room(r.footprint):
             self.admission_waits += 1
             return False
-        self.ex.admit(r.run)
+        try:
+            self.ex.admit(r.run)
+        except (RuntimeError, ValueError, MemoryError) as e:
+            self._fail_run(r, f"admission of run {r.run} failed: {e}", _status_of(e))
+            return False
         r.resident = True
         r.footprint = self.ex.footprint(r.run)      # the built size replaces the estimate
         self.used += r.footprint
@@ -163,7 +223,11 @@ class Server:
                 continue
             if self.used + r.footprint > self.budget:
                 continue
-            self.ex.admit(r.run)
+            try:
+                self.ex.admit(r.run)
+            except (RuntimeError, ValueError, MemoryError) as e:
+                self._fail_run(r, f"admission of run {r.run} failed: {e}", _status_of(e))
+                continue
             r.resident = True
             r.footprint = self.ex.footprint(r.run)
             self.used += r.footprint
@@ -176,7 +240,11 @@ class Server:
         for key in list(self.inflight):
             if self.ex.done(key):
                 batch = self.inflight.pop(key)
-                res = self.ex.results(key, [(req.run, slot) for req, slot in batch])
+                try:
+                    res = self.ex.results(key, [(req.run, slot) for req, slot in batch])
+                except (RuntimeError, ValueError) as e:
+                    self._fail_batch(key, batch, f"result read-back failed: {e}", _status_of(e))
+                    continue
                 now = self.clock()
                 for (req, slot), (e, k, gm) in zip(batch, res):
                     req.t_done = now
@@ -187,11 +255,18 @@ class Server:
                     r.last_used = now
                     self.completed.append(req)
 
+    def _fail_batch(self, key: tuple, batch: list, msg: str, status: int):
+        for req, slot in batch:
+            r = self.runs[req.run]
+            r.busy = False
+            self._release(key, slot)
+            self._fail(req, msg, status)
+
     def schedule(self):
         for key, slots in self.slots.items():
             if key in self.inflight:
                 continue
-            ready = [r for r in self.by_key[key] if r.queue and not r.busy]
+            ready = [r for r in self.by_key[key] if r.queue and not r.busy and r.failed is None]
             if not ready:
                 continue
             ready.sort(key=lambda r: r.queue[0].t_arrival)
@@ -200,6 +275,13 @@ class Server:
             for r in ready:
                 if len(batch) == len(slots):
                     break
+                head = r.queue[0]
+                th = head.theta if head.theta is not None else float(r.thetas[r.step % len(r.thetas)])
+                if not np.isfinite(th):
+                    # the library refuses a non-finite angle (VQE_EINVAL); fail it here
+                    self._fail(r.queue.popleft(), f"request {head.rid}: non-finite angle {th}",
+                               STATUS_EINVAL)
+                    continue
                 cold = not r.resident
                 if not self._admit(r):
                     continue
@@ -215,9 +297,14 @@ class Server:
                 req.t_start = self.clock()
                 req.cold = cold
                 r.busy = True
-                batch.append((req, slot, float(r.thetas[r.step % len(r.thetas)])))
+                batch.append((req, slot, th))
             if batch:
-                self.ex.launch(key, [(req.run, slot, th) for req, slot, th in batch])
+                try:
+                    self.ex.launch(key, [(req.run, slot, th) for req, slot, th in batch])
+                except (RuntimeError, ValueError) as e:
+                    self._fail_batch(key, [(req, slot) for req, slot, _ in batch],
+                                     f"launch failed: {e}", _status_of(e))
+                    continue
                 self.inflight[key] = [(req, slot) for req, slot, _ in batch]
 
     def _in_use(self, run: int) -> bool:
@@ -253,6 +340,16 @@ class Server:
         return pending
 
 
+STATUS_EINVAL = -1      # the library's VQE_EINVAL
+STATUS_ENOMEM = -3      # the library's VQE_ENOMEM
+STATUS_UNKNOWN = -4     # a failure without a library status (reported as a HIP-side error)
+
+
+def _status_of(e) -> int:
+    st = getattr(e, "status", None)
+    return int(st) if isinstance(st, int) else STATUS_UNKNOWN
+
+
 def poisson_trace(n_requests: int, rate: float, n_runs: int, seed: int) -> list:
     """Poisson arrivals at `rate` requests/s, each for a uniformly drawn run."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 3]))
@@ -263,12 +360,17 @@ def poisson_trace(n_requests: int, rate: float, n_runs: int, seed: int) -> list:
 
 
 def latency_summary(reqs: list, skip: int = 0) -> dict:
-    lat = np.array([q.latency for q in reqs[skip:]]) * 1e3
-    span = max(q.t_done for q in reqs[skip:]) - min(q.t_arrival for q in reqs[skip:])
+    """Latency percentiles and throughput of the completed requests after the
+    first `skip` (warm-up); failed requests are counted, not timed."""
+    tail = reqs[skip:]
+    ok = [q for q in tail if not q.failed]
+    lat = np.array([q.latency for q in ok]) * 1e3
+    span = max(q.t_done for q in ok) - min(q.t_arrival for q in ok)
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "p999_ms": float(np.percentile(lat, 99.9)), "mean_ms": float(lat.mean()),
             "updates_per_s": len(lat) / span, "n": int(len(lat)),
-            "cold": int(sum(q.cold for q in reqs[skip:]))}
+            "failed": int(len(tail) - len(ok)),
+            "cold": int(sum(q.cold for q in ok))}
 
 
 # ---------------------------------------------------------------------- device
@@ -312,6 +414,11 @@ class DeviceExecutor(Executor):
                 probe = PB.device_system(ctx, systems[rep_run], dtype, _SinglePool(pool))
             stream.synchronize()
             self.key_fp[key] = probe.H.nbytes() + dim * probe.psi.element_size()
+            # the idle-slot placeholder (no terms, so vacuously real) takes the
+            # representative's real flag: the slot's effective schedule then
+            # equals that of the runs later bound to it
+            if not probe.H.real:
+                empty.desc.flags &= ~B.VQE_REAL
             if schedules and key in schedules:
                 sched_k = int(schedules[key])
             else:
@@ -420,6 +527,12 @@ class DeviceExecutor(Executor):
         k = g["h_k"].numpy()
         gm = g["h_g"].numpy()
         return [(float(e[slot]), int(k[slot]), float(gm[slot])) for _, slot in batch]
+
+    def release(self, key: tuple, slot: int):
+        g = self.group[key]
+        run = g.get("bound", {}).get(slot)
+        if run is not None:
+            self.unbind(run)
 
     def psi(self, run: int):
         if run in self.dev:

@@ -4,10 +4,13 @@ A schedule is the number of wave lanes per CSR row (8, 16, 32, 64) with the
 VQE_SPMV_* options: wide loads (VEC4), the state staged in LDS (LDS, DEEP),
 the pipelined loads (PREFETCH), 16-bit column codes (X16) and, for a real H,
 the real values in the row-padded layout (REAL).  It is picked
-per (register size, dtype, mapping, device) by timing the batched H product
-phase of a real plan over the candidates, and cached.  The choice is
-a function of that key alone, so a state gets the same schedule (and the same
-floating-point summation order) whether it runs alone or inside any batch.
+per (register size, dtype, mapping, value form, device) by timing the batched
+H product phase of a real plan over the candidates, and cached.  The value
+form "complex" keeps the interleaved complex values of the CSR (candidates
+without REAL); "any" also admits REAL, which applies to Hamiltonians whose
+entries are all real.  The choice is a function of that key alone, so a state
+gets the same schedule (and the same floating-point summation order) whether
+it runs alone or inside any batch.
 
 Cache: ``tuned_schedules.json`` next to this file (committed results), plus
 the file named by ADAPTVQE_TUNE_CACHE when set (written after tuning).
@@ -37,9 +40,19 @@ _memo: dict = {}
 _last_timings: dict = {}
 
 
-def _key(ctx, ds) -> str:
+VALUE_FORMS = ("any", "complex")
+
+
+def _key(ctx, ds, value_form: str = "any") -> str:
+    if value_form not in VALUE_FORMS:
+        raise ValueError(f"value form {value_form!r}: expected one of {VALUE_FORMS}")
     _, name = ctx.info()
-    return f"{name}|n{ds.n_qubits}|{ds.dtype}|{ds.key[2]}"
+    key = f"{name}|n{ds.n_qubits}|{ds.dtype}|{ds.key[2]}"
+    return key if value_form == "any" else key + "|complex"
+
+
+def candidates_for(value_form: str = "any") -> tuple:
+    return CANDIDATES if value_form == "any" else tuple(c for c in CANDIDATES if not c & _R)
 
 
 def _load() -> dict:
@@ -90,10 +103,11 @@ def tune_schedule(ctx, systems, candidates=CANDIDATES) -> dict:
     return {"schedule": best, "ms": {str(k): v for k, v in res.items()}}
 
 
-def schedule_for(ctx, ds, systems=None, retune: bool = False) -> int:
+def schedule_for(ctx, ds, systems=None, retune: bool = False, value_form: str = "any") -> int:
     """Tuned schedule for systems shaped like ``ds`` (tuning on ``systems`` or
-    [ds] when no cached entry exists)."""
-    key = _key(ctx, ds)
+    [ds] when no cached entry exists); value_form "complex" restricts the
+    candidates to schedules that stream the complex values."""
+    key = _key(ctx, ds, value_form)
     if not retune:
         if key in _memo:
             return _memo[key]
@@ -101,14 +115,14 @@ def schedule_for(ctx, ds, systems=None, retune: bool = False) -> int:
         if key in cache:
             _memo[key] = int(cache[key]["schedule"])
             return _memo[key]
-    rec = tune_schedule(ctx, systems or [ds])
+    rec = tune_schedule(ctx, systems or [ds], candidates_for(value_form))
     _memo[key] = rec["schedule"]
     _store(key, rec)
     return rec["schedule"]
 
 
-def last_record(ctx, ds) -> dict | None:
-    return _load().get(_key(ctx, ds))
+def last_record(ctx, ds, value_form: str = "any") -> dict | None:
+    return _load().get(_key(ctx, ds, value_form))
 
 
 def default_schedule(ds) -> int:

@@ -89,3 +89,48 @@ def test_served_runs_match_oracle():
         p = psi[r].astype(np.complex128)
         fid = abs(np.vdot(p, tr.psi)) ** 2 / (np.vdot(p, p).real * np.vdot(tr.psi, tr.psi).real)
         assert fid > 0.999999
+
+
+def test_failures_on_the_device_leave_other_runs_serving():
+    """A run whose Hamiltonian names a qubit outside its register (the device
+    CSR builder refuses it, VQE_EINVAL), an allocation failure injected through
+    the binding (VQE_ENOMEM) and a request with a NaN angle: those requests
+    fail with their status, and every other run's results equal the clean
+    trace's, step for step."""
+    import dataclasses
+    systems, thetas = make_runs()
+    trace = S.poisson_trace(90, rate=3000.0, n_runs=len(systems), seed=11)
+    clean, _, _ = serve(systems, thetas, trace)
+    res_clean = by_run(clean)
+
+    h = systems[4].hamiltonian
+    x = h.xmask.copy()
+    x[0] |= np.uint64(1 << h.n_qubits)
+    bad = dict(systems)
+    bad[4] = dataclasses.replace(systems[4], hamiltonian=dataclasses.replace(h, xmask=x))
+    reqs = [S.Request(q.rid, q.run, q.t_arrival) for q in trace]
+    nan_req = next(q for q in reqs if q.run == 3)
+    nan_req.theta = float("nan")
+    ex = S.DeviceExecutor(bad, slots_per_group=4, dtype="c64", schedules=SCHED)
+    server = S.Server(ex, thetas, budget_bytes=10**12)
+    # admission in run order: run 0 meets the injected failure, run 4 the
+    # builder's refusal
+    B.inject_fault("alloc", 1)
+    try:
+        resident = server.prewarm()
+    finally:
+        B.inject_fault("alloc", 0)
+    assert resident == len(systems) - 2
+    out = server.run_trace(reqs)
+    torch.cuda.synchronize()
+    assert len(out) == len(trace)
+    st = {q.run: q.status for q in out if q.failed and q.run != 3}
+    assert st == {0: B.VQE_ENOMEM, 4: B.VQE_EINVAL}
+    assert nan_req.failed and nan_req.status == B.VQE_EINVAL
+    res = by_run([q for q in out if not q.failed])
+    for r in systems:
+        if r in (0, 4):
+            assert r not in res
+            continue
+        assert res[r] == res_clean[r][:len(res[r])], r
+        assert len(res[r]) == len(res_clean[r]) - (1 if r == 3 else 0)

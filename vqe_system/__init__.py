@@ -7,9 +7,9 @@ the excitation pool (Sec. III-E) as Pauli packs, the reference determinant and
 the rotation angles.  It performs none of the method's own arithmetic (no CSR
 compilation, no sparse products, no Taylor update, energy or gradient).
 """
-from .configs import (ELECTRONS, System, SystemSpec, config_c1, config_c2, config_c3,
-                      config_c4, config_c5, make_system, reference_state, shared_pool,
-                      system_seed)
+from .configs import (ELECTRONS, System, SystemSpec, complex_start_state, config_c1, config_c2,
+                      config_c3, config_c4, config_c5, make_system, reference_state,
+                      sector_indices, shared_pool, system_seed)
 from .encoding import bk_matrix, encode_bits, encoding_matrix, gf2_inverse, jw_matrix, ladder_table
 from .fermion import (Excitation, PauliPack, excitation_list, generator_pack, hamiltonian_pack,
                       pool_packs, pool_size_formula, reference_occupation)

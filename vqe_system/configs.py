@@ -15,7 +15,7 @@ import numpy as np
 from .encoding import encode_bits, encoding_matrix
 from .fermion import (PauliPack, excitation_list, hamiltonian_pack, pool_packs,
                       reference_occupation)
-from .integrals import Integrals, draw_thetas, gen_integrals
+from .integrals import STREAM_START, Integrals, draw_thetas, gen_integrals, rng_for
 
 ELECTRONS = {4: 2, 6: 2, 8: 4, 10: 4, 12: 8, 14: 6, 16: 8, 18: 8, 20: 10}
 
@@ -74,6 +74,41 @@ def reference_state(sys: System, dtype=np.complex128) -> np.ndarray:
     return psi
 
 
+def sector_indices(sys: System) -> np.ndarray:
+    """Qubit basis indices of every determinant with the reference's numbers of
+    alpha (even spin-orbitals) and beta (odd) electrons, encoded by the
+    system's mapping; ascending."""
+    n = sys.spec.n_qubits
+    occ = np.arange(1 << n, dtype=np.int64)
+    ref = reference_occupation(sys.spec.n_electrons)
+
+    def count(v, parity):
+        return sum(((v >> m) & 1) for m in range(parity, n, 2))
+
+    keep = (count(occ, 0) == count(ref, 0)) & (count(occ, 1) == count(ref, 1))
+    dets = occ[keep]
+    if sys.spec.mapping == "jw":
+        return dets
+    beta = encoding_matrix(sys.spec.mapping, n)
+    return np.sort(np.array([encode_bits(beta, int(d)) for d in dets], dtype=np.int64))
+
+
+def complex_start_state(sys: System, eps: float = 0.1, dtype=np.complex128) -> np.ndarray:
+    """A seeded complex start state in the reference's particle sector: the
+    reference determinant plus eps times a complex Gaussian vector over the
+    sector (unit expected norm), scaled to unit norm.  Every amplitude outside
+    the sector is exactly zero, and almost every amplitude inside it has a
+    non-zero imaginary part, so products with it run in complex arithmetic."""
+    idx = sector_indices(sys)
+    rng = rng_for(sys.spec.seed, STREAM_START)
+    z = rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)
+    psi = np.zeros(sys.dim, dtype=np.complex128)
+    psi[idx] = eps * z / np.sqrt(2.0 * idx.size)
+    psi[sys.reference_index] += 1.0
+    psi /= np.linalg.norm(psi)
+    return psi.astype(dtype)
+
+
 # The five workloads.  Each returns a list of SystemSpec and a theta seed.
 def config_c1():
     """N=8 (4 orbitals, 4 electrons), JW, 5 adaptive steps."""
@@ -110,5 +145,6 @@ def config_c5(n_runs: int = 64, sizes=(8, 10, 12, 14, 16), seed: int = 5):
 
 
 __all__ = ["SystemSpec", "System", "make_system", "reference_state", "shared_pool",
+           "sector_indices", "complex_start_state",
            "system_seed", "draw_thetas", "excitation_list", "ELECTRONS",
            "config_c1", "config_c2", "config_c3", "config_c4", "config_c5"]

@@ -18,7 +18,8 @@ Recipe:
   * e_const: a scalar (identity) term, 0 unless asked for.
 
 Random streams: numpy's default_rng seeded by SeedSequence([seed, stream]),
-stream 0 for integrals, stream 1 for rotation angles.
+stream 0 for integrals, stream 1 for rotation angles, stream 4 for the
+complex start states.
 """
 from __future__ import annotations
 
@@ -28,6 +29,7 @@ import numpy as np
 
 STREAM_INTEGRALS = 0
 STREAM_THETA = 1
+STREAM_START = 4
 
 
 def rng_for(seed: int, stream: int) -> np.random.Generator:
