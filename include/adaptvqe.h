@@ -276,6 +276,29 @@ VQE_API int taylor5_apply(vqe_ctx *ctx, const vqe_csr *A, double theta, void *ps
 VQE_API int energy(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma_out, double *out);
 
 /*
+ * Energy without allocation.  For callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same computation, kernels and results as energy(), bit for bit;
+ * the FP64 block partial sums of the reduction are held in a static device
+ * array of the library (VQE_NOALLOC_SCRATCH_BYTES, one copy per GPU, reserved
+ * on every GPU the library runs on until the process ends) instead of the
+ * context's growable workspace.  sigma_out is required (device, dim elements
+ * of H->dtype).  The call makes no device allocation and synchronises
+ * nothing.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's partial sums (each call writes every sum it reads, so nothing
+ * needs clearing): calls that overlap on one GPU (other streams, other
+ * contexts, other host threads) race and must be ordered by the caller.
+ * Errors: as energy(); VQE_EINVAL for a null sigma_out; VQE_ESIZE when the
+ * reduction needs more than VQE_NOALLOC_SCRATCH_BYTES (three doubles per
+ * block of the default schedule: every operator of up to 2^20 rows fits);
+ * VQE_EHIP when the array's device address could not be obtained at
+ * vqe_create (vqe_last_error gives the reason).
+ */
+#define VQE_NOALLOC_SCRATCH_BYTES (4u << 20)
+VQE_API int energy_noalloc(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma_out,
+                           double *out);
+
+/*
  * Pool-gradient screen (Eq. 5): g_j = 2 Re sum_r conj(sigma_r) (A_j psi)_r for
  * j = 0..M-1, with sigma = H psi.  `sigma` (device, nullable) is the stored
  * product S psi returned by energy(); when NULL it is computed here.  The

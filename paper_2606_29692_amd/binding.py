@@ -120,6 +120,8 @@ SIGNATURES = {
     "taylor5_apply": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_double, C.c_void_p,
                                 C.c_int32, C.c_void_p]),
     "energy": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "energy_noalloc": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
     "pool_gradients": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.POINTER(vqe_pool),
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
     "vqe_select": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p,
@@ -322,6 +324,18 @@ def energy(ctx: Context, H: DeviceCSR, psi, sigma_out=None, out=None):
         out = torch.empty(3, dtype=torch.float64, device=ctx.torch_device)
     ctx.check(lib().energy(ctx.handle, C.byref(H.desc), _ptr(psi), _ptr(sigma_out), _ptr(out)),
               "energy")
+    return out
+
+
+VQE_NOALLOC_SCRATCH_BYTES = 4 << 20
+
+
+def energy_noalloc(ctx: Context, H: DeviceCSR, psi, sigma_out, out):
+    """energy() without any device allocation: sigma_out and out (device
+    double[3]) are the caller's; the reduction's partial sums use the
+    library's static per-GPU scratch array (see the header)."""
+    ctx.check(lib().energy_noalloc(ctx.handle, C.byref(H.desc), _ptr(psi), _ptr(sigma_out),
+                                   _ptr(out)), "energy_noalloc")
     return out
 
 

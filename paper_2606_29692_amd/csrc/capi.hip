@@ -19,10 +19,43 @@
 #include <cstdlib>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
 static const int kXcd = 8;
+
+// Scratch of the allocation-free entry points: a static device array, one
+// copy per GPU, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, never its device address: the address of each GPU's
+// copy is taken once per device at context creation (with that device
+// current) and used from then on.
+static __device__ __align__(256) double scratch[VQE_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+static const int kMaxDevices = 64;
+static double *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static void scratch_setup(vqe_ctx *ctx)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= kMaxDevices) {
+        vqe_fail(ctx, VQE_EHIP, "device %d: no scratch slot (at most %d devices)", ctx->device,
+                 kMaxDevices);
+        return;
+    }
+    if (!g_scratch_dev[ctx->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            vqe_fail(ctx, VQE_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s",
+                     ctx->device, hipGetErrorString(e));
+            return;
+        }
+        g_scratch_dev[ctx->device] = (double *)p;
+    }
+    ctx->scratch = g_scratch_dev[ctx->device];
+}
 
 extern "C" const char *vqe_strerror(int status)
 {
@@ -67,6 +100,9 @@ extern "C" int vqe_create(int device, void *hip_stream, vqe_ctx **out)
         delete ctx;
         return VQE_ENOMEM;
     }
+    // with the device current: this device's scratch address (a failure is
+    // reported by the allocation-free entry points, which need it)
+    scratch_setup(ctx);
     *out = ctx;
     return VQE_OK;
 }

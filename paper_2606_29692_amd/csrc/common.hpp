@@ -25,6 +25,9 @@ struct vqe_ctx {
     size_t ws_bytes;
     // Small pinned host buffer for scalar read-backs of the build phase.
     int64_t *host_scalars;
+    // This device's copy of the library's static scratch array (the
+    // allocation-free entry points), or null if its address is unknown.
+    double *scratch;
 };
 
 // Record an error message on the context and return `status`.

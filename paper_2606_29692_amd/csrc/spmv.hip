@@ -1535,6 +1535,29 @@ extern "C" int energy(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sig
     return vqe_spmv_energy_launch(ctx, H, psi, sigma_out, out, vqe_default_schedule(H));
 }
 
+extern "C" int energy_noalloc(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma_out,
+                              double *out)
+{
+    if (!ctx)
+        return VQE_EINVAL;
+    int rc = check_csr(ctx, H, "energy_noalloc");
+    if (rc)
+        return rc;
+    if (!psi || !sigma_out || !out)
+        return vqe_fail(ctx, VQE_EINVAL, "energy_noalloc: null psi, sigma_out or out");
+    const int lanes = vqe_default_schedule(H);
+    const size_t need = vqe_spmv_partials_bytes(H->dim, lanes);
+    if (need > VQE_NOALLOC_SCRATCH_BYTES)
+        return vqe_fail(ctx, VQE_ESIZE,
+                        "energy_noalloc: the reduction of a %lld-row operator needs %zu bytes of "
+                        "partial sums, more than the %u-byte scratch array",
+                        (long long)H->dim, need, (unsigned)VQE_NOALLOC_SCRATCH_BYTES);
+    if (!ctx->scratch)
+        return vqe_fail(ctx, VQE_EHIP, "energy_noalloc: the scratch array's device address is "
+                                       "unknown (%s)", ctx->err);
+    return vqe_spmv_energy_core(ctx, H, psi, sigma_out, out, lanes, ctx->scratch);
+}
+
 extern "C" int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *sigma,
                              int32_t schedule, int32_t reps, float *ms_out)
 {
