@@ -112,17 +112,47 @@ def plan_tiled(ds) -> bool:
     return any(d.H.dim * d.psi.element_size() > LDS_STATE_BYTES for d in ds)
 
 
+def plan_sched_pad(sched: int, ds) -> bool:
+    """True when the plan streams the complex values in the row-padded layout."""
+    from paper_2606_29692_amd import binding as B
+    return plan_sched_x16(sched, ds) and bool(sched & B.VQE_SPMV_PAD) and \
+        not plan_sched_real(sched, ds)
+
+
+BLK_ROWS, BLK_TILE_BYTES = 2048, 96 * 1024     # blocked layout of column-tiled states
+
+
+def plan_blocked(sched: int, d) -> bool:
+    """True when a column-tiled state runs the blocked layout (every tiled
+    state except the real-value form's, which keeps the CSR order)."""
+    from paper_2606_29692_amd import binding as B
+    big = d.H.dim * d.psi.element_size() > LDS_STATE_BYTES
+    real_tiled = bool(sched & B.VQE_SPMV_REAL) and bool(sched & B.VQE_SPMV_X16) and d.H.real \
+        and d.H.dim <= 65536
+    return big and bool(sched & B.VQE_SPMV_LDS) and bool(sched & B.VQE_SPMV_PREFETCH) and \
+        not real_tiled
+
+
 def stored_h_bytes(sched: int, ds) -> int:
     """Bytes the H-product kernel has to read and write per launch in the
     form it reads: row pointers, 2- or 4-byte columns, complex or real
-    values, the state and the result."""
+    values (row-padded or not), the state and the result.  A blocked state
+    reads each slab's row pointers once (per row block and column tile),
+    16-bit tile-local codes and the complex values."""
     x16, rv = plan_sched_x16(sched, ds), plan_sched_real(sched, ds)
+    pad = rv or plan_sched_pad(sched, ds)
     tot = 0
     for d in ds:
+        if plan_blocked(sched, d):
+            tc = BLK_TILE_BYTES // d.psi.element_size()
+            nb, nt = -(-d.H.dim // BLK_ROWS), -(-d.H.dim // tc)
+            tot += 4 * nb * nt * (BLK_ROWS + 1) + d.H.nnz * (2 + d.H.val.element_size()) + \
+                2 * d.H.dim * d.psi.element_size()
+            continue
         cb = 2 if x16 else 4
         vb = d.H.val.element_size() // (2 if rv else 1)
         nnz = d.H.nnz
-        if rv and d.H.dim * d.psi.element_size() <= LDS_STATE_BYTES:
+        if pad and d.H.dim * d.psi.element_size() <= LDS_STATE_BYTES:
             # the padded layout: every row rounded up to a multiple of eight
             lens = np.diff(d.H.rowptr.cpu().numpy().astype(np.int64))
             nnz = int(((lens + 7) // 8 * 8).sum())
@@ -553,7 +583,9 @@ def main():
                                 "contract's"),
             "h_product_GBps": achieved, "h_product_frac_of_peak": achieved / HBM_PEAK_GBS,
             "stored_bytes_per_launch": stored, "stored_GBps": stored / h_s / 1e9,
-            "column_form": "16-bit col^row codes" if x16 else "int32 CSR columns",
+            "column_form": ("16-bit col^row codes" if x16 else "int32 CSR columns") +
+                           (", rows padded to groups of eight" if rv or plan_sched_pad(sched, ds)
+                            else ""),
             "pool_gradient_spmv_GBps": (nb["h_spmv"] + nb["pool_screen"]) /
                                        ((leg["h_product_ms"] + ph["screen"]) / 1e3) / 1e9,
             "eager_phase_ms": ph, **leg}
@@ -761,7 +793,11 @@ def main():
                      "unit": "GB/s", "frac": head["h_product_frac_of_peak"],
                      "traffic": measured_traffic(sched, wl),
                      "traffic_unit": "bytes per launch (HBM read + write, PMC-calibrated)",
-                     "kernel": (f"column-tiled H product of all {len(ds)} states (k_spmv_tiled, "
+                     "kernel": (f"blocked column-tiled H product of all {len(ds)} states "
+                                f"(k_spmv_blk: row blocks of {BLK_ROWS}, column tiles of "
+                                f"{BLK_TILE_BYTES // 1024} KiB, accumulators in LDS)"
+                                if tiled and all(plan_blocked(sched, d) for d in ds) else
+                                f"column-tiled H product of all {len(ds)} states (k_spmv_tiled, "
                                 f"then k_spmv_tile_sum)" if tiled else
                                 f"H product of all {len(ds)} states (one launch of the schedule's "
                                 f"kernel: k_spmv_lds_pf, k_spmv_lds or k_spmv_energy)"),

@@ -507,6 +507,17 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * to the rounding of FP64 sums (bit for bit in the column-tiled form with
  * FP32 storage). */
 #define VQE_SPMV_REAL 0x8000
+/* VQE_SPMV_PAD (with VQE_SPMV_X16, 16, 32 or 64 lanes; batch plans only):
+ * the padded layout of VQE_SPMV_REAL with the complex values themselves
+ * (interleaved, 8 bytes per entry in FP32 storage): every row of the plan's
+ * copy of the codes and values starts at a multiple of eight entries and is
+ * padded with zero values (at most 7 pads per row, plus dim + 1 int32 row
+ * pointers), so a lane reads its eight codes with one 16-byte load and no
+ * entry needs a row mask.  Plan-owned, rebuilt by vqe_batch_rebind.  Dropped
+ * with the codes, for column-tiled states and where VQE_SPMV_REAL applies.
+ * The row sums are the same FP64 sums of exact-in-FP64 products, grouped over
+ * the lanes differently: results agree to the rounding of FP64 sums. */
+#define VQE_SPMV_PAD 0x10000
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given
  * schedule: `reps` back-to-back launches bracketed by HIP events on the

@@ -10,6 +10,8 @@
  * Functions and the passages they follow:
  *   orc_csr_build   Pauli sum (Eq. 3) -> CSR, the on-the-fly sparse
  *                   compilation of Sec. III-E.
+ *   orc_csr_rows    selected rows of that CSR (for sampled checks of very
+ *                   large operators).
  *   orc_spmv        y = M x, the sparse product each Taylor step and the
  *                   energy are made of (Sec. III-C, Eq. 7).
  *   orc_taylor5     the fifth-order update of Eq. 6, evaluated as the five
@@ -185,6 +187,62 @@ int64_t orc_csr_build(int n_qubits, int64_t n_terms, const uint64_t *x, const ui
             rowptr[r + 1] += rowptr[r];
     }
     return rowptr[dim];
+}
+
+/*
+ * Selected rows of the CSR matrix of a Pauli sum (Eq. 3), for checking a
+ * product at sampled rows when the whole matrix is too large to build: row j
+ * of the result is row rows[j] of orc_csr_build's matrix (same entries, same
+ * ordered sums, same drop rule), columns global.  Phase 1 (col == NULL) fills
+ * rowptr[0..n_rows] with the prefix sums of the rows' lengths; phase 2 fills
+ * col and val.  Returns the number of entries, or -1 on a bad argument or an
+ * allocation failure.
+ */
+int64_t orc_csr_rows(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t *z,
+                     const double *coeff, double tol, const int64_t *rows, int64_t n_rows,
+                     int64_t *rowptr, int32_t *col, double *val)
+{
+    if (n_qubits < 1 || n_qubits > 26 || n_terms < 0 || n_rows < 0)
+        return -1;
+    uint64_t dim = (uint64_t)1 << n_qubits;
+    for (int64_t t = 0; t < n_terms; t++)
+        if ((x[t] | z[t]) >> n_qubits)
+            return -1;
+    for (int64_t j = 0; j < n_rows; j++)
+        if (rows[j] < 0 || (uint64_t)rows[j] >= dim)
+            return -1;
+    int failed = 0;
+#pragma omp parallel
+    {
+        double *acc = (double *)malloc(2 * dim * sizeof(double));
+        unsigned char *seen = (unsigned char *)calloc(dim, 1);
+        int32_t *cols = (int32_t *)malloc((size_t)(n_terms > 0 ? n_terms : 1) * sizeof(int32_t));
+        if (!acc || !seen || !cols) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t j = 0; j < n_rows; j++) {
+                if (col == NULL)
+                    rowptr[j + 1] = build_row(n_qubits, n_terms, x, z, coeff, tol,
+                                              (uint64_t)rows[j], acc, seen, cols, NULL, NULL);
+                else
+                    build_row(n_qubits, n_terms, x, z, coeff, tol, (uint64_t)rows[j], acc, seen,
+                              cols, col + rowptr[j], val + 2 * rowptr[j]);
+            }
+        }
+        free(acc);
+        free(seen);
+        free(cols);
+    }
+    if (failed)
+        return -1;
+    if (col == NULL) {
+        rowptr[0] = 0;
+        for (int64_t j = 0; j < n_rows; j++)
+            rowptr[j + 1] += rowptr[j];
+    }
+    return rowptr[n_rows];
 }
 
 /* y_r = sum_{k in row r} val_k * x[col_k], complex, ascending k. */

@@ -6,6 +6,8 @@ this module imports nothing from the product package.
 
 Every function follows a passage of the paper:
   csr_build  -- Pauli sum (Eq. 3) compiled to CSR (Sec. III-E)
+  csr_rows, spmv_rows -- selected rows of that CSR and the product at them
+                (sampled checks of operators too large to build whole)
   spmv       -- one sparse product (Eq. 7)
   taylor5    -- fifth-order update, Eq. 6 via Eq. 7 and Eq. 8
   normalize  -- unit-norm rescaling (the paper is silent; see the readings)
@@ -68,6 +70,9 @@ def lib():
         L.orc_csr_build.restype = C.c_int64
         L.orc_csr_build.argtypes = [C.c_int, C.c_int64, _U64, _U64, _D, C.c_double, _I64,
                                     C.c_void_p, C.c_void_p]
+        L.orc_csr_rows.restype = C.c_int64
+        L.orc_csr_rows.argtypes = [C.c_int, C.c_int64, _U64, _U64, _D, C.c_double, _I64, C.c_int64,
+                                   _I64, C.c_void_p, C.c_void_p]
         L.orc_spmv.restype = None
         L.orc_spmv.argtypes = [C.c_int64, _I64, _I32, _D, _D, _D]
         L.orc_taylor5.restype = None
@@ -148,6 +153,48 @@ def csr_build(n_qubits: int, xmask, zmask, coeff, tol: float | None = None) -> C
 
 def csr_from_pack(pack, tol: float | None = None) -> CSR:
     return csr_build(pack.n_qubits, pack.xmask, pack.zmask, pack.coeff, tol)
+
+
+@dataclass
+class CSRRows:
+    """Rows `rows` of an operator's CSR (orc_csr_rows): row j of this matrix
+    is row rows[j] of the full one; columns are global."""
+    n_qubits: int
+    rows: np.ndarray     # int64[n]
+    rowptr: np.ndarray   # int64[n+1]
+    col: np.ndarray      # int32[nnz]
+    val: np.ndarray      # complex128[nnz]
+
+
+def csr_rows(pack, rows, tol: float | None = None) -> CSRRows:
+    """Selected rows of the CSR of a Pauli pack (same entries as csr_build)."""
+    x = np.ascontiguousarray(pack.xmask, dtype=np.uint64)
+    z = np.ascontiguousarray(pack.zmask, dtype=np.uint64)
+    c = _c128(pack.coeff)
+    if tol is None:
+        tol = default_tol(c)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    rowptr = np.zeros(r.size + 1, dtype=np.int64)
+    cd = c.view(np.float64)
+    nnz = lib().orc_csr_rows(pack.n_qubits, x.size, x, z, cd, tol, r, r.size, rowptr, None, None)
+    if nnz < 0:
+        raise ValueError("oracle csr_rows: bad arguments")
+    col = np.zeros(max(nnz, 1), dtype=np.int32)
+    val = np.zeros(max(nnz, 1), dtype=np.complex128)
+    lib().orc_csr_rows(pack.n_qubits, x.size, x, z, cd, tol, r, r.size, rowptr,
+                       col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p))
+    return CSRRows(pack.n_qubits, r, rowptr, col[:nnz], val[:nnz])
+
+
+def spmv_rows(m: CSRRows, x) -> np.ndarray:
+    """(M x)_{rows[j]} for every selected row j (orc_spmv over the row subset)."""
+    x = _c128(x)
+    y = np.zeros(m.rows.size, dtype=np.complex128)
+    col = m.col if m.col.size else np.zeros(1, dtype=np.int32)
+    val = np.ascontiguousarray(m.val if m.val.size else np.zeros(1, dtype=np.complex128))
+    lib().orc_spmv(m.rows.size, m.rowptr, np.ascontiguousarray(col), val.view(np.float64),
+                   x.view(np.float64), y.view(np.float64))
+    return y
 
 
 def _colv(m: CSR):

@@ -230,10 +230,16 @@ struct vqe_batch {
     int2 *d_ls_tasks = nullptr;
     unsigned n_ls_tasks = 0;
     // per slot, the plan-owned forms of H its schedule reads: 16-bit column
-    // codes (VQE_SPMV_X16), real parts of the values (VQE_SPMV_REAL) and the
-    // padded layout's row pointers; capacities in bytes
+    // codes (VQE_SPMV_X16), the values in the padded layout (real parts with
+    // VQE_SPMV_REAL, complex with VQE_SPMV_PAD) and its row pointers;
+    // capacities in bytes
     std::vector<void *> col16, vre, prow;
     std::vector<int64_t> col16_cap, vre_cap, prow_cap;
+    // per slot, the blocked layout of a column-tiled H (VQE_SPMV_BLOCKED):
+    // one allocation holding slab row pointers, slab lengths and starts,
+    // codes and values; capacity in bytes
+    std::vector<void *> blk;
+    std::vector<int64_t> blk_cap;
     // re-optimisation (vqe_batch_reoptimize): descriptors, three product
     // descriptor arrays, tasks, then per slot nine vectors and partials
     char *ro_mem = nullptr;
@@ -297,22 +303,27 @@ int grow(vqe_batch *p, void **buf, int64_t *cap, int64_t need, const char *what,
 }
 
 // (Re)build slot s's plan-owned forms of H for its schedule -- the 16-bit
-// column codes, and with VQE_SPMV_REAL the real parts of the values, in the
-// padded layout unless the slot is column-tiled -- and point the slot's host
-// descriptor at them (the caller uploads the descriptor).
+// column codes, and with VQE_SPMV_REAL the real parts of the values, with
+// VQE_SPMV_PAD the complex values, in the padded layout unless the slot is
+// column-tiled -- and point the slot's host descriptor at them (the caller
+// uploads the descriptor).
 int codes_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
 {
     vqe_ctx *ctx = p->ctx;
     SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
     const int64_t rb = (int64_t)vqe_elem_bytes(H->dtype) / 2;
     int rc;
-    if ((sched & VQE_SPMV_REAL) && !(sched & VQE_SPMV_TILED)) {
+    if ((sched & (VQE_SPMV_REAL | VQE_SPMV_PAD)) && !(sched & VQE_SPMV_TILED)) {
+        // the padded layout: real parts (VQE_SPMV_REAL) or complex values
+        const bool real = (sched & VQE_SPMV_REAL) != 0;
+        const int64_t vb = real ? rb : 2 * rb;
         const int64_t cap = H->nnz + (SPMV_PAD - 1) * H->dim + SPMV_PAD;
         if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], cap * 2, "column codes", s)) ||
-            (rc = grow(p, &p->vre[s], &p->vre_cap[s], cap * rb, "real values", s)) ||
+            (rc = grow(p, &p->vre[s], &p->vre_cap[s], cap * vb, "padded values", s)) ||
             (rc = grow(p, &p->prow[s], &p->prow_cap[s], (H->dim + 1) * 4, "row pointers", s)))
             return rc;
-        launch_pad_layout(H, (int32_t *)p->prow[s], (uint16_t *)p->col16[s], p->vre[s], ctx->stream);
+        launch_pad_layout(H, (int32_t *)p->prow[s], (uint16_t *)p->col16[s], p->vre[s], real,
+                          ctx->stream);
         st.col16 = (const uint16_t *)p->col16[s];
         st.vre = p->vre[s];
         st.prow = (const int32_t *)p->prow[s];
@@ -333,6 +344,40 @@ int codes_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     return VQE_OK;
 }
 
+// (Re)build slot s's blocked layout of H (VQE_SPMV_BLOCKED) in its plan-owned
+// allocation and point the slot's host descriptor at it (the caller uploads
+// the descriptor).  The layout is built on the context stream from the CSR,
+// which must stay valid while it runs.
+int blocked_fill(vqe_batch *p, int s, const vqe_csr *H)
+{
+    SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
+    const int32_t R = SPMV_BLK_ROWS, tc = spmv_blk_tile_cols(H->dtype);
+    const int32_t nt = (int32_t)((H->dim + tc - 1) / tc);
+    const int64_t nb = (H->dim + R - 1) / R, nslab = nb * nt;
+    const int64_t cap = H->nnz + 4 * nslab + 4;     // entries, with the slabs' alignment
+    const size_t o_rp = 0, o_len = o_rp + vqe_align((size_t)nslab * (R + 1) * sizeof(int32_t));
+    const size_t o_off = o_len + vqe_align((size_t)nslab * sizeof(int64_t));
+    const size_t o_code = o_off + vqe_align((size_t)(nslab + 1) * sizeof(int64_t));
+    const size_t o_val = o_code + vqe_align((size_t)cap * sizeof(uint16_t));
+    const size_t bytes = o_val + vqe_align((size_t)cap * vqe_elem_bytes(H->dtype));
+    int rc = grow(p, &p->blk[s], &p->blk_cap[s], (int64_t)bytes, "blocked layout", s);
+    if (rc)
+        return rc;
+    char *m = (char *)p->blk[s];
+    launch_blk_layout(H, nt, tc, R, (int32_t *)(m + o_rp), (int64_t *)(m + o_len),
+                      (int64_t *)(m + o_off), (uint16_t *)(m + o_code), m + o_val, p->ctx->stream);
+    VQE_LAUNCH_CHECK(p->ctx);
+    st.brp = (const int32_t *)(m + o_rp);
+    st.boff = (const int64_t *)(m + o_off);
+    st.bcode = (const uint16_t *)(m + o_code);
+    st.bval = m + o_val;
+    st.blk_rows = R;
+    st.tile_cols = tc;
+    st.ntiles = nt;
+    st.nblocks = (int32_t)nb;
+    return VQE_OK;
+}
+
 // The step is two launch sequences: the H products (sequence A) and the rest
 // (sequence B: screen, per-state finalisation and selection, Taylor update,
 // renormalisation).  `ev` (nullable) receives the phase events.
@@ -340,7 +385,9 @@ void launch_products(vqe_batch *p, const SpmvState *states)
 {
     SpmvState dummy{};
     for (auto &l : p->spmv) {
-        if (l.lanes & VQE_SPMV_TILED)
+        if (l.lanes & VQE_SPMV_BLOCKED)
+            launch_spmv_blk(p->dtype, l.lanes, states, l.tasks, l.grid, p->ctx->stream);
+        else if (l.lanes & VQE_SPMV_TILED)
             launch_spmv_tiled(p->dtype, l.lanes, states, l.tasks, l.grid, l.sum_tasks, l.sum_grid,
                               p->ctx->stream);
         else
@@ -590,7 +637,10 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         const int req = items[s].spmv_schedule ? items[s].spmv_schedule : vqe_default_schedule(H);
         lanes[s] = vqe_batch_schedule(H, req);
         int64_t nblk = spmv_blocks(H->dim, lanes[s]);
-        if (lanes[s] & VQE_SPMV_TILED) {
+        if (lanes[s] & VQE_SPMV_BLOCKED) {
+            // the layout lives in the slot's own allocation (blocked_fill)
+            nblk = (H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS;
+        } else if (lanes[s] & VQE_SPMV_TILED) {
             // real-value tiles are twice as wide (real parts in storage precision)
             tcols[s] = (lanes[s] & VQE_SPMV_REAL) ? spmv_tile_cols_real(dtype) : spmv_tile_cols(dtype);
             ntiles[s] = (int)((H->dim + tcols[s] - 1) / tcols[s]);
@@ -613,6 +663,12 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         if (per.empty())
             per.resize(kXcd);
         const int64_t dim = items[s].H->dim;
+        if (lanes[s] & VQE_SPMV_BLOCKED) {
+            const int nb = (int)((dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS);
+            for (int b = 0; b < nb; b++)
+                per[xcd_of[s]].push_back(make_int2(s, b));
+            continue;
+        }
         if (lanes[s] & VQE_SPMV_TILED) {
             const int nb = (int)((dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS);
             for (int b = 0; b < nb; b++)
@@ -641,7 +697,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         spmv_tab.push_back({kv.first, A.take(flat.size() * sizeof(int2))});
         spmv_lists.push_back(std::move(flat));
         std::vector<int2> sflat;
-        if (kv.first & VQE_SPMV_TILED)
+        if ((kv.first & VQE_SPMV_TILED) && !(kv.first & VQE_SPMV_BLOCKED))
             sflat = interleave(per_sum[kv.first], make_int2(-1, 0));
         sum_tab.push_back(A.take(sflat.size() * sizeof(int2) + 8));
         sum_lists.push_back(std::move(sflat));
@@ -924,7 +980,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         st.shift = it.H->diag_shift;
         st.nblocks = (int32_t)spmv_blocks(it.H->dim, lanes[s]);
         st.lanes = lanes[s];
-        if (lanes[s] & VQE_SPMV_TILED) {
+        if (lanes[s] & VQE_SPMV_BLOCKED) {
+            st.nblocks = (int32_t)((it.H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS);
+        } else if (lanes[s] & VQE_SPMV_TILED) {
             st.tptr = (const int32_t *)(D + o_tptr[s]);
             st.tile_part = (double *)(D + o_tpart[s]);
             st.ntiles = ntiles[s];
@@ -1038,12 +1096,15 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         v->assign(B, nullptr);
     for (auto *v : {&p->col16_cap, &p->vre_cap, &p->prow_cap})
         v->assign(B, 0);
+    p->blk.assign(B, nullptr);
+    p->blk_cap.assign(B, 0);
     bool any16 = false;
     for (int s = 0; s < B; s++) {
-        if (!(lanes[s] & VQE_SPMV_X16))
+        if (!(lanes[s] & (VQE_SPMV_X16 | VQE_SPMV_BLOCKED)))
             continue;
         any16 = true;
-        const int rc16 = codes_fill(p, s, items[s].H, lanes[s]);
+        const int rc16 = (lanes[s] & VQE_SPMV_BLOCKED) ? blocked_fill(p, s, items[s].H)
+                                                       : codes_fill(p, s, items[s].H, lanes[s]);
         if (rc16) {
             vqe_batch_destroy(p);
             return rc16;
@@ -1113,7 +1174,11 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
     ss->shift = it->H->diag_shift;
     TaylorState *ts = reinterpret_cast<TaylorState *>(p->image.data() + p->o_tay) + slot;
     ts->psi = it->psi;
-    if (sched & VQE_SPMV_X16) {
+    if (sched & VQE_SPMV_BLOCKED) {
+        rc = blocked_fill(p, slot, it->H);
+        if (rc)
+            return rc;
+    } else if (sched & VQE_SPMV_X16) {
         rc = codes_fill(p, slot, it->H, sched);
         if (rc)
             return rc;
@@ -1208,7 +1273,7 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
         (void)hipFree(p->ls_mem);
     if (p->ro_mem)
         (void)hipFree(p->ro_mem);
-    for (const auto *v : {&p->col16, &p->vre, &p->prow})
+    for (const auto *v : {&p->col16, &p->vre, &p->prow, &p->blk})
         for (void *m : *v)
             if (m)
                 (void)hipFree(m);
@@ -1223,7 +1288,7 @@ extern "C" int64_t vqe_batch_workspace_bytes(const vqe_batch *p)
     if (!p)
         return -1;
     int64_t c16 = 0;
-    for (const auto *v : {&p->col16_cap, &p->vre_cap, &p->prow_cap})
+    for (const auto *v : {&p->col16_cap, &p->vre_cap, &p->prow_cap, &p->blk_cap})
         for (int64_t c : *v)
             c16 += c;
     return (int64_t)(p->dmem_bytes + p->table_bytes + p->ls_bytes + p->ro_bytes) + c16;

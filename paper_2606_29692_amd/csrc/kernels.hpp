@@ -103,7 +103,7 @@ struct ScreenState {
 // where D deposits the bits of e into the free bit positions, base holds the
 // tile's fixed bits, and P sets every pivot bit piv_i to k_i ^ |beta_i & r|.
 #define MF_LANE_BITS 8     // screen: 64 lanes x 4 elements cover the lowest free bits
-#define MF_MAX_TB 4
+#define MF_MAX_TB 8         // screen row tiles: at most 2^8 (states of up to 21 qubits in FP32 storage)
 struct MfRec {
     uint32_t x, zsign;      // flip mask, sign mask: A[r ^ x, r] = v (-1)^{|zsign & r|}
     uint32_t cx;            // x with the tile bits removed (LDS index offset)
@@ -272,6 +272,17 @@ void launch_spmv(int dtype, int lanes, const SpmvState &single, const SpmvState 
 void launch_spmv_tiled(int dtype, int sched, const SpmvState *states, const int2 *tasks,
                        unsigned grid, const int2 *sum_tasks, unsigned sum_grid, hipStream_t s);
 void launch_tile_bounds(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s);
+// blocked layout of a column-tiled state (VQE_SPMV_BLOCKED): tile width and
+// LDS bytes of the product's workgroups; the product itself (tasks {state,
+// row block}); and the layout's build from the CSR (slab row pointers brp
+// [nb * nt * (R + 1)], scratch blen [nb * nt], slab starts boff [nb * nt + 1],
+// codes and values with room for nnz + 4 nb nt + 4 entries)
+int32_t spmv_blk_tile_cols(int dtype);
+size_t spmv_blk_lds(int dtype);
+void launch_spmv_blk(int dtype, int sched, const SpmvState *states, const int2 *tasks,
+                     unsigned grid, hipStream_t s);
+void launch_blk_layout(const vqe_csr *H, int32_t nt, int32_t tc, int32_t R, int32_t *brp,
+                       int64_t *blen, int64_t *boff, uint16_t *bcode, void *bval, hipStream_t s);
 int32_t spmv_tile_cols(int dtype);
 // tile width of the column-tiled form with real values (VQE_SPMV_REAL): twice
 // as many columns, since a real tile holds storage-precision real parts
@@ -282,9 +293,11 @@ void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s);
 // out[k] = Re val[k] (FP32 or FP64 by H's dtype) for every entry of H
 void launch_val_real(const vqe_csr *H, void *out, hipStream_t s);
 // padded layout of H (dim <= SPMV_X16_MAX_DIM): prow[dim + 1], the 16-bit
-// codes and the real parts of the values with every row rounded up to a
-// multiple of SPMV_PAD entries (room for nnz + (SPMV_PAD - 1) dim entries)
-void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vre, hipStream_t s);
+// codes and the values -- their real parts (real) or the complex values --
+// with every row rounded up to a multiple of SPMV_PAD entries (room for
+// nnz + (SPMV_PAD - 1) dim entries)
+void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vpad, bool real,
+                       hipStream_t s);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 
 void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, unsigned grid,

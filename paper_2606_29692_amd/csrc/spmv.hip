@@ -11,6 +11,8 @@
 // on the same XCD (workgroup IDs are dealt round-robin over the 8 XCDs).
 #include "kernels.hpp"
 
+#include <algorithm>
+
 // The LDS schedules hold the state in LDS, so one 16-wave workgroup fills a
 // CU (4 waves per SIMD): the register allocator may use the whole budget.
 #define VQE_LDS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 4)))
@@ -618,16 +620,17 @@ k_pad_rowptr(const int32_t *__restrict__ rowptr, int32_t *__restrict__ prow, int
         prow[dim] = (int32_t)s_sum[1023];
 }
 
-// Column codes and real values in the padded layout, one wave per row; a
-// row's pad entries repeat its last column with the value zero.
-template <int DT>
+// Column codes and values in the padded layout, one wave per row: the real
+// parts (RVAL) or the complex values themselves; a row's pad entries repeat
+// its last column with the value zero.
+template <int DT, bool RVAL>
 __global__ void __launch_bounds__(256)
 k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
            const void *__restrict__ val, const int32_t *__restrict__ prow,
-           uint16_t *__restrict__ code, void *__restrict__ vre, int64_t dim)
+           uint16_t *__restrict__ code, void *__restrict__ vpad, int64_t dim)
 {
     using T = typename Elem<DT>::T;
-    using R = typename ValOf<DT, true>::T;
+    using R = typename ValOf<DT, RVAL>::T;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= dim)
         return;
@@ -636,8 +639,14 @@ k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     for (int32_t j = (int32_t)(threadIdx.x & 63); j < plen; j += 64) {
         const int32_t k = k0 + (j < len ? j : len - 1);
         code[p0 + j] = (uint16_t)((uint32_t)col[k] ^ (uint32_t)r);
-        reinterpret_cast<R *>(vre)[p0 + j] =
-            j < len ? (R)ldg(reinterpret_cast<const T *>(val), k).x : (R)0;
+        R v{};
+        if (j < len) {
+            if constexpr (RVAL)
+                v = (R)ldg(reinterpret_cast<const T *>(val), k).x;
+            else
+                v = ldg(reinterpret_cast<const T *>(val), k);
+        }
+        reinterpret_cast<R *>(vpad)[p0 + j] = v;
     }
 }
 
@@ -655,28 +664,29 @@ k_pad_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
 // entries of the arrays are added entry by entry.  With X16 the column of
 // entry k of row r is read as the 16-bit code col16[k] = col[k] ^ r (8 bytes
 // per group of four instead of 16), for states of at most 2^16 rows.  With
-// RV (operators whose entries are all real) the codes and values are the
-// plan's padded layout: each row starts at a multiple of eight and is padded
-// with zero values to whole groups (row pointers st.prow), so no entry needs
-// a row mask and there is no tail, and a lane takes eight entries with one
-// 16-byte code load; the values are the real parts, 4 instead of 8 bytes per
-// entry in FP32 storage, and a workgroup whose staged state has no imaginary
-// part multiplies in real arithmetic (RX).  The kernel, k_spmv_lds_pf, stages
+// PL the codes and values are the plan's padded layout: each row starts at a
+// multiple of eight and is padded with zero values to whole groups (row
+// pointers st.prow), so no entry needs a row mask and there is no tail, and a
+// lane takes eight entries with one 16-byte code load.  With RV (operators
+// whose entries are all real; always in the padded layout) the values are the
+// real parts, 4 instead of 8 bytes per entry in FP32 storage, and a workgroup
+// whose staged state has no imaginary part multiplies in real arithmetic (RX).  The kernel, k_spmv_lds_pf, stages
 // and then runs pf_rows.
 
 // The rows [r0, r1) of one workgroup of the pipelined LDS schedule, the state
 // already staged in LDS at smem (complex, or with RX its real parts in FP64)
 // and the row pointers at s_rp; writes sigma and the workgroup's energy
 // partials.
-template <int DT, int L, int D, bool X16, bool RV, bool RX>
+template <int DT, int L, int D, bool X16, bool RV, bool RX, bool PL>
 __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsigned char *smem,
                                         const int32_t *s_rp, int64_t r0, int64_t r1)
 {
+    static_assert(!RV || PL, "real values come in the padded layout");
     using T = typename Elem<DT>::T;
     using X = typename std::conditional<RX, double, T>::type;
     // a lane's group: 4 entries, or 8 in the padded layout (one 16-byte code
     // load and 16-byte value loads)
-    constexpr int GE = RV ? SPMV_PAD : 4;
+    constexpr int GE = PL ? SPMV_PAD : 4;
     constexpr int U = 256 / (L * GE) > 0 ? 256 / (L * GE) : 1;
     constexpr int W = U * GE;                // entries per lane per pass
     constexpr int PASS = W * L;              // entries per sub-group per pass
@@ -688,14 +698,14 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
     constexpr int G = VQE_WAVE / L;
     const int lane = tid & 63, wid = tid >> 6;
     const int sub = lane / L, sl = lane % L;
-    // the padded layout (RV) holds whole groups only, up to st.cap entries
-    const int nnz = (int)(RV ? st.cap : st.nnz), zc = (int)dim;
-    const int whole = RV ? 0x7fffffff : nnz & ~3;   // groups starting below this are whole
+    // the padded layout (PL) holds whole groups only, up to st.cap entries
+    const int nnz = (int)(PL ? st.cap : st.nnz), zc = (int)dim;
+    const int whole = PL ? 0x7fffffff : nnz & ~3;   // groups starting below this are whole
     const __amdgpu_buffer_rsrc_t rc =
         X16 ? __builtin_amdgcn_make_buffer_rsrc((void *)st.col16, (short)0, nnz * 2, VQE_BUF_WORD3)
             : __builtin_amdgcn_make_buffer_rsrc((void *)st.col, (short)0, nnz * 4, VQE_BUF_WORD3);
     const __amdgpu_buffer_rsrc_t rv =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(RV ? st.vre : st.val), (short)0, (int)(nnz * EB),
+        __builtin_amdgcn_make_buffer_rsrc((void *)(PL ? st.vre : st.val), (short)0, (int)(nnz * EB),
                                           VQE_BUF_WORD3);
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
 
@@ -747,7 +757,7 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
             for (int q = 0; q < GE; q++) {
                 const int k = kb + u * GE * L + q;
                 const int col = X16 ? (rx ^ c[GE * u + q]) : c[GE * u + q];
-                cm[GE * u + q] = RV || (unsigned)(k - k0) < len ? col : zc;
+                cm[GE * u + q] = PL || (unsigned)(k - k0) < len ? col : zc;
             }
         lds_gather_fma<X, V, W>(s_x, cm, v, are, aim);
     };
@@ -771,7 +781,7 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
         if (k1 > whole) {
             const int k = (k0 > whole ? k0 : whole) + sl;
             if (k < k1) {
-                const V a = ldv(reinterpret_cast<const V *>(RV ? st.vre : st.val), k);
+                const V a = ldv(reinterpret_cast<const V *>(PL ? st.vre : st.val), k);
                 const int col = X16 ? ((int)r ^ (int)gmem(st.col16)[k]) : gmem(st.col)[k];
                 entry_fma(a, s_x[col], are, aim);
             }
@@ -833,7 +843,7 @@ __device__ __forceinline__ void pf_rows(const SpmvState &st, int blk, const unsi
 
 // The pipelined LDS schedule's kernel (described above pf_rows): one
 // workgroup per (state, block of rows).
-template <int DT, int L, int D, bool BATCH, bool X16, bool RV>
+template <int DT, int L, int D, bool BATCH, bool X16, bool RV, bool PL>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
               const int2 *__restrict__ tasks)
@@ -861,7 +871,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
     const int64_t r1 = r0 + SPMV_LDS_ROWS < dim ? r0 + SPMV_LDS_ROWS : dim;
     int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)(dim + 1) * sizeof(T));
-    stage_lds<4>(s_rp, (RV ? st.prow : st.rowptr) + r0, r1 - r0 + 1, tid);
+    stage_lds<4>(s_rp, (PL ? st.prow : st.rowptr) + r0, r1 - r0 + 1, tid);
     if constexpr (RV) {
         // a real state (every imaginary part zero) runs in real arithmetic
         double *s_xr = reinterpret_cast<double *>(smem);
@@ -869,7 +879,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
         if (tid == 0)
             s_xr[dim] = 0.0;
         if (!__syncthreads_or(cplx)) {
-            pf_rows<DT, L, D, X16, RV, true>(st, blk, smem, s_rp, r0, r1);
+            pf_rows<DT, L, D, X16, RV, true, PL>(st, blk, smem, s_rp, r0, r1);
             return;
         }
     }
@@ -877,7 +887,7 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
     if (tid == 0)
         s_x[dim] = T{};
     __syncthreads();
-    pf_rows<DT, L, D, X16, RV, false>(st, blk, smem, s_rp, r0, r1);
+    pf_rows<DT, L, D, X16, RV, false, PL>(st, blk, smem, s_rp, r0, r1);
 }
 
 
@@ -1133,6 +1143,323 @@ k_spmv_tile_sum(const SpmvState *__restrict__ states, const int2 *__restrict__ t
     }
 }
 
+// ------------------------------------------------------------------ blocked layout
+// The column-tiled product of states larger than LDS, blocked: the plan lays
+// H out per (row block, column tile) slab (the entries of the block's rows
+// whose columns fall in the tile, rows in order, each slab starting at a
+// multiple of four entries), with 16-bit tile-local column codes (any state
+// size, since a tile holds fewer than 2^16 columns) and the values (complex,
+// interleaved).  One workgroup owns a row block and walks every tile in
+// ascending order: it stages the tile of the state and the slab's row
+// pointers in LDS, streams the slab with the pipelined row loop, and adds each
+// row's sum to the row's FP64 accumulator in LDS; after the last tile it
+// writes sigma and the energy partials.  Each slab is one contiguous stream,
+// so no line is shared between two workgroups' reads, and no per-tile partial
+// sums go through device memory.
+
+// first k in [lo, hi) with col[k] >= lim (columns ascend within a row)
+__device__ __forceinline__ int first_col_at_least(const int32_t *col, int lo, int hi, int64_t lim)
+{
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)col[mid] < lim)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Step 1: the number of entries of row r in tile t, stored in the slab's
+// row-pointer slot i + 1 (i = r - block * R); one thread per (row, tile),
+// tiles fastest.  The slots start zeroed.
+__global__ void __launch_bounds__(256)
+k_blk_count(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int64_t dim,
+            int32_t nt, int32_t tc, int32_t R, int32_t *__restrict__ brp)
+{
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= dim * nt)
+        return;
+    const int64_t r = gid / nt;
+    const int t = (int)(gid - r * nt);
+    const int k0 = rowptr[r], k1 = rowptr[r + 1];
+    const int lo = first_col_at_least(col, k0, k1, (int64_t)t * tc);
+    const int hi = first_col_at_least(col, lo, k1, (int64_t)(t + 1) * tc);
+    const int64_t b = r / R, i = r - b * R;
+    brp[(b * nt + t) * (R + 1) + i + 1] = hi - lo;
+}
+
+// Step 2: per slab (one 256-thread workgroup), the row lengths in slots
+// 1..R become the rows' starts (inclusive prefix sums: slot i = start of row
+// i, slot R = the slab's length); the slab's length rounded up to four entries
+// goes to blen.
+__global__ void __launch_bounds__(256)
+k_blk_scan(int32_t *__restrict__ brp, int32_t R, int64_t *__restrict__ blen)
+{
+    __shared__ int32_t s_tot[256];
+    const int tid = threadIdx.x;
+    int32_t *p = brp + (int64_t)blockIdx.x * (R + 1);
+    const int per = (R + 255) / 256;
+    const int a = 1 + tid * per;
+    const int e = a + per < R + 1 ? a + per : R + 1;
+    int32_t sum = 0;
+    for (int i = a; i < e; i++)
+        sum += p[i];
+    s_tot[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t v = tid >= off ? s_tot[tid - off] : 0;
+        __syncthreads();
+        s_tot[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = s_tot[tid] - sum;
+    for (int i = a; i < e; i++) {
+        run += p[i];
+        p[i] = run;
+    }
+    if (tid == 0)
+        p[0] = 0;
+    if (tid == 255)
+        blen[blockIdx.x] = ((int64_t)s_tot[255] + 3) & ~(int64_t)3;
+}
+
+// Step 3: slab starts, the exclusive prefix sums of the rounded lengths
+// (boff[n] = the total); one workgroup, each thread a contiguous run.
+__global__ void __launch_bounds__(1024)
+k_blk_offsets(const int64_t *__restrict__ blen, int64_t n, int64_t *__restrict__ boff)
+{
+    __shared__ int64_t s_sum[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t a = (int64_t)tid * per < n ? (int64_t)tid * per : n;
+    const int64_t e = a + per < n ? a + per : n;
+    int64_t tot = 0;
+    for (int64_t i = a; i < e; i++)
+        tot += blen[i];
+    s_sum[tid] = tot;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = tid >= off ? s_sum[tid - off] : 0;
+        __syncthreads();
+        s_sum[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = s_sum[tid] - tot;
+    for (int64_t i = a; i < e; i++) {
+        boff[i] = run;
+        run += blen[i];
+    }
+    if (tid == 1023)
+        boff[n] = s_sum[1023];
+}
+
+// Step 4: copy row r's entries of tile t into its slab (codes col - t * tc),
+// one thread per (row, tile); the entries between one slab's end and the next
+// slab's start are set to zero by the thread of the block's last row.
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_blk_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+           const void *__restrict__ val, int64_t dim, int32_t nt, int32_t tc, int32_t R,
+           const int32_t *__restrict__ brp, const int64_t *__restrict__ boff,
+           uint16_t *__restrict__ bcode, void *__restrict__ bval)
+{
+    using T = typename Elem<DT>::T;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= dim * nt)
+        return;
+    const int64_t r = gid / nt;
+    const int t = (int)(gid - r * nt);
+    const int k0 = rowptr[r], k1 = rowptr[r + 1];
+    const int lo = first_col_at_least(col, k0, k1, (int64_t)t * tc);
+    const int hi = first_col_at_least(col, lo, k1, (int64_t)(t + 1) * tc);
+    const int64_t b = r / R, i = r - b * R;
+    const int64_t slab = b * nt + t;
+    const int32_t *rp = brp + slab * (R + 1);
+    const int64_t dst = boff[slab] + rp[i];
+    const T *v = reinterpret_cast<const T *>(val);
+    T *bv = reinterpret_cast<T *>(bval);
+    for (int k = lo; k < hi; k++) {
+        bcode[dst + (k - lo)] = (uint16_t)(col[k] - t * tc);
+        bv[dst + (k - lo)] = v[k];
+    }
+    const int64_t rows = dim - b * R < R ? dim - b * R : R;
+    if (i == rows - 1)
+        for (int64_t k = boff[slab] + rp[rows]; k < boff[slab + 1]; k++) {
+            bcode[k] = 0;
+            bv[k] = T{};
+        }
+}
+
+// The rows of one slab of a blocked state (tile of the state at s_x, its
+// zero element at index w; the slab's row pointers at s_rp): the pipelined row
+// loop of the LDS schedule with L lanes per row, U groups of four entries per
+// lane per pass and D rows in flight per sub-group; each row's sum is added to
+// its FP64 accumulator in LDS.
+template <int DT, int L, int D, int U>
+__device__ __forceinline__ void blk_rows(const SpmvState &st, int64_t slab, int w,
+                                         const typename Elem<DT>::T *s_x, const int32_t *s_rp,
+                                         double2 *s_acc, int nrows)
+{
+    using T = typename Elem<DT>::T;
+    constexpr int W = U * 4;                 // entries per lane per pass
+    constexpr int PASS = W * L;              // entries per sub-group per pass
+    constexpr unsigned EB = sizeof(T);
+    constexpr int G = VQE_WAVE / L;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int sub = lane / L, sl = lane % L;
+    const int64_t base = st.boff[slab];
+    const int nrec = (s_rp[nrows] + 3) & ~3;   // the slab's entries, whole groups
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(st.bcode + base), (short)0, nrec * 2, VQE_BUF_WORD3);
+    const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(reinterpret_cast<const T *>(st.bval) + base), (short)0, (int)(nrec * EB),
+        VQE_BUF_WORD3);
+
+    auto issue = [&](int kb, int k1, int c[W], T v[W]) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int k = kb + u * 4 * L;
+            const bool ok = k < k1;
+            typedef unsigned v2u __attribute__((ext_vector_type(2)));
+            const v2u c2 = __builtin_amdgcn_raw_buffer_load_b64(rc, ok ? (unsigned)k * 2u : VQE_BUF_OOB, 0, 0);
+            c[4 * u + 0] = (int)(c2.x & 0xffffu);
+            c[4 * u + 1] = (int)(c2.x >> 16);
+            c[4 * u + 2] = (int)(c2.y & 0xffffu);
+            c[4 * u + 3] = (int)(c2.y >> 16);
+            BufVal<DT, false>::load(rv, ok ? (unsigned)k * EB : VQE_BUF_OOB, v + 4 * u);
+        }
+    };
+    // entries outside the row [k0, k1) read the zero element
+    auto consume = [&](int kb, int k0, int k1, const int c[W], const T v[W], double &are,
+                       double &aim) {
+        int cm[W];
+        const unsigned len = (unsigned)(k1 - k0);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int k = kb + u * 4 * L + q;
+                cm[4 * u + q] = (unsigned)(k - k0) < len ? c[4 * u + q] : w;
+            }
+        lds_gather_fma<T, T, W>(s_x, cm, v, are, aim);
+    };
+    auto row_bounds = [&](int i, int &k0, int &k1) {
+        if (i < nrows) {
+            k0 = s_rp[i];
+            k1 = s_rp[i + 1];
+        } else {
+            k0 = k1 = 0;
+        }
+    };
+    auto finish = [&](int i, int k0, int k1, double are, double aim) {
+        for (int kb = (k0 & ~3) + 4 * sl + PASS; kb - 4 * sl < k1; kb += PASS) {
+            int c[W];
+            T v[W];
+            issue(kb, k1, c, v);
+            consume(kb, k0, k1, c, v, are, aim);
+        }
+        are = group_sum<L>(are);
+        aim = group_sum<L>(aim);
+        if (sl == 0 && i < nrows) {
+            const double2 a = s_acc[i];
+            s_acc[i] = make_double2(a.x + are, a.y + aim);
+        }
+    };
+
+    int cb[D][W];
+    T vb[D][W];
+    int kb0[D], kb1[D], rr[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        rr[d] = (wid + 16 * d) * G + sub;
+        row_bounds(rr[d], kb0[d], kb1[d]);
+        issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    for (int row = wid * G; row < nrows; row += 16 * D * G) {
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            {
+                double are = 0.0, aim = 0.0;
+                consume((kb0[d] & ~3) + 4 * sl, kb0[d], kb1[d], cb[d], vb[d], are, aim);
+                finish(rr[d], kb0[d], kb1[d], are, aim);
+            }
+            rr[d] += 16 * D * G;
+            row_bounds(rr[d], kb0[d], kb1[d]);
+            issue((kb0[d] & ~3) + 4 * sl, kb1[d], cb[d], vb[d]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The blocked product's kernel: one workgroup per (state, row block).
+template <int DT, int L, int D, int U>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
+k_spmv_blk(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const SpmvState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    using T = typename Elem<DT>::T;
+    extern __shared__ unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int64_t dim = st.dim;
+    const int R = st.blk_rows, tc = st.tile_cols, nt = st.ntiles;
+    const int b = task.y;
+    const int64_t r0 = (int64_t)b * R;
+    const int nrows = (int)(dim - r0 < R ? dim - r0 : R);
+    // LDS: the rows' accumulators, the tile (and its zero element), the
+    // slab's row pointers
+    double2 *s_acc = reinterpret_cast<double2 *>(smem);
+    T *s_x = reinterpret_cast<T *>(smem + (size_t)R * sizeof(double2));
+    int32_t *s_rp = reinterpret_cast<int32_t *>(smem + (size_t)R * sizeof(double2) +
+                                                (size_t)(tc + 1) * sizeof(T));
+    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    for (int i = tid; i < nrows; i += 1024)
+        s_acc[i] = make_double2(0.0, 0.0);
+    for (int t = 0; t < nt; t++) {
+        const int64_t c_lo = (int64_t)t * tc;
+        const int w = (int)(dim - c_lo < tc ? dim - c_lo : tc);
+        const int64_t slab = (int64_t)b * nt + t;
+        __syncthreads();      // every wave is done with the previous tile
+        stage_lds<2>(s_rp, st.brp + slab * (R + 1), nrows + 1, tid);
+        stage_lds<8>(s_x, psi + c_lo, w, tid);
+        if (tid == 0)
+            s_x[w] = T{};
+        __syncthreads();
+        blk_rows<DT, L, D, U>(st, slab, w, s_x, s_rp, s_acc, nrows);
+    }
+    __syncthreads();
+    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
+    for (int i = tid; i < nrows; i += 1024) {
+        const double2 a = s_acc[i];
+        Elem<DT>::st(st.sigma, r0 + i, a);
+        energy_terms(ldg(psi, r0 + i), a.x, a.y, e_re, e_im, e_n2);
+    }
+    __shared__ double s_part[16][3];
+    const int lane = tid & 63, wid = tid >> 6;
+    e_re = wave_sum(e_re);
+    e_im = wave_sum(e_im);
+    e_n2 = wave_sum(e_n2);
+    if (lane == 0) {
+        s_part[wid][0] = e_re;
+        s_part[wid][1] = e_im;
+        s_part[wid][2] = e_n2;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double v = 0.0;
+        for (int q = 0; q < 16; q++)
+            v += s_part[q][tid];
+        gmem(st.partials)[(int64_t)b * 3 + tid] = v;
+    }
+}
+
 // Per-tile row bounds: the first entry of row r with column >= t * tile_cols.
 __global__ void __launch_bounds__(256)
 k_tile_bounds(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
@@ -1219,17 +1546,17 @@ static void launch_spmv_lds_t(const SpmvState &single, const SpmvState *states, 
     }
 }
 
-template <int DT, int L, int D, bool X16 = false, bool RV = false>
+template <int DT, int L, int D, bool X16 = false, bool RV = false, bool PL = RV>
 static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, const int2 *tasks,
                              unsigned grid, hipStream_t s, size_t lds)
 {
     if (tasks) {
-        auto k = k_spmv_lds_pf<DT, L, D, true, X16, RV>;
+        auto k = k_spmv_lds_pf<DT, L, D, true, X16, RV, PL>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
     } else {
-        auto k = k_spmv_lds_pf<DT, L, D, false, false, false>;
+        auto k = k_spmv_lds_pf<DT, L, D, false, false, false, false>;
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         k<<<grid, 1024, lds, s>>>(single, states, tasks);
@@ -1244,9 +1571,15 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
     constexpr int P = VQE_SPMV_LDS | VQE_SPMV_PREFETCH;
     constexpr int X = P | VQE_SPMV_X16;
     constexpr int R = X | VQE_SPMV_REAL;
+    constexpr int Q = X | VQE_SPMV_PAD;
     switch (sched) {
-    // the 16-bit column form and the real values exist only in batch plans
-    // (tasks non-null)
+    // the 16-bit column form, the padded layout and the real values exist
+    // only in batch plans (tasks non-null)
+    case 16 | Q: launch_spmv_pf_t<DT, 16, 2, true, false, true>(single, states, tasks, grid, s, lds); return;
+    case 32 | Q: launch_spmv_pf_t<DT, 32, 2, true, false, true>(single, states, tasks, grid, s, lds); return;
+    case 64 | Q: launch_spmv_pf_t<DT, 64, 2, true, false, true>(single, states, tasks, grid, s, lds); return;
+    case 32 | Q | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 32, 3, true, false, true>(single, states, tasks, grid, s, lds); return;
+    case 64 | Q | VQE_SPMV_DEEP: launch_spmv_pf_t<DT, 64, 3, true, false, true>(single, states, tasks, grid, s, lds); return;
     case 16 | R: launch_spmv_pf_t<DT, 16, 2, true, true>(single, states, tasks, grid, s, lds); return;
     case 32 | R: launch_spmv_pf_t<DT, 32, 2, true, true>(single, states, tasks, grid, s, lds); return;
     case 64 | R: launch_spmv_pf_t<DT, 64, 2, true, true>(single, states, tasks, grid, s, lds); return;
@@ -1282,6 +1615,81 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
     case 32 | VQE_SPMV_VEC4: launch_spmv_t<DT, 32, 4>(single, states, tasks, grid, s); break;
     default: launch_spmv_t<DT, 64, 4>(single, states, tasks, grid, s); break;
     }
+}
+
+int32_t spmv_blk_tile_cols(int dtype) { return (int32_t)(SPMV_BLK_TILE_BYTES / vqe_elem_bytes(dtype)); }
+
+size_t spmv_blk_lds(int dtype)
+{
+    return (size_t)SPMV_BLK_ROWS * 2 * sizeof(double) +
+           (size_t)(spmv_blk_tile_cols(dtype) + 1) * vqe_elem_bytes(dtype) +
+           (size_t)(SPMV_BLK_ROWS + 1) * sizeof(int32_t);
+}
+
+// Blocked schedules: 8 lanes take two groups of four entries per pass (64
+// entries), wider sub-groups one group (64, 128 or 256 entries).
+template <int DT, int L, int D, int U>
+static void launch_blk_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s)
+{
+    const size_t lds = spmv_blk_lds(DT);
+    auto k = k_spmv_blk<DT, L, D, U>;
+    (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k<<<grid, 1024, lds, s>>>(states, tasks);
+}
+
+template <int DT>
+static void launch_blk_dt(int sched, const SpmvState *states, const int2 *tasks, unsigned grid,
+                          hipStream_t s)
+{
+    const bool deep = (sched & VQE_SPMV_DEEP) != 0;
+    switch (sched & 0xff) {
+    case 8: deep ? launch_blk_t<DT, 8, 3, 2>(states, tasks, grid, s)
+                 : launch_blk_t<DT, 8, 2, 2>(states, tasks, grid, s); break;
+    case 16: deep ? launch_blk_t<DT, 16, 3, 1>(states, tasks, grid, s)
+                  : launch_blk_t<DT, 16, 2, 1>(states, tasks, grid, s); break;
+    case 64: deep ? launch_blk_t<DT, 64, 3, 1>(states, tasks, grid, s)
+                  : launch_blk_t<DT, 64, 2, 1>(states, tasks, grid, s); break;
+    default: deep ? launch_blk_t<DT, 32, 3, 1>(states, tasks, grid, s)
+                  : launch_blk_t<DT, 32, 2, 1>(states, tasks, grid, s); break;
+    }
+}
+
+void launch_spmv_blk(int dtype, int sched, const SpmvState *states, const int2 *tasks,
+                     unsigned grid, hipStream_t s)
+{
+    if (dtype == VQE_C128)
+        launch_blk_dt<VQE_C128>(sched, states, tasks, grid, s);
+    else
+        launch_blk_dt<VQE_C64>(sched, states, tasks, grid, s);
+}
+
+namespace {
+__global__ void __launch_bounds__(256) k_zero_i32(int32_t *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+}  // namespace
+
+void launch_blk_layout(const vqe_csr *H, int32_t nt, int32_t tc, int32_t R, int32_t *brp,
+                       int64_t *blen, int64_t *boff, uint16_t *bcode, void *bval, hipStream_t s)
+{
+    const int64_t dim = H->dim;
+    const int64_t nb = (dim + R - 1) / R;
+    const int64_t nslab = nb * nt;
+    const int64_t nrp = nslab * (R + 1);
+    const unsigned zgrid = (unsigned)std::min<int64_t>((nrp + 255) / 256, 65536);
+    k_zero_i32<<<zgrid, 256, 0, s>>>(brp, nrp);
+    const unsigned g = (unsigned)((dim * nt + 255) / 256);
+    k_blk_count<<<g, 256, 0, s>>>(H->rowptr, H->col, dim, nt, tc, R, brp);
+    k_blk_scan<<<(unsigned)nslab, 256, 0, s>>>(brp, R, blen);
+    k_blk_offsets<<<1, 1024, 0, s>>>(blen, nslab, boff);
+    if (H->dtype == VQE_C128)
+        k_blk_fill<VQE_C128><<<g, 256, 0, s>>>(H->rowptr, H->col, H->val, dim, nt, tc, R, brp, boff,
+                                               bcode, bval);
+    else
+        k_blk_fill<VQE_C64><<<g, 256, 0, s>>>(H->rowptr, H->col, H->val, dim, nt, tc, R, brp, boff,
+                                              bcode, bval);
 }
 
 void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState *states,
@@ -1370,6 +1778,11 @@ bool vqe_valid_schedule(int sched)
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
+    case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_PAD:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_PAD:
+    case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_PAD:
+    case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_PAD:
+    case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_PAD:
         return true;
     default:
         return false;
@@ -1393,11 +1806,17 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
     // and runs with 32 or 64 lanes when the state fits LDS
     if ((sched & VQE_SPMV_PREFETCH) &&
         (!(sched & VQE_SPMV_LDS) || H->nnz * (int64_t)vqe_elem_bytes(H->dtype) > 0x7fffff00LL ||
-         (sched & 0xff) < ((sched & VQE_SPMV_REAL) ? 16 : 32)))
-        return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL);
-    // the 16-bit column form needs column XOR row below 2^16
+         (sched & 0xff) < ((sched & (VQE_SPMV_REAL | VQE_SPMV_PAD)) ? 16 : 32)))
+        return sched & ~(VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL |
+                         VQE_SPMV_PAD);
+    // the 16-bit column form needs column XOR row below 2^16; the padded
+    // layout comes with it; the real values imply the padded layout
     if ((sched & VQE_SPMV_X16) && H->dim > SPMV_X16_MAX_DIM)
-        return sched & ~(VQE_SPMV_X16 | VQE_SPMV_REAL);
+        return sched & ~(VQE_SPMV_X16 | VQE_SPMV_REAL | VQE_SPMV_PAD);
+    if (!(sched & VQE_SPMV_X16))
+        sched &= ~VQE_SPMV_PAD;
+    if (sched & VQE_SPMV_REAL)
+        sched &= ~VQE_SPMV_PAD;
     return sched;
 }
 
@@ -1407,10 +1826,16 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
 {
     const bool big = H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES;
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
-    if (big && aligned && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) &&
-        H->nnz * (int64_t)vqe_elem_bytes(H->dtype) <= 0x7fffff00LL && H->dim <= ((int64_t)1 << 30))
-        return (H->dim > SPMV_X16_MAX_DIM ? sched & ~(VQE_SPMV_X16 | VQE_SPMV_REAL)
-                : (H->flags & VQE_REAL) ? sched : sched & ~VQE_SPMV_REAL) | VQE_SPMV_TILED;
+    if (big && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) && H->dim <= ((int64_t)1 << 30)) {
+        // the real-value form keeps the column-tiled CSR (16-bit col ^ row
+        // codes, real parts, per-tile row bounds) where it applies
+        if ((sched & VQE_SPMV_REAL) && (sched & VQE_SPMV_X16) && (H->flags & VQE_REAL) && aligned &&
+            H->dim <= SPMV_X16_MAX_DIM && H->nnz * (int64_t)vqe_elem_bytes(H->dtype) <= 0x7fffff00LL)
+            return (sched & ~VQE_SPMV_PAD) | VQE_SPMV_TILED;
+        // otherwise the blocked layout (complex values, tile-local codes)
+        return (sched & (0xff | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP)) |
+               VQE_SPMV_TILED | VQE_SPMV_BLOCKED;
+    }
     return vqe_effective_schedule(H, sched);
 }
 
@@ -1425,14 +1850,22 @@ void launch_val_real(const vqe_csr *H, void *out, hipStream_t s)
         k_val_real<VQE_C64><<<grid, 256, 0, s>>>(H->val, out, H->nnz);
 }
 
-void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vre, hipStream_t s)
+void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vpad, bool real,
+                       hipStream_t s)
 {
     k_pad_rowptr<<<1, 1024, 0, s>>>(H->rowptr, prow, H->dim);
     const unsigned grid = (unsigned)((H->dim + 3) / 4);
-    if (H->dtype == VQE_C128)
-        k_pad_fill<VQE_C128><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vre, H->dim);
-    else
-        k_pad_fill<VQE_C64><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vre, H->dim);
+    if (H->dtype == VQE_C128) {
+        if (real)
+            k_pad_fill<VQE_C128, true><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vpad, H->dim);
+        else
+            k_pad_fill<VQE_C128, false><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vpad, H->dim);
+    } else {
+        if (real)
+            k_pad_fill<VQE_C64, true><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vpad, H->dim);
+        else
+            k_pad_fill<VQE_C64, false><<<grid, 256, 0, s>>>(H->rowptr, H->col, H->val, prow, code, vpad, H->dim);
+    }
 }
 
 void launch_col_xor16(const vqe_csr *H, uint16_t *col16, hipStream_t s)

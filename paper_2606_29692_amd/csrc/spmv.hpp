@@ -49,15 +49,33 @@ struct SpmvState {
     // the column-tiled form [nnz], with col16 in the CSR's layout; otherwise
     // col16 and vre hold the padded layout (rows rounded up to a multiple of
     // SPMV_PAD entries, zero values in the pads) with row pointers
-    // prow[dim + 1] and room for cap entries
+    // prow[dim + 1] and room for cap entries.  With VQE_SPMV_PAD (complex
+    // values) vre holds the complex values in the same padded layout.
     const void *vre;
     const int32_t *prow;
     int64_t cap;
+    // blocked layout (column-tiled states of schedules without VQE_SPMV_REAL):
+    // per (row block b, column tile t) a slab of the block's entries with
+    // columns in the tile, rows in order, starting at entry boff[b * ntiles + t]
+    // (a multiple of four; the few entries between slabs are zero); row i of
+    // the block is [brp[(b * ntiles + t) * (blk_rows + 1) + i], ... + i + 1)
+    // relative to the slab; codes are the tile-local columns col - t * tile_cols
+    const uint16_t *bcode;
+    const void *bval;
+    const int32_t *brp;
+    const int64_t *boff;
+    int32_t blk_rows;
 };
 
 // Column-tiled H product: tile width (state elements staged in LDS per pass)
 // and rows per workgroup of the tile-sum kernel.
 #define VQE_SPMV_TILED 0x1000
+// Blocked layout of a column-tiled state (with VQE_SPMV_TILED): one
+// workgroup per block of SPMV_BLK_ROWS rows walks every column tile of
+// SPMV_BLK_TILE_BYTES, keeping its rows' FP64 sums in LDS.
+#define VQE_SPMV_BLOCKED 0x20000
+#define SPMV_BLK_ROWS 2048
+#define SPMV_BLK_TILE_BYTES (96 * 1024)
 // largest dimension whose column XOR row fits 16 bits
 #define SPMV_X16_MAX_DIM 65536
 // row length granule of the padded layout (real values, states that fit LDS)

@@ -2,8 +2,9 @@
 
 A schedule is the number of wave lanes per CSR row (8, 16, 32, 64) with the
 VQE_SPMV_* options: wide loads (VEC4), the state staged in LDS (LDS, DEEP),
-the pipelined loads (PREFETCH), 16-bit column codes (X16) and, for a real H,
-the real values in the row-padded layout (REAL).  It is picked
+the pipelined loads (PREFETCH), 16-bit column codes (X16), the complex
+values in the row-padded layout (PAD) and, for a real H, the real values in
+that layout (REAL).  It is picked
 per (register size, dtype, mapping, value form, device) by timing the batched
 H product phase of a real plan over the candidates, and cached.  The value
 form "complex" keeps the interleaved complex values of the CSR (candidates
@@ -25,7 +26,7 @@ import numpy as np
 from . import binding as B
 
 _L, _V, _D, _P = B.VQE_SPMV_LDS, B.VQE_SPMV_VEC4, B.VQE_SPMV_DEEP, B.VQE_SPMV_PREFETCH
-_X, _R = B.VQE_SPMV_X16, B.VQE_SPMV_REAL
+_X, _R, _Q = B.VQE_SPMV_X16, B.VQE_SPMV_REAL, B.VQE_SPMV_PAD
 CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               8 | _L, 16 | _L, 32 | _L, 64 | _L, 8 | _L | _D, 16 | _L | _D, 32 | _L | _D, 64 | _L | _D,
               32 | _L | _P, 64 | _L | _P, 32 | _L | _P | _D, 64 | _L | _P | _D,
@@ -33,7 +34,9 @@ CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               32 | _L | _P | _X, 64 | _L | _P | _X, 32 | _L | _P | _D | _X, 64 | _L | _P | _D | _X,
               16 | _L | _P | _X | _R, 32 | _L | _P | _X | _R, 64 | _L | _P | _X | _R,
               32 | _L | _P | _D | _X | _R,
-              64 | _L | _P | _D | _X | _R)
+              64 | _L | _P | _D | _X | _R,
+              16 | _L | _P | _X | _Q, 32 | _L | _P | _X | _Q, 64 | _L | _P | _X | _Q,
+              32 | _L | _P | _D | _X | _Q)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}

@@ -344,3 +344,34 @@ def test_jw_bk_same_trajectory_energies():
     np.testing.assert_allclose(tb.energies, tj.energies, rtol=0, atol=1e-12)
     for gj, gb in zip(tj.gradients, tb.gradients):
         np.testing.assert_allclose(gb, gj, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("mapping", ["jw", "bk"])
+def test_csr_rows_are_rows_of_the_kronecker_sum(mapping):
+    """orc_csr_rows (selected rows, any order, with repeats) gives those rows
+    of the dense Kronecker-product matrix of the Pauli sum, and bit for bit
+    the full builder's rows; the sampled product equals the dense product at
+    those rows.  Bad rows and masks outside the register are refused."""
+    s = vs.make_system(vs.SystemSpec(8, 4, mapping, False, 23), with_pool=False)
+    h = s.hamiltonian
+    dense = D.pauli_sum_dense(8, h.xmask, h.zmask, h.coeff)
+    full = orc.csr_from_pack(h)
+    rows = np.random.default_rng(24).integers(0, 256, 80)
+    rows[:3] = [255, 0, 255]
+    R = orc.csr_rows(h, rows)
+    x = np.random.default_rng(25).standard_normal(256) + 1j * np.random.default_rng(26).standard_normal(256)
+    for j, r in enumerate(rows):
+        a = slice(R.rowptr[j], R.rowptr[j + 1])
+        b = slice(full.rowptr[r], full.rowptr[r + 1])
+        assert np.array_equal(R.col[a], full.col[b]) and np.array_equal(R.val[a], full.val[b])
+        row = np.zeros(256, dtype=np.complex128)
+        row[R.col[a]] = R.val[a]
+        np.testing.assert_allclose(row, dense[r], rtol=0, atol=1e-15 * np.abs(h.coeff).sum())
+    np.testing.assert_allclose(orc.spmv_rows(R, x), (dense @ x)[rows], rtol=0,
+                               atol=1e-13 * np.abs(dense @ x).max())
+    with pytest.raises(ValueError):
+        orc.csr_rows(h, [256])
+    bad = vs.PauliPack(8, np.array([1 << 8], dtype=np.uint64), np.array([0], dtype=np.uint64),
+                       np.array([1.0 + 0j]))
+    with pytest.raises(ValueError):
+        orc.csr_rows(bad, [0])
