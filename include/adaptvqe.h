@@ -476,7 +476,19 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * tile (a contiguous sub-range of the row) against the tile staged in LDS,
  * with FP64 per-tile row sums added in ascending tile order (8, 16, 32 or 64
  * lanes).  The plan keeps per-tile row bounds ((tiles + 1) * dim int32) and
- * the per-tile sums (tiles * dim complex FP64) for such states. */
+ * the per-tile sums (tiles * dim complex FP64) for such states.
+ * That column-tiled CSR form serves the real-value schedules (VQE_SPMV_REAL)
+ * of states of at most 2^16 rows.  Every other pipelined schedule runs a
+ * larger-than-LDS state in the blocked layout instead: the plan copies H into
+ * slabs of (2048-row block, 96 KiB column tile), each the block's entries in
+ * the tile with 16-bit tile-local column codes and the complex values (about
+ * nnz * (2 + value bytes) plus 4 bytes per row per tile of slab row
+ * pointers, plan-owned, rebuilt by vqe_batch_rebind), and one workgroup per
+ * row block walks the tiles with its rows' FP64 sums in LDS; any state size
+ * and any nnz below 2^31.  There the lanes (8, 16, 32 or 64) set the
+ * sub-group width, VQE_SPMV_X16 two groups of four entries per lane and pass
+ * instead of one, and VQE_SPMV_DEEP four rows in flight per sub-group instead
+ * of two. */
 #define VQE_SPMV_PREFETCH 0x800
 /* VQE_SPMV_X16 (with VQE_SPMV_LDS | VQE_SPMV_PREFETCH, 32 or 64 lanes; batch
  * plans only): the product reads each column as the 16-bit code

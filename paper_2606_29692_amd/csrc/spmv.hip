@@ -1626,8 +1626,10 @@ size_t spmv_blk_lds(int dtype)
            (size_t)(SPMV_BLK_ROWS + 1) * sizeof(int32_t);
 }
 
-// Blocked schedules: 8 lanes take two groups of four entries per pass (64
-// entries), wider sub-groups one group (64, 128 or 256 entries).
+// Blocked schedules: L lanes per row (8, 16, 32 or 64); VQE_SPMV_X16 gives
+// each lane two groups of four entries per pass instead of one; VQE_SPMV_DEEP
+// keeps four rows per sub-group in flight instead of two (short segments carry
+// few bytes per row, so narrow sub-groups need many rows in flight).
 template <int DT, int L, int D, int U>
 static void launch_blk_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s)
 {
@@ -1637,20 +1639,28 @@ static void launch_blk_t(const SpmvState *states, const int2 *tasks, unsigned gr
     k<<<grid, 1024, lds, s>>>(states, tasks);
 }
 
+template <int DT, int L>
+static void launch_blk_l(int sched, const SpmvState *states, const int2 *tasks, unsigned grid,
+                         hipStream_t s)
+{
+    const bool deep = (sched & VQE_SPMV_DEEP) != 0, wide = (sched & VQE_SPMV_X16) != 0;
+    if (deep)
+        wide ? launch_blk_t<DT, L, 4, 2>(states, tasks, grid, s)
+             : launch_blk_t<DT, L, 4, 1>(states, tasks, grid, s);
+    else
+        wide ? launch_blk_t<DT, L, 2, 2>(states, tasks, grid, s)
+             : launch_blk_t<DT, L, 2, 1>(states, tasks, grid, s);
+}
+
 template <int DT>
 static void launch_blk_dt(int sched, const SpmvState *states, const int2 *tasks, unsigned grid,
                           hipStream_t s)
 {
-    const bool deep = (sched & VQE_SPMV_DEEP) != 0;
     switch (sched & 0xff) {
-    case 8: deep ? launch_blk_t<DT, 8, 3, 2>(states, tasks, grid, s)
-                 : launch_blk_t<DT, 8, 2, 2>(states, tasks, grid, s); break;
-    case 16: deep ? launch_blk_t<DT, 16, 3, 1>(states, tasks, grid, s)
-                  : launch_blk_t<DT, 16, 2, 1>(states, tasks, grid, s); break;
-    case 64: deep ? launch_blk_t<DT, 64, 3, 1>(states, tasks, grid, s)
-                  : launch_blk_t<DT, 64, 2, 1>(states, tasks, grid, s); break;
-    default: deep ? launch_blk_t<DT, 32, 3, 1>(states, tasks, grid, s)
-                  : launch_blk_t<DT, 32, 2, 1>(states, tasks, grid, s); break;
+    case 8: launch_blk_l<DT, 8>(sched, states, tasks, grid, s); break;
+    case 16: launch_blk_l<DT, 16>(sched, states, tasks, grid, s); break;
+    case 64: launch_blk_l<DT, 64>(sched, states, tasks, grid, s); break;
+    default: launch_blk_l<DT, 32>(sched, states, tasks, grid, s); break;
     }
 }
 
@@ -1778,6 +1788,13 @@ bool vqe_valid_schedule(int sched)
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
+    // narrow pipelined schedules with the codes (plain LDS for states that
+    // fit; the blocked product's narrow forms for larger states)
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
+    case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
+    case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
     case 16 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_PAD:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_PAD:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_PAD:
@@ -1832,8 +1849,9 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
         if ((sched & VQE_SPMV_REAL) && (sched & VQE_SPMV_X16) && (H->flags & VQE_REAL) && aligned &&
             H->dim <= SPMV_X16_MAX_DIM && H->nnz * (int64_t)vqe_elem_bytes(H->dtype) <= 0x7fffff00LL)
             return (sched & ~VQE_SPMV_PAD) | VQE_SPMV_TILED;
-        // otherwise the blocked layout (complex values, tile-local codes)
-        return (sched & (0xff | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP)) |
+        // otherwise the blocked layout (complex values, tile-local codes;
+        // VQE_SPMV_X16 and VQE_SPMV_DEEP select the pass width and depth)
+        return (sched & (0xff | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16)) |
                VQE_SPMV_TILED | VQE_SPMV_BLOCKED;
     }
     return vqe_effective_schedule(H, sched);
