@@ -340,14 +340,16 @@ def serving_bench(n_requests: int, warm: int, log_fn=log):
     return out
 
 
-def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: int):
+def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: int,
+              tiled_screen: bool = False):
     """Time one batch plan's whole adaptive step (captured graphs):
       throughput  K steps between two events (whole-step graph, no events
                   inside), after W warm-up steps;
       latency     L steps with an event at every step boundary;
       H product   R steps recording events before and after the H-product
                   graph (the roofline's kernel duration) and at the end.
-    thetas: device float64 [W + K + L + R + 1, n_states]."""
+    thetas: device float64 [W + K + L + R + 1, n_states].  tiled_screen: the
+    step flag for states known to be complex (the row-tiled screen)."""
     import torch
     Ev = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
     t = 0
@@ -357,19 +359,20 @@ def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: in
         plan.theta.copy_(thetas[t % thetas.shape[0]])
         t += 1
 
+    ts = tiled_screen
     for _ in range(W):
         next_theta()
-        plan.step(renorm=True, graph=True)
+        plan.step(renorm=True, graph=True, tiled_screen=ts)
     ev3 = [Ev() for _ in range(3)]
     next_theta()
-    plan.step_timed(ev3, renorm=True, graph=True)      # captures the split graphs
+    plan.step_timed(ev3, renorm=True, graph=True, tiled_screen=ts)   # captures the split graphs
     torch.cuda.synchronize()
     start, stop = Ev(), Ev()
     start.record(stream)
     t_host = time.perf_counter()
     for _ in range(K):
         next_theta()
-        plan.step(renorm=True, graph=True)
+        plan.step(renorm=True, graph=True, tiled_screen=ts)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_host
@@ -378,14 +381,14 @@ def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: in
     bounds[0].record(stream)
     for i in range(L):
         next_theta()
-        plan.step(renorm=True, graph=True)
+        plan.step(renorm=True, graph=True, tiled_screen=ts)
         bounds[i + 1].record(stream)
     torch.cuda.synchronize()
     step_lat = [bounds[i].elapsed_time(bounds[i + 1]) for i in range(L)]
     evs = [[Ev() for _ in range(3)] for _ in range(R)]
     for i in range(R):
         next_theta()
-        plan.step_timed(evs[i], renorm=True, graph=True)
+        plan.step_timed(evs[i], renorm=True, graph=True, tiled_screen=ts)
     torch.cuda.synchronize()
     h_ms = [e[0].elapsed_time(e[1]) for e in evs]
     rest_ms = [e[1].elapsed_time(e[2]) for e in evs]
@@ -396,12 +399,12 @@ def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: in
             "h_product_launches_timed": R, "rest_of_step_ms": float(np.mean(rest_ms))}
 
 
-def eager_phases(plan, n: int = 10) -> dict:
+def eager_phases(plan, n: int = 10, tiled_screen: bool = False) -> dict:
     """Phase breakdown of the same step launched eagerly (7 events)."""
     import torch
     ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(n)]
     for t in range(n):
-        plan.step_timed(ev2[t], renorm=True)
+        plan.step_timed(ev2[t], renorm=True, tiled_screen=tiled_screen)
     torch.cuda.synchronize()
     m = lambda a, b: float(np.mean([e[a].elapsed_time(e[b]) for e in ev2]))   # noqa: E731
     return {"h_spmv": m(0, 1), "screen": m(2, 3), "taylor": m(4, 5), "renorm": m(5, 6),
@@ -440,7 +443,7 @@ def mixed_batch_leg(ctx, stream, pools_mf: bool, K: int, W: int, L: int, R: int)
     plan = PB.make_batch(ctx, ds, schedules=[scheds[d.n_qubits] for d in ds])
     rng = np.random.default_rng(np.random.SeedSequence([4, 1]))
     th = torch.from_numpy(rng.uniform(-0.1, 0.1, size=(W + K + L + R + 1, len(ds)))).to("cuda")
-    leg = timed_leg(plan, stream, len(ds), th, K, W, L, R)
+    leg = timed_leg(plan, stream, len(ds), th, K, W, L, R, tiled_screen=pools_mf)
     nb = PB.bytes_per_step(ds)
     plan.close()
     by_n = {str(n): sum(1 for d in ds if d.n_qubits == n) for n in scheds}
@@ -562,8 +565,11 @@ def main():
             T._last_timings.clear()
         set_states(ds, systems, form)
         plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
-        leg = timed_leg(plan, stream, len(ds), thetas, K, W, L, R)
-        ph = eager_phases(plan)
+        # complex states take the row-tiled screen (the step flag for them)
+        ts = form == "complex" and args.matrix_free
+        leg = timed_leg(plan, stream, len(ds), thetas, K, W, L, R, tiled_screen=ts)
+        ph = eager_phases(plan, tiled_screen=ts)
+        leg["tiled_screen"] = ts
         return sched, leg, ph, plan
 
     def form_record(form: str, sched: int, leg: dict, ph: dict) -> dict:

@@ -370,6 +370,18 @@ typedef struct vqe_batch_io {
 #define VQE_STEP_LINESEARCH 16u /* choose each state's angle by line search before
                                    the update (see vqe_batch_set_line_search); the
                                    chosen angle is written to theta */
+#define VQE_STEP_TILED_SCREEN 32u /* matrix-free plans: screen every state on row
+                                   tiles of its complex psi and sigma (the screen
+                                   used for states with imaginary parts), skipping
+                                   the plan's screen of real states on one
+                                   whole-state tile of real parts, which sends a
+                                   state with imaginary parts through the same row
+                                   tiles from inside its own launch, with fewer
+                                   workgroups.  For callers whose states are
+                                   complex.  The same sums for a complex state,
+                                   bit for bit; for a real state the same sums
+                                   formed in complex arithmetic per row tile,
+                                   equal to the rounding of FP64 sums */
 
 typedef struct vqe_batch vqe_batch;
 

@@ -23,6 +23,7 @@ VQE_PAIRING = 1
 VQE_REAL = 2
 VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_NO_UPDATE, VQE_STEP_GRAPH = 1, 2, 4, 8
 VQE_STEP_LINESEARCH = 16
+VQE_STEP_TILED_SCREEN = 32
 VQE_SPMV_VEC4 = 0x100
 VQE_SPMV_LDS = 0x200
 VQE_SPMV_DEEP = 0x400
@@ -599,10 +600,11 @@ class BatchPlan:
         self.handle = h
 
     @staticmethod
-    def _flags(renorm, forced, update, graph, line_search):
+    def _flags(renorm, forced, update, graph, line_search, tiled_screen=False):
         return ((VQE_STEP_RENORM if renorm else 0) | (VQE_STEP_FORCED if forced else 0)
                 | (0 if update else VQE_STEP_NO_UPDATE) | (VQE_STEP_GRAPH if graph else 0)
-                | (VQE_STEP_LINESEARCH if line_search else 0))
+                | (VQE_STEP_LINESEARCH if line_search else 0)
+                | (VQE_STEP_TILED_SCREEN if tiled_screen else 0))
 
     def set_line_search(self, theta_max: float):
         """Enable (theta_max > 0) or disable steps whose angle is chosen by line
@@ -634,15 +636,15 @@ class BatchPlan:
             "vqe_batch_reoptimize")
 
     def step(self, renorm: bool = True, forced: bool = False, update: bool = True,
-             graph: bool = False, line_search: bool = False):
-        flags = self._flags(renorm, forced, update, graph, line_search)
+             graph: bool = False, line_search: bool = False, tiled_screen: bool = False):
+        flags = self._flags(renorm, forced, update, graph, line_search, tiled_screen)
         self.ctx.check(lib().vqe_batch_step(self.handle, flags), "vqe_batch_step")
 
     def step_timed(self, events, renorm: bool = True, forced: bool = False, update: bool = True,
-                   graph: bool = False, line_search: bool = False):
+                   graph: bool = False, line_search: bool = False, tiled_screen: bool = False):
         """Step recording 3 or 7 torch.cuda.Event objects on the context stream
         (see vqe_batch_step_timed)."""
-        flags = self._flags(renorm, forced, update, graph, line_search)
+        flags = self._flags(renorm, forced, update, graph, line_search, tiled_screen)
         for e in events:
             if not e.cuda_event:          # torch creates the HIP event on first record
                 e.record(self.ctx.stream)

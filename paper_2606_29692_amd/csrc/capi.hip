@@ -199,8 +199,8 @@ struct vqe_batch {
     unsigned n_tay_tasks = 0;
     int2 *d_norm_tasks = nullptr;
     unsigned n_norm_tasks = 0;
-    hipGraphExec_t exec[16] = {};  // rest-of-step graphs by flag set (step_key)
-    hipGraph_t graph[16] = {};
+    hipGraphExec_t exec[32] = {};  // rest-of-step graphs by flag set (step_key)
+    hipGraph_t graph[32] = {};
     bool compact_taylor = false;   // every pool has a compact pair table
     bool mf = false;               // every pool is matrix-free: screen and update from records
     // host image of the descriptors (for rebinding slots)
@@ -211,8 +211,8 @@ struct vqe_batch {
     std::vector<int64_t> dims;
     hipGraphExec_t exec_spmv = nullptr;
     hipGraph_t graph_spmv = nullptr;
-    hipGraphExec_t exec_all[16] = {};  // whole-step graphs by flag set (steps without events)
-    hipGraph_t graph_all[16] = {};
+    hipGraphExec_t exec_all[32] = {};  // whole-step graphs by flag set (steps without events)
+    hipGraph_t graph_all[32] = {};
     // line search (vqe_batch_set_line_search)
     std::vector<PairTable> tables_host;            // CSR mode: pair tables (host copy)
     std::vector<const vqe_mf_pool *> mf_host;      // mf mode: pool of each table
@@ -415,7 +415,7 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
     // and the selection (the energy phase event coincides with the start)
     int rc = mark(2);
     const bool grad = p->mf || p->n_screen_tasks;
-    if (p->mf && p->n_screen1_tasks)
+    if (p->mf && p->n_screen1_tasks && !(flags & VQE_STEP_TILED_SCREEN))
         launch_screen_mf_real(p->dtype, p->d_screen, p->d_screen1_tasks, p->n_screen1_tasks,
                               p->screen1_lds, s);
     else if (p->mf)
@@ -513,7 +513,8 @@ template <class F> int capture(vqe_ctx *ctx, F fn, hipGraph_t *g_out, hipGraphEx
 int graph_step(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
 {
     vqe_ctx *ctx = p->ctx;
-    const unsigned key = (flags & 7u) | ((flags & VQE_STEP_LINESEARCH) ? 8u : 0u);
+    const unsigned key = (flags & 7u) | ((flags & VQE_STEP_LINESEARCH) ? 8u : 0u) |
+                         ((flags & VQE_STEP_TILED_SCREEN) ? 16u : 0u);
     int rc;
     if (!ev) {
         if (!p->exec_all[key] &&
@@ -1214,7 +1215,7 @@ extern "C" int vqe_batch_step(vqe_batch *p, uint32_t flags)
     if (!p)
         return VQE_EINVAL;
     if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH |
-                            VQE_STEP_LINESEARCH))
+                            VQE_STEP_LINESEARCH | VQE_STEP_TILED_SCREEN))
         return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step: unknown flags");
     if ((flags & VQE_STEP_LINESEARCH) && !p->ls_ready)
         return vqe_fail(p->ctx, VQE_EINVAL,
@@ -1232,7 +1233,7 @@ extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
     if (!events || (n_events != 3 && n_events != 7) ||
         (n_events == 7 && (flags & VQE_STEP_GRAPH)) ||
         (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_NO_UPDATE | VQE_STEP_GRAPH |
-                             VQE_STEP_LINESEARCH)) ||
+                             VQE_STEP_LINESEARCH | VQE_STEP_TILED_SCREEN)) ||
         ((flags & VQE_STEP_LINESEARCH) && !p->ls_ready))
         return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_step_timed: bad flags or events");
     for (int i = 0; i < n_events; i++)
@@ -1251,13 +1252,13 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
     if (!p)
         return VQE_EINVAL;
     (void)hipStreamSynchronize(p->ctx->stream);
-    for (int i = 0; i < 16; i++) {
+    for (int i = 0; i < 32; i++) {
         if (p->exec[i])
             (void)hipGraphExecDestroy(p->exec[i]);
         if (p->graph[i])
             (void)hipGraphDestroy(p->graph[i]);
     }
-    for (int i = 0; i < 16; i++) {
+    for (int i = 0; i < 32; i++) {
         if (p->exec_all[i])
             (void)hipGraphExecDestroy(p->exec_all[i]);
         if (p->graph_all[i])

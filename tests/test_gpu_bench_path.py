@@ -8,7 +8,8 @@ Sec. III-D selection, Eq. 6-8 update) and the final energy (Eq. 1).
 Two value forms, as the benchmark runs them:
   * complex: the interleaved complex values of H (a schedule without the
     real-value option) and states started from seeded complex states of their
-    particle sector, so the H product and the screen run in complex arithmetic;
+    particle sector, so the H product and the screen run in complex arithmetic
+    (the step flag that sends every state to the row-tiled screen);
   * real: the real-value specialisation (the real parts of a real H in the
     row-padded layout) on real states from the reference.
 Every state's energies, all 204 gradients and its final state are compared
@@ -80,7 +81,7 @@ def test_bench_call_all_states_vs_oracle(ctx, workload, form):
     G = np.zeros((STEPS, 64, 204))
     for t in range(STEPS):
         plan.theta.copy_(torch.from_numpy(thetas[:, t]))
-        plan.step(renorm=True, graph=True)
+        plan.step(renorm=True, graph=True, tiled_screen=form == "complex")
         E[t] = host(plan.energies).reshape(-1, 3)[:, 0]
         K[t] = host(plan.k)
         G[t] = host(plan.g).reshape(64, 204)
@@ -121,3 +122,28 @@ def test_bench_call_all_states_vs_oracle(ctx, workload, form):
     print(f"{form} form, 64 states x {STEPS} steps: max|dE| {worst['dE']:.2e} Ha, max|dg| "
           f"{worst['dg']:.2e}, max 1-F {worst['1-F']:.2e}, selections equal to the oracle's "
           f"{agree}/{64 * STEPS}")
+
+
+def test_tiled_screen_flag(ctx, workload):
+    """The step flag that sends every state to the row-tiled screen: on
+    complex states the same gradients bit for bit as the plan's default
+    screen (which runs the same row tiles for them from inside its launch);
+    on real states the same gradients to the rounding of FP64 sums."""
+    specs, systems, _ = workload
+    pools = PB.PoolCache(ctx, matrix_free=True)
+    sub = systems[:8]
+    ds = [PB.device_system(ctx, s, "c64", pools) for s in sub]
+    for i, (d, s) in enumerate(zip(ds, sub)):
+        if i % 2:
+            d.psi.copy_(torch.from_numpy(vs.complex_start_state(s).astype(np.complex64)))
+    plan = PB.make_batch(ctx, ds, schedules=[18976] * len(ds))
+    plan.step(update=False)
+    g0 = host(plan.g).reshape(len(ds), -1).copy()
+    plan.step(update=False, tiled_screen=True, graph=True)
+    g1 = host(plan.g).reshape(len(ds), -1).copy()
+    for i in range(len(ds)):
+        if i % 2:
+            np.testing.assert_array_equal(g1[i], g0[i])
+        else:
+            np.testing.assert_allclose(g1[i], g0[i], rtol=0, atol=1e-12 * max(1.0, np.abs(g0[i]).max()))
+    plan.close()
