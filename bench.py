@@ -46,7 +46,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # column-tiled)
 LDS_STATE_BYTES = 147 * 1024
 PMC_PROFILES = ("h_product_14q_64states_complex_pmc.md", "h_product_14q_64states_pmc.md",
-                "h_product_16q_16states_pmc.md", "h_product_18q_pmc.md")
+                "h_product_16q_16states_pmc.md", "h_product_18q_16states_pmc.md",
+                "h_product_20q_4states_pmc.md")
 
 
 def _traffic_record(path: str, schedule: int, workload: str):
@@ -588,6 +589,7 @@ def main():
                                 "for a real H: the specialisation's own accounting, not the "
                                 "contract's"),
             "h_product_GBps": achieved, "h_product_frac_of_peak": achieved / HBM_PEAK_GBS,
+            "traffic_bytes_per_launch": measured_traffic(sched, wl),
             "stored_bytes_per_launch": stored, "stored_GBps": stored / h_s / 1e9,
             "column_form": ("16-bit col^row codes" if x16 else "int32 CSR columns") +
                            (", rows padded to groups of eight" if rv or plan_sched_pad(sched, ds)
