@@ -497,7 +497,8 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * nnz * (2 + value bytes) plus 4 bytes per row per tile of slab row
  * pointers, plan-owned, rebuilt by vqe_batch_rebind), and one workgroup per
  * row block walks the tiles with its rows' FP64 sums in LDS; any state size
- * and any nnz below 2^31.  There the lanes (8, 16, 32 or 64) set the
+ * and any nnz below 2^31.  There the lanes (4, 8, 16, 32 or 64; four only
+ * there, elsewhere a four-lane schedule runs with eight) set the
  * sub-group width, VQE_SPMV_X16 two groups of four entries per lane and pass
  * instead of one, and VQE_SPMV_DEEP four rows in flight per sub-group instead
  * of two. */

@@ -185,6 +185,7 @@ struct vqe_batch {
     int4 *d_screen_tasks = nullptr;
     unsigned n_screen_tasks = 0;
     int32_t max_m = 0;          // largest pool of the plan
+    int64_t max_gpart = 0;      // largest M x (screen tiles): the gradient partials per state
     size_t screen_lds = 0;
     // real-state screen (matrix-free pools of real anti-Hermitian generators
     // whose states fit one LDS tile as reals): tasks per (state, range)
@@ -426,7 +427,10 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
                       (unsigned)p->B, p->screen_lds, s);
     // without a line search the matrix-free update does the finalisation
     // itself (one kernel boundary less)
-    const bool fused_fin = p->mf && p->max_m <= FIN_LDS_G && !(flags & VQE_STEP_NO_UPDATE) &&
+    // (only while the screen's partial sums are few: every update block reads
+    // all of its state's)
+    const bool fused_fin = p->mf && p->max_m <= FIN_LDS_G && p->max_gpart <= FIN_FUSE_PARTIALS &&
+                           !(flags & VQE_STEP_NO_UPDATE) &&
                            !(flags & VQE_STEP_LINESEARCH);
     if (!fused_fin)
         launch_step_fin(p->d_spmv, p->d_screen, p->d_tables, p->d_sel, (unsigned)p->B, grad,
@@ -1074,6 +1078,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     p->tables_host = tables;
     for (const PairTable &t : tables)
         p->max_m = std::max(p->max_m, t.M);
+    for (const PairTable &t : tables)
+        p->max_gpart = std::max<int64_t>(p->max_gpart, (int64_t)t.M * t.nt);
     if (mf_mode) {
         p->mf_host.assign(tables.size(), nullptr);
         for (int s = 0; s < B; s++)

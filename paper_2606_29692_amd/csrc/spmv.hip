@@ -1626,7 +1626,7 @@ size_t spmv_blk_lds(int dtype)
            (size_t)(SPMV_BLK_ROWS + 1) * sizeof(int32_t);
 }
 
-// Blocked schedules: L lanes per row (8, 16, 32 or 64); VQE_SPMV_X16 gives
+// Blocked schedules: L lanes per row (4, 8, 16, 32 or 64); VQE_SPMV_X16 gives
 // each lane two groups of four entries per pass instead of one; VQE_SPMV_DEEP
 // keeps four rows per sub-group in flight instead of two (short segments carry
 // few bytes per row, so narrow sub-groups need many rows in flight).
@@ -1657,6 +1657,7 @@ static void launch_blk_dt(int sched, const SpmvState *states, const int2 *tasks,
                           hipStream_t s)
 {
     switch (sched & 0xff) {
+    case 4: launch_blk_l<DT, 4>(sched, states, tasks, grid, s); break;
     case 8: launch_blk_l<DT, 8>(sched, states, tasks, grid, s); break;
     case 16: launch_blk_l<DT, 16>(sched, states, tasks, grid, s); break;
     case 64: launch_blk_l<DT, 64>(sched, states, tasks, grid, s); break;
@@ -1789,7 +1790,12 @@ bool vqe_valid_schedule(int sched)
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_REAL:
     // narrow pipelined schedules with the codes (plain LDS for states that
-    // fit; the blocked product's narrow forms for larger states)
+    // fit, with at least eight lanes; the blocked product's narrow forms for
+    // larger states)
+    case 4 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH:
+    case 4 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
+    case 4 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
+    case 4 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
     case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP:
     case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16:
     case 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16:
@@ -1811,6 +1817,10 @@ bool vqe_valid_schedule(int sched)
 // schedule with the same lanes is used.
 int vqe_effective_schedule(const vqe_csr *H, int sched)
 {
+    // four lanes per row exist only in the blocked product of states larger
+    // than LDS; elsewhere the same schedule runs with eight
+    if ((sched & 0xff) == 4)
+        sched = (sched & ~0xff) | 8;
     // the real-value form needs an operator flagged real, and the codes
     if (!(H->flags & VQE_REAL))
         sched &= ~VQE_SPMV_REAL;

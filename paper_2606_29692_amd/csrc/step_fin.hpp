@@ -8,6 +8,10 @@
 #include "kernels.hpp"
 
 #define FIN_LDS_G 2048   // gradients per state kept in LDS for the selection
+// the matrix-free update repeats its state's finalisation in every block while
+// the screen leaves at most this many partial sums per state (generators x
+// row tiles); beyond, one finalisation kernel per state runs before the update
+#define FIN_FUSE_PARTIALS 4096
 
 // With write false nothing is stored, so that every workgroup of a state's
 // update can form the same selection.  Returns the selected index in every

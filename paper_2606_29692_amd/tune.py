@@ -39,7 +39,7 @@ CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               32 | _L | _P | _D | _X | _Q,
               # narrow sub-groups (the blocked product of states larger than LDS)
               8 | _L | _P | _D, 8 | _L | _P | _X, 8 | _L | _P | _D | _X, 16 | _L | _P | _X,
-              16 | _L | _P | _D | _X)
+              16 | _L | _P | _D | _X, 4 | _L | _P, 4 | _L | _P | _D, 4 | _L | _P | _X)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}

@@ -273,7 +273,10 @@ def test_full_size_bench_config(ctx, sched):
                                    64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
                                    B.VQE_SPMV_PAD,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
-                                   B.VQE_SPMV_X16 | B.VQE_SPMV_PAD])
+                                   B.VQE_SPMV_X16 | B.VQE_SPMV_PAD,
+                                   4 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
+                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
+                                   B.VQE_SPMV_X16])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]

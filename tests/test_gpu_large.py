@@ -58,7 +58,7 @@ def host(t):
 
 @pytest.mark.parametrize("sched", [8 | P, 16 | P, 32 | P, 16 | P | B.VQE_SPMV_DEEP,
                                    8 | P | B.VQE_SPMV_DEEP, 8 | P | B.VQE_SPMV_DEEP | B.VQE_SPMV_X16,
-                                   64 | P | B.VQE_SPMV_X16])
+                                   64 | P | B.VQE_SPMV_X16, 4 | P, 4 | P | B.VQE_SPMV_X16])
 def test_blocked_18_qubits_sigma_energy(ctx, systems18, sched):
     pools = PB.PoolCache(ctx, matrix_free=True)
     ds, psis = [], []
