@@ -123,6 +123,27 @@ def plan_sched_pad(sched: int, ds) -> bool:
 BLK_ROWS, BLK_TILE_BYTES = 2048, 96 * 1024     # blocked layout of column-tiled states
 
 
+def plan_sliced(sched: int, d) -> bool:
+    """True when a state runs the sliced layout (one row per lane): the
+    schedule asks for it and the state fits LDS."""
+    from paper_2606_29692_amd import binding as B
+    return bool(sched & B.VQE_SPMV_SLICED) and \
+        d.H.dim * d.psi.element_size() <= LDS_STATE_BYTES and d.H.dim < 65536
+
+
+def sliced_entries(d, e: int) -> int:
+    """Entries (pads included) of a state's sliced layout: per block of
+    2048 rows sorted by length, slices of 64 rows padded to their longest row
+    rounded up to e."""
+    lens = np.diff(d.H.rowptr.cpu().numpy().astype(np.int64))
+    tot = 0
+    for b in range(0, len(lens), BLK_ROWS):
+        l = np.sort(lens[b:b + BLK_ROWS])[::-1]
+        mx = l[::64]
+        tot += int(((mx + e - 1) // e * e).sum()) * 64
+    return tot
+
+
 def plan_blocked(sched: int, d) -> bool:
     """True when a column-tiled state runs the blocked layout (every tiled
     state except the real-value form's, which keeps the CSR order)."""
@@ -144,6 +165,11 @@ def stored_h_bytes(sched: int, ds) -> int:
     pad = rv or plan_sched_pad(sched, ds)
     tot = 0
     for d in ds:
+        if plan_sliced(sched, d):
+            ns = -(-d.H.dim // BLK_ROWS) * (BLK_ROWS // 64)
+            tot += 2 * d.H.dim + 8 * ns + sliced_entries(d, sched & 0xff) * \
+                (2 + d.H.val.element_size()) + 2 * d.H.dim * d.psi.element_size()
+            continue
         if plan_blocked(sched, d):
             tc = BLK_TILE_BYTES // d.psi.element_size()
             nb, nt = -(-d.H.dim // BLK_ROWS), -(-d.H.dim // tc)
@@ -591,9 +617,11 @@ def main():
             "h_product_GBps": achieved, "h_product_frac_of_peak": achieved / HBM_PEAK_GBS,
             "traffic_bytes_per_launch": measured_traffic(sched, wl),
             "stored_bytes_per_launch": stored, "stored_GBps": stored / h_s / 1e9,
-            "column_form": ("16-bit col^row codes" if x16 else "int32 CSR columns") +
-                           (", rows padded to groups of eight" if rv or plan_sched_pad(sched, ds)
-                            else ""),
+            "column_form": ("16-bit columns, one row per lane in slices of 64 rows sorted by "
+                            "length" if all(plan_sliced(sched, d) for d in ds) else
+                            ("16-bit col^row codes" if x16 else "int32 CSR columns") +
+                            (", rows padded to groups of eight" if rv or plan_sched_pad(sched, ds)
+                             else "")),
             "pool_gradient_spmv_GBps": (nb["h_spmv"] + nb["pool_screen"]) /
                                        ((leg["h_product_ms"] + ph["screen"]) / 1e3) / 1e9,
             "eager_phase_ms": ph, **leg}
@@ -808,7 +836,7 @@ def main():
                                 f"column-tiled H product of all {len(ds)} states (k_spmv_tiled, "
                                 f"then k_spmv_tile_sum)" if tiled else
                                 f"H product of all {len(ds)} states (one launch of the schedule's "
-                                f"kernel: k_spmv_lds_pf, k_spmv_lds or k_spmv_energy)"),
+                                f"kernel: k_spmv_sell, k_spmv_lds_pf, k_spmv_lds or k_spmv_energy)"),
                      "bytes_per_launch": nbytes["h_spmv"],
                      "launch_ms": head["h_product_ms"],
                      "launches_timed": head["h_product_launches_timed"],

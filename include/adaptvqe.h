@@ -543,6 +543,22 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * The row sums are the same FP64 sums of exact-in-FP64 products, grouped over
  * the lanes differently: results agree to the rounding of FP64 sums. */
 #define VQE_SPMV_PAD 0x10000
+/* VQE_SPMV_SLICED (with VQE_SPMV_LDS and E = 2, 4 or 8 in place of the lanes;
+ * batch plans only; states that fit LDS): one row per wave lane.  The plan
+ * sorts each block of 2048 rows by length (longest first, ties by row) and
+ * stores every 64 consecutive sorted rows as a slice in which lane i's j-th
+ * entry sits at ((j / E) * 64 + i) * E + j mod E, so that each load of E
+ * entries is contiguous over the wave; a slice is padded to its longest row,
+ * rounded up to E, with zero values (a few percent of the entries for the
+ * molecular Hamiltonians at 14 qubits).  Columns are stored as 16-bit
+ * indices beside the complex values (about nnz * (2 + value bytes) plus 2
+ * bytes per row and 8 per slice; plan-owned, rebuilt by vqe_batch_rebind,
+ * which then waits for the layout's size).  Each lane sums its row in the
+ * CSR's column order.  A state larger than LDS runs the blocked layout with
+ * eight lanes (| VQE_SPMV_PREFETCH | VQE_SPMV_X16); single calls
+ * (vqe_time_spmv) run the 32-lane pipelined schedule.  Results agree with the
+ * other schedules to the rounding of FP64 sums. */
+#define VQE_SPMV_SLICED 0x40000
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given
  * schedule: `reps` back-to-back launches bracketed by HIP events on the

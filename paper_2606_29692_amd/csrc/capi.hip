@@ -345,6 +345,47 @@ int codes_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     return VQE_OK;
 }
 
+// (Re)build slot s's sliced layout of H (VQE_SPMV_SLICED) in its plan-owned
+// buffers -- the slice table (row order, slice lengths and starts, the total)
+// in prow, the codes in col16, the values in vre -- and point the slot's host
+// descriptor at it (the caller uploads the descriptor).  The codes and values
+// are sized from the table, so this waits for the context stream once.
+int sliced_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
+{
+    vqe_ctx *ctx = p->ctx;
+    SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
+    const int E = sched & 0xff;
+    const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
+    const int64_t ns = nb * SPMV_SLICES_PER_BLOCK;
+    const size_t o_len = vqe_align((size_t)H->dim * sizeof(uint16_t));
+    const size_t o_sl = o_len + vqe_align((size_t)ns * sizeof(int32_t));
+    const size_t o_tot = o_sl + vqe_align((size_t)ns * sizeof(int2));
+    int rc = grow(p, &p->prow[s], &p->prow_cap[s], (int64_t)(o_tot + sizeof(int64_t)), "slice table", s);
+    if (rc)
+        return rc;
+    char *m = (char *)p->prow[s];
+    launch_sell_layout(H, E, (uint16_t *)m, (int32_t *)(m + o_len), (int2 *)(m + o_sl),
+                       (int64_t *)(m + o_tot), ctx->stream);
+    VQE_LAUNCH_CHECK(ctx);
+    int64_t total = 0;
+    VQE_HIP(ctx, hipMemcpyAsync(&total, m + o_tot, sizeof(total), hipMemcpyDeviceToHost, ctx->stream));
+    VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (total < 0 || total > 0x7fffffffLL)
+        return vqe_fail(ctx, VQE_ESIZE, "sliced layout of slot %d: %lld entries", s, (long long)total);
+    const int64_t n = total > 0 ? total : 1;
+    if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], n * 2, "slice codes", s)) ||
+        (rc = grow(p, &p->vre[s], &p->vre_cap[s], n * (int64_t)vqe_elem_bytes(H->dtype), "slice values", s)))
+        return rc;
+    launch_sell_fill(H, E, (const uint16_t *)m, (const int2 *)(m + o_sl), (uint16_t *)p->col16[s],
+                     p->vre[s], ctx->stream);
+    VQE_LAUNCH_CHECK(ctx);
+    st.scode = (const uint16_t *)p->col16[s];
+    st.sval = p->vre[s];
+    st.srow = (const uint16_t *)m;
+    st.sslice = (const int2 *)(m + o_sl);
+    return VQE_OK;
+}
+
 // (Re)build slot s's blocked layout of H (VQE_SPMV_BLOCKED) in its plan-owned
 // allocation and point the slot's host descriptor at it (the caller uploads
 // the descriptor).  The layout is built on the context stream from the CSR,
@@ -1107,11 +1148,12 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     p->blk_cap.assign(B, 0);
     bool any16 = false;
     for (int s = 0; s < B; s++) {
-        if (!(lanes[s] & (VQE_SPMV_X16 | VQE_SPMV_BLOCKED)))
+        if (!(lanes[s] & (VQE_SPMV_X16 | VQE_SPMV_BLOCKED | VQE_SPMV_SLICED)))
             continue;
         any16 = true;
-        const int rc16 = (lanes[s] & VQE_SPMV_BLOCKED) ? blocked_fill(p, s, items[s].H)
-                                                       : codes_fill(p, s, items[s].H, lanes[s]);
+        const int rc16 = (lanes[s] & VQE_SPMV_BLOCKED)  ? blocked_fill(p, s, items[s].H)
+                         : (lanes[s] & VQE_SPMV_SLICED) ? sliced_fill(p, s, items[s].H, lanes[s])
+                                                        : codes_fill(p, s, items[s].H, lanes[s]);
         if (rc16) {
             vqe_batch_destroy(p);
             return rc16;
@@ -1183,6 +1225,10 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
     ts->psi = it->psi;
     if (sched & VQE_SPMV_BLOCKED) {
         rc = blocked_fill(p, slot, it->H);
+        if (rc)
+            return rc;
+    } else if (sched & VQE_SPMV_SLICED) {
+        rc = sliced_fill(p, slot, it->H, sched);
         if (rc)
             return rc;
     } else if (sched & VQE_SPMV_X16) {

@@ -298,6 +298,15 @@ void launch_val_real(const vqe_csr *H, void *out, hipStream_t s);
 // nnz + (SPMV_PAD - 1) dim entries)
 void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vpad, bool real,
                        hipStream_t s);
+// sliced layout of H (a state that fits LDS; VQE_SPMV_SLICED with E entries
+// per lane and load group): the per-block row order srow [dim], the slice
+// lengths slen [blocks * SPMV_SLICES_PER_BLOCK], the slices (start, length)
+// sslice [same] and *total, the entries of all slices (device int64) ...
+void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, int2 *sslice,
+                        int64_t *total, hipStream_t s);
+// ... then, with room for total entries, the codes and values
+void launch_sell_fill(const vqe_csr *H, int E, const uint16_t *srow, const int2 *sslice,
+                      uint16_t *code, void *val, hipStream_t s);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 
 void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, unsigned grid,

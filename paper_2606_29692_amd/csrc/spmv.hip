@@ -891,6 +891,250 @@ k_spmv_lds_pf(SpmvState single, const SpmvState *__restrict__ states,
 }
 
 
+// ------------------------------------------------------------------ sliced layout
+// VQE_SPMV_SLICED: one row per wave lane (the layout is described with
+// SpmvState::scode).  Rows of a block are sorted by length so that the 64 rows
+// of a slice are nearly equally long (the pads are a few percent of the
+// entries at 14 qubits); a lane's loads of E entries sit next to its
+// neighbours' (one contiguous run per wave and load), every lane sums its row
+// in the CSR's column order with no cross-lane reduction, and the slice's
+// length is uniform over the wave, so the loop has no row masks.
+
+typedef unsigned sell_v2u __attribute__((ext_vector_type(2)));
+typedef unsigned sell_v4u __attribute__((ext_vector_type(4)));
+typedef int sell_v2i __attribute__((ext_vector_type(2)));
+
+// Sort each block's rows by length, longest first (ties by row), and give
+// each slice its length rounded up to E; one workgroup per block.
+__global__ void __launch_bounds__(1024)
+k_sell_sort(const int32_t *__restrict__ rowptr, int64_t dim, int E, uint16_t *__restrict__ srow,
+            int32_t *__restrict__ slen)
+{
+    __shared__ uint32_t key[SPMV_LDS_ROWS];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * SPMV_LDS_ROWS;
+    const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
+    for (int i = tid; i < SPMV_LDS_ROWS; i += 1024) {
+        uint32_t k = 0xffffffffu;   // no row: sorts last
+        if (i < n) {
+            const uint32_t len = (uint32_t)(gmem(rowptr)[r0 + i + 1] - gmem(rowptr)[r0 + i]);
+            k = ((0xffffu - len) << 16) | (uint32_t)i;
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    // bitonic sort, ascending keys
+    for (int k = 2; k <= SPMV_LDS_ROWS; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < SPMV_LDS_ROWS; i += 1024) {
+                const int q = i ^ j;
+                if (q > i) {
+                    const uint32_t a = key[i], b = key[q];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[q] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = tid; i < n; i += 1024)
+        srow[r0 + i] = (uint16_t)(key[i] & 0xffffu);
+    if (tid < SPMV_SLICES_PER_BLOCK) {
+        int len = 0;
+        if (tid * VQE_WAVE < n) {
+            len = (int)(0xffffu - (key[tid * VQE_WAVE] >> 16));
+            len = (len + E - 1) / E * E;
+        }
+        slen[(int64_t)blockIdx.x * SPMV_SLICES_PER_BLOCK + tid] = len;
+    }
+}
+
+// Slice starts (entries) in slice order and the total; one thread (a state
+// that fits LDS has at most a few hundred slices).
+__global__ void k_sell_scan(const int32_t *__restrict__ slen, int64_t ns, int2 *__restrict__ sslice,
+                            int64_t *__restrict__ total)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    int64_t at = 0;
+    for (int64_t c = 0; c < ns; c++) {
+        const int len = slen[c];
+        sslice[c] = make_int2((int)at, len);
+        at += (int64_t)len * VQE_WAVE;
+    }
+    *total = at;
+}
+
+// Codes and values of one slice per wave (pads: column dim, value zero).
+template <int DT>
+__global__ void __launch_bounds__(64)
+k_sell_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+            const void *__restrict__ val, int64_t dim, int E, const uint16_t *__restrict__ srow,
+            const int2 *__restrict__ sslice, uint16_t *__restrict__ code, void *__restrict__ sval)
+{
+    using T = typename Elem<DT>::T;
+    const int64_t c = blockIdx.x;
+    const int64_t r0 = (c / SPMV_SLICES_PER_BLOCK) * SPMV_LDS_ROWS;
+    const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
+    const int lane = threadIdx.x;
+    const int i = (int)(c % SPMV_SLICES_PER_BLOCK) * VQE_WAVE + lane;
+    const int2 sl = sslice[c];
+    int64_t k0 = 0;
+    int len = 0;
+    if (i < n) {
+        const int64_t row = r0 + srow[r0 + i];
+        k0 = rowptr[row];
+        len = rowptr[row + 1] - (int32_t)k0;
+    }
+    T *out = reinterpret_cast<T *>(sval);
+    const T *in = reinterpret_cast<const T *>(val);
+    for (int j = 0; j < sl.y; j++) {
+        const int64_t at = (int64_t)sl.x + ((int64_t)(j / E) * VQE_WAVE + lane) * E + j % E;
+        code[at] = j < len ? (uint16_t)col[k0 + j] : (uint16_t)dim;
+        out[at] = j < len ? in[k0 + j] : T{};
+    }
+}
+
+// E consecutive entries of one lane: their codes (two per word) and values.
+template <int DT, int E>
+struct SellGroup {
+    using T = typename Elem<DT>::T;
+    unsigned c[E / 2];
+    T v[E];
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ code,
+                                         const T *__restrict__ val, int64_t at)
+    {
+        if constexpr (E == 2) {
+            c[0] = gmem(reinterpret_cast<const unsigned *>(code + at))[0];
+        } else if constexpr (E == 4) {
+            const sell_v2u w = gmem(reinterpret_cast<const sell_v2u *>(code + at))[0];
+            c[0] = w.x;
+            c[1] = w.y;
+        } else {
+            const sell_v4u w = gmem(reinterpret_cast<const sell_v4u *>(code + at))[0];
+            c[0] = w.x;
+            c[1] = w.y;
+            c[2] = w.z;
+            c[3] = w.w;
+        }
+        if constexpr (DT == VQE_C64) {
+#pragma unroll
+            for (int q = 0; q < E / 2; q++) {
+                const vqe_v4f a = gmem(reinterpret_cast<const vqe_v4f *>(val + at))[q];
+                v[2 * q] = make_float2(a.x, a.y);
+                v[2 * q + 1] = make_float2(a.z, a.w);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < E; q++)
+                v[q] = ldg(val, at + q);
+        }
+    }
+    // each product added to the row's sums in turn (four FMAs per entry)
+    __device__ __forceinline__ void use(const T *s_x, double &are, double &aim) const
+    {
+#pragma unroll
+        for (int q = 0; q < E; q++) {
+            const T x = s_x[(q & 1) ? c[q / 2] >> 16 : c[q / 2] & 0xffffu];
+            const double ar = (double)v[q].x, ai = (double)v[q].y;
+            const double xr = (double)x.x, xi = (double)x.y;
+            are = fma(ar, xr, are);
+            are = fma(-ai, xi, are);
+            aim = fma(ar, xi, aim);
+            aim = fma(ai, xr, aim);
+        }
+    }
+};
+
+// One workgroup per (state, block of SPMV_LDS_ROWS rows): the state staged in
+// LDS (plus the zero element), each wave takes the block's slices in turn and
+// keeps D groups of E entries per lane in flight.
+template <int DT, int E, int D>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
+k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 t = tasks[blockIdx.x];
+    if (t.x < 0)
+        return;
+    const SpmvState st = states[t.x];
+    if (VQE_SKIP(st))
+        return;
+    const int blk = t.y;
+    using T = typename Elem<DT>::T;
+    extern __shared__ unsigned char smem[];
+    T *s_x = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t dim = st.dim;
+    stage_lds<8>(s_x, reinterpret_cast<const T *>(st.psi), dim, tid);
+    if (tid == 0)
+        s_x[dim] = T{};
+    __syncthreads();
+    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
+    const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
+    const int ns = (n + VQE_WAVE - 1) / VQE_WAVE;
+    const uint16_t *__restrict__ code = st.scode;
+    const T *__restrict__ val = reinterpret_cast<const T *>(st.sval);
+    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
+    for (int k = wid; k < ns; k += 16) {
+        // the slice's start and length are uniform over the wave
+        const sell_v2i sl =
+            gmem(reinterpret_cast<const sell_v2i *>(st.sslice))[(int64_t)blk * SPMV_SLICES_PER_BLOCK + k];
+        const int start = __builtin_amdgcn_readfirstlane(sl.x);
+        const int ng = __builtin_amdgcn_readfirstlane(sl.y) / E;
+        const int i = k * VQE_WAVE + lane;
+        const bool on = i < n;
+        const int64_t row = r0 + (on ? (int64_t)gmem(st.srow)[r0 + i] : 0);
+        const int64_t at = (int64_t)start + lane * E;
+        constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
+        double are = 0.0, aim = 0.0;
+        if (ng > 0) {
+            // every load is issued (past the slice's end it repeats the last
+            // group, which is in cache), so no load sits under a branch and
+            // each group's wait leaves the later groups' loads in flight
+            SellGroup<DT, E> g[D];
+#pragma unroll
+            for (int d = 0; d < D; d++)
+                g[d].load(code, val, at + (int64_t)(d < ng ? d : ng - 1) * STEP);
+            int q = 0;
+            for (; q + D <= ng; q += D) {
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    g[d].use(s_x, are, aim);
+                    const int nx = q + D + d < ng ? q + D + d : ng - 1;
+                    g[d].load(code, val, at + (int64_t)nx * STEP);
+                    // keep the refill ahead of the next group's products
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < D; d++)
+                if (q + d < ng)
+                    g[d].use(s_x, are, aim);
+        }
+        if (on) {
+            Elem<DT>::st(st.sigma, row, make_double2(are, aim));
+            energy_terms(s_x[row], are, aim, e_re, e_im, e_n2);
+        }
+    }
+    __shared__ double s_part[16][3];
+    e_re = wave_sum(e_re);
+    e_im = wave_sum(e_im);
+    e_n2 = wave_sum(e_n2);
+    if (lane == 0) {
+        s_part[wid][0] = e_re;
+        s_part[wid][1] = e_im;
+        s_part[wid][2] = e_n2;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double v = 0.0;
+        for (int w = 0; w < 16; w++)
+            v += s_part[w][tid];
+        gmem(st.partials)[(int64_t)blk * 3 + tid] = v;
+    }
+}
+
 // Column-tiled variant of the pipelined LDS schedule, for states larger than
 // LDS.  A workgroup takes one block of rows and one column tile: it stages
 // that tile of the state (SPMV_TILE_BYTES) and, per row, streams only the
@@ -1563,10 +1807,30 @@ static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, c
     }
 }
 
+// Sliced schedules: E entries per lane and load group, D groups in flight.
+template <int DT, int E, int D>
+static void launch_sell_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
+                          size_t lds)
+{
+    auto k = k_spmv_sell<DT, E, D>;
+    (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k<<<grid, 1024, lds, s>>>(states, tasks);
+}
+
 template <int DT>
 static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *states,
                            const int2 *tasks, unsigned grid, hipStream_t s, size_t lds)
 {
+    if ((sched & VQE_SPMV_SLICED) && tasks) {
+        // the sliced layout exists only in batch plans; E = 2, 4 or 8
+        // (FP64 values keep half as many groups in flight: the registers)
+        constexpr bool W = DT == VQE_C128;
+        switch (sched & 0xff) {
+        case 2: launch_sell_t<DT, 2, W ? 2 : 4>(states, tasks, grid, s, lds); return;
+        case 8: launch_sell_t<DT, 8, W ? 1 : 2>(states, tasks, grid, s, lds); return;
+        default: launch_sell_t<DT, 4, W ? 2 : 3>(states, tasks, grid, s, lds); return;
+        }
+    }
     constexpr int D = VQE_SPMV_LDS | VQE_SPMV_DEEP;
     constexpr int P = VQE_SPMV_LDS | VQE_SPMV_PREFETCH;
     constexpr int X = P | VQE_SPMV_X16;
@@ -1703,6 +1967,27 @@ void launch_blk_layout(const vqe_csr *H, int32_t nt, int32_t tc, int32_t R, int3
                                               bcode, bval);
 }
 
+void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, int2 *sslice,
+                        int64_t *total, hipStream_t s)
+{
+    const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
+    k_sell_sort<<<(unsigned)nb, 1024, 0, s>>>(H->rowptr, H->dim, E, srow, slen);
+    k_sell_scan<<<1, 64, 0, s>>>(slen, nb * SPMV_SLICES_PER_BLOCK, sslice, total);
+}
+
+void launch_sell_fill(const vqe_csr *H, int E, const uint16_t *srow, const int2 *sslice,
+                      uint16_t *code, void *val, hipStream_t s)
+{
+    const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
+    const unsigned g = (unsigned)(nb * SPMV_SLICES_PER_BLOCK);
+    if (H->dtype == VQE_C128)
+        k_sell_fill<VQE_C128><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, E, srow, sslice,
+                                               code, val);
+    else
+        k_sell_fill<VQE_C64><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, E, srow, sslice,
+                                              code, val);
+}
+
 void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState *states,
                  const int2 *tasks, unsigned grid, hipStream_t s, int64_t max_dim)
 {
@@ -1806,6 +2091,9 @@ bool vqe_valid_schedule(int sched)
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16 | VQE_SPMV_PAD:
     case 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_PAD:
     case 64 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_DEEP | VQE_SPMV_X16 | VQE_SPMV_PAD:
+    case 2 | VQE_SPMV_LDS | VQE_SPMV_SLICED:
+    case 4 | VQE_SPMV_LDS | VQE_SPMV_SLICED:
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_SLICED:
         return true;
     default:
         return false;
@@ -1817,6 +2105,13 @@ bool vqe_valid_schedule(int sched)
 // schedule with the same lanes is used.
 int vqe_effective_schedule(const vqe_csr *H, int sched)
 {
+    // the sliced layout needs a state that fits LDS (with its 16-bit columns);
+    // otherwise the 32-lane pipelined schedule with the codes stands in
+    if (sched & VQE_SPMV_SLICED) {
+        if (H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES || H->dim >= 65536)
+            return vqe_effective_schedule(H, 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16);
+        return sched & (VQE_SPMV_SLICED | VQE_SPMV_LDS | 0xff);
+    }
     // four lanes per row exist only in the blocked product of states larger
     // than LDS; elsewhere the same schedule runs with eight
     if ((sched & 0xff) == 4)
@@ -1852,6 +2147,10 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
 int vqe_batch_schedule(const vqe_csr *H, int sched)
 {
     const bool big = H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES;
+    // a sliced schedule runs a state larger than LDS in the blocked layout
+    // with eight lanes and two groups per lane
+    if ((sched & VQE_SPMV_SLICED) && big)
+        sched = 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16;
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
     if (big && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) && H->dim <= ((int64_t)1 << 30)) {
         // the real-value form keeps the column-tiled CSR (16-bit col ^ row
@@ -1941,6 +2240,8 @@ int vqe_spmv_energy_core(vqe_ctx *ctx, const vqe_csr *H, const void *psi, void *
                          double *out, int lanes, double *partials)
 {
     const int64_t dim = H->dim;
+    if (lanes & VQE_SPMV_SLICED)   // batch plans only
+        lanes = 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH;
     lanes = vqe_effective_schedule(H, lanes);
     const int64_t nblk = spmv_blocks(dim, lanes);
     SpmvState st{};
@@ -2031,9 +2332,10 @@ extern "C" int vqe_time_spmv(vqe_ctx *ctx, const vqe_csr *H, const void *psi, vo
         return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: bad arguments");
     if (!vqe_valid_schedule(schedule))
         return vqe_fail(ctx, VQE_EINVAL, "vqe_time_spmv: unknown schedule %d", schedule);
-    // a single call has no 16-bit column codes or real values: the same
-    // schedule without them
-    const int lanes = schedule & ~(VQE_SPMV_X16 | VQE_SPMV_REAL);
+    // a single call has no 16-bit column codes, real values or sliced layout:
+    // the same schedule without them (the 32-lane pipelined one for a sliced)
+    const int lanes = (schedule & VQE_SPMV_SLICED) ? 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH
+                                                   : schedule & ~(VQE_SPMV_X16 | VQE_SPMV_REAL);
     // energy result goes after the partials in the workspace
     const size_t o_out = vqe_spmv_partials_bytes(H->dim, lanes);
     rc = vqe_ws_reserve(ctx, o_out + 256);

@@ -65,6 +65,18 @@ struct SpmvState {
     const int32_t *brp;
     const int64_t *boff;
     int32_t blk_rows;
+    // sliced layout (VQE_SPMV_SLICED; states that fit LDS): per block of
+    // SPMV_LDS_ROWS rows, srow[block start + i] is the block-local row taken
+    // by sorted position i (rows by length, longest first), and slice k of
+    // block b (sorted positions 64k ... 64k + 63) starts at entry
+    // sslice[b * SPMV_SLICES_PER_BLOCK + k].x with .y entries per lane; lane
+    // i's j-th entry is at start + ((j / E) * 64 + i) * E + j % E, with the
+    // absolute 16-bit column in scode and the value in sval (pads: column dim,
+    // value zero)
+    const uint16_t *scode;
+    const void *sval;
+    const uint16_t *srow;
+    const int2 *sslice;
 };
 
 // Column-tiled H product: tile width (state elements staged in LDS per pass)
@@ -76,6 +88,8 @@ struct SpmvState {
 #define VQE_SPMV_BLOCKED 0x20000
 #define SPMV_BLK_ROWS 2048
 #define SPMV_BLK_TILE_BYTES (96 * 1024)
+// Sliced layout: slices of one wave's rows per block of SPMV_LDS_ROWS rows.
+#define SPMV_SLICES_PER_BLOCK (SPMV_LDS_ROWS / VQE_WAVE)
 // largest dimension whose column XOR row fits 16 bits
 #define SPMV_X16_MAX_DIM 65536
 // row length granule of the padded layout (real values, states that fit LDS)

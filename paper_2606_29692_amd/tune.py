@@ -3,8 +3,9 @@
 A schedule is the number of wave lanes per CSR row (8, 16, 32, 64) with the
 VQE_SPMV_* options: wide loads (VEC4), the state staged in LDS (LDS, DEEP),
 the pipelined loads (PREFETCH), 16-bit column codes (X16), the complex
-values in the row-padded layout (PAD) and, for a real H, the real values in
-that layout (REAL).  It is picked
+values in the row-padded layout (PAD), for a real H the real values in
+that layout (REAL), and the sliced layout with one row per lane (SLICED,
+with 2, 4 or 8 entries per lane and load in place of the lanes).  It is picked
 per (register size, dtype, mapping, value form, device) by timing the batched
 H product phase of a real plan over the candidates, and cached.  The value
 form "complex" keeps the interleaved complex values of the CSR (candidates
@@ -26,7 +27,7 @@ import numpy as np
 from . import binding as B
 
 _L, _V, _D, _P = B.VQE_SPMV_LDS, B.VQE_SPMV_VEC4, B.VQE_SPMV_DEEP, B.VQE_SPMV_PREFETCH
-_X, _R, _Q = B.VQE_SPMV_X16, B.VQE_SPMV_REAL, B.VQE_SPMV_PAD
+_X, _R, _Q, _S = B.VQE_SPMV_X16, B.VQE_SPMV_REAL, B.VQE_SPMV_PAD, B.VQE_SPMV_SLICED
 CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               8 | _L, 16 | _L, 32 | _L, 64 | _L, 8 | _L | _D, 16 | _L | _D, 32 | _L | _D, 64 | _L | _D,
               32 | _L | _P, 64 | _L | _P, 32 | _L | _P | _D, 64 | _L | _P | _D,
@@ -39,7 +40,9 @@ CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               32 | _L | _P | _D | _X | _Q,
               # narrow sub-groups (the blocked product of states larger than LDS)
               8 | _L | _P | _D, 8 | _L | _P | _X, 8 | _L | _P | _D | _X, 16 | _L | _P | _X,
-              16 | _L | _P | _D | _X, 4 | _L | _P, 4 | _L | _P | _D, 4 | _L | _P | _X)
+              16 | _L | _P | _D | _X, 4 | _L | _P, 4 | _L | _P | _D, 4 | _L | _P | _X,
+              # one row per lane, rows sorted by length into slices of 64
+              2 | _L | _S, 4 | _L | _S, 8 | _L | _S)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}

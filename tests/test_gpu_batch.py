@@ -206,7 +206,8 @@ def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
                                    B.VQE_SPMV_X16,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
-                                   B.VQE_SPMV_REAL])
+                                   B.VQE_SPMV_REAL,
+                                   4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED])
 def test_full_size_bench_config(ctx, sched):
     """64 states at 14 qubits in FP32 storage (the benchmark workload):
     sampled states against the oracle, invariants on every state."""
@@ -276,7 +277,10 @@ def test_full_size_bench_config(ctx, sched):
                                    B.VQE_SPMV_X16 | B.VQE_SPMV_PAD,
                                    4 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH,
                                    8 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP |
-                                   B.VQE_SPMV_X16])
+                                   B.VQE_SPMV_X16,
+                                   2 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
+                                   4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
+                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
@@ -303,6 +307,50 @@ def test_every_spmv_schedule_matches_oracle(ctx, sched):
         np.testing.assert_allclose(host(plan.gradients(i)), g_o, rtol=0,
                                    atol=1e-12 * max(1.0, np.abs(g_o).max()))
     plan.close()
+
+
+@pytest.mark.parametrize("sched", [e | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED for e in (2, 4, 8)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sliced_layout_sizes_vs_oracle(ctx, sched, dtype):
+    """The sliced layout at register sizes that leave slices and blocks
+    partly empty: 4 qubits (16 rows, under one slice), 6 (one slice), 10 (a
+    partial block), 12 and 14 (several blocks; 14 in FP64 exceeds LDS and
+    takes the blocked product), in one plan: sigma on every row and the
+    energy against the oracle, and the plan bit-identical to a plan of each
+    state alone."""
+    specs = [vs.SystemSpec(4, 2, "jw", False, 401), vs.SystemSpec(6, 2, "bk", False, 402),
+             vs.SystemSpec(10, 4, "jw", False, 403), vs.SystemSpec(12, 8, "bk", False, 404),
+             vs.SystemSpec(14, 6, "jw", False, 405)]
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx)
+    ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+    rng = np.random.default_rng(sched + 7)
+    psis = []
+    for d in ds:
+        v = rng.standard_normal(d.H.dim) + 1j * rng.standard_normal(d.H.dim)
+        v /= np.linalg.norm(v)
+        d.psi.copy_(torch.from_numpy(v))
+        psis.append(host(d.psi).astype(np.complex128))
+    plan = PB.make_batch(ctx, ds, schedules=[sched] * len(ds))
+    plan.step(update=False)
+    e = host(plan.energies).reshape(-1, 3).copy()
+    sig = [host(plan.sigma[i]).copy() for i in range(len(ds))]
+    plan.close()
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    for i, s in enumerate(systems):
+        oH = orc.csr_from_pack(s.hamiltonian)
+        e_o, n2, _, sg_o = orc.energy(oH, psis[i])
+        ref = sg_o - ds[i].H.diag_shift * psis[i]
+        err = np.linalg.norm(sig[i].astype(np.complex128) - ref) / np.linalg.norm(ref)
+        print(f"{s.spec.n_qubits} qubits {dtype}: sigma rel err {err:.2e}, |dE| {abs(e[i, 0] - e_o):.2e}")
+        assert err <= tol
+        assert abs(e[i, 0] - e_o) <= (1e-12 if dtype == "c128" else 1e-6) * max(1.0, abs(e_o))
+        assert abs(e[i, 1] - n2) <= 1e-12 * max(1.0, n2)
+        alone = PB.make_batch(ctx, [ds[i]], schedules=[sched])
+        alone.step(update=False)
+        np.testing.assert_array_equal(host(alone.sigma[0]), sig[i])
+        np.testing.assert_array_equal(host(alone.energies)[:3], e[i])
+        alone.close()
 
 
 def test_screen_full_pair_table(ctx):
@@ -339,7 +387,9 @@ def test_screen_full_pair_table(ctx):
                                    64 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
-                                   B.VQE_SPMV_REAL])
+                                   B.VQE_SPMV_REAL,
+                                   2 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
+                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("op", ["half", "zero"])
 def test_spmv_rows_without_entries(ctx, sched, dtype, op):
@@ -380,15 +430,17 @@ def test_spmv_rows_without_entries(ctx, sched, dtype, op):
     plan.close()
 
 
-@pytest.mark.parametrize("real", [False, True])
-def test_x16_rebind_rebuilds_codes(ctx, real):
-    """A slot with the 16-bit column form (and the real values) rebound to a
-    Hamiltonian with more entries (its codes and values are rebuilt in larger
-    buffers) gives the energies and sigma of that Hamiltonian's own plan, bit
-    for bit; both match the oracle."""
+@pytest.mark.parametrize("form", ["codes", "real", "sliced"])
+def test_x16_rebind_rebuilds_codes(ctx, form):
+    """A slot with the 16-bit column form (and the real values), or with the
+    sliced layout, rebound to a Hamiltonian with more entries (its codes and
+    values are rebuilt in larger buffers) gives the energies and sigma of that
+    Hamiltonian's own plan, bit for bit; both match the oracle."""
     sched = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_DEEP | B.VQE_SPMV_X16
-    if real:
+    if form == "real":
         sched |= B.VQE_SPMV_REAL
+    elif form == "sliced":
+        sched = 4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
     s = vs.make_system(vs.SystemSpec(12, 8, "jw", False, 91))
     ha = s.hamiltonian
     # two thirds of the terms: exact cancellations of the full sum are lost,
