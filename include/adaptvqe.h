@@ -409,6 +409,16 @@ VQE_API int vqe_batch_rebind(vqe_batch *plan, int32_t slot, const vqe_batch_item
  */
 VQE_API int vqe_batch_step_timed(vqe_batch *plan, uint32_t flags, void **events, int32_t n_events);
 /*
+ * Time the plan's H products alone (Eq. 1's sigma = S psi with the energy
+ * partials of every active slot, the kernels a step runs first): `reps`
+ * back-to-back launches of them bracketed by two HIP events on the context
+ * stream, so that the events' and the launches' own cost is spread over the
+ * launches; *ms_out = average milliseconds per launch.  psi is read only;
+ * sigma and the energy partials are rewritten (the same values each time).
+ * Waits for the context stream.  For measurement.
+ */
+VQE_API int vqe_batch_time_products(vqe_batch *plan, int32_t reps, float *ms_out);
+/*
  * Parameter optimisation (the adaptive loop of Sec. III-D leaves the choice of
  * the angle open).  Enables steps with VQE_STEP_LINESEARCH: after the
  * selection, each state's angle is the theta in [-theta_max, theta_max] that

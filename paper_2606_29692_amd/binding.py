@@ -139,6 +139,7 @@ SIGNATURES = {
     "vqe_batch_reoptimize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_int32, C.c_double, C.c_void_p]),
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
+    "vqe_batch_time_products": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_float)]),
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
     "vqe_default_schedule": (C.c_int32, [C.POINTER(vqe_csr)]),
@@ -652,6 +653,14 @@ class BatchPlan:
         n = len(events)
         arr = (C.c_void_p * n)(*[C.c_void_p(e.cuda_event) for e in events])
         self.ctx.check(lib().vqe_batch_step_timed(self.handle, flags, arr, n), "vqe_batch_step_timed")
+
+    def time_products(self, reps: int = 20) -> float:
+        """Average milliseconds of the H products alone over `reps`
+        back-to-back launches (see vqe_batch_time_products)."""
+        ms = C.c_float()
+        self.ctx.check(lib().vqe_batch_time_products(self.handle, int(reps), C.byref(ms)),
+                       "vqe_batch_time_products")
+        return float(ms.value)
 
     def rebind(self, slot: int, H: DeviceCSR, pool: DevicePool, psi):
         """Bind another state (same size, dtype, pool) to a slot; the slot keeps

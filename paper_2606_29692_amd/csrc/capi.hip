@@ -1299,6 +1299,39 @@ extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
     return enqueue_step(p, flags, ev);
 }
 
+extern "C" int vqe_batch_time_products(vqe_batch *p, int32_t reps, float *ms_out)
+{
+    if (!p)
+        return VQE_EINVAL;
+    vqe_ctx *ctx = p->ctx;
+    if (reps < 1 || !ms_out)
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_time_products: bad arguments");
+    hipEvent_t e0, e1;
+    VQE_HIP(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return vqe_fail(ctx, VQE_EHIP, "vqe_batch_time_products: event creation failed");
+    }
+    hipError_t e = hipEventRecord(e0, ctx->stream);
+    for (int i = 0; i < reps && e == hipSuccess; i++) {
+        launch_products(p, p->d_spmv);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess)
+        return vqe_fail(ctx, VQE_EHIP, "vqe_batch_time_products: %s", hipGetErrorString(e));
+    *ms_out = ms / (float)reps;
+    return VQE_OK;
+}
+
 extern "C" int vqe_batch_destroy(vqe_batch *p)
 {
     if (!p)

@@ -87,18 +87,13 @@ def _store(key: str, rec: dict):
 
 
 def time_batch_spmv(ctx, systems, schedule: int, reps: int = 10) -> float:
-    """Median milliseconds of the batched H-product phase with the given schedule."""
-    import torch
+    """Milliseconds per launch of the batched H products with the given
+    schedule: the median of three runs of `reps` back-to-back launches."""
     from .batch import make_batch
     plan = make_batch(ctx, systems, schedules=[schedule] * len(systems))
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
     for _ in range(3):
         plan.step(update=False)
-    times = []
-    for _ in range(reps):
-        plan.step_timed(ev, update=False)
-        ctx.stream.synchronize()
-        times.append(ev[0].elapsed_time(ev[1]))
+    times = [plan.time_products(reps) for _ in range(3)]
     plan.close()
     return float(np.median(times))
 

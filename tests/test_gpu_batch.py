@@ -353,6 +353,29 @@ def test_sliced_layout_sizes_vs_oracle(ctx, sched, dtype):
         alone.close()
 
 
+def test_time_products_rewrites_the_same_results(ctx):
+    """Back-to-back timing launches of the H products leave psi as it was
+    and rewrite sigma and the energy partials with the step's own values."""
+    specs = mixed_specs()[:3]
+    pools = PB.PoolCache(ctx)
+    ds = [PB.device_system(ctx, vs.make_system(s), "c64", pools) for s in specs]
+    plan = PB.make_batch(ctx, ds, schedules=[4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED] * len(ds))
+    plan.step(update=False)
+    psi0 = [host(d.psi).copy() for d in ds]
+    sig0 = [host(plan.sigma[i]).copy() for i in range(len(ds))]
+    e0 = host(plan.energies).copy()
+    ms = plan.time_products(5)
+    assert ms > 0.0
+    for i, d in enumerate(ds):
+        np.testing.assert_array_equal(host(d.psi), psi0[i])
+        np.testing.assert_array_equal(host(plan.sigma[i]), sig0[i])
+    plan.step(update=False)
+    np.testing.assert_array_equal(host(plan.energies), e0)
+    with pytest.raises(B.VqeError):
+        plan.time_products(0)
+    plan.close()
+
+
 def test_screen_full_pair_table(ctx):
     """Generators with entries other than +-1 (scaled excitations) take the
     full pair table instead of the compact one; both match the oracle."""
