@@ -124,24 +124,10 @@ BLK_ROWS, BLK_TILE_BYTES = 2048, 96 * 1024     # blocked layout of column-tiled 
 
 
 def plan_sliced(sched: int, d) -> bool:
-    """True when a state runs the sliced layout (one row per lane): the
-    schedule asks for it and the state fits LDS."""
+    """True when a state runs the sliced layout (one row per lane; column
+    tiled, slab by slab, when the state is larger than LDS)."""
     from paper_2606_29692_amd import binding as B
-    return bool(sched & B.VQE_SPMV_SLICED) and \
-        d.H.dim * d.psi.element_size() <= LDS_STATE_BYTES and d.H.dim < 65536
-
-
-def sliced_entries(d, e: int) -> int:
-    """Entries (pads included) of a state's sliced layout: per block of
-    2048 rows sorted by length, slices of 64 rows padded to their longest row
-    rounded up to e."""
-    lens = np.diff(d.H.rowptr.cpu().numpy().astype(np.int64))
-    tot = 0
-    for b in range(0, len(lens), BLK_ROWS):
-        l = np.sort(lens[b:b + BLK_ROWS])[::-1]
-        mx = l[::64]
-        tot += int(((mx + e - 1) // e * e).sum()) * 64
-    return tot
+    return bool(sched & B.VQE_SPMV_SLICED)
 
 
 def plan_blocked(sched: int, d) -> bool:
@@ -155,20 +141,25 @@ def plan_blocked(sched: int, d) -> bool:
         not real_tiled
 
 
-def stored_h_bytes(sched: int, ds) -> int:
+def stored_h_bytes(sched: int, ds, entries=None) -> int:
     """Bytes the H-product kernel has to read and write per launch in the
     form it reads: row pointers, 2- or 4-byte columns, complex or real
     values (row-padded or not), the state and the result.  A blocked state
     reads each slab's row pointers once (per row block and column tile),
-    16-bit tile-local codes and the complex values."""
+    16-bit tile-local codes and the complex values.  A sliced state reads its
+    layout's entries (``entries``, from the plan; pads included) as 16-bit
+    columns and complex values, 2 bytes of row order per row (per row and
+    column tile when tiled) and 8 bytes per slice (and per slab)."""
     x16, rv = plan_sched_x16(sched, ds), plan_sched_real(sched, ds)
     pad = rv or plan_sched_pad(sched, ds)
     tot = 0
-    for d in ds:
+    for i, d in enumerate(ds):
         if plan_sliced(sched, d):
-            ns = -(-d.H.dim // BLK_ROWS) * (BLK_ROWS // 64)
-            tot += 2 * d.H.dim + 8 * ns + sliced_entries(d, sched & 0xff) * \
-                (2 + d.H.val.element_size()) + 2 * d.H.dim * d.psi.element_size()
+            nb = -(-d.H.dim // BLK_ROWS)
+            big = d.H.dim * d.psi.element_size() > LDS_STATE_BYTES
+            nt = -(-d.H.dim // (BLK_TILE_BYTES // d.psi.element_size())) if big else 1
+            tot += 2 * d.H.dim * nt + 8 * nb * nt * (BLK_ROWS // 64 + (1 if big else 0)) + \
+                entries[i] * (2 + d.H.val.element_size()) + 2 * d.H.dim * d.psi.element_size()
             continue
         if plan_blocked(sched, d):
             tc = BLK_TILE_BYTES // d.psi.element_size()
@@ -603,6 +594,7 @@ def main():
         # complex states take the row-tiled screen (the step flag for them)
         ts = form == "complex" and args.matrix_free
         leg = timed_leg(plan, stream, len(ds), thetas, K, W, L, R, tiled_screen=ts)
+        leg["layout_entries"] = [plan.layout_entries(i) for i in range(len(ds))]
         ph = eager_phases(plan, tiled_screen=ts)
         leg["tiled_screen"] = ts
         return sched, leg, ph, plan
@@ -610,7 +602,7 @@ def main():
     def form_record(form: str, sched: int, leg: dict, ph: dict) -> dict:
         acc = "complex" if form == "complex" else "real"
         nb = PB.bytes_per_step(ds, value_form=acc)
-        stored = stored_h_bytes(sched, ds)
+        stored = stored_h_bytes(sched, ds, leg.pop("layout_entries"))
         h_s = leg["h_product_ms"] / 1e3
         achieved = nb["h_spmv"] / h_s / 1e9
         x16, rv = plan_sched_x16(sched, ds), plan_sched_real(sched, ds)
@@ -626,7 +618,8 @@ def main():
             "traffic_bytes_per_launch": measured_traffic(sched, wl),
             "stored_bytes_per_launch": stored, "stored_GBps": stored / h_s / 1e9,
             "column_form": ("16-bit columns, one row per lane in slices of 64 rows sorted by "
-                            "length" if all(plan_sliced(sched, d) for d in ds) else
+                            "length" + (" per column tile" if plan_tiled(ds) else "")
+                            if all(plan_sliced(sched, d) for d in ds) else
                             ("16-bit col^row codes" if x16 else "int32 CSR columns") +
                             (", rows padded to groups of eight" if rv or plan_sched_pad(sched, ds)
                              else "")),
@@ -837,7 +830,11 @@ def main():
                      "unit": "GB/s", "frac": head["h_product_frac_of_peak"],
                      "traffic": measured_traffic(sched, wl),
                      "traffic_unit": "bytes per launch (HBM read + write, PMC-calibrated)",
-                     "kernel": (f"blocked column-tiled H product of all {len(ds)} states "
+                     "kernel": (f"sliced column-tiled H product of all {len(ds)} states "
+                                f"(k_spmv_sellt: row blocks of {BLK_ROWS}, column tiles of "
+                                f"{BLK_TILE_BYTES // 1024} KiB, one row per lane, accumulators in LDS)"
+                                if tiled and all(plan_sliced(sched, d) for d in ds) else
+                                f"blocked column-tiled H product of all {len(ds)} states "
                                 f"(k_spmv_blk: row blocks of {BLK_ROWS}, column tiles of "
                                 f"{BLK_TILE_BYTES // 1024} KiB, accumulators in LDS)"
                                 if tiled and all(plan_blocked(sched, d) for d in ds) else

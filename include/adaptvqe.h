@@ -419,6 +419,12 @@ VQE_API int vqe_batch_step_timed(vqe_batch *plan, uint32_t flags, void **events,
  */
 VQE_API int vqe_batch_time_products(vqe_batch *plan, int32_t reps, float *ms_out);
 /*
+ * Entries (pads included) of slot `slot`'s sliced layout (VQE_SPMV_SLICED),
+ * the entries its H product streams per launch; 0 for the other schedules.
+ * VQE_EINVAL for a bad slot.
+ */
+VQE_API int vqe_batch_layout_entries(const vqe_batch *plan, int32_t slot, int64_t *entries_out);
+/*
  * Parameter optimisation (the adaptive loop of Sec. III-D leaves the choice of
  * the angle open).  Enables steps with VQE_STEP_LINESEARCH: after the
  * selection, each state's angle is the theta in [-theta_max, theta_max] that
@@ -554,20 +560,24 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * the lanes differently: results agree to the rounding of FP64 sums. */
 #define VQE_SPMV_PAD 0x10000
 /* VQE_SPMV_SLICED (with VQE_SPMV_LDS and E = 2, 4 or 8 in place of the lanes;
- * batch plans only; states that fit LDS): one row per wave lane.  The plan
- * sorts each block of 2048 rows by length (longest first, ties by row) and
- * stores every 64 consecutive sorted rows as a slice in which lane i's j-th
- * entry sits at ((j / E) * 64 + i) * E + j mod E, so that each load of E
- * entries is contiguous over the wave; a slice is padded to its longest row,
- * rounded up to E, with zero values (a few percent of the entries for the
- * molecular Hamiltonians at 14 qubits).  Columns are stored as 16-bit
- * indices beside the complex values (about nnz * (2 + value bytes) plus 2
- * bytes per row and 8 per slice; plan-owned, rebuilt by vqe_batch_rebind,
- * which then waits for the layout's size).  Each lane sums its row in the
- * CSR's column order.  A state larger than LDS runs the blocked layout with
- * eight lanes (| VQE_SPMV_PREFETCH | VQE_SPMV_X16); single calls
- * (vqe_time_spmv) run the 32-lane pipelined schedule.  Results agree with the
- * other schedules to the rounding of FP64 sums. */
+ * batch plans only): one row per wave lane.  The plan sorts each block of
+ * 2048 rows by length (longest first, ties by row) and stores every 64
+ * consecutive sorted rows as a slice in which lane i's j-th entry sits at
+ * ((j / E) * 64 + i) * E + j mod E, so that each load of E entries is
+ * contiguous over the wave; a slice is padded to its longest row, rounded up
+ * to E, with zero values (a few percent of the entries for the molecular
+ * Hamiltonians at 14 qubits).  Columns are stored as 16-bit indices beside
+ * the complex values (about nnz * (2 + value bytes) plus 2 bytes per row and
+ * 8 per slice; plan-owned, rebuilt by vqe_batch_rebind, which then waits for
+ * the layout's size; vqe_batch_layout_entries reports the entries).  Each
+ * lane sums its row in the CSR's column order.  A state larger than LDS is
+ * cut into the slabs of the blocked layout (2048-row block, 96 KiB column
+ * tile), each slab sorted and sliced by the rows' entries in its tile, with
+ * tile-local codes and 2 bytes per row and tile of row order; one workgroup
+ * per row block walks the tiles with its rows' FP64 sums in LDS, and a row
+ * sums its tiles in ascending order.  Single calls (vqe_time_spmv) run the
+ * 32-lane pipelined schedule.  Results agree with the other schedules to the
+ * rounding of FP64 sums. */
 #define VQE_SPMV_SLICED 0x40000
 /*
  * Time the H product (sigma = S psi with the energy reduction) with the given

@@ -140,6 +140,7 @@ SIGNATURES = {
                                        C.c_void_p, C.c_int32, C.c_double, C.c_void_p]),
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
     "vqe_batch_time_products": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_float)]),
+    "vqe_batch_layout_entries": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
     "vqe_default_schedule": (C.c_int32, [C.POINTER(vqe_csr)]),
@@ -661,6 +662,13 @@ class BatchPlan:
         self.ctx.check(lib().vqe_batch_time_products(self.handle, int(reps), C.byref(ms)),
                        "vqe_batch_time_products")
         return float(ms.value)
+
+    def layout_entries(self, slot: int) -> int:
+        """Entries (pads included) of the slot's sliced layout, else 0."""
+        n = C.c_int64()
+        self.ctx.check(lib().vqe_batch_layout_entries(self.handle, int(slot), C.byref(n)),
+                       "vqe_batch_layout_entries")
+        return int(n.value)
 
     def rebind(self, slot: int, H: DeviceCSR, pool: DevicePool, psi):
         """Bind another state (same size, dtype, pool) to a slot; the slot keeps

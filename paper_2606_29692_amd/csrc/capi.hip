@@ -241,6 +241,8 @@ struct vqe_batch {
     // codes and values; capacity in bytes
     std::vector<void *> blk;
     std::vector<int64_t> blk_cap;
+    // per slot, the entries (pads included) of a sliced layout, else 0
+    std::vector<int64_t> entries;
     // re-optimisation (vqe_batch_reoptimize): descriptors, three product
     // descriptor arrays, tasks, then per slot nine vectors and partials
     char *ro_mem = nullptr;
@@ -383,6 +385,56 @@ int sliced_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     st.sval = p->vre[s];
     st.srow = (const uint16_t *)m;
     st.sslice = (const int2 *)(m + o_sl);
+    p->entries[s] = total;
+    return VQE_OK;
+}
+
+// (Re)build slot s's sliced layout of a column-tiled H (VQE_SPMV_SLICED on a
+// state larger than LDS): the slab tables (row order, slices, slab totals and
+// starts, the total) in prow, the tile-local codes in col16, the values in
+// vre; points the slot's host descriptor at them (the caller uploads it).
+// Waits for the context stream once (the layout's size).
+int sliced_tiled_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
+{
+    vqe_ctx *ctx = p->ctx;
+    SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
+    const int E = sched & 0xff;
+    const int32_t R = SPMV_BLK_ROWS, tc = spmv_blk_tile_cols(H->dtype);
+    const int32_t nt = (int32_t)((H->dim + tc - 1) / tc);
+    const int64_t nb = (H->dim + R - 1) / R, nslab = nb * nt;
+    const size_t o_sl = vqe_align((size_t)nslab * R * sizeof(uint16_t));
+    const size_t o_tot = o_sl + vqe_align((size_t)nslab * SPMV_SLICES_PER_BLOCK * sizeof(int2));
+    const size_t o_base = o_tot + vqe_align((size_t)nslab * sizeof(int64_t));
+    const size_t o_all = o_base + vqe_align((size_t)nslab * sizeof(int64_t));
+    int rc = grow(p, &p->prow[s], &p->prow_cap[s], (int64_t)(o_all + sizeof(int64_t)), "slab tables", s);
+    if (rc)
+        return rc;
+    char *m = (char *)p->prow[s];
+    launch_sellt_layout(H, nt, tc, E, (uint16_t *)m, (int2 *)(m + o_sl), (int64_t *)(m + o_tot),
+                        (int64_t *)(m + o_base), (int64_t *)(m + o_all), ctx->stream);
+    VQE_LAUNCH_CHECK(ctx);
+    int64_t total = 0;
+    VQE_HIP(ctx, hipMemcpyAsync(&total, m + o_all, sizeof(total), hipMemcpyDeviceToHost, ctx->stream));
+    VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (total < 0)
+        return vqe_fail(ctx, VQE_EHIP, "sliced layout of slot %d: bad size", s);
+    const int64_t n = total > 0 ? total : 1;
+    if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], n * 2, "slice codes", s)) ||
+        (rc = grow(p, &p->vre[s], &p->vre_cap[s], n * (int64_t)vqe_elem_bytes(H->dtype), "slice values", s)))
+        return rc;
+    launch_sellt_fill(H, nt, tc, E, (const uint16_t *)m, (const int2 *)(m + o_sl),
+                      (const int64_t *)(m + o_base), (uint16_t *)p->col16[s], p->vre[s], ctx->stream);
+    VQE_LAUNCH_CHECK(ctx);
+    st.scode = (const uint16_t *)p->col16[s];
+    st.sval = p->vre[s];
+    st.srow = (const uint16_t *)m;
+    st.sslice = (const int2 *)(m + o_sl);
+    st.boff = (const int64_t *)(m + o_base);
+    st.blk_rows = R;
+    st.tile_cols = tc;
+    st.ntiles = nt;
+    st.nblocks = (int32_t)nb;
+    p->entries[s] = total;
     return VQE_OK;
 }
 
@@ -1146,14 +1198,17 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         v->assign(B, 0);
     p->blk.assign(B, nullptr);
     p->blk_cap.assign(B, 0);
+    p->entries.assign(B, 0);
     bool any16 = false;
     for (int s = 0; s < B; s++) {
         if (!(lanes[s] & (VQE_SPMV_X16 | VQE_SPMV_BLOCKED | VQE_SPMV_SLICED)))
             continue;
         any16 = true;
-        const int rc16 = (lanes[s] & VQE_SPMV_BLOCKED)  ? blocked_fill(p, s, items[s].H)
-                         : (lanes[s] & VQE_SPMV_SLICED) ? sliced_fill(p, s, items[s].H, lanes[s])
-                                                        : codes_fill(p, s, items[s].H, lanes[s]);
+        const bool sl = (lanes[s] & VQE_SPMV_SLICED) != 0, bl = (lanes[s] & VQE_SPMV_BLOCKED) != 0;
+        const int rc16 = sl && bl ? sliced_tiled_fill(p, s, items[s].H, lanes[s])
+                         : bl     ? blocked_fill(p, s, items[s].H)
+                         : sl     ? sliced_fill(p, s, items[s].H, lanes[s])
+                                  : codes_fill(p, s, items[s].H, lanes[s]);
         if (rc16) {
             vqe_batch_destroy(p);
             return rc16;
@@ -1223,7 +1278,11 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
     ss->shift = it->H->diag_shift;
     TaylorState *ts = reinterpret_cast<TaylorState *>(p->image.data() + p->o_tay) + slot;
     ts->psi = it->psi;
-    if (sched & VQE_SPMV_BLOCKED) {
+    if ((sched & VQE_SPMV_BLOCKED) && (sched & VQE_SPMV_SLICED)) {
+        rc = sliced_tiled_fill(p, slot, it->H, sched);
+        if (rc)
+            return rc;
+    } else if (sched & VQE_SPMV_BLOCKED) {
         rc = blocked_fill(p, slot, it->H);
         if (rc)
             return rc;
@@ -1297,6 +1356,16 @@ extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
     if (n_events == 3)
         return enqueue_step3(p, flags, ev);
     return enqueue_step(p, flags, ev);
+}
+
+extern "C" int vqe_batch_layout_entries(const vqe_batch *p, int32_t slot, int64_t *entries_out)
+{
+    if (!p || !entries_out)
+        return VQE_EINVAL;
+    if (slot < 0 || slot >= p->B)
+        return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_layout_entries: bad slot %d", slot);
+    *entries_out = p->entries[slot];
+    return VQE_OK;
 }
 
 extern "C" int vqe_batch_time_products(vqe_batch *p, int32_t reps, float *ms_out)

@@ -1881,6 +1881,262 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
     }
 }
 
+// ------------------------------------------------------------------ sliced, column-tiled
+// VQE_SPMV_SLICED on a state larger than LDS: the slabs of the blocked layout
+// (a block of SPMV_BLK_ROWS rows against one column tile of
+// SPMV_BLK_TILE_BYTES) are each sorted and sliced like the sliced layout, by
+// the rows' segment lengths in the tile.  srow[slab * R + i] is the
+// block-local row at sorted position i of the slab; sslice[slab *
+// SPMV_SLICES_PER_BLOCK + k] = (start relative to the slab's boff[slab],
+// entries per lane); codes are tile-local (col - t * tile_cols), pads code
+// tile_cols (the staged tile's zero element).  One workgroup per row block
+// walks the tiles with its rows' FP64 sums in LDS, as the blocked product.
+
+// Layout step 1: per (row block, tile), the row's entries in the tile; one
+// thread per row (tiles in turn; columns ascending).
+__global__ void __launch_bounds__(256)
+k_sellt_count(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int64_t dim,
+              int32_t nt, int32_t tc, int32_t R, uint16_t *__restrict__ cnt)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= dim)
+        return;
+    const int64_t b = r / R, i = r - b * R;
+    int k = rowptr[r];
+    const int k1 = rowptr[r + 1];
+    for (int t = 0; t < nt; t++) {
+        const int k2 = first_col_at_least(col, k, k1, (int64_t)(t + 1) * tc);
+        cnt[(b * nt + t) * R + i] = (uint16_t)(k2 - k);
+        k = k2;
+    }
+}
+
+// Step 2: one workgroup per slab sorts the block's rows by their entries in
+// the tile (longest first, ties by row; in place: the counts become the row
+// order) and writes the slab's slices (start in the slab, length rounded up
+// to E) and its total entries.
+__global__ void __launch_bounds__(1024)
+k_sellt_sort(int64_t dim, int32_t nt, int E, uint16_t *__restrict__ cnt_row,
+             int2 *__restrict__ sslice, int64_t *__restrict__ stot)
+{
+    constexpr int R = SPMV_BLK_ROWS;
+    __shared__ uint32_t key[R];
+    const int tid = threadIdx.x;
+    const int64_t slab = blockIdx.x;
+    const int64_t r0 = (slab / nt) * R;
+    const int n = (int)(dim - r0 < R ? dim - r0 : R);
+    uint16_t *c = cnt_row + slab * R;
+    for (int i = tid; i < R; i += 1024)
+        key[i] = i < n ? ((0xffffu - (uint32_t)c[i]) << 16) | (uint32_t)i : 0xffffffffu;
+    __syncthreads();
+    for (int k = 2; k <= R; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < R; i += 1024) {
+                const int q = i ^ j;
+                if (q > i) {
+                    const uint32_t a = key[i], b = key[q];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[q] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = tid; i < n; i += 1024)
+        c[i] = (uint16_t)(key[i] & 0xffffu);
+    if (tid == 0) {
+        int at = 0;
+        for (int k = 0; k < SPMV_SLICES_PER_BLOCK; k++) {
+            int len = 0;
+            if (k * VQE_WAVE < n) {
+                len = (int)(0xffffu - (key[k * VQE_WAVE] >> 16));
+                len = (len + E - 1) / E * E;
+            }
+            sslice[slab * SPMV_SLICES_PER_BLOCK + k] = make_int2(at, len);
+            at += len * VQE_WAVE;
+        }
+        stot[slab] = at;
+    }
+}
+
+// Step 3: the slabs' starts (exclusive prefix of their totals) and the
+// layout's total entries; one workgroup.
+__global__ void __launch_bounds__(1024)
+k_sellt_scan(const int64_t *__restrict__ stot, int64_t nslab, int64_t *__restrict__ sbase,
+             int64_t *__restrict__ total)
+{
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (nslab + 1023) / 1024;
+    const int64_t lo = (int64_t)tid * per < nslab ? (int64_t)tid * per : nslab;
+    const int64_t hi = lo + per < nslab ? lo + per : nslab;
+    int64_t sum = 0;
+    for (int64_t j = lo; j < hi; j++)
+        sum += stot[j];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t at = part[tid] - sum;
+    for (int64_t j = lo; j < hi; j++) {
+        sbase[j] = at;
+        at += stot[j];
+    }
+    if (tid == 1023)
+        *total = part[1023];
+}
+
+// Step 4: codes and values, one wave per slice (empty slices return).
+template <int DT>
+__global__ void __launch_bounds__(64)
+k_sellt_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+             const void *__restrict__ val, int64_t dim, int32_t nt, int32_t tc, int E,
+             const uint16_t *__restrict__ srow, const int2 *__restrict__ sslice,
+             const int64_t *__restrict__ sbase, uint16_t *__restrict__ code, void *__restrict__ sval)
+{
+    using T = typename Elem<DT>::T;
+    constexpr int R = SPMV_BLK_ROWS;
+    const int64_t q = blockIdx.x;
+    const int2 sl = sslice[q];
+    if (sl.y == 0)
+        return;
+    const int64_t slab = q / SPMV_SLICES_PER_BLOCK;
+    const int k = (int)(q - slab * SPMV_SLICES_PER_BLOCK);
+    const int64_t b = slab / nt;
+    const int t = (int)(slab - b * nt);
+    const int64_t r0 = b * R;
+    const int n = (int)(dim - r0 < R ? dim - r0 : R);
+    const int lane = threadIdx.x;
+    const int i = k * VQE_WAVE + lane;
+    const int64_t c_lo = (int64_t)t * tc;
+    int k0 = 0, len = 0;
+    if (i < n) {
+        const int64_t row = r0 + srow[slab * R + i];
+        const int a = rowptr[row], e = rowptr[row + 1];
+        k0 = first_col_at_least(col, a, e, c_lo);
+        len = first_col_at_least(col, k0, e, c_lo + tc) - k0;
+    }
+    T *out = reinterpret_cast<T *>(sval);
+    const T *in = reinterpret_cast<const T *>(val);
+    const int64_t base = sbase[slab] + sl.x;
+    for (int j = 0; j < sl.y; j++) {
+        const int64_t at = base + ((int64_t)(j / E) * VQE_WAVE + lane) * E + j % E;
+        code[at] = j < len ? (uint16_t)(col[k0 + j] - c_lo) : (uint16_t)tc;
+        out[at] = j < len ? in[k0 + j] : T{};
+    }
+}
+
+// The product: one workgroup per (state, row block); per tile with entries,
+// the tile staged in LDS (and its zero element), each wave takes the slab's
+// slices in turn, every lane sums its row's segment with D groups of E
+// entries in flight and adds it to the row's FP64 sums in LDS (each row once
+// per slab, tiles in ascending order).
+template <int DT, int E, int D>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
+k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0)
+        return;
+    const SpmvState st = states[task.x];
+    if (VQE_SKIP(st))
+        return;
+    using T = typename Elem<DT>::T;
+    constexpr int R = SPMV_BLK_ROWS;
+    extern __shared__ unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t dim = st.dim;
+    const int tc = st.tile_cols, nt = st.ntiles;
+    const int b = task.y;
+    const int64_t r0 = (int64_t)b * R;
+    const int n = (int)(dim - r0 < R ? dim - r0 : R);
+    double2 *s_acc = reinterpret_cast<double2 *>(smem);
+    T *s_x = reinterpret_cast<T *>(smem + (size_t)R * sizeof(double2));
+    const T *__restrict__ psi = reinterpret_cast<const T *>(st.psi);
+    const uint16_t *__restrict__ code = st.scode;
+    const T *__restrict__ val = reinterpret_cast<const T *>(st.sval);
+    for (int i = tid; i < n; i += 1024)
+        s_acc[i] = make_double2(0.0, 0.0);
+    if (tid == 0)
+        s_x[tc] = T{};
+    constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
+    for (int t = 0; t < nt; t++) {
+        const int64_t slab = (int64_t)b * nt + t;
+        const sell_v2i *sls = reinterpret_cast<const sell_v2i *>(st.sslice) + slab * SPMV_SLICES_PER_BLOCK;
+        // the longest slice first: a tile with no entries in this block is skipped
+        if (__builtin_amdgcn_readfirstlane(gmem(sls)[0].y) == 0)
+            continue;
+        const int64_t c_lo = (int64_t)t * tc;
+        const int w = (int)(dim - c_lo < tc ? dim - c_lo : tc);
+        __syncthreads();      // every wave is done with the previous tile
+        stage_lds<8>(s_x, psi + c_lo, w, tid);
+        __syncthreads();
+        const int64_t base = gmem(st.boff)[slab];
+        for (int k = wid; k < SPMV_SLICES_PER_BLOCK; k += 16) {
+            const sell_v2i sl = gmem(sls)[k];
+            const int ng = __builtin_amdgcn_readfirstlane(sl.y) / E;
+            if (ng == 0)
+                break;     // slices are longest first
+            const int i = k * VQE_WAVE + lane;
+            const int64_t at = base + __builtin_amdgcn_readfirstlane(sl.x) + lane * E;
+            double are = 0.0, aim = 0.0;
+            SellGroup<DT, E> g[D];
+#pragma unroll
+            for (int d = 0; d < D; d++)
+                g[d].load(code, val, at + (int64_t)(d < ng ? d : ng - 1) * STEP);
+            int q = 0;
+            for (; q + D <= ng; q += D) {
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    g[d].use(s_x, are, aim);
+                    const int nx = q + D + d < ng ? q + D + d : ng - 1;
+                    g[d].load(code, val, at + (int64_t)nx * STEP);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < D; d++)
+                if (q + d < ng)
+                    g[d].use(s_x, are, aim);
+            if (i < n) {
+                const int rl = gmem(st.srow)[slab * R + i];
+                double2 a = s_acc[rl];
+                a.x += are;
+                a.y += aim;
+                s_acc[rl] = a;
+            }
+        }
+    }
+    __syncthreads();
+    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
+    for (int i = tid; i < n; i += 1024) {
+        const double2 a = s_acc[i];
+        Elem<DT>::st(st.sigma, r0 + i, a);
+        energy_terms(ldg(psi, r0 + i), a.x, a.y, e_re, e_im, e_n2);
+    }
+    __shared__ double s_part[16][3];
+    e_re = wave_sum(e_re);
+    e_im = wave_sum(e_im);
+    e_n2 = wave_sum(e_n2);
+    if (lane == 0) {
+        s_part[wid][0] = e_re;
+        s_part[wid][1] = e_im;
+        s_part[wid][2] = e_n2;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double v = 0.0;
+        for (int q = 0; q < 16; q++)
+            v += s_part[q][tid];
+        gmem(st.partials)[(int64_t)b * 3 + tid] = v;
+    }
+}
+
 int32_t spmv_blk_tile_cols(int dtype) { return (int32_t)(SPMV_BLK_TILE_BYTES / vqe_elem_bytes(dtype)); }
 
 size_t spmv_blk_lds(int dtype)
@@ -1929,9 +2185,40 @@ static void launch_blk_dt(int sched, const SpmvState *states, const int2 *tasks,
     }
 }
 
+// Sliced schedules of column-tiled states: E entries per lane and load group,
+// D groups in flight (FP64 values: half as many, the registers).
+template <int DT, int E, int D>
+static void launch_sellt_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s)
+{
+    const size_t lds = (size_t)SPMV_BLK_ROWS * sizeof(double2) +
+                       (size_t)(spmv_blk_tile_cols(DT) + 1) * vqe_elem_bytes(DT);
+    auto k = k_spmv_sellt<DT, E, D>;
+    (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k<<<grid, 1024, lds, s>>>(states, tasks);
+}
+
+template <int DT>
+static void launch_sellt_dt(int sched, const SpmvState *states, const int2 *tasks, unsigned grid,
+                            hipStream_t s)
+{
+    constexpr bool W = DT == VQE_C128;
+    switch (sched & 0xff) {
+    case 2: launch_sellt_t<DT, 2, W ? 2 : 4>(states, tasks, grid, s); break;
+    case 8: launch_sellt_t<DT, 8, W ? 1 : 2>(states, tasks, grid, s); break;
+    default: launch_sellt_t<DT, 4, W ? 2 : 3>(states, tasks, grid, s); break;
+    }
+}
+
 void launch_spmv_blk(int dtype, int sched, const SpmvState *states, const int2 *tasks,
                      unsigned grid, hipStream_t s)
 {
+    if (sched & VQE_SPMV_SLICED) {
+        if (dtype == VQE_C128)
+            launch_sellt_dt<VQE_C128>(sched, states, tasks, grid, s);
+        else
+            launch_sellt_dt<VQE_C64>(sched, states, tasks, grid, s);
+        return;
+    }
     if (dtype == VQE_C128)
         launch_blk_dt<VQE_C128>(sched, states, tasks, grid, s);
     else
@@ -1973,6 +2260,30 @@ void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, 
     const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
     k_sell_sort<<<(unsigned)nb, 1024, 0, s>>>(H->rowptr, H->dim, E, srow, slen);
     k_sell_scan<<<1, 64, 0, s>>>(slen, nb * SPMV_SLICES_PER_BLOCK, sslice, total);
+}
+
+void launch_sellt_layout(const vqe_csr *H, int32_t nt, int32_t tc, int E, uint16_t *srow,
+                         int2 *sslice, int64_t *stot, int64_t *sbase, int64_t *total, hipStream_t s)
+{
+    const int64_t nb = (H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS, nslab = nb * nt;
+    k_sellt_count<<<(unsigned)((H->dim + 255) / 256), 256, 0, s>>>(H->rowptr, H->col, H->dim, nt, tc,
+                                                                  SPMV_BLK_ROWS, srow);
+    k_sellt_sort<<<(unsigned)nslab, 1024, 0, s>>>(H->dim, nt, E, srow, sslice, stot);
+    k_sellt_scan<<<1, 1024, 0, s>>>(stot, nslab, sbase, total);
+}
+
+void launch_sellt_fill(const vqe_csr *H, int32_t nt, int32_t tc, int E, const uint16_t *srow,
+                       const int2 *sslice, const int64_t *sbase, uint16_t *code, void *val,
+                       hipStream_t s)
+{
+    const int64_t nb = (H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS;
+    const unsigned g = (unsigned)(nb * nt * SPMV_SLICES_PER_BLOCK);
+    if (H->dtype == VQE_C128)
+        k_sellt_fill<VQE_C128><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, nt, tc, E, srow,
+                                                sslice, sbase, code, val);
+    else
+        k_sellt_fill<VQE_C64><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, nt, tc, E, srow,
+                                               sslice, sbase, code, val);
 }
 
 void launch_sell_fill(const vqe_csr *H, int E, const uint16_t *srow, const int2 *sslice,
@@ -2147,10 +2458,10 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
 int vqe_batch_schedule(const vqe_csr *H, int sched)
 {
     const bool big = H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES;
-    // a sliced schedule runs a state larger than LDS in the blocked layout
-    // with eight lanes and two groups per lane
+    // a sliced schedule runs a state larger than LDS in the slabs of the
+    // blocked layout, each sorted and sliced
     if ((sched & VQE_SPMV_SLICED) && big)
-        sched = 8 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16;
+        return (sched & (0xff | VQE_SPMV_LDS | VQE_SPMV_SLICED)) | VQE_SPMV_TILED | VQE_SPMV_BLOCKED;
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
     if (big && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) && H->dim <= ((int64_t)1 << 30)) {
         // the real-value form keeps the column-tiled CSR (16-bit col ^ row

@@ -1,6 +1,7 @@
 """Registers larger than LDS at 18 and 20 qubits: the blocked column-tiled H
 product (per (row block, column tile) slabs, tile-local 16-bit codes,
-accumulators in LDS), FP32 storage against the FP64 oracle.
+accumulators in LDS) and its sliced form (each slab's rows sorted into
+64-row slices, one row per lane), FP32 storage against the FP64 oracle.
 
 * 18 qubits (262,144 rows, about 1.2e8 entries per H): sigma = H psi on every
   row and the energy (Eq. 1) for JW and BK systems with seeded complex start
@@ -56,9 +57,13 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+S = B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
+
+
 @pytest.mark.parametrize("sched", [8 | P, 16 | P, 32 | P, 16 | P | B.VQE_SPMV_DEEP,
                                    8 | P | B.VQE_SPMV_DEEP, 8 | P | B.VQE_SPMV_DEEP | B.VQE_SPMV_X16,
-                                   64 | P | B.VQE_SPMV_X16, 4 | P, 4 | P | B.VQE_SPMV_X16])
+                                   64 | P | B.VQE_SPMV_X16, 4 | P, 4 | P | B.VQE_SPMV_X16,
+                                   2 | S, 4 | S, 8 | S])
 def test_blocked_18_qubits_sigma_energy(ctx, systems18, sched):
     pools = PB.PoolCache(ctx, matrix_free=True)
     ds, psis = [], []
@@ -120,7 +125,8 @@ def test_blocked_18_qubits_adaptive_steps(ctx, systems18):
         assert abs(g_o[K[t]]) >= np.abs(g_o).max() * (1 - 1e-5)
 
 
-def test_blocked_20_qubits_sector_rows(ctx):
+@pytest.mark.parametrize("sched", [16 | P, 2 | S])
+def test_blocked_20_qubits_sector_rows(ctx, sched):
     sy = vs.make_system(vs.SystemSpec(20, 10, "jw", False, vs.system_seed(200, 0)), with_pool=False)
     sy.pool = vs.shared_pool(20, 10, "jw")
     pools = PB.PoolCache(ctx, matrix_free=True)
@@ -128,8 +134,8 @@ def test_blocked_20_qubits_sector_rows(ctx):
     d = PB.device_system(ctx, sy, "c64", pools)
     p = vs.complex_start_state(sy).astype(np.complex64)
     d.psi.copy_(torch.from_numpy(p))
-    plan = PB.make_batch(ctx, [d], schedules=[16 | P])
-    print("20 qubits: step", flush=True)
+    plan = PB.make_batch(ctx, [d], schedules=[sched])
+    print(f"20 qubits, schedule {sched}: step", flush=True)
     plan.step(update=False)
     e = host(plan.energies)[:3].copy()
     sg = host(plan.sigma[0]).astype(np.complex128)
