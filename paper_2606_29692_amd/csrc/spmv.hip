@@ -1064,6 +1064,8 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
     using T = typename Elem<DT>::T;
     extern __shared__ unsigned char smem[];
     T *s_x = reinterpret_cast<T *>(smem);
+    // FP32 storage: the block's results gather in LDS after the state
+    float2 *s_sig = reinterpret_cast<float2 *>(smem + (size_t)(st.dim + 1) * sizeof(T));
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t dim = st.dim;
     stage_lds<8>(s_x, reinterpret_cast<const T *>(st.psi), dim, tid);
@@ -1113,9 +1115,18 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
                     g[d].use(s_x, are, aim);
         }
         if (on) {
-            Elem<DT>::st(st.sigma, row, make_double2(are, aim));
+            if constexpr (DT == VQE_C64)
+                s_sig[row - r0] = make_float2((float)are, (float)aim);
+            else
+                Elem<DT>::st(st.sigma, row, make_double2(are, aim));
             energy_terms(s_x[row], are, aim, e_re, e_im, e_n2);
         }
+    }
+    if constexpr (DT == VQE_C64) {
+        // the block's results leave in row order
+        __syncthreads();
+        for (int i = tid; i < n; i += 1024)
+            stg(reinterpret_cast<float2 *>(st.sigma), r0 + i, s_sig[i]);
     }
     __shared__ double s_part[16][3];
     e_re = wave_sum(e_re);
@@ -1812,6 +1823,10 @@ template <int DT, int E, int D>
 static void launch_sell_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
                           size_t lds)
 {
+    // the state (with its zero element; lds counts it with the row pointers
+    // of the other LDS schedules) and, in FP32 storage, a block of results
+    lds = lds - (SPMV_LDS_ROWS + 1) * sizeof(int32_t) +
+          (DT == VQE_C64 ? SPMV_LDS_ROWS * sizeof(float2) : 0);
     auto k = k_spmv_sell<DT, E, D>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);
