@@ -575,7 +575,9 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * tile), each slab sorted and sliced by the rows' entries in its tile, with
  * tile-local codes and 2 bytes per row and tile of row order; one workgroup
  * per row block walks the tiles with its rows' FP64 sums in LDS, and a row
- * sums its tiles in ascending order.  Single calls (vqe_time_spmv) run the
+ * sums its tiles in ascending order; there VQE_SPMV_DEEP keeps the next
+ * tile's loads in flight while a tile is multiplied (ignored for states that
+ * fit LDS).  Single calls (vqe_time_spmv) run the
  * 32-lane pipelined schedule.  Results agree with the other schedules to the
  * rounding of FP64 sums. */
 #define VQE_SPMV_SLICED 0x40000

@@ -2051,7 +2051,7 @@ k_sellt_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col
 // slices in turn, every lane sums its row's segment with D groups of E
 // entries in flight and adds it to the row's FP64 sums in LDS (each row once
 // per slab, tiles in ascending order).
-template <int DT, int E, int D>
+template <int DT, int E, int D, bool PF>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
 {
@@ -2080,17 +2080,48 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     if (tid == 0)
         s_x[tc] = T{};
     constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
+    // A tile is loaded into registers (16 bytes per thread and chunk) and
+    // written to LDS between the tiles' barriers; with PF the next tile's
+    // loads are issued while the current tile is multiplied.  A tile's bytes
+    // are a multiple of 16 (dim and the tile width are even) and start
+    // 16-byte aligned.
+    constexpr int SP = (SPMV_BLK_TILE_BYTES / 16 + 1023) / 1024;
+    vqe_v4f pre[SP];
+    auto fetch = [&](int t) {
+        const int64_t c_lo = (int64_t)t * tc;
+        const int64_t nbytes = (dim - c_lo < tc ? dim - c_lo : tc) * (int64_t)sizeof(T);
+        const vqe_v4f *src = reinterpret_cast<const vqe_v4f *>(psi + c_lo);
+#pragma unroll
+        for (int u = 0; u < SP; u++) {
+            const int c = tid + 1024 * u;
+            if ((int64_t)c * 16 < nbytes)
+                pre[u] = gmem(src)[c];
+        }
+        return nbytes;
+    };
+    int64_t staged = PF ? fetch(0) : 0;
     for (int t = 0; t < nt; t++) {
         const int64_t slab = (int64_t)b * nt + t;
         const sell_v2i *sls = reinterpret_cast<const sell_v2i *>(st.sslice) + slab * SPMV_SLICES_PER_BLOCK;
-        // the longest slice first: a tile with no entries in this block is skipped
-        if (__builtin_amdgcn_readfirstlane(gmem(sls)[0].y) == 0)
+        // the longest slice first: without PF a tile with no entries in this
+        // block is skipped
+        const bool empty = __builtin_amdgcn_readfirstlane(gmem(sls)[0].y) == 0;
+        if (!PF && empty)
             continue;
-        const int64_t c_lo = (int64_t)t * tc;
-        const int w = (int)(dim - c_lo < tc ? dim - c_lo : tc);
+        if (!PF)
+            staged = fetch(t);
         __syncthreads();      // every wave is done with the previous tile
-        stage_lds<8>(s_x, psi + c_lo, w, tid);
+#pragma unroll
+        for (int u = 0; u < SP; u++) {
+            const int c = tid + 1024 * u;
+            if ((int64_t)c * 16 < staged)
+                reinterpret_cast<vqe_v4f *>(s_x)[c] = pre[u];
+        }
         __syncthreads();
+        if (PF && t + 1 < nt)
+            staged = fetch(t + 1);
+        if (empty)
+            continue;
         const int64_t base = gmem(st.boff)[slab];
         for (int k = wid; k < SPMV_SLICES_PER_BLOCK; k += 16) {
             const sell_v2i sl = gmem(sls)[k];
@@ -2203,11 +2234,12 @@ static void launch_blk_dt(int sched, const SpmvState *states, const int2 *tasks,
 // Sliced schedules of column-tiled states: E entries per lane and load group,
 // D groups in flight (FP64 values: half as many, the registers).
 template <int DT, int E, int D>
-static void launch_sellt_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s)
+static void launch_sellt_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
+                           bool pf)
 {
     const size_t lds = (size_t)SPMV_BLK_ROWS * sizeof(double2) +
                        (size_t)(spmv_blk_tile_cols(DT) + 1) * vqe_elem_bytes(DT);
-    auto k = k_spmv_sellt<DT, E, D>;
+    auto k = pf ? k_spmv_sellt<DT, E, D, true> : k_spmv_sellt<DT, E, D, false>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);
 }
@@ -2217,10 +2249,12 @@ static void launch_sellt_dt(int sched, const SpmvState *states, const int2 *task
                             hipStream_t s)
 {
     constexpr bool W = DT == VQE_C128;
+    // VQE_SPMV_DEEP: the next column tile's loads in flight during each tile
+    const bool pf = (sched & VQE_SPMV_DEEP) != 0;
     switch (sched & 0xff) {
-    case 2: launch_sellt_t<DT, 2, W ? 2 : 4>(states, tasks, grid, s); break;
-    case 8: launch_sellt_t<DT, 8, W ? 1 : 2>(states, tasks, grid, s); break;
-    default: launch_sellt_t<DT, 4, W ? 2 : 3>(states, tasks, grid, s); break;
+    case 2: launch_sellt_t<DT, 2, W ? 2 : 4>(states, tasks, grid, s, pf); break;
+    case 8: launch_sellt_t<DT, 8, W ? 1 : 2>(states, tasks, grid, s, pf); break;
+    default: launch_sellt_t<DT, 4, W ? 2 : 3>(states, tasks, grid, s, pf); break;
     }
 }
 
@@ -2420,6 +2454,9 @@ bool vqe_valid_schedule(int sched)
     case 2 | VQE_SPMV_LDS | VQE_SPMV_SLICED:
     case 4 | VQE_SPMV_LDS | VQE_SPMV_SLICED:
     case 8 | VQE_SPMV_LDS | VQE_SPMV_SLICED:
+    case 2 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP:
+    case 4 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP:
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP:
         return true;
     default:
         return false;
@@ -2476,7 +2513,8 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
     // a sliced schedule runs a state larger than LDS in the slabs of the
     // blocked layout, each sorted and sliced
     if ((sched & VQE_SPMV_SLICED) && big)
-        return (sched & (0xff | VQE_SPMV_LDS | VQE_SPMV_SLICED)) | VQE_SPMV_TILED | VQE_SPMV_BLOCKED;
+        return (sched & (0xff | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP)) | VQE_SPMV_TILED |
+               VQE_SPMV_BLOCKED;
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
     if (big && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) && H->dim <= ((int64_t)1 << 30)) {
         // the real-value form keeps the column-tiled CSR (16-bit col ^ row

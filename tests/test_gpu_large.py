@@ -63,7 +63,7 @@ S = B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
 @pytest.mark.parametrize("sched", [8 | P, 16 | P, 32 | P, 16 | P | B.VQE_SPMV_DEEP,
                                    8 | P | B.VQE_SPMV_DEEP, 8 | P | B.VQE_SPMV_DEEP | B.VQE_SPMV_X16,
                                    64 | P | B.VQE_SPMV_X16, 4 | P, 4 | P | B.VQE_SPMV_X16,
-                                   2 | S, 4 | S, 8 | S])
+                                   2 | S, 4 | S, 8 | S, 2 | S | B.VQE_SPMV_DEEP])
 def test_blocked_18_qubits_sigma_energy(ctx, systems18, sched):
     pools = PB.PoolCache(ctx, matrix_free=True)
     ds, psis = [], []
@@ -125,7 +125,7 @@ def test_blocked_18_qubits_adaptive_steps(ctx, systems18):
         assert abs(g_o[K[t]]) >= np.abs(g_o).max() * (1 - 1e-5)
 
 
-@pytest.mark.parametrize("sched", [16 | P, 2 | S])
+@pytest.mark.parametrize("sched", [16 | P, 2 | S, 2 | S | B.VQE_SPMV_DEEP])
 def test_blocked_20_qubits_sector_rows(ctx, sched):
     sy = vs.make_system(vs.SystemSpec(20, 10, "jw", False, vs.system_seed(200, 0)), with_pool=False)
     sy.pool = vs.shared_pool(20, 10, "jw")

@@ -25,6 +25,8 @@ SCHED_R = SCHED_X16 | B.VQE_SPMV_REAL
 # one row per lane, each (row block, column tile) slab sorted and sliced
 SCHED_S = 2 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
 SCHED_S4 = 4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
+# and the next column tile's loads in flight while a tile is multiplied
+SCHED_SD = SCHED_S | B.VQE_SPMV_DEEP
 
 
 @pytest.fixture(scope="module")
@@ -70,7 +72,8 @@ def oracle_run(system, thetas, K):
 
 
 @pytest.mark.parametrize("matrix_free,sched", [(False, SCHED), (True, SCHED), (True, SCHED_X16),
-                                                (True, SCHED_R), (True, SCHED_S), (False, SCHED_S4)])
+                                                (True, SCHED_R), (True, SCHED_S), (False, SCHED_S4),
+                                                (True, SCHED_SD)])
 def test_tiled_fp64_14_qubits(ctx, matrix_free, sched):
     specs = [vs.SystemSpec(14, 6, m, False, vs.system_seed(60, i)) for i, m in enumerate(["jw", "bk"])]
     systems = [vs.make_system(s) for s in specs]
@@ -84,7 +87,7 @@ def test_tiled_fp64_14_qubits(ctx, matrix_free, sched):
         assert np.linalg.norm(psi[i] - tr.psi) <= 1e-12 * np.linalg.norm(tr.psi)
 
 
-@pytest.mark.parametrize("sched", [SCHED, SCHED_X16, SCHED_R, SCHED_S, SCHED_S4])
+@pytest.mark.parametrize("sched", [SCHED, SCHED_X16, SCHED_R, SCHED_S, SCHED_S4, SCHED_SD])
 def test_tiled_fp32_16_qubits(ctx, sched):
     specs = [vs.SystemSpec(16, 8, "jw", False, vs.system_seed(61, i)) for i in range(2)]
     systems = [vs.make_system(s) for s in specs]
@@ -98,7 +101,7 @@ def test_tiled_fp32_16_qubits(ctx, sched):
     assert de < 1e-6 and dg < 1e-5 and fid > 0.999999
 
 
-@pytest.mark.parametrize("sched", [SCHED, SCHED_X16, SCHED_R, SCHED_S])
+@pytest.mark.parametrize("sched", [SCHED, SCHED_X16, SCHED_R, SCHED_S, SCHED_SD])
 def test_tiled_rebind(ctx, sched):
     """Slot 0 rebound to another Hamiltonian of the same size: its tile
     bounds are rebuilt, and the energy matches that system's own plan."""
