@@ -187,9 +187,8 @@ def test_matrix_free_alone_vs_mixed_and_graph(ctx):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_complex_states_screen_vs_oracle(ctx, dtype):
     """States with imaginary parts (seeded complex start states): the
-    matrix-free screen, which sums a real-valued generator's gradient over the
-    real parts and then the imaginary parts of psi and sigma, against the
-    oracle's gradients; energies too.  FP64 to 1e-12 relative, FP32 storage
+    matrix-free screen of a plan's default step against the oracle's
+    gradients; energies too.  FP64 to 1e-12 relative, FP32 storage
     within the FP32 bars (|dE| < 1e-6, |dg| < 1e-5)."""
     specs = mixed_specs() + ([vs.SystemSpec(14, 6, "jw", False, 206)] if dtype == "c64" else [])
     systems = [vs.make_system(s) for s in specs]
