@@ -102,9 +102,12 @@ def plan_sched_x16(sched: int, ds) -> bool:
 
 def plan_sched_real(sched: int, ds) -> bool:
     """True when the batch plan streams the real parts of every H (the codes
-    are read and every H is flagged real)."""
+    are read, or the sliced layout of states that fit LDS, and every H is
+    flagged real)."""
     from paper_2606_29692_amd import binding as B
-    return plan_sched_x16(sched, ds) and bool(sched & B.VQE_SPMV_REAL) and all(d.H.real for d in ds)
+    sliced = bool(sched & B.VQE_SPMV_SLICED) and not plan_tiled(ds)
+    return (plan_sched_x16(sched, ds) or sliced) and bool(sched & B.VQE_SPMV_REAL) and \
+        all(d.H.real for d in ds)
 
 
 def plan_tiled(ds) -> bool:
@@ -158,8 +161,9 @@ def stored_h_bytes(sched: int, ds, entries=None) -> int:
             nb = -(-d.H.dim // BLK_ROWS)
             big = d.H.dim * d.psi.element_size() > LDS_STATE_BYTES
             nt = -(-d.H.dim // (BLK_TILE_BYTES // d.psi.element_size())) if big else 1
+            vb = d.H.val.element_size() // (2 if rv else 1)
             tot += 2 * d.H.dim * nt + 8 * nb * nt * (BLK_ROWS // 64 + (1 if big else 0)) + \
-                entries[i] * (2 + d.H.val.element_size()) + 2 * d.H.dim * d.psi.element_size()
+                entries[i] * (2 + vb) + 2 * d.H.dim * d.psi.element_size()
             continue
         if plan_blocked(sched, d):
             tc = BLK_TILE_BYTES // d.psi.element_size()
@@ -618,7 +622,8 @@ def main():
             "traffic_bytes_per_launch": measured_traffic(sched, wl),
             "stored_bytes_per_launch": stored, "stored_GBps": stored / h_s / 1e9,
             "column_form": ("16-bit columns, one row per lane in slices of 64 rows sorted by "
-                            "length" + (" per column tile" if plan_tiled(ds) else "")
+                            "length" + (" per column tile" if plan_tiled(ds) else "") +
+                            (", real values" if rv else "")
                             if all(plan_sliced(sched, d) for d in ds) else
                             ("16-bit col^row codes" if x16 else "int32 CSR columns") +
                             (", rows padded to groups of eight" if rv or plan_sched_pad(sched, ds)

@@ -577,7 +577,11 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * per row block walks the tiles with its rows' FP64 sums in LDS, and a row
  * sums its tiles in ascending order; there VQE_SPMV_DEEP keeps the next
  * tile's loads in flight while a tile is multiplied (ignored for states that
- * fit LDS).  Single calls (vqe_time_spmv) run the
+ * fit LDS).  With VQE_SPMV_REAL (an H flagged real; states that fit LDS) the
+ * slices hold the values' real parts (6 bytes per entry in FP32 storage) and
+ * a state whose imaginary parts are all zero is multiplied in real
+ * arithmetic (checked per workgroup at run time); the sums are the complex
+ * form's, bit for bit.  Single calls (vqe_time_spmv) run the
  * 32-lane pipelined schedule.  Results agree with the other schedules to the
  * rounding of FP64 sums. */
 #define VQE_SPMV_SLICED 0x40000

@@ -375,11 +375,13 @@ int sliced_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     if (total < 0 || total > 0x7fffffffLL)
         return vqe_fail(ctx, VQE_ESIZE, "sliced layout of slot %d: %lld entries", s, (long long)total);
     const int64_t n = total > 0 ? total : 1;
+    const bool real = (sched & VQE_SPMV_REAL) != 0;
+    const int64_t vb = (int64_t)vqe_elem_bytes(H->dtype) / (real ? 2 : 1);
     if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], n * 2, "slice codes", s)) ||
-        (rc = grow(p, &p->vre[s], &p->vre_cap[s], n * (int64_t)vqe_elem_bytes(H->dtype), "slice values", s)))
+        (rc = grow(p, &p->vre[s], &p->vre_cap[s], n * vb, "slice values", s)))
         return rc;
-    launch_sell_fill(H, E, (const uint16_t *)m, (const int2 *)(m + o_sl), (uint16_t *)p->col16[s],
-                     p->vre[s], ctx->stream);
+    launch_sell_fill(H, E, real, (const uint16_t *)m, (const int2 *)(m + o_sl),
+                     (uint16_t *)p->col16[s], p->vre[s], ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
     st.scode = (const uint16_t *)p->col16[s];
     st.sval = p->vre[s];

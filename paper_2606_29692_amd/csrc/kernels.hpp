@@ -304,9 +304,10 @@ void launch_pad_layout(const vqe_csr *H, int32_t *prow, uint16_t *code, void *vp
 // sslice [same] and *total, the entries of all slices (device int64) ...
 void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, int2 *sslice,
                         int64_t *total, hipStream_t s);
-// ... then, with room for total entries, the codes and values
-void launch_sell_fill(const vqe_csr *H, int E, const uint16_t *srow, const int2 *sslice,
-                      uint16_t *code, void *val, hipStream_t s);
+// ... then, with room for total entries, the codes and the values (their real
+// parts with real)
+void launch_sell_fill(const vqe_csr *H, int E, bool real, const uint16_t *srow,
+                      const int2 *sslice, uint16_t *code, void *val, hipStream_t s);
 // sliced layout of a column-tiled state (VQE_SPMV_SLICED on a state larger
 // than LDS): per slab of the blocked layout (nt tiles of tc columns) the row
 // order srow [slabs * SPMV_BLK_ROWS] (first the rows' entry counts), the

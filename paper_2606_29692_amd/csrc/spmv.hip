@@ -966,14 +966,16 @@ __global__ void k_sell_scan(const int32_t *__restrict__ slen, int64_t ns, int2 *
     *total = at;
 }
 
-// Codes and values of one slice per wave (pads: column dim, value zero).
-template <int DT>
+// Codes and values of one slice per wave (pads: column dim, value zero); RV:
+// the values' real parts (an operator whose entries are all real).
+template <int DT, bool RV>
 __global__ void __launch_bounds__(64)
 k_sell_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
             const void *__restrict__ val, int64_t dim, int E, const uint16_t *__restrict__ srow,
             const int2 *__restrict__ sslice, uint16_t *__restrict__ code, void *__restrict__ sval)
 {
     using T = typename Elem<DT>::T;
+    using V = typename ValOf<DT, RV>::T;
     const int64_t c = blockIdx.x;
     const int64_t r0 = (c / SPMV_SLICES_PER_BLOCK) * SPMV_LDS_ROWS;
     const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
@@ -987,23 +989,63 @@ k_sell_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
         k0 = rowptr[row];
         len = rowptr[row + 1] - (int32_t)k0;
     }
-    T *out = reinterpret_cast<T *>(sval);
+    V *out = reinterpret_cast<V *>(sval);
     const T *in = reinterpret_cast<const T *>(val);
     for (int j = 0; j < sl.y; j++) {
         const int64_t at = (int64_t)sl.x + ((int64_t)(j / E) * VQE_WAVE + lane) * E + j % E;
         code[at] = j < len ? (uint16_t)col[k0 + j] : (uint16_t)dim;
-        out[at] = j < len ? in[k0 + j] : T{};
+        if constexpr (RV)
+            out[at] = j < len ? in[k0 + j].x : V{};
+        else
+            out[at] = j < len ? in[k0 + j] : V{};
     }
 }
 
-// E consecutive entries of one lane: their codes (two per word) and values.
-template <int DT, int E>
+// One entry's product added to the row's sums in turn (each product with its
+// own FMA): complex value and state; real value, complex state; real value,
+// real state (FP64 real parts).
+template <typename V, typename X>
+__device__ __forceinline__ void sell_fma(const V a, const X x, double &are, double &aim)
+{
+    const double ar = (double)a.x, ai = (double)a.y, xr = (double)x.x, xi = (double)x.y;
+    are = fma(ar, xr, are);
+    are = fma(-ai, xi, are);
+    aim = fma(ar, xi, aim);
+    aim = fma(ai, xr, aim);
+}
+template <typename X>
+__device__ __forceinline__ void sell_fma(const float a, const X x, double &are, double &aim)
+{
+    are = fma((double)a, (double)x.x, are);
+    aim = fma((double)a, (double)x.y, aim);
+}
+template <typename X>
+__device__ __forceinline__ void sell_fma(const double a, const X x, double &are, double &aim)
+{
+    are = fma(a, (double)x.x, are);
+    aim = fma(a, (double)x.y, aim);
+}
+__device__ __forceinline__ void sell_fma(const float a, const double x, double &are, double &aim)
+{
+    (void)aim;
+    are = fma((double)a, x, are);
+}
+__device__ __forceinline__ void sell_fma(const double a, const double x, double &are, double &aim)
+{
+    (void)aim;
+    are = fma(a, x, are);
+}
+
+// E consecutive entries of one lane: their codes (two per word) and values
+// (complex, or their real parts with RV).
+template <int DT, int E, bool RV = false>
 struct SellGroup {
     using T = typename Elem<DT>::T;
+    using V = typename ValOf<DT, RV>::T;
     unsigned c[E / 2];
-    T v[E];
+    V v[E];
     __device__ __forceinline__ void load(const uint16_t *__restrict__ code,
-                                         const T *__restrict__ val, int64_t at)
+                                         const V *__restrict__ val, int64_t at)
     {
         if constexpr (E == 2) {
             c[0] = gmem(reinterpret_cast<const unsigned *>(code + at))[0];
@@ -1018,7 +1060,27 @@ struct SellGroup {
             c[2] = w.z;
             c[3] = w.w;
         }
-        if constexpr (DT == VQE_C64) {
+        if constexpr (RV && DT == VQE_C64 && E == 2) {
+            const vqe_v2f a = gmem(reinterpret_cast<const vqe_v2f *>(val + at))[0];
+            v[0] = a.x;
+            v[1] = a.y;
+        } else if constexpr (RV && DT == VQE_C64) {
+#pragma unroll
+            for (int q = 0; q < E / 4; q++) {
+                const vqe_v4f a = gmem(reinterpret_cast<const vqe_v4f *>(val + at))[q];
+                v[4 * q] = a.x;
+                v[4 * q + 1] = a.y;
+                v[4 * q + 2] = a.z;
+                v[4 * q + 3] = a.w;
+            }
+        } else if constexpr (RV) {
+#pragma unroll
+            for (int q = 0; q < E / 2; q++) {
+                const vqe_v2d a = gmem(reinterpret_cast<const vqe_v2d *>(val + at))[q];
+                v[2 * q] = a.x;
+                v[2 * q + 1] = a.y;
+            }
+        } else if constexpr (DT == VQE_C64) {
 #pragma unroll
             for (int q = 0; q < E / 2; q++) {
                 const vqe_v4f a = gmem(reinterpret_cast<const vqe_v4f *>(val + at))[q];
@@ -1031,52 +1093,31 @@ struct SellGroup {
                 v[q] = ldg(val, at + q);
         }
     }
-    // each product added to the row's sums in turn (four FMAs per entry)
-    __device__ __forceinline__ void use(const T *s_x, double &are, double &aim) const
+    // each product added to the row's sums in turn; X: the staged state's
+    // element (complex, or the real parts in FP64)
+    template <typename X>
+    __device__ __forceinline__ void use(const X *s_x, double &are, double &aim) const
     {
 #pragma unroll
-        for (int q = 0; q < E; q++) {
-            const T x = s_x[(q & 1) ? c[q / 2] >> 16 : c[q / 2] & 0xffffu];
-            const double ar = (double)v[q].x, ai = (double)v[q].y;
-            const double xr = (double)x.x, xi = (double)x.y;
-            are = fma(ar, xr, are);
-            are = fma(-ai, xi, are);
-            aim = fma(ar, xi, aim);
-            aim = fma(ai, xr, aim);
-        }
+        for (int q = 0; q < E; q++)
+            sell_fma(v[q], s_x[(q & 1) ? c[q / 2] >> 16 : c[q / 2] & 0xffffu], are, aim);
     }
 };
 
-// One workgroup per (state, block of SPMV_LDS_ROWS rows): the state staged in
-// LDS (plus the zero element), each wave takes the block's slices in turn and
-// keeps D groups of E entries per lane in flight.
-template <int DT, int E, int D>
-__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
-k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+// The slices of one block against the staged state s_x (X: complex, or the
+// real parts in FP64 for a real state); each wave takes the block's slices in
+// turn and keeps D groups of E entries per lane in flight.
+template <int DT, int E, int D, bool RV, typename X>
+__device__ __forceinline__ void sell_rows(const SpmvState &st, int blk, const X *s_x, float2 *s_sig)
 {
-    const int2 t = tasks[blockIdx.x];
-    if (t.x < 0)
-        return;
-    const SpmvState st = states[t.x];
-    if (VQE_SKIP(st))
-        return;
-    const int blk = t.y;
-    using T = typename Elem<DT>::T;
-    extern __shared__ unsigned char smem[];
-    T *s_x = reinterpret_cast<T *>(smem);
-    // FP32 storage: the block's results gather in LDS after the state
-    float2 *s_sig = reinterpret_cast<float2 *>(smem + (size_t)(st.dim + 1) * sizeof(T));
+    using V = typename ValOf<DT, RV>::T;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t dim = st.dim;
-    stage_lds<8>(s_x, reinterpret_cast<const T *>(st.psi), dim, tid);
-    if (tid == 0)
-        s_x[dim] = T{};
-    __syncthreads();
     const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
     const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
     const int ns = (n + VQE_WAVE - 1) / VQE_WAVE;
     const uint16_t *__restrict__ code = st.scode;
-    const T *__restrict__ val = reinterpret_cast<const T *>(st.sval);
+    const V *__restrict__ val = reinterpret_cast<const V *>(st.sval);
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
     for (int k = wid; k < ns; k += 16) {
         // the slice's start and length are uniform over the wave
@@ -1094,7 +1135,7 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
             // every load is issued (past the slice's end it repeats the last
             // group, which is in cache), so no load sits under a branch and
             // each group's wait leaves the later groups' loads in flight
-            SellGroup<DT, E> g[D];
+            SellGroup<DT, E, RV> g[D];
 #pragma unroll
             for (int d = 0; d < D; d++)
                 g[d].load(code, val, at + (int64_t)(d < ng ? d : ng - 1) * STEP);
@@ -1144,6 +1185,46 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
             v += s_part[w][tid];
         gmem(st.partials)[(int64_t)blk * 3 + tid] = v;
     }
+}
+
+// One workgroup per (state, block of SPMV_LDS_ROWS rows): the state staged in
+// LDS (plus the zero element), then the block's slices.  With RV (the real
+// parts of a real H) a state whose imaginary parts are all zero is staged as
+// FP64 real parts and multiplied in real arithmetic; any other state takes
+// the complex staging in the same launch.
+template <int DT, int E, int D, bool RV>
+__global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
+k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
+{
+    const int2 t = tasks[blockIdx.x];
+    if (t.x < 0)
+        return;
+    const SpmvState st = states[t.x];
+    if (VQE_SKIP(st))
+        return;
+    using T = typename Elem<DT>::T;
+    extern __shared__ unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int64_t dim = st.dim;
+    const T *psi = reinterpret_cast<const T *>(st.psi);
+    // FP32 storage: the block's results gather in LDS after the state
+    float2 *s_sig = reinterpret_cast<float2 *>(smem + (size_t)(dim + 1) * sizeof(T));
+    if constexpr (RV) {
+        double *s_xr = reinterpret_cast<double *>(smem);
+        const int cplx = stage_real<8>(s_xr, psi, dim, tid);
+        if (tid == 0)
+            s_xr[dim] = 0.0;
+        if (!__syncthreads_or(cplx)) {
+            sell_rows<DT, E, D, RV>(st, t.y, s_xr, s_sig);
+            return;
+        }
+    }
+    T *s_x = reinterpret_cast<T *>(smem);
+    stage_lds<8>(s_x, psi, dim, tid);
+    if (tid == 0)
+        s_x[dim] = T{};
+    __syncthreads();
+    sell_rows<DT, E, D, RV>(st, t.y, s_x, s_sig);
 }
 
 // Column-tiled variant of the pipelined LDS schedule, for states larger than
@@ -1818,16 +1899,17 @@ static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, c
     }
 }
 
-// Sliced schedules: E entries per lane and load group, D groups in flight.
+// Sliced schedules: E entries per lane and load group, D groups in flight;
+// rv: the real parts of the values (VQE_SPMV_REAL).
 template <int DT, int E, int D>
 static void launch_sell_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
-                          size_t lds)
+                          size_t lds, bool rv)
 {
     // the state (with its zero element; lds counts it with the row pointers
     // of the other LDS schedules) and, in FP32 storage, a block of results
     lds = lds - (SPMV_LDS_ROWS + 1) * sizeof(int32_t) +
           (DT == VQE_C64 ? SPMV_LDS_ROWS * sizeof(float2) : 0);
-    auto k = k_spmv_sell<DT, E, D>;
+    auto k = rv ? k_spmv_sell<DT, E, D, true> : k_spmv_sell<DT, E, D, false>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);
 }
@@ -1840,10 +1922,11 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
         // the sliced layout exists only in batch plans; E = 2, 4 or 8
         // (FP64 values keep half as many groups in flight: the registers)
         constexpr bool W = DT == VQE_C128;
+        const bool rv = (sched & VQE_SPMV_REAL) != 0;
         switch (sched & 0xff) {
-        case 2: launch_sell_t<DT, 2, W ? 2 : 4>(states, tasks, grid, s, lds); return;
-        case 8: launch_sell_t<DT, 8, W ? 1 : 2>(states, tasks, grid, s, lds); return;
-        default: launch_sell_t<DT, 4, W ? 2 : 3>(states, tasks, grid, s, lds); return;
+        case 2: launch_sell_t<DT, 2, W ? 2 : 4>(states, tasks, grid, s, lds, rv); return;
+        case 8: launch_sell_t<DT, 8, W ? 1 : 2>(states, tasks, grid, s, lds, rv); return;
+        default: launch_sell_t<DT, 4, W ? 2 : 3>(states, tasks, grid, s, lds, rv); return;
         }
     }
     constexpr int D = VQE_SPMV_LDS | VQE_SPMV_DEEP;
@@ -2335,17 +2418,14 @@ void launch_sellt_fill(const vqe_csr *H, int32_t nt, int32_t tc, int E, const ui
                                                sslice, sbase, code, val);
 }
 
-void launch_sell_fill(const vqe_csr *H, int E, const uint16_t *srow, const int2 *sslice,
-                      uint16_t *code, void *val, hipStream_t s)
+void launch_sell_fill(const vqe_csr *H, int E, bool real, const uint16_t *srow,
+                      const int2 *sslice, uint16_t *code, void *val, hipStream_t s)
 {
     const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
     const unsigned g = (unsigned)(nb * SPMV_SLICES_PER_BLOCK);
-    if (H->dtype == VQE_C128)
-        k_sell_fill<VQE_C128><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, E, srow, sslice,
-                                               code, val);
-    else
-        k_sell_fill<VQE_C64><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, E, srow, sslice,
-                                              code, val);
+    auto k = H->dtype == VQE_C128 ? (real ? k_sell_fill<VQE_C128, true> : k_sell_fill<VQE_C128, false>)
+                                  : (real ? k_sell_fill<VQE_C64, true> : k_sell_fill<VQE_C64, false>);
+    k<<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, E, srow, sslice, code, val);
 }
 
 void launch_spmv(int dtype, int sched, const SpmvState &single, const SpmvState *states,
@@ -2457,6 +2537,9 @@ bool vqe_valid_schedule(int sched)
     case 2 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP:
     case 4 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP:
     case 8 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP:
+    case 2 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
+    case 4 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
+    case 8 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
         return true;
     default:
         return false;
@@ -2473,7 +2556,9 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
     if (sched & VQE_SPMV_SLICED) {
         if (H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES || H->dim >= 65536)
             return vqe_effective_schedule(H, 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16);
-        return sched & (VQE_SPMV_SLICED | VQE_SPMV_LDS | 0xff);
+        // the real values need an operator flagged real
+        return sched & (VQE_SPMV_SLICED | VQE_SPMV_LDS | 0xff |
+                        ((H->flags & VQE_REAL) ? VQE_SPMV_REAL : 0));
     }
     // four lanes per row exist only in the blocked product of states larger
     // than LDS; elsewhere the same schedule runs with eight

@@ -42,7 +42,8 @@ CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               8 | _L | _P | _D, 8 | _L | _P | _X, 8 | _L | _P | _D | _X, 16 | _L | _P | _X,
               16 | _L | _P | _D | _X, 4 | _L | _P, 4 | _L | _P | _D, 4 | _L | _P | _X,
               # one row per lane, rows sorted by length into slices of 64
-              2 | _L | _S, 4 | _L | _S, 8 | _L | _S, 2 | _L | _S | _D, 4 | _L | _S | _D)
+              2 | _L | _S, 4 | _L | _S, 8 | _L | _S, 2 | _L | _S | _D, 4 | _L | _S | _D,
+              2 | _L | _S | _R, 4 | _L | _S | _R, 8 | _L | _S | _R)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}

@@ -280,7 +280,9 @@ def test_full_size_bench_config(ctx, sched):
                                    B.VQE_SPMV_X16,
                                    2 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
                                    4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
-                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED])
+                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
+                                   4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL,
+                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
@@ -309,7 +311,8 @@ def test_every_spmv_schedule_matches_oracle(ctx, sched):
     plan.close()
 
 
-@pytest.mark.parametrize("sched", [e | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED for e in (2, 4, 8)])
+@pytest.mark.parametrize("sched", [e | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED for e in (2, 4, 8)] +
+                         [4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_sliced_layout_sizes_vs_oracle(ctx, sched, dtype):
     """The sliced layout at register sizes that leave slices and blocks
@@ -523,12 +526,17 @@ def test_real_flag_from_terms(ctx):
             assert B.csr_from_pack(ctx, pack, dt).real == w
 
 
+@pytest.mark.parametrize("layout", ["padded", "sliced"])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_real_values_match_complex_values(ctx, dtype):
+def test_real_values_match_complex_values(ctx, dtype, layout):
     """The real-value form against the complex-value form of the same
-    schedule on the same states: bit for bit in FP32 storage (every product
-    is exact in FP64), to rounding in FP64 storage; both against the oracle."""
+    schedule on the same (real) states: bit for bit in FP32 storage (every
+    product is exact in FP64) and, in the sliced layout (the same sums in the
+    same order), in FP64 storage too; to rounding in FP64 storage with the
+    row-padded layout; both against the oracle."""
     x = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16
+    if layout == "sliced":
+        x = 4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
     specs = [vs.SystemSpec(12, 6, "jw", False, 130), vs.SystemSpec(12, 4, "bk", False, 131),
              vs.SystemSpec(14, 6, "jw", True, 132)]
     systems = [vs.make_system(s) for s in specs]
@@ -547,7 +555,7 @@ def test_real_values_match_complex_values(ctx, dtype):
         plan.close()
     a, b = out[x], out[x | B.VQE_SPMV_REAL]
     np.testing.assert_array_equal(a[3], b[3])
-    if dtype == "c64":
+    if dtype == "c64" or layout == "sliced":
         np.testing.assert_array_equal(a[0], b[0])
         for i in range(3):
             np.testing.assert_array_equal(a[1][i], b[1][i])
