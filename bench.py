@@ -124,6 +124,7 @@ def plan_sched_pad(sched: int, ds) -> bool:
 
 
 BLK_ROWS, BLK_TILE_BYTES = 2048, 96 * 1024     # blocked layout of column-tiled states
+SELLT_ROWS, SELLT_TILE_BYTES = 2040, 128 * 1024  # sliced layout of column-tiled states
 
 
 def plan_sliced(sched: int, d) -> bool:
@@ -158,9 +159,9 @@ def stored_h_bytes(sched: int, ds, entries=None) -> int:
     tot = 0
     for i, d in enumerate(ds):
         if plan_sliced(sched, d):
-            nb = -(-d.H.dim // BLK_ROWS)
             big = d.H.dim * d.psi.element_size() > LDS_STATE_BYTES
-            nt = -(-d.H.dim // (BLK_TILE_BYTES // d.psi.element_size())) if big else 1
+            nb = -(-d.H.dim // (SELLT_ROWS if big else BLK_ROWS))
+            nt = -(-d.H.dim // (SELLT_TILE_BYTES // d.psi.element_size())) if big else 1
             vb = d.H.val.element_size() // (2 if rv else 1)
             tot += 2 * d.H.dim * nt + 8 * nb * nt * (BLK_ROWS // 64 + (1 if big else 0)) + \
                 entries[i] * (2 + vb) + 2 * d.H.dim * d.psi.element_size()
@@ -836,8 +837,8 @@ def main():
                      "traffic": measured_traffic(sched, wl),
                      "traffic_unit": "bytes per launch (HBM read + write, PMC-calibrated)",
                      "kernel": (f"sliced column-tiled H product of all {len(ds)} states "
-                                f"(k_spmv_sellt: row blocks of {BLK_ROWS}, column tiles of "
-                                f"{BLK_TILE_BYTES // 1024} KiB, one row per lane, accumulators in LDS)"
+                                f"(k_spmv_sellt: row blocks of {SELLT_ROWS}, column tiles of "
+                                f"{SELLT_TILE_BYTES // 1024} KiB, one row per lane, accumulators in LDS)"
                                 if tiled and all(plan_sliced(sched, d) for d in ds) else
                                 f"blocked column-tiled H product of all {len(ds)} states "
                                 f"(k_spmv_blk: row blocks of {BLK_ROWS}, column tiles of "

@@ -401,7 +401,7 @@ int sliced_tiled_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     vqe_ctx *ctx = p->ctx;
     SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
     const int E = sched & 0xff;
-    const int32_t R = SPMV_BLK_ROWS, tc = spmv_blk_tile_cols(H->dtype);
+    const int32_t R = SPMV_SELLT_ROWS, tc = spmv_sellt_tile_cols(H->dtype);
     const int32_t nt = (int32_t)((H->dim + tc - 1) / tc);
     const int64_t nb = (H->dim + R - 1) / R, nslab = nb * nt;
     const size_t o_sl = vqe_align((size_t)nslab * R * sizeof(uint16_t));
@@ -738,8 +738,10 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         lanes[s] = vqe_batch_schedule(H, req);
         int64_t nblk = spmv_blocks(H->dim, lanes[s]);
         if (lanes[s] & VQE_SPMV_BLOCKED) {
-            // the layout lives in the slot's own allocation (blocked_fill)
-            nblk = (H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS;
+            // the layout lives in the slot's own buffers (blocked_fill,
+            // sliced_tiled_fill)
+            const int64_t rb = (lanes[s] & VQE_SPMV_SLICED) ? SPMV_SELLT_ROWS : SPMV_BLK_ROWS;
+            nblk = (H->dim + rb - 1) / rb;
         } else if (lanes[s] & VQE_SPMV_TILED) {
             // real-value tiles are twice as wide (real parts in storage precision)
             tcols[s] = (lanes[s] & VQE_SPMV_REAL) ? spmv_tile_cols_real(dtype) : spmv_tile_cols(dtype);
@@ -764,7 +766,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             per.resize(kXcd);
         const int64_t dim = items[s].H->dim;
         if (lanes[s] & VQE_SPMV_BLOCKED) {
-            const int nb = (int)((dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS);
+            const int64_t rb = (lanes[s] & VQE_SPMV_SLICED) ? SPMV_SELLT_ROWS : SPMV_BLK_ROWS;
+            const int nb = (int)((dim + rb - 1) / rb);
             for (int b = 0; b < nb; b++)
                 per[xcd_of[s]].push_back(make_int2(s, b));
             continue;
@@ -1081,7 +1084,8 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         st.nblocks = (int32_t)spmv_blocks(it.H->dim, lanes[s]);
         st.lanes = lanes[s];
         if (lanes[s] & VQE_SPMV_BLOCKED) {
-            st.nblocks = (int32_t)((it.H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS);
+            const int64_t rb = (lanes[s] & VQE_SPMV_SLICED) ? SPMV_SELLT_ROWS : SPMV_BLK_ROWS;
+            st.nblocks = (int32_t)((it.H->dim + rb - 1) / rb);
         } else if (lanes[s] & VQE_SPMV_TILED) {
             st.tptr = (const int32_t *)(D + o_tptr[s]);
             st.tile_part = (double *)(D + o_tpart[s]);

@@ -278,6 +278,8 @@ void launch_tile_bounds(const SpmvState *states, const int2 *tasks, unsigned gri
 // [nb * nt * (R + 1)], scratch blen [nb * nt], slab starts boff [nb * nt + 1],
 // codes and values with room for nnz + 4 nb nt + 4 entries)
 int32_t spmv_blk_tile_cols(int dtype);
+// columns per tile of the sliced column-tiled layout (SPMV_SELLT_TILE_BYTES)
+int32_t spmv_sellt_tile_cols(int dtype);
 size_t spmv_blk_lds(int dtype);
 void launch_spmv_blk(int dtype, int sched, const SpmvState *states, const int2 *tasks,
                      unsigned grid, hipStream_t s);

@@ -1980,10 +1980,10 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
 }
 
 // ------------------------------------------------------------------ sliced, column-tiled
-// VQE_SPMV_SLICED on a state larger than LDS: the slabs of the blocked layout
-// (a block of SPMV_BLK_ROWS rows against one column tile of
-// SPMV_BLK_TILE_BYTES) are each sorted and sliced like the sliced layout, by
-// the rows' segment lengths in the tile.  srow[slab * R + i] is the
+// VQE_SPMV_SLICED on a state larger than LDS: slabs of a block of
+// SPMV_SELLT_ROWS rows against one column tile of SPMV_SELLT_TILE_BYTES are
+// each sorted and sliced like the sliced layout, by the rows' segment lengths
+// in the tile.  srow[slab * R + i] is the
 // block-local row at sorted position i of the slab; sslice[slab *
 // SPMV_SLICES_PER_BLOCK + k] = (start relative to the slab's boff[slab],
 // entries per lane); codes are tile-local (col - t * tile_cols), pads code
@@ -2017,19 +2017,20 @@ __global__ void __launch_bounds__(1024)
 k_sellt_sort(int64_t dim, int32_t nt, int E, uint16_t *__restrict__ cnt_row,
              int2 *__restrict__ sslice, int64_t *__restrict__ stot)
 {
-    constexpr int R = SPMV_BLK_ROWS;
-    __shared__ uint32_t key[R];
+    constexpr int R = SPMV_SELLT_ROWS, RK = 2048;   // rows, keys (a power of two)
+    static_assert(R <= RK && (RK + VQE_WAVE - 1) / VQE_WAVE <= SPMV_SLICES_PER_BLOCK, "block size");
+    __shared__ uint32_t key[RK];
     const int tid = threadIdx.x;
     const int64_t slab = blockIdx.x;
     const int64_t r0 = (slab / nt) * R;
     const int n = (int)(dim - r0 < R ? dim - r0 : R);
     uint16_t *c = cnt_row + slab * R;
-    for (int i = tid; i < R; i += 1024)
+    for (int i = tid; i < RK; i += 1024)
         key[i] = i < n ? ((0xffffu - (uint32_t)c[i]) << 16) | (uint32_t)i : 0xffffffffu;
     __syncthreads();
-    for (int k = 2; k <= R; k <<= 1)
+    for (int k = 2; k <= RK; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < R; i += 1024) {
+            for (int i = tid; i < RK; i += 1024) {
                 const int q = i ^ j;
                 if (q > i) {
                     const uint32_t a = key[i], b = key[q];
@@ -2098,7 +2099,7 @@ k_sellt_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col
              const int64_t *__restrict__ sbase, uint16_t *__restrict__ code, void *__restrict__ sval)
 {
     using T = typename Elem<DT>::T;
-    constexpr int R = SPMV_BLK_ROWS;
+    constexpr int R = SPMV_SELLT_ROWS;
     const int64_t q = blockIdx.x;
     const int2 sl = sslice[q];
     if (sl.y == 0)
@@ -2145,7 +2146,7 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     if (VQE_SKIP(st))
         return;
     using T = typename Elem<DT>::T;
-    constexpr int R = SPMV_BLK_ROWS;
+    constexpr int R = SPMV_SELLT_ROWS;
     extern __shared__ unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t dim = st.dim;
@@ -2168,7 +2169,7 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     // loads are issued while the current tile is multiplied.  A tile's bytes
     // are a multiple of 16 (dim and the tile width are even) and start
     // 16-byte aligned.
-    constexpr int SP = (SPMV_BLK_TILE_BYTES / 16 + 1023) / 1024;
+    constexpr int SP = (SPMV_SELLT_TILE_BYTES / 16 + 1023) / 1024;
     vqe_v4f pre[SP];
     auto fetch = [&](int t) {
         const int64_t c_lo = (int64_t)t * tc;
@@ -2248,7 +2249,9 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
         Elem<DT>::st(st.sigma, r0 + i, a);
         energy_terms(ldg(psi, r0 + i), a.x, a.y, e_re, e_im, e_n2);
     }
-    __shared__ double s_part[16][3];
+    // the waves' energy sums in the tile's space (the tiles are done): the
+    // rows' sums and one tile fill the LDS
+    double (*s_part)[3] = reinterpret_cast<double (*)[3]>(s_x);
     e_re = wave_sum(e_re);
     e_im = wave_sum(e_im);
     e_n2 = wave_sum(e_n2);
@@ -2267,6 +2270,7 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
 }
 
 int32_t spmv_blk_tile_cols(int dtype) { return (int32_t)(SPMV_BLK_TILE_BYTES / vqe_elem_bytes(dtype)); }
+int32_t spmv_sellt_tile_cols(int dtype) { return (int32_t)(SPMV_SELLT_TILE_BYTES / vqe_elem_bytes(dtype)); }
 
 size_t spmv_blk_lds(int dtype)
 {
@@ -2320,8 +2324,8 @@ template <int DT, int E, int D>
 static void launch_sellt_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
                            bool pf)
 {
-    const size_t lds = (size_t)SPMV_BLK_ROWS * sizeof(double2) +
-                       (size_t)(spmv_blk_tile_cols(DT) + 1) * vqe_elem_bytes(DT);
+    const size_t lds = (size_t)SPMV_SELLT_ROWS * sizeof(double2) +
+                       (size_t)(spmv_sellt_tile_cols(DT) + 1) * vqe_elem_bytes(DT);
     auto k = pf ? k_spmv_sellt<DT, E, D, true> : k_spmv_sellt<DT, E, D, false>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);
@@ -2397,9 +2401,9 @@ void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, 
 void launch_sellt_layout(const vqe_csr *H, int32_t nt, int32_t tc, int E, uint16_t *srow,
                          int2 *sslice, int64_t *stot, int64_t *sbase, int64_t *total, hipStream_t s)
 {
-    const int64_t nb = (H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS, nslab = nb * nt;
+    const int64_t nb = (H->dim + SPMV_SELLT_ROWS - 1) / SPMV_SELLT_ROWS, nslab = nb * nt;
     k_sellt_count<<<(unsigned)((H->dim + 255) / 256), 256, 0, s>>>(H->rowptr, H->col, H->dim, nt, tc,
-                                                                  SPMV_BLK_ROWS, srow);
+                                                                  SPMV_SELLT_ROWS, srow);
     k_sellt_sort<<<(unsigned)nslab, 1024, 0, s>>>(H->dim, nt, E, srow, sslice, stot);
     k_sellt_scan<<<1, 1024, 0, s>>>(stot, nslab, sbase, total);
 }
@@ -2408,7 +2412,7 @@ void launch_sellt_fill(const vqe_csr *H, int32_t nt, int32_t tc, int E, const ui
                        const int2 *sslice, const int64_t *sbase, uint16_t *code, void *val,
                        hipStream_t s)
 {
-    const int64_t nb = (H->dim + SPMV_BLK_ROWS - 1) / SPMV_BLK_ROWS;
+    const int64_t nb = (H->dim + SPMV_SELLT_ROWS - 1) / SPMV_SELLT_ROWS;
     const unsigned g = (unsigned)(nb * nt * SPMV_SLICES_PER_BLOCK);
     if (H->dtype == VQE_C128)
         k_sellt_fill<VQE_C128><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, nt, tc, E, srow,

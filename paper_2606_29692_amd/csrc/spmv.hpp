@@ -88,6 +88,12 @@ struct SpmvState {
 #define VQE_SPMV_BLOCKED 0x20000
 #define SPMV_BLK_ROWS 2048
 #define SPMV_BLK_TILE_BYTES (96 * 1024)
+// Sliced column-tiled layout: rows per block (their FP64 sums fill the LDS
+// beside one tile) and tile bytes (a power of two of columns, so that a
+// block, whose rows share their high bits, meets only the tiles its rows'
+// flip masks reach)
+#define SPMV_SELLT_ROWS 2040
+#define SPMV_SELLT_TILE_BYTES (128 * 1024)
 // Sliced layout: slices of one wave's rows per block of SPMV_LDS_ROWS rows.
 #define SPMV_SLICES_PER_BLOCK (SPMV_LDS_ROWS / VQE_WAVE)
 // largest dimension whose column XOR row fits 16 bits
