@@ -340,6 +340,9 @@ def serving_bench(n_requests: int, warm: int, log_fn=log):
         rate = factor * cap
         trace = S.poisson_trace(n_requests, rate, len(systems), seed=int(factor * 10))
         t_cold = time.perf_counter()
+        # the library's default schedules: a tuned sliced layout would be
+        # rebuilt on every rebind of a slot (about 0.15 ms at 14 qubits) on
+        # the launch path, which raised p99 from 2.1 to 3.1 ms at 0.8x
         ex = S.DeviceExecutor(systems, slots_per_group=16, dtype="c64")
         server = S.Server(ex, thetas, budget_bytes=budget)
         resident = server.prewarm()

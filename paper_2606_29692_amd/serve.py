@@ -380,8 +380,11 @@ class DeviceExecutor(Executor):
     def __init__(self, systems: dict, slots_per_group: int = 16, dtype: str = "c64",
                  schedules: dict | None = None, device: int = 0):
         """`systems`: run -> vqe_system.System.  `schedules`: register-size key ->
-        H-product schedule (default: the library's default for the first run
-        of that size, built on the device here)."""
+        H-product schedule, or "tuned" for the autotuner's choice for the first
+        run of that size (cached, else timed here), or None for the library's
+        default for that run.  Every slot's plan-owned layout of H is sized on
+        that first run here, so that binding runs of the same size later does
+        not reallocate while other groups run."""
         import torch
         from . import batch as PB
         from . import binding as B
@@ -419,11 +422,13 @@ class DeviceExecutor(Executor):
             # equals that of the runs later bound to it
             if not probe.H.real:
                 empty.desc.flags &= ~B.VQE_REAL
-            if schedules and key in schedules:
+            if schedules == "tuned":
+                from . import tune as T
+                sched_k = T.schedule_for(ctx, probe, systems=[probe], value_form="any")
+            elif schedules and key in schedules:
                 sched_k = int(schedules[key])
             else:
                 sched_k = B.default_schedule(probe.H)
-            del probe
             sched = [sched_k] * slots_per_group
             states = []
             with torch.cuda.stream(stream):
@@ -431,6 +436,12 @@ class DeviceExecutor(Executor):
                     states.append((empty, pool, torch.zeros(dim, dtype=tdt, device="cuda")))
                 plan = B.BatchPlan(ctx, states, schedules=sched, with_active=True)
                 plan.active.zero_()
+                # size every slot's layout of H on the probe, then unbind
+                for slot in range(slots_per_group):
+                    plan.rebind(slot, probe.H, probe.pool, probe.psi)
+                    plan.rebind(slot, empty, pool, states[slot][2])
+            stream.synchronize()
+            del probe
             pin = dict(pin_memory=True)
             self.group[key] = {"ctx": ctx, "stream": stream, "plan": plan, "pool": pool,
                                "empty": empty, "event": None, "dim": dim,

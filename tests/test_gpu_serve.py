@@ -22,6 +22,11 @@ from paper_2606_29692_amd import serve as S  # noqa: E402
 SCHED = {(8, 4, "jw"): 16,
          (10, 4, "jw"): 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 | B.VQE_SPMV_REAL,
          (12, 8, "jw"): 32 | B.VQE_SPMV_LDS}
+# the sliced layout (rebuilt from the device on every rebind of a slot; with
+# real values at 10 qubits)
+SLICED = B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
+SCHED_SLICED = {(8, 4, "jw"): 4 | SLICED, (10, 4, "jw"): 4 | SLICED | B.VQE_SPMV_REAL,
+                (12, 8, "jw"): 2 | SLICED}
 
 
 def make_runs():
@@ -34,8 +39,8 @@ def make_runs():
     return systems, thetas
 
 
-def serve(systems, thetas, reqs, budget=10**12, slots=4):
-    ex = S.DeviceExecutor(systems, slots_per_group=slots, dtype="c64", schedules=SCHED)
+def serve(systems, thetas, reqs, budget=10**12, slots=4, sched=SCHED):
+    ex = S.DeviceExecutor(systems, slots_per_group=slots, dtype="c64", schedules=sched)
     server = S.Server(ex, thetas, budget_bytes=budget)
     out = server.run_trace([S.Request(q.rid, q.run, q.t_arrival) for q in reqs])
     torch.cuda.synchronize()
@@ -50,31 +55,34 @@ def by_run(reqs):
     return d
 
 
-def test_alone_vs_mixed_and_eviction():
+@pytest.mark.parametrize("sched", [SCHED, SCHED_SLICED], ids=["csr", "sliced"])
+def test_alone_vs_mixed_and_eviction(sched):
     systems, thetas = make_runs()
     trace = S.poisson_trace(150, rate=3000.0, n_runs=len(systems), seed=5)
-    mixed, psi_mixed, srv = serve(systems, thetas, trace)
+    mixed, psi_mixed, srv = serve(systems, thetas, trace, sched=sched)
     assert all(q.t_done >= q.t_arrival for q in mixed)
     res_mixed = by_run(mixed)
     # alone: each of three runs with only its own requests
     for r in (0, 4, 8):
         mine = [q for q in trace if q.run == r]
-        alone, psi_alone, _ = serve({r: systems[r]}, {r: thetas[r]}, mine)
+        alone, psi_alone, _ = serve({r: systems[r]}, {r: thetas[r]}, mine, sched=sched)
         print(f"run {r}: {len(mine)} requests", flush=True)
         assert by_run(alone)[r] == res_mixed[r]
         np.testing.assert_array_equal(psi_alone[r], psi_mixed[r])
     # a budget that holds only a few runs: evictions and resumes, same results
-    small, psi_small, srv_small = serve(systems, thetas, trace, budget=srv.ex.fixed_bytes() + 6_000_000)
+    small, psi_small, srv_small = serve(systems, thetas, trace, budget=srv.ex.fixed_bytes() + 6_000_000,
+                                        sched=sched)
     assert srv_small.evictions > 0
     assert by_run(small) == res_mixed
     for r in systems:
         np.testing.assert_array_equal(psi_small[r], psi_mixed[r])
 
 
-def test_served_runs_match_oracle():
+@pytest.mark.parametrize("sched", [SCHED, SCHED_SLICED, "tuned"], ids=["csr", "sliced", "tuned"])
+def test_served_runs_match_oracle(sched):
     systems, thetas = make_runs()
     trace = S.poisson_trace(120, rate=3000.0, n_runs=len(systems), seed=9)
-    out, psi, _ = serve(systems, thetas, trace)
+    out, psi, _ = serve(systems, thetas, trace, sched=sched)
     res = by_run(out)
     for r in (2, 5):
         s = systems[r]
