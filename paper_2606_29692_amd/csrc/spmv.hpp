@@ -65,14 +65,18 @@ struct SpmvState {
     const int32_t *brp;
     const int64_t *boff;
     int32_t blk_rows;
-    // sliced layout (VQE_SPMV_SLICED; states that fit LDS): per block of
-    // SPMV_LDS_ROWS rows, srow[block start + i] is the block-local row taken
-    // by sorted position i (rows by length, longest first), and slice k of
-    // block b (sorted positions 64k ... 64k + 63) starts at entry
+    // sliced layout (VQE_SPMV_SLICED), for a state that fits LDS: per block
+    // of SPMV_LDS_ROWS rows, srow[block start + i] is the block-local row
+    // taken by sorted position i (rows by length, longest first), and slice k
+    // of block b (sorted positions 64k ... 64k + 63) starts at entry
     // sslice[b * SPMV_SLICES_PER_BLOCK + k].x with .y entries per lane; lane
     // i's j-th entry is at start + ((j / E) * 64 + i) * E + j % E, with the
-    // absolute 16-bit column in scode and the value in sval (pads: column dim,
-    // value zero)
+    // absolute 16-bit column in scode and the value (or its real part with
+    // VQE_SPMV_REAL) in sval (pads: column dim, value zero).  For a
+    // column-tiled state the same per slab (SPMV_SELLT_ROWS-row block b,
+    // tile t; slab = b * ntiles + t): srow[slab * SPMV_SELLT_ROWS + i], the
+    // slices' starts relative to the slab's start boff[slab], tile-local
+    // columns (pads: tile_cols)
     const uint16_t *scode;
     const void *sval;
     const uint16_t *srow;
