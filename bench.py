@@ -310,11 +310,13 @@ def plain_fp64_path(ctx, system, n_req: int):
     return taylor_rate, step_rate, lat_stats(lat), lat_stats(slat)
 
 
-def serving_bench(n_requests: int, warm: int, log_fn=log):
+def serving_bench(n_requests: int, warm: int, log_fn=log, schedules: str = "tuned"):
     """Config C5: 64 resident runs with register sizes drawn from {8,...,16};
     Poisson request streams at 0.8x and 2x the capacity of the plain
     sequential FP64 single-request path; continuous batching (FP32 storage,
-    slot groups per register size, one stream each) against that path."""
+    slot groups per register size, one stream each) against that path.
+    schedules: "default" (the library's per register size) or "tuned" (the
+    autotuner's; sliced ones bind a layout built per run at admission)."""
     import torch
     import vqe_system as vs
     from paper_2606_29692_amd import binding as B
@@ -334,16 +336,15 @@ def serving_bench(n_requests: int, warm: int, log_fn=log):
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.5 * free)
     out = {"runs": len(systems), "register_sizes": sizes, "requests": n_requests,
+           "schedules": schedules,
            "warmup_requests": warm, "sequential_fp64_capacity_per_s": cap,
            "budget_bytes": budget}
     for factor in (0.8, 2.0):
         rate = factor * cap
         trace = S.poisson_trace(n_requests, rate, len(systems), seed=int(factor * 10))
         t_cold = time.perf_counter()
-        # the library's default schedules: a tuned sliced layout would be
-        # rebuilt on every rebind of a slot (about 0.15 ms at 14 qubits) on
-        # the launch path, which raised p99 from 2.1 to 3.1 ms at 0.8x
-        ex = S.DeviceExecutor(systems, slots_per_group=16, dtype="c64")
+        ex = S.DeviceExecutor(systems, slots_per_group=16, dtype="c64",
+                              schedules="tuned" if schedules == "tuned" else None)
         server = S.Server(ex, thetas, budget_bytes=budget)
         resident = server.prewarm()
         torch.cuda.synchronize()
@@ -532,6 +533,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests per serving point (0: skip the serving measurement)")
     ap.add_argument("--serve-warmup", type=int, default=256)
+    ap.add_argument("--serve-schedules", choices=["default", "tuned"], default="tuned",
+                    help="H product schedules of the serving executor: the autotuner's per "
+                         "register size (sliced ones bind a layout built once per run), or the "
+                         "library's defaults")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): states are "
@@ -796,7 +801,8 @@ def main():
     serving = None
     if args.serve_requests > 0:
         serving = serving_bench(args.serve_requests, min(args.serve_warmup,
-                                                         args.serve_requests // 4))
+                                                         args.serve_requests // 4),
+                                schedules=args.serve_schedules)
 
     hnnz = ds[0].H.nnz
     tiled = plan_tiled(ds)

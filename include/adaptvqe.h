@@ -398,6 +398,35 @@ VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
  */
 VQE_API int vqe_batch_rebind(vqe_batch *plan, int32_t slot, const vqe_batch_item *item);
 /*
+ * A sliced layout (VQE_SPMV_SLICED) of one operator, built once so that batch
+ * slots can point to it: a serving loop builds it when it admits a run, and
+ * binding the run to a slot later (vqe_batch_rebind_layout) copies no data
+ * and waits for nothing.  vqe_layout_create builds the layout of H (the same
+ * content as a slot's own: the sort, slices, codes and values of the Eq. 1
+ * product) for `schedule` (0: the default) as a batch plan would resolve it
+ * for H; it waits for the context stream once, and the contents are
+ * written on that stream (ready for work enqueued there afterwards).
+ * VQE_ENOTSUP when that schedule has no sliced layout for H, VQE_EINVAL for
+ * a bad operator or schedule, VQE_ENOMEM when the device memory runs out.
+ * The layout belongs to the caller (vqe_layout_destroy, which waits for the
+ * context stream), must outlive every slot bound to it and be destroyed
+ * before its context; it reads H only while it is built.
+ * vqe_layout_bytes: its device bytes.
+ */
+typedef struct vqe_layout vqe_layout;
+VQE_API int vqe_layout_create(vqe_ctx *ctx, const vqe_csr *H, int32_t schedule, vqe_layout **out);
+VQE_API int vqe_layout_destroy(vqe_layout *layout);
+VQE_API int64_t vqe_layout_bytes(const vqe_layout *layout);
+/*
+ * vqe_batch_rebind with a layout built for item->H (the same vqe_csr
+ * descriptor) and the slot's schedule: the slot points to the layout instead
+ * of rebuilding its own.  VQE_EINVAL if the layout was built for another
+ * operator, size, dtype or schedule.  The results equal those of
+ * vqe_batch_rebind, bit for bit.
+ */
+VQE_API int vqe_batch_rebind_layout(vqe_batch *plan, int32_t slot, const vqe_batch_item *item,
+                                    const vqe_layout *layout);
+/*
  * The same step while recording caller-created HIP events (hipEvent_t) on the
  * context stream.  n_events = 3: [0] before the H products, [1] after them,
  * [2] at the end of the step (eager, or with VQE_STEP_GRAPH the H-product

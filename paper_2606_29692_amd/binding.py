@@ -141,6 +141,10 @@ SIGNATURES = {
     "vqe_batch_workspace_bytes": (C.c_int64, [C.c_void_p]),
     "vqe_batch_time_products": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_float)]),
     "vqe_batch_layout_entries": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
+    "vqe_layout_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "vqe_layout_destroy": (C.c_int, [C.c_void_p]),
+    "vqe_layout_bytes": (C.c_int64, [C.c_void_p]),
+    "vqe_batch_rebind_layout": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "vqe_time_spmv": (C.c_int, [C.c_void_p, C.POINTER(vqe_csr), C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
     "vqe_default_schedule": (C.c_int32, [C.POINTER(vqe_csr)]),
@@ -201,8 +205,8 @@ class Context:
         if st != VQE_OK:
             raise VqeError(st, f"vqe_create: {lib().vqe_strerror(st).decode()}")
         self.handle = h
-        # batch plans made on this context: destroyed before the context,
-        # since a plan uses its context's stream until it is destroyed
+        # batch plans and sliced layouts made on this context: destroyed
+        # before the context, since they use its stream until destroyed
         self._plans = weakref.WeakSet()
 
     def check(self, status: int, what: str):
@@ -550,6 +554,33 @@ def default_schedule(H: DeviceCSR) -> int:
     return int(lib().vqe_default_schedule(C.byref(H.desc)))
 
 
+class Layout:
+    """A sliced layout of one operator for a batch schedule (vqe_layout_create),
+    to be bound to plan slots with BatchPlan.rebind(..., layout=...)."""
+
+    def __init__(self, ctx: Context, H: DeviceCSR, schedule: int):
+        h = C.c_void_p()
+        ctx.check(lib().vqe_layout_create(ctx.handle, C.addressof(H.desc), int(schedule), C.byref(h)),
+                  "vqe_layout_create")
+        self.ctx, self.H, self.handle = ctx, H, h
+        ctx._plans.add(self)
+
+    def nbytes(self) -> int:
+        return int(lib().vqe_layout_bytes(self.handle)) if self.handle else 0
+
+    def close(self):
+        if self.handle:
+            if getattr(self.ctx, "handle", None):     # as BatchPlan.close
+                lib().vqe_layout_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class BatchPlan:
     """One adaptive step for B states per launch sequence (optionally a HIP graph).
 
@@ -670,19 +701,25 @@ class BatchPlan:
                        "vqe_batch_layout_entries")
         return int(n.value)
 
-    def rebind(self, slot: int, H: DeviceCSR, pool: DevicePool, psi):
+    def rebind(self, slot: int, H: DeviceCSR, pool: DevicePool, psi, layout: "Layout | None" = None):
         """Bind another state (same size, dtype, pool) to a slot; the slot keeps
-        its sigma buffer."""
+        its sigma buffer.  With `layout` (built for H and this slot's schedule)
+        the slot points to it instead of rebuilding its own layout of H."""
         it = vqe_batch_item()
         it.H = C.addressof(H.desc)
         it.pool = C.addressof(pool.desc)
         it.psi = psi.data_ptr()
         it.sigma = self.sigma[slot].data_ptr()
         it.spmv_schedule = int(self.schedules[slot]) if self.schedules is not None else 0
-        self.ctx.check(lib().vqe_batch_rebind(self.handle, int(slot), C.byref(it)), "vqe_batch_rebind")
+        if layout is None:
+            self.ctx.check(lib().vqe_batch_rebind(self.handle, int(slot), C.byref(it)),
+                           "vqe_batch_rebind")
+        else:
+            self.ctx.check(lib().vqe_batch_rebind_layout(self.handle, int(slot), C.byref(it),
+                                                         layout.handle), "vqe_batch_rebind_layout")
         # keep the bound objects alive while the slot refers to them
         self._bound = getattr(self, "_bound", {})
-        self._bound[slot] = (H, pool, psi)
+        self._bound[slot] = (H, pool, psi, layout)
 
     def gradients(self, s: int):
         M = self.states[s][1].M
@@ -694,7 +731,11 @@ class BatchPlan:
 
     def close(self):
         if getattr(self, "handle", None):
-            lib().vqe_batch_destroy(self.handle)
+            # a context closed first (finalisers of a garbage cycle run in any
+            # order, after its weak references are cleared) has taken its
+            # stream: the plan is then left to the process's end
+            if getattr(self.ctx, "handle", None):
+                lib().vqe_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -285,9 +285,8 @@ std::vector<T> interleave(const std::vector<std::vector<T>> &per, const T &pad)
 
 // Grow one of slot s's plan-owned buffers to at least `need` bytes (the
 // caller rebuilds the contents).
-int grow(vqe_batch *p, void **buf, int64_t *cap, int64_t need, const char *what, int s)
+int grow_ctx(vqe_ctx *ctx, void **buf, int64_t *cap, int64_t need, const char *what, int s)
 {
-    vqe_ctx *ctx = p->ctx;
     if (*cap >= need)
         return VQE_OK;
     if (*buf) {
@@ -304,6 +303,18 @@ int grow(vqe_batch *p, void **buf, int64_t *cap, int64_t need, const char *what,
     *cap = need;
     return VQE_OK;
 }
+
+int grow(vqe_batch *p, void **buf, int64_t *cap, int64_t need, const char *what, int s)
+{
+    return grow_ctx(p->ctx, buf, cap, need, what, s);
+}
+
+// Buffers of a sliced layout (the slot's own, or a vqe_layout's): the slice
+// or slab tables, the codes and the values, with their capacities in bytes.
+struct SellBufs {
+    void **meta, **code, **val;
+    int64_t *meta_cap, *code_cap, *val_cap;
+};
 
 // (Re)build slot s's plan-owned forms of H for its schedule -- the 16-bit
 // column codes, and with VQE_SPMV_REAL the real parts of the values, with
@@ -347,25 +358,24 @@ int codes_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     return VQE_OK;
 }
 
-// (Re)build slot s's sliced layout of H (VQE_SPMV_SLICED) in its plan-owned
-// buffers -- the slice table (row order, slice lengths and starts, the total)
-// in prow, the codes in col16, the values in vre -- and point the slot's host
-// descriptor at it (the caller uploads the descriptor).  The codes and values
-// are sized from the table, so this waits for the context stream once.
-int sliced_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
+// Build the sliced layout of H (VQE_SPMV_SLICED) in the buffers b -- the
+// slice table (row order, slice lengths and starts, the total) in meta, the
+// codes in code, the values in val -- and point st's layout fields at it.
+// The codes and values are sized from the table, so this waits for the
+// context stream once.  s names the slot in messages (-1: a vqe_layout).
+int sliced_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs &b, SpmvState &st,
+                 int64_t *entries, int s)
 {
-    vqe_ctx *ctx = p->ctx;
-    SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
     const int E = sched & 0xff;
     const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
     const int64_t ns = nb * SPMV_SLICES_PER_BLOCK;
     const size_t o_len = vqe_align((size_t)H->dim * sizeof(uint16_t));
     const size_t o_sl = o_len + vqe_align((size_t)ns * sizeof(int32_t));
     const size_t o_tot = o_sl + vqe_align((size_t)ns * sizeof(int2));
-    int rc = grow(p, &p->prow[s], &p->prow_cap[s], (int64_t)(o_tot + sizeof(int64_t)), "slice table", s);
+    int rc = grow_ctx(ctx, b.meta, b.meta_cap, (int64_t)(o_tot + sizeof(int64_t)), "slice table", s);
     if (rc)
         return rc;
-    char *m = (char *)p->prow[s];
+    char *m = (char *)*b.meta;
     launch_sell_layout(H, E, (uint16_t *)m, (int32_t *)(m + o_len), (int2 *)(m + o_sl),
                        (int64_t *)(m + o_tot), ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
@@ -377,29 +387,26 @@ int sliced_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     const int64_t n = total > 0 ? total : 1;
     const bool real = (sched & VQE_SPMV_REAL) != 0;
     const int64_t vb = (int64_t)vqe_elem_bytes(H->dtype) / (real ? 2 : 1);
-    if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], n * 2, "slice codes", s)) ||
-        (rc = grow(p, &p->vre[s], &p->vre_cap[s], n * vb, "slice values", s)))
+    if ((rc = grow_ctx(ctx, b.code, b.code_cap, n * 2, "slice codes", s)) ||
+        (rc = grow_ctx(ctx, b.val, b.val_cap, n * vb, "slice values", s)))
         return rc;
     launch_sell_fill(H, E, real, (const uint16_t *)m, (const int2 *)(m + o_sl),
-                     (uint16_t *)p->col16[s], p->vre[s], ctx->stream);
+                     (uint16_t *)*b.code, *b.val, ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
-    st.scode = (const uint16_t *)p->col16[s];
-    st.sval = p->vre[s];
+    st.scode = (const uint16_t *)*b.code;
+    st.sval = *b.val;
     st.srow = (const uint16_t *)m;
     st.sslice = (const int2 *)(m + o_sl);
-    p->entries[s] = total;
+    *entries = total;
     return VQE_OK;
 }
 
-// (Re)build slot s's sliced layout of a column-tiled H (VQE_SPMV_SLICED on a
-// state larger than LDS): the slab tables (row order, slices, slab totals and
-// starts, the total) in prow, the tile-local codes in col16, the values in
-// vre; points the slot's host descriptor at them (the caller uploads it).
-// Waits for the context stream once (the layout's size).
-int sliced_tiled_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
+// The same for a column-tiled H (VQE_SPMV_SLICED on a state larger than LDS):
+// the slab tables (row order, slices, slab totals and starts, the total) in
+// meta, the tile-local codes in code, the values in val.
+int sliced_tiled_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs &b, SpmvState &st,
+                       int64_t *entries, int s)
 {
-    vqe_ctx *ctx = p->ctx;
-    SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
     const int E = sched & 0xff;
     const int32_t R = SPMV_SELLT_ROWS, tc = spmv_sellt_tile_cols(H->dtype);
     const int32_t nt = (int32_t)((H->dim + tc - 1) / tc);
@@ -408,10 +415,10 @@ int sliced_tiled_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     const size_t o_tot = o_sl + vqe_align((size_t)nslab * SPMV_SLICES_PER_BLOCK * sizeof(int2));
     const size_t o_base = o_tot + vqe_align((size_t)nslab * sizeof(int64_t));
     const size_t o_all = o_base + vqe_align((size_t)nslab * sizeof(int64_t));
-    int rc = grow(p, &p->prow[s], &p->prow_cap[s], (int64_t)(o_all + sizeof(int64_t)), "slab tables", s);
+    int rc = grow_ctx(ctx, b.meta, b.meta_cap, (int64_t)(o_all + sizeof(int64_t)), "slab tables", s);
     if (rc)
         return rc;
-    char *m = (char *)p->prow[s];
+    char *m = (char *)*b.meta;
     launch_sellt_layout(H, nt, tc, E, (uint16_t *)m, (int2 *)(m + o_sl), (int64_t *)(m + o_tot),
                         (int64_t *)(m + o_base), (int64_t *)(m + o_all), ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
@@ -421,14 +428,14 @@ int sliced_tiled_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     if (total < 0)
         return vqe_fail(ctx, VQE_EHIP, "sliced layout of slot %d: bad size", s);
     const int64_t n = total > 0 ? total : 1;
-    if ((rc = grow(p, &p->col16[s], &p->col16_cap[s], n * 2, "slice codes", s)) ||
-        (rc = grow(p, &p->vre[s], &p->vre_cap[s], n * (int64_t)vqe_elem_bytes(H->dtype), "slice values", s)))
+    if ((rc = grow_ctx(ctx, b.code, b.code_cap, n * 2, "slice codes", s)) ||
+        (rc = grow_ctx(ctx, b.val, b.val_cap, n * (int64_t)vqe_elem_bytes(H->dtype), "slice values", s)))
         return rc;
     launch_sellt_fill(H, nt, tc, E, (const uint16_t *)m, (const int2 *)(m + o_sl),
-                      (const int64_t *)(m + o_base), (uint16_t *)p->col16[s], p->vre[s], ctx->stream);
+                      (const int64_t *)(m + o_base), (uint16_t *)*b.code, *b.val, ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
-    st.scode = (const uint16_t *)p->col16[s];
-    st.sval = p->vre[s];
+    st.scode = (const uint16_t *)*b.code;
+    st.sval = *b.val;
     st.srow = (const uint16_t *)m;
     st.sslice = (const int2 *)(m + o_sl);
     st.boff = (const int64_t *)(m + o_base);
@@ -436,8 +443,20 @@ int sliced_tiled_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
     st.tile_cols = tc;
     st.ntiles = nt;
     st.nblocks = (int32_t)nb;
-    p->entries[s] = total;
+    *entries = total;
     return VQE_OK;
+}
+
+// (Re)build slot s's sliced layout (either form) in its plan-owned buffers --
+// tables in prow, codes in col16, values in vre -- and point the slot's host
+// descriptor at it (the caller uploads the descriptor).
+int sliced_fill(vqe_batch *p, int s, const vqe_csr *H, int sched)
+{
+    SpmvState &st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv)[s];
+    const SellBufs b{&p->prow[s], &p->col16[s], &p->vre[s], &p->prow_cap[s], &p->col16_cap[s],
+                     &p->vre_cap[s]};
+    return (sched & VQE_SPMV_BLOCKED) ? sliced_tiled_build(p->ctx, H, sched, b, st, &p->entries[s], s)
+                                      : sliced_build(p->ctx, H, sched, b, st, &p->entries[s], s);
 }
 
 // (Re)build slot s's blocked layout of H (VQE_SPMV_BLOCKED) in its plan-owned
@@ -739,7 +758,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
         int64_t nblk = spmv_blocks(H->dim, lanes[s]);
         if (lanes[s] & VQE_SPMV_BLOCKED) {
             // the layout lives in the slot's own buffers (blocked_fill,
-            // sliced_tiled_fill)
+            // sliced_fill)
             const int64_t rb = (lanes[s] & VQE_SPMV_SLICED) ? SPMV_SELLT_ROWS : SPMV_BLK_ROWS;
             nblk = (H->dim + rb - 1) / rb;
         } else if (lanes[s] & VQE_SPMV_TILED) {
@@ -1211,10 +1230,9 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
             continue;
         any16 = true;
         const bool sl = (lanes[s] & VQE_SPMV_SLICED) != 0, bl = (lanes[s] & VQE_SPMV_BLOCKED) != 0;
-        const int rc16 = sl && bl ? sliced_tiled_fill(p, s, items[s].H, lanes[s])
-                         : bl     ? blocked_fill(p, s, items[s].H)
-                         : sl     ? sliced_fill(p, s, items[s].H, lanes[s])
-                                  : codes_fill(p, s, items[s].H, lanes[s]);
+        const int rc16 = sl   ? sliced_fill(p, s, items[s].H, lanes[s])
+                         : bl ? blocked_fill(p, s, items[s].H)
+                              : codes_fill(p, s, items[s].H, lanes[s]);
         if (rc16) {
             vqe_batch_destroy(p);
             return rc16;
@@ -1252,24 +1270,44 @@ namespace {
 void ls_fill_slot(vqe_batch *p, int s, double theta_max, char *D);
 }
 
-extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item *it)
+// A sliced layout of one operator, built once (vqe_layout_create) and pointed
+// to by batch slots (vqe_batch_rebind_layout).
+struct vqe_layout {
+    vqe_ctx *ctx = nullptr;
+    int32_t sched = 0;          // the effective batch schedule it was built for
+    int32_t dtype = 0;
+    int64_t dim = 0;
+    const vqe_csr *H = nullptr; // identity check only
+    void *meta = nullptr, *code = nullptr, *val = nullptr;
+    int64_t meta_cap = 0, code_cap = 0, val_cap = 0;
+    SpmvState st{};             // the layout's fields of a slot descriptor
+    int64_t entries = 0;
+};
+
+namespace {
+int rebind_impl(vqe_batch *p, int32_t slot, const vqe_batch_item *it, const vqe_layout *layout,
+                const char *who)
 {
     if (!p)
         return VQE_EINVAL;
     vqe_ctx *ctx = p->ctx;
     if (slot < 0 || slot >= p->B || !it)
-        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: bad slot or item");
-    int rc = check_csr(ctx, it->H, "vqe_batch_rebind");
+        return vqe_fail(ctx, VQE_EINVAL, "%s: bad slot or item", who);
+    int rc = check_csr(ctx, it->H, who);
     if (rc)
         return rc;
     if (!it->pool || !it->psi || !it->sigma || it->H->dtype != p->dtype ||
         it->H->dim != p->dims[slot] ||
         (p->mf ? (const void *)it->pool->mf : (const void *)it->pool->ops) != p->pool_ops[slot])
-        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: item does not match slot %d", slot);
+        return vqe_fail(ctx, VQE_EINVAL, "%s: item does not match slot %d", who, slot);
     const int sched = vqe_batch_schedule(
         it->H, it->spmv_schedule ? it->spmv_schedule : vqe_default_schedule(it->H));
     if (sched != p->sched[slot])
-        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_rebind: schedule differs from slot %d", slot);
+        return vqe_fail(ctx, VQE_EINVAL, "%s: schedule differs from slot %d", who, slot);
+    if (layout && (layout->sched != sched || layout->dim != it->H->dim ||
+                   layout->dtype != it->H->dtype || layout->H != it->H))
+        return vqe_fail(ctx, VQE_EINVAL, "%s: the layout was not built for this operator and schedule",
+                        who);
     SpmvState *st = reinterpret_cast<SpmvState *>(p->image.data() + p->o_spmv) + slot;
     st->rowptr = it->H->rowptr;
     st->col = it->H->col;
@@ -1284,16 +1322,28 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
     ss->shift = it->H->diag_shift;
     TaylorState *ts = reinterpret_cast<TaylorState *>(p->image.data() + p->o_tay) + slot;
     ts->psi = it->psi;
-    if ((sched & VQE_SPMV_BLOCKED) && (sched & VQE_SPMV_SLICED)) {
-        rc = sliced_tiled_fill(p, slot, it->H, sched);
+    if (layout) {
+        // a prebuilt sliced layout of this H: the slot points to its buffers,
+        // taking the fields the builder writes (the column-tiled form also
+        // fixes the slab geometry; otherwise the slot keeps its block count)
+        st->scode = layout->st.scode;
+        st->sval = layout->st.sval;
+        st->srow = layout->st.srow;
+        st->sslice = layout->st.sslice;
+        if (sched & VQE_SPMV_BLOCKED) {
+            st->boff = layout->st.boff;
+            st->blk_rows = layout->st.blk_rows;
+            st->tile_cols = layout->st.tile_cols;
+            st->ntiles = layout->st.ntiles;
+            st->nblocks = layout->st.nblocks;
+        }
+        p->entries[slot] = layout->entries;
+    } else if (sched & VQE_SPMV_SLICED) {
+        rc = sliced_fill(p, slot, it->H, sched);
         if (rc)
             return rc;
     } else if (sched & VQE_SPMV_BLOCKED) {
         rc = blocked_fill(p, slot, it->H);
-        if (rc)
-            return rc;
-    } else if (sched & VQE_SPMV_SLICED) {
-        rc = sliced_fill(p, slot, it->H, sched);
         if (rc)
             return rc;
     } else if (sched & VQE_SPMV_X16) {
@@ -1325,6 +1375,72 @@ extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item
                                         hipMemcpyHostToDevice, s));
     }
     return VQE_OK;
+}
+}  // namespace
+
+extern "C" int vqe_batch_rebind(vqe_batch *p, int32_t slot, const vqe_batch_item *it)
+{
+    return rebind_impl(p, slot, it, nullptr, "vqe_batch_rebind");
+}
+
+extern "C" int vqe_batch_rebind_layout(vqe_batch *p, int32_t slot, const vqe_batch_item *it,
+                                       const vqe_layout *layout)
+{
+    if (p && !layout)
+        return vqe_fail(p->ctx, VQE_EINVAL, "vqe_batch_rebind_layout: null layout");
+    return rebind_impl(p, slot, it, layout, "vqe_batch_rebind_layout");
+}
+
+extern "C" int vqe_layout_create(vqe_ctx *ctx, const vqe_csr *H, int32_t schedule, vqe_layout **out)
+{
+    if (!ctx)
+        return VQE_EINVAL;
+    if (!out)
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_layout_create: null out");
+    *out = nullptr;
+    int rc = check_csr(ctx, H, "vqe_layout_create");
+    if (rc)
+        return rc;
+    if (schedule != 0 && !vqe_valid_schedule(schedule))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_layout_create: unknown schedule %d", schedule);
+    const int sched = vqe_batch_schedule(H, schedule ? schedule : vqe_default_schedule(H));
+    if (!(sched & VQE_SPMV_SLICED))
+        return vqe_fail(ctx, VQE_ENOTSUP, "vqe_layout_create: schedule %d has no sliced layout "
+                        "for this operator", schedule);
+    vqe_layout *L = new (std::nothrow) vqe_layout();
+    if (!L)
+        return vqe_fail(ctx, VQE_ENOMEM, "vqe_layout_create: allocation failed");
+    L->ctx = ctx;
+    L->sched = sched;
+    L->dtype = H->dtype;
+    L->dim = H->dim;
+    L->H = H;
+    const SellBufs b{&L->meta, &L->code, &L->val, &L->meta_cap, &L->code_cap, &L->val_cap};
+    rc = (sched & VQE_SPMV_BLOCKED) ? sliced_tiled_build(ctx, H, sched, b, L->st, &L->entries, -1)
+                                    : sliced_build(ctx, H, sched, b, L->st, &L->entries, -1);
+    if (rc) {
+        vqe_layout_destroy(L);
+        return rc;
+    }
+    *out = L;
+    return VQE_OK;
+}
+
+extern "C" int vqe_layout_destroy(vqe_layout *L)
+{
+    if (!L)
+        return VQE_EINVAL;
+    (void)hipStreamSynchronize(L->ctx->stream);
+    for (void *m : {L->meta, L->code, L->val})
+        if (m)
+            (void)hipFree(m);
+    delete L;
+    return VQE_OK;
+}
+
+extern "C" int64_t vqe_layout_bytes(const vqe_layout *L)
+{
+    return L ? L->meta_cap + L->code_cap + L->val_cap : 0;
 }
 
 extern "C" int vqe_batch_step(vqe_batch *p, uint32_t flags)

@@ -382,9 +382,11 @@ class DeviceExecutor(Executor):
         """`systems`: run -> vqe_system.System.  `schedules`: register-size key ->
         H-product schedule, or "tuned" for the autotuner's choice for the first
         run of that size (cached, else timed here), or None for the library's
-        default for that run.  Every slot's plan-owned layout of H is sized on
-        that first run here, so that binding runs of the same size later does
-        not reallocate while other groups run."""
+        default for that run.  With a sliced schedule each run's layout of H is
+        built once when the run is admitted and slots point to it; otherwise
+        every slot's plan-owned layout is sized on that first run here, so
+        that binding runs of the same size later does not reallocate while
+        other groups run."""
         import torch
         from . import batch as PB
         from . import binding as B
@@ -429,6 +431,12 @@ class DeviceExecutor(Executor):
                 sched_k = int(schedules[key])
             else:
                 sched_k = B.default_schedule(probe.H)
+            sliced = bool(sched_k & B.VQE_SPMV_SLICED)
+            if sliced:
+                # a run's footprint includes its layout
+                lay = B.Layout(ctx, probe.H, sched_k)
+                self.key_fp[key] += lay.nbytes()
+                lay.close()
             sched = [sched_k] * slots_per_group
             states = []
             with torch.cuda.stream(stream):
@@ -436,8 +444,9 @@ class DeviceExecutor(Executor):
                     states.append((empty, pool, torch.zeros(dim, dtype=tdt, device="cuda")))
                 plan = B.BatchPlan(ctx, states, schedules=sched, with_active=True)
                 plan.active.zero_()
-                # size every slot's layout of H on the probe, then unbind
-                for slot in range(slots_per_group):
+                # size every slot's own layout of H on the probe, then unbind
+                # (a sliced schedule binds the runs' own layouts instead)
+                for slot in range(slots_per_group if not sliced else 0):
                     plan.rebind(slot, probe.H, probe.pool, probe.psi)
                     plan.rebind(slot, empty, pool, states[slot][2])
             stream.synchronize()
@@ -445,6 +454,7 @@ class DeviceExecutor(Executor):
             pin = dict(pin_memory=True)
             self.group[key] = {"ctx": ctx, "stream": stream, "plan": plan, "pool": pool,
                                "empty": empty, "event": None, "dim": dim,
+                               "sched": sched_k, "sliced": sliced,
                                "slots": slots_per_group,
                                "h_active": torch.zeros(slots_per_group, dtype=torch.int32, **pin),
                                "h_theta": torch.zeros(slots_per_group, dtype=torch.float64, **pin),
@@ -466,7 +476,9 @@ class DeviceExecutor(Executor):
         # the device size once built, else the size measured for a run of the
         # same register size (plus 5%)
         if run in self.dev:
-            return self.dev[run].H.nbytes() + dim * self.dev[run].psi.element_size()
+            ds = self.dev[run]
+            lay = getattr(ds, "layout", None)
+            return ds.H.nbytes() + dim * ds.psi.element_size() + (lay.nbytes() if lay else 0)
         return int(self.key_fp[self.keyof[run]] * 1.05)
 
     def fixed_bytes(self) -> int:
@@ -485,6 +497,8 @@ class DeviceExecutor(Executor):
                                        _SinglePool(g["pool"]))
             if run in self.saved:
                 ds.psi.copy_(self.saved.pop(run).to(ds.psi.device))
+            if g["sliced"]:
+                ds.layout = self.B.Layout(g["ctx"], ds.H, g["sched"])
         g["stream"].synchronize()
         self.dev[run] = ds
 
@@ -495,6 +509,8 @@ class DeviceExecutor(Executor):
         self.unbind(run)
         ds = self.dev.pop(run)
         self.saved[run] = ds.psi.detach().cpu().clone()
+        if getattr(ds, "layout", None) is not None:
+            ds.layout.close()
         del ds
         g["stream"].synchronize()
 
@@ -511,7 +527,7 @@ class DeviceExecutor(Executor):
         for run, slot, th in batch:
             if bound.get(slot) != run:
                 ds = self.dev[run]
-                plan.rebind(slot, ds.H, ds.pool, ds.psi)
+                plan.rebind(slot, ds.H, ds.pool, ds.psi, layout=getattr(ds, "layout", None))
                 bound[slot] = run
             active[slot] = 1
             theta[slot] = th

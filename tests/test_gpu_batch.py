@@ -501,6 +501,54 @@ def test_x16_rebind_rebuilds_codes(ctx, form):
     own.close()
 
 
+S = B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
+
+
+@pytest.mark.parametrize("n_q,sched,real", [(12, 4 | S, False), (12, 8 | S | B.VQE_SPMV_REAL, True),
+                                            (16, 2 | S, False), (16, 2 | S | B.VQE_SPMV_DEEP, False)])
+def test_prebuilt_layout_matches_own_layout(ctx, n_q, sched, real):
+    """A slot pointed to a prebuilt sliced layout of H (vqe_layout_create,
+    vqe_batch_rebind_layout), column-tiled at 16 qubits, gives the energies and
+    sigma of the slot's own layout of the same H bit for bit, after a rebind
+    from another operator and back again; a layout built for another operator
+    is refused, and a schedule with no sliced layout is refused."""
+    ne = n_q // 2
+    sa = vs.make_system(vs.SystemSpec(n_q, ne, "jw", False, vs.system_seed(310, n_q)), with_pool=False)
+    sb = vs.make_system(vs.SystemSpec(n_q, ne, "jw", False, vs.system_seed(311, n_q)), with_pool=False)
+    pk = vs.shared_pool(n_q, ne, "jw")
+    pool = B.MatrixFreePool(pk, "c64")
+    Ha = B.csr_from_pack(ctx, sa.hamiltonian, "c64")
+    Hb = B.csr_from_pack(ctx, sb.hamiltonian, "c64")
+    assert Ha.real and Hb.real
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal(1 << n_q) + (0 if real else 1j) * rng.standard_normal(1 << n_q)
+    v /= np.linalg.norm(v)
+    psi = torch.from_numpy(v).to(torch.complex64).to(ctx.torch_device)
+    own = B.BatchPlan(ctx, [(Ha, pool, psi)], schedules=[sched])
+    own.step(update=False)
+    e_own = host(own.energies)[:3].copy()
+    sg_own = host(own.sigma[0]).copy()
+    own.close()
+    La = B.Layout(ctx, Ha, sched)
+    Lb = B.Layout(ctx, Hb, sched)
+    assert La.nbytes() > 0 and Lb.nbytes() > 0
+    plan = B.BatchPlan(ctx, [(Hb, pool, psi)], schedules=[sched])
+    plan.rebind(0, Hb, pool, psi, layout=Lb)
+    plan.step(update=False)
+    plan.rebind(0, Ha, pool, psi, layout=La)
+    for graph in (False, True, True):
+        plan.step(update=False, graph=graph)
+        np.testing.assert_array_equal(host(plan.energies)[:3], e_own)
+        np.testing.assert_array_equal(host(plan.sigma[0]), sg_own)
+    with pytest.raises(B.VqeError):
+        plan.rebind(0, Ha, pool, psi, layout=Lb)
+    with pytest.raises(B.VqeError):
+        B.Layout(ctx, Ha, 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH)
+    plan.close()
+    La.close()
+    Lb.close()
+
+
 def _y_pack(n, x, z, c):
     return vs.PauliPack(n, np.array(x, dtype=np.uint64), np.array(z, dtype=np.uint64),
                         np.array(c, dtype=np.complex128))

@@ -22,8 +22,8 @@ from paper_2606_29692_amd import serve as S  # noqa: E402
 SCHED = {(8, 4, "jw"): 16,
          (10, 4, "jw"): 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 | B.VQE_SPMV_REAL,
          (12, 8, "jw"): 32 | B.VQE_SPMV_LDS}
-# the sliced layout (rebuilt from the device on every rebind of a slot; with
-# real values at 10 qubits)
+# the sliced layout (built once per run at admission and bound to the slot;
+# with real values at 10 qubits)
 SLICED = B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
 SCHED_SLICED = {(8, 4, "jw"): 4 | SLICED, (10, 4, "jw"): 4 | SLICED | B.VQE_SPMV_REAL,
                 (12, 8, "jw"): 2 | SLICED}
@@ -69,9 +69,11 @@ def test_alone_vs_mixed_and_eviction(sched):
         print(f"run {r}: {len(mine)} requests", flush=True)
         assert by_run(alone)[r] == res_mixed[r]
         np.testing.assert_array_equal(psi_alone[r], psi_mixed[r])
-    # a budget that holds only a few runs: evictions and resumes, same results
-    small, psi_small, srv_small = serve(systems, thetas, trace, budget=srv.ex.fixed_bytes() + 6_000_000,
-                                        sched=sched)
+    # a budget that holds only a few runs (twice the largest run's footprint,
+    # which with the sliced layout includes the run's own layout): evictions
+    # and resumes, same results
+    budget = srv.ex.fixed_bytes() + 2 * max(srv.ex.footprint(r) for r in systems)
+    small, psi_small, srv_small = serve(systems, thetas, trace, budget=budget, sched=sched)
     assert srv_small.evictions > 0
     assert by_run(small) == res_mixed
     for r in systems:
