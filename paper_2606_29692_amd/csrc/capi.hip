@@ -402,8 +402,9 @@ int sliced_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs &b, S
 }
 
 // The same for a column-tiled H (VQE_SPMV_SLICED on a state larger than LDS):
-// the slab tables (row order, slices, slab totals and starts, the total) in
-// meta, the tile-local codes in code, the values in val.
+// the slab tables (row order, slices, slab totals and starts, the total, the
+// tile parts each slab reaches) in meta, the tile-local codes in code, the
+// values in val.
 int sliced_tiled_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs &b, SpmvState &st,
                        int64_t *entries, int s)
 {
@@ -415,12 +416,15 @@ int sliced_tiled_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs
     const size_t o_tot = o_sl + vqe_align((size_t)nslab * SPMV_SLICES_PER_BLOCK * sizeof(int2));
     const size_t o_base = o_tot + vqe_align((size_t)nslab * sizeof(int64_t));
     const size_t o_all = o_base + vqe_align((size_t)nslab * sizeof(int64_t));
-    int rc = grow_ctx(ctx, b.meta, b.meta_cap, (int64_t)(o_all + sizeof(int64_t)), "slab tables", s);
+    const size_t o_msk = o_all + vqe_align(sizeof(int64_t));
+    int rc = grow_ctx(ctx, b.meta, b.meta_cap, (int64_t)(o_msk + (size_t)nslab * sizeof(uint32_t)),
+                      "slab tables", s);
     if (rc)
         return rc;
     char *m = (char *)*b.meta;
+    uint32_t *msk = (uint32_t *)(m + o_msk);
     launch_sellt_layout(H, nt, tc, E, (uint16_t *)m, (int2 *)(m + o_sl), (int64_t *)(m + o_tot),
-                        (int64_t *)(m + o_base), (int64_t *)(m + o_all), ctx->stream);
+                        (int64_t *)(m + o_base), (int64_t *)(m + o_all), msk, ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
     int64_t total = 0;
     VQE_HIP(ctx, hipMemcpyAsync(&total, m + o_all, sizeof(total), hipMemcpyDeviceToHost, ctx->stream));
@@ -432,13 +436,14 @@ int sliced_tiled_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs
         (rc = grow_ctx(ctx, b.val, b.val_cap, n * (int64_t)vqe_elem_bytes(H->dtype), "slice values", s)))
         return rc;
     launch_sellt_fill(H, nt, tc, E, (const uint16_t *)m, (const int2 *)(m + o_sl),
-                      (const int64_t *)(m + o_base), (uint16_t *)*b.code, *b.val, ctx->stream);
+                      (const int64_t *)(m + o_base), (uint16_t *)*b.code, *b.val, msk, ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
     st.scode = (const uint16_t *)*b.code;
     st.sval = *b.val;
     st.srow = (const uint16_t *)m;
     st.sslice = (const int2 *)(m + o_sl);
     st.boff = (const int64_t *)(m + o_base);
+    st.smask = msk;
     st.blk_rows = R;
     st.tile_cols = tc;
     st.ntiles = nt;
@@ -1332,6 +1337,7 @@ int rebind_impl(vqe_batch *p, int32_t slot, const vqe_batch_item *it, const vqe_
         st->sslice = layout->st.sslice;
         if (sched & VQE_SPMV_BLOCKED) {
             st->boff = layout->st.boff;
+            st->smask = layout->st.smask;
             st->blk_rows = layout->st.blk_rows;
             st->tile_cols = layout->st.tile_cols;
             st->ntiles = layout->st.ntiles;

@@ -312,15 +312,18 @@ void launch_sell_fill(const vqe_csr *H, int E, bool real, const uint16_t *srow,
                       const int2 *sslice, uint16_t *code, void *val, hipStream_t s);
 // sliced layout of a column-tiled state (VQE_SPMV_SLICED on a state larger
 // than LDS): per slab of the blocked layout (nt tiles of tc columns) the row
-// order srow [slabs * SPMV_BLK_ROWS] (first the rows' entry counts), the
+// order srow [slabs * SPMV_SELLT_ROWS] (first the rows' entry counts), the
 // slices sslice [slabs * SPMV_SLICES_PER_BLOCK] (start in the slab, length),
-// the slab totals stot and starts sbase [slabs] and *total ...
+// the slab totals stot and starts sbase [slabs], *total, and the part masks
+// smask [slabs] cleared ...
 void launch_sellt_layout(const vqe_csr *H, int32_t nt, int32_t tc, int E, uint16_t *srow,
-                         int2 *sslice, int64_t *stot, int64_t *sbase, int64_t *total, hipStream_t s);
-// ... then, with room for total entries, the tile-local codes and the values
+                         int2 *sslice, int64_t *stot, int64_t *sbase, int64_t *total, uint32_t *smask,
+                         hipStream_t s);
+// ... then, with room for total entries, the tile-local codes, the values and
+// the tile parts each slab's codes reach (smask)
 void launch_sellt_fill(const vqe_csr *H, int32_t nt, int32_t tc, int E, const uint16_t *srow,
                        const int2 *sslice, const int64_t *sbase, uint16_t *code, void *val,
-                       hipStream_t s);
+                       uint32_t *smask, hipStream_t s);
 __global__ void k_energy_finalize(SpmvState single, const SpmvState *states, int n_states);
 
 void launch_pool_grad(int dtype, const GradGroup *groups, const int4 *tasks, unsigned grid,

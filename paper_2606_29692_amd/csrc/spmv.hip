@@ -2012,10 +2012,10 @@ k_sellt_count(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ co
 // Step 2: one workgroup per slab sorts the block's rows by their entries in
 // the tile (longest first, ties by row; in place: the counts become the row
 // order) and writes the slab's slices (start in the slab, length rounded up
-// to E) and its total entries.
+// to E) and its total entries, and clears its part mask.
 __global__ void __launch_bounds__(1024)
 k_sellt_sort(int64_t dim, int32_t nt, int E, uint16_t *__restrict__ cnt_row,
-             int2 *__restrict__ sslice, int64_t *__restrict__ stot)
+             int2 *__restrict__ sslice, int64_t *__restrict__ stot, uint32_t *__restrict__ smask)
 {
     constexpr int R = SPMV_SELLT_ROWS, RK = 2048;   // rows, keys (a power of two)
     static_assert(R <= RK && (RK + VQE_WAVE - 1) / VQE_WAVE <= SPMV_SLICES_PER_BLOCK, "block size");
@@ -2056,6 +2056,7 @@ k_sellt_sort(int64_t dim, int32_t nt, int E, uint16_t *__restrict__ cnt_row,
             at += len * VQE_WAVE;
         }
         stot[slab] = at;
+        smask[slab] = 0;     // the fill sets the parts the codes reach
     }
 }
 
@@ -2090,13 +2091,15 @@ k_sellt_scan(const int64_t *__restrict__ stot, int64_t nslab, int64_t *__restric
         *total = part[1023];
 }
 
-// Step 4: codes and values, one wave per slice (empty slices return).
+// Step 4: codes and values, one wave per slice (empty slices return), and
+// the tile parts the slice's columns reach, ORed into its slab's mask.
 template <int DT>
 __global__ void __launch_bounds__(64)
 k_sellt_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
              const void *__restrict__ val, int64_t dim, int32_t nt, int32_t tc, int E,
              const uint16_t *__restrict__ srow, const int2 *__restrict__ sslice,
-             const int64_t *__restrict__ sbase, uint16_t *__restrict__ code, void *__restrict__ sval)
+             const int64_t *__restrict__ sbase, uint16_t *__restrict__ code, void *__restrict__ sval,
+             uint32_t *__restrict__ smask)
 {
     using T = typename Elem<DT>::T;
     constexpr int R = SPMV_SELLT_ROWS;
@@ -2123,18 +2126,27 @@ k_sellt_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col
     T *out = reinterpret_cast<T *>(sval);
     const T *in = reinterpret_cast<const T *>(val);
     const int64_t base = sbase[slab] + sl.x;
+    constexpr int PART = SPMV_SELLT_PART_BYTES / (int)sizeof(T);
+    uint32_t parts = 0;
     for (int j = 0; j < sl.y; j++) {
         const int64_t at = base + ((int64_t)(j / E) * VQE_WAVE + lane) * E + j % E;
-        code[at] = j < len ? (uint16_t)(col[k0 + j] - c_lo) : (uint16_t)tc;
+        const int c = j < len ? col[k0 + j] - (int)c_lo : tc;
+        code[at] = (uint16_t)c;
         out[at] = j < len ? in[k0 + j] : T{};
+        if (j < len)
+            parts |= 1u << (c / PART);
     }
+    for (int off = VQE_WAVE / 2; off > 0; off >>= 1)
+        parts |= (uint32_t)__shfl_xor((int)parts, off);
+    if (lane == 0 && parts)
+        atomicOr(smask + slab, parts);
 }
 
 // The product: one workgroup per (state, row block); per tile with entries,
-// the tile staged in LDS (and its zero element), each wave takes the slab's
-// slices in turn, every lane sums its row's segment with D groups of E
-// entries in flight and adds it to the row's FP64 sums in LDS (each row once
-// per slab, tiles in ascending order).
+// the parts of the tile that the slab reaches staged in LDS (and its zero
+// element), each wave takes two of the slab's slices, every lane sums its
+// row's segment with D groups of E entries in flight and adds it to the row's
+// FP64 sums in LDS (each row once per slab, tiles in ascending order).
 template <int DT, int E, int D, bool PF>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
@@ -2164,50 +2176,63 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     if (tid == 0)
         s_x[tc] = T{};
     constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
-    // A tile is loaded into registers (16 bytes per thread and chunk) and
-    // written to LDS between the tiles' barriers; with PF the next tile's
-    // loads are issued while the current tile is multiplied.  A tile's bytes
-    // are a multiple of 16 (dim and the tile width are even) and start
-    // 16-byte aligned.
-    constexpr int SP = (SPMV_SELLT_TILE_BYTES / 16 + 1023) / 1024;
+    // A tile is loaded into registers (16 bytes per thread and part) and
+    // written to LDS between the tiles' barriers, only the parts of the tile
+    // that the slab's columns reach; with PF the next tile's loads are issued
+    // while the current tile is multiplied.  A tile's bytes are a multiple of
+    // 16 (dim and the tile width are even) and start 16-byte aligned.
+    constexpr int SP = SPMV_SELLT_TILE_BYTES / SPMV_SELLT_PART_BYTES;
+    static_assert(SPMV_SELLT_PART_BYTES == 16 * 1024 && SP <= 32, "a part is 16 bytes per thread");
     vqe_v4f pre[SP];
-    auto fetch = [&](int t) {
+    auto fetch = [&](int t, uint32_t parts) {
         const int64_t c_lo = (int64_t)t * tc;
         const int64_t nbytes = (dim - c_lo < tc ? dim - c_lo : tc) * (int64_t)sizeof(T);
         const vqe_v4f *src = reinterpret_cast<const vqe_v4f *>(psi + c_lo);
 #pragma unroll
         for (int u = 0; u < SP; u++) {
             const int c = tid + 1024 * u;
-            if ((int64_t)c * 16 < nbytes)
+            if (((parts >> u) & 1u) && (int64_t)c * 16 < nbytes)
                 pre[u] = gmem(src)[c];
         }
         return nbytes;
     };
-    int64_t staged = PF ? fetch(0) : 0;
+    auto parts_of = [&](int t) {
+        return (uint32_t)__builtin_amdgcn_readfirstlane((int)gmem(st.smask)[(int64_t)b * nt + t]);
+    };
+    uint32_t parts = PF ? parts_of(0) : 0u;
+    int64_t staged = PF ? fetch(0, parts) : 0;
+    // wave w takes slices w and 31 - w of each slab (longest with shortest:
+    // the slices are sorted longest first)
+    static_assert(SPMV_SLICES_PER_BLOCK == 32, "two slices per wave");
     for (int t = 0; t < nt; t++) {
         const int64_t slab = (int64_t)b * nt + t;
         const sell_v2i *sls = reinterpret_cast<const sell_v2i *>(st.sslice) + slab * SPMV_SLICES_PER_BLOCK;
-        // the longest slice first: without PF a tile with no entries in this
-        // block is skipped
-        const bool empty = __builtin_amdgcn_readfirstlane(gmem(sls)[0].y) == 0;
-        if (!PF && empty)
-            continue;
-        if (!PF)
-            staged = fetch(t);
+        // a slab with no entries reaches no part; without PF its tile is
+        // skipped
+        if (!PF) {
+            parts = parts_of(t);
+            if (parts == 0)
+                continue;
+            staged = fetch(t, parts);
+        }
+        const uint32_t here = parts;
         __syncthreads();      // every wave is done with the previous tile
 #pragma unroll
         for (int u = 0; u < SP; u++) {
             const int c = tid + 1024 * u;
-            if ((int64_t)c * 16 < staged)
+            if (((here >> u) & 1u) && (int64_t)c * 16 < staged)
                 reinterpret_cast<vqe_v4f *>(s_x)[c] = pre[u];
         }
         __syncthreads();
-        if (PF && t + 1 < nt)
-            staged = fetch(t + 1);
-        if (empty)
+        if (PF && t + 1 < nt) {
+            parts = parts_of(t + 1);
+            staged = fetch(t + 1, parts);
+        }
+        if (here == 0)
             continue;
         const int64_t base = gmem(st.boff)[slab];
-        for (int k = wid; k < SPMV_SLICES_PER_BLOCK; k += 16) {
+        for (int h = 0; h < 2; h++) {
+            const int k = h ? SPMV_SLICES_PER_BLOCK - 1 - wid : wid;
             const sell_v2i sl = gmem(sls)[k];
             const int ng = __builtin_amdgcn_readfirstlane(sl.y) / E;
             if (ng == 0)
@@ -2399,27 +2424,28 @@ void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, 
 }
 
 void launch_sellt_layout(const vqe_csr *H, int32_t nt, int32_t tc, int E, uint16_t *srow,
-                         int2 *sslice, int64_t *stot, int64_t *sbase, int64_t *total, hipStream_t s)
+                         int2 *sslice, int64_t *stot, int64_t *sbase, int64_t *total, uint32_t *smask,
+                         hipStream_t s)
 {
     const int64_t nb = (H->dim + SPMV_SELLT_ROWS - 1) / SPMV_SELLT_ROWS, nslab = nb * nt;
     k_sellt_count<<<(unsigned)((H->dim + 255) / 256), 256, 0, s>>>(H->rowptr, H->col, H->dim, nt, tc,
                                                                   SPMV_SELLT_ROWS, srow);
-    k_sellt_sort<<<(unsigned)nslab, 1024, 0, s>>>(H->dim, nt, E, srow, sslice, stot);
+    k_sellt_sort<<<(unsigned)nslab, 1024, 0, s>>>(H->dim, nt, E, srow, sslice, stot, smask);
     k_sellt_scan<<<1, 1024, 0, s>>>(stot, nslab, sbase, total);
 }
 
 void launch_sellt_fill(const vqe_csr *H, int32_t nt, int32_t tc, int E, const uint16_t *srow,
                        const int2 *sslice, const int64_t *sbase, uint16_t *code, void *val,
-                       hipStream_t s)
+                       uint32_t *smask, hipStream_t s)
 {
     const int64_t nb = (H->dim + SPMV_SELLT_ROWS - 1) / SPMV_SELLT_ROWS;
     const unsigned g = (unsigned)(nb * nt * SPMV_SLICES_PER_BLOCK);
     if (H->dtype == VQE_C128)
         k_sellt_fill<VQE_C128><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, nt, tc, E, srow,
-                                                sslice, sbase, code, val);
+                                                sslice, sbase, code, val, smask);
     else
         k_sellt_fill<VQE_C64><<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, nt, tc, E, srow,
-                                               sslice, sbase, code, val);
+                                               sslice, sbase, code, val, smask);
 }
 
 void launch_sell_fill(const vqe_csr *H, int E, bool real, const uint16_t *srow,

@@ -76,11 +76,14 @@ struct SpmvState {
     // column-tiled state the same per slab (SPMV_SELLT_ROWS-row block b,
     // tile t; slab = b * ntiles + t): srow[slab * SPMV_SELLT_ROWS + i], the
     // slices' starts relative to the slab's start boff[slab], tile-local
-    // columns (pads: tile_cols)
+    // columns (pads: tile_cols), and per slab smask[slab] with bit u set when
+    // the slab's codes reach part u of the tile (SPMV_SELLT_PART_BYTES each,
+    // the parts the product stages)
     const uint16_t *scode;
     const void *sval;
     const uint16_t *srow;
     const int2 *sslice;
+    const uint32_t *smask;
 };
 
 // Column-tiled H product: tile width (state elements staged in LDS per pass)
@@ -98,6 +101,9 @@ struct SpmvState {
 // flip masks reach)
 #define SPMV_SELLT_ROWS 2040
 #define SPMV_SELLT_TILE_BYTES (128 * 1024)
+// a tile is staged in parts of 16 bytes per thread of a 1024-thread workgroup;
+// a slab stages only the parts its columns reach
+#define SPMV_SELLT_PART_BYTES (16 * 1024)
 // Sliced layout: slices of one wave's rows per block of SPMV_LDS_ROWS rows.
 #define SPMV_SLICES_PER_BLOCK (SPMV_LDS_ROWS / VQE_WAVE)
 // largest dimension whose column XOR row fits 16 bits
