@@ -2196,26 +2196,56 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
         }
         return nbytes;
     };
-    auto parts_of = [&](int t) {
-        return (uint32_t)__builtin_amdgcn_readfirstlane((int)gmem(st.smask)[(int64_t)b * nt + t]);
+    // the slabs' part masks, 64 tiles at a time one per lane, and the tiles
+    // with entries in this block as a bit mask of that window
+    int win = -1;
+    uint32_t pv = 0u;
+    uint64_t live = 0ull;
+    auto load_window = [&](int w) {
+        win = w;
+        const int tl = w * 64 + lane;
+        pv = tl < nt ? gmem(st.smask)[(int64_t)b * nt + tl] : 0u;
+        live = __builtin_amdgcn_ballot_w64(pv != 0u);
     };
-    uint32_t parts = PF ? parts_of(0) : 0u;
-    int64_t staged = PF ? fetch(0, parts) : 0;
+    // the first tile at or after t with entries in this block (nt: none)
+    auto next_tile = [&](int t) {
+        while (t < nt) {
+            if ((t >> 6) != win)
+                load_window(t >> 6);
+            const uint64_t m = live & (~0ull << (t & 63));
+            if (m)
+                return win * 64 + (int)__builtin_ctzll(m);
+            t = (win + 1) * 64;
+        }
+        return nt;
+    };
+    auto parts_at = [&](int t) {   // t in the current window
+        return (uint32_t)__builtin_amdgcn_readlane((int)pv, t & 63);
+    };
     // wave w takes slices w and 31 - w of each slab (longest with shortest:
     // the slices are sorted longest first)
     static_assert(SPMV_SLICES_PER_BLOCK == 32, "two slices per wave");
-    for (int t = 0; t < nt; t++) {
+    const int ka = wid, kb = SPMV_SLICES_PER_BLOCK - 1 - wid;
+    int t = next_tile(0);
+    uint32_t parts = 0u;
+    int64_t staged = 0;
+    if (PF && t < nt) {
+        parts = parts_at(t);
+        staged = fetch(t, parts);
+    }
+    while (t < nt) {
         const int64_t slab = (int64_t)b * nt + t;
+        const uint32_t here = PF ? parts : parts_at(t);
+        if (!PF)
+            staged = fetch(t, here);
+        // the slab's tables, loaded before the barriers: its start, the two
+        // slices and the rows their lanes take (clamped to the block)
         const sell_v2i *sls = reinterpret_cast<const sell_v2i *>(st.sslice) + slab * SPMV_SLICES_PER_BLOCK;
-        // a slab with no entries reaches no part; without PF its tile is
-        // skipped
-        if (!PF) {
-            parts = parts_of(t);
-            if (parts == 0)
-                continue;
-            staged = fetch(t, parts);
-        }
-        const uint32_t here = parts;
+        const int64_t base = gmem(st.boff)[slab];
+        const sell_v2i sl2[2] = {gmem(sls)[ka], gmem(sls)[kb]};
+        const uint16_t *srow = st.srow + slab * R;
+        const int ia = ka * VQE_WAVE + lane, ib = kb * VQE_WAVE + lane;
+        const int rl2[2] = {gmem(srow)[ia < n ? ia : n - 1], gmem(srow)[ib < n ? ib : n - 1]};
         __syncthreads();      // every wave is done with the previous tile
 #pragma unroll
         for (int u = 0; u < SP; u++) {
@@ -2224,48 +2254,72 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
                 reinterpret_cast<vqe_v4f *>(s_x)[c] = pre[u];
         }
         __syncthreads();
-        if (PF && t + 1 < nt) {
-            parts = parts_of(t + 1);
-            staged = fetch(t + 1, parts);
+        const int tn = next_tile(t + 1);
+        if (PF && tn < nt) {
+            parts = parts_at(tn);
+            staged = fetch(tn, parts);
         }
-        if (here == 0)
-            continue;
-        const int64_t base = gmem(st.boff)[slab];
-        for (int h = 0; h < 2; h++) {
-            const int k = h ? SPMV_SLICES_PER_BLOCK - 1 - wid : wid;
-            const sell_v2i sl = gmem(sls)[k];
-            const int ng = __builtin_amdgcn_readfirstlane(sl.y) / E;
-            if (ng == 0)
-                break;     // slices are longest first
-            const int i = k * VQE_WAVE + lane;
-            const int64_t at = base + __builtin_amdgcn_readfirstlane(sl.x) + lane * E;
+        // the wave's two slices as one stream of groups (the first slice's,
+        // then the second's), so that the second slice's first groups load
+        // while the first one finishes; each slice sums into its own pair
+        const int nga = __builtin_amdgcn_readfirstlane(sl2[0].y) / E;
+        const int ngb = __builtin_amdgcn_readfirstlane(sl2[1].y) / E;
+        if (nga > 0) {
+            const int ng = nga + ngb;
+            const int64_t ata = base + __builtin_amdgcn_readfirstlane(sl2[0].x) + lane * E;
+            const int64_t atb = base + __builtin_amdgcn_readfirstlane(sl2[1].x) + lane * E - (int64_t)nga * STEP;
+            // stream group p (clamped to the last) and its address
+            auto addr = [&](int p) {
+                const int pc = p < ng ? p : ng - 1;
+                return (pc < nga ? ata : atb) + (int64_t)pc * STEP;
+            };
+            // one running sum; at the second slice's first group the first
+            // slice's sum is set aside and the sum restarts
             double are = 0.0, aim = 0.0;
+            double2 sa = make_double2(0.0, 0.0), sb;
             SellGroup<DT, E> g[D];
 #pragma unroll
             for (int d = 0; d < D; d++)
-                g[d].load(code, val, at + (int64_t)(d < ng ? d : ng - 1) * STEP);
+                g[d].load(code, val, addr(d));
             int q = 0;
             for (; q + D <= ng; q += D) {
 #pragma unroll
                 for (int d = 0; d < D; d++) {
+                    if (q + d == nga) {
+                        sa = make_double2(are, aim);
+                        are = aim = 0.0;
+                    }
                     g[d].use(s_x, are, aim);
-                    const int nx = q + D + d < ng ? q + D + d : ng - 1;
-                    g[d].load(code, val, at + (int64_t)nx * STEP);
+                    g[d].load(code, val, addr(q + D + d));
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
 #pragma unroll
             for (int d = 0; d < D; d++)
-                if (q + d < ng)
+                if (q + d < ng) {
+                    if (q + d == nga) {
+                        sa = make_double2(are, aim);
+                        are = aim = 0.0;
+                    }
                     g[d].use(s_x, are, aim);
-            if (i < n) {
-                const int rl = gmem(st.srow)[slab * R + i];
-                double2 a = s_acc[rl];
-                a.x += are;
-                a.y += aim;
-                s_acc[rl] = a;
+                }
+            if (ngb == 0)
+                sa = make_double2(are, aim);
+            sb = make_double2(are, aim);
+            if (ka * VQE_WAVE + lane < n) {
+                double2 a = s_acc[rl2[0]];
+                a.x += sa.x;
+                a.y += sa.y;
+                s_acc[rl2[0]] = a;
+            }
+            if (ngb > 0 && kb * VQE_WAVE + lane < n) {
+                double2 a = s_acc[rl2[1]];
+                a.x += sb.x;
+                a.y += sb.y;
+                s_acc[rl2[1]] = a;
             }
         }
+        t = tn;
     }
     __syncthreads();
     double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
