@@ -394,7 +394,8 @@ VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
  * slot's state at creation and use the same pool (same ops array).  The new
  * descriptors are copied on the context stream, so they apply to every step
  * enqueued afterwards, graph replays included; steps already enqueued keep
- * the old binding.  Errors: VQE_EINVAL (slot out of range, mismatch).
+ * the old binding.  Errors: VQE_EINVAL (slot out of range, mismatch, psi or
+ * sigma not 16-byte aligned).
  */
 VQE_API int vqe_batch_rebind(vqe_batch *plan, int32_t slot, const vqe_batch_item *item);
 /*

@@ -1305,6 +1305,8 @@ int rebind_impl(vqe_batch *p, int32_t slot, const vqe_batch_item *it, const vqe_
         it->H->dim != p->dims[slot] ||
         (p->mf ? (const void *)it->pool->mf : (const void *)it->pool->ops) != p->pool_ops[slot])
         return vqe_fail(ctx, VQE_EINVAL, "%s: item does not match slot %d", who, slot);
+    if ((((uintptr_t)it->psi) & 15) || (((uintptr_t)it->sigma) & 15))
+        return vqe_fail(ctx, VQE_EINVAL, "%s: psi and sigma must be 16-byte aligned", who);
     const int sched = vqe_batch_schedule(
         it->H, it->spmv_schedule ? it->spmv_schedule : vqe_default_schedule(it->H));
     if (sched != p->sched[slot])

@@ -1104,70 +1104,125 @@ struct SellGroup {
     }
 };
 
-// The slices of one block against the staged state s_x (X: complex, or the
-// real parts in FP64 for a real state); each wave takes the block's slices in
-// turn and keeps D groups of E entries per lane in flight.
-template <int DT, int E, int D, bool RV, typename X>
-__device__ __forceinline__ void sell_rows(const SpmvState &st, int blk, const X *s_x, float2 *s_sig)
-{
+// One wave's share of a block of the sliced layout: slices A = wid and
+// B = wid + 16 (those the block has), taken as one stream of groups (A's,
+// then B's) so that B's first groups load while A finishes; D groups of E
+// entries per lane in flight.  Every load is issued (past the stream's end
+// it repeats the last group, which is in cache), so no load sits under a
+// branch and each group's wait leaves the later groups' loads in flight.
+template <int DT, int E, int D, bool RV>
+struct SellWave {
     using V = typename ValOf<DT, RV>::T;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t dim = st.dim;
-    const int64_t r0 = (int64_t)blk * SPMV_LDS_ROWS;
-    const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
-    const int ns = (n + VQE_WAVE - 1) / VQE_WAVE;
-    const uint16_t *__restrict__ code = st.scode;
-    const V *__restrict__ val = reinterpret_cast<const V *>(st.sval);
-    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
-    for (int k = wid; k < ns; k += 16) {
-        // the slice's start and length are uniform over the wave
-        const sell_v2i sl =
-            gmem(reinterpret_cast<const sell_v2i *>(st.sslice))[(int64_t)blk * SPMV_SLICES_PER_BLOCK + k];
-        const int start = __builtin_amdgcn_readfirstlane(sl.x);
-        const int ng = __builtin_amdgcn_readfirstlane(sl.y) / E;
-        const int i = k * VQE_WAVE + lane;
-        const bool on = i < n;
-        const int64_t row = r0 + (on ? (int64_t)gmem(st.srow)[r0 + i] : 0);
-        const int64_t at = (int64_t)start + lane * E;
-        constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
+    static constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
+    const uint16_t *code;
+    const V *val;
+    int64_t r0, ata, atb;
+    int n, ns, nga, ngb, ng, ra, rb;   // ra, rb: block-local rows of this lane
+    SellGroup<DT, E, RV> g[D];
+
+    __device__ __forceinline__ void init(const SpmvState &st, int blk, int lane, int wid)
+    {
+        code = st.scode;
+        val = reinterpret_cast<const V *>(st.sval);
+        r0 = (int64_t)blk * SPMV_LDS_ROWS;
+        n = (int)(st.dim - r0 < SPMV_LDS_ROWS ? st.dim - r0 : SPMV_LDS_ROWS);
+        ns = (n + VQE_WAVE - 1) / VQE_WAVE;
+        const int ka = wid, kb = wid + 16;
+        const sell_v2i *sls = reinterpret_cast<const sell_v2i *>(st.sslice) + (int64_t)blk * SPMV_SLICES_PER_BLOCK;
+        sell_v2i a = {0, 0}, b = {0, 0};
+        if (ka < ns)
+            a = gmem(sls)[ka];
+        if (kb < ns)
+            b = gmem(sls)[kb];
+        nga = __builtin_amdgcn_readfirstlane(a.y) / E;
+        ngb = __builtin_amdgcn_readfirstlane(b.y) / E;
+        ng = nga + ngb;
+        ata = (int64_t)__builtin_amdgcn_readfirstlane(a.x) + lane * E;
+        atb = (int64_t)__builtin_amdgcn_readfirstlane(b.x) + lane * E - (int64_t)nga * STEP;
+        const int ia = ka * VQE_WAVE + lane, ib = kb * VQE_WAVE + lane;
+        ra = gmem(st.srow)[r0 + (ia < n ? ia : n - 1)];
+        rb = gmem(st.srow)[r0 + (ib < n ? ib : n - 1)];
+    }
+    // stream group p (clamped to the last) and its first entry for this lane
+    __device__ __forceinline__ int64_t addr(int p) const
+    {
+        const int pc = p < ng ? p : ng - 1;
+        return (pc < nga ? ata : atb) + (int64_t)pc * STEP;
+    }
+    // the stream's first groups (a wave with groups only)
+    __device__ __forceinline__ void prefetch()
+    {
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            g[d].load(code, val, addr(d));
+    }
+    // the rows' sums for A and B against the staged state s_x (X: complex, or
+    // the real parts in FP64 for a real state); prefetch() came first
+    template <typename X>
+    __device__ __forceinline__ void run(const X *s_x, double2 &sa, double2 &sb)
+    {
         double are = 0.0, aim = 0.0;
-        if (ng > 0) {
-            // every load is issued (past the slice's end it repeats the last
-            // group, which is in cache), so no load sits under a branch and
-            // each group's wait leaves the later groups' loads in flight
-            SellGroup<DT, E, RV> g[D];
+        sa = make_double2(0.0, 0.0);
+        sb = make_double2(0.0, 0.0);
+        if (ng == 0)
+            return;
+        int q = 0;
+        for (; q + D <= ng; q += D) {
 #pragma unroll
-            for (int d = 0; d < D; d++)
-                g[d].load(code, val, at + (int64_t)(d < ng ? d : ng - 1) * STEP);
-            int q = 0;
-            for (; q + D <= ng; q += D) {
-#pragma unroll
-                for (int d = 0; d < D; d++) {
-                    g[d].use(s_x, are, aim);
-                    const int nx = q + D + d < ng ? q + D + d : ng - 1;
-                    g[d].load(code, val, at + (int64_t)nx * STEP);
-                    // keep the refill ahead of the next group's products
-                    __builtin_amdgcn_sched_barrier(0);
+            for (int d = 0; d < D; d++) {
+                if (q + d == nga) {     // B's first group: A's sums are done
+                    sa = make_double2(are, aim);
+                    are = aim = 0.0;
                 }
+                g[d].use(s_x, are, aim);
+                g[d].load(code, val, addr(q + D + d));
+                // keep the refill ahead of the next group's products
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int d = 0; d < D; d++)
-                if (q + d < ng)
-                    g[d].use(s_x, are, aim);
         }
-        if (on) {
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            if (q + d < ng) {
+                if (q + d == nga) {
+                    sa = make_double2(are, aim);
+                    are = aim = 0.0;
+                }
+                g[d].use(s_x, are, aim);
+            }
+        if (ngb == 0)
+            sa = make_double2(are, aim);
+        else
+            sb = make_double2(are, aim);
+    }
+};
+
+// The block's rows from a wave's sums: sigma (FP32 storage: gathered in LDS
+// and stored in row order), the energy terms and the block's partials.
+template <int DT, int E, int D, bool RV, typename X>
+__device__ __forceinline__ void sell_finish(const SpmvState &st, int blk, const SellWave<DT, E, D, RV> &w,
+                                            const X *s_x, float2 *s_sig, double2 sa, double2 sb)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double e_re = 0.0, e_im = 0.0, e_n2 = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int k = wid + 16 * h;
+        const int i = k * VQE_WAVE + lane;
+        if (k < w.ns && i < w.n) {
+            const int64_t row = w.r0 + (h ? w.rb : w.ra);
+            const double2 a = h ? sb : sa;
             if constexpr (DT == VQE_C64)
-                s_sig[row - r0] = make_float2((float)are, (float)aim);
+                s_sig[row - w.r0] = make_float2((float)a.x, (float)a.y);
             else
-                Elem<DT>::st(st.sigma, row, make_double2(are, aim));
-            energy_terms(s_x[row], are, aim, e_re, e_im, e_n2);
+                Elem<DT>::st(st.sigma, row, a);
+            energy_terms(s_x[row], a.x, a.y, e_re, e_im, e_n2);
         }
     }
     if constexpr (DT == VQE_C64) {
         // the block's results leave in row order
         __syncthreads();
-        for (int i = tid; i < n; i += 1024)
-            stg(reinterpret_cast<float2 *>(st.sigma), r0 + i, s_sig[i]);
+        for (int i = tid; i < w.n; i += 1024)
+            stg(reinterpret_cast<float2 *>(st.sigma), w.r0 + i, s_sig[i]);
     }
     __shared__ double s_part[16][3];
     e_re = wave_sum(e_re);
@@ -1181,17 +1236,18 @@ __device__ __forceinline__ void sell_rows(const SpmvState &st, int blk, const X 
     __syncthreads();
     if (tid < 3) {
         double v = 0.0;
-        for (int w = 0; w < 16; w++)
-            v += s_part[w][tid];
+        for (int q = 0; q < 16; q++)
+            v += s_part[q][tid];
         gmem(st.partials)[(int64_t)blk * 3 + tid] = v;
     }
 }
 
 // One workgroup per (state, block of SPMV_LDS_ROWS rows): the state staged in
-// LDS (plus the zero element), then the block's slices.  With RV (the real
-// parts of a real H) a state whose imaginary parts are all zero is staged as
-// FP64 real parts and multiplied in real arithmetic; any other state takes
-// the complex staging in the same launch.
+// LDS (plus the zero element), then the block's slices; each wave's first
+// groups are loaded together with the staged state.  With RV (the real parts
+// of a real H) a state whose imaginary parts are all zero is staged as FP64
+// real parts and multiplied in real arithmetic; any other state takes the
+// complex staging in the same launch.
 template <int DT, int E, int D, bool RV>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
@@ -1204,27 +1260,57 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
         return;
     using T = typename Elem<DT>::T;
     extern __shared__ unsigned char smem[];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t dim = st.dim;
     const T *psi = reinterpret_cast<const T *>(st.psi);
     // FP32 storage: the block's results gather in LDS after the state
     float2 *s_sig = reinterpret_cast<float2 *>(smem + (size_t)(dim + 1) * sizeof(T));
+    SellWave<DT, E, D, RV> w;
+    w.init(st, t.y, lane, wid);
+    double2 sa, sb;
     if constexpr (RV) {
+        if (w.ng > 0)
+            w.prefetch();
         double *s_xr = reinterpret_cast<double *>(smem);
         const int cplx = stage_real<8>(s_xr, psi, dim, tid);
         if (tid == 0)
             s_xr[dim] = 0.0;
         if (!__syncthreads_or(cplx)) {
-            sell_rows<DT, E, D, RV>(st, t.y, s_xr, s_sig);
+            w.run(s_xr, sa, sb);
+            sell_finish(st, t.y, w, s_xr, s_sig, sa, sb);
             return;
         }
     }
+    // the state in 16-byte chunks (dim * sizeof(T) is a multiple of 16 and
+    // psi 16-byte aligned): the first SP per thread loaded before the wave's
+    // first groups, so both latencies overlap
     T *s_x = reinterpret_cast<T *>(smem);
-    stage_lds<8>(s_x, psi, dim, tid);
+    constexpr int SP = 8;
+    const int64_t nch = dim * (int64_t)sizeof(T) / 16;
+    const vqe_v4f *src = reinterpret_cast<const vqe_v4f *>(psi);
+    vqe_v4f *dst = reinterpret_cast<vqe_v4f *>(s_x);
+    vqe_v4f pre[SP];
+#pragma unroll
+    for (int u = 0; u < SP; u++) {
+        const int64_t c = tid + 1024 * u;
+        if (c < nch)
+            pre[u] = gmem(src)[c];
+    }
+    if (!RV && w.ng > 0)
+        w.prefetch();
+#pragma unroll
+    for (int u = 0; u < SP; u++) {
+        const int64_t c = tid + 1024 * u;
+        if (c < nch)
+            dst[c] = pre[u];
+    }
+    for (int64_t c = tid + 1024 * SP; c < nch; c += 1024)
+        dst[c] = gmem(src)[c];
     if (tid == 0)
         s_x[dim] = T{};
     __syncthreads();
-    sell_rows<DT, E, D, RV>(st, t.y, s_x, s_sig);
+    w.run(s_x, sa, sb);
+    sell_finish(st, t.y, w, s_x, s_sig, sa, sb);
 }
 
 // Column-tiled variant of the pipelined LDS schedule, for states larger than
