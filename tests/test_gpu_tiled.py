@@ -3,7 +3,9 @@
 FP64 storage at 14 qubits (256 KiB state: two 128 KiB column tiles) against
 the oracle to 1e-12 along forced trajectories; FP32 storage at 16 qubits
 (four tiles) against the oracle within the FP32 bars; a slot rebound to
-another Hamiltonian recomputes its tile bounds (or its sliced slabs).
+another Hamiltonian recomputes its tile bounds (or its sliced slabs); the
+sliced tiles of a sparse operator at 17 and 21 qubits (blocks that reach two
+or three tiles, part masks in two windows) against the oracle on every row.
 """
 import numpy as np
 import pytest
@@ -155,3 +157,48 @@ def test_tiled_real_values_complex_state(ctx, dtype, n):
             plan.close()
         d = np.linalg.norm(sig[SCHED_R] - sig[SCHED_X16]) / np.linalg.norm(sig[SCHED_X16])
         assert d <= tol
+
+
+def _sparse_pack(n):
+    """Four Pauli strings on n qubits: Z on qubit 3 (diagonal), X0 X(n-1),
+    X(n-1) X(n-2) (a flip of the two top qubits only, so a row block's other
+    tile lies far from its own) and Y5 Y(n-3)."""
+    x = [0, 1 | 1 << (n - 1), 1 << (n - 1) | 1 << (n - 2), 1 << 5 | 1 << (n - 3)]
+    z = [1 << 3, 0, 0, 1 << 5 | 1 << (n - 3)]
+    c = [-0.3, 0.7, 0.5, 0.2]
+    return vs.PauliPack(n, np.array(x, dtype=np.uint64), np.array(z, dtype=np.uint64),
+                        np.array(c, dtype=np.complex128))
+
+
+@pytest.mark.parametrize("n_q", [17, 21])
+@pytest.mark.parametrize("sched", [SCHED_S, SCHED_SD])
+def test_sliced_tiles_of_a_sparse_operator(ctx, n_q, sched):
+    """The sliced column-tiled product of an operator whose row blocks reach
+    only two or three of the column tiles, and few 16 KiB parts of them (at
+    21 qubits the 128 tiles span two windows of 64 part masks, and a block's
+    far tile lies in the other window): sigma on every row and the energy
+    against the oracle, FP32 storage."""
+    pack = _sparse_pack(n_q)
+    H = B.csr_from_pack(ctx, pack, "c64")
+    gen = vs.PauliPack(n_q, np.array([3], dtype=np.uint64), np.array([0], dtype=np.uint64),
+                       np.array([1j], dtype=np.complex128))
+    pool = B.MatrixFreePool([gen], "c64")
+    rng = np.random.default_rng(n_q)
+    v = rng.standard_normal(1 << n_q) + 1j * rng.standard_normal(1 << n_q)
+    v /= np.linalg.norm(v)
+    psi = torch.from_numpy(v.astype(np.complex64)).to(ctx.torch_device)
+    print(f"{n_q} qubits, schedule {sched}: plan", flush=True)
+    plan = B.BatchPlan(ctx, [(H, pool, psi)], schedules=[sched])
+    plan.step(update=False)
+    e = host(plan.energies)[:3].copy()
+    sg = host(plan.sigma[0]).astype(np.complex128)
+    plan.close()
+    vin = host(psi).astype(np.complex128)
+    R = orc.csr_rows(pack, np.arange(1 << n_q))
+    ref = orc.spmv_rows(R, vin)
+    err = np.linalg.norm(sg - ref) / np.linalg.norm(ref)
+    n2 = float(np.vdot(vin, vin).real)
+    e_o = float(np.vdot(vin, ref).real) / n2
+    print(f"  sigma rel err {err:.2e}, |dE| {abs(e[0] - e_o):.2e}")
+    assert err < 2e-6
+    assert abs(e[0] - e_o) < 1e-6 and abs(e[1] - n2) < 1e-6
