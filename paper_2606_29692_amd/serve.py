@@ -452,9 +452,12 @@ class DeviceExecutor(Executor):
             stream.synchronize()
             del probe
             pin = dict(pin_memory=True)
+            # idle slots of a sliced group point to the placeholder's own
+            # layout, so unbinding a run rebuilds nothing
+            empty_layout = B.Layout(ctx, empty, sched_k) if sliced else None
             self.group[key] = {"ctx": ctx, "stream": stream, "plan": plan, "pool": pool,
-                               "empty": empty, "event": None, "dim": dim,
-                               "sched": sched_k, "sliced": sliced,
+                               "empty": empty, "empty_layout": empty_layout, "event": None,
+                               "dim": dim, "sched": sched_k, "sliced": sliced,
                                "slots": slots_per_group,
                                "h_active": torch.zeros(slots_per_group, dtype=torch.int32, **pin),
                                "h_theta": torch.zeros(slots_per_group, dtype=torch.float64, **pin),
@@ -572,7 +575,8 @@ class DeviceExecutor(Executor):
             for slot, r in list(g.get("bound", {}).items()):
                 if r == run:
                     with self.torch.cuda.stream(g["stream"]):
-                        g["plan"].rebind(slot, g["empty"], g["pool"], g["plan"].states[slot][2])
+                        g["plan"].rebind(slot, g["empty"], g["pool"], g["plan"].states[slot][2],
+                                         layout=g["empty_layout"])
                     del g["bound"][slot]
 
 
