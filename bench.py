@@ -124,7 +124,7 @@ def plan_sched_pad(sched: int, ds) -> bool:
 
 
 BLK_ROWS, BLK_TILE_BYTES = 2048, 96 * 1024     # blocked layout of column-tiled states
-SELLT_ROWS, SELLT_TILE_BYTES = 2040, 128 * 1024  # sliced layout of column-tiled states
+SELLT_ROWS, SELLT_TILE_BYTES = 2048, 128 * 1024  # sliced layout of column-tiled states
 
 
 def plan_sliced(sched: int, d) -> bool:

@@ -601,7 +601,7 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * 8 per slice; plan-owned, rebuilt by vqe_batch_rebind, which then waits for
  * the layout's size; vqe_batch_layout_entries reports the entries).  Each
  * lane sums its row in the CSR's column order.  A state larger than LDS is
- * cut into slabs (2040-row block, 128 KiB column tile aligned to a power of
+ * cut into slabs (2048-row block, 128 KiB column tile aligned to a power of
  * two of columns), each slab sorted and sliced by the rows' entries in its tile, with
  * tile-local codes and 2 bytes per row and tile of row order; one workgroup
  * per row block walks the tiles with its rows' FP64 sums in LDS, and a row

@@ -2072,9 +2072,10 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
 // in the tile.  srow[slab * R + i] is the
 // block-local row at sorted position i of the slab; sslice[slab *
 // SPMV_SLICES_PER_BLOCK + k] = (start relative to the slab's boff[slab],
-// entries per lane); codes are tile-local (col - t * tile_cols), pads code
-// tile_cols (the staged tile's zero element).  One workgroup per row block
-// walks the tiles with its rows' FP64 sums in LDS, as the blocked product.
+// entries per lane); codes are tile-local (col - t * tile_cols); a pad takes
+// the column of its slice's first entry (so it reads a staged element) and
+// the value zero.  One workgroup per row block walks the tiles with its rows'
+// FP64 sums in LDS, as the blocked product.
 
 // Layout step 1: per (row block, tile), the row's entries in the tile; one
 // thread per row (tiles in turn; columns ascending).
@@ -2213,10 +2214,12 @@ k_sellt_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col
     const T *in = reinterpret_cast<const T *>(val);
     const int64_t base = sbase[slab] + sl.x;
     constexpr int PART = SPMV_SELLT_PART_BYTES / (int)sizeof(T);
+    // the pads' column: the slice's first entry (lane 0 holds its longest row)
+    const int cpad = __shfl(len > 0 ? col[k0] - (int)c_lo : 0, 0);
     uint32_t parts = 0;
     for (int j = 0; j < sl.y; j++) {
         const int64_t at = base + ((int64_t)(j / E) * VQE_WAVE + lane) * E + j % E;
-        const int c = j < len ? col[k0 + j] - (int)c_lo : tc;
+        const int c = j < len ? col[k0 + j] - (int)c_lo : cpad;
         code[at] = (uint16_t)c;
         out[at] = j < len ? in[k0 + j] : T{};
         if (j < len)
@@ -2229,8 +2232,8 @@ k_sellt_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col
 }
 
 // The product: one workgroup per (state, row block); per tile with entries,
-// the parts of the tile that the slab reaches staged in LDS (and its zero
-// element), each wave takes two of the slab's slices, every lane sums its
+// the parts of the tile that the slab reaches staged in LDS, each wave takes
+// two of the slab's slices, every lane sums its
 // row's segment with D groups of E entries in flight and adds it to the row's
 // FP64 sums in LDS (each row once per slab, tiles in ascending order).
 template <int DT, int E, int D, bool PF>
@@ -2259,8 +2262,6 @@ k_spmv_sellt(const SpmvState *__restrict__ states, const int2 *__restrict__ task
     const T *__restrict__ val = reinterpret_cast<const T *>(st.sval);
     for (int i = tid; i < n; i += 1024)
         s_acc[i] = make_double2(0.0, 0.0);
-    if (tid == 0)
-        s_x[tc] = T{};
     constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
     // A tile is loaded into registers (16 bytes per thread and part) and
     // written to LDS between the tiles' barriers, only the parts of the tile
@@ -2490,7 +2491,7 @@ static void launch_sellt_t(const SpmvState *states, const int2 *tasks, unsigned 
                            bool pf)
 {
     const size_t lds = (size_t)SPMV_SELLT_ROWS * sizeof(double2) +
-                       (size_t)(spmv_sellt_tile_cols(DT) + 1) * vqe_elem_bytes(DT);
+                       (size_t)spmv_sellt_tile_cols(DT) * vqe_elem_bytes(DT);
     auto k = pf ? k_spmv_sellt<DT, E, D, true> : k_spmv_sellt<DT, E, D, false>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);

@@ -76,7 +76,8 @@ struct SpmvState {
     // column-tiled state the same per slab (SPMV_SELLT_ROWS-row block b,
     // tile t; slab = b * ntiles + t): srow[slab * SPMV_SELLT_ROWS + i], the
     // slices' starts relative to the slab's start boff[slab], tile-local
-    // columns (pads: tile_cols), and per slab smask[slab] with bit u set when
+    // columns (pads: the column of the slice's first entry, value zero), and
+    // per slab smask[slab] with bit u set when
     // the slab's codes reach part u of the tile (SPMV_SELLT_PART_BYTES each,
     // the parts the product stages)
     const uint16_t *scode;
@@ -95,11 +96,12 @@ struct SpmvState {
 #define VQE_SPMV_BLOCKED 0x20000
 #define SPMV_BLK_ROWS 2048
 #define SPMV_BLK_TILE_BYTES (96 * 1024)
-// Sliced column-tiled layout: rows per block (their FP64 sums fill the LDS
-// beside one tile) and tile bytes (a power of two of columns, so that a
-// block, whose rows share their high bits, meets only the tiles its rows'
+// Sliced column-tiled layout: rows per block (their FP64 sums and one tile
+// fill the LDS exactly; a pad's code is a column its slice reaches, so no
+// zero element is staged) and tile bytes (a power of two of columns, so that
+// a block, whose rows share their high bits, meets only the tiles its rows'
 // flip masks reach)
-#define SPMV_SELLT_ROWS 2040
+#define SPMV_SELLT_ROWS 2048
 #define SPMV_SELLT_TILE_BYTES (128 * 1024)
 // a tile is staged in parts of 16 bytes per thread of a 1024-thread workgroup;
 // a slab stages only the parts its columns reach
