@@ -153,7 +153,10 @@ def stored_h_bytes(sched: int, ds, entries=None) -> int:
     16-bit tile-local codes and the complex values.  A sliced state reads its
     layout's entries (``entries``, from the plan; pads included) as 16-bit
     columns and complex values, 2 bytes of row order per row (per row and
-    column tile when tiled) and 8 bytes per slice (and per slab)."""
+    column tile when tiled) and 8 bytes per slice (and per slab); with the
+    flip-mask indices, 4 bytes per three entries and at most 2 KiB of masks
+    per row block in place of the columns."""
+    from paper_2606_29692_amd import binding as B
     x16, rv = plan_sched_x16(sched, ds), plan_sched_real(sched, ds)
     pad = rv or plan_sched_pad(sched, ds)
     tot = 0
@@ -163,8 +166,10 @@ def stored_h_bytes(sched: int, ds, entries=None) -> int:
             nb = -(-d.H.dim // (SELLT_ROWS if big else BLK_ROWS))
             nt = -(-d.H.dim // (SELLT_TILE_BYTES // d.psi.element_size())) if big else 1
             vb = d.H.val.element_size() // (2 if rv else 1)
+            xi = bool(sched & B.VQE_SPMV_XIDX) and not big
+            codes = (entries[i] // 3 * 4 + 2048 * nb) if xi else 2 * entries[i]
             tot += 2 * d.H.dim * nt + 8 * nb * nt * (BLK_ROWS // 64 + (1 if big else 0)) + \
-                entries[i] * (2 + vb) + 2 * d.H.dim * d.psi.element_size()
+                codes + entries[i] * vb + 2 * d.H.dim * d.psi.element_size()
             continue
         if plan_blocked(sched, d):
             tc = BLK_TILE_BYTES // d.psi.element_size()
@@ -630,7 +635,9 @@ def main():
             "h_product_GBps": achieved, "h_product_frac_of_peak": achieved / HBM_PEAK_GBS,
             "traffic_bytes_per_launch": measured_traffic(sched, wl),
             "stored_bytes_per_launch": stored, "stored_GBps": stored / h_s / 1e9,
-            "column_form": ("16-bit columns, one row per lane in slices of 64 rows sorted by "
+            "column_form": (("10-bit flip-mask indices (three per 32-bit word)"
+                             if sched & B.VQE_SPMV_XIDX and not plan_tiled(ds) else "16-bit columns") +
+                            ", one row per lane in slices of 64 rows sorted by "
                             "length" + (" per column tile" if plan_tiled(ds) else "") +
                             (", real values" if rv else "")
                             if all(plan_sliced(sched, d) for d in ds) else

@@ -32,6 +32,7 @@ VQE_SPMV_X16 = 0x4000
 VQE_SPMV_REAL = 0x8000
 VQE_SPMV_PAD = 0x10000
 VQE_SPMV_SLICED = 0x40000
+VQE_SPMV_XIDX = 0x80000
 REL_TIE = 1e-6
 
 DTYPES = {"c128": VQE_C128, "c64": VQE_C64}

@@ -367,36 +367,61 @@ int sliced_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs &b, S
                  int64_t *entries, int s)
 {
     const int E = sched & 0xff;
+    const bool xi = (sched & VQE_SPMV_XIDX) != 0;
     const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
     const int64_t ns = nb * SPMV_SLICES_PER_BLOCK;
     const size_t o_len = vqe_align((size_t)H->dim * sizeof(uint16_t));
     const size_t o_sl = o_len + vqe_align((size_t)ns * sizeof(int32_t));
     const size_t o_tot = o_sl + vqe_align((size_t)ns * sizeof(int2));
-    int rc = grow_ctx(ctx, b.meta, b.meta_cap, (int64_t)(o_tot + sizeof(int64_t)), "slice table", s);
+    // the index form: the masks' marks, numbers, table and count
+    const size_t o_mark = o_tot + vqe_align(sizeof(int64_t));
+    const size_t o_xmap = o_mark + vqe_align((size_t)H->dim * sizeof(uint32_t));
+    const size_t o_xtab = o_xmap + vqe_align((size_t)H->dim * sizeof(uint16_t));
+    const size_t o_nx = o_xtab + vqe_align((size_t)SPMV_XIDX_MAX * sizeof(uint16_t));
+    const size_t need = xi ? o_nx + sizeof(int64_t) : o_tot + sizeof(int64_t);
+    int rc = grow_ctx(ctx, b.meta, b.meta_cap, (int64_t)need, "slice table", s);
     if (rc)
         return rc;
     char *m = (char *)*b.meta;
     launch_sell_layout(H, E, (uint16_t *)m, (int32_t *)(m + o_len), (int2 *)(m + o_sl),
                        (int64_t *)(m + o_tot), ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
-    int64_t total = 0;
+    if (xi) {
+        launch_sell_xtab(H, (uint32_t *)(m + o_mark), (uint16_t *)(m + o_xmap), (uint16_t *)(m + o_xtab),
+                         (int64_t *)(m + o_nx), ctx->stream);
+        VQE_LAUNCH_CHECK(ctx);
+    }
+    int64_t total = 0, nx = 0;
     VQE_HIP(ctx, hipMemcpyAsync(&total, m + o_tot, sizeof(total), hipMemcpyDeviceToHost, ctx->stream));
+    if (xi)
+        VQE_HIP(ctx, hipMemcpyAsync(&nx, m + o_nx, sizeof(nx), hipMemcpyDeviceToHost, ctx->stream));
     VQE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (total < 0 || total > 0x7fffffffLL)
         return vqe_fail(ctx, VQE_ESIZE, "sliced layout of slot %d: %lld entries", s, (long long)total);
+    if (nx < 0 || nx > SPMV_XIDX_MAX)
+        return vqe_fail(ctx, VQE_ENOTSUP, "sliced layout of slot %d: %lld flip masks, more than the "
+                        "index form's %d", s, (long long)nx, SPMV_XIDX_MAX);
     const int64_t n = total > 0 ? total : 1;
     const bool real = (sched & VQE_SPMV_REAL) != 0;
     const int64_t vb = (int64_t)vqe_elem_bytes(H->dtype) / (real ? 2 : 1);
-    if ((rc = grow_ctx(ctx, b.code, b.code_cap, n * 2, "slice codes", s)) ||
+    // 16-bit columns, or one 32-bit word per three entries (whole groups)
+    const int64_t cb = xi ? (n + 2) / 3 * 4 + 8 : n * 2;
+    if ((rc = grow_ctx(ctx, b.code, b.code_cap, cb, "slice codes", s)) ||
         (rc = grow_ctx(ctx, b.val, b.val_cap, n * vb, "slice values", s)))
         return rc;
-    launch_sell_fill(H, E, real, (const uint16_t *)m, (const int2 *)(m + o_sl),
-                     (uint16_t *)*b.code, *b.val, ctx->stream);
+    if (xi)
+        launch_sell_fill_x(H, real, (const uint16_t *)m, (const int2 *)(m + o_sl),
+                           (const uint16_t *)(m + o_xmap), (uint32_t *)*b.code, *b.val, ctx->stream);
+    else
+        launch_sell_fill(H, E, real, (const uint16_t *)m, (const int2 *)(m + o_sl),
+                         (uint16_t *)*b.code, *b.val, ctx->stream);
     VQE_LAUNCH_CHECK(ctx);
     st.scode = (const uint16_t *)*b.code;
     st.sval = *b.val;
     st.srow = (const uint16_t *)m;
     st.sslice = (const int2 *)(m + o_sl);
+    st.sxtab = xi ? (const uint16_t *)(m + o_xtab) : nullptr;
+    st.nx = (int32_t)nx;
     *entries = total;
     return VQE_OK;
 }
@@ -1337,6 +1362,8 @@ int rebind_impl(vqe_batch *p, int32_t slot, const vqe_batch_item *it, const vqe_
         st->sval = layout->st.sval;
         st->srow = layout->st.srow;
         st->sslice = layout->st.sslice;
+        st->sxtab = layout->st.sxtab;
+        st->nx = layout->st.nx;
         if (sched & VQE_SPMV_BLOCKED) {
             st->boff = layout->st.boff;
             st->smask = layout->st.smask;

@@ -310,6 +310,15 @@ void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, 
 // parts with real)
 void launch_sell_fill(const vqe_csr *H, int E, bool real, const uint16_t *srow,
                       const int2 *sslice, uint16_t *code, void *val, hipStream_t s);
+// flip-mask index form (VQE_SPMV_XIDX): the masks col ^ row the operator
+// uses, numbered ascending (xmap [dim], with mark [dim] as scratch), the
+// first SPMV_XIDX_MAX of them in xtab and their count in *nx ...
+void launch_sell_xtab(const vqe_csr *H, uint32_t *mark, uint16_t *xmap, uint16_t *xtab, int64_t *nx,
+                      hipStream_t s);
+// ... then, with room for the slices' entries, the packed indices (one
+// 32-bit word per three entries) and the values
+void launch_sell_fill_x(const vqe_csr *H, bool real, const uint16_t *srow, const int2 *sslice,
+                        const uint16_t *xmap, uint32_t *code, void *val, hipStream_t s);
 // sliced layout of a column-tiled state (VQE_SPMV_SLICED on a state larger
 // than LDS): per slab of the blocked layout (nt tiles of tc columns) the row
 // order srow [slabs * SPMV_SELLT_ROWS] (first the rows' entry counts), the

@@ -1001,6 +1001,111 @@ k_sell_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     }
 }
 
+// Flip-mask index form (VQE_SPMV_XIDX): the masks x = col ^ row an operator
+// uses (Eq. 3: every Pauli string maps r to r ^ x), numbered in ascending
+// order, and the slices' entries stored as those numbers.
+__global__ void __launch_bounds__(256)
+k_sell_xclear(uint32_t *__restrict__ mark, int64_t dim)
+{
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (x < dim)
+        mark[x] = 0u;
+}
+
+// mark[x] = 1 for every mask the operator uses; one thread per row (col and
+// row are below dim = 2^N, so is their XOR).
+__global__ void __launch_bounds__(256)
+k_sell_xmark(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int64_t dim,
+             uint32_t *__restrict__ mark)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= dim)
+        return;
+    for (int k = rowptr[r]; k < rowptr[r + 1]; k++)
+        mark[(uint32_t)col[k] ^ (uint32_t)r] = 1u;
+}
+
+// The masks' numbers xmap[x] (ascending x), the table xtab[number] = x for
+// the first SPMV_XIDX_MAX numbers and the count; one workgroup (dim <= 2^16).
+__global__ void __launch_bounds__(1024)
+k_sell_xscan(const uint32_t *__restrict__ mark, int64_t dim, uint16_t *__restrict__ xmap,
+             uint16_t *__restrict__ xtab, int64_t *__restrict__ nx)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (dim + 1023) / 1024;
+    const int64_t lo = (int64_t)tid * per < dim ? (int64_t)tid * per : dim;
+    const int64_t hi = lo + per < dim ? lo + per : dim;
+    int c = 0;
+    for (int64_t x = lo; x < hi; x++)
+        c += mark[x] != 0u;
+    part[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int at = part[tid] - c;
+    for (int64_t x = lo; x < hi; x++)
+        if (mark[x]) {
+            xmap[x] = (uint16_t)at;
+            if (at < SPMV_XIDX_MAX)
+                xtab[at] = (uint16_t)x;
+            at++;
+        }
+    if (tid == 1023)
+        *nx = part[1023];
+}
+
+// Indices and values of one slice per wave (E = SPMV_XIDX_E; pads: index 0,
+// value zero); RV: the values' real parts.
+template <int DT, bool RV>
+__global__ void __launch_bounds__(64)
+k_sell_fill_x(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+              const void *__restrict__ val, int64_t dim, const uint16_t *__restrict__ srow,
+              const int2 *__restrict__ sslice, const uint16_t *__restrict__ xmap,
+              uint32_t *__restrict__ code, void *__restrict__ sval)
+{
+    using T = typename Elem<DT>::T;
+    using V = typename ValOf<DT, RV>::T;
+    constexpr int E = SPMV_XIDX_E;
+    const int64_t c = blockIdx.x;
+    const int64_t r0 = (c / SPMV_SLICES_PER_BLOCK) * SPMV_LDS_ROWS;
+    const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
+    const int lane = threadIdx.x;
+    const int i = (int)(c % SPMV_SLICES_PER_BLOCK) * VQE_WAVE + lane;
+    const int2 sl = sslice[c];
+    int64_t k0 = 0, row = 0;
+    int len = 0;
+    if (i < n) {
+        row = r0 + srow[r0 + i];
+        k0 = rowptr[row];
+        len = rowptr[row + 1] - (int32_t)k0;
+    }
+    V *out = reinterpret_cast<V *>(sval);
+    const T *in = reinterpret_cast<const T *>(val);
+    for (int g = 0; g < sl.y / E; g++) {
+        // the group's first entry: a multiple of E, so its words start at a
+        // multiple of two
+        const int64_t at = (int64_t)sl.x + ((int64_t)g * VQE_WAVE + lane) * E;
+        uint32_t w[2] = {0u, 0u};
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int j = g * E + e;
+            const uint32_t idx = j < len ? xmap[(uint32_t)col[k0 + j] ^ (uint32_t)row] : 0u;
+            w[e / 3] |= idx << (10 * (e % 3));
+            if constexpr (RV)
+                out[at + e] = j < len ? in[k0 + j].x : V{};
+            else
+                out[at + e] = j < len ? in[k0 + j] : V{};
+        }
+        code[at / 3] = w[0];
+        code[at / 3 + 1] = w[1];
+    }
+}
+
 // One entry's product added to the row's sums in turn (each product with its
 // own FMA): complex value and state; real value, complex state; real value,
 // real state (FP64 real parts).
@@ -1042,6 +1147,7 @@ template <int DT, int E, bool RV = false>
 struct SellGroup {
     using T = typename Elem<DT>::T;
     using V = typename ValOf<DT, RV>::T;
+    using C = uint16_t;     // the layout's code unit
     unsigned c[E / 2];
     V v[E];
     __device__ __forceinline__ void load(const uint16_t *__restrict__ code,
@@ -1104,25 +1210,84 @@ struct SellGroup {
     }
 };
 
+// The same for the flip-mask index form: SPMV_XIDX_E entries per lane, their
+// indices in two 32-bit words (three 10-bit fields each); an entry's column
+// is the lane's row XOR the indexed mask.
+template <int DT, bool RV = false>
+struct SellGroupX {
+    using V = typename ValOf<DT, RV>::T;
+    using C = uint32_t;
+    static constexpr int E = SPMV_XIDX_E;
+    unsigned c[2];
+    V v[E];
+    // at: the group's first entry (a multiple of E, so the words are 8-byte
+    // and the values 16-byte aligned, 8-byte for FP32 real parts)
+    __device__ __forceinline__ void load(const uint32_t *__restrict__ code, const V *__restrict__ val,
+                                         int64_t at)
+    {
+        const sell_v2u w = gmem(reinterpret_cast<const sell_v2u *>(code + at / 3))[0];
+        c[0] = w.x;
+        c[1] = w.y;
+        if constexpr (RV && DT == VQE_C64) {
+#pragma unroll
+            for (int q = 0; q < E / 2; q++) {
+                const vqe_v2f a = gmem(reinterpret_cast<const vqe_v2f *>(val + at))[q];
+                v[2 * q] = a.x;
+                v[2 * q + 1] = a.y;
+            }
+        } else if constexpr (RV) {
+#pragma unroll
+            for (int q = 0; q < E / 2; q++) {
+                const vqe_v2d a = gmem(reinterpret_cast<const vqe_v2d *>(val + at))[q];
+                v[2 * q] = a.x;
+                v[2 * q + 1] = a.y;
+            }
+        } else if constexpr (DT == VQE_C64) {
+#pragma unroll
+            for (int q = 0; q < E / 2; q++) {
+                const vqe_v4f a = gmem(reinterpret_cast<const vqe_v4f *>(val + at))[q];
+                v[2 * q] = make_float2(a.x, a.y);
+                v[2 * q + 1] = make_float2(a.z, a.w);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < E; q++)
+                v[q] = ldg(val, at + q);
+        }
+    }
+    // each product added to the row's sums in turn; s_xt: the masks staged in
+    // LDS, row: the lane's row
+    template <typename X>
+    __device__ __forceinline__ void use(const X *s_x, const uint16_t *s_xt, uint32_t row, double &are,
+                                        double &aim) const
+    {
+#pragma unroll
+        for (int q = 0; q < E; q++)
+            sell_fma(v[q], s_x[row ^ (uint32_t)s_xt[(c[q / 3] >> (10 * (q % 3))) & 1023u]], are, aim);
+    }
+};
+
 // One wave's share of a block of the sliced layout: slices A = wid and
 // B = wid + 16 (those the block has), taken as one stream of groups (A's,
 // then B's) so that B's first groups load while A finishes; D groups of E
 // entries per lane in flight.  Every load is issued (past the stream's end
 // it repeats the last group, which is in cache), so no load sits under a
 // branch and each group's wait leaves the later groups' loads in flight.
-template <int DT, int E, int D, bool RV>
+template <int DT, int E, int D, bool RV, bool XI = false>
 struct SellWave {
     using V = typename ValOf<DT, RV>::T;
+    using G = typename std::conditional<XI, SellGroupX<DT, RV>, SellGroup<DT, E, RV>>::type;
     static constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
-    const uint16_t *code;
+    const typename G::C *code;
     const V *val;
     int64_t r0, ata, atb;
     int n, ns, nga, ngb, ng, ra, rb;   // ra, rb: block-local rows of this lane
-    SellGroup<DT, E, RV> g[D];
+    G g[D];
 
     __device__ __forceinline__ void init(const SpmvState &st, int blk, int lane, int wid)
     {
-        code = st.scode;
+        static_assert(!XI || E == SPMV_XIDX_E, "the index form has its own group");
+        code = reinterpret_cast<const typename G::C *>(st.scode);
         val = reinterpret_cast<const V *>(st.sval);
         r0 = (int64_t)blk * SPMV_LDS_ROWS;
         n = (int)(st.dim - r0 < SPMV_LDS_ROWS ? st.dim - r0 : SPMV_LDS_ROWS);
@@ -1157,15 +1322,23 @@ struct SellWave {
             g[d].load(code, val, addr(d));
     }
     // the rows' sums for A and B against the staged state s_x (X: complex, or
-    // the real parts in FP64 for a real state); prefetch() came first
+    // the real parts in FP64 for a real state; s_xt: the staged flip masks of
+    // the index form); prefetch() came first
     template <typename X>
-    __device__ __forceinline__ void run(const X *s_x, double2 &sa, double2 &sb)
+    __device__ __forceinline__ void run(const X *s_x, const uint16_t *s_xt, double2 &sa, double2 &sb)
     {
         double are = 0.0, aim = 0.0;
         sa = make_double2(0.0, 0.0);
         sb = make_double2(0.0, 0.0);
         if (ng == 0)
             return;
+        uint32_t row = (uint32_t)(r0 + ra);
+        auto use = [&](const G &gr) {
+            if constexpr (XI)
+                gr.use(s_x, s_xt, row, are, aim);
+            else
+                gr.use(s_x, are, aim);
+        };
         int q = 0;
         for (; q + D <= ng; q += D) {
 #pragma unroll
@@ -1173,8 +1346,9 @@ struct SellWave {
                 if (q + d == nga) {     // B's first group: A's sums are done
                     sa = make_double2(are, aim);
                     are = aim = 0.0;
+                    row = (uint32_t)(r0 + rb);
                 }
-                g[d].use(s_x, are, aim);
+                use(g[d]);
                 g[d].load(code, val, addr(q + D + d));
                 // keep the refill ahead of the next group's products
                 __builtin_amdgcn_sched_barrier(0);
@@ -1186,8 +1360,9 @@ struct SellWave {
                 if (q + d == nga) {
                     sa = make_double2(are, aim);
                     are = aim = 0.0;
+                    row = (uint32_t)(r0 + rb);
                 }
-                g[d].use(s_x, are, aim);
+                use(g[d]);
             }
         if (ngb == 0)
             sa = make_double2(are, aim);
@@ -1198,8 +1373,8 @@ struct SellWave {
 
 // The block's rows from a wave's sums: sigma (FP32 storage: gathered in LDS
 // and stored in row order), the energy terms and the block's partials.
-template <int DT, int E, int D, bool RV, typename X>
-__device__ __forceinline__ void sell_finish(const SpmvState &st, int blk, const SellWave<DT, E, D, RV> &w,
+template <int DT, int E, int D, bool RV, bool XI, typename X>
+__device__ __forceinline__ void sell_finish(const SpmvState &st, int blk, const SellWave<DT, E, D, RV, XI> &w,
                                             const X *s_x, float2 *s_sig, double2 sa, double2 sb)
 {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1247,8 +1422,11 @@ __device__ __forceinline__ void sell_finish(const SpmvState &st, int blk, const 
 // groups are loaded together with the staged state.  With RV (the real parts
 // of a real H) a state whose imaginary parts are all zero is staged as FP64
 // real parts and multiplied in real arithmetic; any other state takes the
-// complex staging in the same launch.
-template <int DT, int E, int D, bool RV>
+// complex staging in the same launch.  XI: the flip-mask index form, its
+// masks staged after the block's results (every one of the SPMV_XIDX_MAX
+// slots written, zero past the operator's count, so every index gives a
+// column below dim).
+template <int DT, int E, int D, bool RV, bool XI>
 __global__ void __launch_bounds__(1024) VQE_LDS_OCCUPANCY
 k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks)
 {
@@ -1265,8 +1443,14 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
     const T *psi = reinterpret_cast<const T *>(st.psi);
     // FP32 storage: the block's results gather in LDS after the state
     float2 *s_sig = reinterpret_cast<float2 *>(smem + (size_t)(dim + 1) * sizeof(T));
-    SellWave<DT, E, D, RV> w;
+    uint16_t *s_xt = reinterpret_cast<uint16_t *>(
+        smem + (size_t)(dim + 1) * sizeof(T) + (DT == VQE_C64 ? SPMV_LDS_ROWS * sizeof(float2) : 0));
+    SellWave<DT, E, D, RV, XI> w;
     w.init(st, t.y, lane, wid);
+    if constexpr (XI) {
+        static_assert(SPMV_XIDX_MAX <= 1024, "one mask per thread");
+        s_xt[tid] = tid < st.nx ? gmem(st.sxtab)[tid] : (uint16_t)0;
+    }
     double2 sa, sb;
     if constexpr (RV) {
         if (w.ng > 0)
@@ -1276,7 +1460,7 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
         if (tid == 0)
             s_xr[dim] = 0.0;
         if (!__syncthreads_or(cplx)) {
-            w.run(s_xr, sa, sb);
+            w.run(s_xr, s_xt, sa, sb);
             sell_finish(st, t.y, w, s_xr, s_sig, sa, sb);
             return;
         }
@@ -1309,7 +1493,7 @@ k_spmv_sell(const SpmvState *__restrict__ states, const int2 *__restrict__ tasks
     if (tid == 0)
         s_x[dim] = T{};
     __syncthreads();
-    w.run(s_x, sa, sb);
+    w.run(s_x, s_xt, sa, sb);
     sell_finish(st, t.y, w, s_x, s_sig, sa, sb);
 }
 
@@ -1987,15 +2171,16 @@ static void launch_spmv_pf_t(const SpmvState &single, const SpmvState *states, c
 
 // Sliced schedules: E entries per lane and load group, D groups in flight;
 // rv: the real parts of the values (VQE_SPMV_REAL).
-template <int DT, int E, int D>
+template <int DT, int E, int D, bool XI = false>
 static void launch_sell_t(const SpmvState *states, const int2 *tasks, unsigned grid, hipStream_t s,
                           size_t lds, bool rv)
 {
     // the state (with its zero element; lds counts it with the row pointers
-    // of the other LDS schedules) and, in FP32 storage, a block of results
+    // of the other LDS schedules), in FP32 storage a block of results, and
+    // the flip masks of the index form
     lds = lds - (SPMV_LDS_ROWS + 1) * sizeof(int32_t) +
-          (DT == VQE_C64 ? SPMV_LDS_ROWS * sizeof(float2) : 0);
-    auto k = rv ? k_spmv_sell<DT, E, D, true> : k_spmv_sell<DT, E, D, false>;
+          (DT == VQE_C64 ? SPMV_LDS_ROWS * sizeof(float2) : 0) + (XI ? SPMV_XIDX_MAX * sizeof(uint16_t) : 0);
+    auto k = rv ? k_spmv_sell<DT, E, D, true, XI> : k_spmv_sell<DT, E, D, false, XI>;
     (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k<<<grid, 1024, lds, s>>>(states, tasks);
 }
@@ -2009,6 +2194,10 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
         // (FP64 values keep half as many groups in flight: the registers)
         constexpr bool W = DT == VQE_C128;
         const bool rv = (sched & VQE_SPMV_REAL) != 0;
+        if (sched & VQE_SPMV_XIDX) {
+            launch_sell_t<DT, SPMV_XIDX_E, W ? 1 : 3, true>(states, tasks, grid, s, lds, rv);
+            return;
+        }
         switch (sched & 0xff) {
         case 2: launch_sell_t<DT, 2, W ? 2 : 4>(states, tasks, grid, s, lds, rv); return;
         case 8: launch_sell_t<DT, 8, W ? 1 : 2>(states, tasks, grid, s, lds, rv); return;
@@ -2564,6 +2753,25 @@ void launch_sell_layout(const vqe_csr *H, int E, uint16_t *srow, int32_t *slen, 
     k_sell_scan<<<1, 64, 0, s>>>(slen, nb * SPMV_SLICES_PER_BLOCK, sslice, total);
 }
 
+void launch_sell_xtab(const vqe_csr *H, uint32_t *mark, uint16_t *xmap, uint16_t *xtab, int64_t *nx,
+                      hipStream_t s)
+{
+    const unsigned g = (unsigned)((H->dim + 255) / 256);
+    k_sell_xclear<<<g, 256, 0, s>>>(mark, H->dim);
+    k_sell_xmark<<<g, 256, 0, s>>>(H->rowptr, H->col, H->dim, mark);
+    k_sell_xscan<<<1, 1024, 0, s>>>(mark, H->dim, xmap, xtab, nx);
+}
+
+void launch_sell_fill_x(const vqe_csr *H, bool real, const uint16_t *srow, const int2 *sslice,
+                        const uint16_t *xmap, uint32_t *code, void *val, hipStream_t s)
+{
+    const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
+    const unsigned g = (unsigned)(nb * SPMV_SLICES_PER_BLOCK);
+    auto k = H->dtype == VQE_C128 ? (real ? k_sell_fill_x<VQE_C128, true> : k_sell_fill_x<VQE_C128, false>)
+                                  : (real ? k_sell_fill_x<VQE_C64, true> : k_sell_fill_x<VQE_C64, false>);
+    k<<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, srow, sslice, xmap, code, val);
+}
+
 void launch_sellt_layout(const vqe_csr *H, int32_t nt, int32_t tc, int E, uint16_t *srow,
                          int2 *sslice, int64_t *stot, int64_t *sbase, int64_t *total, uint32_t *smask,
                          hipStream_t s)
@@ -2711,6 +2919,8 @@ bool vqe_valid_schedule(int sched)
     case 2 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
     case 4 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
     case 8 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
+    case SPMV_XIDX_E | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX:
+    case SPMV_XIDX_E | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX | VQE_SPMV_REAL:
         return true;
     default:
         return false;
@@ -2727,8 +2937,13 @@ int vqe_effective_schedule(const vqe_csr *H, int sched)
     if (sched & VQE_SPMV_SLICED) {
         if (H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES || H->dim >= 65536)
             return vqe_effective_schedule(H, 32 | VQE_SPMV_LDS | VQE_SPMV_PREFETCH | VQE_SPMV_X16);
+        // the index form stages its masks too (states of up to 128 KiB)
+        if ((sched & VQE_SPMV_XIDX) &&
+            (H->dim + 1) * (int64_t)vqe_elem_bytes(H->dtype) + SPMV_LDS_ROWS * (int64_t)sizeof(float2) +
+                    SPMV_XIDX_MAX * (int64_t)sizeof(uint16_t) > 160 * 1024)
+            sched = (sched & ~(VQE_SPMV_XIDX | 0xff)) | 4;
         // the real values need an operator flagged real
-        return sched & (VQE_SPMV_SLICED | VQE_SPMV_LDS | 0xff |
+        return sched & (VQE_SPMV_SLICED | VQE_SPMV_LDS | VQE_SPMV_XIDX | 0xff |
                         ((H->flags & VQE_REAL) ? VQE_SPMV_REAL : 0));
     }
     // four lanes per row exist only in the blocked product of states larger
@@ -2768,9 +2983,13 @@ int vqe_batch_schedule(const vqe_csr *H, int sched)
     const bool big = H->dim * (int64_t)vqe_elem_bytes(H->dtype) > SPMV_LDS_MAX_BYTES;
     // a sliced schedule runs a state larger than LDS in the slabs of the
     // blocked layout, each sorted and sliced
-    if ((sched & VQE_SPMV_SLICED) && big)
+    if ((sched & VQE_SPMV_SLICED) && big) {
+        // (the index form's states fit LDS; larger ones take two entries per group)
+        if (sched & VQE_SPMV_XIDX)
+            sched = (sched & ~(VQE_SPMV_XIDX | 0xff)) | 2;
         return (sched & (0xff | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_DEEP)) | VQE_SPMV_TILED |
                VQE_SPMV_BLOCKED;
+    }
     const bool aligned = ((((uintptr_t)H->col) & 15) == 0) && ((((uintptr_t)H->val) & 31) == 0);
     if (big && (sched & VQE_SPMV_LDS) && (sched & VQE_SPMV_PREFETCH) && H->dim <= ((int64_t)1 << 30)) {
         // the real-value form keeps the column-tiled CSR (16-bit col ^ row

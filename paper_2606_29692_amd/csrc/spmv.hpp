@@ -85,6 +85,12 @@ struct SpmvState {
     const uint16_t *srow;
     const int2 *sslice;
     const uint32_t *smask;
+    // flip-mask index form (VQE_SPMV_XIDX): the operator's flip masks,
+    // ascending, sxtab[0 .. nx); scode then holds 32-bit words of three
+    // 10-bit indices, word (start + ((j / 6) * 64 + i) * 6) / 3 + (j % 6) / 3
+    // holding entry j of lane i in bits 10 * (j % 3)
+    const uint16_t *sxtab;
+    int32_t nx;
 };
 
 // Column-tiled H product: tile width (state elements staged in LDS per pass)
@@ -108,6 +114,9 @@ struct SpmvState {
 #define SPMV_SELLT_PART_BYTES (16 * 1024)
 // Sliced layout: slices of one wave's rows per block of SPMV_LDS_ROWS rows.
 #define SPMV_SLICES_PER_BLOCK (SPMV_LDS_ROWS / VQE_WAVE)
+// flip-mask index form: table entries (10-bit indices) and entries per group
+#define SPMV_XIDX_MAX 1024
+#define SPMV_XIDX_E 6
 // largest dimension whose column XOR row fits 16 bits
 #define SPMV_X16_MAX_DIM 65536
 // row length granule of the padded layout (real values, states that fit LDS)

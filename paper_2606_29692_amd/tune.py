@@ -28,6 +28,7 @@ from . import binding as B
 
 _L, _V, _D, _P = B.VQE_SPMV_LDS, B.VQE_SPMV_VEC4, B.VQE_SPMV_DEEP, B.VQE_SPMV_PREFETCH
 _X, _R, _Q, _S = B.VQE_SPMV_X16, B.VQE_SPMV_REAL, B.VQE_SPMV_PAD, B.VQE_SPMV_SLICED
+_I = B.VQE_SPMV_XIDX
 CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               8 | _L, 16 | _L, 32 | _L, 64 | _L, 8 | _L | _D, 16 | _L | _D, 32 | _L | _D, 64 | _L | _D,
               32 | _L | _P, 64 | _L | _P, 32 | _L | _P | _D, 64 | _L | _P | _D,
@@ -43,7 +44,9 @@ CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               16 | _L | _P | _D | _X, 4 | _L | _P, 4 | _L | _P | _D, 4 | _L | _P | _X,
               # one row per lane, rows sorted by length into slices of 64
               2 | _L | _S, 4 | _L | _S, 8 | _L | _S, 2 | _L | _S | _D, 4 | _L | _S | _D,
-              2 | _L | _S | _R, 4 | _L | _S | _R, 8 | _L | _S | _R)
+              2 | _L | _S | _R, 4 | _L | _S | _R, 8 | _L | _S | _R,
+              # and with the flip masks' 10-bit indices in place of the columns
+              6 | _L | _S | _I, 6 | _L | _S | _I | _R)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}
@@ -89,9 +92,15 @@ def _store(key: str, rec: dict):
 
 def time_batch_spmv(ctx, systems, schedule: int, reps: int = 10) -> float:
     """Milliseconds per launch of the batched H products with the given
-    schedule: the median of three runs of `reps` back-to-back launches."""
+    schedule: the median of three runs of `reps` back-to-back launches
+    (infinite for a schedule the operators do not support)."""
     from .batch import make_batch
-    plan = make_batch(ctx, systems, schedules=[schedule] * len(systems))
+    try:
+        plan = make_batch(ctx, systems, schedules=[schedule] * len(systems))
+    except B.VqeError as e:
+        if e.status != B.VQE_ENOTSUP:
+            raise
+        return float("inf")
     for _ in range(3):
         plan.step(update=False)
     times = [plan.time_products(reps) for _ in range(3)]

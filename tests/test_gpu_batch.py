@@ -23,6 +23,10 @@ from paper_2606_29692_amd import batch as PB  # noqa: E402
 from paper_2606_29692_amd import binding as B  # noqa: E402
 
 
+# the sliced layout with the flip masks' 10-bit indices in place of the columns
+XI = 6 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_XIDX
+
+
 @pytest.fixture(scope="module")
 def ctx():
     # one non-default stream (graph capture needs one) shared by torch and the
@@ -207,7 +211,7 @@ def test_fp32_batch_mixed_sizes_vs_oracle(ctx):
                                    B.VQE_SPMV_X16,
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
                                    B.VQE_SPMV_REAL,
-                                   4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED])
+                                   4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED, XI, XI | B.VQE_SPMV_REAL])
 def test_full_size_bench_config(ctx, sched):
     """64 states at 14 qubits in FP32 storage (the benchmark workload):
     sampled states against the oracle, invariants on every state."""
@@ -282,7 +286,8 @@ def test_full_size_bench_config(ctx, sched):
                                    4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
                                    8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
                                    4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL,
-                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL])
+                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL,
+                                   XI, XI | B.VQE_SPMV_REAL])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
@@ -312,7 +317,8 @@ def test_every_spmv_schedule_matches_oracle(ctx, sched):
 
 
 @pytest.mark.parametrize("sched", [e | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED for e in (2, 4, 8)] +
-                         [4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL])
+                         [4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL,
+                          XI, XI | B.VQE_SPMV_REAL])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_sliced_layout_sizes_vs_oracle(ctx, sched, dtype):
     """The sliced layout at register sizes that leave slices and blocks
@@ -415,7 +421,7 @@ def test_screen_full_pair_table(ctx):
                                    32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16 |
                                    B.VQE_SPMV_REAL,
                                    2 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
-                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED])
+                                   8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED, XI])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("op", ["half", "zero"])
 def test_spmv_rows_without_entries(ctx, sched, dtype, op):
@@ -505,6 +511,7 @@ S = B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
 
 
 @pytest.mark.parametrize("n_q,sched,real", [(12, 4 | S, False), (12, 8 | S | B.VQE_SPMV_REAL, True),
+                                            (12, XI, False), (12, XI | B.VQE_SPMV_REAL, True),
                                             (16, 2 | S, False), (16, 2 | S | B.VQE_SPMV_DEEP, False)])
 def test_prebuilt_layout_matches_own_layout(ctx, n_q, sched, real):
     """A slot pointed to a prebuilt sliced layout of H (vqe_layout_create,
@@ -549,6 +556,45 @@ def test_prebuilt_layout_matches_own_layout(ctx, n_q, sched, real):
     Lb.close()
 
 
+def test_flip_mask_indices_sum_like_columns_and_refuse_too_many_masks(ctx):
+    """The sliced layout with flip-mask indices gives the sigma and energy
+    of the one with 16-bit columns bit for bit (each lane sums its row's
+    entries in the same order; the pads only add zeros), and both match the
+    oracle; an operator with more than 1024 distinct flip masks is refused
+    with VQE_ENOTSUP by the plan and by vqe_layout_create."""
+    s = vs.make_system(vs.SystemSpec(12, 8, "jw", False, 61))
+    pool = B.pool_from_packs(ctx, s.pool, "c64")
+    H = B.csr_from_pack(ctx, s.hamiltonian, "c64")
+    rng = np.random.default_rng(61)
+    v = rng.standard_normal(1 << 12) + 1j * rng.standard_normal(1 << 12)
+    v /= np.linalg.norm(v)
+    psi = torch.from_numpy(v).to(torch.complex64).to(ctx.torch_device)
+    res = {}
+    for sched in (4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED, XI):
+        plan = B.BatchPlan(ctx, [(H, pool, psi)], schedules=[sched])
+        plan.step(update=False)
+        res[sched] = (host(plan.energies)[:3].copy(), host(plan.sigma[0]).astype(np.complex128))
+        plan.close()
+    vin = host(psi).astype(np.complex128)
+    e_o, _, _, sg_o = orc.energy(orc.csr_from_pack(s.hamiltonian), vin)
+    for e, sg in res.values():
+        assert abs(e[0] - e_o) <= 1e-6
+        assert np.linalg.norm(sg - sg_o) <= 2e-6 * np.linalg.norm(sg_o)
+    a, b = res.values()
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    # 1100 distinct flip masks
+    xs = rng.choice(1 << 12, size=1100, replace=False).astype(np.uint64)
+    many = vs.PauliPack(12, xs, np.zeros_like(xs), rng.standard_normal(xs.size) + 0j)
+    Hm = B.csr_from_pack(ctx, many, "c64")
+    with pytest.raises(B.VqeError) as err:
+        B.BatchPlan(ctx, [(Hm, pool, psi)], schedules=[XI])
+    assert err.value.status == B.VQE_ENOTSUP
+    with pytest.raises(B.VqeError) as err:
+        B.Layout(ctx, Hm, XI)
+    assert err.value.status == B.VQE_ENOTSUP
+
+
 def _y_pack(n, x, z, c):
     return vs.PauliPack(n, np.array(x, dtype=np.uint64), np.array(z, dtype=np.uint64),
                         np.array(c, dtype=np.complex128))
@@ -574,17 +620,19 @@ def test_real_flag_from_terms(ctx):
             assert B.csr_from_pack(ctx, pack, dt).real == w
 
 
-@pytest.mark.parametrize("layout", ["padded", "sliced"])
+@pytest.mark.parametrize("layout", ["padded", "sliced", "indices"])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_real_values_match_complex_values(ctx, dtype, layout):
     """The real-value form against the complex-value form of the same
     schedule on the same (real) states: bit for bit in FP32 storage (every
-    product is exact in FP64) and, in the sliced layout (the same sums in the
-    same order), in FP64 storage too; to rounding in FP64 storage with the
+    product is exact in FP64) and, in the sliced layout with columns or with
+    flip-mask indices (the same sums in the same order), in FP64 storage too; to rounding in FP64 storage with the
     row-padded layout; both against the oracle."""
     x = 32 | B.VQE_SPMV_LDS | B.VQE_SPMV_PREFETCH | B.VQE_SPMV_X16
     if layout == "sliced":
         x = 4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
+    elif layout == "indices":
+        x = XI
     specs = [vs.SystemSpec(12, 6, "jw", False, 130), vs.SystemSpec(12, 4, "bk", False, 131),
              vs.SystemSpec(14, 6, "jw", True, 132)]
     systems = [vs.make_system(s) for s in specs]
@@ -603,7 +651,7 @@ def test_real_values_match_complex_values(ctx, dtype, layout):
         plan.close()
     a, b = out[x], out[x | B.VQE_SPMV_REAL]
     np.testing.assert_array_equal(a[3], b[3])
-    if dtype == "c64" or layout == "sliced":
+    if dtype == "c64" or layout in ("sliced", "indices"):
         np.testing.assert_array_equal(a[0], b[0])
         for i in range(3):
             np.testing.assert_array_equal(a[1][i], b[1][i])
