@@ -624,8 +624,9 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * to a 32-bit word, 1.33 bytes per entry instead of 2.  Pads take index 0
  * and the value zero.  The plan (or vqe_layout_create) reports VQE_ENOTSUP
  * for an operator with more than 1024 distinct flip masks; a state larger
- * than LDS runs the column-tiled sliced product with E = 2.  Results equal
- * those of the other sliced schedules to the rounding of FP64 sums.
+ * than LDS runs the column-tiled sliced product with E = 2.  Each lane adds
+ * its row's entries in the order of the 16-bit column form, so the results
+ * equal that form's bit for bit (the pads add zeros).
  */
 #define VQE_SPMV_XIDX 0x80000
 /*
