@@ -27,6 +27,9 @@ SCHED = {(8, 4, "jw"): 16,
 SLICED = B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED
 SCHED_SLICED = {(8, 4, "jw"): 4 | SLICED, (10, 4, "jw"): 4 | SLICED | B.VQE_SPMV_REAL,
                 (12, 8, "jw"): 2 | SLICED}
+# the same with the flip masks' 10-bit indices in place of the columns
+XI = 6 | SLICED | B.VQE_SPMV_XIDX
+SCHED_XIDX = {(8, 4, "jw"): XI, (10, 4, "jw"): XI | B.VQE_SPMV_REAL, (12, 8, "jw"): XI}
 
 
 def make_runs():
@@ -55,7 +58,7 @@ def by_run(reqs):
     return d
 
 
-@pytest.mark.parametrize("sched", [SCHED, SCHED_SLICED], ids=["csr", "sliced"])
+@pytest.mark.parametrize("sched", [SCHED, SCHED_SLICED, SCHED_XIDX], ids=["csr", "sliced", "indices"])
 def test_alone_vs_mixed_and_eviction(sched):
     systems, thetas = make_runs()
     trace = S.poisson_trace(150, rate=3000.0, n_runs=len(systems), seed=5)
@@ -80,7 +83,8 @@ def test_alone_vs_mixed_and_eviction(sched):
         np.testing.assert_array_equal(psi_small[r], psi_mixed[r])
 
 
-@pytest.mark.parametrize("sched", [SCHED, SCHED_SLICED, "tuned"], ids=["csr", "sliced", "tuned"])
+@pytest.mark.parametrize("sched", [SCHED, SCHED_SLICED, SCHED_XIDX, "tuned"],
+                         ids=["csr", "sliced", "indices", "tuned"])
 def test_served_runs_match_oracle(sched):
     systems, thetas = make_runs()
     trace = S.poisson_trace(120, rate=3000.0, n_runs=len(systems), seed=9)
