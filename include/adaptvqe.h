@@ -616,12 +616,12 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * rounding of FP64 sums. */
 #define VQE_SPMV_SLICED 0x40000
 /*
- * With VQE_SPMV_SLICED and E = 6, for a state that fits LDS: every entry's
+ * With VQE_SPMV_SLICED and E = 3 or 6, for a state that fits LDS: every entry's
  * column is row ^ x with x one of the operator's flip masks (Eq. 3: a Pauli
  * string maps basis state r to r ^ x), so the slices store the index of x in
  * a per-operator table of at most 1024 masks (ascending; 2 bytes each, staged
  * in LDS beside the state) instead of the 16-bit column: three 10-bit indices
- * to a 32-bit word, 1.33 bytes per entry instead of 2.  Pads take index 0
+ * to a 32-bit word (E / 3 words per group), 1.33 bytes per entry instead of 2.  Pads take index 0
  * and the value zero.  The plan (or vqe_layout_create) reports VQE_ENOTSUP
  * for an operator with more than 1024 distinct flip masks; a state larger
  * than LDS runs the column-tiled sliced product with E = 2.  Each lane adds

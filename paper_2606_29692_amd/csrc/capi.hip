@@ -410,7 +410,7 @@ int sliced_build(vqe_ctx *ctx, const vqe_csr *H, int sched, const SellBufs &b, S
         (rc = grow_ctx(ctx, b.val, b.val_cap, n * vb, "slice values", s)))
         return rc;
     if (xi)
-        launch_sell_fill_x(H, real, (const uint16_t *)m, (const int2 *)(m + o_sl),
+        launch_sell_fill_x(H, E, real, (const uint16_t *)m, (const int2 *)(m + o_sl),
                            (const uint16_t *)(m + o_xmap), (uint32_t *)*b.code, *b.val, ctx->stream);
     else
         launch_sell_fill(H, E, real, (const uint16_t *)m, (const int2 *)(m + o_sl),

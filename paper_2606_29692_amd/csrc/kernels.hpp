@@ -317,7 +317,7 @@ void launch_sell_xtab(const vqe_csr *H, uint32_t *mark, uint16_t *xmap, uint16_t
                       hipStream_t s);
 // ... then, with room for the slices' entries, the packed indices (one
 // 32-bit word per three entries) and the values
-void launch_sell_fill_x(const vqe_csr *H, bool real, const uint16_t *srow, const int2 *sslice,
+void launch_sell_fill_x(const vqe_csr *H, int E, bool real, const uint16_t *srow, const int2 *sslice,
                         const uint16_t *xmap, uint32_t *code, void *val, hipStream_t s);
 // sliced layout of a column-tiled state (VQE_SPMV_SLICED on a state larger
 // than LDS): per slab of the blocked layout (nt tiles of tc columns) the row

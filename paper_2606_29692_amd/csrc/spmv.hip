@@ -1059,9 +1059,9 @@ k_sell_xscan(const uint32_t *__restrict__ mark, int64_t dim, uint16_t *__restric
         *nx = part[1023];
 }
 
-// Indices and values of one slice per wave (E = SPMV_XIDX_E; pads: index 0,
-// value zero); RV: the values' real parts.
-template <int DT, bool RV>
+// Indices and values of one slice per wave (E = 3 or 6 entries per group,
+// E / 3 words; pads: index 0, value zero); RV: the values' real parts.
+template <int DT, bool RV, int E>
 __global__ void __launch_bounds__(64)
 k_sell_fill_x(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
               const void *__restrict__ val, int64_t dim, const uint16_t *__restrict__ srow,
@@ -1070,7 +1070,7 @@ k_sell_fill_x(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ co
 {
     using T = typename Elem<DT>::T;
     using V = typename ValOf<DT, RV>::T;
-    constexpr int E = SPMV_XIDX_E;
+    static_assert(E == 3 || E == 6, "three indices to a word");
     const int64_t c = blockIdx.x;
     const int64_t r0 = (c / SPMV_SLICES_PER_BLOCK) * SPMV_LDS_ROWS;
     const int n = (int)(dim - r0 < SPMV_LDS_ROWS ? dim - r0 : SPMV_LDS_ROWS);
@@ -1088,9 +1088,9 @@ k_sell_fill_x(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ co
     const T *in = reinterpret_cast<const T *>(val);
     for (int g = 0; g < sl.y / E; g++) {
         // the group's first entry: a multiple of E, so its words start at a
-        // multiple of two
+        // multiple of E / 3
         const int64_t at = (int64_t)sl.x + ((int64_t)g * VQE_WAVE + lane) * E;
-        uint32_t w[2] = {0u, 0u};
+        uint32_t w[E / 3] = {};
 #pragma unroll
         for (int e = 0; e < E; e++) {
             const int j = g * E + e;
@@ -1101,8 +1101,9 @@ k_sell_fill_x(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ co
             else
                 out[at + e] = j < len ? in[k0 + j] : V{};
         }
-        code[at / 3] = w[0];
-        code[at / 3 + 1] = w[1];
+#pragma unroll
+        for (int q = 0; q < E / 3; q++)
+            code[at / 3 + q] = w[q];
     }
 }
 
@@ -1210,21 +1211,33 @@ struct SellGroup {
     }
 };
 
-// The same for the flip-mask index form: SPMV_XIDX_E entries per lane, their
-// indices in two 32-bit words (three 10-bit fields each); an entry's column
+// The same for the flip-mask index form: E = 3 or 6 entries per lane, their
+// indices in E / 3 32-bit words (three 10-bit fields each); an entry's column
 // is the lane's row XOR the indexed mask.
-template <int DT, bool RV = false>
+template <int DT, bool RV, int E>
 struct SellGroupX {
     using V = typename ValOf<DT, RV>::T;
     using C = uint32_t;
-    static constexpr int E = SPMV_XIDX_E;
-    unsigned c[2];
+    static_assert(E == 3 || E == 6, "three indices to a word");
+    unsigned c[E / 3];
     V v[E];
-    // at: the group's first entry (a multiple of E, so the words are 8-byte
-    // and the values 16-byte aligned, 8-byte for FP32 real parts)
+    // at: the group's first entry (a multiple of E: with E = 6 the words are
+    // 8-byte and the values 16-byte aligned, 8-byte for FP32 real parts; with
+    // E = 3 the values are aligned to their own size)
     __device__ __forceinline__ void load(const uint32_t *__restrict__ code, const V *__restrict__ val,
                                          int64_t at)
     {
+        if constexpr (E == 3) {
+            c[0] = gmem(code)[at / 3];
+#pragma unroll
+            for (int q = 0; q < E; q++) {
+                if constexpr (RV)
+                    v[q] = gmem(val)[at + q];
+                else
+                    v[q] = ldg(val, at + q);
+            }
+            return;
+        }
         const sell_v2u w = gmem(reinterpret_cast<const sell_v2u *>(code + at / 3))[0];
         c[0] = w.x;
         c[1] = w.y;
@@ -1276,7 +1289,7 @@ struct SellGroupX {
 template <int DT, int E, int D, bool RV, bool XI = false>
 struct SellWave {
     using V = typename ValOf<DT, RV>::T;
-    using G = typename std::conditional<XI, SellGroupX<DT, RV>, SellGroup<DT, E, RV>>::type;
+    using G = typename std::conditional<XI, SellGroupX<DT, RV, E>, SellGroup<DT, E, RV>>::type;
     static constexpr int64_t STEP = (int64_t)VQE_WAVE * E;
     const typename G::C *code;
     const V *val;
@@ -1286,7 +1299,6 @@ struct SellWave {
 
     __device__ __forceinline__ void init(const SpmvState &st, int blk, int lane, int wid)
     {
-        static_assert(!XI || E == SPMV_XIDX_E, "the index form has its own group");
         code = reinterpret_cast<const typename G::C *>(st.scode);
         val = reinterpret_cast<const V *>(st.sval);
         r0 = (int64_t)blk * SPMV_LDS_ROWS;
@@ -2195,7 +2207,10 @@ static void launch_spmv_dt(int sched, const SpmvState &single, const SpmvState *
         constexpr bool W = DT == VQE_C128;
         const bool rv = (sched & VQE_SPMV_REAL) != 0;
         if (sched & VQE_SPMV_XIDX) {
-            launch_sell_t<DT, SPMV_XIDX_E, W ? 1 : 3, true>(states, tasks, grid, s, lds, rv);
+            if ((sched & 0xff) == 3)
+                launch_sell_t<DT, 3, W ? 2 : 6, true>(states, tasks, grid, s, lds, rv);
+            else
+                launch_sell_t<DT, 6, W ? 1 : 3, true>(states, tasks, grid, s, lds, rv);
             return;
         }
         switch (sched & 0xff) {
@@ -2762,14 +2777,25 @@ void launch_sell_xtab(const vqe_csr *H, uint32_t *mark, uint16_t *xmap, uint16_t
     k_sell_xscan<<<1, 1024, 0, s>>>(mark, H->dim, xmap, xtab, nx);
 }
 
-void launch_sell_fill_x(const vqe_csr *H, bool real, const uint16_t *srow, const int2 *sslice,
-                        const uint16_t *xmap, uint32_t *code, void *val, hipStream_t s)
+template <int E>
+static void launch_sell_fill_x_e(const vqe_csr *H, bool real, const uint16_t *srow, const int2 *sslice,
+                                 const uint16_t *xmap, uint32_t *code, void *val, hipStream_t s)
 {
     const int64_t nb = (H->dim + SPMV_LDS_ROWS - 1) / SPMV_LDS_ROWS;
     const unsigned g = (unsigned)(nb * SPMV_SLICES_PER_BLOCK);
-    auto k = H->dtype == VQE_C128 ? (real ? k_sell_fill_x<VQE_C128, true> : k_sell_fill_x<VQE_C128, false>)
-                                  : (real ? k_sell_fill_x<VQE_C64, true> : k_sell_fill_x<VQE_C64, false>);
+    auto k = H->dtype == VQE_C128
+                 ? (real ? k_sell_fill_x<VQE_C128, true, E> : k_sell_fill_x<VQE_C128, false, E>)
+                 : (real ? k_sell_fill_x<VQE_C64, true, E> : k_sell_fill_x<VQE_C64, false, E>);
     k<<<g, 64, 0, s>>>(H->rowptr, H->col, H->val, H->dim, srow, sslice, xmap, code, val);
+}
+
+void launch_sell_fill_x(const vqe_csr *H, int E, bool real, const uint16_t *srow, const int2 *sslice,
+                        const uint16_t *xmap, uint32_t *code, void *val, hipStream_t s)
+{
+    if (E == 3)
+        launch_sell_fill_x_e<3>(H, real, srow, sslice, xmap, code, val, s);
+    else
+        launch_sell_fill_x_e<6>(H, real, srow, sslice, xmap, code, val, s);
 }
 
 void launch_sellt_layout(const vqe_csr *H, int32_t nt, int32_t tc, int E, uint16_t *srow,
@@ -2919,8 +2945,10 @@ bool vqe_valid_schedule(int sched)
     case 2 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
     case 4 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
     case 8 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_REAL:
-    case SPMV_XIDX_E | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX:
-    case SPMV_XIDX_E | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX | VQE_SPMV_REAL:
+    case 3 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX:
+    case 3 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX | VQE_SPMV_REAL:
+    case 6 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX:
+    case 6 | VQE_SPMV_LDS | VQE_SPMV_SLICED | VQE_SPMV_XIDX | VQE_SPMV_REAL:
         return true;
     default:
         return false;

@@ -85,9 +85,9 @@ struct SpmvState {
     const uint16_t *srow;
     const int2 *sslice;
     const uint32_t *smask;
-    // flip-mask index form (VQE_SPMV_XIDX): the operator's flip masks,
-    // ascending, sxtab[0 .. nx); scode then holds 32-bit words of three
-    // 10-bit indices, word (start + ((j / 6) * 64 + i) * 6) / 3 + (j % 6) / 3
+    // flip-mask index form (VQE_SPMV_XIDX, E = 3 or 6): the operator's flip
+    // masks, ascending, sxtab[0 .. nx); scode then holds 32-bit words of three
+    // 10-bit indices, word (start + ((j / E) * 64 + i) * E) / 3 + (j % E) / 3
     // holding entry j of lane i in bits 10 * (j % 3)
     const uint16_t *sxtab;
     int32_t nx;
@@ -114,9 +114,8 @@ struct SpmvState {
 #define SPMV_SELLT_PART_BYTES (16 * 1024)
 // Sliced layout: slices of one wave's rows per block of SPMV_LDS_ROWS rows.
 #define SPMV_SLICES_PER_BLOCK (SPMV_LDS_ROWS / VQE_WAVE)
-// flip-mask index form: table entries (10-bit indices) and entries per group
+// flip-mask index form: table entries (10-bit indices)
 #define SPMV_XIDX_MAX 1024
-#define SPMV_XIDX_E 6
 // largest dimension whose column XOR row fits 16 bits
 #define SPMV_X16_MAX_DIM 65536
 // row length granule of the padded layout (real values, states that fit LDS)

@@ -46,7 +46,7 @@ CANDIDATES = (8, 16, 32, 64, 16 | _V, 32 | _V, 64 | _V,
               2 | _L | _S, 4 | _L | _S, 8 | _L | _S, 2 | _L | _S | _D, 4 | _L | _S | _D,
               2 | _L | _S | _R, 4 | _L | _S | _R, 8 | _L | _S | _R,
               # and with the flip masks' 10-bit indices in place of the columns
-              6 | _L | _S | _I, 6 | _L | _S | _I | _R)
+              3 | _L | _S | _I, 6 | _L | _S | _I, 3 | _L | _S | _I | _R, 6 | _L | _S | _I | _R)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuned_schedules.json")
 _memo: dict = {}

@@ -25,6 +25,7 @@ from paper_2606_29692_amd import binding as B  # noqa: E402
 
 # the sliced layout with the flip masks' 10-bit indices in place of the columns
 XI = 6 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_XIDX
+XI3 = 3 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_XIDX   # three entries per group
 
 
 @pytest.fixture(scope="module")
@@ -287,7 +288,7 @@ def test_full_size_bench_config(ctx, sched):
                                    8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED,
                                    4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL,
                                    8 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL,
-                                   XI, XI | B.VQE_SPMV_REAL])
+                                   XI, XI | B.VQE_SPMV_REAL, XI3, XI3 | B.VQE_SPMV_REAL])
 def test_every_spmv_schedule_matches_oracle(ctx, sched):
     """Each H-product schedule, batched over mixed sizes, against the oracle."""
     specs = mixed_specs()[:3] + [vs.SystemSpec(14, 6, "jw", False, 106)]
@@ -318,7 +319,7 @@ def test_every_spmv_schedule_matches_oracle(ctx, sched):
 
 @pytest.mark.parametrize("sched", [e | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED for e in (2, 4, 8)] +
                          [4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED | B.VQE_SPMV_REAL,
-                          XI, XI | B.VQE_SPMV_REAL])
+                          XI, XI | B.VQE_SPMV_REAL, XI3, XI3 | B.VQE_SPMV_REAL])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_sliced_layout_sizes_vs_oracle(ctx, sched, dtype):
     """The sliced layout at register sizes that leave slices and blocks
@@ -570,7 +571,7 @@ def test_flip_mask_indices_sum_like_columns_and_refuse_too_many_masks(ctx):
     v /= np.linalg.norm(v)
     psi = torch.from_numpy(v).to(torch.complex64).to(ctx.torch_device)
     res = {}
-    for sched in (4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED, XI):
+    for sched in (4 | B.VQE_SPMV_LDS | B.VQE_SPMV_SLICED, XI, XI3):
         plan = B.BatchPlan(ctx, [(H, pool, psi)], schedules=[sched])
         plan.step(update=False)
         res[sched] = (host(plan.energies)[:3].copy(), host(plan.sigma[0]).astype(np.complex128))
@@ -580,9 +581,10 @@ def test_flip_mask_indices_sum_like_columns_and_refuse_too_many_masks(ctx):
     for e, sg in res.values():
         assert abs(e[0] - e_o) <= 1e-6
         assert np.linalg.norm(sg - sg_o) <= 2e-6 * np.linalg.norm(sg_o)
-    a, b = res.values()
-    np.testing.assert_array_equal(a[0], b[0])
-    np.testing.assert_array_equal(a[1], b[1])
+    a, *others = res.values()
+    for b in others:
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
     # 1100 distinct flip masks
     xs = rng.choice(1 << 12, size=1100, replace=False).astype(np.uint64)
     many = vs.PauliPack(12, xs, np.zeros_like(xs), rng.standard_normal(xs.size) + 0j)
