@@ -561,8 +561,9 @@ def test_flip_mask_indices_sum_like_columns_and_refuse_too_many_masks(ctx):
     """The sliced layout with flip-mask indices gives the sigma and energy
     of the one with 16-bit columns bit for bit (each lane sums its row's
     entries in the same order; the pads only add zeros), and both match the
-    oracle; an operator with more than 1024 distinct flip masks is refused
-    with VQE_ENOTSUP by the plan and by vqe_layout_create."""
+    oracle; an operator with exactly 1024 distinct flip masks (every index)
+    matches the oracle, and one with more is refused with VQE_ENOTSUP by the
+    plan and by vqe_layout_create."""
     s = vs.make_system(vs.SystemSpec(12, 8, "jw", False, 61))
     pool = B.pool_from_packs(ctx, s.pool, "c64")
     H = B.csr_from_pack(ctx, s.hamiltonian, "c64")
@@ -585,6 +586,17 @@ def test_flip_mask_indices_sum_like_columns_and_refuse_too_many_masks(ctx):
     for b in others:
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
+    # exactly 1024 distinct flip masks (every 10-bit index used): accepted
+    xs = rng.choice(1 << 12, size=1024, replace=False).astype(np.uint64)
+    full = vs.PauliPack(12, xs, np.zeros_like(xs), rng.standard_normal(xs.size) + 0j)
+    Hf = B.csr_from_pack(ctx, full, "c64")
+    for sched in (XI, XI3):
+        plan = B.BatchPlan(ctx, [(Hf, pool, psi)], schedules=[sched])
+        plan.step(update=False)
+        sg = host(plan.sigma[0]).astype(np.complex128)
+        plan.close()
+        ref = orc.energy(orc.csr_from_pack(full), vin)[3]
+        assert np.linalg.norm(sg - ref) <= 2e-6 * np.linalg.norm(ref)
     # 1100 distinct flip masks
     xs = rng.choice(1 << 12, size=1100, replace=False).astype(np.uint64)
     many = vs.PauliPack(12, xs, np.zeros_like(xs), rng.standard_normal(xs.size) + 0j)
