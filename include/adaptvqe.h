@@ -589,7 +589,8 @@ VQE_API int64_t vqe_batch_workspace_bytes(const vqe_batch *plan);
  * The row sums are the same FP64 sums of exact-in-FP64 products, grouped over
  * the lanes differently: results agree to the rounding of FP64 sums. */
 #define VQE_SPMV_PAD 0x10000
-/* VQE_SPMV_SLICED (with VQE_SPMV_LDS and E = 2, 4 or 8 in place of the lanes;
+/* VQE_SPMV_SLICED (with VQE_SPMV_LDS and E = 2, 4 or 8 in place of the lanes,
+ * or E = 3 or 6 with VQE_SPMV_XIDX below;
  * batch plans only): one row per wave lane.  The plan sorts each block of
  * 2048 rows by length (longest first, ties by row) and stores every 64
  * consecutive sorted rows as a slice in which lane i's j-th entry sits at

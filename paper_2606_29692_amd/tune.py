@@ -5,7 +5,9 @@ VQE_SPMV_* options: wide loads (VEC4), the state staged in LDS (LDS, DEEP),
 the pipelined loads (PREFETCH), 16-bit column codes (X16), the complex
 values in the row-padded layout (PAD), for a real H the real values in
 that layout (REAL), and the sliced layout with one row per lane (SLICED,
-with 2, 4 or 8 entries per lane and load in place of the lanes).  It is picked
+with 2, 4 or 8 entries per lane and load in place of the lanes, or 3 or 6
+with the flip masks' 10-bit indices in place of the columns, XIDX; an
+operator with too many masks for it times as infinite).  It is picked
 per (register size, dtype, mapping, value form, device) by timing the batched
 H product phase of a real plan over the candidates, and cached.  The value
 form "complex" keeps the interleaved complex values of the CSR (candidates
