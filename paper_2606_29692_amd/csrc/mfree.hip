@@ -911,7 +911,7 @@ k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tas
 // Renormalisation after the fused update: |psi'|^2 = |psi|^2 (from this
 // step's H product) plus the update blocks' changes, summed in block order.
 template <int DT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_norm_scale_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks)
 {
     const int2 t = tasks[blockIdx.x];
@@ -938,9 +938,20 @@ k_norm_scale_mf(const TaylorState *__restrict__ states, const int2 *__restrict__
     const double inv = 1.0 / sqrt(n2);
     const int64_t r0 = (int64_t)t.y * NORM_ROWS_PER_BLOCK;
     const int64_t r1 = r0 + NORM_ROWS_PER_BLOCK < stp->dim ? r0 + NORM_ROWS_PER_BLOCK : stp->dim;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
-        const double2 p = Elem<DT>::ld(stp->psi, r);
-        Elem<DT>::st(stp->psi, r, make_double2(p.x * inv, p.y * inv));
+    // a block's rows in two passes of 1,024 threads, both loads first
+    constexpr int NT = 1024, U = NORM_ROWS_PER_BLOCK / NT;
+    double2 p[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int64_t r = r0 + threadIdx.x + (int64_t)u * NT;
+        if (r < r1)
+            p[u] = Elem<DT>::ld(stp->psi, r);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int64_t r = r0 + threadIdx.x + (int64_t)u * NT;
+        if (r < r1)
+            Elem<DT>::st(stp->psi, r, make_double2(p[u].x * inv, p[u].y * inv));
     }
 }
 
@@ -978,9 +989,9 @@ void launch_norm_mf(int dtype, const TaylorState *states, const int2 *tasks, uns
                     hipStream_t s)
 {
     if (dtype == VQE_C128)
-        k_norm_scale_mf<VQE_C128><<<grid, 256, 0, s>>>(states, tasks);
+        k_norm_scale_mf<VQE_C128><<<grid, 1024, 0, s>>>(states, tasks);
     else
-        k_norm_scale_mf<VQE_C64><<<grid, 256, 0, s>>>(states, tasks);
+        k_norm_scale_mf<VQE_C64><<<grid, 1024, 0, s>>>(states, tasks);
 }
 
 void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
