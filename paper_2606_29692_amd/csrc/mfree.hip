@@ -285,23 +285,68 @@ int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, ch
     out->tabs.clear();
     out->lists.clear();
     out->list_info.clear();
-    std::vector<uint32_t> tbs(M);
+    // Tile bits: kt bits outside a generator's flip mask (never bit 0: the
+    // staging reads row pairs {2i, 2i + 1}).  Each generator's own choice is
+    // its kt highest such bits; every distinct set is staged once per tile,
+    // so when a greedy cover -- repeatedly the kt-subset of bits 1 .. n-1
+    // that the most of the remaining generators can use (ties: the higher
+    // bits) -- needs fewer sets, the generators take the cover's sets.
+    std::vector<uint32_t> tbs(M, 0u), own(M, 0u);
     for (int j = 0; j < M; j++) {
-        const vqe_mf_desc &d = pool->desc[j];
-        // tile bits: the kt highest bits outside x
-        uint32_t tb = 0;
         int got = 0;
-        for (int p = n - 1; p >= 0 && got < kt; p--)
-            if (!((d.x >> p) & 1)) {
-                tb |= 1u << p;
+        for (int p = n - 1; p >= 1 && got < kt; p--)
+            if (!((pool->desc[j].x >> p) & 1)) {
+                own[j] |= 1u << p;
                 got++;
             }
-        if (got < kt || (tb & 1u)) {
-            // (the staging reads row pairs {2i, 2i + 1}, so bit 0 is never a tile bit)
+        if (got < kt) {
             std::snprintf(err, n_err, "matrix-free screen: generator %d leaves no tile bit", j);
             return VQE_ENOTSUP;
         }
-        tbs[j] = tb;
+    }
+    auto distinct = [](std::vector<uint32_t> v) {
+        std::sort(v.begin(), v.end());
+        return (size_t)(std::unique(v.begin(), v.end()) - v.begin());
+    };
+    if (kt > 0) {
+        std::vector<uint32_t> cand;
+        for (int64_t m = ((int64_t)1 << (n - 1)) - 1; m >= 0; m--)
+            if (__builtin_popcountll((unsigned long long)m) == kt)
+                cand.push_back((uint32_t)m << 1);
+        std::vector<int32_t> left(M);
+        for (int j = 0; j < M; j++)
+            left[j] = j;
+        while (!left.empty()) {
+            size_t best = 0;
+            int64_t best_cnt = 0;
+            for (size_t c = 0; c < cand.size(); c++) {
+                int64_t cnt = 0;
+                for (int32_t j : left)
+                    cnt += (pool->desc[j].x & cand[c]) == 0;
+                if (cnt > best_cnt) {
+                    best_cnt = cnt;
+                    best = c;
+                }
+            }
+            if (best_cnt == 0) {
+                std::snprintf(err, n_err, "matrix-free screen: generator %d leaves no tile bit", left[0]);
+                return VQE_ENOTSUP;
+            }
+            std::vector<int32_t> rest;
+            for (int32_t j : left) {
+                if ((pool->desc[j].x & cand[best]) == 0)
+                    tbs[j] = cand[best];
+                else
+                    rest.push_back(j);
+            }
+            left.swap(rest);
+        }
+    }
+    if (distinct(tbs) >= distinct(own))
+        tbs = own;
+    for (int j = 0; j < M; j++) {
+        const vqe_mf_desc &d = pool->desc[j];
+        const uint32_t tb = tbs[j];
         int64_t owners = 0;
         for (int v = 0; v < ntile; v++) {
             uint32_t vbits = 0;

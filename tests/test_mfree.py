@@ -69,14 +69,31 @@ def test_jw_constraint_counts():
     assert counts.count(1) == 8 and counts.count(3) == 18 and len(counts) == 26
 
 
-def tile_bits(x, n, kt):
-    out = []
-    for p in range(n - 1, -1, -1):
-        if len(out) == kt:
-            break
-        if not (x >> p) & 1:
-            out.append(p)
-    return out
+def pool_tile_bits(xs, n, kt):
+    """The screen's tile bits of every generator (flip masks xs), as lists of
+    bit positions: each generator's kt highest bits outside its mask (bit 0
+    excluded), unless the greedy cover the library documents -- repeatedly
+    the kt-subset of bits 1..n-1 (candidates in descending mask order; the
+    first wins a tie) that the most remaining generators avoid -- needs fewer
+    distinct sets."""
+    own = []
+    for x in xs:
+        b = [p for p in range(n - 1, 0, -1) if not (x >> p) & 1][:kt]
+        own.append(sorted(b))
+    cand = [m << 1 for m in range((1 << (n - 1)) - 1, -1, -1) if bin(m).count("1") == kt]
+    out = [None] * len(xs)
+    left = list(range(len(xs)))
+    while left:
+        counts = [sum(1 for j in left if not (xs[j] & c)) for c in cand]
+        best = max(range(len(cand)), key=lambda i: (counts[i], -i))
+        assert counts[best] > 0
+        c = cand[best]
+        for j in left:
+            if not (xs[j] & c):
+                out[j] = [p for p in range(n) if (c >> p) & 1]
+        left = [j for j in left if out[j] is None]
+    distinct = lambda v: len({tuple(t) for t in v})  # noqa: E731
+    return out if distinct(out) < distinct(own) else own
 
 
 def compress(a, tb):
@@ -90,6 +107,7 @@ def test_owner_rows_cover_every_pair_once(n, ne, mapping):
     s = vs.make_system(vs.SystemSpec(n, ne, mapping, False, vs.system_seed(4, n)))
     pool = B.MfPool(s.pool)
     dim = 1 << n
+    tbs = {kt: pool_tile_bits([pool.get(j)["x"] for j in range(pool.M)], n, kt) for kt in (1, 2)}
     for j in range(pool.M):
         d = pool.get(j)
         h = d["x"].bit_length() - 1
@@ -101,7 +119,8 @@ def test_owner_rows_cover_every_pair_once(n, ne, mapping):
         # screen tiles of dim / 2^kt rows
         for kt in (1, 2):
             tile_rows = dim >> kt
-            tb = tile_bits(d["x"], n, kt)
+            tb = tbs[kt][j]
+            assert not (d["x"] & sum(1 << p for p in tb)) and 0 not in tb
             seen = []
             for v in range(1 << kt):
                 rows, idx = pool.owner_rows(j, tile_rows, v)
