@@ -965,6 +965,21 @@ k_norm_scale_mf(const TaylorState *__restrict__ states, const int2 *__restrict__
     const TaylorState *stp = states + t.x;
     if (VQE_SKIP(*stp))
         return;
+    const int64_t r0 = (int64_t)t.y * NORM_ROWS_PER_BLOCK;
+    const int64_t r1 = r0 + NORM_ROWS_PER_BLOCK < stp->dim ? r0 + NORM_ROWS_PER_BLOCK : stp->dim;
+    // a block's rows in two passes of 1,024 threads, their loads issued
+    // before the norm's (the rows do not depend on it)
+    constexpr int NT = 1024, U = NORM_ROWS_PER_BLOCK / NT;
+    const bool renorm = stp->renorm != 0;
+    double2 p[U];
+    if (renorm) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t r = r0 + threadIdx.x + (int64_t)u * NT;
+            if (r < r1)
+                p[u] = Elem<DT>::ld(stp->psi, r);
+        }
+    }
     __shared__ double s_n2;
     if (threadIdx.x < 64) {
         double d = 0.0;
@@ -978,20 +993,9 @@ k_norm_scale_mf(const TaylorState *__restrict__ states, const int2 *__restrict__
     const double n2 = s_n2;
     if (t.y == 0 && threadIdx.x == 0 && stp->norm2_out)
         stp->norm2_out[0] = n2;
-    if (!stp->renorm)
+    if (!renorm)
         return;
     const double inv = 1.0 / sqrt(n2);
-    const int64_t r0 = (int64_t)t.y * NORM_ROWS_PER_BLOCK;
-    const int64_t r1 = r0 + NORM_ROWS_PER_BLOCK < stp->dim ? r0 + NORM_ROWS_PER_BLOCK : stp->dim;
-    // a block's rows in two passes of 1,024 threads, both loads first
-    constexpr int NT = 1024, U = NORM_ROWS_PER_BLOCK / NT;
-    double2 p[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-        const int64_t r = r0 + threadIdx.x + (int64_t)u * NT;
-        if (r < r1)
-            p[u] = Elem<DT>::ld(stp->psi, r);
-    }
 #pragma unroll
     for (int u = 0; u < U; u++) {
         const int64_t r = r0 + threadIdx.x + (int64_t)u * NT;
