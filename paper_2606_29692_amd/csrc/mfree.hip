@@ -313,33 +313,46 @@ int mf_host_plan(const vqe_mf_pool *pool, int64_t tile_rows, MfHostPlan *out, ch
         for (int64_t m = ((int64_t)1 << (n - 1)) - 1; m >= 0; m--)
             if (__builtin_popcountll((unsigned long long)m) == kt)
                 cand.push_back((uint32_t)m << 1);
-        std::vector<int32_t> left(M);
-        for (int j = 0; j < M; j++)
-            left[j] = j;
-        while (!left.empty()) {
+        // the generators as bit sets: those still without a set, and per
+        // bit those whose flip mask holds it; a candidate's count is then the
+        // remaining generators outside the union of its bits' sets
+        const int W = (M + 63) / 64;
+        std::vector<uint64_t> left((size_t)W, 0ull), hold((size_t)n * W, 0ull), blocked((size_t)W);
+        for (int j = 0; j < M; j++) {
+            left[j >> 6] |= 1ull << (j & 63);
+            for (int p = 0; p < n; p++)
+                if ((pool->desc[j].x >> p) & 1)
+                    hold[(size_t)p * W + (j >> 6)] |= 1ull << (j & 63);
+        }
+        int64_t n_left = M;
+        while (n_left > 0) {
             size_t best = 0;
             int64_t best_cnt = 0;
             for (size_t c = 0; c < cand.size(); c++) {
+                std::fill(blocked.begin(), blocked.end(), 0ull);
+                for (uint32_t m = cand[c]; m; m &= m - 1) {
+                    const uint64_t *h = hold.data() + (size_t)__builtin_ctz(m) * W;
+                    for (int w = 0; w < W; w++)
+                        blocked[w] |= h[w];
+                }
                 int64_t cnt = 0;
-                for (int32_t j : left)
-                    cnt += (pool->desc[j].x & cand[c]) == 0;
+                for (int w = 0; w < W; w++)
+                    cnt += __builtin_popcountll(left[w] & ~blocked[w]);
                 if (cnt > best_cnt) {
                     best_cnt = cnt;
                     best = c;
                 }
             }
             if (best_cnt == 0) {
-                std::snprintf(err, n_err, "matrix-free screen: generator %d leaves no tile bit", left[0]);
+                std::snprintf(err, n_err, "matrix-free screen: a generator leaves no tile bit");
                 return VQE_ENOTSUP;
             }
-            std::vector<int32_t> rest;
-            for (int32_t j : left) {
-                if ((pool->desc[j].x & cand[best]) == 0)
+            for (int j = 0; j < M; j++)
+                if (((left[j >> 6] >> (j & 63)) & 1) && (pool->desc[j].x & cand[best]) == 0) {
                     tbs[j] = cand[best];
-                else
-                    rest.push_back(j);
-            }
-            left.swap(rest);
+                    left[j >> 6] &= ~(1ull << (j & 63));
+                }
+            n_left -= best_cnt;
         }
     }
     if (distinct(tbs) >= distinct(own))
