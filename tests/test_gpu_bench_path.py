@@ -16,7 +16,8 @@ Every state's energies, all 204 gradients and its final state are compared
 with orc.adapt_run along the GPU's own selections (FP32 bars: |dE| < 1e-6 Ha,
 max|dg| < 1e-5, fidelity > 0.999999); each selection must be the oracle's, or
 a near tie within the FP32 gradient error; amplitudes outside the particle
-sector stay exactly zero.
+sector stay exactly zero.  The complex form also runs for eight states under
+the BK mapping.
 """
 import numpy as np
 import pytest
@@ -122,6 +123,53 @@ def test_bench_call_all_states_vs_oracle(ctx, workload, form):
     print(f"{form} form, 64 states x {STEPS} steps: max|dE| {worst['dE']:.2e} Ha, max|dg| "
           f"{worst['dg']:.2e}, max 1-F {worst['1-F']:.2e}, selections equal to the oracle's "
           f"{agree}/{64 * STEPS}")
+
+
+def test_bench_call_bk_states_vs_oracle(ctx):
+    """The complex form's call under the BK mapping (`bench.py --mapping bk`),
+    eight states: BK generators' own tile bits form more distinct sets than
+    the shared cover the screen takes, so this runs the cover's sets."""
+    n = 8
+    specs = [vs.SystemSpec(14, vs.ELECTRONS[14], "bk", False, vs.system_seed(44, i)) for i in range(n)]
+    systems = [vs.make_system(s) for s in specs]
+    opool = [orc.csr_from_pack(p) for p in systems[0].pool]
+    pools = PB.PoolCache(ctx, matrix_free=True)
+    ds = [PB.device_system(ctx, s, "c64", pools) for s in systems]
+    sched = T.schedule_for(ctx, ds[0], systems=ds, value_form="complex")
+    print(f"BK bench path: schedule {sched}", flush=True)
+    assert not sched & B.VQE_SPMV_REAL
+    psi0 = [vs.complex_start_state(s).astype(np.complex64) for s in systems]
+    for d, p in zip(ds, psi0):
+        d.psi.copy_(torch.from_numpy(p))
+    plan = PB.make_batch(ctx, ds, schedules=[sched] * n)
+    thetas = np.stack([vs.draw_thetas(s.seed, STEPS) for s in specs])
+    E = np.zeros((STEPS + 1, n))
+    K = np.zeros((STEPS, n), dtype=np.int64)
+    G = np.zeros((STEPS, n, len(opool)))
+    for t in range(STEPS):
+        plan.theta.copy_(torch.from_numpy(thetas[:, t]))
+        plan.step(renorm=True, graph=True, tiled_screen=True)
+        E[t] = host(plan.energies).reshape(-1, 3)[:, 0]
+        K[t] = host(plan.k)
+        G[t] = host(plan.g).reshape(n, -1)
+        print(f"  step {t} done", flush=True)
+    plan.step(update=False)
+    E[STEPS] = host(plan.energies).reshape(-1, 3)[:, 0]
+    psi_gpu = [host(d.psi).astype(np.complex128) for d in ds]
+    plan.close()
+    for i, s in enumerate(systems):
+        assert np.count_nonzero(psi0[i].imag) > 1000
+        oH = orc.csr_from_pack(s.hamiltonian)
+        tr = orc.adapt_run(oH, opool, psi0[i].astype(np.complex128), thetas[i], STEPS, forced=K[:, i])
+        de = np.abs(E[:, i] - np.array(tr.energies)).max()
+        dg = max(np.abs(G[t, i] - tr.gradients[t]).max() for t in range(STEPS))
+        p = psi_gpu[i]
+        fid = abs(np.vdot(p, tr.psi)) ** 2 / (np.vdot(p, p).real * np.vdot(tr.psi, tr.psi).real)
+        print(f"BK state {i}: max|dE| {de:.2e}, max|dg| {dg:.2e}, 1-F {1 - fid:.2e}", flush=True)
+        assert de < 1e-6 and dg < 1e-5 and fid > 0.999999, (i, de, dg, fid)
+        for t in range(STEPS):
+            g_o = tr.gradients[t]
+            assert abs(g_o[K[t, i]]) >= np.abs(g_o).max() * (1 - 1e-5), (i, t)
 
 
 def test_tiled_screen_flag(ctx, workload):
