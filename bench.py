@@ -9,7 +9,10 @@ H product with the FP64 energy reduction, the pool-gradient screen over all
 204 generators, argmax selection, the fused fifth-order Taylor update and the
 FP64 renormalisation.  Storage is FP32 (complex64, with an FP64 diagonal
 shift); products and reductions are FP64.  Inputs are resident in HBM before
-the timed region.
+the timed region.  The throughput leg runs the K timed steps as one captured
+graph of K steps (vqe_batch_run; each step takes its angles from the next row
+of a device array), and reports beside it the same steps launched one graph
+per step with a host-issued angle copy before each.
 
 The headline leg keeps the interleaved complex layout end to end: the
 Hamiltonians' complex values are streamed, and every state starts from a
@@ -40,6 +43,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
+RUN_MAX = 1024             # steps per vqe_batch_run call (VQE_RUN_MAX_STEPS)
 
 
 # state bytes that fit in LDS beside the staged row pointers (larger states are
@@ -375,8 +379,12 @@ def serving_bench(n_requests: int, warm: int, log_fn=log, schedules: str = "tune
 def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: int,
               tiled_screen: bool = False):
     """Time one batch plan's whole adaptive step (captured graphs):
-      throughput  K steps between two events (whole-step graph, no events
-                  inside), after W warm-up steps;
+      throughput  K steps between two events as ONE graph launch
+                  (vqe_batch_run: step i takes its angles from row i of a
+                  device array written before the timed region), after W
+                  warm-up steps and one warm-up run; beside it the same K
+                  steps as K whole-step graph launches with a host-issued
+                  angle copy before each;
       latency     L steps with an event at every step boundary;
       H product   R back-to-back launches of the H products alone between two
                   events (the roofline's kernel duration: the events' own cost,
@@ -401,17 +409,42 @@ def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: in
     ev3 = [Ev() for _ in range(3)]
     next_theta()
     plan.step_timed(ev3, renorm=True, graph=True, tiled_screen=ts)   # captures the split graphs
+    # runs of at most RUN_MAX steps (the library's limit per call); the rows
+    # of a later run are written on the plan's stream between the runs
+    C = min(K, RUN_MAX)
+    sizes = [C] * (K // C) + ([K % C] if K % C else [])
+    rows = torch.empty((C, n_states), dtype=torch.float64, device=thetas.device)
+
+    def fill_rows(n):
+        nonlocal t
+        idx = torch.arange(t, t + n, device=thetas.device) % thetas.shape[0]
+        rows[:n].copy_(thetas[idx])
+        t += n
+
+    for n in sorted(set(sizes)):       # captures the graph of each run length
+        fill_rows(n)
+        plan.run(rows[:n], renorm=True, graph=True, tiled_screen=ts)
+    fill_rows(sizes[0])
     torch.cuda.synchronize()
     start, stop = Ev(), Ev()
     start.record(stream)
     t_host = time.perf_counter()
-    for _ in range(K):
-        next_theta()
-        plan.step(renorm=True, graph=True, tiled_screen=ts)
+    for i, n in enumerate(sizes):
+        if i:
+            fill_rows(n)
+        plan.run(rows[:n], renorm=True, graph=True, tiled_screen=ts)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_host
     ms_per_step = start.elapsed_time(stop) / K
+    start1, stop1 = Ev(), Ev()
+    start1.record(stream)
+    for _ in range(K):
+        next_theta()
+        plan.step(renorm=True, graph=True, tiled_screen=ts)
+    stop1.record(stream)
+    torch.cuda.synchronize()
+    ms_single = start1.elapsed_time(stop1) / K
     bounds = [Ev() for _ in range(L + 1)]
     bounds[0].record(stream)
     for i in range(L):
@@ -430,6 +463,13 @@ def timed_leg(plan, stream, n_states: int, thetas, K: int, W: int, L: int, R: in
     h_b2b = plan.time_products(R)
     return {"ms_per_step": ms_per_step, "updates_per_s": n_states * K / (ms_per_step * K / 1e3),
             "steps": K, "warmup": W, "host_wall_s": wall,
+            "throughput_launch": f"the {K} steps as {len(sizes)} graph launch(es) of up to {C} "
+                                 "steps (vqe_batch_run), angles row by row from a device array "
+                                 "written before each run",
+            "single_step_graphs": {"ms_per_step": ms_single,
+                                   "updates_per_s": n_states / (ms_single / 1e3),
+                                   "launch": "one whole-step graph per step, a host-issued angle "
+                                             "copy before each"},
             "step_latency": lat_stats(step_lat),
             "h_product_ms": h_b2b, "h_product_launches_timed": R,
             "h_product_timing": "back-to-back launches of the H-product kernels between two HIP "
@@ -656,7 +696,8 @@ def main():
     head = form_record(form, sched, leg, ph)
     nbytes = head["algorithmic_bytes_per_step"]
     log(f"{form} form (schedule {sched}): {leg['ms_per_step']:.3f} ms/step = "
-        f"{leg['updates_per_s']:.0f} updates/s; step latency p50 "
+        f"{leg['updates_per_s']:.0f} updates/s (graphs of up to {RUN_MAX} steps; one graph per "
+        f"step: {leg['single_step_graphs']['ms_per_step']:.3f} ms/step); step latency p50 "
         f"{leg['step_latency']['p50_ms']:.3f} p99 {leg['step_latency']['p99_ms']:.3f} ms "
         f"(n={leg['step_latency']['n']}); H product {leg['h_product_ms'] * 1e3:.1f} us "
         f"({head['h_product_GBps']:.0f} GB/s algorithmic, frac "

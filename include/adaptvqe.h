@@ -389,6 +389,25 @@ VQE_API int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *item
                      const vqe_batch_io *io, double rel_tie, vqe_batch **out);
 VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
 /*
+ * n_steps adaptive steps of the plan in one call (Sec. III-D's loop of
+ * screen, selection and Eq. 6-8 update, repeated), the angles given: step i
+ * first copies row i of theta_rows (DEVICE float64 [n_steps][B], row-major,
+ * read when that step runs) into the plan's angle buffer (io->theta, which
+ * holds the last row afterwards) and then runs as vqe_batch_step.  flags:
+ * VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_TILED_SCREEN as for
+ * vqe_batch_step, and VQE_STEP_GRAPH: the n_steps steps form ONE captured
+ * graph, launched once (no host work and no launch gap between the steps);
+ * it is captured on first use for its (flags, n_steps, theta_rows) and kept
+ * (up to 4 per plan, the least recently used replaced), so a caller that
+ * refills the same rows replays it.  The per-step outputs (energies,
+ * gradients, selection) are those of the last step.  Errors: VQE_EINVAL for
+ * another flag (VQE_STEP_NO_UPDATE, VQE_STEP_LINESEARCH), n_steps outside
+ * [0, VQE_RUN_MAX_STEPS] or theta_rows NULL with n_steps > 0; n_steps = 0
+ * does nothing.
+ */
+#define VQE_RUN_MAX_STEPS 1024
+VQE_API int vqe_batch_run(vqe_batch *plan, uint32_t flags, const double *theta_rows, int32_t n_steps);
+/*
  * Bind another state to slot `slot` of a plan (continuous batching): the new
  * item must have the same dimension, dtype and H-product schedule as the
  * slot's state at creation and use the same pool (same ops array).  The new

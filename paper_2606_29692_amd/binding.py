@@ -135,6 +135,7 @@ SIGNATURES = {
     "vqe_batch_step": (C.c_int, [C.c_void_p, C.c_uint32]),
     "vqe_batch_rebind": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(vqe_batch_item)]),
     "vqe_batch_step_timed": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p), C.c_int32]),
+    "vqe_batch_run": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_int32]),
     "vqe_batch_destroy": (C.c_int, [C.c_void_p]),
     "vqe_batch_set_line_search": (C.c_int, [C.c_void_p, C.c_double]),
     "vqe_batch_reoptimize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
@@ -674,6 +675,22 @@ class BatchPlan:
              graph: bool = False, line_search: bool = False, tiled_screen: bool = False):
         flags = self._flags(renorm, forced, update, graph, line_search, tiled_screen)
         self.ctx.check(lib().vqe_batch_step(self.handle, flags), "vqe_batch_step")
+
+    def run(self, theta_rows, renorm: bool = True, forced: bool = False, graph: bool = True,
+            tiled_screen: bool = False):
+        """theta_rows.shape[0] adaptive steps in one call (vqe_batch_run): step
+        i takes its angles from row i of theta_rows, a contiguous float64
+        [n_steps, B] tensor on the plan's device; with graph the steps are one
+        graph launch."""
+        torch = _torch()
+        if theta_rows.dtype != torch.float64 or theta_rows.dim() != 2 or \
+                theta_rows.shape[1] != self.B or not theta_rows.is_contiguous() or \
+                theta_rows.device != self.theta.device:
+            raise ValueError("run: theta_rows must be a contiguous float64 [n_steps, B] tensor "
+                             "on the plan's device")
+        flags = self._flags(renorm, forced, True, graph, False, tiled_screen)
+        self.ctx.check(lib().vqe_batch_run(self.handle, flags, theta_rows.data_ptr(),
+                                           int(theta_rows.shape[0])), "vqe_batch_run")
 
     def step_timed(self, events, renorm: bool = True, forced: bool = False, update: bool = True,
                    graph: bool = False, line_search: bool = False, tiled_screen: bool = False):

@@ -24,6 +24,7 @@
 #include <vector>
 
 static const int kXcd = 8;
+#define VQE_RUN_GRAPHS 4   // multi-step graphs kept per plan
 
 // Scratch of the allocation-free entry points: a static device array, one
 // copy per GPU, held until the process ends.  In host code `scratch` names a
@@ -214,6 +215,19 @@ struct vqe_batch {
     hipGraph_t graph_spmv = nullptr;
     hipGraphExec_t exec_all[32] = {};  // whole-step graphs by flag set (steps without events)
     hipGraph_t graph_all[32] = {};
+    // multi-step graphs of vqe_batch_run, by (flags, steps, angle rows); the
+    // least recently used one is replaced
+    struct RunGraph {
+        uint32_t flags = 0;
+        int32_t n = 0;
+        const double *rows = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        uint64_t used = 0;
+    };
+    RunGraph runs[VQE_RUN_GRAPHS];
+    uint64_t run_tick = 0;
+    double *theta_io = nullptr;        // the caller's angle buffer [B]
     // line search (vqe_batch_set_line_search)
     std::vector<PairTable> tables_host;            // CSR mode: pair tables (host copy)
     std::vector<const vqe_mf_pool *> mf_host;      // mf mode: pool of each table
@@ -757,6 +771,7 @@ extern "C" int vqe_batch_create(vqe_ctx *ctx, int32_t B, const vqe_batch_item *i
     if (!p)
         return VQE_ENOMEM;
     p->ctx = ctx;
+    p->theta_io = io->theta;
     p->B = B;
     p->dtype = dtype;
     p->rel_tie = rel_tie;
@@ -1493,6 +1508,60 @@ extern "C" int vqe_batch_step(vqe_batch *p, uint32_t flags)
     return enqueue_step(p, flags);
 }
 
+extern "C" int vqe_batch_run(vqe_batch *p, uint32_t flags, const double *theta_rows, int32_t n_steps)
+{
+    if (!p)
+        return VQE_EINVAL;
+    vqe_ctx *ctx = p->ctx;
+    if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_GRAPH | VQE_STEP_TILED_SCREEN))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_run: unknown flags, or a flag a run of updates "
+                        "with given angles does not take");
+    if (n_steps < 0 || n_steps > VQE_RUN_MAX_STEPS || (n_steps > 0 && !theta_rows))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_run: bad steps (%d) or angle rows", n_steps);
+    if (n_steps == 0)
+        return VQE_OK;
+    const uint32_t sflags = flags & ~(uint32_t)VQE_STEP_GRAPH;
+    // each step: its row of angles into the plan's angle buffer, then the step
+    auto enqueue = [&]() -> int {
+        for (int32_t i = 0; i < n_steps; i++) {
+            launch_theta_row(theta_rows + (size_t)i * p->B, p->theta_io, p->B, ctx->stream);
+            const int rc = enqueue_step(p, sflags);
+            if (rc)
+                return rc;
+        }
+        return VQE_OK;
+    };
+    if (!(flags & VQE_STEP_GRAPH))
+        return enqueue();
+    vqe_batch::RunGraph *hit = nullptr, *lru = &p->runs[0];
+    for (auto &r : p->runs) {
+        if (r.x && r.flags == sflags && r.n == n_steps && r.rows == theta_rows)
+            hit = &r;
+        if (r.used < lru->used)
+            lru = &r;
+    }
+    if (!hit) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        const int rc = capture(ctx, enqueue, &g, &x);
+        if (rc)
+            return rc;
+        if (lru->x)
+            (void)hipGraphExecDestroy(lru->x);
+        if (lru->g)
+            (void)hipGraphDestroy(lru->g);
+        lru->flags = sflags;
+        lru->n = n_steps;
+        lru->rows = theta_rows;
+        lru->g = g;
+        lru->x = x;
+        hit = lru;
+    }
+    hit->used = ++p->run_tick;
+    VQE_HIP(ctx, hipGraphLaunch(hit->x, ctx->stream));
+    return VQE_OK;
+}
+
 extern "C" int vqe_batch_step_timed(vqe_batch *p, uint32_t flags, void **events,
                                     int32_t n_events)
 {
@@ -1574,6 +1643,12 @@ extern "C" int vqe_batch_destroy(vqe_batch *p)
             (void)hipGraphExecDestroy(p->exec_all[i]);
         if (p->graph_all[i])
             (void)hipGraphDestroy(p->graph_all[i]);
+    }
+    for (auto &r : p->runs) {
+        if (r.x)
+            (void)hipGraphExecDestroy(r.x);
+        if (r.g)
+            (void)hipGraphDestroy(r.g);
     }
     if (p->exec_spmv)
         (void)hipGraphExecDestroy(p->exec_spmv);

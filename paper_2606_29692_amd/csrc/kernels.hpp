@@ -239,6 +239,9 @@ void launch_taylor_mf_fin(int dtype, const TaylorState *states, const int2 *task
                           double rel_tie, hipStream_t s);
 // renormalisation after launch_taylor_mf from the pre-update norm and the
 // update's changes (states with n2_prev and tay_partials set)
+// dst[0..n) = src[0..n): one row of a caller's angle schedule into a plan's
+// angle buffer (a kernel, so that it can sit in a captured graph)
+void launch_theta_row(const double *src, double *dst, int n, hipStream_t s);
 void launch_norm_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                     hipStream_t s);
 

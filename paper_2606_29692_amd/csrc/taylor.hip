@@ -322,7 +322,21 @@ __global__ void k_store_state(int64_t dim, const double2 *acc, void *psi)
 
 constexpr int64_t kGenericWgMaxNnz = 1 << 18;
 
+__global__ void __launch_bounds__(256)
+k_theta_row(const double *__restrict__ src, double *__restrict__ dst, int n)
+{
+    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
 }  // namespace
+
+void launch_theta_row(const double *src, double *dst, int n, hipStream_t s)
+{
+    if (n > 0)
+        k_theta_row<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, n);
+}
 
 void launch_taylor_pair(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                         hipStream_t s)

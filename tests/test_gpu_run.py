@@ -1,0 +1,134 @@
+"""Several adaptive steps per call (vqe_batch_run).
+
+Step i takes its angles from row i of a device array and then runs as a
+single step (Eq. 5 screen, selection, Eq. 6-8 update, renormalisation).  The
+eager run and the one-graph run must equal the same steps taken one at a time
+with those angles, bit for bit (the same kernels on the same inputs); the
+graph is kept for its rows, so refilled rows replay it with the new angles;
+bad arguments are refused.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import vqe_system as vs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2606_29692_amd import batch as PB  # noqa: E402
+from paper_2606_29692_amd import binding as B  # noqa: E402
+
+STEPS = 4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    prev = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    c = B.Context(0, stream)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+    torch.cuda.set_stream(prev)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().copy()
+
+
+def setup(ctx, case):
+    if case == "matrix-free c64, complex states, row-tiled screen":
+        specs, _ = vs.config_c4(n_states=6, mixed=True)
+        dtype, mf, tiled = "c64", True, True
+    else:
+        specs = [vs.SystemSpec(8, 4, "jw", False, 301), vs.SystemSpec(10, 4, "bk", False, 302),
+                 vs.SystemSpec(12, 8, "jw", True, 303)]
+        dtype, mf, tiled = "c128", False, False
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx, matrix_free=mf)
+    ds = [PB.device_system(ctx, s, dtype, pools) for s in systems]
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    if tiled:
+        psi0 = [vs.complex_start_state(s).astype(npdt) for s in systems]
+    else:
+        psi0 = [vs.reference_state(s).astype(npdt) for s in systems]
+    plan = PB.make_batch(ctx, ds)
+    return ds, psi0, plan, tiled
+
+
+def reset(ds, psi0):
+    for d, p in zip(ds, psi0):
+        d.psi.copy_(torch.from_numpy(p))
+
+
+def outputs(plan, ds):
+    return [host(plan.energies), host(plan.g), host(plan.k), host(plan.gmax), host(plan.theta)] + \
+        [host(d.psi) for d in ds]
+
+
+def one_at_a_time(plan, ds, psi0, rows, tiled):
+    reset(ds, psi0)
+    for i in range(rows.shape[0]):
+        plan.theta.copy_(rows[i])
+        plan.step(renorm=True, tiled_screen=tiled)
+    return outputs(plan, ds)
+
+
+def assert_same(a, b, what):
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y, err_msg=what)
+
+
+@pytest.mark.parametrize("case", ["matrix-free c64, complex states, row-tiled screen",
+                                  "CSR pools c128, real states"])
+def test_run_equals_single_steps(ctx, case):
+    print(f"run of {STEPS} steps: {case}", flush=True)
+    ds, psi0, plan, tiled = setup(ctx, case)
+    rng = np.random.default_rng(7)
+    a = rng.uniform(-0.3, 0.3, size=(STEPS, plan.B))
+    b = rng.uniform(-0.3, 0.3, size=(STEPS, plan.B))
+    rows = torch.from_numpy(a).to(plan.theta.device).contiguous()
+    want = one_at_a_time(plan, ds, psi0, rows, tiled)
+    assert np.array_equal(want[4], a[-1])
+    reset(ds, psi0)
+    plan.run(rows, graph=False, tiled_screen=tiled)
+    assert_same(outputs(plan, ds), want, "eager run")
+    reset(ds, psi0)
+    plan.run(rows, graph=True, tiled_screen=tiled)
+    assert_same(outputs(plan, ds), want, "graph run")
+    # the kept graph reads the rows when it runs: refill them and replay
+    rows.copy_(torch.from_numpy(b))
+    want_b = one_at_a_time(plan, ds, psi0, rows, tiled)
+    reset(ds, psi0)
+    plan.run(rows, graph=True, tiled_screen=tiled)
+    assert_same(outputs(plan, ds), want_b, "graph replay with refilled rows")
+    # a run of part of the rows (another graph), then the rest continuing it
+    reset(ds, psi0)
+    plan.run(rows[:1], graph=True, tiled_screen=tiled)
+    plan.run(rows[1:], graph=True, tiled_screen=tiled)
+    assert_same(outputs(plan, ds), want_b, "two graph runs")
+    plan.close()
+
+
+def test_run_refuses_bad_arguments(ctx):
+    ds, psi0, plan, _ = setup(ctx, "CSR pools c128, real states")
+    rows = torch.zeros((2, plan.B), dtype=torch.float64, device=plan.theta.device)
+    run = B.lib().vqe_batch_run
+    h, ptr = plan.handle, C.c_void_p(rows.data_ptr())
+    assert run(h, B.VQE_STEP_RENORM | B.VQE_STEP_LINESEARCH, ptr, 2) == B.VQE_EINVAL
+    assert run(h, B.VQE_STEP_NO_UPDATE, ptr, 2) == B.VQE_EINVAL
+    assert run(h, B.VQE_STEP_RENORM, None, 2) == B.VQE_EINVAL
+    assert run(h, B.VQE_STEP_RENORM, ptr, -1) == B.VQE_EINVAL
+    assert run(h, B.VQE_STEP_RENORM, ptr, 1025) == B.VQE_EINVAL
+    before = [host(d.psi) for d in ds]
+    assert run(h, B.VQE_STEP_RENORM | B.VQE_STEP_GRAPH, ptr, 0) == B.VQE_OK
+    assert all(np.array_equal(x, host(d.psi)) for x, d in zip(before, ds))
+    with pytest.raises(ValueError):
+        plan.run(rows.t())
+    with pytest.raises(ValueError):
+        plan.run(rows.float())
+    plan.close()
