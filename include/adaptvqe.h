@@ -391,9 +391,10 @@ VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
 /*
  * n_steps adaptive steps of the plan in one call (Sec. III-D's loop of
  * screen, selection and Eq. 6-8 update, repeated), the angles given: step i
- * first copies row i of theta_rows (DEVICE float64 [n_steps][B], row-major,
- * read when that step runs) into the plan's angle buffer (io->theta, which
- * holds the last row afterwards) and then runs as vqe_batch_step.  flags:
+ * runs as vqe_batch_step with its angles from row i of theta_rows (DEVICE
+ * float64 [n_steps][B], row-major, read when that step runs); the plan's
+ * angle buffer (io->theta) receives each row, so afterwards it holds the
+ * last row for every active slot.  flags:
  * VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_TILED_SCREEN as for
  * vqe_batch_step, and VQE_STEP_GRAPH: the n_steps steps form ONE captured
  * graph, launched once (no host work and no launch gap between the steps);

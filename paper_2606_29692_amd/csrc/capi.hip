@@ -561,7 +561,9 @@ int enqueue_spmv(vqe_batch *p)
     return VQE_OK;
 }
 
-int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
+// theta_row (nullable, matrix-free plans): the update's angles from this
+// device row instead of the plan's angle buffer (which the update then sets)
+int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev, const double *theta_row = nullptr)
 {
     vqe_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
@@ -608,9 +610,9 @@ int enqueue_rest(vqe_batch *p, uint32_t flags, hipEvent_t *ev)
         if (fused_fin)
             launch_taylor_mf_fin(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, p->d_spmv,
                                  p->d_screen, p->d_tables, p->d_sel, !(flags & VQE_STEP_FORCED),
-                                 p->rel_tie, s);
+                                 p->rel_tie, theta_row, s);
         else if (p->mf)
-            launch_taylor_mf(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
+            launch_taylor_mf(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, theta_row, s);
         else if (p->compact_taylor)
             launch_taylor_compact(p->dtype, p->d_tay, p->d_tay_tasks, p->n_tay_tasks, s);
         else
@@ -1521,11 +1523,19 @@ extern "C" int vqe_batch_run(vqe_batch *p, uint32_t flags, const double *theta_r
     if (n_steps == 0)
         return VQE_OK;
     const uint32_t sflags = flags & ~(uint32_t)VQE_STEP_GRAPH;
-    // each step: its row of angles into the plan's angle buffer, then the step
+    // each step with its row of angles: the matrix-free update reads the row
+    // itself; otherwise the row is first copied into the plan's angle buffer
     auto enqueue = [&]() -> int {
         for (int32_t i = 0; i < n_steps; i++) {
-            launch_theta_row(theta_rows + (size_t)i * p->B, p->theta_io, p->B, ctx->stream);
-            const int rc = enqueue_step(p, sflags);
+            const double *row = theta_rows + (size_t)i * p->B;
+            int rc;
+            if (p->mf) {
+                rc = enqueue_spmv(p);
+                rc = rc ? rc : enqueue_rest(p, sflags, nullptr, row);
+            } else {
+                launch_theta_row(row, p->theta_io, p->B, ctx->stream);
+                rc = enqueue_step(p, sflags);
+            }
             if (rc)
                 return rc;
         }

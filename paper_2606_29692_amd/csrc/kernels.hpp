@@ -229,14 +229,16 @@ inline size_t screen_real_lds(int64_t dim, int dtype)
 {
     return (size_t)dim * (dtype == VQE_C64 ? 2 * sizeof(float) : 2 * sizeof(double));
 }
+// (theta_row, nullable: state s takes the angle theta_row[s] and stores it as
+// its angle, instead of reading its angle)
 void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
-                      hipStream_t s);
+                      const double *theta_row, hipStream_t s);
 // the matrix-free update with the step's finalisation (launch_step_fin) done
 // by every update workgroup for its state (pools of at most 2048 generators)
 void launch_taylor_mf_fin(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                           const SpmvState *spmv, const ScreenState *screen,
                           const PairTable *tables, const SelectState *sel, bool select,
-                          double rel_tie, hipStream_t s);
+                          double rel_tie, const double *theta_row, hipStream_t s);
 // renormalisation after launch_taylor_mf from the pre-update norm and the
 // update's changes (states with n2_prev and tay_partials set)
 // dst[0..n) = src[0..n): one row of a caller's angle schedule into a plan's

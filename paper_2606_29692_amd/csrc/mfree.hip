@@ -864,7 +864,8 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 // The update of one owner pair e of the record (Eq. 6-8 on the 2x2 block);
 // returns the change of |psi_r|^2 + |psi_c|^2 between the stored values.
 template <int DT>
-__device__ __forceinline__ double taylor_pair(const TaylorState *stp, const MfRec &rec, uint32_t e)
+__device__ __forceinline__ double taylor_pair(const TaylorState *stp, const MfRec &rec, uint32_t e,
+                                              double theta)
 {
     // deposit e into the free bits, then the pivots
     uint32_t a = 0, fm = rec.free_mask, ee = e;
@@ -882,7 +883,6 @@ __device__ __forceinline__ double taylor_pair(const TaylorState *stp, const MfRe
     const double sa = (__popc(rec.zsign & c) & 1) ? -1.0 : 1.0;
     const double sb = (__popc(rec.zsign & r) & 1) ? -1.0 : 1.0;
     const double2 A = make_double2(sa * v.x, sa * v.y), Bv = make_double2(sb * v.x, sb * v.y);
-    const double theta = *stp->theta;
     double cf[6];
     cf[0] = 1.0;
 #pragma unroll
@@ -920,13 +920,15 @@ __device__ __forceinline__ double taylor_pair(const TaylorState *stp, const MfRe
 // norm as the pre-update norm plus these changes.  With FIN every workgroup
 // first forms the step's finalisation for its state (energy, gradients,
 // selection; stored by the state's first workgroup) and updates along the
-// generator it selects.
+// generator it selects.  With theta_row set the angle of state s is
+// theta_row[s] (one row of a caller's angle schedule), which the state's
+// first workgroup also stores as the state's angle.
 template <int DT, bool FIN>
 __global__ void __launch_bounds__(TAYLOR_ROWS_PER_BLOCK)
 k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tasks,
             const SpmvState *__restrict__ spmv, const ScreenState *__restrict__ screen,
             const PairTable *__restrict__ tables, const SelectState *__restrict__ sel,
-            int do_select, double rel_tie)
+            int do_select, double rel_tie, const double *__restrict__ theta_row)
 {
     const int2 task = tasks[blockIdx.x];
     if (task.x < 0)
@@ -944,12 +946,20 @@ k_taylor_mf(const TaylorState *__restrict__ states, const int2 *__restrict__ tas
     } else {
         k = *stp->k;
     }
+    double theta;
+    if (theta_row) {
+        theta = theta_row[task.x];
+        if (task.y == 0 && threadIdx.x == 0)
+            *const_cast<double *>(stp->theta) = theta;
+    } else {
+        theta = *stp->theta;
+    }
     double dn = 0.0;
     if (k >= 0 && k < stp->M) {
         const MfRec &rec = stp->mf->full_recs[k];
         const int64_t e = (int64_t)task.y * TAYLOR_ROWS_PER_BLOCK + threadIdx.x;
         if (rec.nfree >= 0 && e < ((int64_t)1 << rec.nfree))
-            dn = taylor_pair<DT>(stp, rec, (uint32_t)e);
+            dn = taylor_pair<DT>(stp, rec, (uint32_t)e, theta);
     }
     if (!stp->tay_partials)
         return;
@@ -1057,27 +1067,27 @@ void launch_norm_mf(int dtype, const TaylorState *states, const int2 *tasks, uns
 }
 
 void launch_taylor_mf(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
-                      hipStream_t s)
+                      const double *theta_row, hipStream_t s)
 {
     if (dtype == VQE_C128)
         k_taylor_mf<VQE_C128, false><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
-            states, tasks, nullptr, nullptr, nullptr, nullptr, 0, 0.0);
+            states, tasks, nullptr, nullptr, nullptr, nullptr, 0, 0.0, theta_row);
     else
         k_taylor_mf<VQE_C64, false><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
-            states, tasks, nullptr, nullptr, nullptr, nullptr, 0, 0.0);
+            states, tasks, nullptr, nullptr, nullptr, nullptr, 0, 0.0, theta_row);
 }
 
 void launch_taylor_mf_fin(int dtype, const TaylorState *states, const int2 *tasks, unsigned grid,
                           const SpmvState *spmv, const ScreenState *screen,
                           const PairTable *tables, const SelectState *sel, bool select,
-                          double rel_tie, hipStream_t s)
+                          double rel_tie, const double *theta_row, hipStream_t s)
 {
     if (dtype == VQE_C128)
         k_taylor_mf<VQE_C128, true><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
-            states, tasks, spmv, screen, tables, sel, select ? 1 : 0, rel_tie);
+            states, tasks, spmv, screen, tables, sel, select ? 1 : 0, rel_tie, theta_row);
     else
         k_taylor_mf<VQE_C64, true><<<grid, TAYLOR_ROWS_PER_BLOCK, 0, s>>>(
-            states, tasks, spmv, screen, tables, sel, select ? 1 : 0, rel_tie);
+            states, tasks, spmv, screen, tables, sel, select ? 1 : 0, rel_tie, theta_row);
 }
 
 // ------------------------------------------------------------------ C ABI
