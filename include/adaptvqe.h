@@ -394,17 +394,20 @@ VQE_API int vqe_batch_step(vqe_batch *plan, uint32_t flags);
  * runs as vqe_batch_step with its angles from row i of theta_rows (DEVICE
  * float64 [n_steps][B], row-major, read when that step runs); the plan's
  * angle buffer (io->theta) receives each row, so afterwards it holds the
- * last row for every active slot.  flags:
- * VQE_STEP_RENORM, VQE_STEP_FORCED, VQE_STEP_TILED_SCREEN as for
+ * last row for every active slot.  With VQE_STEP_LINESEARCH (after
+ * vqe_batch_set_line_search) theta_rows must be NULL and every step chooses
+ * its angles by line search, as vqe_batch_step does: n_steps whole adaptive
+ * iterations with no host work between them.  flags: VQE_STEP_RENORM,
+ * VQE_STEP_FORCED, VQE_STEP_TILED_SCREEN, VQE_STEP_LINESEARCH as for
  * vqe_batch_step, and VQE_STEP_GRAPH: the n_steps steps form ONE captured
  * graph, launched once (no host work and no launch gap between the steps);
  * it is captured on first use for its (flags, n_steps, theta_rows) and kept
  * (up to 4 per plan, the least recently used replaced), so a caller that
  * refills the same rows replays it.  The per-step outputs (energies,
  * gradients, selection) are those of the last step.  Errors: VQE_EINVAL for
- * another flag (VQE_STEP_NO_UPDATE, VQE_STEP_LINESEARCH), n_steps outside
- * [0, VQE_RUN_MAX_STEPS] or theta_rows NULL with n_steps > 0; n_steps = 0
- * does nothing.
+ * another flag (VQE_STEP_NO_UPDATE), n_steps outside [0, VQE_RUN_MAX_STEPS],
+ * theta_rows NULL with n_steps > 0 and no line search, theta_rows given with
+ * one, or a line search not enabled; n_steps = 0 does nothing.
  */
 #define VQE_RUN_MAX_STEPS 1024
 VQE_API int vqe_batch_run(vqe_batch *plan, uint32_t flags, const double *theta_rows, int32_t n_steps);

@@ -676,18 +676,26 @@ class BatchPlan:
         flags = self._flags(renorm, forced, update, graph, line_search, tiled_screen)
         self.ctx.check(lib().vqe_batch_step(self.handle, flags), "vqe_batch_step")
 
-    def run(self, theta_rows, renorm: bool = True, forced: bool = False, graph: bool = True,
-            tiled_screen: bool = False):
-        """theta_rows.shape[0] adaptive steps in one call (vqe_batch_run): step
-        i takes its angles from row i of theta_rows, a contiguous float64
-        [n_steps, B] tensor on the plan's device; with graph the steps are one
-        graph launch."""
+    def run(self, theta_rows=None, renorm: bool = True, forced: bool = False, graph: bool = True,
+            tiled_screen: bool = False, line_search_steps: int = 0):
+        """Several adaptive steps in one call (vqe_batch_run): theta_rows.shape[0]
+        steps, step i taking its angles from row i of theta_rows (a contiguous
+        float64 [n_steps, B] tensor on the plan's device), or, with theta_rows
+        None, line_search_steps steps that choose their angles by line search;
+        with graph the steps are one graph launch."""
         torch = _torch()
-        if theta_rows.dtype != torch.float64 or theta_rows.dim() != 2 or \
+        if theta_rows is None:
+            if line_search_steps < 0:
+                raise ValueError("run: line_search_steps must be >= 0")
+            flags = self._flags(renorm, forced, True, graph, True, tiled_screen)
+            self.ctx.check(lib().vqe_batch_run(self.handle, flags, None, int(line_search_steps)),
+                           "vqe_batch_run")
+            return
+        if line_search_steps or theta_rows.dtype != torch.float64 or theta_rows.dim() != 2 or \
                 theta_rows.shape[1] != self.B or not theta_rows.is_contiguous() or \
                 theta_rows.device != self.theta.device:
             raise ValueError("run: theta_rows must be a contiguous float64 [n_steps, B] tensor "
-                             "on the plan's device")
+                             "on the plan's device (and no line search with given angles)")
         flags = self._flags(renorm, forced, True, graph, False, tiled_screen)
         self.ctx.check(lib().vqe_batch_run(self.handle, flags, theta_rows.data_ptr(),
                                            int(theta_rows.shape[0])), "vqe_batch_run")

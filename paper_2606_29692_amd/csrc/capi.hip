@@ -1515,21 +1515,31 @@ extern "C" int vqe_batch_run(vqe_batch *p, uint32_t flags, const double *theta_r
     if (!p)
         return VQE_EINVAL;
     vqe_ctx *ctx = p->ctx;
-    if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_GRAPH | VQE_STEP_TILED_SCREEN))
+    if (flags & ~(uint32_t)(VQE_STEP_RENORM | VQE_STEP_FORCED | VQE_STEP_GRAPH | VQE_STEP_TILED_SCREEN |
+                            VQE_STEP_LINESEARCH))
         return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_run: unknown flags, or a flag a run of updates "
-                        "with given angles does not take");
-    if (n_steps < 0 || n_steps > VQE_RUN_MAX_STEPS || (n_steps > 0 && !theta_rows))
-        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_run: bad steps (%d) or angle rows", n_steps);
+                        "does not take");
+    const bool ls = (flags & VQE_STEP_LINESEARCH) != 0;
+    if (n_steps < 0 || n_steps > VQE_RUN_MAX_STEPS || (n_steps > 0 && !ls && !theta_rows) ||
+        (ls && theta_rows))
+        return vqe_fail(ctx, VQE_EINVAL, "vqe_batch_run: bad steps (%d), or angle rows given with "
+                        "a line search or missing without one", n_steps);
+    if (ls && !p->ls_ready)
+        return vqe_fail(ctx, VQE_EINVAL,
+                        "vqe_batch_run: line search not enabled (vqe_batch_set_line_search)");
     if (n_steps == 0)
         return VQE_OK;
     const uint32_t sflags = flags & ~(uint32_t)VQE_STEP_GRAPH;
     // each step with its row of angles: the matrix-free update reads the row
-    // itself; otherwise the row is first copied into the plan's angle buffer
+    // itself; otherwise the row is first copied into the plan's angle buffer;
+    // with a line search each step chooses its own angles
     auto enqueue = [&]() -> int {
         for (int32_t i = 0; i < n_steps; i++) {
-            const double *row = theta_rows + (size_t)i * p->B;
+            const double *row = ls ? nullptr : theta_rows + (size_t)i * p->B;
             int rc;
-            if (p->mf) {
+            if (ls) {
+                rc = enqueue_step(p, sflags);
+            } else if (p->mf) {
                 rc = enqueue_spmv(p);
                 rc = rc ? rc : enqueue_rest(p, sflags, nullptr, row);
             } else {

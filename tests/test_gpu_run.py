@@ -5,7 +5,8 @@ single step (Eq. 5 screen, selection, Eq. 6-8 update, renormalisation).  The
 eager run and the one-graph run must equal the same steps taken one at a time
 with those angles, bit for bit (the same kernels on the same inputs); the
 graph is kept for its rows, so refilled rows replay it with the new angles;
-bad arguments are refused.
+bad arguments are refused.  With a line search the steps choose their own
+angles, as single line-search steps do.
 """
 import ctypes as C
 
@@ -120,6 +121,7 @@ def test_run_refuses_bad_arguments(ctx):
     run = B.lib().vqe_batch_run
     h, ptr = plan.handle, C.c_void_p(rows.data_ptr())
     assert run(h, B.VQE_STEP_RENORM | B.VQE_STEP_LINESEARCH, ptr, 2) == B.VQE_EINVAL
+    assert run(h, B.VQE_STEP_RENORM | B.VQE_STEP_LINESEARCH, None, 2) == B.VQE_EINVAL  # not enabled
     assert run(h, B.VQE_STEP_NO_UPDATE, ptr, 2) == B.VQE_EINVAL
     assert run(h, B.VQE_STEP_RENORM, None, 2) == B.VQE_EINVAL
     assert run(h, B.VQE_STEP_RENORM, ptr, -1) == B.VQE_EINVAL
@@ -131,4 +133,26 @@ def test_run_refuses_bad_arguments(ctx):
         plan.run(rows.t())
     with pytest.raises(ValueError):
         plan.run(rows.float())
+    plan.close()
+
+
+def test_line_search_run_equals_single_steps(ctx):
+    """With a line search each step of the run chooses its own angles: the
+    same as line-search steps taken one at a time, bit for bit."""
+    ds, psi0, plan, tiled = setup(ctx, "matrix-free c64, complex states, row-tiled screen")
+    plan.set_line_search(1.0)
+    reset(ds, psi0)
+    for _ in range(STEPS):
+        plan.step(renorm=True, line_search=True, tiled_screen=tiled)
+    want = outputs(plan, ds)
+    assert np.any(want[4] != 0.0)
+    for graph in (False, True):
+        reset(ds, psi0)
+        plan.run(None, line_search_steps=STEPS, graph=graph, tiled_screen=tiled)
+        assert_same(outputs(plan, ds), want, f"line-search run, graph={graph}")
+    rows = torch.zeros((2, plan.B), dtype=torch.float64, device=plan.theta.device)
+    assert B.lib().vqe_batch_run(plan.handle, B.VQE_STEP_RENORM | B.VQE_STEP_LINESEARCH,
+                                 C.c_void_p(rows.data_ptr()), 2) == B.VQE_EINVAL
+    with pytest.raises(ValueError):
+        plan.run(rows, line_search_steps=2)
     plan.close()
