@@ -505,8 +505,9 @@ def set_states(ds, systems, form: str):
 
 def mixed_batch_leg(ctx, stream, pools_mf: bool, K: int, W: int, L: int, R: int):
     """Config C4: 64 states with N cycling over 10/12/14 (n_e 4/8/6), each with
-    its own pool, one launch sequence per step, complex start states, the
-    complex-value schedule tuned per register size."""
+    its own pool, one launch sequence per step, complex start states; the
+    complex-value schedules chosen for the batch (each size's own, or one
+    shared by all states when one H-product launch for the batch is faster)."""
     import torch
     import vqe_system as vs
     from paper_2606_29692_amd import batch as PB
@@ -516,11 +517,10 @@ def mixed_batch_leg(ctx, stream, pools_mf: bool, K: int, W: int, L: int, R: int)
     pools = PB.PoolCache(ctx, matrix_free=pools_mf)
     ds = [PB.device_system(ctx, s, "c64", pools) for s in systems]
     set_states(ds, systems, "complex")
-    scheds = {}
-    for n in sorted({d.n_qubits for d in ds}):
-        same = [d for d in ds if d.n_qubits == n]
-        scheds[n] = T.schedule_for(ctx, same[0], systems=same, value_form="complex")
-    plan = PB.make_batch(ctx, ds, schedules=[scheds[d.n_qubits] for d in ds])
+    per_slot = T.schedules_for_batch(ctx, ds, value_form="complex")
+    choice = T.last_batch_record(ctx, ds, value_form="complex")
+    scheds = {d.n_qubits: s for d, s in zip(ds, per_slot)}
+    plan = PB.make_batch(ctx, ds, schedules=per_slot)
     rng = np.random.default_rng(np.random.SeedSequence([4, 1]))
     th = torch.from_numpy(rng.uniform(-0.1, 0.1, size=(W + K + L + R + 1, len(ds)))).to("cuda")
     leg = timed_leg(plan, stream, len(ds), th, K, W, L, R, tiled_screen=pools_mf)
@@ -529,7 +529,9 @@ def mixed_batch_leg(ctx, stream, pools_mf: bool, K: int, W: int, L: int, R: int)
     by_n = {str(n): sum(1 for d in ds if d.n_qubits == n) for n in scheds}
     out = {"workload": "64 states, N = (10, 12, 14)[i mod 3] (22/21/21), n_e 4/8/6, JW, own "
                        "pool per size (54/92/204), complex start states, FP32 storage",
-           "states_by_qubits": by_n, "schedules": {str(k): v for k, v in scheds.items()},
+           "states_by_qubits": by_n, "schedules": {str(k): v for k, v in sorted(scheds.items())},
+           "schedule_choice": {"shared": choice["shared"], "own_per_size": choice["own"],
+                               "h_product_ms_by_choice": choice["ms"]} if choice else None,
            "algorithmic_bytes_per_step": nb,
            "h_product_GBps": nb["h_spmv"] / (leg["h_product_ms"] / 1e3) / 1e9, **leg}
     del ds, pools
@@ -803,7 +805,8 @@ def main():
         mixed = mixed_batch_leg(ctx, stream, args.matrix_free, K, W, L, R)
         log(f"mixed 10/12/14 batch: {mixed['ms_per_step']:.3f} ms/step = "
             f"{mixed['updates_per_s']:.0f} updates/s, H product {mixed['h_product_ms'] * 1e3:.1f} us "
-            f"({mixed['h_product_GBps']:.0f} GB/s), step p99 {mixed['step_latency']['p99_ms']:.3f} ms")
+            f"({mixed['h_product_GBps']:.0f} GB/s), step p99 {mixed['step_latency']['p99_ms']:.3f} ms; "
+            f"schedules {mixed['schedules']}")
 
     # practical HBM ceiling for context: a plain device copy (read + write) of 2 GiB
     # (an elementwise kernel, dst = src * 1, so profilers see it as a kernel)

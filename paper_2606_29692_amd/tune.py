@@ -16,6 +16,12 @@ entries are all real.  The choice is a function of that key alone, so a state
 gets the same schedule (and the same floating-point summation order) whether
 it runs alone or inside any batch.
 
+A batch of several register sizes runs one H-product launch per schedule in
+use; schedules_for_batch may instead give every state one shared schedule,
+when one launch for the whole batch is faster (the smaller states' workgroups
+then fill the CUs that a few large states leave idle).  That choice depends on
+the batch, so it gives up the alone-or-in-any-batch property above.
+
 Cache: ``tuned_schedules.json`` next to this file (committed results), plus
 the file named by ADAPTVQE_TUNE_CACHE when set (written after tuning).
 """
@@ -92,13 +98,16 @@ def _store(key: str, rec: dict):
         json.dump(data, f, indent=1, sort_keys=True)
 
 
-def time_batch_spmv(ctx, systems, schedule: int, reps: int = 10) -> float:
+def time_batch_spmv(ctx, systems, schedule, reps: int = 10) -> float:
     """Milliseconds per launch of the batched H products with the given
-    schedule: the median of three runs of `reps` back-to-back launches
-    (infinite for a schedule the operators do not support)."""
+    schedule (one for every system, or a list with one per system): the
+    median of three runs of `reps` back-to-back launches (infinite for a
+    schedule the operators do not support)."""
     from .batch import make_batch
+    scheds = [int(x) for x in schedule] if isinstance(schedule, (list, tuple)) else \
+        [int(schedule)] * len(systems)
     try:
-        plan = make_batch(ctx, systems, schedules=[schedule] * len(systems))
+        plan = make_batch(ctx, systems, schedules=scheds)
     except B.VqeError as e:
         if e.status != B.VQE_ENOTSUP:
             raise
@@ -135,6 +144,54 @@ def schedule_for(ctx, ds, systems=None, retune: bool = False, value_form: str = 
     _memo[key] = rec["schedule"]
     _store(key, rec)
     return rec["schedule"]
+
+
+def _batch_key(ctx, ds: list, value_form: str) -> str:
+    _, name = ctx.info()
+    counts: dict = {}
+    for d in ds:
+        k = f"n{d.n_qubits}|{d.dtype}|{d.key[2]}"
+        counts[k] = counts.get(k, 0) + 1
+    comp = ",".join(f"{k}x{counts[k]}" for k in sorted(counts))
+    return f"{name}|batch|{comp}" + ("" if value_form == "any" else "|complex")
+
+
+def schedules_for_batch(ctx, ds: list, retune: bool = False, value_form: str = "any") -> list:
+    """One schedule per state of a batch of several register sizes: each
+    size's own (schedule_for, tuned on that size's states of the batch), or,
+    when it is faster for the batch as a whole, one schedule shared by every
+    state (candidates: the sizes' own schedules that every state supports).
+    The batch's H products are timed with each choice; the record is cached
+    under the batch's composition (sizes and counts)."""
+    sizes = sorted({d.n_qubits for d in ds})
+    own = {}
+    for n in sizes:
+        same = [d for d in ds if d.n_qubits == n]
+        own[n] = schedule_for(ctx, same[0], systems=same, value_form=value_form)
+    if len(sizes) == 1:
+        return [own[sizes[0]]] * len(ds)
+    key = _batch_key(ctx, ds, value_form)
+    rec = None
+    if not retune:
+        rec = _memo.get(key) or _load().get(key)
+    if rec is None:
+        per_size = [own[d.n_qubits] for d in ds]
+        ms = {"per-size": time_batch_spmv(ctx, ds, per_size)}
+        for c in sorted(set(own.values())):
+            ms[str(c)] = time_batch_spmv(ctx, ds, c)
+        best = min(ms, key=ms.get)
+        rec = {"shared": None if best == "per-size" else int(best),
+               "own": {str(n): own[n] for n in sizes}, "ms": ms}
+        _store(key, rec)
+    _memo[key] = rec
+    if rec["shared"] is not None:
+        return [int(rec["shared"])] * len(ds)
+    return [own[d.n_qubits] for d in ds]
+
+
+def last_batch_record(ctx, ds: list, value_form: str = "any") -> dict | None:
+    key = _batch_key(ctx, ds, value_form)
+    return _memo.get(key) or _load().get(key)
 
 
 def last_record(ctx, ds, value_form: str = "any") -> dict | None:

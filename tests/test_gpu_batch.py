@@ -824,3 +824,56 @@ def test_real_schedule_mixed_plan(ctx, dtype):
     plan.close()
     for pl in alone:
         pl.close()
+
+
+def test_shared_schedule_for_a_mixed_batch(ctx, tmp_path, monkeypatch):
+    """schedules_for_batch on the C4 shape (10/12/14 qubits, complex values):
+    every state gets its size's own schedule or all get one shared schedule,
+    whichever runs the batch's H products faster; the batch with the chosen
+    schedules matches the oracle over two steps (FP32 bars) and, under a
+    shared schedule, each state's sigma equals that of the same state alone
+    under that schedule, bit for bit."""
+    from paper_2606_29692_amd import tune as T
+    monkeypatch.setenv("ADAPTVQE_TUNE_CACHE", str(tmp_path / "tune.json"))
+    specs, _ = vs.config_c4(n_states=6, mixed=True)
+    systems = [vs.make_system(s) for s in specs]
+    pools = PB.PoolCache(ctx, matrix_free=True)
+    ds = [PB.device_system(ctx, s, "c64", pools) for s in systems]
+    per_slot = T.schedules_for_batch(ctx, ds, retune=True, value_form="complex")
+    rec = T.last_batch_record(ctx, ds, value_form="complex")
+    print(f"batch choice: shared {rec['shared']}, own {rec['own']}, ms {rec['ms']}", flush=True)
+    own = {int(n): s for n, s in rec["own"].items()}
+    if rec["shared"] is None:
+        assert per_slot == [own[d.n_qubits] for d in ds]
+    else:
+        assert per_slot == [rec["shared"]] * len(ds) and rec["shared"] in own.values()
+    assert min(rec["ms"].values()) == rec["ms"]["per-size" if rec["shared"] is None else str(rec["shared"])]
+    plan = PB.make_batch(ctx, ds, schedules=per_slot)
+    steps = 2
+    thetas = np.stack([vs.draw_thetas(s.seed, steps) for s in specs])
+    E, K, G = [], [], []
+    for t in range(steps):
+        plan.theta.copy_(torch.from_numpy(thetas[:, t]))
+        plan.step(renorm=True, graph=True, tiled_screen=True)
+        E.append(host(plan.energies).reshape(-1, 3)[:, 0].copy())
+        K.append(host(plan.k).copy())
+        G.append([host(plan.gradients(i)).copy() for i in range(len(ds))])
+    plan.close()
+    K = np.array(K)
+    for i, s in enumerate(systems):
+        tr = _oracle_run(s, thetas[i], steps, forced=K[:, i])
+        de = max(abs(E[t][i] - tr.energies[t]) for t in range(steps))
+        dg = max(np.abs(G[t][i] - tr.gradients[t]).max() for t in range(steps))
+        assert de < 1e-6 and dg < 1e-5, (i, de, dg)
+    # sigma of each state alone under the batch's schedule equals its sigma in the batch
+    for d in ds:
+        d.reset()
+    both = PB.make_batch(ctx, ds, schedules=per_slot)
+    both.step(update=False)
+    sig_b = [host(x) for x in both.sigma]
+    both.close()
+    for i, d in enumerate(ds):
+        alone = PB.make_batch(ctx, [d], schedules=[per_slot[i]])
+        alone.step(update=False)
+        np.testing.assert_array_equal(host(alone.sigma[0]), sig_b[i])
+        alone.close()
