@@ -178,7 +178,12 @@ def schedules_for_batch(ctx, ds: list, retune: bool = False, value_form: str = "
         per_size = [own[d.n_qubits] for d in ds]
         ms = {"per-size": time_batch_spmv(ctx, ds, per_size)}
         for c in sorted(set(own.values())):
-            ms[str(c)] = time_batch_spmv(ctx, ds, c)
+            try:
+                ms[str(c)] = time_batch_spmv(ctx, ds, c)
+            except B.VqeError as e:      # a size's schedule that another size refuses
+                if e.status != B.VQE_EINVAL:
+                    raise
+                ms[str(c)] = float("inf")
         best = min(ms, key=ms.get)
         rec = {"shared": None if best == "per-size" else int(best),
                "own": {str(n): own[n] for n in sizes}, "ms": ms}
