@@ -64,11 +64,19 @@ _last_timings: dict = {}
 VALUE_FORMS = ("any", "complex")
 
 
+def _device_tag(ctx) -> str:
+    """The device part of a cache key: the architecture name and the CU count
+    (the marketing name the runtime reports can differ between processes of
+    the same machine, for instance under a profiler)."""
+    n_cu, name = ctx.info()
+    arch = name[name.rfind("(") + 1:name.rfind(")")] if "(" in name and ")" in name else name
+    return f"{arch}|{n_cu}cu"
+
+
 def _key(ctx, ds, value_form: str = "any") -> str:
     if value_form not in VALUE_FORMS:
         raise ValueError(f"value form {value_form!r}: expected one of {VALUE_FORMS}")
-    _, name = ctx.info()
-    key = f"{name}|n{ds.n_qubits}|{ds.dtype}|{ds.key[2]}"
+    key = f"{_device_tag(ctx)}|n{ds.n_qubits}|{ds.dtype}|{ds.key[2]}"
     return key if value_form == "any" else key + "|complex"
 
 
@@ -147,13 +155,12 @@ def schedule_for(ctx, ds, systems=None, retune: bool = False, value_form: str = 
 
 
 def _batch_key(ctx, ds: list, value_form: str) -> str:
-    _, name = ctx.info()
     counts: dict = {}
     for d in ds:
         k = f"n{d.n_qubits}|{d.dtype}|{d.key[2]}"
         counts[k] = counts.get(k, 0) + 1
     comp = ",".join(f"{k}x{counts[k]}" for k in sorted(counts))
-    return f"{name}|batch|{comp}" + ("" if value_form == "any" else "|complex")
+    return f"{_device_tag(ctx)}|batch|{comp}" + ("" if value_form == "any" else "|complex")
 
 
 def schedules_for_batch(ctx, ds: list, retune: bool = False, value_form: str = "any") -> list:
